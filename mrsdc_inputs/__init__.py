@@ -1,0 +1,12 @@
+"""Seeded synthetic inputs shared by the GPU library's tests and the CPU oracle.
+
+Holds meshes, assembled finite element operators, couplings, motion laws and
+seeded initial fields: the arrays a caller passes to the time stepper.  It
+contains none of the time-stepping method's arithmetic.
+"""
+from .mesh import FACES, Body, Face, box  # noqa: F401
+from .problems import (  # noqa: F401
+    EQUI_NOLEFT, FP32_REFINE, FP64, LOBATTO, MESH_LEVELS, Contact, Motion, Patch, Problem,
+    Scheme, config0, config1, config2, config3_scenario, machine, noise_T0, patch_box,
+    scenario_params, serving_trace,
+)
