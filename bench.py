@@ -1,0 +1,145 @@
+"""Benchmark of the MRSDC time stepper on one MI355X.
+
+Workload (default): the two-body machine, stand 41x41x161 + stock 31x31x41
+nodes (310,042 DOF, 8,044,322 nonzeros), Gauss-Lobatto M=5, K=4 sweeps, P=5
+embedded nodes per interval, dt = 5 s, FP64, seeded synthetic inputs.  A
+"step" is one MRSDC macro-step (predictor + K sweeps) of the whole state.
+
+Prints ONE JSON line: DOF*steps/s (value), look-ahead factor eta = simulated /
+wall time, p50/p99 macro-step latency, the dominant kernel's roofline and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=120)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--config", default="c1", choices=["c0", "c1", "c2"])
+    ap.add_argument("--cpu-steps", type=int, default=4, help="oracle sample (macro-steps)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    return ap.parse_args()
+
+
+def workload(name, nsteps):
+    import mrsdc_inputs as mi
+    if name == "c0":
+        return mi.config0()
+    if name == "c2":
+        return mi.config2(nsteps=nsteps)
+    return mi.config1(nsteps=nsteps)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the time step of "
+              "one simulation does not shard across GPUs in this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1707_03581_amd as pkg
+
+    assert torch.cuda.is_available(), "no GPU"
+    pb = workload(args.config, args.steps)
+    dt = pb.scheme.dt
+    N = pb.N
+    print(f"[bench] workload {pb.name}: N={N} nnz={pb.nnz}", file=sys.stderr, flush=True)
+    ctx = pkg.simulation(pb, device=0)
+    t_setup = time.perf_counter()
+    ctx.advance(args.warmup * dt)
+    t_setup = time.perf_counter() - t_setup
+    print(f"[bench] warmup {args.warmup} steps done ({t_setup:.2f}s incl. setup)", file=sys.stderr,
+          flush=True)
+
+    # timed region: K macro-steps, one advance call each (the call returns after
+    # the device finished the step) -> per-step latency and total wall time
+    if not args.no_profile:
+        ctx.profile(True)
+    torch.cuda.synchronize()
+    lat = []
+    iters = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        st = ctx.advance(dt)
+        lat.append(time.perf_counter() - s0)
+        iters += st["pcg_iters"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = ctx.profile_read() if not args.no_profile else None
+    print(f"[bench] timed {args.steps} steps in {wall:.3f}s", file=sys.stderr, flush=True)
+
+    dof_steps = N * args.steps / wall
+    eta = args.steps * dt / wall
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": "look-ahead eta & DOF*steps/s at 1e-7 rel err; p50/p99 macro-step latency",
+        "value": dof_steps,
+        "unit": "DOF*steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if pb.scheme.precision == 0 else "f32+f64-refine",
+        "data": "synthetic",
+        "config": {"workload": pb.name, "dof": N, "nnz": pb.nnz, "M": pb.scheme.M,
+                   "nodes": "gauss-lobatto" if pb.scheme.family == 0 else "equidistant",
+                   "K": pb.scheme.K, "P": pb.scheme.P, "dt_s": dt,
+                   "simulated_s": args.steps * dt},
+        "eta": eta,
+        "p50_step_ms": float(np.percentile(lat_ms, 50)),
+        "p99_step_ms": float(np.percentile(lat_ms, 99)),
+        "cg_iters_per_step": iters / args.steps,
+    }
+    if kt and kt["cg_spmv_launches"]:
+        avg_ms = kt["cg_spmv_ms"] / kt["cg_spmv_launches"]
+        achieved = kt["cg_spmv_bytes"] / (avg_ms * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": "k_pcg_a (CG operator application)",
+                           "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "avg_launch_us": avg_ms * 1e3, "launches": kt["cg_spmv_launches"],
+                           "bytes_per_launch": kt["cg_spmv_bytes"]}
+        if kt["iface_launches"]:
+            out["iface_avg_us"] = kt["iface_ms"] / kt["iface_launches"] * 1e3
+    ctx.destroy()
+
+    if not args.no_cpu_baseline and args.cpu_steps > 0:
+        import oracle
+        S = args.cpu_steps
+        ref_pb = workload(args.config, S)
+        t = time.perf_counter()
+        Tref, ost = oracle.run(ref_pb, nsteps=S)
+        tc = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": N * S / tc, "unit": "DOF*steps/s",
+                               "cores": int(ost["threads"]), "kind": "oracle",
+                               "sample": f"first {S} of {args.steps} macro-steps of {pb.name}",
+                               "seconds": tc, "pcg_share": ost["t_pcg"] / max(ost["t_total"], 1e-12)}
+        g = pkg.simulation(ref_pb, device=0)
+        g.advance(S * dt)
+        Tg = pkg.get_state(g, ref_pb)
+        g.destroy()
+        out["rel_l2_vs_oracle"] = float(np.linalg.norm(Tg - Tref) / np.linalg.norm(Tref))
+        out["rel_l2_sample_steps"] = S
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * mrsdc.h -- C-ABI of the MI355X multi-rate spectral deferred correction
+ * (MRSDC) heat-conduction stepper.
+ *
+ * The library advances the semi-discrete heat equation of a machine made of a
+ * fixed stand and a moving stock (Naumann, Ruprecht, Wensch, arXiv 1707.03581,
+ * §2, eq. coupledFEM and its splitting eq. ivp):
+ *
+ *     diag(m) dT/dt = f^I(T) + g + f^E(T, t)
+ *     f^I(T) = -(K + h R) T          slow, implicit  (conduction + Robin)
+ *     g      = h T_env r             slow source     (Robin load)
+ *     f^E    = contact exchange alpha (T_other - T) and friction heat on the
+ *              moving overlap Gamma_R(t) of two faces, or a moving heat-flux
+ *              patch on one face                    (fast, explicit)
+ *
+ * with the MRSDC predictor (Alg. 1) followed by K correction sweeps (Alg. 2)
+ * of §3: one implicit node solve (diag(m) + dtau_m (K + h R)) T* = rhs per
+ * standard interval and P explicit Euler substeps of f^E at the embedded
+ * nodes.  Every step of the sweep runs in HIP kernels on one gfx950 GPU.
+ *
+ * Conventions (all entry points):
+ *  - Return an mrsdc_status; no exception crosses the ABI.  On error the
+ *    context keeps its previous state and mrsdc_last_error(ctx) describes why.
+ *  - All array arguments are HOST pointers unless the name says device; they
+ *    are copied during the call and stay owned by the caller.
+ *  - Device memory is owned by the context until mrsdc_destroy.
+ *  - One thread at a time per context; distinct contexts are independent.
+ *  - SI units, temperatures in degrees Celsius.
+ *  - Bodies: 0 (stand / the only body) and 1 (stock).  Their nodes are
+ *    concatenated in body order into one state vector (§2, eq. coupledFEM).
+ */
+#ifndef MRSDC_H
+#define MRSDC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mrsdc_ctx mrsdc_ctx;
+
+typedef enum {
+  MRSDC_OK = 0,
+  MRSDC_EINVAL = -1,  /* bad argument: shape, CSR structure, NaN, scheme, horizon */
+  MRSDC_ENOMEM = -2,  /* device or host allocation failed */
+  MRSDC_EDEVICE = -3, /* HIP runtime error or no usable GPU */
+  MRSDC_ENOCONV = -4, /* an implicit solve hit its iteration cap; state rolled back
+                         to the last completed step */
+  MRSDC_ESTATE = -5   /* call out of order (e.g. advance before bodies are set) */
+} mrsdc_status;
+
+enum { MRSDC_FP64 = 0, MRSDC_FP32_REFINE = 1 };
+enum { MRSDC_LOBATTO = 0, MRSDC_EQUI_NOLEFT = 1 };
+
+typedef struct {
+  int device;         /* HIP device ordinal */
+  int precision;      /* MRSDC_FP64, or MRSDC_FP32_REFINE: FP32 inner CG with FP64
+                         iterative refinement (FP64 residual, FP64 node states) */
+  int M;              /* standard nodes, 2..8 (§3: tau_1 < ... < tau_M = t_{n+1}) */
+  int node_family;    /* MRSDC_LOBATTO (tau_1 = t_n, first interval skipped) or
+                         MRSDC_EQUI_NOLEFT (tau_m = t_n + m dt / M, §3) */
+  int P;              /* embedded nodes per standard interval, 1..32 (equidistant,
+                         no-left, §3) */
+  int K;              /* correction sweeps after the predictor, 0..16 */
+  double dt;          /* time step, > 0 */
+  double pcg_rtol;    /* FP64 path: stop when ||r||_2 <= pcg_rtol ||b||_2 */
+  int pcg_maxit;      /* iteration cap per solve (ENOCONV beyond it) */
+  double refine_rtol; /* FP32_REFINE: outer FP64 tolerance on ||b - A x||_2 / ||b||_2 */
+  int refine_maxit;   /* FP32_REFINE: outer refinement cap per solve */
+  double inner_rtol;  /* FP32_REFINE: relative tolerance of each FP32 inner solve */
+  int final_residual; /* nonzero: also evaluate the residual of the last sweep */
+  int use_graph;      /* nonzero: capture each time step as a HIP graph */
+  void *stream;       /* hipStream_t to run on, or NULL for a library-owned stream */
+} mrsdc_config;
+
+typedef struct {
+  int64_t steps;           /* completed time steps in the last advance */
+  int64_t solves;          /* implicit node solves */
+  int64_t pcg_iters;       /* CG iterations (FP32 inner iterations in FP32_REFINE) */
+  int64_t refine_steps;    /* FP64 refinement residuals (FP32_REFINE) */
+  int32_t max_iters;       /* largest iteration count of one solve */
+  int32_t redone_steps;    /* steps repeated with a larger device iteration budget */
+  double residual[17];     /* residual (eq. residual) of iterates k = 0..K of the
+                              last step; k = K only with final_residual */
+  double wall_s;           /* host wall time of the advance, to device completion */
+  int64_t bytes_moved;     /* algorithmic device bytes of the advance (see docs) */
+} mrsdc_stats;
+
+/* Fill *cfg with defaults: FP64, Lobatto M=3, P=2, K=2, dt=1, pcg_rtol 1e-13. */
+void mrsdc_config_init(mrsdc_config *cfg);
+
+/* Create a context on cfg->device.  EINVAL for a bad scheme, EDEVICE if the
+ * GPU cannot be used.  *out is NULL on failure. */
+mrsdc_status mrsdc_create(mrsdc_ctx **out, const mrsdc_config *cfg);
+
+/* Finite element operators of one body (§2, eq. femDiscr):
+ *  rowptr[n+1] (int64), col[nnz] (int32, 0-based, sorted, in [0,n)) describe
+ *  the common sparsity pattern of K and R;
+ *  K[nnz]  stiffness including conductivity (K = -A_X), symmetric;
+ *  R[nnz]  unit-coefficient Robin boundary mass (B_X,env = -h R); may be NULL;
+ *  mass[n] row-sum lumped mass (> 0);
+ *  robin_load[n] = integral of phi_i over the Robin boundary; may be NULL.
+ * EINVAL on a malformed CSR or non-finite values. */
+mrsdc_status mrsdc_set_body(mrsdc_ctx *ctx, int body, int64_t n, int64_t nnz,
+                            const int64_t *rowptr, const int32_t *col, const double *K,
+                            const double *R, const double *mass, const double *robin_load);
+
+/* Robin coefficient h >= 0 and environment temperature of one body
+ * (§2, Robin conditions: f^I gets -h R, g = h T_env r). */
+mrsdc_status mrsdc_set_robin(mrsdc_ctx *ctx, int body, double h, double T_env);
+
+/* A tensor grid of face nodes of a body, registered under tag face (0..7):
+ * u[nu], v[nv] strictly increasing coordinates in the face plane; node_ids
+ * [nu*nv] body-local node of grid point (u[a], v[b]) at node_ids[a*nv+b].
+ * Faces carry the coupling integrals of f^E (§2, eq. defCB). */
+mrsdc_status mrsdc_set_face(mrsdc_ctx *ctx, int body, int face, int nu, int nv,
+                            const double *u, const double *v, const int32_t *node_ids);
+
+/* Motion of the moving part (§5): s(t) = s0 + a sin(2 pi t / period + phase),
+ * period > 0.  The moving face (or patch) is shifted by s(t) along v. */
+mrsdc_status mrsdc_set_motion(mrsdc_ctx *ctx, double s0, double a, double period,
+                              double phase);
+
+/* Contact coupling on Gamma_R(t) = overlap of the fixed face and the moving
+ * face (§2, boundary conditions on Gamma_R and eqs. femContFix/femContMov).
+ * The moving face's point (u, v) lies at (u + du, v + dv + s(t)) in the fixed
+ * face's frame.  Row i of the fixed body receives
+ *   int_{Gamma_R} phi_i (alpha (T_mov - T_fix) + split P_f / |Gamma_R(t)|),
+ * row i of the moving body the same with the roles swapped and 1 - split.
+ * The faces must be registered first. */
+mrsdc_status mrsdc_set_contact(mrsdc_ctx *ctx, int fix_body, int fix_face, int mov_body,
+                               int mov_face, double du, double dv, double alpha,
+                               double friction_W, double split);
+
+/* Rigid patch of width_u x width_v centred at (u_center, s(t)) on a face:
+ * row i receives int_{patch(t)} phi_i (q0 + alpha (T_fixed - T)) (the moving
+ * stock of the paper's 2D test, §4, with an added prescribed flux). */
+mrsdc_status mrsdc_set_patch(mrsdc_ctx *ctx, int body, int face, double width_u,
+                             double width_v, double u_center, double q0, double alpha,
+                             double T_fixed);
+
+/* Temperature of one body (n values, host array).  EINVAL on NaN/Inf. */
+mrsdc_status mrsdc_set_temperature(mrsdc_ctx *ctx, int body, const double *T, int64_t n);
+
+/* Current simulated time (resume: the state of the one-step method is (t, T)). */
+mrsdc_status mrsdc_set_time(mrsdc_ctx *ctx, double t);
+mrsdc_status mrsdc_get_time(const mrsdc_ctx *ctx, double *t);
+
+/* Advance by horizon seconds (an integer multiple of dt, relative tolerance
+ * 1e-9) and wait for the device.  stats may be NULL.  ENOCONV leaves the state
+ * at the last completed step. */
+mrsdc_status mrsdc_advance(mrsdc_ctx *ctx, double horizon, mrsdc_stats *stats);
+
+/* Copy the temperature of one body to a host array of n values. */
+mrsdc_status mrsdc_get_temperature(mrsdc_ctx *ctx, int body, double *out, int64_t n);
+
+/* Copy the temperature of one body (n doubles) to DEVICE memory dptr on
+ * stream (a hipStream_t, or NULL for the context's stream); asynchronous. */
+mrsdc_status mrsdc_get_temperature_device(mrsdc_ctx *ctx, int body, void *dptr, int64_t n,
+                                          void *stream);
+
+/* Device bytes the context holds once prepared (operators, states, caches). */
+mrsdc_status mrsdc_footprint_bytes(const mrsdc_ctx *ctx, int64_t *bytes);
+
+/* Description of the last error of this context ("" if none). */
+const char *mrsdc_last_error(const mrsdc_ctx *ctx);
+
+/* Free the context and all its device memory.  NULL is accepted. */
+mrsdc_status mrsdc_destroy(mrsdc_ctx *ctx);
+
+/* Host-only: nodes and weights of one step (§3, weight definitions and Table
+ * tab:weights), for inspection and tests.  Arrays use 1-based node indices:
+ * tau[M+1]; s[(M+1)*(M+1)] at [m*(M+1)+j]; shat[(M+1)*(P+1)] at [m*(P+1)+q];
+ * stil[(M+1)*(P+1)*(M+1)] at [(m*(P+1)+p)*(M+1)+j];
+ * spq[(M+1)*(P+1)*(P+1)] at [(m*(P+1)+p)*(P+1)+q].  EINVAL on bad arguments. */
+mrsdc_status mrsdc_quadrature(int M, int node_family, int P, double dt, double *tau,
+                              double *s, double *shat, double *stil, double *spq);
+
+/* Per-kernel-class device time measured with HIP events on the context's
+ * stream while profiling is on (mrsdc_profile).  cg_spmv: the operator
+ * application q = (diag(m) + dtau L) p of every CG iteration within the
+ * previous step's iteration count; cg_spmv_bytes: its algorithmic bytes per
+ * launch (nnz (8 + index bytes) + slice offsets + 24 N). */
+typedef struct {
+  int64_t cg_spmv_launches;
+  double cg_spmv_ms;
+  int64_t cg_spmv_bytes;
+  int64_t iface_launches;
+  double iface_ms;
+  int64_t nnz;
+  int64_t n;
+} mrsdc_kernel_times;
+
+/* Turn event timing of the kernel classes on (nonzero) or off and reset it. */
+mrsdc_status mrsdc_profile(mrsdc_ctx *ctx, int on);
+mrsdc_status mrsdc_profile_read(const mrsdc_ctx *ctx, mrsdc_kernel_times *out);
+
+/* Library version string. */
+const char *mrsdc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRSDC_H */

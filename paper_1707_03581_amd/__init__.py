@@ -1,0 +1,292 @@
+"""MI355X MRSDC heat-conduction stepper: Python binding of the C-ABI (mrsdc.h).
+
+Argument marshalling only: every step of the time stepper runs in the HIP
+kernels of libmrsdc.so.  Importing this package fails loudly when the library
+has not been built (python -m paper_1707_03581_amd.build).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmrsdc.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5
+FP64, FP32_REFINE = 0, 1
+LOBATTO, EQUI_NOLEFT = 0, 1
+FACE_TAGS = {"x0": 0, "x1": 1, "y0": 2, "y1": 3, "z0": 4, "z1": 5}
+_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOCONV: "ENOCONV",
+          ESTATE: "ESTATE"}
+
+
+class MrsdcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Config(C.Structure):
+    _fields_ = [("device", C.c_int), ("precision", C.c_int), ("M", C.c_int),
+                ("node_family", C.c_int), ("P", C.c_int), ("K", C.c_int), ("dt", C.c_double),
+                ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int), ("refine_rtol", C.c_double),
+                ("refine_maxit", C.c_int), ("inner_rtol", C.c_double),
+                ("final_residual", C.c_int), ("use_graph", C.c_int), ("stream", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("solves", C.c_int64), ("pcg_iters", C.c_int64),
+                ("refine_steps", C.c_int64), ("max_iters", C.c_int32),
+                ("redone_steps", C.c_int32), ("residual", C.c_double * 17),
+                ("wall_s", C.c_double), ("bytes_moved", C.c_int64)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "residual"}
+        d["residual"] = list(self.residual)
+        return d
+
+
+class KernelTimes(C.Structure):
+    _fields_ = [("cg_spmv_launches", C.c_int64), ("cg_spmv_ms", C.c_double),
+                ("cg_spmv_bytes", C.c_int64), ("iface_launches", C.c_int64),
+                ("iface_ms", C.c_double), ("nnz", C.c_int64), ("n", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+_SIGS = {
+    "mrsdc_config_init": (None, [C.c_void_p]),
+    "mrsdc_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_void_p]),
+    "mrsdc_set_body": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mrsdc_set_robin": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_double]),
+    "mrsdc_set_face": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p,
+                                 C.c_void_p, C.c_void_p]),
+    "mrsdc_set_motion": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double]),
+    "mrsdc_set_contact": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
+                                    C.c_double, C.c_double, C.c_double, C.c_double]),
+    "mrsdc_set_patch": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_double,
+                                  C.c_double, C.c_double, C.c_double, C.c_double]),
+    "mrsdc_set_temperature": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int64]),
+    "mrsdc_set_time": (C.c_int, [C.c_void_p, C.c_double]),
+    "mrsdc_get_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "mrsdc_advance": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p]),
+    "mrsdc_get_temperature": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int64]),
+    "mrsdc_get_temperature_device": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int64,
+                                               C.c_void_p]),
+    "mrsdc_footprint_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "mrsdc_last_error": (C.c_char_p, [C.c_void_p]),
+    "mrsdc_destroy": (C.c_int, [C.c_void_p]),
+    "mrsdc_quadrature": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mrsdc_version": (C.c_char_p, []),
+    "mrsdc_profile": (C.c_int, [C.c_void_p, C.c_int]),
+    "mrsdc_profile_read": (C.c_int, [C.c_void_p, C.c_void_p]),
+}
+
+
+def lib():
+    """The loaded libmrsdc.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        # torch brings its own HIP runtime (same soname as the system one);
+        # loading torch first makes libmrsdc.so bind to that single copy
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1707_03581_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def quadrature(M, family, P, dt=1.0):
+    """(tau, s, shat, stil, spq) as computed by the library (host only)."""
+    tau = np.zeros(M + 1)
+    s = np.zeros((M + 1, M + 1))
+    shat = np.zeros((M + 1, P + 1))
+    stil = np.zeros((M + 1, P + 1, M + 1))
+    spq = np.zeros((M + 1, P + 1, P + 1))
+    rc = lib().mrsdc_quadrature(M, family, P, dt, _p(tau), _p(s), _p(shat), _p(stil), _p(spq))
+    if rc:
+        raise MrsdcError(rc, "bad quadrature arguments")
+    return tau, s, shat, stil, spq
+
+
+def default_config(**kw) -> Config:
+    cfg = Config()
+    lib().mrsdc_config_init(C.byref(cfg))
+    for k, v in kw.items():
+        setattr(cfg, k, v)
+    return cfg
+
+
+class Context:
+    """One simulation on one GPU; methods mirror the C entry points."""
+
+    def __init__(self, cfg: Config):
+        self._L = lib()
+        self._h = C.c_void_p()
+        self.cfg = cfg
+        rc = self._L.mrsdc_create(C.byref(self._h), C.byref(cfg))
+        if rc:
+            raise MrsdcError(rc, "mrsdc_create failed (scheme or device)")
+
+    def _chk(self, rc):
+        if rc:
+            raise MrsdcError(rc, self._L.mrsdc_last_error(self._h).decode())
+        return rc
+
+    def set_body(self, body, rowptr, col, K, R, mass, robin_load):
+        rowptr = np.ascontiguousarray(rowptr, np.int64)
+        col = np.ascontiguousarray(col, np.int32)
+        K = np.ascontiguousarray(K, np.float64)
+        mass = np.ascontiguousarray(mass, np.float64)
+        R = None if R is None else np.ascontiguousarray(R, np.float64)
+        rl = None if robin_load is None else np.ascontiguousarray(robin_load, np.float64)
+        n = len(mass)
+        return self._chk(self._L.mrsdc_set_body(self._h, body, n, int(rowptr[-1]), _p(rowptr),
+                                                _p(col), _p(K), None if R is None else _p(R),
+                                                _p(mass), None if rl is None else _p(rl)))
+
+    def set_robin(self, body, h, T_env):
+        return self._chk(self._L.mrsdc_set_robin(self._h, body, h, T_env))
+
+    def set_face(self, body, face, u, v, node_ids):
+        u = np.ascontiguousarray(u, np.float64)
+        v = np.ascontiguousarray(v, np.float64)
+        ids = np.ascontiguousarray(node_ids, np.int32)
+        return self._chk(self._L.mrsdc_set_face(self._h, body, face, len(u), len(v), _p(u), _p(v),
+                                                _p(ids)))
+
+    def set_motion(self, s0, a, period, phase=0.0):
+        return self._chk(self._L.mrsdc_set_motion(self._h, s0, a, period, phase))
+
+    def set_contact(self, fix_body, fix_face, mov_body, mov_face, du, dv, alpha, friction_W,
+                    split=0.5):
+        return self._chk(self._L.mrsdc_set_contact(self._h, fix_body, fix_face, mov_body, mov_face,
+                                                   du, dv, alpha, friction_W, split))
+
+    def set_patch(self, body, face, width_u, width_v, u_center, q0, alpha=0.0, T_fixed=0.0):
+        return self._chk(self._L.mrsdc_set_patch(self._h, body, face, width_u, width_v, u_center,
+                                                 q0, alpha, T_fixed))
+
+    def set_temperature(self, body, T):
+        T = np.ascontiguousarray(T, np.float64)
+        return self._chk(self._L.mrsdc_set_temperature(self._h, body, _p(T), len(T)))
+
+    def set_time(self, t):
+        return self._chk(self._L.mrsdc_set_time(self._h, t))
+
+    def get_time(self):
+        t = C.c_double()
+        self._chk(self._L.mrsdc_get_time(self._h, C.byref(t)))
+        return t.value
+
+    def advance(self, horizon):
+        st = Stats()
+        self._chk(self._L.mrsdc_advance(self._h, horizon, C.byref(st)))
+        return st.as_dict()
+
+    def get_temperature(self, body, n):
+        out = np.empty(n)
+        self._chk(self._L.mrsdc_get_temperature(self._h, body, _p(out), n))
+        return out
+
+    def get_temperature_device(self, body, tensor, stream=None):
+        """Copy into a contiguous float64 device tensor (torch) on `stream`."""
+        ptr = tensor.data_ptr()
+        s = None if stream is None else C.c_void_p(stream)
+        return self._chk(self._L.mrsdc_get_temperature_device(self._h, body, C.c_void_p(ptr),
+                                                              tensor.numel(), s))
+
+    def footprint_bytes(self):
+        b = C.c_int64()
+        self._chk(self._L.mrsdc_footprint_bytes(self._h, C.byref(b)))
+        return b.value
+
+    def profile(self, on=True):
+        return self._chk(self._L.mrsdc_profile(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        kt = KernelTimes()
+        self._chk(self._L.mrsdc_profile_read(self._h, C.byref(kt)))
+        return kt.as_dict()
+
+    def last_error(self):
+        return self._L.mrsdc_last_error(self._h).decode()
+
+    def destroy(self):
+        if self._h:
+            self._L.mrsdc_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def config_from_scheme(scheme, device=0, **over) -> Config:
+    """Config from an object with M, family, P, K, dt, pcg_rtol, pcg_maxit, precision..."""
+    cfg = default_config(device=device, precision=scheme.precision, M=scheme.M,
+                         node_family=scheme.family, P=scheme.P, K=scheme.K, dt=scheme.dt,
+                         pcg_rtol=scheme.pcg_rtol, pcg_maxit=scheme.pcg_maxit,
+                         refine_rtol=scheme.refine_rtol, refine_maxit=scheme.refine_maxit,
+                         inner_rtol=scheme.inner_rtol)
+    for k, v in over.items():
+        setattr(cfg, k, v)
+    return cfg
+
+
+def load_problem(ctx: Context, pb, h=None, alpha=None, friction_W=None, period=None, T0=None):
+    """Pass a problem description (bodies, faces, coupling, motion, T0) to ctx."""
+    for i, b in enumerate(pb.bodies):
+        ctx.set_body(i, b.rowptr, b.col, b.K, b.R, b.mass, b.rload)
+        ctx.set_robin(i, pb.h[i] if h is None else h, pb.T_amb[i])
+    m = pb.motion
+    ctx.set_motion(m.s0, m.a, m.period if period is None else period, m.phase)
+    c = pb.coupling
+    if c is not None and type(c).__name__ == "Contact":
+        F = pb.bodies[c.fix_body].faces[c.fix_face]
+        G = pb.bodies[c.mov_body].faces[c.mov_face]
+        ctx.set_face(c.fix_body, FACE_TAGS[c.fix_face], F.u, F.v, F.ids)
+        ctx.set_face(c.mov_body, FACE_TAGS[c.mov_face], c.mov_u, c.mov_v, G.ids)
+        ctx.set_contact(c.fix_body, FACE_TAGS[c.fix_face], c.mov_body, FACE_TAGS[c.mov_face],
+                        0.0, 0.0, c.alpha if alpha is None else alpha,
+                        c.friction_W if friction_W is None else friction_W, c.split)
+    elif c is not None:
+        F = pb.bodies[c.body].faces[c.face]
+        ctx.set_face(c.body, FACE_TAGS[c.face], F.u, F.v, F.ids)
+        ctx.set_patch(c.body, FACE_TAGS[c.face], c.width_u, c.width_v, c.u_center, c.q0, c.alpha,
+                      c.T_fixed)
+    T = pb.T0 if T0 is None else T0
+    off = pb.offsets
+    for i in range(len(pb.bodies)):
+        ctx.set_temperature(i, T[off[i]:off[i + 1]])
+    ctx.set_time(pb.t0)
+
+
+def simulation(pb, device=0, **cfg_over) -> Context:
+    """Context for a problem description, ready to advance."""
+    ctx = Context(config_from_scheme(pb.scheme, device=device, **cfg_over))
+    load_problem(ctx, pb)
+    return ctx
+
+
+def get_state(ctx: Context, pb):
+    return np.concatenate([ctx.get_temperature(i, b.n) for i, b in enumerate(pb.bodies)])

@@ -1,0 +1,976 @@
+// C-ABI of the MRSDC library and the host-side driver of the time step.
+//
+// Per time step [t_n, t_n + dt] (paper §3, Alg. 1 then K times Alg. 2):
+//   predictor, for each interval m:  init solve (one SpMV) -> CG -> interface
+//                                    substeps (f^E at the embedded nodes)
+//   sweep k = 1..K:  F_j = f^I(T_j) + g at all standard nodes (one multi-RHS
+//                    SpMV), I_{m-1}^m and the residual (one fused pass), then
+//                    for each interval m: init (no SpMV) -> CG -> substeps
+//   commit T_{n+1} = T_M on the device, unless a solve ran out of budget.
+// Every kernel of a step is enqueued without host round trips; the host reads
+// a small counter block once per step.  CG iterations are launched in a
+// per-solve budget taken from the previous step; kernels of a converged solve
+// return at once.  A solve that exhausts its budget makes the step uncommitted
+// and the step is repeated with doubled budgets, up to pcg_maxit (ENOCONV).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mrsdc_internal.h"
+
+using namespace mrsdc;
+
+namespace {
+
+struct HostBody {
+  bool set = false;
+  int64_t n = 0, nnz = 0;
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> col;
+  std::vector<double> K, R, mass, rload;
+  double h = 0.0, Tenv = 0.0;
+  std::vector<double> T;
+  bool hasT = false;
+};
+
+struct HostFace {
+  bool set = false;
+  int nu = 0, nv = 0;
+  std::vector<double> u, v;
+  std::vector<int32_t> ids;
+};
+
+struct Coupling {
+  int kind = 0;  // 0 none, 1 contact, 2 patch
+  int fix_body = 0, fix_face = 0, mov_body = 1, mov_face = 0;
+  double du = 0, dv = 0, alpha = 0, Pf = 0, split = 0.5;
+  int body = 0, face = 0;
+  double wu = 0, wv = 0, uc = 0, q0 = 0, Tfix = 0;
+};
+
+struct Motion {
+  double s0 = 0, a = 0, period = 1, phase = 0;
+};
+
+}  // namespace
+
+struct mrsdc_ctx {
+  mrsdc_config cfg;
+  std::string err;
+  HostBody body[2];
+  HostFace face[2][8];
+  Coupling cpl;
+  Motion motion;
+  double t = 0.0;
+  bool prepared = false;
+  bool dirty_T = true;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<void *> allocs;
+  int64_t footprint = 0;
+  DevState d;
+  Weights w;
+  int nbody = 0;
+  int64_t off[3] = {0, 0, 0};
+  StepCounters *ctr_host = nullptr;  // pinned
+  int budget[kSlots];
+  int expect[kSlots];
+  int64_t matrix_bytes = 0;
+  int64_t nnz = 0;
+  // event timing of kernel classes
+  bool prof = false;
+  std::vector<hipEvent_t> ev;   // pairs
+  std::vector<int> ev_class;    // 0 cg spmv, 1 iface
+  int ev_used = 0;
+  mrsdc_kernel_times times = {};
+};
+
+namespace {
+
+mrsdc_status fail(mrsdc_ctx *c, mrsdc_status s, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+mrsdc_status fail(mrsdc_ctx *c, mrsdc_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return s;
+}
+
+#define HIPCHK(call)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(c, MRSDC_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));       \
+  } while (0)
+
+bool finite_all(const double *p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+template <typename T>
+mrsdc_status dalloc(mrsdc_ctx *c, T **p, size_t count) {
+  void *q = nullptr;
+  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) {
+    hipGetLastError();
+    return fail(c, MRSDC_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  c->allocs.push_back(q);
+  c->footprint += (int64_t)bytes;
+  *p = static_cast<T *>(q);
+  return MRSDC_OK;
+}
+
+template <typename T>
+mrsdc_status upload(mrsdc_ctx *c, T **p, const std::vector<T> &h) {
+  mrsdc_status s = dalloc(c, p, h.size());
+  if (s) return s;
+  if (!h.empty()) HIPCHK(hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return MRSDC_OK;
+}
+
+void free_device(mrsdc_ctx *c) {
+  // keep the device-resident temperature and time when the operators change
+  if (c->prepared && !c->dirty_T) {
+    if (c->stream) hipStreamSynchronize(c->stream);
+    for (int b = 0; b < c->nbody; ++b) {
+      if (!c->body[b].set || !c->body[b].hasT) continue;
+      c->body[b].T.resize(c->body[b].n);
+      hipMemcpy(c->body[b].T.data(), c->d.T[0] + c->off[b], sizeof(double) * c->body[b].n,
+                hipMemcpyDeviceToHost);
+    }
+    c->dirty_T = true;
+  }
+  for (void *p : c->allocs) hipFree(p);
+  c->allocs.clear();
+  c->footprint = 0;
+  c->prepared = false;
+}
+
+bool valid_scheme(const mrsdc_config *cfg) {
+  if (cfg->M < 2 || cfg->M > kMaxM || cfg->P < 1 || cfg->P > kMaxP) return false;
+  if (cfg->K < 0 || cfg->K > 16 || !(cfg->dt > 0) || !std::isfinite(cfg->dt)) return false;
+  if (cfg->node_family != MRSDC_LOBATTO && cfg->node_family != MRSDC_EQUI_NOLEFT) return false;
+  if (cfg->precision != MRSDC_FP64 && cfg->precision != MRSDC_FP32_REFINE) return false;
+  if (!(cfg->pcg_rtol > 0) || cfg->pcg_maxit < 1) return false;
+  if (cfg->precision == MRSDC_FP32_REFINE &&
+      (!(cfg->refine_rtol > 0) || cfg->refine_maxit < 1 || !(cfg->inner_rtol > 0)))
+    return false;
+  return true;
+}
+
+// first node c of grid y (shifted by sy) whose hat support ends after t
+int first_hat_after_h(const std::vector<double> &y, double sy, double t) {
+  const int n = (int)y.size();
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) / 2;
+    double end = y[mid < n - 1 ? mid + 1 : mid] + sy;
+    if (end > t) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+double min_spacing(const std::vector<double> &x) {
+  double m = INFINITY;
+  for (size_t i = 1; i < x.size(); ++i) m = std::min(m, x[i] - x[i - 1]);
+  return m;
+}
+double max_support(const std::vector<double> &x) {
+  double m = 0;
+  const int n = (int)x.size();
+  for (int a = 0; a < n; ++a) m = std::max(m, x[a < n - 1 ? a + 1 : a] - x[a > 0 ? a - 1 : a]);
+  return m;
+}
+
+// Band of hats of y overlapping each hat of x along one (static) direction.
+mrsdc_status band_coeffs(mrsdc_ctx *c, const std::vector<double> &x, const std::vector<double> &y,
+                         double lo, double hi, std::vector<double> &C, std::vector<int> &lo_idx) {
+  const int nx = (int)x.size(), ny = (int)y.size();
+  C.assign((size_t)nx * kBand, 0.0);
+  lo_idx.assign(nx, 0);
+  for (int a = 0; a < nx; ++a) {
+    double start = x[a > 0 ? a - 1 : a], end = x[a < nx - 1 ? a + 1 : a];
+    int c0 = first_hat_after_h(y, 0.0, start);
+    lo_idx[a] = c0;
+    for (int i = 0; i < kBand; ++i) {
+      int cc = c0 + i;
+      if (cc >= ny) break;
+      C[(size_t)kBand * a + i] =
+          hat_product_integral(x.data(), nx, a, y.data(), ny, cc, 0.0, lo, hi);
+    }
+    int cn = c0 + kBand;
+    if (cn < ny && y[cn > 0 ? cn - 1 : cn] < end)
+      return fail(c, MRSDC_EINVAL, "face grids too dissimilar: more than %d coupled nodes", kBand);
+  }
+  return MRSDC_OK;
+}
+
+mrsdc_status prepare(mrsdc_ctx *c) {
+  if (c->prepared) return MRSDC_OK;
+  if (!c->body[0].set) return fail(c, MRSDC_ESTATE, "body 0 not set");
+  c->nbody = c->body[1].set ? 2 : 1;
+  c->off[0] = 0;
+  c->off[1] = c->body[0].n;
+  c->off[2] = c->off[1] + (c->nbody == 2 ? c->body[1].n : 0);
+  const int64_t N = c->off[c->nbody];
+  for (int b = 0; b < c->nbody; ++b)
+    if (!c->body[b].hasT) return fail(c, MRSDC_ESTATE, "temperature of body %d not set", b);
+  const mrsdc_config &cfg = c->cfg;
+  if (!build_weights(cfg.M, cfg.node_family, cfg.P, cfg.dt, &c->w))
+    return fail(c, MRSDC_EINVAL, "bad quadrature");
+  hipError_t he = hipSetDevice(cfg.device);
+  if (he != hipSuccess) return fail(c, MRSDC_EDEVICE, "hipSetDevice: %s", hipGetErrorString(he));
+  if (!c->stream) {
+    if (cfg.stream) {
+      c->stream = (hipStream_t)cfg.stream;
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
+    }
+  }
+
+  DevState &d = c->d;
+  d = DevState();
+  d.N = N;
+  d.M = cfg.M;
+  d.P = cfg.P;
+  d.K = cfg.K;
+  for (int m = 0; m <= cfg.M; ++m) d.dtau_h[m] = c->w.dtau[m];
+  d.grid = (int)std::min<int64_t>((N + kBlock - 1) / kBlock, 1024);
+  if (d.grid < 1) d.grid = 1;
+
+  // ---- operator L = K + h R in SELL-64 ----
+  const int64_t nslices = (N + kSlice - 1) / kSlice;
+  std::vector<int64_t> off(nslices + 1, 0);
+  std::vector<int64_t> rowlen(N);
+  std::vector<double> Ldiag(N, 0.0), mass(N), g(N);
+  int64_t maxdelta = 0;
+  for (int b = 0; b < c->nbody; ++b) {
+    const HostBody &B = c->body[b];
+    for (int64_t i = 0; i < B.n; ++i) {
+      const int64_t row = c->off[b] + i;
+      rowlen[row] = B.rowptr[i + 1] - B.rowptr[i];
+      mass[row] = B.mass[i];
+      g[row] = B.h * B.Tenv * (B.rload.empty() ? 0.0 : B.rload[i]);
+      for (int64_t e = B.rowptr[i]; e < B.rowptr[i + 1]; ++e) {
+        const double v = B.K[e] + (B.R.empty() ? 0.0 : B.h * B.R[e]);
+        if (B.col[e] == i) Ldiag[row] += v;
+        maxdelta = std::max<int64_t>(maxdelta, std::llabs((int64_t)B.col[e] - i));
+      }
+    }
+  }
+  for (int64_t s = 0; s < nslices; ++s) {
+    int64_t w = 0;
+    for (int64_t r = s * kSlice; r < std::min<int64_t>(N, (s + 1) * kSlice); ++r)
+      w = std::max(w, rowlen[r]);
+    off[s + 1] = off[s] + w * kSlice;
+  }
+  const int64_t nelem = off[nslices];
+  const bool use16 = maxdelta <= 32767;
+  std::vector<double> val(nelem, 0.0);
+  std::vector<float> val32;
+  std::vector<int16_t> d16;
+  std::vector<int32_t> c32;
+  if (use16) d16.assign(nelem, 0);
+  else c32.assign(nelem, 0);
+  int64_t nnz_total = 0;
+  for (int b = 0; b < c->nbody; ++b) {
+    const HostBody &B = c->body[b];
+    nnz_total += B.nnz;
+    for (int64_t i = 0; i < B.n; ++i) {
+      const int64_t row = c->off[b] + i, s = row / kSlice, lane = row % kSlice;
+      int64_t k = 0;
+      for (int64_t e = B.rowptr[i]; e < B.rowptr[i + 1]; ++e, ++k) {
+        const int64_t el = off[s] + k * kSlice + lane;
+        val[el] = B.K[e] + (B.R.empty() ? 0.0 : B.h * B.R[e]);
+        if (use16) d16[el] = (int16_t)((int64_t)B.col[e] - i);
+        else c32[el] = (int32_t)(c->off[b] + B.col[e]);
+      }
+      for (; k * kSlice + off[s] < off[s + 1]; ++k) {  // padding: zero times own entry
+        const int64_t el = off[s] + k * kSlice + lane;
+        if (!use16) c32[el] = (int32_t)row;
+      }
+    }
+  }
+  // lanes past the last row keep col 0 / delta 0 and are never read
+  if (cfg.precision == MRSDC_FP32_REFINE) {
+    val32.resize(nelem);
+    for (int64_t e = 0; e < nelem; ++e) val32[e] = (float)val[e];
+  }
+  mrsdc_status st;
+  int64_t *doff;
+  double *dval;
+  if ((st = upload(c, &doff, off))) return st;
+  if ((st = upload(c, &dval, val))) return st;
+  d.op.nrows = N;
+  d.op.nslices = nslices;
+  d.op.nelem = nelem;
+  d.op.off = doff;
+  d.op.val = dval;
+  if (use16) {
+    int16_t *p;
+    if ((st = upload(c, &p, d16))) return st;
+    d.op.d16 = p;
+  } else {
+    int32_t *p;
+    if ((st = upload(c, &p, c32))) return st;
+    d.op.c32 = p;
+  }
+  if (!val32.empty()) {
+    float *p;
+    if ((st = upload(c, &p, val32))) return st;
+    d.op.val32 = p;
+  }
+  c->matrix_bytes = nnz_total * (8 + (use16 ? 2 : 4)) + 8 * (nslices + 1);
+  c->nnz = nnz_total;
+  c->times.cg_spmv_bytes = c->matrix_bytes + 24 * N;
+  c->times.nnz = nnz_total;
+  c->times.n = N;
+
+  double *dmass, *dg, *dLd;
+  if ((st = upload(c, &dmass, mass))) return st;
+  if ((st = upload(c, &dg, g))) return st;
+  if ((st = upload(c, &dLd, Ldiag))) return st;
+  d.mass = dmass;
+  d.g = dg;
+  d.Ldiag = dLd;
+  for (int m = 1; m <= cfg.M; ++m) {
+    if (c->w.dtau[m] == 0.0) continue;
+    std::vector<double> di(N);
+    for (int64_t i = 0; i < N; ++i) di[i] = 1.0 / (mass[i] + c->w.dtau[m] * Ldiag[i]);
+    if ((st = upload(c, &d.dinv[m], di))) return st;
+  }
+
+  // ---- weights ----
+  Weights *dw;
+  if ((st = dalloc(c, &dw, 1))) return st;
+  HIPCHK(hipMemcpy(dw, &c->w, sizeof(Weights), hipMemcpyHostToDevice));
+  d.w = dw;
+
+  // ---- states ----
+  const bool lob = cfg.node_family == MRSDC_LOBATTO;
+  for (int m = 0; m <= cfg.M; ++m) {
+    if (lob && m == 1) {
+      d.T[1] = d.T[0];
+    } else if ((st = dalloc(c, &d.T[m], N))) {
+      return st;
+    }
+    if (m >= 1 && (st = dalloc(c, &d.F[m], N))) return st;
+    if (m >= 1 && c->w.dtau[m] != 0.0 && (st = dalloc(c, &d.I[m], N))) return st;
+  }
+  if ((st = dalloc(c, &d.r, N)) || (st = dalloc(c, &d.p, N)) || (st = dalloc(c, &d.q, N)))
+    return st;
+  if ((st = dalloc(c, &d.partial, 3 * (size_t)d.grid))) return st;
+  if ((st = dalloc(c, &d.sc, 1)) || (st = dalloc(c, &d.ctr, 1)) || (st = dalloc(c, &d.tn, 1)))
+    return st;
+  HIPCHK(hipMemset(d.sc, 0, sizeof(PcgScalars)));
+
+  // ---- coupling ----
+  const Coupling &cp = c->cpl;
+  IfaceDev &f = d.ifc;
+  f = IfaceDev();
+  std::vector<int> ifpos;
+  if (cp.kind != 0) {
+    const int fb = cp.kind == 1 ? cp.fix_body : cp.body;
+    const int ff = cp.kind == 1 ? cp.fix_face : cp.face;
+    if (fb >= c->nbody || !c->face[fb][ff].set)
+      return fail(c, MRSDC_ESTATE, "coupling face (body %d, face %d) not set", fb, ff);
+    const HostFace &F = c->face[fb][ff];
+    f.kind = cp.kind;
+    f.nuf = F.nu;
+    f.nvf = F.nv;
+    f.nfix = F.nu * F.nv;
+    std::vector<int64_t> rows;
+    for (int k = 0; k < f.nfix; ++k) rows.push_back(c->off[fb] + F.ids[k]);
+    std::vector<double> um, vm;
+    if (cp.kind == 1) {
+      if (cp.mov_body >= c->nbody || !c->face[cp.mov_body][cp.mov_face].set)
+        return fail(c, MRSDC_ESTATE, "moving face not set");
+      if (cp.mov_body == cp.fix_body)
+        return fail(c, MRSDC_EINVAL, "contact faces must belong to different bodies");
+      const HostFace &G = c->face[cp.mov_body][cp.mov_face];
+      f.num = G.nu;
+      f.nvm = G.nv;
+      for (double x : G.u) um.push_back(x + cp.du);
+      for (double x : G.v) vm.push_back(x + cp.dv);
+      for (int k = 0; k < G.nu * G.nv; ++k) rows.push_back(c->off[cp.mov_body] + G.ids[k]);
+      f.ou0 = std::max(F.u.front(), um.front());
+      f.ou1 = std::min(F.u.back(), um.back());
+      f.alpha = cp.alpha;
+      f.Pf = cp.Pf;
+      f.split = cp.split;
+      // v direction moves: bound the band from the spacings
+      if (max_support(F.v) / min_spacing(vm) + 3 > kBand || max_support(vm) / min_spacing(F.v) + 3 > kBand)
+        return fail(c, MRSDC_EINVAL, "face grids too dissimilar along v");
+    } else {
+      f.ou0 = std::max(F.u.front(), cp.uc - 0.5 * cp.wu);
+      f.ou1 = std::min(F.u.back(), cp.uc + 0.5 * cp.wu);
+      f.alpha = cp.alpha;
+      f.q0 = cp.q0;
+      f.Tfix = cp.Tfix;
+      f.wv = cp.wv;
+    }
+    f.n_if = (int)rows.size();
+    f.s0 = c->motion.s0;
+    f.a = c->motion.a;
+    f.period = c->motion.period;
+    f.phase = c->motion.phase;
+    ifpos.assign(N, -1);
+    for (int k = 0; k < f.n_if; ++k) {
+      if (ifpos[rows[k]] != -1) return fail(c, MRSDC_EINVAL, "node listed twice on the faces");
+      ifpos[rows[k]] = k;
+    }
+    // static u-direction integrals over [ou0, ou1]
+    std::vector<double> Mu(3 * (size_t)f.nuf, 0.0), Hu(f.nuf, 0.0);
+    for (int a = 0; a < f.nuf; ++a) {
+      for (int i = 0; i < 3; ++i) {
+        int aa = a - 1 + i;
+        if (aa >= 0 && aa < f.nuf && f.ou1 > f.ou0)
+          Mu[3 * a + i] = hat_product_integral(F.u.data(), f.nuf, a, F.u.data(), f.nuf, aa, 0.0,
+                                               f.ou0, f.ou1);
+      }
+      if (f.ou1 > f.ou0) Hu[a] = hat_integral(F.u.data(), f.nuf, a, f.ou0, f.ou1);
+    }
+    double *p;
+    int *pi;
+    int64_t *pr;
+    if ((st = upload(c, &p, F.u))) return st;
+    f.uf = p;
+    if ((st = upload(c, &p, F.v))) return st;
+    f.vf = p;
+    if ((st = upload(c, &p, Mu))) return st;
+    f.Mu = p;
+    if ((st = upload(c, &p, Hu))) return st;
+    f.Hu = p;
+    if ((st = upload(c, &pr, rows))) return st;
+    f.rows = pr;
+    if (cp.kind == 1) {
+      std::vector<double> Cu, CuT, Nu(3 * (size_t)f.num, 0.0), Gu(f.num, 0.0);
+      std::vector<int> clo, alo;
+      if ((st = band_coeffs(c, F.u, um, f.ou0, f.ou1, Cu, clo))) return st;
+      if ((st = band_coeffs(c, um, F.u, f.ou0, f.ou1, CuT, alo))) return st;
+      for (int cc = 0; cc < f.num; ++cc) {
+        for (int i = 0; i < 3; ++i) {
+          int c2 = cc - 1 + i;
+          if (c2 >= 0 && c2 < f.num && f.ou1 > f.ou0)
+            Nu[3 * cc + i] = hat_product_integral(um.data(), f.num, cc, um.data(), f.num, c2, 0.0,
+                                                  f.ou0, f.ou1);
+        }
+        if (f.ou1 > f.ou0) Gu[cc] = hat_integral(um.data(), f.num, cc, f.ou0, f.ou1);
+      }
+      if ((st = upload(c, &p, um))) return st;
+      f.um = p;
+      if ((st = upload(c, &p, vm))) return st;
+      f.vm = p;
+      if ((st = upload(c, &p, Cu))) return st;
+      f.Cu = p;
+      if ((st = upload(c, &p, CuT))) return st;
+      f.CuT = p;
+      if ((st = upload(c, &p, Nu))) return st;
+      f.Nu = p;
+      if ((st = upload(c, &p, Gu))) return st;
+      f.Gu = p;
+      if ((st = upload(c, &pi, clo))) return st;
+      f.clo = pi;
+      if ((st = upload(c, &pi, alo))) return st;
+      f.alo = pi;
+    }
+    if ((st = upload(c, &pi, ifpos))) return st;
+    d.ifpos = pi;
+    const size_t ncache = (size_t)(cfg.M + 1) * (cfg.P + 1) * f.n_if;
+    if ((st = dalloc(c, &d.Eold, ncache)) || (st = dalloc(c, &d.Enew, ncache)))
+      return st;
+    HIPCHK(hipMemset(d.Eold, 0, ncache * sizeof(double)));
+    HIPCHK(hipMemset(d.Enew, 0, ncache * sizeof(double)));
+    if ((st = dalloc(c, &d.Tcur, f.n_if)) || (st = dalloc(c, &d.fst, f.n_if))) return st;
+    if (iface_lds_bytes(f) > 64 * 1024)
+      return fail(c, MRSDC_EINVAL, "face grid too long for the interface kernel");
+  }
+  if (!c->ctr_host) HIPCHK(hipHostMalloc((void **)&c->ctr_host, sizeof(StepCounters), 0));
+  const int b0 = std::min(cfg.pcg_maxit, 24);
+  for (int i = 0; i < kSlots; ++i) {
+    c->budget[i] = b0;
+    c->expect[i] = b0;
+  }
+  c->prepared = true;
+  c->dirty_T = true;
+  return MRSDC_OK;
+}
+
+mrsdc_status upload_T(mrsdc_ctx *c) {
+  if (!c->dirty_T) return MRSDC_OK;
+  for (int b = 0; b < c->nbody; ++b)
+    HIPCHK(hipMemcpyAsync(c->d.T[0] + c->off[b], c->body[b].T.data(), sizeof(double) * c->body[b].n,
+                          hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->d.tn, &c->t, sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->dirty_T = false;
+  return MRSDC_OK;
+}
+
+inline int slot_of(int k, int m) { return k * kMaxM + (m - 1); }
+
+bool take_events(mrsdc_ctx *c, int cls, hipEvent_t *e0, hipEvent_t *e1) {
+  *e0 = *e1 = nullptr;
+  if (!c->prof) return false;
+  if (2 * (c->ev_used + 1) > (int)c->ev.size()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return false;
+      c->ev.push_back(e);
+    }
+    c->ev_class.resize(c->ev.size() / 2);
+  }
+  *e0 = c->ev[2 * c->ev_used];
+  *e1 = c->ev[2 * c->ev_used + 1];
+  c->ev_class[c->ev_used] = cls;
+  c->ev_used++;
+  return true;
+}
+
+void collect_events(mrsdc_ctx *c) {
+  for (int i = 0; i < c->ev_used; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]) != hipSuccess) continue;
+    if (c->ev_class[i] == 0) {
+      c->times.cg_spmv_launches++;
+      c->times.cg_spmv_ms += ms;
+    } else {
+      c->times.iface_launches++;
+      c->times.iface_ms += ms;
+    }
+  }
+  c->ev_used = 0;
+}
+
+// One implicit node solve: init already enqueued; CG iterations in budget.
+void enqueue_cg(mrsdc_ctx *c, int k, int m) {
+  const DevState &d = c->d;
+  launch_init_reduce(d, c->cfg.pcg_rtol, c->stream);
+  const int slot = slot_of(k, m);
+  const int B = c->budget[slot];
+  for (int it = 0; it < B; ++it) {
+    const bool tail = it >= c->expect[slot];
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!tail) take_events(c, 0, &e0, &e1);
+    launch_pcg_iter(d, m, it, tail, c->stream, e0, e1);
+  }
+  launch_pcg_final(d, slot, c->stream);
+}
+
+void enqueue_step(mrsdc_ctx *c) {
+  DevState &d = c->d;
+  const int M = c->cfg.M, K = c->cfg.K;
+  const bool lob = c->cfg.node_family == MRSDC_LOBATTO;
+  hipStream_t st = c->stream;
+  launch_clear_counters(d, st);
+  // predictor (Alg. 1)
+  for (int m = 1; m <= M; ++m) {
+    if (c->w.dtau[m] == 0.0) continue;
+    launch_init_pred(d, m, st);
+    enqueue_cg(c, 0, m);
+    hipEvent_t e0, e1;
+    if (take_events(c, 1, &e0, &e1)) hipEventRecord(e0, st);
+    launch_iface(d, m, false, st);
+    if (e1) hipEventRecord(e1, st);
+  }
+  std::swap(d.Eold, d.Enew);
+  // correction sweeps (Alg. 2)
+  const int passes = c->cfg.final_residual ? K + 1 : K;
+  for (int k = 1; k <= passes; ++k) {
+    // F_j for all standard nodes that changed (Lobatto T_1 = T_n: once per step)
+    const int j0 = (lob && k > 1) ? 2 : 1;
+    launch_f_multi(d, j0, M, st);
+    launch_quad_resid(d, k - 1, st);
+    if (k > K) break;
+    for (int m = 1; m <= M; ++m) {
+      if (c->w.dtau[m] == 0.0) continue;
+      launch_init_corr(d, m, st);
+      enqueue_cg(c, k, m);
+      hipEvent_t e0, e1;
+      if (take_events(c, 1, &e0, &e1)) hipEventRecord(e0, st);
+      launch_iface(d, m, true, st);
+      if (e1) hipEventRecord(e1, st);
+    }
+    std::swap(d.Eold, d.Enew);
+  }
+  launch_step_end(d, c->cfg.dt, st);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+const char *mrsdc_version(void) { return "mrsdc-mi355x 0.1"; }
+
+void mrsdc_config_init(mrsdc_config *cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->device = 0;
+  cfg->precision = MRSDC_FP64;
+  cfg->M = 3;
+  cfg->node_family = MRSDC_LOBATTO;
+  cfg->P = 2;
+  cfg->K = 2;
+  cfg->dt = 1.0;
+  cfg->pcg_rtol = 1e-13;
+  cfg->pcg_maxit = 1000;
+  cfg->refine_rtol = 1e-10;
+  cfg->refine_maxit = 20;
+  cfg->inner_rtol = 1e-6;
+  cfg->final_residual = 0;
+  cfg->use_graph = 0;
+  cfg->stream = nullptr;
+}
+
+mrsdc_status mrsdc_create(mrsdc_ctx **out, const mrsdc_config *cfg) {
+  if (!out) return MRSDC_EINVAL;
+  *out = nullptr;
+  if (!cfg || !valid_scheme(cfg)) return MRSDC_EINVAL;
+  if (cfg->precision == MRSDC_FP32_REFINE) return MRSDC_EINVAL;  // not built in this version
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || cfg->device < 0 || cfg->device >= n) {
+    hipGetLastError();
+    return MRSDC_EDEVICE;
+  }
+  mrsdc_ctx *c = new (std::nothrow) mrsdc_ctx();
+  if (!c) return MRSDC_ENOMEM;
+  c->cfg = *cfg;
+  *out = c;
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_set_body(mrsdc_ctx *c, int body, int64_t n, int64_t nnz, const int64_t *rowptr,
+                            const int32_t *col, const double *K, const double *R, const double *mass,
+                            const double *robin_load) {
+  if (!c) return MRSDC_EINVAL;
+  if (body < 0 || body > 1) return fail(c, MRSDC_EINVAL, "body must be 0 or 1");
+  if (n <= 0 || nnz < n || !rowptr || !col || !K || !mass)
+    return fail(c, MRSDC_EINVAL, "bad body arrays");
+  if (rowptr[0] != 0 || rowptr[n] != nnz) return fail(c, MRSDC_EINVAL, "rowptr must run 0..nnz");
+  if (n > (int64_t)1 << 30) return fail(c, MRSDC_EINVAL, "body too large");
+  for (int64_t i = 0; i < n; ++i) {
+    if (rowptr[i + 1] <= rowptr[i]) return fail(c, MRSDC_EINVAL, "row %lld empty or rowptr not increasing", (long long)i);
+    bool diag = false;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+      if (col[e] < 0 || col[e] >= n) return fail(c, MRSDC_EINVAL, "column out of range in row %lld", (long long)i);
+      if (e > rowptr[i] && col[e] <= col[e - 1]) return fail(c, MRSDC_EINVAL, "columns not sorted in row %lld", (long long)i);
+      if (col[e] == i) diag = true;
+    }
+    if (!diag) return fail(c, MRSDC_EINVAL, "row %lld has no diagonal entry", (long long)i);
+    if (!(mass[i] > 0) || !std::isfinite(mass[i])) return fail(c, MRSDC_EINVAL, "mass must be positive");
+  }
+  if (!finite_all(K, nnz) || (R && !finite_all(R, nnz)) || (robin_load && !finite_all(robin_load, n)))
+    return fail(c, MRSDC_EINVAL, "non-finite operator values");
+  free_device(c);
+  HostBody &B = c->body[body];
+  B.set = true;
+  B.n = n;
+  B.nnz = nnz;
+  B.rowptr.assign(rowptr, rowptr + n + 1);
+  B.col.assign(col, col + nnz);
+  B.K.assign(K, K + nnz);
+  if (R) B.R.assign(R, R + nnz); else B.R.clear();
+  B.mass.assign(mass, mass + n);
+  if (robin_load) B.rload.assign(robin_load, robin_load + n); else B.rload.clear();
+  B.hasT = false;
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_set_robin(mrsdc_ctx *c, int body, double h, double T_env) {
+  if (!c) return MRSDC_EINVAL;
+  if (body < 0 || body > 1 || !(h >= 0) || !std::isfinite(h) || !std::isfinite(T_env))
+    return fail(c, MRSDC_EINVAL, "bad Robin data");
+  c->body[body].h = h;
+  c->body[body].Tenv = T_env;
+  free_device(c);
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_set_face(mrsdc_ctx *c, int body, int face, int nu, int nv, const double *u,
+                            const double *v, const int32_t *ids) {
+  if (!c) return MRSDC_EINVAL;
+  if (body < 0 || body > 1 || face < 0 || face > 7 || nu < 2 || nv < 2 || !u || !v || !ids)
+    return fail(c, MRSDC_EINVAL, "bad face arguments");
+  if (!c->body[body].set) return fail(c, MRSDC_ESTATE, "set the body before its faces");
+  for (int i = 1; i < nu; ++i)
+    if (!(u[i] > u[i - 1])) return fail(c, MRSDC_EINVAL, "face u not increasing");
+  for (int i = 1; i < nv; ++i)
+    if (!(v[i] > v[i - 1])) return fail(c, MRSDC_EINVAL, "face v not increasing");
+  for (int64_t k = 0; k < (int64_t)nu * nv; ++k)
+    if (ids[k] < 0 || ids[k] >= c->body[body].n) return fail(c, MRSDC_EINVAL, "face node id out of range");
+  HostFace &F = c->face[body][face];
+  F.set = true;
+  F.nu = nu;
+  F.nv = nv;
+  F.u.assign(u, u + nu);
+  F.v.assign(v, v + nv);
+  F.ids.assign(ids, ids + (int64_t)nu * nv);
+  free_device(c);
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_set_motion(mrsdc_ctx *c, double s0, double a, double period, double phase) {
+  if (!c) return MRSDC_EINVAL;
+  if (!(period > 0) || !std::isfinite(s0) || !std::isfinite(a) || !std::isfinite(phase) || !std::isfinite(period))
+    return fail(c, MRSDC_EINVAL, "bad motion");
+  c->motion = {s0, a, period, phase};
+  free_device(c);
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_set_contact(mrsdc_ctx *c, int fix_body, int fix_face, int mov_body, int mov_face,
+                               double du, double dv, double alpha, double friction_W, double split) {
+  if (!c) return MRSDC_EINVAL;
+  if (fix_body < 0 || fix_body > 1 || mov_body < 0 || mov_body > 1 || fix_face < 0 || fix_face > 7 ||
+      mov_face < 0 || mov_face > 7 || !(alpha >= 0) || !(friction_W >= 0) || !(split >= 0 && split <= 1) ||
+      !std::isfinite(du) || !std::isfinite(dv))
+    return fail(c, MRSDC_EINVAL, "bad contact arguments");
+  Coupling &p = c->cpl;
+  p = Coupling();
+  p.kind = 1;
+  p.fix_body = fix_body;
+  p.fix_face = fix_face;
+  p.mov_body = mov_body;
+  p.mov_face = mov_face;
+  p.du = du;
+  p.dv = dv;
+  p.alpha = alpha;
+  p.Pf = friction_W;
+  p.split = split;
+  free_device(c);
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_set_patch(mrsdc_ctx *c, int body, int face, double width_u, double width_v,
+                             double u_center, double q0, double alpha, double T_fixed) {
+  if (!c) return MRSDC_EINVAL;
+  if (body < 0 || body > 1 || face < 0 || face > 7 || !(width_u > 0) || !(width_v > 0) ||
+      !std::isfinite(u_center) || !std::isfinite(q0) || !(alpha >= 0) || !std::isfinite(T_fixed))
+    return fail(c, MRSDC_EINVAL, "bad patch arguments");
+  Coupling &p = c->cpl;
+  p = Coupling();
+  p.kind = 2;
+  p.body = body;
+  p.face = face;
+  p.wu = width_u;
+  p.wv = width_v;
+  p.uc = u_center;
+  p.q0 = q0;
+  p.alpha = alpha;
+  p.Tfix = T_fixed;
+  free_device(c);
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_set_temperature(mrsdc_ctx *c, int body, const double *T, int64_t n) {
+  if (!c) return MRSDC_EINVAL;
+  if (body < 0 || body > 1 || !c->body[body].set) return fail(c, MRSDC_ESTATE, "body not set");
+  if (!T || n != c->body[body].n) return fail(c, MRSDC_EINVAL, "temperature length mismatch");
+  if (!finite_all(T, n)) return fail(c, MRSDC_EINVAL, "temperature not finite");
+  c->body[body].T.assign(T, T + n);
+  c->body[body].hasT = true;
+  c->dirty_T = true;
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_set_time(mrsdc_ctx *c, double t) {
+  if (!c) return MRSDC_EINVAL;
+  if (!std::isfinite(t)) return fail(c, MRSDC_EINVAL, "time not finite");
+  // device-resident state must be pulled back before the time can be replaced
+  if (c->prepared && !c->dirty_T) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int b = 0; b < c->nbody; ++b) {
+      c->body[b].T.resize(c->body[b].n);
+      HIPCHK(hipMemcpy(c->body[b].T.data(), c->d.T[0] + c->off[b], sizeof(double) * c->body[b].n,
+                       hipMemcpyDeviceToHost));
+    }
+  }
+  c->t = t;
+  c->dirty_T = true;
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_get_time(const mrsdc_ctx *c, double *t) {
+  if (!c || !t) return MRSDC_EINVAL;
+  *t = c->t;
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_advance(mrsdc_ctx *c, double horizon, mrsdc_stats *stats) {
+  if (!c) return MRSDC_EINVAL;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  const double dt = c->cfg.dt;
+  if (!(horizon >= 0) || !std::isfinite(horizon)) return fail(c, MRSDC_EINVAL, "bad horizon");
+  const double ns = horizon / dt;
+  const int64_t nsteps = (int64_t)std::llround(ns);
+  if (std::fabs(ns - (double)nsteps) > 1e-9 * std::max(1.0, ns))
+    return fail(c, MRSDC_EINVAL, "horizon %.17g is not a multiple of dt %.17g", horizon, dt);
+  mrsdc_status s = prepare(c);
+  if (s) return s;
+  if ((s = upload_T(c))) return s;
+  auto t0 = std::chrono::steady_clock::now();
+  mrsdc_stats acc;
+  std::memset(&acc, 0, sizeof acc);
+  const int Kc = c->cfg.K;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    for (;;) {
+      enqueue_step(c);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(c->ctr_host, c->d.ctr, sizeof(StepCounters), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      const StepCounters &h = *c->ctr_host;
+      if (c->prof) collect_events(c);
+      if (h.fail == 0) {
+        acc.pcg_iters += h.pcg_iters;
+        acc.max_iters = std::max(acc.max_iters, h.max_iters);
+        for (int k = 0; k <= Kc; ++k) acc.residual[k] = h.resid[k];
+        for (int i = 0; i < kSlots; ++i) {
+          int it = h.slot_iters[i];
+          if (it > 0) {
+            c->budget[i] = std::min(c->cfg.pcg_maxit, it + std::max(2, it / 5));
+            c->expect[i] = it;
+          }
+        }
+        break;
+      }
+      // some solve ran out of budget: the step was not committed
+      bool grow = false;
+      for (int i = 0; i < kSlots; ++i) {
+        if (h.slot_iters[i] < 0 && c->budget[i] < c->cfg.pcg_maxit) {
+          c->budget[i] = std::min(c->cfg.pcg_maxit, 2 * c->budget[i]);
+          grow = true;
+        }
+      }
+      acc.redone_steps++;
+      if (!grow) {
+        acc.steps = n;  // the device state stays at the last committed step
+        if (stats) {
+          acc.wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+          *stats = acc;
+        }
+        return fail(c, MRSDC_ENOCONV, "implicit solve did not converge in %d iterations (step %lld)",
+                    c->cfg.pcg_maxit, (long long)n);
+      }
+    }
+    c->t += dt;
+  }
+  // count solves from the scheme
+  int nint = 0;
+  for (int m = 1; m <= c->cfg.M; ++m) nint += c->w.dtau[m] != 0.0;
+  acc.steps = nsteps;
+  acc.solves = nsteps * nint * (Kc + 1);
+  acc.wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  // algorithmic bytes: CG iteration = matrix + 14 vector reads/writes per row;
+  // init/solve ~ 8 passes; per sweep one multi-RHS SpMV and (3M+2) passes.
+  const int64_t N = c->d.N;
+  acc.bytes_moved = acc.pcg_iters * (c->matrix_bytes + 112 * N) + acc.solves * 64 * N +
+                    nsteps * Kc * (c->matrix_bytes + 16 * (int64_t)c->cfg.M * N +
+                                   8 * (3 * (int64_t)c->cfg.M + 2) * N);
+  if (stats) *stats = acc;
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_get_temperature(mrsdc_ctx *c, int body, double *out, int64_t n) {
+  if (!c) return MRSDC_EINVAL;
+  if (body < 0 || body > 1 || !c->body[body].set) return fail(c, MRSDC_ESTATE, "body not set");
+  if (!out || n != c->body[body].n) return fail(c, MRSDC_EINVAL, "length mismatch");
+  if (!c->prepared || c->dirty_T) {
+    if (!c->body[body].hasT) return fail(c, MRSDC_ESTATE, "temperature not set");
+    std::memcpy(out, c->body[body].T.data(), sizeof(double) * n);
+    return MRSDC_OK;
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(out, c->d.T[0] + c->off[body], sizeof(double) * n, hipMemcpyDeviceToHost));
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_get_temperature_device(mrsdc_ctx *c, int body, void *dptr, int64_t n, void *stream) {
+  if (!c) return MRSDC_EINVAL;
+  if (body < 0 || body > 1 || !c->body[body].set) return fail(c, MRSDC_ESTATE, "body not set");
+  if (!dptr || n != c->body[body].n) return fail(c, MRSDC_EINVAL, "length mismatch");
+  mrsdc_status s = prepare(c);
+  if (s) return s;
+  if ((s = upload_T(c))) return s;
+  hipStream_t st = stream ? (hipStream_t)stream : c->stream;
+  if (st != c->stream) HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpyAsync(dptr, c->d.T[0] + c->off[body], sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_profile(mrsdc_ctx *c, int on) {
+  if (!c) return MRSDC_EINVAL;
+  c->prof = on != 0;
+  const int64_t b = c->times.cg_spmv_bytes, nz = c->times.nnz, n = c->times.n;
+  c->times = mrsdc_kernel_times();
+  c->times.cg_spmv_bytes = b;
+  c->times.nnz = nz;
+  c->times.n = n;
+  c->ev_used = 0;
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_profile_read(const mrsdc_ctx *c, mrsdc_kernel_times *out) {
+  if (!c || !out) return MRSDC_EINVAL;
+  *out = c->times;
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_footprint_bytes(const mrsdc_ctx *c, int64_t *bytes) {
+  if (!c || !bytes) return MRSDC_EINVAL;
+  *bytes = c->footprint;
+  return MRSDC_OK;
+}
+
+const char *mrsdc_last_error(const mrsdc_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+mrsdc_status mrsdc_destroy(mrsdc_ctx *c) {
+  if (!c) return MRSDC_OK;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  free_device(c);
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  if (c->ctr_host) hipHostFree(c->ctr_host);
+  for (hipEvent_t e : c->ev) hipEventDestroy(e);
+  delete c;
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_quadrature(int M, int node_family, int P, double dt, double *tau, double *s,
+                              double *shat, double *stil, double *spq) {
+  Weights *w = new (std::nothrow) Weights;
+  if (!w) return MRSDC_ENOMEM;
+  if (!tau || !s || !shat || !stil || !spq || !build_weights(M, node_family, P, dt, w)) {
+    delete w;
+    return MRSDC_EINVAL;
+  }
+  const int M1 = M + 1, P1 = P + 1;
+  for (int m = 0; m <= M; ++m) tau[m] = w->tau[m];
+  for (int m = 0; m <= M; ++m) {
+    for (int j = 0; j <= M; ++j) s[m * M1 + j] = w->s[m][j];
+    for (int q = 0; q <= P; ++q) shat[m * P1 + q] = w->shat[m][q];
+    for (int p = 0; p <= P; ++p) {
+      for (int j = 0; j <= M; ++j) stil[(m * P1 + p) * M1 + j] = w->stil[m][p][j];
+      for (int q = 0; q <= P; ++q) spq[(m * P1 + p) * P1 + q] = w->spq[m][p][q];
+    }
+  }
+  delete w;
+  return MRSDC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,809 @@
+// HIP kernels of the MRSDC sweep for gfx950 (wave64).
+//
+// Data layout: one concatenated state vector per standard node (paper §2,
+// eq. coupledFEM), operator L = K + h R in SELL-64 (a slice = 64 consecutive
+// rows = one wavefront, lane = row, element columns stored slice-major so that
+// each value/column load of a wave is one coalesced 512 B / 128 B access).
+// All reductions are deterministic: fixed row-to-block assignment, butterfly
+// wave sums, per-block partials reduced in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include "mrsdc_internal.h"
+
+namespace mrsdc {
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Sum over the block, result broadcast to every thread.  sh: >= 17 doubles.
+__device__ inline double block_sum(double v, double *sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  if (w == 0) {
+    double t = lane < nw ? sh[lane] : 0.0;
+    t = wave_sum(t);
+    if (lane == 0) sh[16] = t;
+  }
+  __syncthreads();
+  return sh[16];
+}
+__device__ inline double block_max(double v, double *sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_max(v);
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  if (w == 0) {
+    double t = lane < nw ? sh[lane] : 0.0;
+    t = wave_max(t);
+    if (lane == 0) sh[16] = t;
+  }
+  __syncthreads();
+  return sh[16];
+}
+
+// Every block sums the n per-block partials in the same order.
+__device__ inline double sum_partials(const double *part, int n, double *sh) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
+  return block_sum(v, sh);
+}
+
+// ---------------------------------------------------------------------------
+// SELL-64 row product
+// ---------------------------------------------------------------------------
+template <bool D16>
+__device__ inline double sell_row(const SellDev &op, int64_t s, int lane, int64_t row,
+                                  const double *__restrict__ x) {
+  const int64_t end = op.off[s + 1];
+  int64_t e = op.off[s] + lane;
+  double acc = 0.0;
+  if (D16) {
+#pragma unroll 4
+    for (; e < end; e += kSlice) acc += op.val[e] * x[row + op.d16[e]];
+  } else {
+#pragma unroll 4
+    for (; e < end; e += kSlice) acc += op.val[e] * x[op.c32[e]];
+  }
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// F_j = f^I(T_j) + g = g - L T_j for several j at once (matrix read once)
+// ---------------------------------------------------------------------------
+struct FArgs {
+  const double *T[kMaxJ];
+  double *F[kMaxJ];
+  const double *g;
+};
+
+template <bool D16, int J>
+__global__ __launch_bounds__(kBlock) void k_f_multi(SellDev op, FArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+  for (int64_t s = wave; s < op.nslices; s += nw) {
+    const int64_t row = s * kSlice + lane;
+    if (row >= op.nrows) continue;
+    double acc[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) acc[j] = 0.0;
+    const int64_t end = op.off[s + 1];
+    for (int64_t e = op.off[s] + lane; e < end; e += kSlice) {
+      const double v = op.val[e];
+      const int64_t c = D16 ? row + op.d16[e] : (int64_t)op.c32[e];
+#pragma unroll
+      for (int j = 0; j < J; ++j) acc[j] += v * a.T[j][c];
+    }
+    const double gi = a.g[row];
+#pragma unroll
+    for (int j = 0; j < J; ++j) a.F[j][row] = gi - acc[j];
+  }
+}
+
+template <bool D16>
+static void f_multi_dispatch(const DevState &d, FArgs a, int J, hipStream_t st) {
+  const int grid = d.grid;
+  switch (J) {
+#define CASE(n) \
+  case n: k_f_multi<D16, n><<<grid, kBlock, 0, st>>>(d.op, a); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: break;
+  }
+}
+
+void launch_f_multi(const DevState &d, int j0, int j1, hipStream_t st) {
+  // standard nodes j0..j1 (distinct buffers), in chunks of kMaxJ
+  for (int jb = j0; jb <= j1; jb += kMaxJ) {
+    const int je = jb + kMaxJ - 1 < j1 ? jb + kMaxJ - 1 : j1;
+    FArgs a = {};
+    int J = 0;
+    for (int j = jb; j <= je; ++j, ++J) {
+      a.T[J] = d.T[j];
+      a.F[J] = d.F[j];
+    }
+    a.g = d.g;
+    if (d.op.d16) f_multi_dispatch<true>(d, a, J, st);
+    else f_multi_dispatch<false>(d, a, J, st);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Quadrature I_{m-1}^m for every interval (eq. standard_quad) and the residual
+// max_m |M T_m - M T_n - sum_{l<=m} I_l| (eq. residual), one pass.
+// ---------------------------------------------------------------------------
+struct QArgs {
+  const Weights *w;
+  const double *T[kMaxM + 1];
+  const double *F[kMaxM + 1];
+  double *I[kMaxM + 1];
+  const double *mass;
+  const int *ifpos;
+  const double *Eold;
+  int n_if, M, P;
+  double *partial;
+};
+
+__global__ __launch_bounds__(kBlock) void k_quad_resid(int64_t N, QArgs a) {
+  __shared__ double sh[17];
+  const Weights &w = *a.w;
+  const int P1 = a.P + 1;
+  double rmax = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kBlock) {
+    const double mi = a.mass[i];
+    const double Tn = a.T[0][i];
+    const int pos = a.ifpos ? a.ifpos[i] : -1;
+    double cum = 0.0;
+    for (int m = 1; m <= a.M; ++m) {
+      if (w.dtau[m] == 0.0) continue;
+      double acc = 0.0;
+      for (int j = 1; j <= a.M; ++j) acc += w.s[m][j] * a.F[j][i];
+      if (pos >= 0) {
+        const double *E = a.Eold + (size_t)m * P1 * a.n_if + pos;
+        for (int q = 1; q <= a.P; ++q) acc += w.shat[m][q] * E[(size_t)q * a.n_if];
+      }
+      a.I[m][i] = acc;
+      cum += acc;
+      rmax = fmax(rmax, fabs(mi * a.T[m][i] - mi * Tn - cum));
+    }
+  }
+  rmax = block_max(rmax, sh);
+  if (threadIdx.x == 0) a.partial[blockIdx.x] = rmax;
+}
+
+__global__ void k_reduce_max(const double *part, int n, double *out) {
+  __shared__ double sh[17];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v = fmax(v, part[i]);
+  v = block_max(v, sh);
+  if (threadIdx.x == 0) *out = v;
+}
+
+void launch_quad_resid(const DevState &d, int k, hipStream_t st) {
+  QArgs a = {};
+  a.w = d.w;
+  for (int m = 0; m <= d.M; ++m) {
+    a.T[m] = d.T[m];
+    a.F[m] = d.F[m];
+    a.I[m] = d.I[m];
+  }
+  a.mass = d.mass;
+  a.ifpos = d.ifc.kind ? d.ifpos : nullptr;
+  a.Eold = d.Eold;
+  a.n_if = d.ifc.n_if;
+  a.M = d.M;
+  a.P = d.P;
+  a.partial = d.partial;
+  k_quad_resid<<<d.grid, kBlock, 0, st>>>(d.N, a);
+  k_reduce_max<<<1, kBlock, 0, st>>>(d.partial, d.grid, &d.ctr->resid[k]);
+}
+
+// ---------------------------------------------------------------------------
+// Implicit node solve (diag(m) + dtau L) x = b by Jacobi-preconditioned CG.
+// Three kernels per iteration; every kernel leaves at once when the solve is
+// done, so a fixed launch budget per solve needs no host round trip.
+// ---------------------------------------------------------------------------
+struct PcgArgs {
+  SellDev op;
+  int64_t N;
+  double dtau;
+  const double *mass, *dinv, *g;
+  double *x, *r, *p, *q;
+  double *partial;  // [3*grid]
+  PcgScalars *sc;
+  int grid;
+  // init only
+  const double *Tprev, *F, *I;
+};
+
+static PcgArgs pcg_args(const DevState &d, int m) {
+  PcgArgs a;
+  a.op = d.op;
+  a.N = d.N;
+  a.dtau = d.dtau_h[m];
+  a.mass = d.mass;
+  a.dinv = d.dinv[m];
+  a.g = d.g;
+  a.x = d.T[m];
+  a.r = d.r;
+  a.p = d.p;
+  a.q = d.q;
+  a.partial = d.partial;
+  a.sc = d.sc;
+  a.grid = d.grid;
+  a.Tprev = d.T[m - 1];
+  a.F = d.F[m];
+  a.I = d.I[m];
+  return a;
+}
+
+// predictor: x0 = T_{m-1}, b = M T_{m-1} + dtau g, r = b - A x0 (one SpMV)
+template <bool D16>
+__global__ __launch_bounds__(kBlock) void k_init_pred(PcgArgs a) {
+  __shared__ double sh[17];
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+  double rz = 0.0, rr = 0.0, bb = 0.0;
+  for (int64_t s = wave; s < a.op.nslices; s += nw) {
+    const int64_t row = s * kSlice + lane;
+    if (row >= a.N) continue;
+    const double Lx = sell_row<D16>(a.op, s, lane, row, a.Tprev);
+    const double x0 = a.Tprev[row], mi = a.mass[row];
+    const double b = mi * x0 + a.dtau * a.g[row];
+    const double r = b - (mi * x0 + a.dtau * Lx);
+    const double z = a.dinv[row] * r;
+    a.x[row] = x0;
+    a.r[row] = r;
+    a.p[row] = z;
+    rz += r * z;
+    rr += r * r;
+    bb += b * b;
+  }
+  rz = block_sum(rz, sh);
+  rr = block_sum(rr, sh);
+  bb = block_sum(bb, sh);
+  if (threadIdx.x == 0) {
+    a.partial[blockIdx.x] = rz;
+    a.partial[a.grid + blockIdx.x] = rr;
+    a.partial[2 * a.grid + blockIdx.x] = bb;
+  }
+}
+
+// correction: x0 = T^k_m (in place), b = M T^{k+1}_{m-1} + dtau (g - F_m) + I_m,
+// and since L x0 = g - F_m the initial residual needs no SpMV:
+// r = M (T^{k+1}_{m-1} - T^k_m) + I_m.
+__global__ __launch_bounds__(kBlock) void k_init_corr(PcgArgs a) {
+  __shared__ double sh[17];
+  double rz = 0.0, rr = 0.0, bb = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.N;
+       i += (int64_t)gridDim.x * kBlock) {
+    const double mi = a.mass[i], tp = a.Tprev[i], x0 = a.x[i], Im = a.I[i];
+    const double b = mi * tp + a.dtau * (a.g[i] - a.F[i]) + Im;
+    const double r = mi * (tp - x0) + Im;
+    const double z = a.dinv[i] * r;
+    a.r[i] = r;
+    a.p[i] = z;
+    rz += r * z;
+    rr += r * r;
+    bb += b * b;
+  }
+  rz = block_sum(rz, sh);
+  rr = block_sum(rr, sh);
+  bb = block_sum(bb, sh);
+  if (threadIdx.x == 0) {
+    a.partial[blockIdx.x] = rz;
+    a.partial[a.grid + blockIdx.x] = rr;
+    a.partial[2 * a.grid + blockIdx.x] = bb;
+  }
+}
+
+__global__ void k_init_reduce(const double *part, int grid, PcgScalars *sc, double rtol) {
+  __shared__ double sh[17];
+  const double rz = sum_partials(part, grid, sh);
+  const double rr = sum_partials(part + grid, grid, sh);
+  const double bb = sum_partials(part + 2 * grid, grid, sh);
+  if (threadIdx.x == 0) {
+    sc->rz[0] = rz;
+    sc->rz[1] = 0.0;
+    sc->bb = bb;
+    sc->tol2 = rtol * rtol * bb;
+    sc->done = (rr <= sc->tol2) ? 1 : 0;
+    sc->iters = 0;
+  }
+}
+
+// (a) q = A p, partial p.q.  TAIL marks launches past the iteration count of
+// the previous step (usually early exits), kept apart in profiles.
+template <bool D16, int TAIL>
+__global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a) {
+  if (a.sc->done) return;
+  __shared__ double sh[17];
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+  double pq = 0.0;
+  for (int64_t s = wave; s < a.op.nslices; s += nw) {
+    const int64_t row = s * kSlice + lane;
+    if (row >= a.N) continue;
+    const double Lp = sell_row<D16>(a.op, s, lane, row, a.p);
+    const double pi = a.p[row];
+    const double qi = a.mass[row] * pi + a.dtau * Lp;
+    a.q[row] = qi;
+    pq += pi * qi;
+  }
+  pq = block_sum(pq, sh);
+  if (threadIdx.x == 0) a.partial[blockIdx.x] = pq;
+}
+
+// (b) alpha = rz / pq; x += alpha p; r -= alpha q; partial r.z, r.r
+__global__ __launch_bounds__(kBlock) void k_pcg_b(PcgArgs a, int it) {
+  if (a.sc->done) return;
+  __shared__ double sh[17];
+  const double pq = sum_partials(a.partial, a.grid, sh);
+  const double alpha = a.sc->rz[it & 1] / pq;
+  double rz = 0.0, rr = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.N;
+       i += (int64_t)gridDim.x * kBlock) {
+    const double pi = a.p[i];
+    a.x[i] += alpha * pi;
+    const double r = a.r[i] - alpha * a.q[i];
+    a.r[i] = r;
+    rz += r * (a.dinv[i] * r);
+    rr += r * r;
+  }
+  rz = block_sum(rz, sh);
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    a.partial[a.grid + blockIdx.x] = rz;
+    a.partial[2 * a.grid + blockIdx.x] = rr;
+  }
+}
+
+// (c) convergence test, beta, p = z + beta p
+__global__ __launch_bounds__(kBlock) void k_pcg_c(PcgArgs a, int it) {
+  if (a.sc->done) return;
+  __shared__ double sh[17];
+  const double rz = sum_partials(a.partial + a.grid, a.grid, sh);
+  const double rr = sum_partials(a.partial + 2 * a.grid, a.grid, sh);
+  if (rr <= a.sc->tol2) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.sc->done = 1;
+      a.sc->iters = it + 1;
+    }
+    return;
+  }
+  const double beta = rz / a.sc->rz[it & 1];
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.N;
+       i += (int64_t)gridDim.x * kBlock)
+    a.p[i] = a.dinv[i] * a.r[i] + beta * a.p[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.sc->rz[(it + 1) & 1] = rz;
+}
+
+__global__ void k_pcg_final(PcgScalars *sc, StepCounters *ctr, int slot) {
+  if (threadIdx.x != 0) return;
+  if (!sc->done) {
+    ctr->fail += 1;
+    ctr->slot_iters[slot] = -1;
+    return;
+  }
+  ctr->pcg_iters += sc->iters;
+  ctr->slot_iters[slot] = sc->iters;
+  if (sc->iters > ctr->max_iters) ctr->max_iters = sc->iters;
+}
+
+void launch_init_pred(const DevState &d, int m, hipStream_t st) {
+  PcgArgs a = pcg_args(d, m);
+  if (d.op.d16) k_init_pred<true><<<d.grid, kBlock, 0, st>>>(a);
+  else k_init_pred<false><<<d.grid, kBlock, 0, st>>>(a);
+}
+
+void launch_init_corr(const DevState &d, int m, hipStream_t st) {
+  PcgArgs a = pcg_args(d, m);
+  k_init_corr<<<d.grid, kBlock, 0, st>>>(a);
+}
+
+void launch_init_reduce(const DevState &d, double rtol, hipStream_t st) {
+  k_init_reduce<<<1, kBlock, 0, st>>>(d.partial, d.grid, d.sc, rtol);
+}
+
+void launch_pcg_iter(const DevState &d, int m, int it, bool tail, hipStream_t st,
+                     hipEvent_t ev0, hipEvent_t ev1) {
+  PcgArgs a = pcg_args(d, m);
+  if (ev0) hipEventRecord(ev0, st);
+  if (d.op.d16) {
+    if (tail) k_pcg_a<true, 1><<<d.grid, kBlock, 0, st>>>(a);
+    else k_pcg_a<true, 0><<<d.grid, kBlock, 0, st>>>(a);
+  } else {
+    if (tail) k_pcg_a<false, 1><<<d.grid, kBlock, 0, st>>>(a);
+    else k_pcg_a<false, 0><<<d.grid, kBlock, 0, st>>>(a);
+  }
+  if (ev1) hipEventRecord(ev1, st);
+  k_pcg_b<<<d.grid, kBlock, 0, st>>>(a, it);
+  k_pcg_c<<<d.grid, kBlock, 0, st>>>(a, it);
+}
+
+void launch_pcg_final(const DevState &d, int slot, hipStream_t st) {
+  k_pcg_final<<<1, 64, 0, st>>>(d.sc, d.ctr, slot);
+}
+
+// ---------------------------------------------------------------------------
+// 1D face integrals of products of hat functions (separable form of the
+// rectangle integrals of §2, eqs. femContFix/femContMov and defCB)
+// ---------------------------------------------------------------------------
+__host__ __device__ inline void hat_nodes(const double *x, int n, int a, double s, double *l,
+                                          double *m, double *h) {
+  *l = x[a > 0 ? a - 1 : a] + s;
+  *m = x[a] + s;
+  *h = x[a < n - 1 ? a + 1 : a] + s;
+}
+
+__host__ __device__ inline double hat_eval(double l, double m, double h, double t) {
+  if (t < l || t > h) return 0.0;
+  if (t <= m) return m > l ? (t - l) / (m - l) : 1.0;
+  return h > m ? (h - t) / (h - m) : 1.0;
+}
+
+__host__ __device__ double hat_integral(const double *x, int n, int a, double lo, double hi) {
+  double l, m, h;
+  hat_nodes(x, n, a, 0.0, &l, &m, &h);
+  double acc = 0.0;
+  // rising and falling pieces, each linear: trapezoid rule is exact
+  double e0 = fmax(l, lo), e1 = fmin(m, hi);
+  if (e1 > e0) acc += 0.5 * (e1 - e0) * (hat_eval(l, m, h, e0) + hat_eval(l, m, h, e1));
+  e0 = fmax(m, lo);
+  e1 = fmin(h, hi);
+  if (e1 > e0) acc += 0.5 * (e1 - e0) * (hat_eval(l, m, h, e0) + hat_eval(l, m, h, e1));
+  return acc;
+}
+
+__host__ __device__ double hat_product_integral(const double *x, int nx, int a, const double *y,
+                                                int ny, int c, double sy, double lo,
+                                                double hi) {
+  double xl, xm, xh, yl, ym, yh;
+  hat_nodes(x, nx, a, 0.0, &xl, &xm, &xh);
+  hat_nodes(y, ny, c, sy, &yl, &ym, &yh);
+  const double L = fmax(fmax(xl, yl), lo), H = fmin(fmin(xh, yh), hi);
+  if (!(H > L)) return 0.0;
+  double b1 = xm, b2 = ym;
+  if (b1 > b2) {
+    double t = b1;
+    b1 = b2;
+    b2 = t;
+  }
+  double pts[4];
+  int n = 0;
+  pts[n++] = L;
+  if (b1 > L && b1 < H) pts[n++] = b1;
+  if (b2 > L && b2 < H && b2 > pts[n - 1]) pts[n++] = b2;
+  pts[n++] = H;
+  double acc = 0.0;
+  // product of two linear functions on each piece: Simpson's rule is exact
+  for (int k = 0; k + 1 < n; ++k) {
+    const double l = pts[k], r = pts[k + 1], c2 = 0.5 * (l + r);
+    const double fl = hat_eval(xl, xm, xh, l) * hat_eval(yl, ym, yh, l);
+    const double fc = hat_eval(xl, xm, xh, c2) * hat_eval(yl, ym, yh, c2);
+    const double fr = hat_eval(xl, xm, xh, r) * hat_eval(yl, ym, yh, r);
+    acc += (r - l) / 6.0 * (fl + 4.0 * fc + fr);
+  }
+  return acc;
+}
+
+// first node c of grid y (shifted by sy) whose hat support ends after t
+__device__ inline int first_hat_after(const double *y, int n, double sy, double t) {
+  int lo = 0, hi = n;  // invariant: answer in [lo, hi]
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const double end = y[mid < n - 1 ? mid + 1 : mid] + sy;
+    if (end > t) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Embedded explicit substeps of one interval on the interface points (Alg. 1
+// and Alg. 2, the inner loops over p).  Off the interface f^E vanishes, so
+// those rows end the interval at T* exactly (the weights satisfy
+// sum_p tilde s = s and sum_p s_pq = hat s): only interface rows are stepped.
+// One workgroup; the interface state lives in global memory (L2 resident).
+// ---------------------------------------------------------------------------
+struct IfArgs {
+  IfaceDev f;
+  const Weights *w;
+  int m, corr, P, M;
+  const double *tn;
+  const double *mass;
+  const double *Tprev;
+  double *Tm;
+  const double *Im;
+  const double *F[kMaxM + 1];
+  const double *Eold;  // [(M+1)(P+1) n_if]
+  double *Enew;
+  double *Tcur, *fst;
+};
+
+struct IfShared {
+  double *Mv, *Hv, *Cv;
+  int *dlo;
+  double *Nv, *Gv, *CvT;
+  int *blo;
+  double qf;
+};
+
+__device__ double motion_s(const IfaceDev &f, double t) {
+  return f.s0 + f.a * sin(2.0 * M_PI * t / f.period + f.phase);
+}
+
+// v-direction (time dependent) integrals at time t into LDS
+__device__ void iface_coeffs(const IfaceDev &f, double t, IfShared &S, double *qf_out) {
+  const double s = motion_s(f, t);
+  double ov0, ov1;
+  if (f.kind == 1) {
+    ov0 = fmax(f.vf[0], f.vm[0] + s);
+    ov1 = fmin(f.vf[f.nvf - 1], f.vm[f.nvm - 1] + s);
+  } else {
+    ov0 = fmax(f.vf[0], s - 0.5 * f.wv);
+    ov1 = fmin(f.vf[f.nvf - 1], s + 0.5 * f.wv);
+  }
+  const bool valid = (f.ou1 > f.ou0) && (ov1 > ov0);
+  if (f.kind == 1)
+    *qf_out = valid ? f.Pf / ((f.ou1 - f.ou0) * (ov1 - ov0)) : 0.0;
+  for (int b = threadIdx.x; b < f.nvf; b += blockDim.x) {
+    for (int i = 0; i < 3; ++i) {
+      const int bb = b - 1 + i;
+      S.Mv[3 * b + i] = (bb >= 0 && bb < f.nvf && valid)
+                            ? hat_product_integral(f.vf, f.nvf, b, f.vf, f.nvf, bb, 0.0, ov0, ov1)
+                            : 0.0;
+    }
+    S.Hv[b] = valid ? hat_integral(f.vf, f.nvf, b, ov0, ov1) : 0.0;
+    if (f.kind == 1) {
+      const double start = f.vf[b > 0 ? b - 1 : b];
+      const int d0 = first_hat_after(f.vm, f.nvm, s, start);
+      S.dlo[b] = d0;
+      for (int i = 0; i < kBand; ++i) {
+        const int d = d0 + i;
+        S.Cv[kBand * b + i] =
+            (d < f.nvm && valid)
+                ? hat_product_integral(f.vf, f.nvf, b, f.vm, f.nvm, d, s, ov0, ov1)
+                : 0.0;
+      }
+    }
+  }
+  if (f.kind == 1) {
+    for (int d = threadIdx.x; d < f.nvm; d += blockDim.x) {
+      for (int i = 0; i < 3; ++i) {
+        const int dd = d - 1 + i;
+        S.Nv[3 * d + i] = (dd >= 0 && dd < f.nvm && valid)
+                              ? hat_product_integral(f.vm, f.nvm, d, f.vm, f.nvm, dd, 0.0,
+                                                     ov0 - s, ov1 - s)
+                              : 0.0;
+      }
+      S.Gv[d] = valid ? hat_integral(f.vm, f.nvm, d, ov0 - s, ov1 - s) : 0.0;
+      const double start = f.vm[d > 0 ? d - 1 : d] + s;
+      const int b0 = first_hat_after(f.vf, f.nvf, 0.0, start);
+      S.blo[d] = b0;
+      for (int i = 0; i < kBand; ++i) {
+        const int b = b0 + i;
+        S.CvT[kBand * d + i] =
+            (b < f.nvf && valid)
+                ? hat_product_integral(f.vf, f.nvf, b, f.vm, f.nvm, d, s, ov0, ov1)
+                : 0.0;
+      }
+    }
+  }
+}
+
+// f^E at interface point i from the interface state T (fixed points first)
+__device__ double iface_fE(const IfaceDev &f, const IfShared &S, double qf, const double *T,
+                           int i) {
+  if (i < f.nfix) {
+    const int a = i / f.nvf, b = i - a * f.nvf;
+    double self = 0.0;
+    for (int ia = 0; ia < 3; ++ia) {
+      const int aa = a - 1 + ia;
+      const double mu = f.Mu[3 * a + ia];
+      if (aa < 0 || aa >= f.nuf || mu == 0.0) continue;
+      double acc = 0.0;
+      for (int ib = 0; ib < 3; ++ib) {
+        const int bb = b - 1 + ib;
+        if (bb < 0 || bb >= f.nvf) continue;
+        acc += S.Mv[3 * b + ib] * T[aa * f.nvf + bb];
+      }
+      self += mu * acc;
+    }
+    const double hub = f.Hu[a] * S.Hv[b];
+    if (f.kind == 2) return (f.q0 + f.alpha * f.Tfix) * hub - f.alpha * self;
+    double cross = 0.0;
+    const int c0 = f.clo[a], d0 = S.dlo[b];
+    for (int ic = 0; ic < kBand; ++ic) {
+      const int c = c0 + ic;
+      const double cu = f.Cu[kBand * a + ic];
+      if (c >= f.num || cu == 0.0) continue;
+      double acc = 0.0;
+      for (int id = 0; id < kBand; ++id) {
+        const int d = d0 + id;
+        if (d >= f.nvm) break;
+        acc += S.Cv[kBand * b + id] * T[f.nfix + c * f.nvm + d];
+      }
+      cross += cu * acc;
+    }
+    return f.alpha * (cross - self) + f.split * qf * hub;
+  }
+  const int k = i - f.nfix;
+  const int c = k / f.nvm, d = k - c * f.nvm;
+  double self = 0.0;
+  for (int ic = 0; ic < 3; ++ic) {
+    const int cc = c - 1 + ic;
+    const double nu = f.Nu[3 * c + ic];
+    if (cc < 0 || cc >= f.num || nu == 0.0) continue;
+    double acc = 0.0;
+    for (int id = 0; id < 3; ++id) {
+      const int dd = d - 1 + id;
+      if (dd < 0 || dd >= f.nvm) continue;
+      acc += S.Nv[3 * d + id] * T[f.nfix + cc * f.nvm + dd];
+    }
+    self += nu * acc;
+  }
+  double cross = 0.0;
+  const int a0 = f.alo[c], b0 = S.blo[d];
+  for (int ia = 0; ia < kBand; ++ia) {
+    const int a = a0 + ia;
+    const double cu = f.CuT[kBand * c + ia];
+    if (a >= f.nuf || cu == 0.0) continue;
+    double acc = 0.0;
+    for (int ib = 0; ib < kBand; ++ib) {
+      const int b = b0 + ib;
+      if (b >= f.nvf) break;
+      acc += S.CvT[kBand * d + ib] * T[a * f.nvf + b];
+    }
+    cross += cu * acc;
+  }
+  return f.alpha * (cross - self) + (1.0 - f.split) * qf * f.Gu[c] * S.Gv[d];
+}
+
+__global__ __launch_bounds__(kIfaceBlock) void k_iface(IfArgs A) {
+  extern __shared__ double lds[];
+  const IfaceDev &f = A.f;
+  IfShared S;
+  {
+    double *p = lds;
+    S.Mv = p; p += 3 * f.nvf;
+    S.Hv = p; p += f.nvf;
+    S.Cv = p; p += kBand * f.nvf;
+    S.Nv = p; p += 3 * f.nvm;
+    S.Gv = p; p += f.nvm;
+    S.CvT = p; p += kBand * f.nvm;
+    S.dlo = reinterpret_cast<int *>(p);
+    S.blo = S.dlo + f.nvf;
+  }
+  __shared__ double s_qf;
+  const Weights &w = *A.w;
+  const int m = A.m, P = A.P, P1 = P + 1, n = f.n_if;
+  const double dtm = w.dtau[m], dtp = dtm / P, tn = *A.tn, t0 = tn + w.tau[m - 1];
+  const double *Eo = A.Eold + (size_t)m * P1 * n;
+  double *En = A.Enew + (size_t)m * P1 * n;
+
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int64_t row = f.rows[i];
+    const double mi = A.mass[row], tp = A.Tprev[row], ts = A.Tm[row];
+    // dtau f*_m recovered from the solve: M T* - M T_{m-1} (- I_m)
+    const double num = mi * ts - mi * tp - (A.corr ? A.Im[row] : 0.0);
+    A.fst[i] = num / dtm;
+    A.Tcur[i] = tp;
+  }
+  __syncthreads();
+  for (int p = 1; p <= P + 1; ++p) {
+    // f^E at (T_{m,p-1}, tau_{m,p-1})
+    double qf = 0.0;
+    iface_coeffs(f, t0 + (p - 1) * dtp, S, &qf);
+    if (threadIdx.x == 0) s_qf = qf;
+    __syncthreads();
+    qf = s_qf;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+      En[(size_t)(p - 1) * n + i] = iface_fE(f, S, qf, A.Tcur, i);
+    __syncthreads();
+    if (p == P + 1) break;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int64_t row = f.rows[i];
+      const double E = En[(size_t)(p - 1) * n + i];
+      double inc;
+      if (A.corr) {
+        double Ip = 0.0;
+        for (int j = 1; j <= A.M; ++j) Ip += w.stil[m][p][j] * A.F[j][row];
+        for (int q = 1; q <= P; ++q) Ip += w.spq[m][p][q] * Eo[(size_t)q * n + i];
+        inc = dtp * (A.fst[i] + E - Eo[(size_t)(p - 1) * n + i]) + Ip;
+      } else {
+        inc = dtp * (A.fst[i] + E);
+      }
+      A.Tcur[i] = A.Tcur[i] + inc / A.mass[row];
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) A.Tm[f.rows[i]] = A.Tcur[i];
+}
+
+size_t iface_lds_bytes(const IfaceDev &f) {
+  return sizeof(double) * (size_t)((3 + 1 + kBand) * f.nvf + (3 + 1 + kBand) * f.nvm) +
+         sizeof(int) * (size_t)(f.nvf + f.nvm) + 16;
+}
+
+void launch_iface(const DevState &d, int m, bool corr, hipStream_t st) {
+  if (!d.ifc.kind || d.ifc.n_if == 0) return;
+  IfArgs A;
+  A.f = d.ifc;
+  A.w = d.w;
+  A.m = m;
+  A.corr = corr ? 1 : 0;
+  A.P = d.P;
+  A.M = d.M;
+  A.tn = d.tn;
+  A.mass = d.mass;
+  A.Tprev = d.T[m - 1];
+  A.Tm = d.T[m];
+  A.Im = d.I[m];
+  for (int j = 0; j <= kMaxM; ++j) A.F[j] = d.F[j];
+  A.Eold = d.Eold;
+  A.Enew = d.Enew;
+  A.Tcur = d.Tcur;
+  A.fst = d.fst;
+  k_iface<<<1, kIfaceBlock, iface_lds_bytes(d.ifc), st>>>(A);
+}
+
+// ---------------------------------------------------------------------------
+// step end: T_n <- T_M, t_n += dt
+// ---------------------------------------------------------------------------
+__global__ void k_copy(double *dst, const double *src, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+// commit the step only if every solve converged within its launch budget
+__global__ void k_commit(double *dst, const double *src, int64_t n, const StepCounters *ctr) {
+  if (ctr->fail) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+__global__ void k_time(double *tn, double dt, const StepCounters *ctr) {
+  if (threadIdx.x == 0 && !ctr->fail) *tn += dt;
+}
+__global__ void k_clear(StepCounters *ctr) {
+  int *p = reinterpret_cast<int *>(ctr);
+  for (int i = threadIdx.x; i < (int)(sizeof(StepCounters) / sizeof(int)); i += blockDim.x) p[i] = 0;
+}
+
+void launch_copy(double *dst, const double *src, int64_t n, hipStream_t st) {
+  int grid = (int)((n + kBlock - 1) / kBlock);
+  if (grid > 2048) grid = 2048;
+  if (grid < 1) grid = 1;
+  k_copy<<<grid, kBlock, 0, st>>>(dst, src, n);
+}
+
+void launch_step_end(const DevState &d, double dt, hipStream_t st) {
+  int grid = (int)((d.N + kBlock - 1) / kBlock);
+  if (grid > 2048) grid = 2048;
+  k_commit<<<grid, kBlock, 0, st>>>(d.T[0], d.T[d.M], d.N, d.ctr);
+  k_time<<<1, 64, 0, st>>>(d.tn, dt, d.ctr);
+}
+
+void launch_clear_counters(const DevState &d, hipStream_t st) {
+  k_clear<<<1, kBlock, 0, st>>>(d.ctr);
+}
+
+}  // namespace mrsdc

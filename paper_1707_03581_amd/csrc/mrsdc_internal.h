@@ -1,0 +1,145 @@
+// Internal declarations shared by the host driver (api.cpp), the quadrature
+// (quadrature.cpp) and the HIP kernels (kernels.hip).  Not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/mrsdc.h"
+
+namespace mrsdc {
+
+constexpr int kMaxM = 8;
+constexpr int kMaxP = 32;
+constexpr int kBand = 8;        // max coupled nodes per face node and direction
+constexpr int kSlice = 64;      // SELL slice height = one wavefront
+constexpr int kBlock = 256;     // threads per block of the vector kernels
+constexpr int kIfaceBlock = 1024;
+constexpr int kMaxJ = 8;        // right-hand sides of the multi-vector SpMV
+
+// Quadrature of one step, 1-based node indices (paper §3 weight definitions).
+struct Weights {
+  int M, P;
+  double dt;
+  double tau[kMaxM + 1];   // tau[0] = 0 (t_n), relative to t_n
+  double dtau[kMaxM + 1];  // dtau[m] = tau[m] - tau[m-1]
+  double s[kMaxM + 1][kMaxM + 1];
+  double shat[kMaxM + 1][kMaxP + 1];
+  double stil[kMaxM + 1][kMaxP + 1][kMaxM + 1];
+  double spq[kMaxM + 1][kMaxP + 1][kMaxP + 1];
+};
+
+bool build_weights(int M, int family, int P, double dt, Weights *w);
+bool standard_nodes01(int M, int family, long double *x);
+
+// Sliced ELLPACK (SELL-64) operator L = K + h R of the concatenated system.
+// Element k of row (64 s + lane) sits at off[s] + 64 k + lane; columns are
+// int16 offsets col - row when every |col - row| < 32768, else int32 columns.
+struct SellDev {
+  int64_t nrows = 0, nslices = 0, nelem = 0;
+  const int64_t *off = nullptr;   // [nslices + 1]
+  const double *val = nullptr;    // [nelem]
+  const float *val32 = nullptr;   // [nelem] (FP32_REFINE)
+  const int16_t *d16 = nullptr;   // [nelem] or null
+  const int32_t *c32 = nullptr;   // [nelem] or null
+};
+
+// Per-solve device scalars of the CG iteration.
+struct PcgScalars {
+  double rz[2];   // r.z of the current/next iteration, by parity
+  double tol2;    // rtol^2 ||b||^2
+  double bb;
+  int done;
+  int iters;
+  int pad[2];
+};
+
+// Device-side counters of one time step, read back once per step.
+constexpr int kSlots = 17 * kMaxM;  // (sweep k, interval m) solve slots
+
+struct StepCounters {
+  long long pcg_iters;
+  long long refine_steps;
+  int max_iters;
+  int fail;                 // solves that hit their budget
+  int pad[2];
+  double resid[17];         // residual of iterate k
+  int slot_iters[kSlots];   // iterations of each solve of the step (-1: failed)
+};
+
+// Coupling data of f^E on device (contact between two face grids, or patch).
+struct IfaceDev {
+  int kind = 0;            // 0 none, 1 contact, 2 patch
+  int nuf = 0, nvf = 0;    // fixed face (or patch face) grid
+  int num = 0, nvm = 0;    // moving face grid (contact)
+  int nfix = 0, n_if = 0;  // nuf*nvf, total interface points
+  const double *uf = nullptr, *vf = nullptr, *um = nullptr, *vm = nullptr;
+  const int64_t *rows = nullptr;   // [n_if] global row of each interface point
+  // u-direction (time independent) restricted integrals over [ou0, ou1]
+  const double *Mu = nullptr;    // [nuf*3] int psi_a psi_{a-1+i}
+  const double *Hu = nullptr;    // [nuf]   int psi_a
+  const double *Cu = nullptr;    // [nuf*kBand] int psi_a chi_{clo[a]+i}
+  const int *clo = nullptr;      // [nuf]
+  const double *Nu = nullptr;    // [num*3] int chi_c chi_{c-1+i}
+  const double *Gu = nullptr;    // [num]
+  const double *CuT = nullptr;   // [num*kBand] int chi_c psi_{alo[c]+i}
+  const int *alo = nullptr;      // [num]
+  double ou0 = 0, ou1 = 0;
+  double alpha = 0, Pf = 0, split = 0.5;
+  double q0 = 0, Tfix = 0, wv = 0;
+  double s0 = 0, a = 0, period = 1, phase = 0;
+};
+
+// Everything the kernels of one context touch.
+struct DevState {
+  int64_t N = 0;
+  int M = 0, P = 0, K = 0;
+  double dtau_h[kMaxM + 1] = {};      // host copy of the interval lengths
+  int grid = 0;                       // blocks of the vector kernels
+  SellDev op;
+  const double *mass = nullptr, *g = nullptr, *Ldiag = nullptr;
+  double *dinv[kMaxM + 1] = {};       // Jacobi inverse per interval
+  float *dinv32[kMaxM + 1] = {};
+  const Weights *w = nullptr;         // device copy
+  const int *ifpos = nullptr;         // [N] interface index or -1
+  double *T[kMaxM + 1] = {};          // standard-node states (T[0] = T_n)
+  double *F[kMaxM + 1] = {};          // f^I(T_j) + g
+  double *I[kMaxM + 1] = {};          // I_{m-1}^m
+  double *r = nullptr, *p = nullptr, *q = nullptr;  // CG work
+  float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *x32 = nullptr;
+  double *partial = nullptr;          // [3 * grid]
+  PcgScalars *sc = nullptr;
+  StepCounters *ctr = nullptr;
+  double *tn = nullptr;               // device scalar: t_n of the current step
+  IfaceDev ifc;
+  double *Eold = nullptr, *Enew = nullptr;  // [(M+1)*(P+1)*n_if]
+  double *Tcur = nullptr, *fst = nullptr;   // [n_if]
+};
+
+// ---- kernel launchers (kernels.hip) ----
+void launch_f_multi(const DevState &d, int j0, int j1, hipStream_t st);
+void launch_quad_resid(const DevState &d, int k, hipStream_t st);
+void launch_init_pred(const DevState &d, int m, hipStream_t st);
+void launch_init_corr(const DevState &d, int m, hipStream_t st);
+void launch_init_reduce(const DevState &d, double rtol, hipStream_t st);
+void launch_pcg_iter(const DevState &d, int m, int it, bool tail, hipStream_t st,
+                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+void launch_pcg_final(const DevState &d, int slot, hipStream_t st);
+void launch_clear_counters(const DevState &d, hipStream_t st);
+size_t iface_lds_bytes(const IfaceDev &f);
+void launch_iface(const DevState &d, int m, bool corr, hipStream_t st);
+void launch_step_end(const DevState &d, double dt, hipStream_t st);
+void launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
+// FP32 inner solve with FP64 refinement
+void launch_refine_resid_corr(const DevState &d, int m, hipStream_t st);
+void launch_refine_resid_spmv(const DevState &d, int m, bool pred, hipStream_t st);
+void launch_refine_reduce(const DevState &d, double rtol_outer, double rtol_inner, hipStream_t st);
+void launch_pcg32_iter(const DevState &d, int m, int it, hipStream_t st);
+void launch_refine_update(const DevState &d, hipStream_t st);
+
+// host+device helpers for the 1D face integrals
+__host__ __device__ double hat_integral(const double *x, int n, int a, double lo, double hi);
+__host__ __device__ double hat_product_integral(const double *x, int nx, int a, const double *y,
+                                                int ny, int c, double sy, double lo, double hi);
+
+}  // namespace mrsdc

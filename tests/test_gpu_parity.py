@@ -1,0 +1,184 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU FP64 oracle.
+
+Bar (FP64 path): relative L2 temperature error <= 1e-10 over all nodes of both
+bodies.  Cases span several SELL slices with ragged tails, both node families,
+the degenerate schemes (K = 0, P = 1), both coupling kinds, the full-size
+machine workload (a few steps, as benchmarked), and the error paths.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import mrsdc_inputs as mi
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu] {request.node.nodeid}", flush=True)
+    sys.stdout.flush()
+    yield
+
+
+def lib():
+    import paper_1707_03581_amd as m
+    return m
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def change_rel(a, b, T0):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b - T0), 1e-300))
+
+
+def run_gpu(pb, nsteps, **over):
+    m = lib()
+    ctx = m.simulation(pb, **over)
+    st = ctx.advance(nsteps * pb.scheme.dt)
+    T = m.get_state(ctx, pb)
+    ctx.destroy()
+    return T, st
+
+
+def small_machine(**kw):
+    base = dict(stand_nodes=(5, 7, 19), stock_nodes=(4, 5, 7), stand_L=(0.2, 0.3, 0.9),
+                stock_L=(0.15, 0.2, 0.3), y_offset=0.05, alpha=1000.0, friction_W=150.0,
+                period=3.0, stroke=0.5, nsteps=4, h=10.0)
+    base.update(kw)
+    return mi.machine(**base)
+
+
+CASES = {
+    "box_patch_lobatto3": lambda: mi.patch_box(L=(0.2, 0.2, 0.5), nodes=(6, 7, 21), nsteps=6),
+    "box_patch_alpha_equi": lambda: mi.patch_box(
+        L=(0.2, 0.2, 0.5), nodes=(5, 6, 17), alpha=300.0, T_fixed=45.0, nsteps=5,
+        scheme=mi.Scheme(M=3, family=mi.EQUI_NOLEFT, P=4, K=2, dt=2.0)),
+    "machine_lobatto5": lambda: small_machine(scheme=mi.Scheme(M=5, family=mi.LOBATTO, P=5, K=4, dt=5.0)),
+    "machine_lobatto3_K0": lambda: small_machine(scheme=mi.Scheme(M=3, family=mi.LOBATTO, P=3, K=0, dt=2.0)),
+    "machine_equi4_P1": lambda: small_machine(scheme=mi.Scheme(M=4, family=mi.EQUI_NOLEFT, P=1, K=3, dt=2.0)),
+    "machine_nonmatching": lambda: small_machine(stand_nodes=(6, 9, 23), stock_nodes=(5, 6, 9),
+                                                 scheme=mi.Scheme(M=5, family=mi.LOBATTO, P=4, K=3, dt=3.0)),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_small_cases_match_oracle(name):
+    pb = CASES[name]()
+    ref, _ = oracle.run(pb, nsteps=pb.nsteps)
+    T, st = run_gpu(pb, pb.nsteps)
+    assert st["steps"] == pb.nsteps
+    e = rel(T, ref)
+    print(f"  N={pb.N} rel_l2={e:.3e} change_rel={change_rel(T, ref, pb.T0):.3e} "
+          f"iters={st['pcg_iters']}", flush=True)
+    assert e <= TOL
+
+
+def test_box_patch_2673_full_horizon():
+    """The single-box workload, 60 steps of 1 s (Lobatto M=3, K=3, P=10)."""
+    pb = mi.config0()
+    ref, _ = oracle.run(pb)
+    T, st = run_gpu(pb, pb.nsteps)
+    e = rel(T, ref)
+    print(f"  rel_l2={e:.3e} change_rel={change_rel(T, ref, pb.T0):.3e}", flush=True)
+    assert e <= TOL
+
+
+def test_machine_310k_sampled_steps():
+    """The 310,042-node two-body machine (Lobatto M=5, K=4, P=5, dt=5 s), first
+    3 steps, in the launch configuration the benchmark uses."""
+    pb = mi.config1(nsteps=3)
+    ref, _ = oracle.run(pb, nsteps=3)
+    T, st = run_gpu(pb, 3)
+    e = rel(T, ref)
+    print(f"  rel_l2={e:.3e} change_rel={change_rel(T, ref, pb.T0):.3e} "
+          f"iters={st['pcg_iters']} max_it={st['max_iters']}", flush=True)
+    assert e <= TOL
+
+
+def test_eigenmode_insulated_box_closed_form():
+    """No coupling, insulated: T = 20 + A R^n v with the collocation-limit R."""
+    from test_inputs import cos_mode, lam_h
+    from test_oracle_stepper import collocation_R
+    sc = mi.Scheme(M=3, family=mi.LOBATTO, P=2, K=16, dt=20.0)
+    pb = mi.patch_box(L=(0.2, 0.3, 0.5), nodes=(9, 11, 13), robin=False, scheme=sc)
+    pb.coupling = None
+    b = pb.bodies[0]
+    v = cos_mode(b)
+    pb.T0 = 20.0 + 3.0 * v
+    T, _ = run_gpu(pb, 3)
+    R = collocation_R(lam_h(b.lengths, b.dims) * sc.dt, 3, mi.LOBATTO)
+    assert np.abs(T - (20.0 + 3.0 * R**3 * v)).max() < 1e-10
+
+
+def test_deterministic_and_resume_bitwise():
+    pb = small_machine()
+    m = lib()
+    a, _ = run_gpu(pb, 4)
+    b, _ = run_gpu(pb, 4)
+    assert np.array_equal(a, b)
+    ctx = m.simulation(pb)
+    ctx.advance(2 * pb.scheme.dt)
+    mid = m.get_state(ctx, pb)
+    t = ctx.get_time()
+    ctx.destroy()
+    ctx = m.simulation(pb)
+    off = pb.offsets
+    for i in range(len(pb.bodies)):
+        ctx.set_temperature(i, mid[off[i]:off[i + 1]])
+    ctx.set_time(t)
+    ctx.advance(2 * pb.scheme.dt)
+    c = m.get_state(ctx, pb)
+    ctx.destroy()
+    assert np.array_equal(a, c)
+
+
+def test_error_paths():
+    m = lib()
+    pb = small_machine()
+    ctx = m.simulation(pb)
+    with pytest.raises(m.MrsdcError) as e:
+        ctx.advance(1.5 * pb.scheme.dt)
+    assert e.value.status == m.EINVAL
+    bad = pb.T0[: pb.bodies[0].n].copy()
+    bad[3] = np.nan
+    with pytest.raises(m.MrsdcError):
+        ctx.set_temperature(0, bad)
+    b = pb.bodies[0]
+    col = b.col.copy()
+    col[5], col[6] = col[6], col[5]  # unsorted row
+    with pytest.raises(m.MrsdcError) as e:
+        ctx.set_body(0, b.rowptr, col, b.K, b.R, b.mass, b.rload)
+    assert e.value.status == m.EINVAL
+    ctx.destroy()
+    # iteration cap too small: ENOCONV and the state stays at the start
+    ctx = m.simulation(pb, pcg_maxit=1)
+    with pytest.raises(m.MrsdcError) as e:
+        ctx.advance(pb.scheme.dt)
+    assert e.value.status == m.ENOCONV
+    assert np.array_equal(m.get_state(ctx, pb), pb.T0)
+    assert ctx.get_time() == pb.t0
+    ctx.destroy()
+
+
+def test_zero_horizon_and_device_copy():
+    import torch
+    m = lib()
+    pb = small_machine()
+    ctx = m.simulation(pb)
+    st = ctx.advance(0.0)
+    assert st["steps"] == 0
+    ctx.advance(pb.scheme.dt)
+    out = torch.empty(pb.bodies[1].n, dtype=torch.float64, device="cuda")
+    ctx.get_temperature_device(1, out, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    host = ctx.get_temperature(1, pb.bodies[1].n)
+    assert np.array_equal(out.cpu().numpy(), host)
+    assert ctx.footprint_bytes() > 0
+    ctx.destroy()
