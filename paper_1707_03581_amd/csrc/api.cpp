@@ -197,10 +197,12 @@ double max_support(const std::vector<double> &x) {
 
 // Band of hats of y overlapping each hat of x along one (static) direction.
 mrsdc_status band_coeffs(mrsdc_ctx *c, const std::vector<double> &x, const std::vector<double> &y,
-                         double lo, double hi, std::vector<double> &C, std::vector<int> &lo_idx) {
+                         double lo, double hi, std::vector<double> &C, std::vector<int> &lo_idx,
+                         std::vector<int> &cnt) {
   const int nx = (int)x.size(), ny = (int)y.size();
   C.assign((size_t)nx * kBand, 0.0);
   lo_idx.assign(nx, 0);
+  cnt.assign(nx, 0);
   for (int a = 0; a < nx; ++a) {
     double start = x[a > 0 ? a - 1 : a], end = x[a < nx - 1 ? a + 1 : a];
     int c0 = first_hat_after_h(y, 0.0, start);
@@ -210,6 +212,7 @@ mrsdc_status band_coeffs(mrsdc_ctx *c, const std::vector<double> &x, const std::
       if (cc >= ny) break;
       C[(size_t)kBand * a + i] =
           hat_product_integral(x.data(), nx, a, y.data(), ny, cc, 0.0, lo, hi);
+      if (C[(size_t)kBand * a + i] != 0.0) cnt[a] = i + 1;
     }
     int cn = c0 + kBand;
     if (cn < ny && y[cn > 0 ? cn - 1 : cn] < end)
@@ -459,9 +462,9 @@ mrsdc_status prepare(mrsdc_ctx *c) {
     f.rows = pr;
     if (cp.kind == 1) {
       std::vector<double> Cu, CuT, Nu(3 * (size_t)f.num, 0.0), Gu(f.num, 0.0);
-      std::vector<int> clo, alo;
-      if ((st = band_coeffs(c, F.u, um, f.ou0, f.ou1, Cu, clo))) return st;
-      if ((st = band_coeffs(c, um, F.u, f.ou0, f.ou1, CuT, alo))) return st;
+      std::vector<int> clo, alo, ccnt, acnt;
+      if ((st = band_coeffs(c, F.u, um, f.ou0, f.ou1, Cu, clo, ccnt))) return st;
+      if ((st = band_coeffs(c, um, F.u, f.ou0, f.ou1, CuT, alo, acnt))) return st;
       for (int cc = 0; cc < f.num; ++cc) {
         for (int i = 0; i < 3; ++i) {
           int c2 = cc - 1 + i;
@@ -487,6 +490,10 @@ mrsdc_status prepare(mrsdc_ctx *c) {
       f.clo = pi;
       if ((st = upload(c, &pi, alo))) return st;
       f.alo = pi;
+      if ((st = upload(c, &pi, ccnt))) return st;
+      f.ccnt = pi;
+      if ((st = upload(c, &pi, acnt))) return st;
+      f.acnt = pi;
     }
     if ((st = upload(c, &pi, ifpos))) return st;
     d.ifpos = pi;
@@ -495,9 +502,13 @@ mrsdc_status prepare(mrsdc_ctx *c) {
       return st;
     HIPCHK(hipMemset(d.Eold, 0, ncache * sizeof(double)));
     HIPCHK(hipMemset(d.Enew, 0, ncache * sizeof(double)));
-    if ((st = dalloc(c, &d.Tcur, f.n_if)) || (st = dalloc(c, &d.fst, f.n_if))) return st;
-    if (iface_lds_bytes(f) > 64 * 1024)
-      return fail(c, MRSDC_EINVAL, "face grid too long for the interface kernel");
+    if ((st = dalloc(c, &d.Tbuf[0], f.n_if)) || (st = dalloc(c, &d.Tbuf[1], f.n_if)) ||
+        (st = dalloc(c, &d.fst, f.n_if)))
+      return st;
+    const size_t ntab = (size_t)(cfg.M + 1) * (cfg.P + 1);
+    if ((st = dalloc(c, &d.coefD, ntab * coef_table_doubles(f))) ||
+        (st = dalloc(c, &d.coefI, ntab * coef_table_ints(f))))
+      return st;
   }
   if (!c->ctr_host) HIPCHK(hipHostMalloc((void **)&c->ctr_host, sizeof(StepCounters), 0));
   const int b0 = std::min(cfg.pcg_maxit, 24);
@@ -577,6 +588,7 @@ void enqueue_step(mrsdc_ctx *c) {
   const bool lob = c->cfg.node_family == MRSDC_LOBATTO;
   hipStream_t st = c->stream;
   launch_clear_counters(d, st);
+  launch_iface_coeffs(d, st);
   // predictor (Alg. 1)
   for (int m = 1; m <= M; ++m) {
     if (c->w.dtau[m] == 0.0) continue;

@@ -521,37 +521,46 @@ __device__ inline int first_hat_after(const double *y, int n, double sy, double 
 // and Alg. 2, the inner loops over p).  Off the interface f^E vanishes, so
 // those rows end the interval at T* exactly (the weights satisfy
 // sum_p tilde s = s and sum_p s_pq = hat s): only interface rows are stepped.
-// One workgroup; the interface state lives in global memory (L2 resident).
+//
+// The time-dependent 1D face integrals depend only on the embedded times,
+// which are the same for the predictor and every sweep of a step, so they are
+// tabulated once per step for all (m, q).  Each substep is then one wide
+// launch over the interface points with double-buffered interface state.
 // ---------------------------------------------------------------------------
-struct IfArgs {
-  IfaceDev f;
-  const Weights *w;
-  int m, corr, P, M;
-  const double *tn;
-  const double *mass;
-  const double *Tprev;
-  double *Tm;
-  const double *Im;
-  const double *F[kMaxM + 1];
-  const double *Eold;  // [(M+1)(P+1) n_if]
-  double *Enew;
-  double *Tcur, *fst;
+struct CoefLayout {
+  int nvf, nvm;
+  __host__ __device__ int dstride() const { return 1 + (4 + kBand) * (nvf + nvm); }
+  __host__ __device__ int istride() const { return 2 * (nvf + nvm); }
+  __host__ __device__ int Mv() const { return 1; }
+  __host__ __device__ int Hv() const { return 1 + 3 * nvf; }
+  __host__ __device__ int Cv() const { return 1 + 4 * nvf; }
+  __host__ __device__ int Nv() const { return 1 + (4 + kBand) * nvf; }
+  __host__ __device__ int Gv() const { return Nv() + 3 * nvm; }
+  __host__ __device__ int CvT() const { return Gv() + nvm; }
+  __host__ __device__ int dlo() const { return 0; }
+  __host__ __device__ int dcnt() const { return nvf; }
+  __host__ __device__ int blo() const { return 2 * nvf; }
+  __host__ __device__ int bcnt() const { return 2 * nvf + nvm; }
 };
 
-struct IfShared {
-  double *Mv, *Hv, *Cv;
-  int *dlo;
-  double *Nv, *Gv, *CvT;
-  int *blo;
-  double qf;
-};
+size_t coef_table_doubles(const IfaceDev &f) { return (size_t)CoefLayout{f.nvf, f.nvm}.dstride(); }
+size_t coef_table_ints(const IfaceDev &f) { return (size_t)CoefLayout{f.nvf, f.nvm}.istride(); }
 
 __device__ double motion_s(const IfaceDev &f, double t) {
   return f.s0 + f.a * sin(2.0 * M_PI * t / f.period + f.phase);
 }
 
-// v-direction (time dependent) integrals at time t into LDS
-__device__ void iface_coeffs(const IfaceDev &f, double t, IfShared &S, double *qf_out) {
+// One block per embedded time point tau_{m,q}: v-direction integrals over the
+// v-extent of Gamma_R(t) (contact) or of the patch, and the friction density.
+__global__ __launch_bounds__(kBlock) void k_iface_coeffs(IfaceDev f, const Weights *w,
+                                                        const double *tn, int P,
+                                                        double *coefD, int *coefI) {
+  const int P1 = P + 1, tp = blockIdx.x, m = tp / P1, q = tp - m * P1;
+  if (m == 0 || w->dtau[m] == 0.0) return;
+  const CoefLayout L{f.nvf, f.nvm};
+  double *D = coefD + (size_t)tp * L.dstride();
+  int *I = coefI + (size_t)tp * L.istride();
+  const double t = *tn + w->tau[m - 1] + q * (w->dtau[m] / P);
   const double s = motion_s(f, t);
   double ov0, ov1;
   if (f.kind == 1) {
@@ -562,56 +571,89 @@ __device__ void iface_coeffs(const IfaceDev &f, double t, IfShared &S, double *q
     ov1 = fmin(f.vf[f.nvf - 1], s + 0.5 * f.wv);
   }
   const bool valid = (f.ou1 > f.ou0) && (ov1 > ov0);
-  if (f.kind == 1)
-    *qf_out = valid ? f.Pf / ((f.ou1 - f.ou0) * (ov1 - ov0)) : 0.0;
+  if (threadIdx.x == 0)
+    D[0] = (f.kind == 1 && valid) ? f.Pf / ((f.ou1 - f.ou0) * (ov1 - ov0)) : 0.0;
   for (int b = threadIdx.x; b < f.nvf; b += blockDim.x) {
     for (int i = 0; i < 3; ++i) {
       const int bb = b - 1 + i;
-      S.Mv[3 * b + i] = (bb >= 0 && bb < f.nvf && valid)
-                            ? hat_product_integral(f.vf, f.nvf, b, f.vf, f.nvf, bb, 0.0, ov0, ov1)
-                            : 0.0;
+      D[L.Mv() + 3 * b + i] =
+          (bb >= 0 && bb < f.nvf && valid)
+              ? hat_product_integral(f.vf, f.nvf, b, f.vf, f.nvf, bb, 0.0, ov0, ov1)
+              : 0.0;
     }
-    S.Hv[b] = valid ? hat_integral(f.vf, f.nvf, b, ov0, ov1) : 0.0;
+    D[L.Hv() + b] = valid ? hat_integral(f.vf, f.nvf, b, ov0, ov1) : 0.0;
     if (f.kind == 1) {
-      const double start = f.vf[b > 0 ? b - 1 : b];
-      const int d0 = first_hat_after(f.vm, f.nvm, s, start);
-      S.dlo[b] = d0;
+      const int d0 = first_hat_after(f.vm, f.nvm, s, f.vf[b > 0 ? b - 1 : b]);
+      int cnt = 0;
       for (int i = 0; i < kBand; ++i) {
         const int d = d0 + i;
-        S.Cv[kBand * b + i] =
-            (d < f.nvm && valid)
-                ? hat_product_integral(f.vf, f.nvf, b, f.vm, f.nvm, d, s, ov0, ov1)
-                : 0.0;
+        const double v = (d < f.nvm && valid)
+                             ? hat_product_integral(f.vf, f.nvf, b, f.vm, f.nvm, d, s, ov0, ov1)
+                             : 0.0;
+        D[L.Cv() + kBand * b + i] = v;
+        if (v != 0.0) cnt = i + 1;
       }
+      I[L.dlo() + b] = d0;
+      I[L.dcnt() + b] = cnt;
     }
   }
   if (f.kind == 1) {
     for (int d = threadIdx.x; d < f.nvm; d += blockDim.x) {
       for (int i = 0; i < 3; ++i) {
         const int dd = d - 1 + i;
-        S.Nv[3 * d + i] = (dd >= 0 && dd < f.nvm && valid)
-                              ? hat_product_integral(f.vm, f.nvm, d, f.vm, f.nvm, dd, 0.0,
-                                                     ov0 - s, ov1 - s)
-                              : 0.0;
+        D[L.Nv() + 3 * d + i] = (dd >= 0 && dd < f.nvm && valid)
+                                    ? hat_product_integral(f.vm, f.nvm, d, f.vm, f.nvm, dd, 0.0,
+                                                           ov0 - s, ov1 - s)
+                                    : 0.0;
       }
-      S.Gv[d] = valid ? hat_integral(f.vm, f.nvm, d, ov0 - s, ov1 - s) : 0.0;
-      const double start = f.vm[d > 0 ? d - 1 : d] + s;
-      const int b0 = first_hat_after(f.vf, f.nvf, 0.0, start);
-      S.blo[d] = b0;
+      D[L.Gv() + d] = valid ? hat_integral(f.vm, f.nvm, d, ov0 - s, ov1 - s) : 0.0;
+      const int b0 = first_hat_after(f.vf, f.nvf, 0.0, f.vm[d > 0 ? d - 1 : d] + s);
+      int cnt = 0;
       for (int i = 0; i < kBand; ++i) {
         const int b = b0 + i;
-        S.CvT[kBand * d + i] =
-            (b < f.nvf && valid)
-                ? hat_product_integral(f.vf, f.nvf, b, f.vm, f.nvm, d, s, ov0, ov1)
-                : 0.0;
+        const double v = (b < f.nvf && valid)
+                             ? hat_product_integral(f.vf, f.nvf, b, f.vm, f.nvm, d, s, ov0, ov1)
+                             : 0.0;
+        D[L.CvT() + kBand * d + i] = v;
+        if (v != 0.0) cnt = i + 1;
       }
+      I[L.blo() + d] = b0;
+      I[L.bcnt() + d] = cnt;
     }
   }
 }
 
-// f^E at interface point i from the interface state T (fixed points first)
-__device__ double iface_fE(const IfaceDev &f, const IfShared &S, double qf, const double *T,
+struct SubArgs {
+  IfaceDev f;
+  const Weights *w;
+  int m, p, P, M, corr;
+  const double *coefD;
+  const int *coefI;
+  const double *mass;
+  const double *Tprev;
+  double *Tm;
+  const double *Im;
+  const double *F[kMaxM + 1];
+  const double *Eold;  // [(M+1)(P+1) n_if]
+  double *Enew;
+  double *Tbuf[2];
+  double *fst;
+};
+
+// interface state: on the first substep T_{m,0} = T_{m-1} is read from the
+// full vector, afterwards from the interface buffer of the previous substep
+template <bool FIRST>
+__device__ inline double tif(const SubArgs &A, const double *Tin, int j) {
+  return FIRST ? A.Tprev[A.f.rows[j]] : Tin[j];
+}
+
+// f^E at interface point i (fixed-face points first, then moving-face points)
+template <bool FIRST>
+__device__ double iface_fE(const SubArgs &A, const double *D, const int *I, const double *Tin,
                            int i) {
+  const IfaceDev &f = A.f;
+  const CoefLayout L{f.nvf, f.nvm};
+  const double qf = D[0];
   if (i < f.nfix) {
     const int a = i / f.nvf, b = i - a * f.nvf;
     double self = 0.0;
@@ -623,25 +665,21 @@ __device__ double iface_fE(const IfaceDev &f, const IfShared &S, double qf, cons
       for (int ib = 0; ib < 3; ++ib) {
         const int bb = b - 1 + ib;
         if (bb < 0 || bb >= f.nvf) continue;
-        acc += S.Mv[3 * b + ib] * T[aa * f.nvf + bb];
+        acc += D[L.Mv() + 3 * b + ib] * tif<FIRST>(A, Tin, aa * f.nvf + bb);
       }
       self += mu * acc;
     }
-    const double hub = f.Hu[a] * S.Hv[b];
+    const double hub = f.Hu[a] * D[L.Hv() + b];
     if (f.kind == 2) return (f.q0 + f.alpha * f.Tfix) * hub - f.alpha * self;
     double cross = 0.0;
-    const int c0 = f.clo[a], d0 = S.dlo[b];
-    for (int ic = 0; ic < kBand; ++ic) {
+    const int c0 = f.clo[a], nc = f.ccnt[a];
+    const int d0 = I[L.dlo() + b], nd = I[L.dcnt() + b];
+    for (int ic = 0; ic < nc; ++ic) {
       const int c = c0 + ic;
-      const double cu = f.Cu[kBand * a + ic];
-      if (c >= f.num || cu == 0.0) continue;
       double acc = 0.0;
-      for (int id = 0; id < kBand; ++id) {
-        const int d = d0 + id;
-        if (d >= f.nvm) break;
-        acc += S.Cv[kBand * b + id] * T[f.nfix + c * f.nvm + d];
-      }
-      cross += cu * acc;
+      for (int id = 0; id < nd; ++id)
+        acc += D[L.Cv() + kBand * b + id] * tif<FIRST>(A, Tin, f.nfix + c * f.nvm + d0 + id);
+      cross += f.Cu[kBand * a + ic] * acc;
     }
     return f.alpha * (cross - self) + f.split * qf * hub;
   }
@@ -656,103 +694,85 @@ __device__ double iface_fE(const IfaceDev &f, const IfShared &S, double qf, cons
     for (int id = 0; id < 3; ++id) {
       const int dd = d - 1 + id;
       if (dd < 0 || dd >= f.nvm) continue;
-      acc += S.Nv[3 * d + id] * T[f.nfix + cc * f.nvm + dd];
+      acc += D[L.Nv() + 3 * d + id] * tif<FIRST>(A, Tin, f.nfix + cc * f.nvm + dd);
     }
     self += nu * acc;
   }
   double cross = 0.0;
-  const int a0 = f.alo[c], b0 = S.blo[d];
-  for (int ia = 0; ia < kBand; ++ia) {
+  const int a0 = f.alo[c], na = f.acnt[c];
+  const int b0 = I[L.blo() + d], nb = I[L.bcnt() + d];
+  for (int ia = 0; ia < na; ++ia) {
     const int a = a0 + ia;
-    const double cu = f.CuT[kBand * c + ia];
-    if (a >= f.nuf || cu == 0.0) continue;
     double acc = 0.0;
-    for (int ib = 0; ib < kBand; ++ib) {
-      const int b = b0 + ib;
-      if (b >= f.nvf) break;
-      acc += S.CvT[kBand * d + ib] * T[a * f.nvf + b];
-    }
-    cross += cu * acc;
+    for (int ib = 0; ib < nb; ++ib)
+      acc += D[L.CvT() + kBand * d + ib] * tif<FIRST>(A, Tin, a * f.nvf + b0 + ib);
+    cross += f.CuT[kBand * c + ia] * acc;
   }
-  return f.alpha * (cross - self) + (1.0 - f.split) * qf * f.Gu[c] * S.Gv[d];
+  return f.alpha * (cross - self) + (1.0 - f.split) * qf * f.Gu[c] * D[L.Gv() + d];
 }
 
-__global__ __launch_bounds__(kIfaceBlock) void k_iface(IfArgs A) {
-  extern __shared__ double lds[];
+// Substep p of interval m (p = P+1: only f^E at tau_m and the write-back).
+template <bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_iface_sub(SubArgs A) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const IfaceDev &f = A.f;
-  IfShared S;
-  {
-    double *p = lds;
-    S.Mv = p; p += 3 * f.nvf;
-    S.Hv = p; p += f.nvf;
-    S.Cv = p; p += kBand * f.nvf;
-    S.Nv = p; p += 3 * f.nvm;
-    S.Gv = p; p += f.nvm;
-    S.CvT = p; p += kBand * f.nvm;
-    S.dlo = reinterpret_cast<int *>(p);
-    S.blo = S.dlo + f.nvf;
-  }
-  __shared__ double s_qf;
+  const int n = f.n_if;
+  if (i >= n) return;
   const Weights &w = *A.w;
-  const int m = A.m, P = A.P, P1 = P + 1, n = f.n_if;
-  const double dtm = w.dtau[m], dtp = dtm / P, tn = *A.tn, t0 = tn + w.tau[m - 1];
-  const double *Eo = A.Eold + (size_t)m * P1 * n;
+  const int m = A.m, p = A.p, P = A.P, P1 = P + 1;
+  const CoefLayout L{f.nvf, f.nvm};
+  const int tp = m * P1 + (p - 1);
+  const double *D = A.coefD + (size_t)tp * L.dstride();
+  const int *I = A.coefI + (size_t)tp * L.istride();
+  const double *Tin = A.Tbuf[(p - 1) & 1];
+  const double E = iface_fE<FIRST>(A, D, I, Tin, i);
   double *En = A.Enew + (size_t)m * P1 * n;
-
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int64_t row = f.rows[i];
-    const double mi = A.mass[row], tp = A.Tprev[row], ts = A.Tm[row];
+  En[(size_t)(p - 1) * n + i] = E;
+  const double Ti = tif<FIRST>(A, Tin, i);
+  const int64_t row = f.rows[i];
+  if (p == P + 1) {
+    A.Tm[row] = Ti;  // T^{k+1}_m <- T_{m,P}
+    return;
+  }
+  const double mi = A.mass[row], dtm = w.dtau[m], dtp = dtm / P;
+  double fs;
+  if (FIRST) {
     // dtau f*_m recovered from the solve: M T* - M T_{m-1} (- I_m)
-    const double num = mi * ts - mi * tp - (A.corr ? A.Im[row] : 0.0);
-    A.fst[i] = num / dtm;
-    A.Tcur[i] = tp;
+    fs = (mi * A.Tm[row] - mi * Ti - (A.corr ? A.Im[row] : 0.0)) / dtm;
+    A.fst[i] = fs;
+  } else {
+    fs = A.fst[i];
   }
-  __syncthreads();
-  for (int p = 1; p <= P + 1; ++p) {
-    // f^E at (T_{m,p-1}, tau_{m,p-1})
-    double qf = 0.0;
-    iface_coeffs(f, t0 + (p - 1) * dtp, S, &qf);
-    if (threadIdx.x == 0) s_qf = qf;
-    __syncthreads();
-    qf = s_qf;
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
-      En[(size_t)(p - 1) * n + i] = iface_fE(f, S, qf, A.Tcur, i);
-    __syncthreads();
-    if (p == P + 1) break;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const int64_t row = f.rows[i];
-      const double E = En[(size_t)(p - 1) * n + i];
-      double inc;
-      if (A.corr) {
-        double Ip = 0.0;
-        for (int j = 1; j <= A.M; ++j) Ip += w.stil[m][p][j] * A.F[j][row];
-        for (int q = 1; q <= P; ++q) Ip += w.spq[m][p][q] * Eo[(size_t)q * n + i];
-        inc = dtp * (A.fst[i] + E - Eo[(size_t)(p - 1) * n + i]) + Ip;
-      } else {
-        inc = dtp * (A.fst[i] + E);
-      }
-      A.Tcur[i] = A.Tcur[i] + inc / A.mass[row];
-    }
-    __syncthreads();
+  double inc;
+  if (A.corr) {
+    const double *Eo = A.Eold + (size_t)m * P1 * n;
+    double Ip = 0.0;
+    for (int j = 1; j <= A.M; ++j) Ip += w.stil[m][p][j] * A.F[j][row];
+    for (int q = 1; q <= P; ++q) Ip += w.spq[m][p][q] * Eo[(size_t)q * n + i];
+    inc = dtp * (fs + E - Eo[(size_t)(p - 1) * n + i]) + Ip;
+  } else {
+    inc = dtp * (fs + E);
   }
-  for (int i = threadIdx.x; i < n; i += blockDim.x) A.Tm[f.rows[i]] = A.Tcur[i];
+  A.Tbuf[p & 1][i] = Ti + inc / mi;
 }
 
-size_t iface_lds_bytes(const IfaceDev &f) {
-  return sizeof(double) * (size_t)((3 + 1 + kBand) * f.nvf + (3 + 1 + kBand) * f.nvm) +
-         sizeof(int) * (size_t)(f.nvf + f.nvm) + 16;
+void launch_iface_coeffs(const DevState &d, hipStream_t st) {
+  if (!d.ifc.kind || d.ifc.n_if == 0) return;
+  k_iface_coeffs<<<(d.M + 1) * (d.P + 1), kBlock, 0, st>>>(d.ifc, d.w, d.tn, d.P, d.coefD,
+                                                           d.coefI);
 }
 
 void launch_iface(const DevState &d, int m, bool corr, hipStream_t st) {
   if (!d.ifc.kind || d.ifc.n_if == 0) return;
-  IfArgs A;
+  SubArgs A;
   A.f = d.ifc;
   A.w = d.w;
   A.m = m;
-  A.corr = corr ? 1 : 0;
   A.P = d.P;
   A.M = d.M;
-  A.tn = d.tn;
+  A.corr = corr ? 1 : 0;
+  A.coefD = d.coefD;
+  A.coefI = d.coefI;
   A.mass = d.mass;
   A.Tprev = d.T[m - 1];
   A.Tm = d.T[m];
@@ -760,9 +780,15 @@ void launch_iface(const DevState &d, int m, bool corr, hipStream_t st) {
   for (int j = 0; j <= kMaxM; ++j) A.F[j] = d.F[j];
   A.Eold = d.Eold;
   A.Enew = d.Enew;
-  A.Tcur = d.Tcur;
+  A.Tbuf[0] = d.Tbuf[0];
+  A.Tbuf[1] = d.Tbuf[1];
   A.fst = d.fst;
-  k_iface<<<1, kIfaceBlock, iface_lds_bytes(d.ifc), st>>>(A);
+  const int grid = (d.ifc.n_if + kBlock - 1) / kBlock;
+  for (int p = 1; p <= d.P + 1; ++p) {
+    A.p = p;
+    if (p == 1) k_iface_sub<true><<<grid, kBlock, 0, st>>>(A);
+    else k_iface_sub<false><<<grid, kBlock, 0, st>>>(A);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -80,10 +80,12 @@ struct IfaceDev {
   const double *Hu = nullptr;    // [nuf]   int psi_a
   const double *Cu = nullptr;    // [nuf*kBand] int psi_a chi_{clo[a]+i}
   const int *clo = nullptr;      // [nuf]
+  const int *ccnt = nullptr;     // [nuf] used entries of the band
   const double *Nu = nullptr;    // [num*3] int chi_c chi_{c-1+i}
   const double *Gu = nullptr;    // [num]
   const double *CuT = nullptr;   // [num*kBand] int chi_c psi_{alo[c]+i}
   const int *alo = nullptr;      // [num]
+  const int *acnt = nullptr;     // [num]
   double ou0 = 0, ou1 = 0;
   double alpha = 0, Pf = 0, split = 0.5;
   double q0 = 0, Tfix = 0, wv = 0;
@@ -113,7 +115,10 @@ struct DevState {
   double *tn = nullptr;               // device scalar: t_n of the current step
   IfaceDev ifc;
   double *Eold = nullptr, *Enew = nullptr;  // [(M+1)*(P+1)*n_if]
-  double *Tcur = nullptr, *fst = nullptr;   // [n_if]
+  double *Tbuf[2] = {};                     // [n_if] interface state, double buffered
+  double *fst = nullptr;                    // [n_if] f*_m on the interface
+  double *coefD = nullptr;                  // [(M+1)(P+1)] tables of v-direction integrals
+  int *coefI = nullptr;
 };
 
 // ---- kernel launchers (kernels.hip) ----
@@ -126,7 +131,9 @@ void launch_pcg_iter(const DevState &d, int m, int it, bool tail, hipStream_t st
                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_pcg_final(const DevState &d, int slot, hipStream_t st);
 void launch_clear_counters(const DevState &d, hipStream_t st);
-size_t iface_lds_bytes(const IfaceDev &f);
+size_t coef_table_doubles(const IfaceDev &f);
+size_t coef_table_ints(const IfaceDev &f);
+void launch_iface_coeffs(const DevState &d, hipStream_t st);
 void launch_iface(const DevState &d, int m, bool corr, hipStream_t st);
 void launch_step_end(const DevState &d, double dt, hipStream_t st);
 void launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
