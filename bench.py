@@ -29,6 +29,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=120)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--config", default="c1", choices=["c0", "c1", "c2"])
+    ap.add_argument("--precision", type=int, default=None, help="0 FP64, 1 FP32+refine")
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle sample (macro-steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")

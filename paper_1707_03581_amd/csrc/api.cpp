@@ -80,8 +80,9 @@ struct mrsdc_ctx {
   int nbody = 0;
   int64_t off[3] = {0, 0, 0};
   StepCounters *ctr_host = nullptr;  // pinned
-  int budget[kSlots];
-  int expect[kSlots];
+  int budget[kSlots];   // CG launch budget per solve slot (inner CG for FP32_REFINE)
+  int expect[kSlots];   // iterations the slot took in the last step
+  int rounds[kSlots];   // refinement round budget per slot
   int64_t matrix_bytes = 0;
   int64_t nnz = 0;
   // event timing of kernel classes
@@ -339,7 +340,12 @@ mrsdc_status prepare(mrsdc_ctx *c) {
   }
   c->matrix_bytes = nnz_total * (8 + (use16 ? 2 : 4)) + 8 * (nslices + 1);
   c->nnz = nnz_total;
-  c->times.cg_spmv_bytes = c->matrix_bytes + 24 * N;
+  // CG operator application: FP64 values (FP32 for the inner solves of the
+  // FP32 path) + column offsets + p, mass, q
+  c->times.cg_spmv_bytes =
+      cfg.precision == MRSDC_FP32_REFINE
+          ? nnz_total * (4 + (use16 ? 2 : 4)) + 8 * (nslices + 1) + 12 * N
+          : c->matrix_bytes + 24 * N;
   c->times.nnz = nnz_total;
   c->times.n = N;
 
@@ -350,11 +356,28 @@ mrsdc_status prepare(mrsdc_ctx *c) {
   d.mass = dmass;
   d.g = dg;
   d.Ldiag = dLd;
+  const bool fp32 = cfg.precision == MRSDC_FP32_REFINE;
   for (int m = 1; m <= cfg.M; ++m) {
     if (c->w.dtau[m] == 0.0) continue;
     std::vector<double> di(N);
     for (int64_t i = 0; i < N; ++i) di[i] = 1.0 / (mass[i] + c->w.dtau[m] * Ldiag[i]);
     if ((st = upload(c, &d.dinv[m], di))) return st;
+    if (fp32) {
+      std::vector<float> d32(N);
+      for (int64_t i = 0; i < N; ++i) d32[i] = (float)di[i];
+      if ((st = upload(c, &d.dinv32[m], d32))) return st;
+    }
+  }
+  if (fp32) {
+    std::vector<float> m32(N);
+    for (int64_t i = 0; i < N; ++i) m32[i] = (float)mass[i];
+    float *pm;
+    if ((st = upload(c, &pm, m32))) return st;
+    d.mass32 = pm;
+    if ((st = dalloc(c, &d.x32, N)) || (st = dalloc(c, &d.r32, N)) ||
+        (st = dalloc(c, &d.p32, N)) || (st = dalloc(c, &d.q32, N)) ||
+        (st = dalloc(c, &d.b64, N)) || (st = dalloc(c, &d.r64, N)))
+      return st;
   }
 
   // ---- weights ----
@@ -379,7 +402,7 @@ mrsdc_status prepare(mrsdc_ctx *c) {
   if ((st = dalloc(c, &d.partial, 3 * (size_t)d.grid))) return st;
   if ((st = dalloc(c, &d.sc, 1)) || (st = dalloc(c, &d.ctr, 1)) || (st = dalloc(c, &d.tn, 1)))
     return st;
-  HIPCHK(hipMemset(d.sc, 0, sizeof(PcgScalars)));
+  HIPCHK(hipMemset(d.sc, 0, sizeof(SolveScalars)));
 
   // ---- coupling ----
   const Coupling &cp = c->cpl;
@@ -515,6 +538,7 @@ mrsdc_status prepare(mrsdc_ctx *c) {
   for (int i = 0; i < kSlots; ++i) {
     c->budget[i] = b0;
     c->expect[i] = b0;
+    c->rounds[i] = std::min(cfg.refine_maxit, 3);
   }
   c->prepared = true;
   c->dirty_T = true;
@@ -567,19 +591,38 @@ void collect_events(mrsdc_ctx *c) {
   c->ev_used = 0;
 }
 
-// One implicit node solve: init already enqueued; CG iterations in budget.
-void enqueue_cg(mrsdc_ctx *c, int k, int m) {
+// CG iterations of one solve within its launch budget.
+void enqueue_cg(mrsdc_ctx *c, int slot, int m, bool fp32) {
   const DevState &d = c->d;
-  launch_init_reduce(d, c->cfg.pcg_rtol, c->stream);
-  const int slot = slot_of(k, m);
   const int B = c->budget[slot];
   for (int it = 0; it < B; ++it) {
     const bool tail = it >= c->expect[slot];
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (!tail) take_events(c, 0, &e0, &e1);
-    launch_pcg_iter(d, m, it, tail, c->stream, e0, e1);
+    if (fp32) launch_pcg32_iter(d, m, slot, it, it == B - 1, tail, c->stream, e0, e1);
+    else launch_pcg_iter(d, m, slot, it, it == B - 1, tail, c->stream, e0, e1);
   }
-  launch_pcg_final(d, slot, c->stream);
+}
+
+// One implicit node solve of interval m (x = T[m] in place).
+void enqueue_solve(mrsdc_ctx *c, int k, int m) {
+  const DevState &d = c->d;
+  const mrsdc_config &cfg = c->cfg;
+  const int slot = slot_of(k, m);
+  if (cfg.precision == MRSDC_FP64) {
+    if (k == 0) launch_init_pred(d, m, slot, cfg.pcg_rtol, c->stream);
+    else launch_init_corr(d, m, slot, cfg.pcg_rtol, c->stream);
+    enqueue_cg(c, slot, m, false);
+    return;
+  }
+  // FP32 inner CG, FP64 refinement: rounds within a budget
+  launch_refine_init(d, m, slot, k == 0, cfg.refine_rtol, c->stream);
+  const int R = c->rounds[slot];
+  for (int r = 0; r < R; ++r) {
+    launch_inner_init(d, m, slot, cfg.inner_rtol, c->stream);
+    enqueue_cg(c, slot, m, true);
+    launch_refine_update(d, m, slot, r, r == R - 1, c->stream);
+  }
 }
 
 void enqueue_step(mrsdc_ctx *c) {
@@ -592,8 +635,7 @@ void enqueue_step(mrsdc_ctx *c) {
   // predictor (Alg. 1)
   for (int m = 1; m <= M; ++m) {
     if (c->w.dtau[m] == 0.0) continue;
-    launch_init_pred(d, m, st);
-    enqueue_cg(c, 0, m);
+    enqueue_solve(c, 0, m);
     hipEvent_t e0, e1;
     if (take_events(c, 1, &e0, &e1)) hipEventRecord(e0, st);
     launch_iface(d, m, false, st);
@@ -610,8 +652,7 @@ void enqueue_step(mrsdc_ctx *c) {
     if (k > K) break;
     for (int m = 1; m <= M; ++m) {
       if (c->w.dtau[m] == 0.0) continue;
-      launch_init_corr(d, m, st);
-      enqueue_cg(c, k, m);
+      enqueue_solve(c, k, m);
       hipEvent_t e0, e1;
       if (take_events(c, 1, &e0, &e1)) hipEventRecord(e0, st);
       launch_iface(d, m, true, st);
@@ -655,7 +696,6 @@ mrsdc_status mrsdc_create(mrsdc_ctx **out, const mrsdc_config *cfg) {
   if (!out) return MRSDC_EINVAL;
   *out = nullptr;
   if (!cfg || !valid_scheme(cfg)) return MRSDC_EINVAL;
-  if (cfg->precision == MRSDC_FP32_REFINE) return MRSDC_EINVAL;  // not built in this version
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || cfg->device < 0 || cfg->device >= n) {
     hipGetLastError();
@@ -849,25 +889,41 @@ mrsdc_status mrsdc_advance(mrsdc_ctx *c, double horizon, mrsdc_stats *stats) {
       HIPCHK(hipStreamSynchronize(c->stream));
       const StepCounters &h = *c->ctr_host;
       if (c->prof) collect_events(c);
+      const bool fp32 = c->cfg.precision == MRSDC_FP32_REFINE;
       if (h.fail == 0) {
         acc.pcg_iters += h.pcg_iters;
+        acc.refine_steps += h.refine_steps;
         acc.max_iters = std::max(acc.max_iters, h.max_iters);
         for (int k = 0; k <= Kc; ++k) acc.residual[k] = h.resid[k];
         for (int i = 0; i < kSlots; ++i) {
-          int it = h.slot_iters[i];
+          const int it = h.slot_iters[i];
           if (it > 0) {
             c->budget[i] = std::min(c->cfg.pcg_maxit, it + std::max(2, it / 5));
             c->expect[i] = it;
+          } else if (it < 0 && fp32 && c->budget[i] < c->cfg.pcg_maxit) {
+            c->budget[i] = std::min(c->cfg.pcg_maxit, 2 * c->budget[i]);  // inner solve cut short
           }
+          if (fp32 && h.slot_rounds[i] > 0)
+            c->rounds[i] = std::min(c->cfg.refine_maxit, h.slot_rounds[i] + 1);
         }
         break;
       }
       // some solve ran out of budget: the step was not committed
       bool grow = false;
       for (int i = 0; i < kSlots; ++i) {
-        if (h.slot_iters[i] < 0 && c->budget[i] < c->cfg.pcg_maxit) {
+        if (!fp32 && h.slot_iters[i] < 0 && c->budget[i] < c->cfg.pcg_maxit) {
           c->budget[i] = std::min(c->cfg.pcg_maxit, 2 * c->budget[i]);
           grow = true;
+        }
+        if (fp32 && h.slot_rounds[i] < 0) {
+          if (c->rounds[i] < c->cfg.refine_maxit) {
+            c->rounds[i] = std::min(c->cfg.refine_maxit, 2 * c->rounds[i]);
+            grow = true;
+          }
+          if (c->budget[i] < c->cfg.pcg_maxit) {
+            c->budget[i] = std::min(c->cfg.pcg_maxit, 2 * c->budget[i]);
+            grow = true;
+          }
         }
       }
       acc.redone_steps++;

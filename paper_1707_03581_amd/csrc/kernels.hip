@@ -6,6 +6,7 @@
 // each value/column load of a wave is one coalesced 512 B / 128 B access).
 // All reductions are deterministic: fixed row-to-block assignment, butterfly
 // wave sums, per-block partials reduced in a fixed order.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "mrsdc_internal.h"
@@ -215,25 +216,359 @@ void launch_quad_resid(const DevState &d, int k, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Implicit node solve (diag(m) + dtau L) x = b by Jacobi-preconditioned CG.
-// Three kernels per iteration; every kernel leaves at once when the solve is
-// done, so a fixed launch budget per solve needs no host round trip.
+// Implicit node solve (diag(m) + dtau L) x = b by Jacobi-preconditioned CG
+// (the paper leaves the solver open).  Three kernels per iteration:
+//   a: q = A p and p.q            -> last block: alpha
+//   b: x += alpha p, r -= alpha q -> last block: convergence, beta
+//   c: p = z + beta p
+// Every kernel returns at once when the solve is done, so a fixed launch
+// budget per solve needs no host round trip.  Global sums are deterministic:
+// each block publishes its partial, the last block to arrive adds them in
+// block order (agent-scope atomics order the partials across XCDs).
+// R is the arithmetic type of the iteration: double (FP64 path) or float
+// (inner solves of the FP32 path; products summed in double).
 // ---------------------------------------------------------------------------
-struct PcgArgs {
+// block sums -> partial[k*grid + block]; consumers read them after the kernel
+template <int K>
+__device__ inline void publish(double (&v)[K], double *partial, int grid, double *sh) {
+  for (int k = 0; k < K; ++k) v[k] = block_sum(v[k], sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < K; ++k) partial[k * grid + blockIdx.x] = v[k];
+}
+
+template <typename R>
+struct CgArgs {
   SellDev op;
   int64_t N;
   double dtau;
-  const double *mass, *dinv, *g;
-  double *x, *r, *p, *q;
+  const R *mass, *dinv;
+  const double *g;
+  R *x, *r, *p, *q;
   double *partial;  // [3*grid]
-  PcgScalars *sc;
-  int grid;
-  // init only
+  SolveScalars *sc;
+  StepCounters *ctr;
+  int slot, grid, inner;
+  // init / refinement
+  double *x64, *b64, *r64;
   const double *Tprev, *F, *I;
 };
 
-static PcgArgs pcg_args(const DevState &d, int m) {
-  PcgArgs a;
+template <bool D16, typename R>
+__device__ inline double sell_row_t(const SellDev &op, int64_t s, int lane, int64_t row,
+                                    const R *__restrict__ x);
+template <>
+__device__ inline double sell_row_t<true, double>(const SellDev &op, int64_t s, int lane,
+                                                  int64_t row, const double *__restrict__ x) {
+  return sell_row<true>(op, s, lane, row, x);
+}
+template <>
+__device__ inline double sell_row_t<false, double>(const SellDev &op, int64_t s, int lane,
+                                                   int64_t row, const double *__restrict__ x) {
+  return sell_row<false>(op, s, lane, row, x);
+}
+// FP32 operator: FP32 values, FP32 products and sums
+template <bool D16>
+__device__ inline float sell_row32(const SellDev &op, int64_t s, int lane, int64_t row,
+                                   const float *__restrict__ x) {
+  const int64_t end = op.off[s + 1];
+  int64_t e = op.off[s] + lane;
+  float acc = 0.0f;
+  if (D16) {
+#pragma unroll 4
+    for (; e < end; e += kSlice) acc += op.val32[e] * x[row + op.d16[e]];
+  } else {
+#pragma unroll 4
+    for (; e < end; e += kSlice) acc += op.val32[e] * x[op.c32[e]];
+  }
+  return acc;
+}
+template <>
+__device__ inline double sell_row_t<true, float>(const SellDev &op, int64_t s, int lane,
+                                                 int64_t row, const float *__restrict__ x) {
+  return sell_row32<true>(op, s, lane, row, x);
+}
+template <>
+__device__ inline double sell_row_t<false, float>(const SellDev &op, int64_t s, int lane,
+                                                  int64_t row, const float *__restrict__ x) {
+  return sell_row32<false>(op, s, lane, row, x);
+}
+// FP64 operator applied to an FP32 vector (refinement update)
+template <bool D16>
+__device__ inline double sell_row_mixed(const SellDev &op, int64_t s, int lane, int64_t row,
+                                        const float *__restrict__ x) {
+  const int64_t end = op.off[s + 1];
+  int64_t e = op.off[s] + lane;
+  double acc = 0.0;
+  if (D16) {
+#pragma unroll 4
+    for (; e < end; e += kSlice) acc += op.val[e] * (double)x[row + op.d16[e]];
+  } else {
+#pragma unroll 4
+    for (; e < end; e += kSlice) acc += op.val[e] * (double)x[op.c32[e]];
+  }
+  return acc;
+}
+
+__device__ inline bool solve_done(const SolveScalars *sc) { return sc->done || sc->ref_done; }
+
+// scalars of a fresh CG solve from the sums r.z, r.r, b.b
+__device__ inline void init_finish(SolveScalars *sc, StepCounters *ctr, int slot, int inner,
+                                   double rtol, const double (&o)[3]) {
+  sc->rz[0] = o[0];
+  sc->rz[1] = 0.0;
+  if (inner) {
+    sc->tol2 = rtol * rtol * o[1];   // relative to the inner right-hand side
+    sc->done = (o[1] == 0.0) ? 1 : 0;
+    return;
+  }
+  sc->bb = o[2];
+  sc->tol2 = rtol * rtol * o[2];
+  sc->done = (o[1] <= sc->tol2) ? 1 : 0;
+  sc->iters = 0;
+  if (sc->done) ctr->slot_iters[slot] = 0;
+}
+
+// predictor: x0 = T_{m-1}, b = M T_{m-1} + dtau g, r = b - A x0 (one SpMV)
+template <bool D16>
+__global__ __launch_bounds__(kBlock) void k_init_pred(CgArgs<double> a) {
+  __shared__ double sh[17];
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int64_t s = wave; s < a.op.nslices; s += nw) {
+    const int64_t row = s * kSlice + lane;
+    if (row >= a.N) continue;
+    const double Lx = sell_row<D16>(a.op, s, lane, row, a.Tprev);
+    const double x0 = a.Tprev[row], mi = a.mass[row];
+    const double b = mi * x0 + a.dtau * a.g[row];
+    const double r = b - (mi * x0 + a.dtau * Lx);
+    const double z = a.dinv[row] * r;
+    a.x[row] = x0;
+    a.r[row] = r;
+    a.p[row] = z;
+    v[0] += r * z;
+    v[1] += r * r;
+    v[2] += b * b;
+  }
+  publish<3>(v, a.partial, a.grid, sh);
+}
+
+// correction: x0 = T^k_m (in place), b = M T^{k+1}_{m-1} + dtau (g - F_m) + I_m,
+// and since L x0 = g - F_m the initial residual needs no SpMV:
+// r = M (T^{k+1}_{m-1} - T^k_m) + I_m.
+__global__ __launch_bounds__(kBlock) void k_init_corr(CgArgs<double> a) {
+  __shared__ double sh[17];
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.N;
+       i += (int64_t)gridDim.x * kBlock) {
+    const double mi = a.mass[i], tp = a.Tprev[i], x0 = a.x[i], Im = a.I[i];
+    const double b = mi * tp + a.dtau * (a.g[i] - a.F[i]) + Im;
+    const double r = mi * (tp - x0) + Im;
+    const double z = a.dinv[i] * r;
+    a.r[i] = r;
+    a.p[i] = z;
+    v[0] += r * z;
+    v[1] += r * r;
+    v[2] += b * b;
+  }
+  publish<3>(v, a.partial, a.grid, sh);
+}
+
+// One block: the scalars of a solve from the partials of the previous kernel.
+// mode 0: FP64 CG init (r.z, r.r, b.b)   1: refinement init (r.r, b.b)
+// mode 2: inner FP32 CG init (r.z, r.r)  3: refinement update (r.r)
+__global__ void k_solve_reduce(const double *part, int grid, SolveScalars *sc, StepCounters *ctr,
+                               int slot, int mode, double rtol, int round, int last_round) {
+  __shared__ double sh[17];
+  const int nk = (mode == 0) ? 3 : (mode == 3 ? 1 : 2);
+  double o[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < nk; ++k) o[k] = sum_partials(part + k * grid, grid, sh);
+  if (threadIdx.x != 0) return;
+  if (mode == 0) {
+    init_finish(sc, ctr, slot, 0, rtol, o);
+  } else if (mode == 1) {
+    sc->ref_bb = o[1];
+    sc->ref_tol2 = rtol * rtol * o[1];
+    sc->ref_done = (o[0] <= sc->ref_tol2) ? 1 : 0;
+    sc->ref_rounds = 0;
+    sc->done = 0;
+    ctr->slot_iters[slot] = 0;  // largest inner iteration count of the solve
+    if (sc->ref_done) ctr->slot_rounds[slot] = 0;
+  } else if (mode == 2) {
+    if (sc->ref_done) return;
+    init_finish(sc, ctr, slot, 1, rtol, o);
+  } else {
+    if (sc->ref_done) return;
+    sc->ref_rounds = round + 1;
+    ctr->refine_steps += 1;
+    if (o[0] <= sc->ref_tol2) {
+      sc->ref_done = 1;
+      ctr->slot_rounds[slot] = round + 1;
+    } else if (last_round) {
+      ctr->slot_rounds[slot] = -1;
+      ctr->fail += 1;
+    }
+  }
+}
+
+// (a) q = A p, p.q -> alpha.  TAIL marks launches past the iteration count of
+// the previous step (usually early exits), kept apart in profiles.
+template <bool D16, int TAIL, typename R>
+__global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
+  if (solve_done(a.sc)) return;
+  __shared__ double sh[17];
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+  double v[1] = {0.0};
+  for (int64_t s = wave; s < a.op.nslices; s += nw) {
+    const int64_t row = s * kSlice + lane;
+    if (row >= a.N) continue;
+    const R Lp = (R)sell_row_t<D16, R>(a.op, s, lane, row, a.p);
+    const R pi = a.p[row];
+    const R qi = a.mass[row] * pi + (R)a.dtau * Lp;
+    a.q[row] = qi;
+    v[0] += (double)pi * (double)qi;
+  }
+  publish<1>(v, a.partial, a.grid, sh);
+}
+
+// (b) alpha = r.z / p.q; x += alpha p; r -= alpha q; partial r.z, r.r
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_pcg_b(CgArgs<R> a, int it) {
+  if (solve_done(a.sc)) return;
+  __shared__ double sh[17];
+  const double pq = sum_partials(a.partial, a.grid, sh);
+  const R alpha = (R)(a.sc->rz[it & 1] / pq);
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.N;
+       i += (int64_t)gridDim.x * kBlock) {
+    a.x[i] += alpha * a.p[i];
+    const R r = a.r[i] - alpha * a.q[i];
+    a.r[i] = r;
+    v[0] += (double)r * (double)(a.dinv[i] * r);
+    v[1] += (double)r * (double)r;
+  }
+  double *part = a.partial + a.grid;
+  for (int k = 0; k < 2; ++k) v[k] = block_sum(v[k], sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = v[0];
+    part[a.grid + blockIdx.x] = v[1];
+  }
+}
+
+// (c) convergence test; beta = r.z_new / r.z; p = z + beta p
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_pcg_c(CgArgs<R> a, int it, int last) {
+  if (solve_done(a.sc)) return;
+  __shared__ double sh[17];
+  const double rz = sum_partials(a.partial + a.grid, a.grid, sh);
+  const double rr = sum_partials(a.partial + 2 * a.grid, a.grid, sh);
+  SolveScalars *sc = a.sc;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (rr <= sc->tol2) {
+    if (lead) {
+      StepCounters *ctr = a.ctr;
+      sc->done = 1;
+      sc->iters = it + 1;
+      ctr->pcg_iters += it + 1;
+      if (!a.inner) ctr->slot_iters[a.slot] = it + 1;
+      else if (ctr->slot_iters[a.slot] >= 0 && it + 1 > ctr->slot_iters[a.slot])
+        ctr->slot_iters[a.slot] = it + 1;
+      if (it + 1 > ctr->max_iters) ctr->max_iters = it + 1;
+    }
+    return;
+  }
+  const R beta = (R)(rz / sc->rz[it & 1]);
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.N;
+       i += (int64_t)gridDim.x * kBlock)
+    a.p[i] = a.dinv[i] * a.r[i] + beta * a.p[i];
+  if (lead) {
+    sc->rz[(it + 1) & 1] = rz;
+    if (last) {
+      // budget exhausted: the FP64 solve failed; an inner solve only signals it
+      a.ctr->slot_iters[a.slot] = -1;
+      a.ctr->pcg_iters += it + 1;
+      if (!a.inner) a.ctr->fail += 1;
+    }
+  }
+}
+
+// ---- FP64 iterative refinement around FP32 inner solves ----
+// init: b and r = b - A x0 in FP64 (corrections without SpMV as above)
+template <bool D16, bool PRED>
+__global__ __launch_bounds__(kBlock) void k_rinit(CgArgs<float> a, const double *mass64) {
+  __shared__ double sh[17];
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+  double v[2] = {0.0, 0.0};
+  for (int64_t s = wave; s < a.op.nslices; s += nw) {
+    const int64_t row = s * kSlice + lane;
+    if (row >= a.N) continue;
+    const double mi = mass64[row], tp = a.Tprev[row];
+    double b, r;
+    if (PRED) {
+      const double Lx = sell_row<D16>(a.op, s, lane, row, a.Tprev);
+      b = mi * tp + a.dtau * a.g[row];
+      r = b - (mi * tp + a.dtau * Lx);
+      a.x64[row] = tp;
+    } else {
+      const double Im = a.I[row];
+      b = mi * tp + a.dtau * (a.g[row] - a.F[row]) + Im;
+      r = mi * (tp - a.x64[row]) + Im;
+    }
+    a.b64[row] = b;
+    a.r64[row] = r;
+    v[0] += r * r;
+    v[1] += b * b;
+  }
+  publish<2>(v, a.partial, a.grid, sh);
+}
+
+// inner init: r32 = r64, d = 0, p = dinv r32; tolerance relative to ||r32||
+__global__ __launch_bounds__(kBlock) void k_inner_init(CgArgs<float> a) {
+  if (a.sc->ref_done) return;
+  __shared__ double sh[17];
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.N;
+       i += (int64_t)gridDim.x * kBlock) {
+    const float r = (float)a.r64[i];
+    const float z = a.dinv[i] * r;
+    a.r[i] = r;
+    a.x[i] = 0.0f;
+    a.p[i] = z;
+    v[0] += (double)r * (double)z;
+    v[1] += (double)r * (double)r;
+  }
+  publish<2>(v, a.partial, a.grid, sh);
+}
+
+// x64 += d; r64 -= A d (FP64 operator); ||r64|| -> refinement converged?
+template <bool D16>
+__global__ __launch_bounds__(kBlock) void k_refine_update(CgArgs<float> a, const double *mass64) {
+  if (a.sc->ref_done) return;
+  __shared__ double sh[17];
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+  double v[1] = {0.0};
+  for (int64_t s = wave; s < a.op.nslices; s += nw) {
+    const int64_t row = s * kSlice + lane;
+    if (row >= a.N) continue;
+    const double d = (double)a.x[row];
+    const double Ad = mass64[row] * d + a.dtau * sell_row_mixed<D16>(a.op, s, lane, row, a.x);
+    a.x64[row] += d;
+    const double r = a.r64[row] - Ad;
+    a.r64[row] = r;
+    v[0] += r * r;
+  }
+  publish<1>(v, a.partial, a.grid, sh);
+}
+
+static CgArgs<double> cg64(const DevState &d, int m, int slot) {
+  CgArgs<double> a;
   a.op = d.op;
   a.N = d.N;
   a.dtau = d.dtau_h[m];
@@ -246,201 +581,110 @@ static PcgArgs pcg_args(const DevState &d, int m) {
   a.q = d.q;
   a.partial = d.partial;
   a.sc = d.sc;
+  a.ctr = d.ctr;
+  a.slot = slot;
   a.grid = d.grid;
+  a.inner = 0;
+  a.x64 = d.T[m];
+  a.b64 = nullptr;
+  a.r64 = nullptr;
   a.Tprev = d.T[m - 1];
   a.F = d.F[m];
   a.I = d.I[m];
   return a;
 }
 
-// predictor: x0 = T_{m-1}, b = M T_{m-1} + dtau g, r = b - A x0 (one SpMV)
-template <bool D16>
-__global__ __launch_bounds__(kBlock) void k_init_pred(PcgArgs a) {
-  __shared__ double sh[17];
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
-  double rz = 0.0, rr = 0.0, bb = 0.0;
-  for (int64_t s = wave; s < a.op.nslices; s += nw) {
-    const int64_t row = s * kSlice + lane;
-    if (row >= a.N) continue;
-    const double Lx = sell_row<D16>(a.op, s, lane, row, a.Tprev);
-    const double x0 = a.Tprev[row], mi = a.mass[row];
-    const double b = mi * x0 + a.dtau * a.g[row];
-    const double r = b - (mi * x0 + a.dtau * Lx);
-    const double z = a.dinv[row] * r;
-    a.x[row] = x0;
-    a.r[row] = r;
-    a.p[row] = z;
-    rz += r * z;
-    rr += r * r;
-    bb += b * b;
-  }
-  rz = block_sum(rz, sh);
-  rr = block_sum(rr, sh);
-  bb = block_sum(bb, sh);
-  if (threadIdx.x == 0) {
-    a.partial[blockIdx.x] = rz;
-    a.partial[a.grid + blockIdx.x] = rr;
-    a.partial[2 * a.grid + blockIdx.x] = bb;
-  }
+static CgArgs<float> cg32(const DevState &d, int m, int slot) {
+  CgArgs<float> a;
+  a.op = d.op;
+  a.N = d.N;
+  a.dtau = d.dtau_h[m];
+  a.mass = d.mass32;
+  a.dinv = d.dinv32[m];
+  a.g = d.g;
+  a.x = d.x32;
+  a.r = d.r32;
+  a.p = d.p32;
+  a.q = d.q32;
+  a.partial = d.partial;
+  a.sc = d.sc;
+  a.ctr = d.ctr;
+  a.slot = slot;
+  a.grid = d.grid;
+  a.inner = 1;
+  a.x64 = d.T[m];
+  a.b64 = d.b64;
+  a.r64 = d.r64;
+  a.Tprev = d.T[m - 1];
+  a.F = d.F[m];
+  a.I = d.I[m];
+  return a;
 }
 
-// correction: x0 = T^k_m (in place), b = M T^{k+1}_{m-1} + dtau (g - F_m) + I_m,
-// and since L x0 = g - F_m the initial residual needs no SpMV:
-// r = M (T^{k+1}_{m-1} - T^k_m) + I_m.
-__global__ __launch_bounds__(kBlock) void k_init_corr(PcgArgs a) {
-  __shared__ double sh[17];
-  double rz = 0.0, rr = 0.0, bb = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.N;
-       i += (int64_t)gridDim.x * kBlock) {
-    const double mi = a.mass[i], tp = a.Tprev[i], x0 = a.x[i], Im = a.I[i];
-    const double b = mi * tp + a.dtau * (a.g[i] - a.F[i]) + Im;
-    const double r = mi * (tp - x0) + Im;
-    const double z = a.dinv[i] * r;
-    a.r[i] = r;
-    a.p[i] = z;
-    rz += r * z;
-    rr += r * r;
-    bb += b * b;
-  }
-  rz = block_sum(rz, sh);
-  rr = block_sum(rr, sh);
-  bb = block_sum(bb, sh);
-  if (threadIdx.x == 0) {
-    a.partial[blockIdx.x] = rz;
-    a.partial[a.grid + blockIdx.x] = rr;
-    a.partial[2 * a.grid + blockIdx.x] = bb;
-  }
+static void solve_reduce(const DevState &d, int slot, int mode, double rtol, int round,
+                         bool last_round, hipStream_t st) {
+  k_solve_reduce<<<1, kBlock, 0, st>>>(d.partial, d.grid, d.sc, d.ctr, slot, mode, rtol, round,
+                                       last_round ? 1 : 0);
 }
 
-__global__ void k_init_reduce(const double *part, int grid, PcgScalars *sc, double rtol) {
-  __shared__ double sh[17];
-  const double rz = sum_partials(part, grid, sh);
-  const double rr = sum_partials(part + grid, grid, sh);
-  const double bb = sum_partials(part + 2 * grid, grid, sh);
-  if (threadIdx.x == 0) {
-    sc->rz[0] = rz;
-    sc->rz[1] = 0.0;
-    sc->bb = bb;
-    sc->tol2 = rtol * rtol * bb;
-    sc->done = (rr <= sc->tol2) ? 1 : 0;
-    sc->iters = 0;
-  }
-}
-
-// (a) q = A p, partial p.q.  TAIL marks launches past the iteration count of
-// the previous step (usually early exits), kept apart in profiles.
-template <bool D16, int TAIL>
-__global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a) {
-  if (a.sc->done) return;
-  __shared__ double sh[17];
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
-  double pq = 0.0;
-  for (int64_t s = wave; s < a.op.nslices; s += nw) {
-    const int64_t row = s * kSlice + lane;
-    if (row >= a.N) continue;
-    const double Lp = sell_row<D16>(a.op, s, lane, row, a.p);
-    const double pi = a.p[row];
-    const double qi = a.mass[row] * pi + a.dtau * Lp;
-    a.q[row] = qi;
-    pq += pi * qi;
-  }
-  pq = block_sum(pq, sh);
-  if (threadIdx.x == 0) a.partial[blockIdx.x] = pq;
-}
-
-// (b) alpha = rz / pq; x += alpha p; r -= alpha q; partial r.z, r.r
-__global__ __launch_bounds__(kBlock) void k_pcg_b(PcgArgs a, int it) {
-  if (a.sc->done) return;
-  __shared__ double sh[17];
-  const double pq = sum_partials(a.partial, a.grid, sh);
-  const double alpha = a.sc->rz[it & 1] / pq;
-  double rz = 0.0, rr = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.N;
-       i += (int64_t)gridDim.x * kBlock) {
-    const double pi = a.p[i];
-    a.x[i] += alpha * pi;
-    const double r = a.r[i] - alpha * a.q[i];
-    a.r[i] = r;
-    rz += r * (a.dinv[i] * r);
-    rr += r * r;
-  }
-  rz = block_sum(rz, sh);
-  rr = block_sum(rr, sh);
-  if (threadIdx.x == 0) {
-    a.partial[a.grid + blockIdx.x] = rz;
-    a.partial[2 * a.grid + blockIdx.x] = rr;
-  }
-}
-
-// (c) convergence test, beta, p = z + beta p
-__global__ __launch_bounds__(kBlock) void k_pcg_c(PcgArgs a, int it) {
-  if (a.sc->done) return;
-  __shared__ double sh[17];
-  const double rz = sum_partials(a.partial + a.grid, a.grid, sh);
-  const double rr = sum_partials(a.partial + 2 * a.grid, a.grid, sh);
-  if (rr <= a.sc->tol2) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      a.sc->done = 1;
-      a.sc->iters = it + 1;
-    }
-    return;
-  }
-  const double beta = rz / a.sc->rz[it & 1];
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.N;
-       i += (int64_t)gridDim.x * kBlock)
-    a.p[i] = a.dinv[i] * a.r[i] + beta * a.p[i];
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.sc->rz[(it + 1) & 1] = rz;
-}
-
-__global__ void k_pcg_final(PcgScalars *sc, StepCounters *ctr, int slot) {
-  if (threadIdx.x != 0) return;
-  if (!sc->done) {
-    ctr->fail += 1;
-    ctr->slot_iters[slot] = -1;
-    return;
-  }
-  ctr->pcg_iters += sc->iters;
-  ctr->slot_iters[slot] = sc->iters;
-  if (sc->iters > ctr->max_iters) ctr->max_iters = sc->iters;
-}
-
-void launch_init_pred(const DevState &d, int m, hipStream_t st) {
-  PcgArgs a = pcg_args(d, m);
+void launch_init_pred(const DevState &d, int m, int slot, double rtol, hipStream_t st) {
+  CgArgs<double> a = cg64(d, m, slot);
   if (d.op.d16) k_init_pred<true><<<d.grid, kBlock, 0, st>>>(a);
   else k_init_pred<false><<<d.grid, kBlock, 0, st>>>(a);
+  solve_reduce(d, slot, 0, rtol, 0, false, st);
 }
 
-void launch_init_corr(const DevState &d, int m, hipStream_t st) {
-  PcgArgs a = pcg_args(d, m);
-  k_init_corr<<<d.grid, kBlock, 0, st>>>(a);
+void launch_init_corr(const DevState &d, int m, int slot, double rtol, hipStream_t st) {
+  k_init_corr<<<d.grid, kBlock, 0, st>>>(cg64(d, m, slot));
+  solve_reduce(d, slot, 0, rtol, 0, false, st);
 }
 
-void launch_init_reduce(const DevState &d, double rtol, hipStream_t st) {
-  k_init_reduce<<<1, kBlock, 0, st>>>(d.partial, d.grid, d.sc, rtol);
+template <typename R>
+static void pcg_iter(const DevState &d, const CgArgs<R> &a, int it, bool last, bool tail,
+                     hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  // with events: the dispatch's own start/end timestamps (AMD launch extension)
+  auto kern = d.op.d16 ? (tail ? k_pcg_a<true, 1, R> : k_pcg_a<true, 0, R>)
+                       : (tail ? k_pcg_a<false, 1, R> : k_pcg_a<false, 0, R>);
+  if (ev0) hipExtLaunchKernelGGL(kern, dim3(d.grid), dim3(kBlock), 0, st, ev0, ev1, 0, a, it);
+  else kern<<<d.grid, kBlock, 0, st>>>(a, it);
+  k_pcg_b<R><<<d.grid, kBlock, 0, st>>>(a, it);
+  k_pcg_c<R><<<d.grid, kBlock, 0, st>>>(a, it, last ? 1 : 0);
 }
 
-void launch_pcg_iter(const DevState &d, int m, int it, bool tail, hipStream_t st,
-                     hipEvent_t ev0, hipEvent_t ev1) {
-  PcgArgs a = pcg_args(d, m);
-  if (ev0) hipEventRecord(ev0, st);
+void launch_pcg_iter(const DevState &d, int m, int slot, int it, bool last, bool tail,
+                     hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  pcg_iter(d, cg64(d, m, slot), it, last, tail, st, ev0, ev1);
+}
+
+void launch_refine_init(const DevState &d, int m, int slot, bool pred, double rtol,
+                        hipStream_t st) {
+  CgArgs<float> a = cg32(d, m, slot);
   if (d.op.d16) {
-    if (tail) k_pcg_a<true, 1><<<d.grid, kBlock, 0, st>>>(a);
-    else k_pcg_a<true, 0><<<d.grid, kBlock, 0, st>>>(a);
+    if (pred) k_rinit<true, true><<<d.grid, kBlock, 0, st>>>(a, d.mass);
+    else k_rinit<true, false><<<d.grid, kBlock, 0, st>>>(a, d.mass);
   } else {
-    if (tail) k_pcg_a<false, 1><<<d.grid, kBlock, 0, st>>>(a);
-    else k_pcg_a<false, 0><<<d.grid, kBlock, 0, st>>>(a);
+    if (pred) k_rinit<false, true><<<d.grid, kBlock, 0, st>>>(a, d.mass);
+    else k_rinit<false, false><<<d.grid, kBlock, 0, st>>>(a, d.mass);
   }
-  if (ev1) hipEventRecord(ev1, st);
-  k_pcg_b<<<d.grid, kBlock, 0, st>>>(a, it);
-  k_pcg_c<<<d.grid, kBlock, 0, st>>>(a, it);
+  solve_reduce(d, slot, 1, rtol, 0, false, st);
 }
 
-void launch_pcg_final(const DevState &d, int slot, hipStream_t st) {
-  k_pcg_final<<<1, 64, 0, st>>>(d.sc, d.ctr, slot);
+void launch_inner_init(const DevState &d, int m, int slot, double inner_rtol, hipStream_t st) {
+  k_inner_init<<<d.grid, kBlock, 0, st>>>(cg32(d, m, slot));
+  solve_reduce(d, slot, 2, inner_rtol, 0, false, st);
+}
+
+void launch_pcg32_iter(const DevState &d, int m, int slot, int it, bool last, bool tail,
+                       hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  pcg_iter(d, cg32(d, m, slot), it, last, tail, st, ev0, ev1);
+}
+
+void launch_refine_update(const DevState &d, int m, int slot, int round, bool last_round,
+                          hipStream_t st) {
+  CgArgs<float> a = cg32(d, m, slot);
+  if (d.op.d16) k_refine_update<true><<<d.grid, kBlock, 0, st>>>(a, d.mass);
+  else k_refine_update<false><<<d.grid, kBlock, 0, st>>>(a, d.mass);
+  solve_reduce(d, slot, 3, 0.0, round, last_round, st);
 }
 
 // ---------------------------------------------------------------------------

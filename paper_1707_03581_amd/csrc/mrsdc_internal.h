@@ -44,14 +44,15 @@ struct SellDev {
   const int32_t *c32 = nullptr;   // [nelem] or null
 };
 
-// Per-solve device scalars of the CG iteration.
-struct PcgScalars {
-  double rz[2];   // r.z of the current/next iteration, by parity
-  double tol2;    // rtol^2 ||b||^2
-  double bb;
-  int done;
-  int iters;
-  int pad[2];
+// Per-solve device scalars of the CG iteration and of the refinement loop.
+struct SolveScalars {
+  double rz[2];      // r.z of the current/next iteration, by parity
+  double tol2;       // CG stopping threshold on ||r||^2
+  double bb;         // ||b||^2
+  double alpha, beta;
+  double ref_bb, ref_tol2;
+  int done, iters;
+  int ref_done, ref_rounds;
 };
 
 // Device-side counters of one time step, read back once per step.
@@ -64,7 +65,8 @@ struct StepCounters {
   int fail;                 // solves that hit their budget
   int pad[2];
   double resid[17];         // residual of iterate k
-  int slot_iters[kSlots];   // iterations of each solve of the step (-1: failed)
+  int slot_iters[kSlots];   // iterations of each solve of the step (-1: budget hit)
+  int slot_rounds[kSlots];  // refinement rounds of each solve (-1: failed)
 };
 
 // Coupling data of f^E on device (contact between two face grids, or patch).
@@ -102,6 +104,7 @@ struct DevState {
   const double *mass = nullptr, *g = nullptr, *Ldiag = nullptr;
   double *dinv[kMaxM + 1] = {};       // Jacobi inverse per interval
   float *dinv32[kMaxM + 1] = {};
+  const float *mass32 = nullptr;
   const Weights *w = nullptr;         // device copy
   const int *ifpos = nullptr;         // [N] interface index or -1
   double *T[kMaxM + 1] = {};          // standard-node states (T[0] = T_n)
@@ -109,8 +112,9 @@ struct DevState {
   double *I[kMaxM + 1] = {};          // I_{m-1}^m
   double *r = nullptr, *p = nullptr, *q = nullptr;  // CG work
   float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *x32 = nullptr;
+  double *b64 = nullptr, *r64 = nullptr;  // refinement right-hand side and residual
   double *partial = nullptr;          // [3 * grid]
-  PcgScalars *sc = nullptr;
+  SolveScalars *sc = nullptr;
   StepCounters *ctr = nullptr;
   double *tn = nullptr;               // device scalar: t_n of the current step
   IfaceDev ifc;
@@ -124,12 +128,17 @@ struct DevState {
 // ---- kernel launchers (kernels.hip) ----
 void launch_f_multi(const DevState &d, int j0, int j1, hipStream_t st);
 void launch_quad_resid(const DevState &d, int k, hipStream_t st);
-void launch_init_pred(const DevState &d, int m, hipStream_t st);
-void launch_init_corr(const DevState &d, int m, hipStream_t st);
-void launch_init_reduce(const DevState &d, double rtol, hipStream_t st);
-void launch_pcg_iter(const DevState &d, int m, int it, bool tail, hipStream_t st,
-                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-void launch_pcg_final(const DevState &d, int slot, hipStream_t st);
+void launch_init_pred(const DevState &d, int m, int slot, double rtol, hipStream_t st);
+void launch_init_corr(const DevState &d, int m, int slot, double rtol, hipStream_t st);
+void launch_pcg_iter(const DevState &d, int m, int slot, int it, bool last, bool tail,
+                     hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+void launch_refine_init(const DevState &d, int m, int slot, bool pred, double rtol,
+                        hipStream_t st);
+void launch_inner_init(const DevState &d, int m, int slot, double inner_rtol, hipStream_t st);
+void launch_pcg32_iter(const DevState &d, int m, int slot, int it, bool last, bool tail,
+                       hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+void launch_refine_update(const DevState &d, int m, int slot, int round, bool last_round,
+                          hipStream_t st);
 void launch_clear_counters(const DevState &d, hipStream_t st);
 size_t coef_table_doubles(const IfaceDev &f);
 size_t coef_table_ints(const IfaceDev &f);
@@ -137,12 +146,6 @@ void launch_iface_coeffs(const DevState &d, hipStream_t st);
 void launch_iface(const DevState &d, int m, bool corr, hipStream_t st);
 void launch_step_end(const DevState &d, double dt, hipStream_t st);
 void launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
-// FP32 inner solve with FP64 refinement
-void launch_refine_resid_corr(const DevState &d, int m, hipStream_t st);
-void launch_refine_resid_spmv(const DevState &d, int m, bool pred, hipStream_t st);
-void launch_refine_reduce(const DevState &d, double rtol_outer, double rtol_inner, hipStream_t st);
-void launch_pcg32_iter(const DevState &d, int m, int it, hipStream_t st);
-void launch_refine_update(const DevState &d, hipStream_t st);
 
 // host+device helpers for the 1D face integrals
 __host__ __device__ double hat_integral(const double *x, int n, int a, double lo, double hi);

@@ -182,3 +182,41 @@ def test_zero_horizon_and_device_copy():
     assert np.array_equal(out.cpu().numpy(), host)
     assert ctx.footprint_bytes() > 0
     ctx.destroy()
+
+
+# ---------------------------------------------------------------------------
+# FP32 inner CG + FP64 iterative refinement: <= 1e-7 relative L2 vs the FP64
+# oracle (the refinement drives each solve to 1e-10; f^E, quadrature and node
+# states stay FP64).
+# ---------------------------------------------------------------------------
+TOL32 = 1e-7
+
+
+@pytest.mark.parametrize("name", ["box_patch_lobatto3", "machine_lobatto5", "machine_nonmatching",
+                                  "machine_equi4_P1"])
+def test_fp32_refine_small_cases(name):
+    pb = CASES[name]()
+    ref, _ = oracle.run(pb, nsteps=pb.nsteps)
+    T, st = run_gpu(pb, pb.nsteps, precision=1)
+    e = rel(T, ref)
+    print(f"  N={pb.N} rel_l2={e:.3e} change_rel={change_rel(T, ref, pb.T0):.3e} "
+          f"inner_iters={st['pcg_iters']} refinements={st['refine_steps']}", flush=True)
+    assert e <= TOL32
+    assert st["refine_steps"] > 0
+
+
+def test_fp32_refine_machine_310k_sampled_steps():
+    pb = mi.config2(nsteps=3)
+    ref, _ = oracle.run(pb, nsteps=3)
+    T, st = run_gpu(pb, 3, precision=1)
+    e = rel(T, ref)
+    print(f"  rel_l2={e:.3e} change_rel={change_rel(T, ref, pb.T0):.3e} "
+          f"inner_iters={st['pcg_iters']} refinements={st['refine_steps']}", flush=True)
+    assert e <= TOL32
+
+
+def test_fp32_refine_deterministic():
+    pb = small_machine()
+    a, _ = run_gpu(pb, 3, precision=1)
+    b, _ = run_gpu(pb, 3, precision=1)
+    assert np.array_equal(a, b)
