@@ -195,6 +195,13 @@ typedef struct {
 mrsdc_status mrsdc_profile(mrsdc_ctx *ctx, int on);
 mrsdc_status mrsdc_profile_read(const mrsdc_ctx *ctx, mrsdc_kernel_times *out);
 
+/* Launch the CG operator application q = (diag(m) + dtau L) p (FP32 operator
+ * for FP32_REFINE) reps times back to back between two HIP events on the
+ * context's stream and report the average time per launch in microseconds and
+ * its algorithmic bytes (as cg_spmv_bytes).  Needs a prepared context (one
+ * advance); overwrites only CG scratch vectors.  For roofline measurement. */
+mrsdc_status mrsdc_time_operator(mrsdc_ctx *ctx, int reps, double *avg_us, int64_t *bytes);
+
 /* Library version string. */
 const char *mrsdc_version(void);
 

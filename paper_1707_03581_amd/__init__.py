@@ -87,6 +87,8 @@ _SIGS = {
     "mrsdc_version": (C.c_char_p, []),
     "mrsdc_profile": (C.c_int, [C.c_void_p, C.c_int]),
     "mrsdc_profile_read": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mrsdc_time_operator": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double),
+                                      C.POINTER(C.c_int64)]),
 }
 
 
@@ -225,6 +227,13 @@ class Context:
         kt = KernelTimes()
         self._chk(self._L.mrsdc_profile_read(self._h, C.byref(kt)))
         return kt.as_dict()
+
+    def time_operator(self, reps=200):
+        """(average microseconds per launch, algorithmic bytes per launch)."""
+        us = C.c_double()
+        by = C.c_int64()
+        self._chk(self._L.mrsdc_time_operator(self._h, reps, C.byref(us), C.byref(by)))
+        return us.value, by.value
 
     def last_error(self):
         return self._L.mrsdc_last_error(self._h).decode()

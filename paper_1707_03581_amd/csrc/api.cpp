@@ -1000,6 +1000,29 @@ mrsdc_status mrsdc_profile_read(const mrsdc_ctx *c, mrsdc_kernel_times *out) {
   return MRSDC_OK;
 }
 
+mrsdc_status mrsdc_time_operator(mrsdc_ctx *c, int reps, double *avg_us, int64_t *bytes) {
+  if (!c || reps < 1 || !avg_us) return MRSDC_EINVAL;
+  if (!c->prepared) return fail(c, MRSDC_ESTATE, "advance at least once before timing");
+  int m = 1;
+  while (m <= c->cfg.M && c->w.dtau[m] == 0.0) ++m;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const bool fp32 = c->cfg.precision == MRSDC_FP32_REFINE;
+  launch_operator_timing(c->d, m, fp32, 3, c->stream);  // warm caches and clocks
+  HIPCHK(hipEventRecord(e0, c->stream));
+  launch_operator_timing(c->d, m, fp32, reps, c->stream);
+  HIPCHK(hipEventRecord(e1, c->stream));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *avg_us = 1e3 * ms / reps;
+  if (bytes) *bytes = c->times.cg_spmv_bytes;
+  return MRSDC_OK;
+}
+
 mrsdc_status mrsdc_footprint_bytes(const mrsdc_ctx *c, int64_t *bytes) {
   if (!c || !bytes) return MRSDC_EINVAL;
   *bytes = c->footprint;

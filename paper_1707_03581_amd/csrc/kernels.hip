@@ -412,11 +412,12 @@ __global__ void k_solve_reduce(const double *part, int grid, SolveScalars *sc, S
   }
 }
 
-// (a) q = A p, p.q -> alpha.  TAIL marks launches past the iteration count of
-// the previous step (usually early exits), kept apart in profiles.
+// (a) q = A p, partial p.q.  TAIL = 1 marks launches past the iteration count
+// of the previous step (usually early exits), TAIL = 2 the stand-alone timing
+// launches (which ignore the convergence flag); both kept apart in profiles.
 template <bool D16, int TAIL, typename R>
 __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
-  if (solve_done(a.sc)) return;
+  if (TAIL != 2 && solve_done(a.sc)) return;
   __shared__ double sh[17];
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
@@ -654,6 +655,25 @@ static void pcg_iter(const DevState &d, const CgArgs<R> &a, int it, bool last, b
 void launch_pcg_iter(const DevState &d, int m, int slot, int it, bool last, bool tail,
                      hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   pcg_iter(d, cg64(d, m, slot), it, last, tail, st, ev0, ev1);
+}
+
+// reps back-to-back operator applications q = A p of interval m (timing only;
+// p holds the last solve's direction, q and the partials are scratch)
+void launch_operator_timing(const DevState &d, int m, bool fp32, int reps, hipStream_t st) {
+  if (fp32) {
+    CgArgs<float> a = cg32(d, m, 0);
+    for (int i = 0; i < reps; ++i) {
+      if (d.op.d16) k_pcg_a<true, 2, float><<<d.grid, kBlock, 0, st>>>(a, 0);
+      else k_pcg_a<false, 2, float><<<d.grid, kBlock, 0, st>>>(a, 0);
+    }
+  } else {
+    CgArgs<double> a = cg64(d, m, 0);
+    a.x = nullptr;
+    for (int i = 0; i < reps; ++i) {
+      if (d.op.d16) k_pcg_a<true, 2, double><<<d.grid, kBlock, 0, st>>>(a, 0);
+      else k_pcg_a<false, 2, double><<<d.grid, kBlock, 0, st>>>(a, 0);
+    }
+  }
 }
 
 void launch_refine_init(const DevState &d, int m, int slot, bool pred, double rtol,

@@ -139,6 +139,7 @@ void launch_pcg32_iter(const DevState &d, int m, int slot, int it, bool last, bo
                        hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_refine_update(const DevState &d, int m, int slot, int round, bool last_round,
                           hipStream_t st);
+void launch_operator_timing(const DevState &d, int m, bool fp32, int reps, hipStream_t st);
 void launch_clear_counters(const DevState &d, hipStream_t st);
 size_t coef_table_doubles(const IfaceDev &f);
 size_t coef_table_ints(const IfaceDev &f);
