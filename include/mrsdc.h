@@ -176,6 +176,43 @@ mrsdc_status mrsdc_destroy(mrsdc_ctx *ctx);
 mrsdc_status mrsdc_quadrature(int M, int node_family, int P, double dt, double *tau,
                               double *s, double *shat, double *stil, double *spq);
 
+/* ---- Batched ensembles: S scenarios of one machine advanced together ----
+ * The scenarios share the operators, faces, motion law and scheme set with
+ * the single-context calls above (mrsdc_set_body, _set_robin, _set_face,
+ * _set_motion, _set_contact); each scenario has its own Robin coefficient h,
+ * contact alpha, friction power, motion period, time and temperature field.
+ * The operator is applied to all scenarios in one pass (multi-right-hand
+ * side).  FP64 path, contact coupling (or none).  A scenario's result does
+ * not depend on the other members of the batch. */
+
+/* Create a batched context of S scenarios (1..64).  EINVAL for S out of
+ * range or a precision other than MRSDC_FP64. */
+mrsdc_status mrsdc_batch_create(mrsdc_ctx **out, const mrsdc_config *cfg, int S);
+
+/* Parameters of scenario s; unset scenarios use the context-wide values. */
+mrsdc_status mrsdc_batch_set_scenario(mrsdc_ctx *ctx, int s, double h, double alpha,
+                                      double friction_W, double period);
+
+/* Temperature of scenario s over all nodes of both bodies (n = total nodes,
+ * concatenated in body order); host array, copied. */
+mrsdc_status mrsdc_batch_set_temperature(mrsdc_ctx *ctx, int s, const double *T, int64_t n);
+
+/* Current time of scenario s (each scenario has its own clock). */
+mrsdc_status mrsdc_batch_set_time(mrsdc_ctx *ctx, int s, double t);
+mrsdc_status mrsdc_batch_get_time(const mrsdc_ctx *ctx, int s, double *t);
+
+/* Include (active != 0) or leave out scenario s in the next steps; inactive
+ * scenarios keep their state and clock. */
+mrsdc_status mrsdc_batch_set_active(mrsdc_ctx *ctx, int s, int active);
+
+/* Advance every active scenario by nsteps time steps of dt; waits for the
+ * device.  Statistics add over the active scenarios.  ENOCONV leaves every
+ * scenario at its last completed step. */
+mrsdc_status mrsdc_batch_advance(mrsdc_ctx *ctx, int nsteps, mrsdc_stats *stats);
+
+/* Temperature of scenario s over all nodes (n = total nodes) into a host array. */
+mrsdc_status mrsdc_batch_get_temperature(mrsdc_ctx *ctx, int s, double *out, int64_t n);
+
 /* Per-kernel-class device time measured with HIP events on the context's
  * stream while profiling is on (mrsdc_profile).  cg_spmv: the operator
  * application q = (diag(m) + dtau L) p of every CG iteration within the

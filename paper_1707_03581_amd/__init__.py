@@ -86,6 +86,15 @@ _SIGS = {
                                    C.c_void_p, C.c_void_p, C.c_void_p]),
     "mrsdc_version": (C.c_char_p, []),
     "mrsdc_profile": (C.c_int, [C.c_void_p, C.c_int]),
+    "mrsdc_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_void_p, C.c_int]),
+    "mrsdc_batch_set_scenario": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_double,
+                                           C.c_double, C.c_double]),
+    "mrsdc_batch_set_temperature": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int64]),
+    "mrsdc_batch_set_time": (C.c_int, [C.c_void_p, C.c_int, C.c_double]),
+    "mrsdc_batch_get_time": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double)]),
+    "mrsdc_batch_set_active": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    "mrsdc_batch_advance": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    "mrsdc_batch_get_temperature": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int64]),
     "mrsdc_profile_read": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mrsdc_time_operator": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int64)]),
@@ -250,6 +259,48 @@ class Context:
             pass
 
 
+class BatchContext(Context):
+    """S scenarios of one machine on one GPU (shared operators, per-scenario
+    h, alpha, friction power, motion period, time and temperature)."""
+
+    def __init__(self, cfg: Config, S: int):
+        self._L = lib()
+        self._h = C.c_void_p()
+        self.cfg = cfg
+        self.S = S
+        rc = self._L.mrsdc_batch_create(C.byref(self._h), C.byref(cfg), S)
+        if rc:
+            raise MrsdcError(rc, "mrsdc_batch_create failed (scheme, S or device)")
+
+    def set_scenario(self, s, h, alpha, friction_W, period):
+        return self._chk(self._L.mrsdc_batch_set_scenario(self._h, s, h, alpha, friction_W, period))
+
+    def set_scenario_temperature(self, s, T):
+        T = np.ascontiguousarray(T, np.float64)
+        return self._chk(self._L.mrsdc_batch_set_temperature(self._h, s, _p(T), len(T)))
+
+    def set_scenario_time(self, s, t):
+        return self._chk(self._L.mrsdc_batch_set_time(self._h, s, t))
+
+    def get_scenario_time(self, s):
+        t = C.c_double()
+        self._chk(self._L.mrsdc_batch_get_time(self._h, s, C.byref(t)))
+        return t.value
+
+    def set_active(self, s, active=True):
+        return self._chk(self._L.mrsdc_batch_set_active(self._h, s, 1 if active else 0))
+
+    def advance_steps(self, nsteps):
+        st = Stats()
+        self._chk(self._L.mrsdc_batch_advance(self._h, nsteps, C.byref(st)))
+        return st.as_dict()
+
+    def get_scenario_temperature(self, s, n):
+        out = np.empty(n)
+        self._chk(self._L.mrsdc_batch_get_temperature(self._h, s, _p(out), n))
+        return out
+
+
 def config_from_scheme(scheme, device=0, **over) -> Config:
     """Config from an object with M, family, P, K, dt, pcg_rtol, pcg_maxit, precision..."""
     cfg = default_config(device=device, precision=scheme.precision, M=scheme.M,
@@ -262,7 +313,8 @@ def config_from_scheme(scheme, device=0, **over) -> Config:
     return cfg
 
 
-def load_problem(ctx: Context, pb, h=None, alpha=None, friction_W=None, period=None, T0=None):
+def load_problem(ctx: Context, pb, h=None, alpha=None, friction_W=None, period=None, T0=None,
+                 temperature=True):
     """Pass a problem description (bodies, faces, coupling, motion, T0) to ctx."""
     for i, b in enumerate(pb.bodies):
         ctx.set_body(i, b.rowptr, b.col, b.K, b.R, b.mass, b.rload)
@@ -283,11 +335,25 @@ def load_problem(ctx: Context, pb, h=None, alpha=None, friction_W=None, period=N
         ctx.set_face(c.body, FACE_TAGS[c.face], F.u, F.v, F.ids)
         ctx.set_patch(c.body, FACE_TAGS[c.face], c.width_u, c.width_v, c.u_center, c.q0, c.alpha,
                       c.T_fixed)
+    if not temperature:
+        return
     T = pb.T0 if T0 is None else T0
     off = pb.offsets
     for i in range(len(pb.bodies)):
         ctx.set_temperature(i, T[off[i]:off[i + 1]])
     ctx.set_time(pb.t0)
+
+
+def batch_simulation(pb, members, device=0, **cfg_over) -> BatchContext:
+    """Batch over a shared machine pb; members: list of dicts with h, alpha,
+    friction_W, period, T0 (and optionally t0)."""
+    ctx = BatchContext(config_from_scheme(pb.scheme, device=device, **cfg_over), len(members))
+    load_problem(ctx, pb, temperature=False)
+    for s, mb in enumerate(members):
+        ctx.set_scenario(s, mb["h"], mb["alpha"], mb["friction_W"], mb["period"])
+        ctx.set_scenario_temperature(s, mb["T0"])
+        ctx.set_scenario_time(s, mb.get("t0", 0.0))
+    return ctx
 
 
 def simulation(pb, device=0, **cfg_over) -> Context:

@@ -23,6 +23,7 @@
 #include <string>
 #include <vector>
 
+#include "batch_internal.h"
 #include "mrsdc_internal.h"
 
 using namespace mrsdc;
@@ -91,6 +92,14 @@ struct mrsdc_ctx {
   std::vector<int> ev_class;    // 0 cg spmv, 1 iface
   int ev_used = 0;
   mrsdc_kernel_times times = {};
+  // batched contexts: S > 0 scenarios sharing the operators
+  int S = 0;
+  std::vector<double> sc_h, sc_alpha, sc_Pf, sc_period, sc_t;
+  std::vector<int> sc_active;
+  std::vector<std::vector<double>> sc_T;  // pending host temperatures (empty: none)
+  BatchArgs ba;
+  BatchScalars *bsc_host = nullptr;       // pinned
+  double *stage = nullptr;                // device staging vector [N]
 };
 
 namespace {
@@ -144,7 +153,18 @@ mrsdc_status upload(mrsdc_ctx *c, T **p, const std::vector<T> &h) {
 
 void free_device(mrsdc_ctx *c) {
   // keep the device-resident temperature and time when the operators change
-  if (c->prepared && !c->dirty_T) {
+  if (c->prepared && c->S > 0) {
+    if (c->stream) hipStreamSynchronize(c->stream);
+    const int64_t N = c->ba.N;
+    for (int s = 0; s < c->S; ++s) {
+      if (!c->sc_T[s].empty()) continue;  // a newer host value is pending
+      std::vector<double> col(N);
+      blaunch_gather(c->stage, c->d.T[0], N, c->S, s, c->stream);
+      hipMemcpyAsync(col.data(), c->stage, sizeof(double) * N, hipMemcpyDeviceToHost, c->stream);
+      hipStreamSynchronize(c->stream);
+      c->sc_T[s] = std::move(col);
+    }
+  } else if (c->prepared && !c->dirty_T) {
     if (c->stream) hipStreamSynchronize(c->stream);
     for (int b = 0; b < c->nbody; ++b) {
       if (!c->body[b].set || !c->body[b].hasT) continue;
@@ -222,6 +242,110 @@ mrsdc_status band_coeffs(mrsdc_ctx *c, const std::vector<double> &x, const std::
   return MRSDC_OK;
 }
 
+// Batched contexts: shared operators in row-major form (one row per
+// wavefront), per-scenario parameters, and the argument block of the batch
+// kernels over the scenario-interleaved vectors allocated by prepare().
+mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
+  DevState &d = c->d;
+  const int S = c->S;
+  mrsdc_status st;
+  std::vector<int64_t> rowptr(N + 1, 0);
+  std::vector<int32_t> col;
+  std::vector<double> Kv, Rv, Kd(N, 0.0), Rd(N, 0.0), gbase(N, 0.0);
+  for (int b = 0; b < c->nbody; ++b) {
+    const HostBody &B = c->body[b];
+    for (int64_t i = 0; i < B.n; ++i) {
+      const int64_t row = c->off[b] + i;
+      gbase[row] = B.Tenv * (B.rload.empty() ? 0.0 : B.rload[i]);
+      for (int64_t e = B.rowptr[i]; e < B.rowptr[i + 1]; ++e) {
+        const double kv = B.K[e], rv = B.R.empty() ? 0.0 : B.R[e];
+        col.push_back((int32_t)(c->off[b] + B.col[e]));
+        Kv.push_back(kv);
+        Rv.push_back(rv);
+        if (B.col[e] == i) {
+          Kd[row] += kv;
+          Rd[row] += rv;
+        }
+      }
+      rowptr[row + 1] = (int64_t)col.size();
+    }
+  }
+  BatchArgs &a = c->ba;
+  a = BatchArgs();
+  a.S = S;
+  a.N = N;
+  a.M = c->cfg.M;
+  a.P = c->cfg.P;
+  a.grid = (int)std::min<int64_t>((N + 3) / 4, 1024);
+  for (int m = 0; m <= c->cfg.M; ++m) a.dtau_h[m] = c->w.dtau[m];
+  int64_t *prp;
+  int32_t *pc;
+  double *pv;
+  if ((st = upload(c, &prp, rowptr))) return st;
+  a.op.rowptr = prp;
+  if ((st = upload(c, &pc, col))) return st;
+  a.op.col = pc;
+  if ((st = upload(c, &pv, Kv))) return st;
+  a.op.Kv = pv;
+  if ((st = upload(c, &pv, Rv))) return st;
+  a.op.Rv = pv;
+  a.op.N = N;
+  if ((st = upload(c, &pv, Kd))) return st;
+  a.Kd = pv;
+  if ((st = upload(c, &pv, Rd))) return st;
+  a.Rd = pv;
+  if ((st = upload(c, &pv, gbase))) return st;
+  a.gbase = pv;
+  a.mass = d.mass;
+  // per-scenario parameters (unset ones take the context-wide values)
+  std::vector<double> h(S), al(S), pf(S), per(S), t(S);
+  std::vector<int> act(S);
+  for (int s = 0; s < S; ++s) {
+    h[s] = std::isnan(c->sc_h[s]) ? c->body[0].h : c->sc_h[s];
+    al[s] = std::isnan(c->sc_alpha[s]) ? c->cpl.alpha : c->sc_alpha[s];
+    pf[s] = std::isnan(c->sc_Pf[s]) ? c->cpl.Pf : c->sc_Pf[s];
+    per[s] = std::isnan(c->sc_period[s]) ? c->motion.period : c->sc_period[s];
+    t[s] = c->sc_t[s];
+    act[s] = c->sc_active[s];
+  }
+  if ((st = upload(c, &pv, h))) return st;
+  a.h = pv;
+  if ((st = upload(c, &pv, al))) return st;
+  a.alpha = pv;
+  if ((st = upload(c, &pv, pf))) return st;
+  a.Pf = pv;
+  if ((st = upload(c, &pv, per))) return st;
+  a.period = pv;
+  if ((st = upload(c, &pv, t))) return st;
+  a.tn = pv;
+  if ((st = dalloc(c, &a.sc, 1))) return st;
+  HIPCHK(hipMemset(a.sc, 0, sizeof(BatchScalars)));
+  HIPCHK(hipMemcpy(a.sc->active, act.data(), sizeof(int) * S, hipMemcpyHostToDevice));
+  if ((st = dalloc(c, &a.partial, 3 * (size_t)a.grid * S))) return st;
+  if ((st = dalloc(c, &c->stage, N))) return st;
+  a.w = d.w;
+  a.ifpos = d.ifc.kind ? d.ifpos : nullptr;
+  a.f = d.ifc;
+  a.n_if = d.ifc.n_if;
+  for (int m = 0; m <= c->cfg.M; ++m) {
+    a.T[m] = d.T[m];
+    a.F[m] = d.F[m];
+    a.I[m] = d.I[m];
+  }
+  a.r = d.r;
+  a.p = d.p;
+  a.q = d.q;
+  a.Eold = d.Eold;
+  a.Enew = d.Enew;
+  a.Tbuf[0] = d.Tbuf[0];
+  a.Tbuf[1] = d.Tbuf[1];
+  a.fst = d.fst;
+  a.coefD = d.coefD;
+  a.coefI = d.coefI;
+  if (!c->bsc_host) HIPCHK(hipHostMalloc((void **)&c->bsc_host, sizeof(BatchScalars), 0));
+  return MRSDC_OK;
+}
+
 mrsdc_status prepare(mrsdc_ctx *c) {
   if (c->prepared) return MRSDC_OK;
   if (!c->body[0].set) return fail(c, MRSDC_ESTATE, "body 0 not set");
@@ -230,8 +354,9 @@ mrsdc_status prepare(mrsdc_ctx *c) {
   c->off[1] = c->body[0].n;
   c->off[2] = c->off[1] + (c->nbody == 2 ? c->body[1].n : 0);
   const int64_t N = c->off[c->nbody];
-  for (int b = 0; b < c->nbody; ++b)
-    if (!c->body[b].hasT) return fail(c, MRSDC_ESTATE, "temperature of body %d not set", b);
+  if (c->S == 0)
+    for (int b = 0; b < c->nbody; ++b)
+      if (!c->body[b].hasT) return fail(c, MRSDC_ESTATE, "temperature of body %d not set", b);
   const mrsdc_config &cfg = c->cfg;
   if (!build_weights(cfg.M, cfg.node_family, cfg.P, cfg.dt, &c->w))
     return fail(c, MRSDC_EINVAL, "bad quadrature");
@@ -255,6 +380,12 @@ mrsdc_status prepare(mrsdc_ctx *c) {
   for (int m = 0; m <= cfg.M; ++m) d.dtau_h[m] = c->w.dtau[m];
   d.grid = (int)std::min<int64_t>((N + kBlock - 1) / kBlock, 1024);
   if (d.grid < 1) d.grid = 1;
+  const bool batch = c->S > 0;
+  const int S = batch ? c->S : 1;
+  if (batch && cfg.precision != MRSDC_FP64)
+    return fail(c, MRSDC_EINVAL, "batched contexts run the FP64 path");
+  if (batch && c->cpl.kind == 2)
+    return fail(c, MRSDC_EINVAL, "batched contexts support the contact coupling only");
 
   // ---- operator L = K + h R in SELL-64 ----
   const int64_t nslices = (N + kSlice - 1) / kSlice;
@@ -358,7 +489,7 @@ mrsdc_status prepare(mrsdc_ctx *c) {
   d.Ldiag = dLd;
   const bool fp32 = cfg.precision == MRSDC_FP32_REFINE;
   for (int m = 1; m <= cfg.M; ++m) {
-    if (c->w.dtau[m] == 0.0) continue;
+    if (c->w.dtau[m] == 0.0 || batch) continue;
     std::vector<double> di(N);
     for (int64_t i = 0; i < N; ++i) di[i] = 1.0 / (mass[i] + c->w.dtau[m] * Ldiag[i]);
     if ((st = upload(c, &d.dinv[m], di))) return st;
@@ -388,17 +519,25 @@ mrsdc_status prepare(mrsdc_ctx *c) {
 
   // ---- states ----
   const bool lob = cfg.node_family == MRSDC_LOBATTO;
+  const size_t NS = (size_t)N * S;
   for (int m = 0; m <= cfg.M; ++m) {
     if (lob && m == 1) {
       d.T[1] = d.T[0];
-    } else if ((st = dalloc(c, &d.T[m], N))) {
+    } else if ((st = dalloc(c, &d.T[m], NS))) {
       return st;
     }
-    if (m >= 1 && (st = dalloc(c, &d.F[m], N))) return st;
-    if (m >= 1 && c->w.dtau[m] != 0.0 && (st = dalloc(c, &d.I[m], N))) return st;
+    if (m >= 1 && (st = dalloc(c, &d.F[m], NS))) return st;
+    if (m >= 1 && c->w.dtau[m] != 0.0 && (st = dalloc(c, &d.I[m], NS))) return st;
   }
-  if ((st = dalloc(c, &d.r, N)) || (st = dalloc(c, &d.p, N)) || (st = dalloc(c, &d.q, N)))
+  if ((st = dalloc(c, &d.r, NS)) || (st = dalloc(c, &d.p, NS)) || (st = dalloc(c, &d.q, NS)))
     return st;
+  if (batch) {  // inactive scenarios keep finite zeros
+    for (int m = 0; m <= cfg.M; ++m) {
+      if (!(lob && m == 1)) HIPCHK(hipMemset(d.T[m], 0, NS * sizeof(double)));
+      if (m >= 1) HIPCHK(hipMemset(d.F[m], 0, NS * sizeof(double)));
+      if (d.I[m]) HIPCHK(hipMemset(d.I[m], 0, NS * sizeof(double)));
+    }
+  }
   if ((st = dalloc(c, &d.partial, 3 * (size_t)d.grid))) return st;
   if ((st = dalloc(c, &d.sc, 1)) || (st = dalloc(c, &d.ctr, 1)) || (st = dalloc(c, &d.tn, 1)))
     return st;
@@ -520,20 +659,21 @@ mrsdc_status prepare(mrsdc_ctx *c) {
     }
     if ((st = upload(c, &pi, ifpos))) return st;
     d.ifpos = pi;
-    const size_t ncache = (size_t)(cfg.M + 1) * (cfg.P + 1) * f.n_if;
+    const size_t ncache = (size_t)(cfg.M + 1) * (cfg.P + 1) * f.n_if * S;
     if ((st = dalloc(c, &d.Eold, ncache)) || (st = dalloc(c, &d.Enew, ncache)))
       return st;
     HIPCHK(hipMemset(d.Eold, 0, ncache * sizeof(double)));
     HIPCHK(hipMemset(d.Enew, 0, ncache * sizeof(double)));
-    if ((st = dalloc(c, &d.Tbuf[0], f.n_if)) || (st = dalloc(c, &d.Tbuf[1], f.n_if)) ||
-        (st = dalloc(c, &d.fst, f.n_if)))
+    if ((st = dalloc(c, &d.Tbuf[0], (size_t)f.n_if * S)) ||
+        (st = dalloc(c, &d.Tbuf[1], (size_t)f.n_if * S)) || (st = dalloc(c, &d.fst, (size_t)f.n_if * S)))
       return st;
-    const size_t ntab = (size_t)(cfg.M + 1) * (cfg.P + 1);
+    const size_t ntab = (size_t)(cfg.M + 1) * (cfg.P + 1) * S;
     if ((st = dalloc(c, &d.coefD, ntab * coef_table_doubles(f))) ||
         (st = dalloc(c, &d.coefI, ntab * coef_table_ints(f))))
       return st;
   }
   if (!c->ctr_host) HIPCHK(hipHostMalloc((void **)&c->ctr_host, sizeof(StepCounters), 0));
+  if (batch && (st = prepare_batch(c, N))) return st;
   const int b0 = std::min(cfg.pcg_maxit, 24);
   for (int i = 0; i < kSlots; ++i) {
     c->budget[i] = b0;
@@ -661,6 +801,71 @@ void enqueue_step(mrsdc_ctx *c) {
     std::swap(d.Eold, d.Enew);
   }
   launch_step_end(d, c->cfg.dt, st);
+}
+
+// ---- batched contexts ----
+mrsdc_status batch_upload_pending(mrsdc_ctx *c) {
+  const int64_t N = c->ba.N;
+  for (int s = 0; s < c->S; ++s) {
+    if (c->sc_T[s].empty()) continue;
+    HIPCHK(hipMemcpyAsync(c->stage, c->sc_T[s].data(), sizeof(double) * N, hipMemcpyHostToDevice,
+                          c->stream));
+    blaunch_scatter(c->d.T[0], c->stage, N, c->S, s, c->stream);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->sc_T[s].clear();
+  }
+  return MRSDC_OK;
+}
+
+mrsdc_status batch_upload_params(mrsdc_ctx *c) {
+  if (!c->prepared) return MRSDC_OK;
+  const int S = c->S;
+  std::vector<double> h(S), al(S), pf(S), per(S);
+  std::vector<int> act(S);
+  for (int s = 0; s < S; ++s) {
+    h[s] = std::isnan(c->sc_h[s]) ? c->body[0].h : c->sc_h[s];
+    al[s] = std::isnan(c->sc_alpha[s]) ? c->cpl.alpha : c->sc_alpha[s];
+    pf[s] = std::isnan(c->sc_Pf[s]) ? c->cpl.Pf : c->sc_Pf[s];
+    per[s] = std::isnan(c->sc_period[s]) ? c->motion.period : c->sc_period[s];
+    act[s] = c->sc_active[s];
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy((void *)c->ba.h, h.data(), sizeof(double) * S, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy((void *)c->ba.alpha, al.data(), sizeof(double) * S, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy((void *)c->ba.Pf, pf.data(), sizeof(double) * S, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy((void *)c->ba.period, per.data(), sizeof(double) * S, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->ba.tn, c->sc_t.data(), sizeof(double) * S, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->ba.sc->active, act.data(), sizeof(int) * S, hipMemcpyHostToDevice));
+  return MRSDC_OK;
+}
+
+void enqueue_batch_step(mrsdc_ctx *c) {
+  BatchArgs &a = c->ba;
+  const int M = c->cfg.M, K = c->cfg.K;
+  const bool lob = c->cfg.node_family == MRSDC_LOBATTO;
+  const double rtol = c->cfg.pcg_rtol;
+  hipStream_t st = c->stream;
+  blaunch_clear(a, st);
+  blaunch_iface_coeffs(a, st);
+  for (int m = 1; m <= M; ++m) {
+    if (c->w.dtau[m] == 0.0) continue;
+    blaunch_solve(a, m, true, slot_of(0, m), c->budget[slot_of(0, m)], rtol, st);
+    blaunch_iface(a, m, false, st);
+  }
+  std::swap(a.Eold, a.Enew);
+  const int passes = c->cfg.final_residual ? K + 1 : K;
+  for (int k = 1; k <= passes; ++k) {
+    blaunch_f_multi(a, (lob && k > 1) ? 2 : 1, M, st);
+    blaunch_quad_resid(a, k - 1, st);
+    if (k > K) break;
+    for (int m = 1; m <= M; ++m) {
+      if (c->w.dtau[m] == 0.0) continue;
+      blaunch_solve(a, m, false, slot_of(k, m), c->budget[slot_of(k, m)], rtol, st);
+      blaunch_iface(a, m, true, st);
+    }
+    std::swap(a.Eold, a.Enew);
+  }
+  blaunch_commit(a, c->cfg.dt, st);
 }
 
 }  // namespace
@@ -867,6 +1072,7 @@ mrsdc_status mrsdc_get_time(const mrsdc_ctx *c, double *t) {
 
 mrsdc_status mrsdc_advance(mrsdc_ctx *c, double horizon, mrsdc_stats *stats) {
   if (!c) return MRSDC_EINVAL;
+  if (c->S > 0) return fail(c, MRSDC_ESTATE, "batched context: use mrsdc_batch_advance");
   if (stats) std::memset(stats, 0, sizeof(*stats));
   const double dt = c->cfg.dt;
   if (!(horizon >= 0) || !std::isfinite(horizon)) return fail(c, MRSDC_EINVAL, "bad horizon");
@@ -1037,8 +1243,176 @@ mrsdc_status mrsdc_destroy(mrsdc_ctx *c) {
   free_device(c);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   if (c->ctr_host) hipHostFree(c->ctr_host);
+  if (c->bsc_host) hipHostFree(c->bsc_host);
   for (hipEvent_t e : c->ev) hipEventDestroy(e);
   delete c;
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_batch_create(mrsdc_ctx **out, const mrsdc_config *cfg, int S) {
+  if (!out) return MRSDC_EINVAL;
+  *out = nullptr;
+  if (S < 1 || S > kMaxS) return MRSDC_EINVAL;
+  if (cfg && cfg->precision != MRSDC_FP64) return MRSDC_EINVAL;
+  mrsdc_status st = mrsdc_create(out, cfg);
+  if (st) return st;
+  mrsdc_ctx *c = *out;
+  c->S = S;
+  c->sc_h.assign(S, NAN);
+  c->sc_alpha.assign(S, NAN);
+  c->sc_Pf.assign(S, NAN);
+  c->sc_period.assign(S, NAN);
+  c->sc_t.assign(S, 0.0);
+  c->sc_active.assign(S, 1);
+  c->sc_T.assign(S, std::vector<double>());
+  return MRSDC_OK;
+}
+
+static mrsdc_status need_batch(mrsdc_ctx *c, int s) {
+  if (!c) return MRSDC_EINVAL;
+  if (c->S == 0) return fail(c, MRSDC_ESTATE, "not a batched context");
+  if (s < 0 || s >= c->S) return fail(c, MRSDC_EINVAL, "scenario %d out of range", s);
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_batch_set_scenario(mrsdc_ctx *c, int s, double h, double alpha, double friction_W,
+                                      double period) {
+  mrsdc_status st = need_batch(c, s);
+  if (st) return st;
+  if (!(h >= 0) || !(alpha >= 0) || !(friction_W >= 0) || !(period > 0) || !std::isfinite(h) ||
+      !std::isfinite(alpha) || !std::isfinite(friction_W) || !std::isfinite(period))
+    return fail(c, MRSDC_EINVAL, "bad scenario parameters");
+  c->sc_h[s] = h;
+  c->sc_alpha[s] = alpha;
+  c->sc_Pf[s] = friction_W;
+  c->sc_period[s] = period;
+  return batch_upload_params(c);
+}
+
+mrsdc_status mrsdc_batch_set_temperature(mrsdc_ctx *c, int s, const double *T, int64_t n) {
+  mrsdc_status st = need_batch(c, s);
+  if (st) return st;
+  int64_t N = 0;
+  for (int b = 0; b < 2; ++b) N += c->body[b].set ? c->body[b].n : 0;
+  if (!T || n != N) return fail(c, MRSDC_EINVAL, "temperature length %lld != %lld", (long long)n, (long long)N);
+  if (!finite_all(T, n)) return fail(c, MRSDC_EINVAL, "temperature not finite");
+  c->sc_T[s].assign(T, T + n);
+  if (c->prepared) return batch_upload_pending(c);
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_batch_set_time(mrsdc_ctx *c, int s, double t) {
+  mrsdc_status st = need_batch(c, s);
+  if (st) return st;
+  if (!std::isfinite(t)) return fail(c, MRSDC_EINVAL, "time not finite");
+  c->sc_t[s] = t;
+  return batch_upload_params(c);
+}
+
+mrsdc_status mrsdc_batch_set_active(mrsdc_ctx *c, int s, int active) {
+  mrsdc_status st = need_batch(c, s);
+  if (st) return st;
+  c->sc_active[s] = active ? 1 : 0;
+  return batch_upload_params(c);
+}
+
+mrsdc_status mrsdc_batch_get_time(const mrsdc_ctx *c, int s, double *t) {
+  if (!c || !t || c->S == 0 || s < 0 || s >= c->S) return MRSDC_EINVAL;
+  *t = c->sc_t[s];
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_batch_advance(mrsdc_ctx *c, int nsteps, mrsdc_stats *stats) {
+  mrsdc_status st = need_batch(c, 0);
+  if (st) return st;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (nsteps < 0) return fail(c, MRSDC_EINVAL, "negative step count");
+  for (int s = 0; s < c->S; ++s)
+    if (c->sc_active[s] && !c->prepared && c->sc_T[s].empty())
+      return fail(c, MRSDC_ESTATE, "temperature of scenario %d not set", s);
+  if ((st = prepare(c))) return st;
+  if ((st = batch_upload_pending(c))) return st;
+  auto t0 = std::chrono::steady_clock::now();
+  mrsdc_stats acc;
+  std::memset(&acc, 0, sizeof acc);
+  const int S = c->S, Kc = c->cfg.K;
+  for (int n = 0; n < nsteps; ++n) {
+    for (;;) {
+      enqueue_batch_step(c);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(c->bsc_host, c->ba.sc, sizeof(BatchScalars), hipMemcpyDeviceToHost,
+                            c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      const BatchScalars &h = *c->bsc_host;
+      bool failed = false;
+      for (int s = 0; s < S; ++s) failed |= (c->sc_active[s] && h.fail[s]);
+      if (!failed) {
+        for (int i = 0; i < kSlots; ++i) {
+          int mx = 0;
+          for (int s = 0; s < S; ++s)
+            if (c->sc_active[s]) mx = std::max(mx, h.slot_iters[i][s]);
+          if (mx > 0) {
+            c->budget[i] = std::min(c->cfg.pcg_maxit, mx + std::max(2, mx / 5));
+            c->expect[i] = mx;
+          }
+          for (int s = 0; s < S; ++s)
+            if (c->sc_active[s] && h.slot_iters[i][s] > 0) {
+              acc.pcg_iters += h.slot_iters[i][s];
+              acc.max_iters = std::max(acc.max_iters, h.slot_iters[i][s]);
+            }
+        }
+        for (int k = 0; k <= Kc; ++k) {
+          double r = 0.0;
+          for (int s = 0; s < S; ++s)
+            if (c->sc_active[s]) r = std::max(r, h.resid[k][s]);
+          acc.residual[k] = r;
+        }
+        break;
+      }
+      bool grow = false;
+      for (int i = 0; i < kSlots; ++i) {
+        bool slot_failed = false;
+        for (int s = 0; s < S; ++s) slot_failed |= (c->sc_active[s] && h.slot_iters[i][s] < 0);
+        if (slot_failed && c->budget[i] < c->cfg.pcg_maxit) {
+          c->budget[i] = std::min(c->cfg.pcg_maxit, 2 * c->budget[i]);
+          grow = true;
+        }
+      }
+      acc.redone_steps++;
+      if (!grow) {
+        acc.steps = n;
+        acc.wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (stats) *stats = acc;
+        return fail(c, MRSDC_ENOCONV, "implicit solve did not converge in %d iterations (step %d)",
+                    c->cfg.pcg_maxit, n);
+      }
+    }
+    for (int s = 0; s < S; ++s)
+      if (c->sc_active[s]) c->sc_t[s] += c->cfg.dt;
+  }
+  int nint = 0, nact = 0;
+  for (int m = 1; m <= c->cfg.M; ++m) nint += c->w.dtau[m] != 0.0;
+  for (int s = 0; s < S; ++s) nact += c->sc_active[s];
+  acc.steps = nsteps;
+  acc.solves = (int64_t)nsteps * nint * (Kc + 1) * nact;
+  acc.wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = acc;
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_batch_get_temperature(mrsdc_ctx *c, int s, double *out, int64_t n) {
+  mrsdc_status st = need_batch(c, s);
+  if (st) return st;
+  if (!out) return fail(c, MRSDC_EINVAL, "null output");
+  if (!c->prepared || !c->sc_T[s].empty()) {
+    if ((int64_t)c->sc_T[s].size() != n) return fail(c, MRSDC_EINVAL, "length mismatch or no state");
+    std::memcpy(out, c->sc_T[s].data(), sizeof(double) * n);
+    return MRSDC_OK;
+  }
+  if (n != c->ba.N) return fail(c, MRSDC_EINVAL, "length mismatch");
+  blaunch_gather(c->stage, c->d.T[0], n, c->S, s, c->stream);
+  HIPCHK(hipMemcpyAsync(out, c->stage, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   return MRSDC_OK;
 }
 

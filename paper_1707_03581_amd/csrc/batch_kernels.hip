@@ -1,0 +1,580 @@
+// Batched MRSDC sweep: S scenarios (S <= 64) of one machine advanced together.
+//
+// The scenarios share the mesh operators K and R (per-scenario Robin h_s,
+// contact alpha_s, friction power P_s and motion period), so the operator is
+// applied as a multi-right-hand-side product.  Layout: every state vector is
+// scenario-interleaved, X[row * S + s]; a wavefront handles one row for all
+// scenarios (lane = scenario), so the row's matrix entries are wave-uniform
+// (scalar loads, read once for S right-hand sides) and every vector access is
+// one contiguous line.  Each scenario keeps its own CG scalars and
+// convergence flag; arithmetic per scenario does not depend on the others, so
+// a scenario's result is the same alone and inside any batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "batch_internal.h"
+
+namespace mrsdc {
+
+__device__ inline double bwave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline int wave_row0() {
+  return __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)));
+}
+
+// sum the per-wave (per-lane = per-scenario) values of the block into
+// partial[k][blk][s]
+template <int K>
+__device__ inline void bpublish(double (&v)[K], double *partial, int grid, int S) {
+  __shared__ double sh[kBlock / 64][K][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int k = 0; k < K; ++k) sh[w][k][lane] = v[k];
+  __syncthreads();
+  if (w == 0 && lane < S) {
+    for (int k = 0; k < K; ++k) {
+      double acc = 0.0;
+      for (int ww = 0; ww < kBlock / 64; ++ww) acc += sh[ww][k][lane];
+      partial[((size_t)k * grid + blockIdx.x) * S + lane] = acc;
+    }
+  }
+}
+
+// multi-RHS row product: K x_s + h_s R x_s for lane s (row entries uniform)
+__device__ inline double brow(const BatchOp &op, int64_t row, int S, int s, double h,
+                              const double *__restrict__ x) {
+  const int64_t e0 = op.rowptr[row], e1 = op.rowptr[row + 1];
+  double k = 0.0, r = 0.0;
+  for (int64_t e = e0; e < e1; ++e) {
+    const double xv = x[(int64_t)op.col[e] * S + s];
+    k += op.Kv[e] * xv;
+    r += op.Rv[e] * xv;
+  }
+  return k + h * r;
+}
+
+// FP32 operator: FP32 values, FP32 products and sums
+__device__ inline float brow32(const BatchOp &op, int64_t row, int S, int s, float h,
+                               const float *__restrict__ x) {
+  const int64_t e0 = op.rowptr[row], e1 = op.rowptr[row + 1];
+  float k = 0.0f, r = 0.0f;
+  for (int64_t e = e0; e < e1; ++e) {
+    const float xv = x[(int64_t)op.col[e] * S + s];
+    k += op.Kv32[e] * xv;
+    r += op.Rv32[e] * xv;
+  }
+  return k + h * r;
+}
+
+__device__ inline bool lane_on(const BatchScalars *sc, int s, int S) {
+  return s < S && sc->active[s] && !sc->done[s];
+}
+
+// ---------------------------------------------------------------------------
+// F_j = g - L_s T_j (several standard nodes j), all scenarios
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void kb_f_multi(BatchArgs a, int j0, int j1) {
+  const int s = threadIdx.x & 63, S = a.S;
+  if (s >= S) return;
+  const double h = a.h[s];
+  for (int64_t row = wave_row0(); row < a.N; row += (int64_t)gridDim.x * (kBlock / 64)) {
+    const double g = h * a.gbase[row];
+    for (int j = j0; j <= j1; ++j) {
+      const double L = brow(a.op, row, S, s, h, a.T[j]);
+      a.F[j][row * S + s] = g - L;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// I_{m-1}^m for all m and the residual per scenario (max-norm)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void kb_quad_resid(BatchArgs a) {
+  const int s = threadIdx.x & 63, S = a.S;
+  const Weights &w = *a.w;
+  const int P1 = a.P + 1;
+  double rmax = 0.0;
+  if (s < S) {
+    for (int64_t row = wave_row0(); row < a.N; row += (int64_t)gridDim.x * (kBlock / 64)) {
+      const int64_t i = row * S + s;
+      const double mi = a.mass[row], Tn = a.T[0][i];
+      const int pos = a.ifpos ? a.ifpos[row] : -1;
+      double cum = 0.0;
+      for (int m = 1; m <= a.M; ++m) {
+        if (w.dtau[m] == 0.0) continue;
+        double acc = 0.0;
+        for (int j = 1; j <= a.M; ++j) acc += w.s[m][j] * a.F[j][i];
+        if (pos >= 0) {
+          const double *E = a.Eold + ((size_t)m * P1 * a.n_if + pos) * S + s;
+          for (int q = 1; q <= a.P; ++q) acc += w.shat[m][q] * E[(size_t)q * a.n_if * S];
+        }
+        a.I[m][i] = acc;
+        cum += acc;
+        rmax = fmax(rmax, fabs(mi * a.T[m][i] - mi * Tn - cum));
+      }
+    }
+  }
+  double v[1] = {rmax};
+  // per-scenario maxima of the block
+  __shared__ double sh[kBlock / 64][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  sh[wv][lane] = v[0];
+  __syncthreads();
+  if (wv == 0 && lane < S) {
+    double mx = 0.0;
+    for (int k = 0; k < kBlock / 64; ++k) mx = fmax(mx, sh[k][lane]);
+    a.partial[(size_t)blockIdx.x * S + lane] = mx;
+  }
+}
+
+constexpr int kRedWaves = 16;  // waves of the one-block reductions
+
+__global__ __launch_bounds__(64 * kRedWaves) void kb_resid_reduce(BatchArgs a, int k) {
+  __shared__ double sh[kRedWaves][64];
+  const int s = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double mx = 0.0;
+  if (s < a.S)
+    for (int b = w; b < a.grid; b += kRedWaves) mx = fmax(mx, a.partial[(size_t)b * a.S + s]);
+  sh[w][s] = mx;
+  __syncthreads();
+  if (w == 0 && s < a.S) {
+    for (int ww = 1; ww < kRedWaves; ++ww) mx = fmax(mx, sh[ww][s]);
+    a.sc->resid[k][s] = mx;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// implicit node solve per scenario: Jacobi-PCG, 3 kernels per iteration plus
+// one-block scalar reductions
+// ---------------------------------------------------------------------------
+__device__ inline double bdinv(const BatchArgs &a, int64_t row, double h, double dtau) {
+  return 1.0 / (a.mass[row] + dtau * (a.Kd[row] + h * a.Rd[row]));
+}
+
+template <bool PRED>
+__global__ __launch_bounds__(kBlock) void kb_init(BatchArgs a, int m, double dtau) {
+  const int s = threadIdx.x & 63, S = a.S;
+  double v[3] = {0.0, 0.0, 0.0};
+  const bool on = s < S && a.sc->active[s];
+  if (on) {
+    const double h = a.h[s];
+    double *x = a.T[m];
+    const double *Tp = a.T[m - 1];
+    for (int64_t row = wave_row0(); row < a.N; row += (int64_t)gridDim.x * (kBlock / 64)) {
+      const int64_t i = row * S + s;
+      const double mi = a.mass[row], tp = Tp[i], g = h * a.gbase[row];
+      double b, r;
+      if (PRED) {
+        const double Lx = brow(a.op, row, S, s, h, Tp);
+        b = mi * tp + dtau * g;
+        r = b - (mi * tp + dtau * Lx);
+        x[i] = tp;
+      } else {
+        const double Im = a.I[m][i];
+        b = mi * tp + dtau * (g - a.F[m][i]) + Im;
+        r = mi * (tp - x[i]) + Im;
+      }
+      const double z = bdinv(a, row, h, dtau) * r;
+      a.r[i] = r;
+      a.p[i] = z;
+      v[0] += r * z;
+      v[1] += r * r;
+      v[2] += b * b;
+    }
+  }
+  bpublish<3>(v, a.partial, a.grid, S);
+}
+
+// mode 0: init (r.z, r.r, b.b); 1: alpha (p.q); 2: convergence (r.z, r.r).
+// Fixed-order sums: wave w adds blocks w, w+16, ..., then wave 0 adds the waves.
+__global__ __launch_bounds__(64 * kRedWaves) void kb_reduce(BatchArgs a, int mode, int it,
+                                                            int last, int slot, double rtol) {
+  __shared__ double sh[3][kRedWaves][64];
+  const int s = threadIdx.x & 63, w = threadIdx.x >> 6;
+  BatchScalars *sc = a.sc;
+  const int nk = mode == 0 ? 3 : (mode == 1 ? 1 : 2);
+  for (int k = 0; k < nk; ++k) {
+    double acc = 0.0;
+    if (s < a.S)
+      for (int b = w; b < a.grid; b += kRedWaves)
+        acc += a.partial[((size_t)k * a.grid + b) * a.S + s];
+    sh[k][w][s] = acc;
+  }
+  __syncthreads();
+  if (w != 0 || s >= a.S) return;
+  double o[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < nk; ++k)
+    for (int ww = 0; ww < kRedWaves; ++ww) o[k] += sh[k][ww][s];
+  if (!sc->active[s]) return;
+  if (mode == 0) {
+    sc->rz[0][s] = o[0];
+    sc->tol2[s] = rtol * rtol * o[2];
+    sc->done[s] = (o[1] <= sc->tol2[s]) ? 1 : 0;
+    if (sc->done[s]) sc->slot_iters[slot][s] = 0;
+    return;
+  }
+  if (sc->done[s]) return;
+  if (mode == 1) {
+    sc->alpha[s] = sc->rz[it & 1][s] / o[0];
+    return;
+  }
+  if (o[1] <= sc->tol2[s]) {
+    sc->done[s] = 1;
+    sc->slot_iters[slot][s] = it + 1;
+    sc->iters_total[s] += it + 1;
+    return;
+  }
+  sc->beta[s] = o[0] / sc->rz[it & 1][s];
+  sc->rz[(it + 1) & 1][s] = o[0];
+  if (last) {
+    sc->slot_iters[slot][s] = -1;
+    sc->fail[s] = 1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void kb_pcg_a(BatchArgs a, int m, double dtau) {
+  const int s = threadIdx.x & 63, S = a.S;
+  double v[1] = {0.0};
+  if (lane_on(a.sc, s, S)) {
+    const double h = a.h[s];
+    for (int64_t row = wave_row0(); row < a.N; row += (int64_t)gridDim.x * (kBlock / 64)) {
+      const int64_t i = row * S + s;
+      const double Lp = brow(a.op, row, S, s, h, a.p);
+      const double pi = a.p[i];
+      const double qi = a.mass[row] * pi + dtau * Lp;
+      a.q[i] = qi;
+      v[0] += pi * qi;
+    }
+  }
+  bpublish<1>(v, a.partial, a.grid, S);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_pcg_b(BatchArgs a, int m, double dtau) {
+  const int s = threadIdx.x & 63, S = a.S;
+  double v[2] = {0.0, 0.0};
+  if (lane_on(a.sc, s, S)) {
+    const double h = a.h[s], alpha = a.sc->alpha[s];
+    double *x = a.T[m];
+    for (int64_t row = wave_row0(); row < a.N; row += (int64_t)gridDim.x * (kBlock / 64)) {
+      const int64_t i = row * S + s;
+      x[i] += alpha * a.p[i];
+      const double r = a.r[i] - alpha * a.q[i];
+      a.r[i] = r;
+      v[0] += r * (bdinv(a, row, h, dtau) * r);
+      v[1] += r * r;
+    }
+  }
+  bpublish<2>(v, a.partial, a.grid, S);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_pcg_c(BatchArgs a, double dtau) {
+  const int s = threadIdx.x & 63, S = a.S;
+  if (!lane_on(a.sc, s, S)) return;
+  const double h = a.h[s], beta = a.sc->beta[s];
+  for (int64_t row = wave_row0(); row < a.N; row += (int64_t)gridDim.x * (kBlock / 64)) {
+    const int64_t i = row * S + s;
+    a.p[i] = bdinv(a, row, h, dtau) * a.r[i] + beta * a.p[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// interface substeps, per scenario (tables with the scenario index fastest)
+// ---------------------------------------------------------------------------
+__device__ inline void hat3(const double *x, int n, int a, double sft, double *l, double *m,
+                            double *h) {
+  *l = x[a > 0 ? a - 1 : a] + sft;
+  *m = x[a] + sft;
+  *h = x[a < n - 1 ? a + 1 : a] + sft;
+}
+
+__device__ inline int bfirst_hat_after(const double *y, int n, double sy, double t) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const double end = y[mid < n - 1 ? mid + 1 : mid] + sy;
+    if (end > t) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+// one block per (time point, scenario)
+__global__ __launch_bounds__(kBlock) void kb_iface_coeffs(BatchArgs a) {
+  const IfaceDev &f = a.f;
+  const int S = a.S, P1 = a.P + 1;
+  const int tp = blockIdx.x / S, s = blockIdx.x - tp * S;
+  const int m = tp / P1, q = tp - m * P1;
+  const Weights &w = *a.w;
+  if (m == 0 || w.dtau[m] == 0.0 || !a.sc->active[s]) return;
+  const CoefLayout L{f.nvf, f.nvm};
+  double *D = a.coefD + (size_t)tp * L.dstride() * S;
+  int *I = a.coefI + (size_t)tp * L.istride() * S;
+  const double t = a.tn[s] + w.tau[m - 1] + q * (w.dtau[m] / a.P);
+  const double sv = f.s0 + f.a * sin(2.0 * M_PI * t / a.period[s] + f.phase);
+  const double ov0 = fmax(f.vf[0], f.vm[0] + sv), ov1 = fmin(f.vf[f.nvf - 1], f.vm[f.nvm - 1] + sv);
+  const bool valid = (f.ou1 > f.ou0) && (ov1 > ov0);
+  if (threadIdx.x == 0)
+    D[0 * S + s] = valid ? a.Pf[s] / ((f.ou1 - f.ou0) * (ov1 - ov0)) : 0.0;
+  for (int b = threadIdx.x; b < f.nvf; b += blockDim.x) {
+    for (int i = 0; i < 3; ++i) {
+      const int bb = b - 1 + i;
+      D[(size_t)(L.Mv() + 3 * b + i) * S + s] =
+          (bb >= 0 && bb < f.nvf && valid)
+              ? hat_product_integral(f.vf, f.nvf, b, f.vf, f.nvf, bb, 0.0, ov0, ov1)
+              : 0.0;
+    }
+    D[(size_t)(L.Hv() + b) * S + s] = valid ? hat_integral(f.vf, f.nvf, b, ov0, ov1) : 0.0;
+    const int d0 = bfirst_hat_after(f.vm, f.nvm, sv, f.vf[b > 0 ? b - 1 : b]);
+    int cnt = 0;
+    for (int i = 0; i < kBand; ++i) {
+      const int d = d0 + i;
+      const double v = (d < f.nvm && valid)
+                           ? hat_product_integral(f.vf, f.nvf, b, f.vm, f.nvm, d, sv, ov0, ov1)
+                           : 0.0;
+      D[(size_t)(L.Cv() + kBand * b + i) * S + s] = v;
+      if (v != 0.0) cnt = i + 1;
+    }
+    I[(size_t)(L.dlo() + b) * S + s] = d0;
+    I[(size_t)(L.dcnt() + b) * S + s] = cnt;
+  }
+  for (int d = threadIdx.x; d < f.nvm; d += blockDim.x) {
+    for (int i = 0; i < 3; ++i) {
+      const int dd = d - 1 + i;
+      D[(size_t)(L.Nv() + 3 * d + i) * S + s] =
+          (dd >= 0 && dd < f.nvm && valid)
+              ? hat_product_integral(f.vm, f.nvm, d, f.vm, f.nvm, dd, 0.0, ov0 - sv, ov1 - sv)
+              : 0.0;
+    }
+    D[(size_t)(L.Gv() + d) * S + s] = valid ? hat_integral(f.vm, f.nvm, d, ov0 - sv, ov1 - sv) : 0.0;
+    const int b0 = bfirst_hat_after(f.vf, f.nvf, 0.0, f.vm[d > 0 ? d - 1 : d] + sv);
+    int cnt = 0;
+    for (int i = 0; i < kBand; ++i) {
+      const int b = b0 + i;
+      const double v = (b < f.nvf && valid)
+                           ? hat_product_integral(f.vf, f.nvf, b, f.vm, f.nvm, d, sv, ov0, ov1)
+                           : 0.0;
+      D[(size_t)(L.CvT() + kBand * d + i) * S + s] = v;
+      if (v != 0.0) cnt = i + 1;
+    }
+    I[(size_t)(L.blo() + d) * S + s] = b0;
+    I[(size_t)(L.bcnt() + d) * S + s] = cnt;
+  }
+}
+
+template <bool FIRST>
+__device__ inline double btif(const BatchArgs &a, const double *Tprev, const double *Tin, int j,
+                              int s) {
+  return FIRST ? Tprev[a.f.rows[j] * a.S + s] : Tin[(size_t)j * a.S + s];
+}
+
+template <bool FIRST>
+__device__ double bfE(const BatchArgs &a, const double *D, const int *I, const double *Tprev,
+                      const double *Tin, int i, int s) {
+  const IfaceDev &f = a.f;
+  const int S = a.S;
+  const CoefLayout L{f.nvf, f.nvm};
+  const double alpha = a.alpha[s], qf = D[s];
+#define DD(k) D[(size_t)(k) * S + s]
+#define II(k) I[(size_t)(k) * S + s]
+  if (i < f.nfix) {
+    const int ua = i / f.nvf, b = i - ua * f.nvf;
+    double self = 0.0;
+    for (int ia = 0; ia < 3; ++ia) {
+      const int aa = ua - 1 + ia;
+      const double mu = f.Mu[3 * ua + ia];
+      if (aa < 0 || aa >= f.nuf || mu == 0.0) continue;
+      double acc = 0.0;
+      for (int ib = 0; ib < 3; ++ib) {
+        const int bb = b - 1 + ib;
+        if (bb < 0 || bb >= f.nvf) continue;
+        acc += DD(L.Mv() + 3 * b + ib) * btif<FIRST>(a, Tprev, Tin, aa * f.nvf + bb, s);
+      }
+      self += mu * acc;
+    }
+    double cross = 0.0;
+    const int c0 = f.clo[ua], nc = f.ccnt[ua];
+    const int d0 = II(L.dlo() + b), nd = II(L.dcnt() + b);
+    for (int ic = 0; ic < nc; ++ic) {
+      const int c = c0 + ic;
+      double acc = 0.0;
+      for (int id = 0; id < nd; ++id)
+        acc += DD(L.Cv() + kBand * b + id) *
+               btif<FIRST>(a, Tprev, Tin, f.nfix + c * f.nvm + d0 + id, s);
+      cross += f.Cu[kBand * ua + ic] * acc;
+    }
+    return alpha * (cross - self) + f.split * qf * f.Hu[ua] * DD(L.Hv() + b);
+  }
+  const int k = i - f.nfix;
+  const int c = k / f.nvm, d = k - c * f.nvm;
+  double self = 0.0;
+  for (int ic = 0; ic < 3; ++ic) {
+    const int cc = c - 1 + ic;
+    const double nu = f.Nu[3 * c + ic];
+    if (cc < 0 || cc >= f.num || nu == 0.0) continue;
+    double acc = 0.0;
+    for (int id = 0; id < 3; ++id) {
+      const int dd = d - 1 + id;
+      if (dd < 0 || dd >= f.nvm) continue;
+      acc += DD(L.Nv() + 3 * d + id) * btif<FIRST>(a, Tprev, Tin, f.nfix + cc * f.nvm + dd, s);
+    }
+    self += nu * acc;
+  }
+  double cross = 0.0;
+  const int a0 = f.alo[c], na = f.acnt[c];
+  const int b0 = II(L.blo() + d), nb = II(L.bcnt() + d);
+  for (int ia = 0; ia < na; ++ia) {
+    const int ua = a0 + ia;
+    double acc = 0.0;
+    for (int ib = 0; ib < nb; ++ib)
+      acc += DD(L.CvT() + kBand * d + ib) * btif<FIRST>(a, Tprev, Tin, ua * f.nvf + b0 + ib, s);
+    cross += f.CuT[kBand * c + ia] * acc;
+  }
+  return alpha * (cross - self) + (1.0 - f.split) * qf * f.Gu[c] * DD(L.Gv() + d);
+#undef DD
+#undef II
+}
+
+// one wave per interface point, lane = scenario
+template <bool FIRST>
+__global__ __launch_bounds__(kBlock) void kb_iface_sub(BatchArgs a, int m, int p, int corr) {
+  const int s = threadIdx.x & 63, S = a.S;
+  const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const IfaceDev &f = a.f;
+  const int n = f.n_if;
+  if (i >= n || s >= S || !a.sc->active[s]) return;
+  const Weights &w = *a.w;
+  const int P = a.P, P1 = P + 1;
+  const CoefLayout L{f.nvf, f.nvm};
+  const int tp = m * P1 + (p - 1);
+  const double *D = a.coefD + (size_t)tp * L.dstride() * S;
+  const int *I = a.coefI + (size_t)tp * L.istride() * S;
+  const double *Tprev = a.T[m - 1];
+  double *Tm = a.T[m];
+  const double *Tin = a.Tbuf[(p - 1) & 1];
+  const double E = bfE<FIRST>(a, D, I, Tprev, Tin, i, s);
+  double *En = a.Enew + (size_t)m * P1 * n * S;
+  En[((size_t)(p - 1) * n + i) * S + s] = E;
+  const double Ti = btif<FIRST>(a, Tprev, Tin, i, s);
+  const int64_t row = f.rows[i];
+  const int64_t gi = row * S + s;
+  if (p == P + 1) {
+    Tm[gi] = Ti;
+    return;
+  }
+  const double mi = a.mass[row], dtm = w.dtau[m], dtp = dtm / P;
+  double fs;
+  if (FIRST) {
+    fs = (mi * Tm[gi] - mi * Ti - (corr ? a.I[m][gi] : 0.0)) / dtm;
+    a.fst[(size_t)i * S + s] = fs;
+  } else {
+    fs = a.fst[(size_t)i * S + s];
+  }
+  double inc;
+  if (corr) {
+    const double *Eo = a.Eold + (size_t)m * P1 * n * S;
+    double Ip = 0.0;
+    for (int j = 1; j <= a.M; ++j) Ip += w.stil[m][p][j] * a.F[j][gi];
+    for (int q = 1; q <= P; ++q) Ip += w.spq[m][p][q] * Eo[((size_t)q * n + i) * S + s];
+    inc = dtp * (fs + E - Eo[((size_t)(p - 1) * n + i) * S + s]) + Ip;
+  } else {
+    inc = dtp * (fs + E);
+  }
+  a.Tbuf[p & 1][(size_t)i * S + s] = Ti + inc / mi;
+}
+
+// ---------------------------------------------------------------------------
+// step bookkeeping
+// ---------------------------------------------------------------------------
+__global__ void kb_clear(BatchArgs a) {
+  BatchScalars *sc = a.sc;
+  const int s = threadIdx.x;
+  if (s >= a.S) return;
+  sc->fail[s] = 0;
+  for (int k = 0; k < 17; ++k) sc->resid[k][s] = 0.0;
+  for (int i = 0; i < kSlots; ++i) sc->slot_iters[i][s] = 0;
+}
+
+// commit T_n <- T_M and t_n += dt for the active scenarios, unless any failed
+__global__ void kb_commit(BatchArgs a, double dt) {
+  for (int s = 0; s < a.S; ++s)
+    if (a.sc->fail[s]) return;
+  const int64_t n = a.N * a.S;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int s = (int)(i % a.S);
+    if (a.sc->active[s]) a.T[0][i] = a.T[a.M][i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x < a.S && a.sc->active[threadIdx.x]) a.tn[threadIdx.x] += dt;
+}
+
+// column s of an interleaved vector <-> contiguous vector
+__global__ void kb_scatter(double *dst, const double *src, int64_t n, int S, int s) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i * S + s] = src[i];
+}
+__global__ void kb_gather(double *dst, const double *src, int64_t n, int S, int s) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i * S + s];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void blaunch_clear(const BatchArgs &a, hipStream_t st) { kb_clear<<<1, 64, 0, st>>>(a); }
+
+void blaunch_iface_coeffs(const BatchArgs &a, hipStream_t st) {
+  if (!a.f.kind) return;
+  kb_iface_coeffs<<<(a.M + 1) * (a.P + 1) * a.S, kBlock, 0, st>>>(a);
+}
+
+void blaunch_f_multi(const BatchArgs &a, int j0, int j1, hipStream_t st) {
+  kb_f_multi<<<a.grid, kBlock, 0, st>>>(a, j0, j1);
+}
+
+void blaunch_quad_resid(const BatchArgs &a, int k, hipStream_t st) {
+  kb_quad_resid<<<a.grid, kBlock, 0, st>>>(a);
+  kb_resid_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, k);
+}
+
+void blaunch_solve(const BatchArgs &a, int m, bool pred, int slot, int budget, double rtol,
+                   hipStream_t st) {
+  const double dtau = a.dtau_h[m];
+  if (pred) kb_init<true><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
+  else kb_init<false><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
+  kb_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, 0, 0, 0, slot, rtol);
+  for (int it = 0; it < budget; ++it) {
+    kb_pcg_a<<<a.grid, kBlock, 0, st>>>(a, m, dtau);
+    kb_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, 1, it, 0, slot, rtol);
+    kb_pcg_b<<<a.grid, kBlock, 0, st>>>(a, m, dtau);
+    kb_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, 2, it, it == budget - 1, slot, rtol);
+    kb_pcg_c<<<a.grid, kBlock, 0, st>>>(a, dtau);
+  }
+}
+
+void blaunch_iface(const BatchArgs &a, int m, bool corr, hipStream_t st) {
+  if (!a.f.kind) return;
+  const int grid = (a.f.n_if + kBlock / 64 - 1) / (kBlock / 64);
+  for (int p = 1; p <= a.P + 1; ++p) {
+    if (p == 1) kb_iface_sub<true><<<grid, kBlock, 0, st>>>(a, m, p, corr ? 1 : 0);
+    else kb_iface_sub<false><<<grid, kBlock, 0, st>>>(a, m, p, corr ? 1 : 0);
+  }
+}
+
+void blaunch_commit(const BatchArgs &a, double dt, hipStream_t st) {
+  int grid = (int)std::min<int64_t>((a.N * a.S + kBlock - 1) / kBlock, 4096);
+  kb_commit<<<grid, kBlock, 0, st>>>(a, dt);
+}
+
+void blaunch_scatter(double *dst, const double *src, int64_t n, int S, int s, hipStream_t st) {
+  kb_scatter<<<1024, kBlock, 0, st>>>(dst, src, n, S, s);
+}
+void blaunch_gather(double *dst, const double *src, int64_t n, int S, int s, hipStream_t st) {
+  kb_gather<<<1024, kBlock, 0, st>>>(dst, src, n, S, s);
+}
+
+}  // namespace mrsdc

@@ -711,64 +711,6 @@ void launch_refine_update(const DevState &d, int m, int slot, int round, bool la
 // 1D face integrals of products of hat functions (separable form of the
 // rectangle integrals of §2, eqs. femContFix/femContMov and defCB)
 // ---------------------------------------------------------------------------
-__host__ __device__ inline void hat_nodes(const double *x, int n, int a, double s, double *l,
-                                          double *m, double *h) {
-  *l = x[a > 0 ? a - 1 : a] + s;
-  *m = x[a] + s;
-  *h = x[a < n - 1 ? a + 1 : a] + s;
-}
-
-__host__ __device__ inline double hat_eval(double l, double m, double h, double t) {
-  if (t < l || t > h) return 0.0;
-  if (t <= m) return m > l ? (t - l) / (m - l) : 1.0;
-  return h > m ? (h - t) / (h - m) : 1.0;
-}
-
-__host__ __device__ double hat_integral(const double *x, int n, int a, double lo, double hi) {
-  double l, m, h;
-  hat_nodes(x, n, a, 0.0, &l, &m, &h);
-  double acc = 0.0;
-  // rising and falling pieces, each linear: trapezoid rule is exact
-  double e0 = fmax(l, lo), e1 = fmin(m, hi);
-  if (e1 > e0) acc += 0.5 * (e1 - e0) * (hat_eval(l, m, h, e0) + hat_eval(l, m, h, e1));
-  e0 = fmax(m, lo);
-  e1 = fmin(h, hi);
-  if (e1 > e0) acc += 0.5 * (e1 - e0) * (hat_eval(l, m, h, e0) + hat_eval(l, m, h, e1));
-  return acc;
-}
-
-__host__ __device__ double hat_product_integral(const double *x, int nx, int a, const double *y,
-                                                int ny, int c, double sy, double lo,
-                                                double hi) {
-  double xl, xm, xh, yl, ym, yh;
-  hat_nodes(x, nx, a, 0.0, &xl, &xm, &xh);
-  hat_nodes(y, ny, c, sy, &yl, &ym, &yh);
-  const double L = fmax(fmax(xl, yl), lo), H = fmin(fmin(xh, yh), hi);
-  if (!(H > L)) return 0.0;
-  double b1 = xm, b2 = ym;
-  if (b1 > b2) {
-    double t = b1;
-    b1 = b2;
-    b2 = t;
-  }
-  double pts[4];
-  int n = 0;
-  pts[n++] = L;
-  if (b1 > L && b1 < H) pts[n++] = b1;
-  if (b2 > L && b2 < H && b2 > pts[n - 1]) pts[n++] = b2;
-  pts[n++] = H;
-  double acc = 0.0;
-  // product of two linear functions on each piece: Simpson's rule is exact
-  for (int k = 0; k + 1 < n; ++k) {
-    const double l = pts[k], r = pts[k + 1], c2 = 0.5 * (l + r);
-    const double fl = hat_eval(xl, xm, xh, l) * hat_eval(yl, ym, yh, l);
-    const double fc = hat_eval(xl, xm, xh, c2) * hat_eval(yl, ym, yh, c2);
-    const double fr = hat_eval(xl, xm, xh, r) * hat_eval(yl, ym, yh, r);
-    acc += (r - l) / 6.0 * (fl + 4.0 * fc + fr);
-  }
-  return acc;
-}
-
 // first node c of grid y (shifted by sy) whose hat support ends after t
 __device__ inline int first_hat_after(const double *y, int n, double sy, double t) {
   int lo = 0, hi = n;  // invariant: answer in [lo, hi]
@@ -791,22 +733,6 @@ __device__ inline int first_hat_after(const double *y, int n, double sy, double 
 // tabulated once per step for all (m, q).  Each substep is then one wide
 // launch over the interface points with double-buffered interface state.
 // ---------------------------------------------------------------------------
-struct CoefLayout {
-  int nvf, nvm;
-  __host__ __device__ int dstride() const { return 1 + (4 + kBand) * (nvf + nvm); }
-  __host__ __device__ int istride() const { return 2 * (nvf + nvm); }
-  __host__ __device__ int Mv() const { return 1; }
-  __host__ __device__ int Hv() const { return 1 + 3 * nvf; }
-  __host__ __device__ int Cv() const { return 1 + 4 * nvf; }
-  __host__ __device__ int Nv() const { return 1 + (4 + kBand) * nvf; }
-  __host__ __device__ int Gv() const { return Nv() + 3 * nvm; }
-  __host__ __device__ int CvT() const { return Gv() + nvm; }
-  __host__ __device__ int dlo() const { return 0; }
-  __host__ __device__ int dcnt() const { return nvf; }
-  __host__ __device__ int blo() const { return 2 * nvf; }
-  __host__ __device__ int bcnt() const { return 2 * nvf + nvm; }
-};
-
 size_t coef_table_doubles(const IfaceDev &f) { return (size_t)CoefLayout{f.nvf, f.nvm}.dstride(); }
 size_t coef_table_ints(const IfaceDev &f) { return (size_t)CoefLayout{f.nvf, f.nvm}.istride(); }
 

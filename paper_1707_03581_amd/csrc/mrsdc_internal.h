@@ -6,6 +6,7 @@
 #include <cstdint>
 
 #include "../../include/mrsdc.h"
+#include "face_integrals.h"
 
 namespace mrsdc {
 
@@ -94,6 +95,26 @@ struct IfaceDev {
   double s0 = 0, a = 0, period = 1, phase = 0;
 };
 
+// Layout of one table of time-dependent (v-direction) face integrals:
+// doubles [friction density | Mv 3*nvf | Hv nvf | Cv kBand*nvf | Nv 3*nvm |
+// Gv nvm | CvT kBand*nvm], ints [dlo nvf | dcnt nvf | blo nvm | bcnt nvm].
+struct CoefLayout {
+  int nvf, nvm;
+  __host__ __device__ int dstride() const { return 1 + (4 + kBand) * (nvf + nvm); }
+  __host__ __device__ int istride() const { return 2 * (nvf + nvm); }
+  __host__ __device__ int Mv() const { return 1; }
+  __host__ __device__ int Hv() const { return 1 + 3 * nvf; }
+  __host__ __device__ int Cv() const { return 1 + 4 * nvf; }
+  __host__ __device__ int Nv() const { return 1 + (4 + kBand) * nvf; }
+  __host__ __device__ int Gv() const { return Nv() + 3 * nvm; }
+  __host__ __device__ int CvT() const { return Gv() + nvm; }
+  __host__ __device__ int dlo() const { return 0; }
+  __host__ __device__ int dcnt() const { return nvf; }
+  __host__ __device__ int blo() const { return 2 * nvf; }
+  __host__ __device__ int bcnt() const { return 2 * nvf + nvm; }
+};
+
+
 // Everything the kernels of one context touch.
 struct DevState {
   int64_t N = 0;
@@ -147,10 +168,5 @@ void launch_iface_coeffs(const DevState &d, hipStream_t st);
 void launch_iface(const DevState &d, int m, bool corr, hipStream_t st);
 void launch_step_end(const DevState &d, double dt, hipStream_t st);
 void launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
-
-// host+device helpers for the 1D face integrals
-__host__ __device__ double hat_integral(const double *x, int n, int a, double lo, double hi);
-__host__ __device__ double hat_product_integral(const double *x, int nx, int a, const double *y,
-                                                int ny, int c, double sy, double lo, double hi);
 
 }  // namespace mrsdc
