@@ -28,13 +28,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=120)
     ap.add_argument("--warmup", type=int, default=4)
-    ap.add_argument("--config", default="c1", choices=["c0", "c1", "c2"])
+    ap.add_argument("--config", default="c1", choices=["c0", "c1", "c2", "c3"],
+                    help="c3: only the 64-member ensemble (printed as its own line)")
     ap.add_argument("--precision", type=int, default=None, help="0 FP64, 1 FP32+refine")
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle sample (macro-steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="event timing of kernel classes inside the timed region (adds overhead)")
     ap.add_argument("--op-reps", type=int, default=200, help="operator timing launches")
+    ap.add_argument("--ensemble-steps", type=int, default=6,
+                    help="macro-steps of the 64-member 7.5 mm ensemble (0: skip)")
+    ap.add_argument("--precision-steps", type=int, default=24,
+                    help="macro-steps of the FP32+refinement form (0: skip)")
     return ap.parse_args()
 
 
@@ -58,6 +63,9 @@ def main():
     import paper_1707_03581_amd as pkg
 
     assert torch.cuda.is_available(), "no GPU"
+    if args.config == "c3":
+        print(json.dumps(ensemble(pkg, args)), flush=True)
+        return
     pb = workload(args.config, args.steps)
     dt = pb.scheme.dt
     N = pb.N
@@ -143,7 +151,69 @@ def main():
         g.destroy()
         out["rel_l2_vs_oracle"] = float(np.linalg.norm(Tg - Tref) / np.linalg.norm(Tref))
         out["rel_l2_sample_steps"] = S
+    if args.precision_steps > 0 and args.config == "c1":
+        out["fp32_refine"] = precision_form(pkg, args)
+    if args.ensemble_steps > 0 and args.config == "c1":
+        out["ensemble"] = ensemble(pkg, args)
     print(json.dumps(out), flush=True)
+
+
+def precision_form(pkg, args):
+    """Same machine, FP32 inner CG + FP64 refinement (error vs the FP64 path)."""
+    import torch
+    pb = workload("c2", args.precision_steps)
+    dt = pb.scheme.dt
+    ctx = pkg.simulation(pb, device=0)
+    ctx.advance(args.warmup * dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.advance(args.precision_steps * dt)
+    wall = time.perf_counter() - t0
+    us, nbytes = ctx.time_operator(args.op_reps)
+    ctx.destroy()
+    print(f"[bench] fp32+refine {args.precision_steps} steps in {wall:.3f}s", file=sys.stderr,
+          flush=True)
+    return {"value": pb.N * args.precision_steps / wall, "unit": "DOF*steps/s",
+            "ms_per_step": wall / args.precision_steps * 1e3,
+            "eta": args.precision_steps * dt / wall,
+            "op_avg_us": us, "op_GBps": nbytes / (us * 1e-6) / 1e9}
+
+
+def ensemble(pkg, args):
+    """64 seeded scenarios on the 7.5 mm machine (714,798 DOF each), one batch."""
+    import torch
+    import mrsdc_inputs as mi
+    S = 64
+    pb = mi.config3_scenario(0, nsteps=args.ensemble_steps, precision=mi.FP64)
+    members = []
+    for s in range(S):
+        h, alpha, pf, period, rng = mi.scenario_params(s)
+        members.append(dict(h=h, alpha=alpha, friction_W=pf, period=period,
+                            T0=20.0 + rng.uniform(-0.5, 0.5, size=pb.N)))
+    dt = pb.scheme.dt
+    ctx = pkg.batch_simulation(pb, members, device=0)
+    ctx.advance_steps(1)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(args.ensemble_steps):
+        s0 = time.perf_counter()
+        ctx.advance_steps(1)
+        lat.append(time.perf_counter() - s0)
+    wall = time.perf_counter() - t0
+    us, nbytes = ctx.time_operator(max(20, args.op_reps // 10))
+    ctx.destroy()
+    print(f"[bench] ensemble {args.ensemble_steps} steps in {wall:.3f}s", file=sys.stderr,
+          flush=True)
+    lat_ms = np.array(lat) * 1e3
+    return {"workload": f"64 x {pb.N} DOF (7.5 mm machine), FP64", "scenarios": S,
+            "dof_total": S * pb.N, "value": S * pb.N * args.ensemble_steps / wall,
+            "unit": "DOF*steps/s", "ms_per_step": wall / args.ensemble_steps * 1e3,
+            "eta_per_scenario": args.ensemble_steps * dt / wall,
+            "p50_step_ms": float(np.percentile(lat_ms, 50)),
+            "p99_step_ms": float(np.percentile(lat_ms, 99)),
+            "op_kernel": "kb_pcg_a (multi-RHS operator)", "op_avg_us": us,
+            "op_GBps": nbytes / (us * 1e-6) / 1e9, "op_frac_hbm": nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
 
 
 if __name__ == "__main__":

@@ -268,6 +268,8 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
         }
       }
       rowptr[row + 1] = (int64_t)col.size();
+      if (rowptr[row + 1] - rowptr[row] > 64)
+        return fail(c, MRSDC_EINVAL, "batched contexts need rows of at most 64 entries");
     }
   }
   BatchArgs &a = c->ba;
@@ -1215,9 +1217,13 @@ mrsdc_status mrsdc_time_operator(mrsdc_ctx *c, int reps, double *avg_us, int64_t
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   const bool fp32 = c->cfg.precision == MRSDC_FP32_REFINE;
-  launch_operator_timing(c->d, m, fp32, 3, c->stream);  // warm caches and clocks
+  auto run = [&](int n) {
+    if (c->S > 0) blaunch_operator_timing(c->ba, m, n, c->stream);
+    else launch_operator_timing(c->d, m, fp32, n, c->stream);
+  };
+  run(3);  // warm caches and clocks
   HIPCHK(hipEventRecord(e0, c->stream));
-  launch_operator_timing(c->d, m, fp32, reps, c->stream);
+  run(reps);
   HIPCHK(hipEventRecord(e1, c->stream));
   HIPCHK(hipEventSynchronize(e1));
   float ms = 0.f;
@@ -1225,7 +1231,11 @@ mrsdc_status mrsdc_time_operator(mrsdc_ctx *c, int reps, double *avg_us, int64_t
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   *avg_us = 1e3 * ms / reps;
-  if (bytes) *bytes = c->times.cg_spmv_bytes;
+  if (bytes) {
+    // batched: shared rows (col 4 B, K and R 8 B each) once, S right-hand sides
+    *bytes = c->S > 0 ? c->nnz * 20 + 8 * (c->ba.N + 1) + (16 * (int64_t)c->S + 8) * c->ba.N
+                      : c->times.cg_spmv_bytes;
+  }
   return MRSDC_OK;
 }
 

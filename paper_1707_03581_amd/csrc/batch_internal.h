@@ -63,6 +63,7 @@ void blaunch_quad_resid(const BatchArgs &a, int k, hipStream_t st);
 void blaunch_solve(const BatchArgs &a, int m, bool pred, int slot, int budget, double rtol,
                    hipStream_t st);
 void blaunch_iface(const BatchArgs &a, int m, bool corr, hipStream_t st);
+void blaunch_operator_timing(const BatchArgs &a, int m, int reps, hipStream_t st);
 void blaunch_commit(const BatchArgs &a, double dt, hipStream_t st);
 void blaunch_scatter(double *dst, const double *src, int64_t n, int S, int s, hipStream_t st);
 void blaunch_gather(double *dst, const double *src, int64_t n, int S, int s, hipStream_t st);
