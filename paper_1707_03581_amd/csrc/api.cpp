@@ -249,27 +249,42 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
   DevState &d = c->d;
   const int S = c->S;
   mrsdc_status st;
-  std::vector<int64_t> rowptr(N + 1, 0);
-  std::vector<int32_t> col;
+  // K as int16 column offsets; R only over the rows that carry a Robin term
+  std::vector<int64_t> rowptr(N + 1, 0), rptr(1, 0);
+  std::vector<int16_t> d16, rd16;
+  std::vector<int> rrow(N, -1);
   std::vector<double> Kv, Rv, Kd(N, 0.0), Rd(N, 0.0), gbase(N, 0.0);
   for (int b = 0; b < c->nbody; ++b) {
     const HostBody &B = c->body[b];
     for (int64_t i = 0; i < B.n; ++i) {
       const int64_t row = c->off[b] + i;
       gbase[row] = B.Tenv * (B.rload.empty() ? 0.0 : B.rload[i]);
+      bool any_r = false;
       for (int64_t e = B.rowptr[i]; e < B.rowptr[i + 1]; ++e) {
+        const int64_t delta = (int64_t)B.col[e] - i;
+        if (delta < -32768 || delta > 32767)
+          return fail(c, MRSDC_EINVAL, "batched contexts need |column - row| < 32768");
         const double kv = B.K[e], rv = B.R.empty() ? 0.0 : B.R[e];
-        col.push_back((int32_t)(c->off[b] + B.col[e]));
+        d16.push_back((int16_t)delta);
         Kv.push_back(kv);
-        Rv.push_back(rv);
+        any_r |= rv != 0.0;
         if (B.col[e] == i) {
           Kd[row] += kv;
           Rd[row] += rv;
         }
       }
-      rowptr[row + 1] = (int64_t)col.size();
+      rowptr[row + 1] = (int64_t)d16.size();
       if (rowptr[row + 1] - rowptr[row] > 64)
         return fail(c, MRSDC_EINVAL, "batched contexts need rows of at most 64 entries");
+      if (any_r) {
+        rrow[row] = (int)(rptr.size() - 1);
+        for (int64_t e = B.rowptr[i]; e < B.rowptr[i + 1]; ++e) {
+          if (B.R[e] == 0.0) continue;
+          rd16.push_back((int16_t)((int64_t)B.col[e] - i));
+          Rv.push_back(B.R[e]);
+        }
+        rptr.push_back((int64_t)rd16.size());
+      }
     }
   }
   BatchArgs &a = c->ba;
@@ -278,17 +293,25 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
   a.N = N;
   a.M = c->cfg.M;
   a.P = c->cfg.P;
-  a.grid = (int)std::min<int64_t>((N + 3) / 4, 1024);
+  // blocks of 4 rows, a multiple of the 8 XCDs
+  a.grid = (int)std::min<int64_t>(((N + 3) / 4 + 7) / 8 * 8, 1024);
   for (int m = 0; m <= c->cfg.M; ++m) a.dtau_h[m] = c->w.dtau[m];
   int64_t *prp;
-  int32_t *pc;
+  int16_t *pd;
+  int *pi;
   double *pv;
   if ((st = upload(c, &prp, rowptr))) return st;
   a.op.rowptr = prp;
-  if ((st = upload(c, &pc, col))) return st;
-  a.op.col = pc;
+  if ((st = upload(c, &pd, d16))) return st;
+  a.op.d16 = pd;
   if ((st = upload(c, &pv, Kv))) return st;
   a.op.Kv = pv;
+  if ((st = upload(c, &pi, rrow))) return st;
+  a.op.rrow = pi;
+  if ((st = upload(c, &prp, rptr))) return st;
+  a.op.rptr = prp;
+  if ((st = upload(c, &pd, rd16))) return st;
+  a.op.rd16 = pd;
   if ((st = upload(c, &pv, Rv))) return st;
   a.op.Rv = pv;
   a.op.N = N;
@@ -1232,8 +1255,9 @@ mrsdc_status mrsdc_time_operator(mrsdc_ctx *c, int reps, double *avg_us, int64_t
   hipEventDestroy(e1);
   *avg_us = 1e3 * ms / reps;
   if (bytes) {
-    // batched: shared rows (col 4 B, K and R 8 B each) once, S right-hand sides
-    *bytes = c->S > 0 ? c->nnz * 20 + 8 * (c->ba.N + 1) + (16 * (int64_t)c->S + 8) * c->ba.N
+    // batched: shared K rows (int16 offset + FP64 value) once, S right-hand
+    // sides read and written (the few Robin rows' R entries are left out)
+    *bytes = c->S > 0 ? c->nnz * 10 + 8 * (c->ba.N + 1) + (16 * (int64_t)c->S + 8) * c->ba.N
                       : c->times.cg_spmv_bytes;
   }
   return MRSDC_OK;

@@ -10,9 +10,13 @@ constexpr int kMaxS = 64;  // scenarios per batch = lanes of a wavefront
 // row's entries are wave-uniform.
 struct BatchOp {
   int64_t N = 0;
-  const int64_t *rowptr = nullptr;
-  const int32_t *col = nullptr;  // global columns
-  const double *Kv = nullptr, *Rv = nullptr;
+  const int64_t *rowptr = nullptr;  // K: [N+1]
+  const int16_t *d16 = nullptr;     // column - row
+  const double *Kv = nullptr;
+  const int *rrow = nullptr;        // [N] index into rptr, -1 for rows without R entries
+  const int64_t *rptr = nullptr;    // R over the Robin rows only
+  const int16_t *rd16 = nullptr;
+  const double *Rv = nullptr;
   const float *Kv32 = nullptr, *Rv32 = nullptr;
 };
 

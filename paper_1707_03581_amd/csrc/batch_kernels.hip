@@ -23,9 +23,25 @@ __device__ inline double bwave_sum(double v) {
   return v;
 }
 
-__device__ inline int wave_row0() {
-  return __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)));
+// XCD-aware row ranges: workgroups are dealt to the 8 XCDs round-robin, so
+// XCD x = block % 8 walks the contiguous rows [x N/8, (x+1) N/8); stencil
+// neighbours of the rows in flight then sit in that XCD's own L2.
+constexpr int kXcd = 8;
+struct RowRange {
+  int64_t row, end, stride;
+};
+__device__ inline RowRange xcd_rows(int64_t N) {
+  const int xcd = blockIdx.x % kXcd, local = blockIdx.x / kXcd, per = gridDim.x / kXcd;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  RowRange r;
+  r.row = N * xcd / kXcd + (int64_t)local * (kBlock / 64) + w;
+  r.end = N * (xcd + 1) / kXcd;
+  r.stride = (int64_t)per * (kBlock / 64);
+  return r;
 }
+#define FOR_ROWS(row, N)                  \
+  for (RowRange rr_ = xcd_rows(N); rr_.row < rr_.end; rr_.row += rr_.stride) \
+    if (const int64_t row = rr_.row; true)
 
 // sum the per-wave (per-lane = per-scenario) values of the block into
 // partial[k][blk][s]
@@ -52,45 +68,60 @@ __device__ inline double readlane_d(double v, int l) {
 }
 
 // multi-RHS row product: K x_s + h_s R x_s for lane s.  The row's entries
-// (at most 64) are fetched with one coalesced load, lane e holding entry e,
-// and broadcast with readlane, so the gathers of all entries are independent.
-// Must be called by the whole wavefront (no divergence): every lane loads its
-// entry; lanes with on == false gather a valid dummy element and their result
-// is to be ignored.
-__device__ inline double brow(const BatchOp &op, int64_t row, int S, int s, bool on, double h,
+// (at most 64) are fetched with one coalesced load, lane e holding entry e
+// (int16 column offset, K value), and broadcast with readlane, so the gathers
+// of all entries are independent.  R lives in its own CSR over the Robin
+// rows only.  Must be called by the whole wavefront (no divergence): every
+// lane loads its entry; lanes with on == false gather a valid dummy element
+// and their result is to be ignored.
+constexpr int kChunk = 16;  // gathers issued before the first is consumed
+
+// sum over entries [0, n) of row of v_e * x[(row + c_e) S + s], entries held
+// one per lane (lanes >= n hold v = 0); chunks of kChunk independent gathers
+__device__ __attribute__((always_inline)) inline double brow_part(int64_t row, int n, int c, double v, int S, int s, bool on,
+                                   const double *__restrict__ x) {
+  double acc = 0.0;
+  for (int e0 = 0; e0 < n; e0 += kChunk) {
+    double xv[kChunk];
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) {
+      const int e = e0 + j < 63 ? e0 + j : 63;
+      const int ce = __builtin_amdgcn_readlane(c, e);
+      xv[j] = x[(on && e0 + j < n) ? (row + ce) * S + s : 0];
+    }
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) {
+      const int e = e0 + j < 63 ? e0 + j : 63;
+      const double ve = readlane_d(v, e);
+      acc += (e0 + j < n ? ve : 0.0) * xv[j];
+    }
+  }
+  return acc;
+}
+
+__device__ __attribute__((always_inline)) inline double brow(const BatchOp &op, int64_t row, int S, int s, bool on, double h,
                               const double *__restrict__ x) {
   const int lane = threadIdx.x & 63;
   const int64_t e0 = op.rowptr[row];
   const int n = (int)(op.rowptr[row + 1] - e0);
   int c = 0;
-  double kv = 0.0, rv = 0.0;
+  double kv = 0.0;
   if (lane < n) {
-    c = op.col[e0 + lane];
+    c = op.d16[e0 + lane];
     kv = op.Kv[e0 + lane];
-    rv = op.Rv[e0 + lane];
   }
-  double k = 0.0, r = 0.0;
-  for (int e = 0; e < n; ++e) {
-    const int ce = __builtin_amdgcn_readlane(c, e);
-    const double ke = readlane_d(kv, e), re = readlane_d(rv, e);
-    const double xv = x[on ? (int64_t)ce * S + s : 0];
-    k += ke * xv;
-    r += re * xv;
+  const double k = brow_part(row, n, c, kv, S, s, on, x);
+  const int rb = op.rrow[row];
+  if (rb < 0) return k;
+  const int64_t f0 = op.rptr[rb];
+  const int nr = (int)(op.rptr[rb + 1] - f0);
+  int cr = 0;
+  double rv = 0.0;
+  if (lane < nr) {
+    cr = op.rd16[f0 + lane];
+    rv = op.Rv[f0 + lane];
   }
-  return k + h * r;
-}
-
-// FP32 operator: FP32 values, FP32 products and sums
-__device__ inline float brow32(const BatchOp &op, int64_t row, int S, int s, float h,
-                               const float *__restrict__ x) {
-  const int64_t e0 = op.rowptr[row], e1 = op.rowptr[row + 1];
-  float k = 0.0f, r = 0.0f;
-  for (int64_t e = e0; e < e1; ++e) {
-    const float xv = x[(int64_t)op.col[e] * S + s];
-    k += op.Kv32[e] * xv;
-    r += op.Rv32[e] * xv;
-  }
-  return k + h * r;
+  return k + h * brow_part(row, nr, cr, rv, S, s, on, x);
 }
 
 __device__ inline bool lane_on(const BatchScalars *sc, int s, int S) {
@@ -104,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void kb_f_multi(BatchArgs a, int j0, int j1
   const int s = threadIdx.x & 63, S = a.S;
   const bool on = s < S;
   const double h = on ? a.h[s] : 0.0;
-  for (int64_t row = wave_row0(); row < a.N; row += (int64_t)gridDim.x * (kBlock / 64)) {
+  FOR_ROWS(row, a.N) {
     const double g = h * a.gbase[row];
     for (int j = j0; j <= j1; ++j) {
       const double L = brow(a.op, row, S, s, on, h, a.T[j]);
@@ -122,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void kb_quad_resid(BatchArgs a) {
   const int P1 = a.P + 1;
   double rmax = 0.0;
   if (s < S) {
-    for (int64_t row = wave_row0(); row < a.N; row += (int64_t)gridDim.x * (kBlock / 64)) {
+    FOR_ROWS(row, a.N) {
       const int64_t i = row * S + s;
       const double mi = a.mass[row], Tn = a.T[0][i];
       const int pos = a.ifpos ? a.ifpos[row] : -1;
@@ -186,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void kb_init(BatchArgs a, int m, double dta
   const double h = on ? a.h[s] : 0.0;
   double *x = a.T[m];
   const double *Tp = a.T[m - 1];
-  for (int64_t row = wave_row0(); row < a.N; row += (int64_t)gridDim.x * (kBlock / 64)) {
+  FOR_ROWS(row, a.N) {
     const double Lx = PRED ? brow(a.op, row, S, s, on, h, Tp) : 0.0;
     if (!on) continue;
     const int64_t i = row * S + s;
@@ -265,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_a(BatchArgs a, int m, double dt
   double v[1] = {0.0};
   const bool on = TIMING ? s < S : lane_on(a.sc, s, S);
   const double h = on ? a.h[s] : 0.0;
-  for (int64_t row = wave_row0(); row < a.N; row += (int64_t)gridDim.x * (kBlock / 64)) {
+  FOR_ROWS(row, a.N) {
     const double Lp = brow(a.op, row, S, s, on, h, a.p);
     if (!on) continue;
     const int64_t i = row * S + s;
@@ -283,7 +314,7 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_b(BatchArgs a, int m, double dt
   if (lane_on(a.sc, s, S)) {
     const double h = a.h[s], alpha = a.sc->alpha[s];
     double *x = a.T[m];
-    for (int64_t row = wave_row0(); row < a.N; row += (int64_t)gridDim.x * (kBlock / 64)) {
+    FOR_ROWS(row, a.N) {
       const int64_t i = row * S + s;
       x[i] += alpha * a.p[i];
       const double r = a.r[i] - alpha * a.q[i];
@@ -299,7 +330,7 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_c(BatchArgs a, double dtau) {
   const int s = threadIdx.x & 63, S = a.S;
   if (!lane_on(a.sc, s, S)) return;
   const double h = a.h[s], beta = a.sc->beta[s];
-  for (int64_t row = wave_row0(); row < a.N; row += (int64_t)gridDim.x * (kBlock / 64)) {
+  FOR_ROWS(row, a.N) {
     const int64_t i = row * S + s;
     a.p[i] = bdinv(a, row, h, dtau) * a.r[i] + beta * a.p[i];
   }

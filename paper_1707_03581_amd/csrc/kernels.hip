@@ -74,10 +74,10 @@ __device__ inline double sell_row(const SellDev &op, int64_t s, int lane, int64_
   int64_t e = op.off[s] + lane;
   double acc = 0.0;
   if (D16) {
-#pragma unroll 4
+#pragma unroll 8
     for (; e < end; e += kSlice) acc += op.val[e] * x[row + op.d16[e]];
   } else {
-#pragma unroll 4
+#pragma unroll 8
     for (; e < end; e += kSlice) acc += op.val[e] * x[op.c32[e]];
   }
   return acc;
