@@ -28,8 +28,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=120)
     ap.add_argument("--warmup", type=int, default=4)
-    ap.add_argument("--config", default="c1", choices=["c0", "c1", "c2", "c3"],
-                    help="c3: only the 64-member ensemble (printed as its own line)")
+    ap.add_argument("--config", default="c1", choices=["c0", "c1", "c2", "c3", "c4"],
+                    help="c3: only the 64-member ensemble; c4: only the serving replay")
+    ap.add_argument("--serve-requests", type=int, default=24, help="requests replayed (c4)")
+    ap.add_argument("--serve-max-steps", type=int, default=12,
+                    help="cap on each request's macro-steps in the bounded replay (c4)")
     ap.add_argument("--precision", type=int, default=None, help="0 FP64, 1 FP32+refine")
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle sample (macro-steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -65,6 +68,9 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     if args.config == "c3":
         print(json.dumps(ensemble(pkg, args)), flush=True)
+        return
+    if args.config == "c4":
+        print(json.dumps(serving(pkg, args)), flush=True)
         return
     pb = workload(args.config, args.steps)
     dt = pb.scheme.dt
@@ -177,6 +183,39 @@ def precision_form(pkg, args):
             "ms_per_step": wall / args.precision_steps * 1e3,
             "eta": args.precision_steps * dt / wall,
             "op_avg_us": us, "op_GBps": nbytes / (us * 1e-6) / 1e9}
+
+
+def serving(pkg, args):
+    """Bounded replay of the seeded request trace (Poisson arrivals at 20/s,
+    mesh levels 2 cm / 1 cm / 5 mm, per-request parameters), continuous
+    batching per level; each request's steps capped to keep the run short."""
+    import mrsdc_inputs as mi
+    from paper_1707_03581_amd.serve import Request, Server, summarize
+    trace = mi.serving_trace(args.serve_requests)
+    needed = sorted({r["level"] for r in trace})
+    levels = {}
+    for name in needed:
+        stand, stock = mi.MESH_LEVELS[name]
+        levels[name] = mi.machine(stand_nodes=stand, stock_nodes=stock, nsteps=1,
+                                  name=f"machine_{name}")
+        print(f"[bench] level {name}: N={levels[name].N}", file=sys.stderr, flush=True)
+    reqs = []
+    for r in trace:
+        rng = np.random.default_rng(r["seed"] + 1)
+        reqs.append(Request(id=r["id"], arrival=r["arrival"], level=r["level"],
+                            nsteps=min(r["nsteps"], args.serve_max_steps), h=r["h"],
+                            alpha=r["alpha"], friction_W=r["friction_W"], period=r["period"],
+                            T0=20.0 + rng.uniform(-0.5, 0.5, size=levels[r["level"]].N)))
+    srv = Server(levels, slots_per_level=64)
+    done = srv.run(reqs)
+    out = summarize(done, 5.0, {k: v.N for k, v in levels.items()})
+    out.update({"metric": "serving: p50/p99 macro-step latency, per-request eta, DOF*steps/s",
+                "workload": f"first {len(reqs)} requests of the 20 req/s trace, <= "
+                            f"{args.serve_max_steps} steps each",
+                "levels": {k: v.N for k, v in levels.items()},
+                "footprint_bytes": srv.footprint})
+    print(f"[bench] serving done in {srv.wall:.2f}s", file=sys.stderr, flush=True)
+    return out
 
 
 def ensemble(pkg, args):
