@@ -22,17 +22,46 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the timed CG operator kernel on the FP64 machine
+# workload, from two counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch), each scaled by what the same counter read for a 256 MiB
+# device-to-device copy (FETCH_SIZE 131088.8 KiB -> x1.99974, WRITE_SIZE
+# 262144.0 KiB -> x1.0).  Valid only for the kernel source it was taken on.
+COUNTER_TRAFFIC = {
+    "kernels_sha256": "7032d655b3f6b8662e7c6d7275e8c39a3896636cc8740c342601e556976ad375",
+    "workload": "machine-310k", "precision": 0,
+    "fetch_kib": 47106.4, "fetch_scale": 1.99974,
+    "write_kib": 2454.3, "write_scale": 1.0,
+}
+
+
+def counter_traffic(pb):
+    """Scaled counter bytes per launch, or None if the kernel source changed."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1707_03581_amd", "csrc", "kernels.hip")
+    try:
+        with open(src, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    c = COUNTER_TRAFFIC
+    if digest != c["kernels_sha256"] or pb.name != c["workload"] or pb.scheme.precision != c["precision"]:
+        return None
+    return (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0
+
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=120)
     ap.add_argument("--warmup", type=int, default=4)
-    ap.add_argument("--config", default="c1", choices=["c0", "c1", "c2", "c3", "c4"],
-                    help="c3: only the 64-member ensemble; c4: only the serving replay")
-    ap.add_argument("--serve-requests", type=int, default=24, help="requests replayed (c4)")
+    ap.add_argument("--config", default="machine", choices=["box", "machine", "machine-fp32", "ensemble", "serve"],
+                    help="ensemble: only the 64-member ensemble; serve: only the serving replay")
+    ap.add_argument("--serve-requests", type=int, default=24, help="requests replayed (serve)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="finish with a device-to-device copy of this many MiB (counter scale)")
     ap.add_argument("--serve-max-steps", type=int, default=12,
-                    help="cap on each request's macro-steps in the bounded replay (c4)")
+                    help="cap on each request's macro-steps in the bounded replay (serve)")
     ap.add_argument("--precision", type=int, default=None, help="0 FP64, 1 FP32+refine")
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle sample (macro-steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -48,11 +77,11 @@ def parse():
 
 def workload(name, nsteps):
     import mrsdc_inputs as mi
-    if name == "c0":
-        return mi.config0()
-    if name == "c2":
-        return mi.config2(nsteps=nsteps)
-    return mi.config1(nsteps=nsteps)
+    if name == "box":
+        return mi.box_patch_2673()
+    if name == "machine-fp32":
+        return mi.machine_310k_fp32(nsteps=nsteps)
+    return mi.machine_310k(nsteps=nsteps)
 
 
 def main():
@@ -66,10 +95,10 @@ def main():
     import paper_1707_03581_amd as pkg
 
     assert torch.cuda.is_available(), "no GPU"
-    if args.config == "c3":
+    if args.config == "ensemble":
         print(json.dumps(ensemble(pkg, args)), flush=True)
         return
-    if args.config == "c4":
+    if args.config == "serve":
         print(json.dumps(serving(pkg, args)), flush=True)
         return
     pb = workload(args.config, args.steps)
@@ -134,7 +163,7 @@ def main():
     achieved = nbytes / (us * 1e-6) / 1e9
     out["roofline"] = {"bound": "hbm", "kernel": "k_pcg_a (CG operator application)",
                        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(pb),
                        "avg_launch_us": us, "launches": args.op_reps, "bytes_per_launch": nbytes}
     if kt and kt["iface_launches"]:
         out["iface_avg_us"] = kt["iface_ms"] / kt["iface_launches"] * 1e3
@@ -157,17 +186,31 @@ def main():
         g.destroy()
         out["rel_l2_vs_oracle"] = float(np.linalg.norm(Tg - Tref) / np.linalg.norm(Tref))
         out["rel_l2_sample_steps"] = S
-    if args.precision_steps > 0 and args.config == "c1":
+    if args.precision_steps > 0 and args.config == "machine":
         out["fp32_refine"] = precision_form(pkg, args)
-    if args.ensemble_steps > 0 and args.config == "c1":
+    if args.ensemble_steps > 0 and args.config == "machine":
         out["ensemble"] = ensemble(pkg, args)
     print(json.dumps(out), flush=True)
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+
+
+def calibrate_copy(mib):
+    """A plain copy of known size: reads and writes mib MiB once each."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"[bench] calibration copy of {mib} MiB done", file=sys.stderr, flush=True)
 
 
 def precision_form(pkg, args):
     """Same machine, FP32 inner CG + FP64 refinement (error vs the FP64 path)."""
     import torch
-    pb = workload("c2", args.precision_steps)
+    pb = workload("machine-fp32", args.precision_steps)
     dt = pb.scheme.dt
     ctx = pkg.simulation(pb, device=0)
     ctx.advance(args.warmup * dt)
@@ -223,7 +266,7 @@ def ensemble(pkg, args):
     import torch
     import mrsdc_inputs as mi
     S = 64
-    pb = mi.config3_scenario(0, nsteps=args.ensemble_steps, precision=mi.FP64)
+    pb = mi.ensemble_member(0, nsteps=args.ensemble_steps, precision=mi.FP64)
     members = []
     for s in range(S):
         h, alpha, pf, period, rng = mi.scenario_params(s)

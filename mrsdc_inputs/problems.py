@@ -174,22 +174,23 @@ def machine(stand_nodes=(41, 41, 161), stock_nodes=(31, 31, 41), stand_L=(0.4, 0
 
 
 # ---------------------------------------------------------------------------
-# The five workloads.  Mesh counts: the single box counts elements (8x8x32 ->
+# The workloads.  Mesh counts: the single box counts elements (8x8x32 ->
 # 9x9x33 nodes); the machine meshes count nodes.
 # ---------------------------------------------------------------------------
 
-def config0() -> Problem:
+def box_patch_2673() -> Problem:
     """FP64 single steel box, 2,673 nodes, moving 2 kW/m^2 patch, 60 s horizon."""
-    return patch_box(name="c0_box_patch_2673")
+    return patch_box(name="box-patch-2673")
 
 
-def config1(nsteps=120) -> Problem:
+def machine_310k(nsteps=120) -> Problem:
     """FP64 two-body machine, stand 41x41x161 + stock 31x31x41 (310,042 nodes)."""
-    return machine(nsteps=nsteps, name="c1_machine_310k")
+    return machine(nsteps=nsteps, name="machine-310k")
 
 
-def config2(nsteps=120) -> Problem:
-    p = machine(nsteps=nsteps, name="c2_machine_310k_fp32refine")
+def machine_310k_fp32(nsteps=120) -> Problem:
+    """The two-body machine with the FP32 inner solves + FP64 refinement."""
+    p = machine(nsteps=nsteps, name="machine-310k-fp32refine")
     p.scheme.precision = FP32_REFINE
     return p
 
@@ -204,12 +205,12 @@ def scenario_params(s: int):
     return h, alpha, pf, period, rng
 
 
-def config3_scenario(s: int, stand_nodes=(54, 54, 214), stock_nodes=(41, 41, 54), nsteps=120,
-                     precision=FP32_REFINE) -> Problem:
+def ensemble_member(s: int, stand_nodes=(54, 54, 214), stock_nodes=(41, 41, 54), nsteps=120,
+                    precision=FP32_REFINE) -> Problem:
     """Scenario s of the 64-member ensemble on the 7.5 mm machine mesh."""
     h, alpha, pf, period, rng = scenario_params(s)
     p = machine(stand_nodes=stand_nodes, stock_nodes=stock_nodes, h=h, alpha=alpha,
-                friction_W=pf, period=period, nsteps=nsteps, name=f"c3_s{s}")
+                friction_W=pf, period=period, nsteps=nsteps, name=f"ensemble-7.5mm-s{s}")
     p.T0 = 20.0 + rng.uniform(-0.5, 0.5, size=p.N)
     p.scheme.precision = precision
     p.meta = dict(scenario=s, h=h, alpha=alpha, friction_W=pf, period=period)

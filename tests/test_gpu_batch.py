@@ -99,7 +99,7 @@ def test_inactive_member_keeps_state_and_clock():
 def test_ensemble_7p5mm_sampled():
     """The 64-member ensemble on the 7.5 mm machine (714,798 DOF per member),
     2 steps; 3 members checked against the oracle."""
-    pb = mi.config3_scenario(0, nsteps=2, precision=mi.FP64)
+    pb = mi.ensemble_member(0, nsteps=2, precision=mi.FP64)
     mem = []
     for s in range(64):
         q = mi.scenario_params(s)

@@ -82,7 +82,7 @@ def test_small_cases_match_oracle(name):
 
 def test_box_patch_2673_full_horizon():
     """The single-box workload, 60 steps of 1 s (Lobatto M=3, K=3, P=10)."""
-    pb = mi.config0()
+    pb = mi.box_patch_2673()
     ref, _ = oracle.run(pb)
     T, st = run_gpu(pb, pb.nsteps)
     e = rel(T, ref)
@@ -93,7 +93,7 @@ def test_box_patch_2673_full_horizon():
 def test_machine_310k_sampled_steps():
     """The 310,042-node two-body machine (Lobatto M=5, K=4, P=5, dt=5 s), first
     3 steps, in the launch configuration the benchmark uses."""
-    pb = mi.config1(nsteps=3)
+    pb = mi.machine_310k(nsteps=3)
     ref, _ = oracle.run(pb, nsteps=3)
     T, st = run_gpu(pb, 3)
     e = rel(T, ref)
@@ -206,7 +206,7 @@ def test_fp32_refine_small_cases(name):
 
 
 def test_fp32_refine_machine_310k_sampled_steps():
-    pb = mi.config2(nsteps=3)
+    pb = mi.machine_310k_fp32(nsteps=3)
     ref, _ = oracle.run(pb, nsteps=3)
     T, st = run_gpu(pb, 3, precision=1)
     e = rel(T, ref)

@@ -81,7 +81,7 @@ def test_cosine_mode_is_discrete_eigenvector(L, nodes):
 
 
 def test_face_grids_and_machine_sizes():
-    p = mi.config0()
+    p = mi.box_patch_2673()
     assert (p.N, p.nnz) == (2673, 60625)
     b = p.bodies[0]
     f = b.faces["x1"]
@@ -99,7 +99,7 @@ def test_face_grids_and_machine_sizes():
 
 
 def test_seeded_inputs_are_reproducible():
-    a, b = mi.config0(), mi.config0()
+    a, b = mi.box_patch_2673(), mi.box_patch_2673()
     assert np.array_equal(a.T0, b.T0)
     s0 = mi.scenario_params(3)[:4]
     assert s0 == mi.scenario_params(3)[:4]
