@@ -562,6 +562,9 @@ mrsdc_status prepare(mrsdc_ctx *c) {
       if (m >= 1) HIPCHK(hipMemset(d.F[m], 0, NS * sizeof(double)));
       if (d.I[m]) HIPCHK(hipMemset(d.I[m], 0, NS * sizeof(double)));
     }
+    HIPCHK(hipMemset(d.r, 0, NS * sizeof(double)));
+    HIPCHK(hipMemset(d.p, 0, NS * sizeof(double)));
+    HIPCHK(hipMemset(d.q, 0, NS * sizeof(double)));
   }
   if ((st = dalloc(c, &d.partial, 3 * (size_t)d.grid))) return st;
   if ((st = dalloc(c, &d.sc, 1)) || (st = dalloc(c, &d.ctr, 1)) || (st = dalloc(c, &d.tn, 1)))

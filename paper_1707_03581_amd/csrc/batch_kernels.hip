@@ -93,7 +93,10 @@ __device__ __attribute__((always_inline)) inline double brow_part(int64_t row, i
     for (int j = 0; j < kChunk; ++j) {
       const int e = e0 + j < 63 ? e0 + j : 63;
       const double ve = readlane_d(v, e);
-      acc += (e0 + j < n ? ve : 0.0) * xv[j];
+      // entries past the row end gathered a placeholder value that may be
+      // any bit pattern (another scenario's slot): skip them, do not scale
+      // them by zero (n is the same for the whole wave)
+      if (e0 + j < n) acc += ve * xv[j];
     }
   }
   return acc;

@@ -115,3 +115,30 @@ def test_ensemble_7p5mm_sampled():
         e = rel(outs[s], ref)
         print(f"  member {s}: rel_l2={e:.3e}", flush=True)
         assert e <= 1e-10
+
+
+def test_blown_up_member_does_not_leak_into_others():
+    """A member whose state overflows makes the step fail (ENOCONV, nothing
+    committed); once it is switched off, its non-finite CG vectors must not
+    reach the other members (rows shorter than the gather chunk read a
+    placeholder slot), which then match their runs alone bitwise."""
+    import paper_1707_03581_amd as m
+    pb = small_machine()
+    mem = members_for(pb, 3, seed0=1200)
+    sign = np.where(np.arange(pb.N) % 2 == 0, 1.0, -1.0)
+    mem[0] = dict(mem[0], T0=1e308 * sign)
+    ctx = m.batch_simulation(pb, mem)
+    with pytest.raises(m.MrsdcError) as e:
+        ctx.advance_steps(1)
+    assert e.value.status == m.ENOCONV
+    for s in (1, 2):
+        assert ctx.get_scenario_time(s) == 0.0
+        assert np.array_equal(ctx.get_scenario_temperature(s, pb.N), mem[s]["T0"])
+    ctx.set_active(0, False)
+    ctx.advance_steps(2)
+    outs = [ctx.get_scenario_temperature(s, pb.N) for s in (1, 2)]
+    ctx.destroy()
+    for s, got in zip((1, 2), outs):
+        alone, _, _ = run_batch(pb, [mem[s]], 2)
+        assert np.all(np.isfinite(got))
+        assert np.array_equal(alone[0], got), s
