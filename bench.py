@@ -189,7 +189,9 @@ def main():
     if args.precision_steps > 0 and args.config == "machine":
         out["fp32_refine"] = precision_form(pkg, args)
     if args.ensemble_steps > 0 and args.config == "machine":
-        out["ensemble"] = ensemble(pkg, args)
+        import mrsdc_inputs as mi
+        out["ensemble"] = ensemble(pkg, args, mi.FP32_REFINE)
+        out["ensemble_fp64"] = ensemble(pkg, args, mi.FP64)
     print(json.dumps(out), flush=True)
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
@@ -261,12 +263,14 @@ def serving(pkg, args):
     return out
 
 
-def ensemble(pkg, args):
+def ensemble(pkg, args, precision=None):
     """64 seeded scenarios on the 7.5 mm machine (714,798 DOF each), one batch."""
     import torch
     import mrsdc_inputs as mi
     S = 64
-    pb = mi.ensemble_member(0, nsteps=args.ensemble_steps, precision=mi.FP64)
+    if precision is None:
+        precision = mi.FP32_REFINE
+    pb = mi.ensemble_member(0, nsteps=args.ensemble_steps, precision=precision)
     members = []
     for s in range(S):
         h, alpha, pf, period, rng = mi.scenario_params(s)
@@ -284,11 +288,28 @@ def ensemble(pkg, args):
         lat.append(time.perf_counter() - s0)
     wall = time.perf_counter() - t0
     us, nbytes = ctx.time_operator(max(20, args.op_reps // 10))
+    T_member0 = ctx.get_scenario_temperature(0, pb.N)
     ctx.destroy()
     print(f"[bench] ensemble {args.ensemble_steps} steps in {wall:.3f}s", file=sys.stderr,
           flush=True)
     lat_ms = np.array(lat) * 1e3
-    return {"workload": f"64 x {pb.N} DOF (7.5 mm machine), FP64", "scenarios": S,
+    form = "FP64" if precision == mi.FP64 else "FP32 inner + FP64 refinement"
+    extra = {}
+    if not args.no_cpu_baseline:
+        # CPU oracle on member 0 over the same steps: error and a per-member baseline
+        import oracle
+        mb = members[0]
+        nst = args.ensemble_steps + 1
+        t = time.perf_counter()
+        ref, ost = oracle.run(pb, nsteps=nst, T0=mb["T0"], h=mb["h"], alpha=mb["alpha"],
+                              friction_W=mb["friction_W"], period=mb["period"])
+        tc = time.perf_counter() - t
+        extra["rel_l2_vs_oracle_member0"] = float(np.linalg.norm(T_member0 - ref) /
+                                                  np.linalg.norm(ref))
+        extra["cpu_baseline"] = {"value": pb.N * nst / tc, "unit": "DOF*steps/s",
+                                 "cores": int(ost["threads"]), "kind": "oracle",
+                                 "sample": f"member 0 alone, {nst} macro-steps", "seconds": tc}
+    return {**extra, "workload": f"64 x {pb.N} DOF (7.5 mm machine), {form}", "scenarios": S,
             "dof_total": S * pb.N, "value": S * pb.N * args.ensemble_steps / wall,
             "unit": "DOF*steps/s", "ms_per_step": wall / args.ensemble_steps * 1e3,
             "eta_per_scenario": args.ensemble_steps * dt / wall,

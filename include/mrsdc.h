@@ -182,11 +182,14 @@ mrsdc_status mrsdc_quadrature(int M, int node_family, int P, double dt, double *
  * _set_motion, _set_contact); each scenario has its own Robin coefficient h,
  * contact alpha, friction power, motion period, time and temperature field.
  * The operator is applied to all scenarios in one pass (multi-right-hand
- * side).  FP64 path, contact coupling (or none).  A scenario's result does
- * not depend on the other members of the batch. */
+ * side).  Both precisions: MRSDC_FP64, or MRSDC_FP32_REFINE (per scenario,
+ * FP32 inner CG with FP32 operator values, vectors and row sums, inside FP64
+ * iterative refinement; node states, quadrature and f^E stay FP64, as for a
+ * single context).  Contact coupling (or none).  A scenario's result does not
+ * depend on the other members of the batch. */
 
 /* Create a batched context of S scenarios (1..64).  EINVAL for S out of
- * range or a precision other than MRSDC_FP64. */
+ * range. */
 mrsdc_status mrsdc_batch_create(mrsdc_ctx **out, const mrsdc_config *cfg, int S);
 
 /* Parameters of scenario s; unset scenarios use the context-wide values. */

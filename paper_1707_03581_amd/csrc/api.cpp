@@ -360,6 +360,27 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
   a.r = d.r;
   a.p = d.p;
   a.q = d.q;
+  if (c->cfg.precision == MRSDC_FP32_REFINE) {
+    // FP32 copies of the shared operator values for the inner solves; FP32
+    // inner vectors and the FP64 refinement residual, scenario-interleaved
+    a.fp32 = 1;
+    std::vector<float> k32(Kv.begin(), Kv.end()), r32(Rv.begin(), Rv.end());
+    float *pf32;
+    if ((st = upload(c, &pf32, k32))) return st;
+    a.op.Kv32 = pf32;
+    if ((st = upload(c, &pf32, r32))) return st;
+    a.op.Rv32 = pf32;
+    const size_t NS = (size_t)N * S;
+    if ((st = dalloc(c, &a.x32, NS)) || (st = dalloc(c, &a.r32, NS)) ||
+        (st = dalloc(c, &a.p32, NS)) || (st = dalloc(c, &a.q32, NS)) ||
+        (st = dalloc(c, &a.r64, NS)))
+      return st;
+    HIPCHK(hipMemset(a.x32, 0, NS * sizeof(float)));
+    HIPCHK(hipMemset(a.r32, 0, NS * sizeof(float)));
+    HIPCHK(hipMemset(a.p32, 0, NS * sizeof(float)));
+    HIPCHK(hipMemset(a.q32, 0, NS * sizeof(float)));
+    HIPCHK(hipMemset(a.r64, 0, NS * sizeof(double)));
+  }
   a.Eold = d.Eold;
   a.Enew = d.Enew;
   a.Tbuf[0] = d.Tbuf[0];
@@ -407,8 +428,6 @@ mrsdc_status prepare(mrsdc_ctx *c) {
   if (d.grid < 1) d.grid = 1;
   const bool batch = c->S > 0;
   const int S = batch ? c->S : 1;
-  if (batch && cfg.precision != MRSDC_FP64)
-    return fail(c, MRSDC_EINVAL, "batched contexts run the FP64 path");
   if (batch && c->cpl.kind == 2)
     return fail(c, MRSDC_EINVAL, "batched contexts support the contact coupling only");
 
@@ -466,28 +485,30 @@ mrsdc_status prepare(mrsdc_ctx *c) {
     }
   }
   // lanes past the last row keep col 0 / delta 0 and are never read
-  if (cfg.precision == MRSDC_FP32_REFINE) {
+  if (cfg.precision == MRSDC_FP32_REFINE && !batch) {
     val32.resize(nelem);
     for (int64_t e = 0; e < nelem; ++e) val32[e] = (float)val[e];
   }
   mrsdc_status st;
-  int64_t *doff;
-  double *dval;
-  if ((st = upload(c, &doff, off))) return st;
-  if ((st = upload(c, &dval, val))) return st;
   d.op.nrows = N;
   d.op.nslices = nslices;
   d.op.nelem = nelem;
-  d.op.off = doff;
-  d.op.val = dval;
-  if (use16) {
-    int16_t *p;
-    if ((st = upload(c, &p, d16))) return st;
-    d.op.d16 = p;
-  } else {
-    int32_t *p;
-    if ((st = upload(c, &p, c32))) return st;
-    d.op.c32 = p;
+  if (!batch) {  // batched contexts keep their own row-major operators
+    int64_t *doff;
+    double *dval;
+    if ((st = upload(c, &doff, off))) return st;
+    if ((st = upload(c, &dval, val))) return st;
+    d.op.off = doff;
+    d.op.val = dval;
+    if (use16) {
+      int16_t *p;
+      if ((st = upload(c, &p, d16))) return st;
+      d.op.d16 = p;
+    } else {
+      int32_t *p;
+      if ((st = upload(c, &p, c32))) return st;
+      d.op.c32 = p;
+    }
   }
   if (!val32.empty()) {
     float *p;
@@ -524,7 +545,7 @@ mrsdc_status prepare(mrsdc_ctx *c) {
       if ((st = upload(c, &d.dinv32[m], d32))) return st;
     }
   }
-  if (fp32) {
+  if (fp32 && !batch) {
     std::vector<float> m32(N);
     for (int64_t i = 0; i < N; ++i) m32[i] = (float)mass[i];
     float *pm;
@@ -554,7 +575,8 @@ mrsdc_status prepare(mrsdc_ctx *c) {
     if (m >= 1 && (st = dalloc(c, &d.F[m], NS))) return st;
     if (m >= 1 && c->w.dtau[m] != 0.0 && (st = dalloc(c, &d.I[m], NS))) return st;
   }
-  if ((st = dalloc(c, &d.r, NS)) || (st = dalloc(c, &d.p, NS)) || (st = dalloc(c, &d.q, NS)))
+  if (!(batch && fp32) &&
+      ((st = dalloc(c, &d.r, NS)) || (st = dalloc(c, &d.p, NS)) || (st = dalloc(c, &d.q, NS))))
     return st;
   if (batch) {  // inactive scenarios keep finite zeros
     for (int m = 0; m <= cfg.M; ++m) {
@@ -562,9 +584,11 @@ mrsdc_status prepare(mrsdc_ctx *c) {
       if (m >= 1) HIPCHK(hipMemset(d.F[m], 0, NS * sizeof(double)));
       if (d.I[m]) HIPCHK(hipMemset(d.I[m], 0, NS * sizeof(double)));
     }
-    HIPCHK(hipMemset(d.r, 0, NS * sizeof(double)));
-    HIPCHK(hipMemset(d.p, 0, NS * sizeof(double)));
-    HIPCHK(hipMemset(d.q, 0, NS * sizeof(double)));
+    if (!fp32) {
+      HIPCHK(hipMemset(d.r, 0, NS * sizeof(double)));
+      HIPCHK(hipMemset(d.p, 0, NS * sizeof(double)));
+      HIPCHK(hipMemset(d.q, 0, NS * sizeof(double)));
+    }
   }
   if ((st = dalloc(c, &d.partial, 3 * (size_t)d.grid))) return st;
   if ((st = dalloc(c, &d.sc, 1)) || (st = dalloc(c, &d.ctr, 1)) || (st = dalloc(c, &d.tn, 1)))
@@ -867,17 +891,29 @@ mrsdc_status batch_upload_params(mrsdc_ctx *c) {
   return MRSDC_OK;
 }
 
+BSolve bsolve(const mrsdc_ctx *c, int k, int m) {
+  BSolve sv;
+  sv.m = m;
+  sv.pred = k == 0;
+  sv.slot = slot_of(k, m);
+  sv.budget = c->budget[sv.slot];
+  sv.rounds = c->rounds[sv.slot];
+  sv.rtol = c->cfg.pcg_rtol;
+  sv.refine_rtol = c->cfg.refine_rtol;
+  sv.inner_rtol = c->cfg.inner_rtol;
+  return sv;
+}
+
 void enqueue_batch_step(mrsdc_ctx *c) {
   BatchArgs &a = c->ba;
   const int M = c->cfg.M, K = c->cfg.K;
   const bool lob = c->cfg.node_family == MRSDC_LOBATTO;
-  const double rtol = c->cfg.pcg_rtol;
   hipStream_t st = c->stream;
   blaunch_clear(a, st);
   blaunch_iface_coeffs(a, st);
   for (int m = 1; m <= M; ++m) {
     if (c->w.dtau[m] == 0.0) continue;
-    blaunch_solve(a, m, true, slot_of(0, m), c->budget[slot_of(0, m)], rtol, st);
+    blaunch_solve(a, bsolve(c, 0, m), st);
     blaunch_iface(a, m, false, st);
   }
   std::swap(a.Eold, a.Enew);
@@ -888,7 +924,7 @@ void enqueue_batch_step(mrsdc_ctx *c) {
     if (k > K) break;
     for (int m = 1; m <= M; ++m) {
       if (c->w.dtau[m] == 0.0) continue;
-      blaunch_solve(a, m, false, slot_of(k, m), c->budget[slot_of(k, m)], rtol, st);
+      blaunch_solve(a, bsolve(c, k, m), st);
       blaunch_iface(a, m, true, st);
     }
     std::swap(a.Eold, a.Enew);
@@ -1260,7 +1296,10 @@ mrsdc_status mrsdc_time_operator(mrsdc_ctx *c, int reps, double *avg_us, int64_t
   if (bytes) {
     // batched: shared K rows (int16 offset + FP64 value) once, S right-hand
     // sides read and written (the few Robin rows' R entries are left out)
-    *bytes = c->S > 0 ? c->nnz * 10 + 8 * (c->ba.N + 1) + (16 * (int64_t)c->S + 8) * c->ba.N
+    // (FP32 form: FP32 values and right-hand sides)
+    const bool f32 = c->cfg.precision == MRSDC_FP32_REFINE;
+    *bytes = c->S > 0 ? c->nnz * (f32 ? 6 : 10) + 8 * (c->ba.N + 1) +
+                            ((f32 ? 8 : 16) * (int64_t)c->S + 8) * c->ba.N
                       : c->times.cg_spmv_bytes;
   }
   return MRSDC_OK;
@@ -1290,7 +1329,6 @@ mrsdc_status mrsdc_batch_create(mrsdc_ctx **out, const mrsdc_config *cfg, int S)
   if (!out) return MRSDC_EINVAL;
   *out = nullptr;
   if (S < 1 || S > kMaxS) return MRSDC_EINVAL;
-  if (cfg && cfg->precision != MRSDC_FP64) return MRSDC_EINVAL;
   mrsdc_status st = mrsdc_create(out, cfg);
   if (st) return st;
   mrsdc_ctx *c = *out;
@@ -1381,22 +1419,34 @@ mrsdc_status mrsdc_batch_advance(mrsdc_ctx *c, int nsteps, mrsdc_stats *stats) {
                             c->stream));
       HIPCHK(hipStreamSynchronize(c->stream));
       const BatchScalars &h = *c->bsc_host;
+      const bool fp32 = c->cfg.precision == MRSDC_FP32_REFINE;
       bool failed = false;
       for (int s = 0; s < S; ++s) failed |= (c->sc_active[s] && h.fail[s]);
       if (!failed) {
         for (int i = 0; i < kSlots; ++i) {
-          int mx = 0;
-          for (int s = 0; s < S; ++s)
-            if (c->sc_active[s]) mx = std::max(mx, h.slot_iters[i][s]);
-          if (mx > 0) {
+          int mx = 0, rmx = 0;
+          bool cut = false;  // an inner solve ran out of its budget (FP32)
+          for (int s = 0; s < S; ++s) {
+            if (!c->sc_active[s]) continue;
+            const int it = h.slot_iters[i][s];
+            if (it < 0) cut = true;
+            else mx = std::max(mx, it);
+            rmx = std::max(rmx, h.slot_rounds[i][s]);
+          }
+          if (cut && fp32) {
+            if (c->budget[i] < c->cfg.pcg_maxit)
+              c->budget[i] = std::min(c->cfg.pcg_maxit, 2 * c->budget[i]);
+          } else if (mx > 0) {
             c->budget[i] = std::min(c->cfg.pcg_maxit, mx + std::max(2, mx / 5));
             c->expect[i] = mx;
           }
-          for (int s = 0; s < S; ++s)
-            if (c->sc_active[s] && h.slot_iters[i][s] > 0) {
-              acc.pcg_iters += h.slot_iters[i][s];
-              acc.max_iters = std::max(acc.max_iters, h.slot_iters[i][s]);
-            }
+          if (fp32 && rmx > 0) c->rounds[i] = std::min(c->cfg.refine_maxit, rmx + 1);
+          acc.max_iters = std::max(acc.max_iters, mx);
+        }
+        for (int s = 0; s < S; ++s) {
+          if (!c->sc_active[s]) continue;
+          acc.pcg_iters += h.iters_total[s];
+          acc.refine_steps += h.refine_total[s];
         }
         for (int k = 0; k <= Kc; ++k) {
           double r = 0.0;
@@ -1406,11 +1456,20 @@ mrsdc_status mrsdc_batch_advance(mrsdc_ctx *c, int nsteps, mrsdc_stats *stats) {
         }
         break;
       }
+      // some solve of an active scenario failed: nothing was committed
       bool grow = false;
       for (int i = 0; i < kSlots; ++i) {
         bool slot_failed = false;
-        for (int s = 0; s < S; ++s) slot_failed |= (c->sc_active[s] && h.slot_iters[i][s] < 0);
-        if (slot_failed && c->budget[i] < c->cfg.pcg_maxit) {
+        for (int s = 0; s < S; ++s) {
+          if (!c->sc_active[s]) continue;
+          slot_failed |= fp32 ? h.slot_rounds[i][s] < 0 : h.slot_iters[i][s] < 0;
+        }
+        if (!slot_failed) continue;
+        if (fp32 && c->rounds[i] < c->cfg.refine_maxit) {
+          c->rounds[i] = std::min(c->cfg.refine_maxit, 2 * c->rounds[i]);
+          grow = true;
+        }
+        if (c->budget[i] < c->cfg.pcg_maxit) {
           c->budget[i] = std::min(c->cfg.pcg_maxit, 2 * c->budget[i]);
           grow = true;
         }

@@ -20,19 +20,34 @@ struct BatchOp {
   const float *Kv32 = nullptr, *Rv32 = nullptr;
 };
 
-// Per-scenario solver scalars (index s fastest).
+// Per-scenario solver scalars (index s fastest).  In the FP32 form, tol2 and
+// done belong to the inner FP32 solve and ref_* to the FP64 refinement around
+// it; the FP64 form never sets ref_done.
 struct BatchScalars {
   double rz[2][kMaxS];
   double tol2[kMaxS];
   double alpha[kMaxS];
   double beta[kMaxS];
+  double ref_tol2[kMaxS];
   double resid[17][kMaxS];
   int active[kMaxS];
   int done[kMaxS];
+  int ref_done[kMaxS];
   int fail[kMaxS];
-  int pad[kMaxS];
-  long long iters_total[kMaxS];
-  int slot_iters[kSlots][kMaxS];
+  long long iters_total[kMaxS];   // CG iterations of the step (inner ones in FP32)
+  long long refine_total[kMaxS];  // refinement rounds of the step
+  int slot_iters[kSlots][kMaxS];  // FP64: iterations (-1 budget hit); FP32: largest inner count
+  int slot_rounds[kSlots][kMaxS]; // FP32: refinement rounds (-1: not converged)
+};
+
+// One implicit node solve of the batch.
+struct BSolve {
+  int m = 0;
+  bool pred = false;
+  int slot = 0;
+  int budget = 0;  // CG launches (inner CG launches per round in FP32)
+  int rounds = 0;  // refinement rounds (FP32)
+  double rtol = 0.0, refine_rtol = 0.0, inner_rtol = 0.0;
 };
 
 struct BatchArgs {
@@ -49,7 +64,11 @@ struct BatchArgs {
   double *T[kMaxM + 1] = {};
   double *F[kMaxM + 1] = {};
   double *I[kMaxM + 1] = {};
-  double *r = nullptr, *p = nullptr, *q = nullptr;
+  double *r = nullptr, *p = nullptr, *q = nullptr;  // FP64 form
+  // FP32 form: inner CG vectors and the FP64 refinement residual
+  float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr;
+  double *r64 = nullptr;
+  int fp32 = 0;
   double *partial = nullptr;  // [3][grid][S]
   BatchScalars *sc = nullptr;
   double *Eold = nullptr, *Enew = nullptr;  // [(M+1)(P+1)][n_if][S]
@@ -64,8 +83,7 @@ void blaunch_clear(const BatchArgs &a, hipStream_t st);
 void blaunch_iface_coeffs(const BatchArgs &a, hipStream_t st);
 void blaunch_f_multi(const BatchArgs &a, int j0, int j1, hipStream_t st);
 void blaunch_quad_resid(const BatchArgs &a, int k, hipStream_t st);
-void blaunch_solve(const BatchArgs &a, int m, bool pred, int slot, int budget, double rtol,
-                   hipStream_t st);
+void blaunch_solve(const BatchArgs &a, const BSolve &sv, hipStream_t st);
 void blaunch_iface(const BatchArgs &a, int m, bool corr, hipStream_t st);
 void blaunch_operator_timing(const BatchArgs &a, int m, int reps, hipStream_t st);
 void blaunch_commit(const BatchArgs &a, double dt, hipStream_t st);

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "batch_internal.h"
 
@@ -67,22 +68,37 @@ __device__ inline double readlane_d(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
 }
 
+template <typename T>
+__device__ inline T readlane_t(T v, int l);
+template <>
+__device__ inline double readlane_t<double>(double v, int l) {
+  return readlane_d(v, l);
+}
+template <>
+__device__ inline float readlane_t<float>(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 // multi-RHS row product: K x_s + h_s R x_s for lane s.  The row's entries
 // (at most 64) are fetched with one coalesced load, lane e holding entry e
 // (int16 column offset, K value), and broadcast with readlane, so the gathers
 // of all entries are independent.  R lives in its own CSR over the Robin
 // rows only.  Must be called by the whole wavefront (no divergence): every
 // lane loads its entry; lanes with on == false gather a valid dummy element
-// and their result is to be ignored.
+// and their result is to be ignored.  AT accumulates, VT is the stored value
+// type, XT the vector type (FP64 form: all double; FP32 inner solves: all
+// float; FP64 refinement of an FP32 correction: double, double, float).
 constexpr int kChunk = 16;  // gathers issued before the first is consumed
 
 // sum over entries [0, n) of row of v_e * x[(row + c_e) S + s], entries held
 // one per lane (lanes >= n hold v = 0); chunks of kChunk independent gathers
-__device__ __attribute__((always_inline)) inline double brow_part(int64_t row, int n, int c, double v, int S, int s, bool on,
-                                   const double *__restrict__ x) {
-  double acc = 0.0;
+template <typename AT, typename VT, typename XT>
+__device__ __attribute__((always_inline)) inline AT brow_part(int64_t row, int n, int c, VT v,
+                                                              int S, int s, bool on,
+                                                              const XT *__restrict__ x) {
+  AT acc = 0;
   for (int e0 = 0; e0 < n; e0 += kChunk) {
-    double xv[kChunk];
+    XT xv[kChunk];
 #pragma unroll
     for (int j = 0; j < kChunk; ++j) {
       const int e = e0 + j < 63 ? e0 + j : 63;
@@ -92,43 +108,75 @@ __device__ __attribute__((always_inline)) inline double brow_part(int64_t row, i
 #pragma unroll
     for (int j = 0; j < kChunk; ++j) {
       const int e = e0 + j < 63 ? e0 + j : 63;
-      const double ve = readlane_d(v, e);
+      const VT ve = readlane_t<VT>(v, e);
       // entries past the row end gathered a placeholder value that may be
       // any bit pattern (another scenario's slot): skip them, do not scale
       // them by zero (n is the same for the whole wave)
-      if (e0 + j < n) acc += ve * xv[j];
+      if (e0 + j < n) acc += (AT)ve * (AT)xv[j];
     }
   }
   return acc;
 }
 
-__device__ __attribute__((always_inline)) inline double brow(const BatchOp &op, int64_t row, int S, int s, bool on, double h,
-                              const double *__restrict__ x) {
+template <typename AT, typename VT, typename XT>
+__device__ __attribute__((always_inline)) inline AT brow(const BatchOp &op, const VT *__restrict__ Kv,
+                                                         const VT *__restrict__ Rv, int64_t row,
+                                                         int S, int s, bool on, AT h,
+                                                         const XT *__restrict__ x) {
   const int lane = threadIdx.x & 63;
   const int64_t e0 = op.rowptr[row];
   const int n = (int)(op.rowptr[row + 1] - e0);
   int c = 0;
-  double kv = 0.0;
+  VT kv = 0;
   if (lane < n) {
     c = op.d16[e0 + lane];
-    kv = op.Kv[e0 + lane];
+    kv = Kv[e0 + lane];
   }
-  const double k = brow_part(row, n, c, kv, S, s, on, x);
+  const AT k = brow_part<AT>(row, n, c, kv, S, s, on, x);
   const int rb = op.rrow[row];
   if (rb < 0) return k;
   const int64_t f0 = op.rptr[rb];
   const int nr = (int)(op.rptr[rb + 1] - f0);
   int cr = 0;
-  double rv = 0.0;
+  VT rv = 0;
   if (lane < nr) {
     cr = op.rd16[f0 + lane];
-    rv = op.Rv[f0 + lane];
+    rv = Rv[f0 + lane];
   }
-  return k + h * brow_part(row, nr, cr, rv, S, s, on, x);
+  return k + h * brow_part<AT>(row, nr, cr, rv, S, s, on, x);
 }
 
+// FP64 operator on an FP64 vector
+__device__ __attribute__((always_inline)) inline double brow64(const BatchArgs &a, int64_t row,
+                                                               int s, bool on, double h,
+                                                               const double *__restrict__ x) {
+  return brow<double>(a.op, a.op.Kv, a.op.Rv, row, a.S, s, on, h, x);
+}
+
+// CG vectors and stored operator values of the FP64 (double) or FP32 (float) form
+template <typename V>
+struct BV;
+template <>
+struct BV<double> {
+  __device__ static const double *K(const BatchArgs &a) { return a.op.Kv; }
+  __device__ static const double *R(const BatchArgs &a) { return a.op.Rv; }
+  __device__ static double *x(const BatchArgs &a, int m) { return a.T[m]; }
+  __device__ static double *r(const BatchArgs &a) { return a.r; }
+  __device__ static double *p(const BatchArgs &a) { return a.p; }
+  __device__ static double *q(const BatchArgs &a) { return a.q; }
+};
+template <>
+struct BV<float> {
+  __device__ static const float *K(const BatchArgs &a) { return a.op.Kv32; }
+  __device__ static const float *R(const BatchArgs &a) { return a.op.Rv32; }
+  __device__ static float *x(const BatchArgs &a, int) { return a.x32; }
+  __device__ static float *r(const BatchArgs &a) { return a.r32; }
+  __device__ static float *p(const BatchArgs &a) { return a.p32; }
+  __device__ static float *q(const BatchArgs &a) { return a.q32; }
+};
+
 __device__ inline bool lane_on(const BatchScalars *sc, int s, int S) {
-  return s < S && sc->active[s] && !sc->done[s];
+  return s < S && sc->active[s] && !sc->done[s] && !sc->ref_done[s];
 }
 
 // ---------------------------------------------------------------------------
@@ -141,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void kb_f_multi(BatchArgs a, int j0, int j1
   FOR_ROWS(row, a.N) {
     const double g = h * a.gbase[row];
     for (int j = j0; j <= j1; ++j) {
-      const double L = brow(a.op, row, S, s, on, h, a.T[j]);
+      const double L = brow64(a, row, s, on, h, a.T[j]);
       if (on) a.F[j][row * S + s] = g - L;
     }
   }
@@ -221,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void kb_init(BatchArgs a, int m, double dta
   double *x = a.T[m];
   const double *Tp = a.T[m - 1];
   FOR_ROWS(row, a.N) {
-    const double Lx = PRED ? brow(a.op, row, S, s, on, h, Tp) : 0.0;
+    const double Lx = PRED ? brow64(a, row, s, on, h, Tp) : 0.0;
     if (!on) continue;
     const int64_t i = row * S + s;
     const double mi = a.mass[row], tp = Tp[i], g = h * a.gbase[row];
@@ -245,14 +293,93 @@ __global__ __launch_bounds__(kBlock) void kb_init(BatchArgs a, int m, double dta
   bpublish<3>(v, a.partial, a.grid, S);
 }
 
-// mode 0: init (r.z, r.r, b.b); 1: alpha (p.q); 2: convergence (r.z, r.r).
+// ---- FP64 iterative refinement around FP32 inner solves (per scenario) ----
+// init: b and r64 = b - A x0 in FP64 (corrections without an SpMV, as above);
+// partial r.r, b.b
+template <bool PRED>
+__global__ __launch_bounds__(kBlock) void kb_rinit(BatchArgs a, int m, double dtau) {
+  const int s = threadIdx.x & 63, S = a.S;
+  double v[2] = {0.0, 0.0};
+  const bool on = s < S && a.sc->active[s];
+  const double h = on ? a.h[s] : 0.0;
+  double *x = a.T[m];
+  const double *Tp = a.T[m - 1];
+  FOR_ROWS(row, a.N) {
+    const double Lx = PRED ? brow64(a, row, s, on, h, Tp) : 0.0;
+    if (!on) continue;
+    const int64_t i = row * S + s;
+    const double mi = a.mass[row], tp = Tp[i], g = h * a.gbase[row];
+    double b, r;
+    if (PRED) {
+      b = mi * tp + dtau * g;
+      r = b - (mi * tp + dtau * Lx);
+      x[i] = tp;
+    } else {
+      const double Im = a.I[m][i];
+      b = mi * tp + dtau * (g - a.F[m][i]) + Im;
+      r = mi * (tp - x[i]) + Im;
+    }
+    a.r64[i] = r;
+    v[0] += r * r;
+    v[1] += b * b;
+  }
+  bpublish<2>(v, a.partial, a.grid, S);
+}
+
+// inner init: r32 = r64, d = 0, p = dinv r32; partial r.z, r.r
+__global__ __launch_bounds__(kBlock) void kb_inner_init(BatchArgs a, double dtau) {
+  const int s = threadIdx.x & 63, S = a.S;
+  double v[2] = {0.0, 0.0};
+  if (s < S && a.sc->active[s] && !a.sc->ref_done[s]) {
+    const double h = a.h[s];
+    FOR_ROWS(row, a.N) {
+      const int64_t i = row * S + s;
+      const float r = (float)a.r64[i];
+      const float z = (float)bdinv(a, row, h, dtau) * r;
+      a.r32[i] = r;
+      a.x32[i] = 0.0f;
+      a.p32[i] = z;
+      v[0] += (double)r * (double)z;
+      v[1] += (double)r * (double)r;
+    }
+  }
+  bpublish<2>(v, a.partial, a.grid, S);
+}
+
+// x64 += d; r64 -= A d with the FP64 operator on the FP32 correction d;
+// partial r.r
+__global__ __launch_bounds__(kBlock) void kb_refine_update(BatchArgs a, int m, double dtau) {
+  const int s = threadIdx.x & 63, S = a.S;
+  double v[1] = {0.0};
+  const bool on = s < S && a.sc->active[s] && !a.sc->ref_done[s];
+  const double h = on ? a.h[s] : 0.0;
+  double *x = a.T[m];
+  FOR_ROWS(row, a.N) {
+    const double Ld = brow<double>(a.op, a.op.Kv, a.op.Rv, row, S, s, on, h, a.x32);
+    if (!on) continue;
+    const int64_t i = row * S + s;
+    const double d = (double)a.x32[i];
+    const double Ad = a.mass[row] * d + dtau * Ld;
+    x[i] += d;
+    const double r = a.r64[i] - Ad;
+    a.r64[i] = r;
+    v[0] += r * r;
+  }
+  bpublish<1>(v, a.partial, a.grid, S);
+}
+
+// Per-scenario scalars from the block partials.  Modes:
+//   0 FP64 init (r.z, r.r, b.b)      1 alpha (p.q)
+//   2 FP64 convergence (r.z, r.r)    3 refinement init (r.r, b.b)
+//   4 inner init (r.z, r.r)          5 refinement check (r.r), it = round
+//   6 inner convergence (r.z, r.r)
 // Fixed-order sums: wave w adds blocks w, w+16, ..., then wave 0 adds the waves.
 __global__ __launch_bounds__(64 * kRedWaves) void kb_reduce(BatchArgs a, int mode, int it,
                                                             int last, int slot, double rtol) {
   __shared__ double sh[3][kRedWaves][64];
   const int s = threadIdx.x & 63, w = threadIdx.x >> 6;
   BatchScalars *sc = a.sc;
-  const int nk = mode == 0 ? 3 : (mode == 1 ? 1 : 2);
+  const int nk = mode == 0 ? 3 : ((mode == 1 || mode == 5) ? 1 : 2);
   for (int k = 0; k < nk; ++k) {
     double acc = 0.0;
     if (s < a.S)
@@ -273,69 +400,115 @@ __global__ __launch_bounds__(64 * kRedWaves) void kb_reduce(BatchArgs a, int mod
     if (sc->done[s]) sc->slot_iters[slot][s] = 0;
     return;
   }
+  if (mode == 3) {
+    sc->ref_tol2[s] = rtol * rtol * o[1];
+    sc->ref_done[s] = (o[0] <= sc->ref_tol2[s]) ? 1 : 0;
+    sc->done[s] = 0;
+    if (sc->ref_done[s]) sc->slot_rounds[slot][s] = 0;
+    return;
+  }
+  if (sc->ref_done[s]) return;
+  if (mode == 4) {
+    sc->rz[0][s] = o[0];
+    sc->tol2[s] = rtol * rtol * o[1];  // relative to the inner right-hand side
+    sc->done[s] = (o[1] == 0.0) ? 1 : 0;
+    return;
+  }
+  if (mode == 5) {
+    sc->refine_total[s] += 1;
+    if (o[0] <= sc->ref_tol2[s]) {
+      sc->ref_done[s] = 1;
+      sc->slot_rounds[slot][s] = it + 1;
+    } else if (last) {
+      sc->slot_rounds[slot][s] = -1;
+      sc->fail[s] = 1;
+    }
+    return;
+  }
   if (sc->done[s]) return;
   if (mode == 1) {
     sc->alpha[s] = sc->rz[it & 1][s] / o[0];
     return;
   }
+  const bool inner = mode == 6;
   if (o[1] <= sc->tol2[s]) {
     sc->done[s] = 1;
-    sc->slot_iters[slot][s] = it + 1;
     sc->iters_total[s] += it + 1;
+    if (!inner) sc->slot_iters[slot][s] = it + 1;
+    else if (sc->slot_iters[slot][s] >= 0 && it + 1 > sc->slot_iters[slot][s])
+      sc->slot_iters[slot][s] = it + 1;
     return;
   }
   sc->beta[s] = o[0] / sc->rz[it & 1][s];
   sc->rz[(it + 1) & 1][s] = o[0];
   if (last) {
+    // budget exhausted: an FP64 solve failed; an inner solve only signals it
     sc->slot_iters[slot][s] = -1;
-    sc->fail[s] = 1;
+    sc->iters_total[s] += it + 1;
+    if (!inner) sc->fail[s] = 1;
   }
 }
 
-// TIMING: stand-alone timing launches that ignore the convergence flags
-template <int TIMING>
+// (a) q = diag(m) p + dtau (K + h R) p, partial p.q.  V = double: the FP64
+// form; V = float: the inner solves of the FP32 form (FP32 values, vectors,
+// products and row sums; dot products summed in FP64).  TIMING: stand-alone
+// timing launches that ignore the convergence flags.
+template <int TIMING, typename V>
 __global__ __launch_bounds__(kBlock) void kb_pcg_a(BatchArgs a, int m, double dtau) {
   const int s = threadIdx.x & 63, S = a.S;
   double v[1] = {0.0};
   const bool on = TIMING ? s < S : lane_on(a.sc, s, S);
-  const double h = on ? a.h[s] : 0.0;
+  const V h = on ? (V)a.h[s] : (V)0;
+  const V dt = (V)dtau;
+  const V *p = BV<V>::p(a);
+  V *q = BV<V>::q(a);
   FOR_ROWS(row, a.N) {
-    const double Lp = brow(a.op, row, S, s, on, h, a.p);
+    const V Lp = brow<V>(a.op, BV<V>::K(a), BV<V>::R(a), row, S, s, on, h, p);
     if (!on) continue;
     const int64_t i = row * S + s;
-    const double pi = a.p[i];
-    const double qi = a.mass[row] * pi + dtau * Lp;
-    a.q[i] = qi;
-    v[0] += pi * qi;
+    const V pi = p[i];
+    const V qi = (V)a.mass[row] * pi + dt * Lp;
+    q[i] = qi;
+    v[0] += (double)pi * (double)qi;
   }
   bpublish<1>(v, a.partial, a.grid, S);
 }
 
+// (b) x += alpha p; r -= alpha q; partial r.z, r.r
+template <typename V>
 __global__ __launch_bounds__(kBlock) void kb_pcg_b(BatchArgs a, int m, double dtau) {
   const int s = threadIdx.x & 63, S = a.S;
   double v[2] = {0.0, 0.0};
   if (lane_on(a.sc, s, S)) {
-    const double h = a.h[s], alpha = a.sc->alpha[s];
-    double *x = a.T[m];
+    const double h = a.h[s];
+    const V alpha = (V)a.sc->alpha[s];
+    V *x = BV<V>::x(a, m), *rv = BV<V>::r(a);
+    const V *p = BV<V>::p(a), *q = BV<V>::q(a);
     FOR_ROWS(row, a.N) {
       const int64_t i = row * S + s;
-      x[i] += alpha * a.p[i];
-      const double r = a.r[i] - alpha * a.q[i];
-      a.r[i] = r;
-      v[0] += r * (bdinv(a, row, h, dtau) * r);
-      v[1] += r * r;
+      x[i] += alpha * p[i];
+      const V r = rv[i] - alpha * q[i];
+      rv[i] = r;
+      const V z = (V)bdinv(a, row, h, dtau) * r;
+      v[0] += (double)r * (double)z;
+      v[1] += (double)r * (double)r;
     }
   }
   bpublish<2>(v, a.partial, a.grid, S);
 }
 
+// (c) p = z + beta p
+template <typename V>
 __global__ __launch_bounds__(kBlock) void kb_pcg_c(BatchArgs a, double dtau) {
   const int s = threadIdx.x & 63, S = a.S;
   if (!lane_on(a.sc, s, S)) return;
-  const double h = a.h[s], beta = a.sc->beta[s];
+  const double h = a.h[s];
+  const V beta = (V)a.sc->beta[s];
+  V *p = BV<V>::p(a);
+  const V *rv = BV<V>::r(a);
   FOR_ROWS(row, a.N) {
     const int64_t i = row * S + s;
-    a.p[i] = bdinv(a, row, h, dtau) * a.r[i] + beta * a.p[i];
+    p[i] = (V)bdinv(a, row, h, dtau) * rv[i] + beta * p[i];
   }
 }
 
@@ -551,8 +724,13 @@ __global__ void kb_clear(BatchArgs a) {
   const int s = threadIdx.x;
   if (s >= a.S) return;
   sc->fail[s] = 0;
+  sc->iters_total[s] = 0;
+  sc->refine_total[s] = 0;
   for (int k = 0; k < 17; ++k) sc->resid[k][s] = 0.0;
-  for (int i = 0; i < kSlots; ++i) sc->slot_iters[i][s] = 0;
+  for (int i = 0; i < kSlots; ++i) {
+    sc->slot_iters[i][s] = 0;
+    sc->slot_rounds[i][s] = 0;
+  }
 }
 
 // commit T_n <- T_M and t_n += dt for the active scenarios, unless any failed
@@ -599,23 +777,48 @@ void blaunch_quad_resid(const BatchArgs &a, int k, hipStream_t st) {
   kb_resid_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, k);
 }
 
-void blaunch_solve(const BatchArgs &a, int m, bool pred, int slot, int budget, double rtol,
-                   hipStream_t st) {
-  const double dtau = a.dtau_h[m];
-  if (pred) kb_init<true><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
-  else kb_init<false><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
-  kb_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, 0, 0, 0, slot, rtol);
+template <typename V>
+static void cg_iterations(const BatchArgs &a, int m, double dtau, int slot, int budget,
+                          double rtol, hipStream_t st) {
+  const int conv = std::is_same<V, float>::value ? 6 : 2;
   for (int it = 0; it < budget; ++it) {
-    kb_pcg_a<0><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
+    kb_pcg_a<0, V><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
     kb_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, 1, it, 0, slot, rtol);
-    kb_pcg_b<<<a.grid, kBlock, 0, st>>>(a, m, dtau);
-    kb_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, 2, it, it == budget - 1, slot, rtol);
-    kb_pcg_c<<<a.grid, kBlock, 0, st>>>(a, dtau);
+    kb_pcg_b<V><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
+    kb_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, conv, it, it == budget - 1, slot, rtol);
+    kb_pcg_c<V><<<a.grid, kBlock, 0, st>>>(a, dtau);
+  }
+}
+
+void blaunch_solve(const BatchArgs &a, const BSolve &sv, hipStream_t st) {
+  const int m = sv.m;
+  const double dtau = a.dtau_h[m];
+  if (!a.fp32) {
+    if (sv.pred) kb_init<true><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
+    else kb_init<false><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
+    kb_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, 0, 0, 0, sv.slot, sv.rtol);
+    cg_iterations<double>(a, m, dtau, sv.slot, sv.budget, sv.rtol, st);
+    return;
+  }
+  // FP32 inner solves inside FP64 refinement rounds
+  if (sv.pred) kb_rinit<true><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
+  else kb_rinit<false><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
+  kb_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, 3, 0, 0, sv.slot, sv.refine_rtol);
+  for (int r = 0; r < sv.rounds; ++r) {
+    kb_inner_init<<<a.grid, kBlock, 0, st>>>(a, dtau);
+    kb_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, 4, 0, 0, sv.slot, sv.inner_rtol);
+    cg_iterations<float>(a, m, dtau, sv.slot, sv.budget, sv.inner_rtol, st);
+    kb_refine_update<<<a.grid, kBlock, 0, st>>>(a, m, dtau);
+    kb_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, 5, r, r == sv.rounds - 1, sv.slot,
+                                            sv.refine_rtol);
   }
 }
 
 void blaunch_operator_timing(const BatchArgs &a, int m, int reps, hipStream_t st) {
-  for (int i = 0; i < reps; ++i) kb_pcg_a<1><<<a.grid, kBlock, 0, st>>>(a, m, a.dtau_h[m]);
+  for (int i = 0; i < reps; ++i) {
+    if (a.fp32) kb_pcg_a<1, float><<<a.grid, kBlock, 0, st>>>(a, m, a.dtau_h[m]);
+    else kb_pcg_a<1, double><<<a.grid, kBlock, 0, st>>>(a, m, a.dtau_h[m]);
+  }
 }
 
 void blaunch_iface(const BatchArgs &a, int m, bool corr, hipStream_t st) {

@@ -117,7 +117,8 @@ def test_ensemble_7p5mm_sampled():
         assert e <= 1e-10
 
 
-def test_blown_up_member_does_not_leak_into_others():
+@pytest.mark.parametrize("precision", [0, 1])
+def test_blown_up_member_does_not_leak_into_others(precision):
     """A member whose state overflows makes the step fail (ENOCONV, nothing
     committed); once it is switched off, its non-finite CG vectors must not
     reach the other members (rows shorter than the gather chunk read a
@@ -127,7 +128,8 @@ def test_blown_up_member_does_not_leak_into_others():
     mem = members_for(pb, 3, seed0=1200)
     sign = np.where(np.arange(pb.N) % 2 == 0, 1.0, -1.0)
     mem[0] = dict(mem[0], T0=1e308 * sign)
-    ctx = m.batch_simulation(pb, mem)
+    over = dict(precision=precision, pcg_maxit=60, refine_maxit=4)
+    ctx = m.batch_simulation(pb, mem, **over)
     with pytest.raises(m.MrsdcError) as e:
         ctx.advance_steps(1)
     assert e.value.status == m.ENOCONV
@@ -139,6 +141,62 @@ def test_blown_up_member_does_not_leak_into_others():
     outs = [ctx.get_scenario_temperature(s, pb.N) for s in (1, 2)]
     ctx.destroy()
     for s, got in zip((1, 2), outs):
-        alone, _, _ = run_batch(pb, [mem[s]], 2)
+        alone, _, _ = run_batch(pb, [mem[s]], 2, **over)
         assert np.all(np.isfinite(got))
         assert np.array_equal(alone[0], got), s
+
+
+# ---------------------------------------------------------------------------
+# FP32 inner solves + FP64 refinement, batched: <= 1e-7 relative L2 against
+# the FP64 oracle run with each member's parameters.
+# ---------------------------------------------------------------------------
+TOL32 = 1e-7
+
+
+@pytest.mark.parametrize("S", [3, 64])
+def test_batch_fp32_refine_members_match_oracle(S):
+    pb = small_machine()
+    mem = members_for(pb, S, seed0=1400)
+    outs, st, _ = run_batch(pb, mem, pb.nsteps, precision=1)
+    print(f"  S={S} inner iterations {st['pcg_iters']} refinements {st['refine_steps']}",
+          flush=True)
+    assert st["refine_steps"] > 0
+    check = range(S) if S <= 4 else [0, 21, 63]
+    for s in check:
+        mb = mem[s]
+        ref, _ = oracle.run(pb, T0=mb["T0"], h=mb["h"], alpha=mb["alpha"],
+                            friction_W=mb["friction_W"], period=mb["period"])
+        e = rel(outs[s], ref)
+        print(f"  S={S} member {s}: rel_l2={e:.3e}", flush=True)
+        assert e <= TOL32
+
+
+def test_batch_fp32_member_alone_equals_member_in_batch():
+    pb = small_machine()
+    mem = members_for(pb, 6, seed0=1500)
+    outs, _, _ = run_batch(pb, mem, 2, precision=1)
+    for s in (0, 4):
+        alone, _, _ = run_batch(pb, [mem[s]], 2, precision=1)
+        assert np.array_equal(alone[0], outs[s])
+
+
+def test_ensemble_7p5mm_fp32_refine_sampled():
+    """The 64-member 7.5 mm ensemble in the FP32 + refinement form, 2 steps;
+    2 members checked against the FP64 oracle."""
+    pb = mi.ensemble_member(0, nsteps=2, precision=mi.FP32_REFINE)
+    mem = []
+    for s in range(64):
+        q = mi.scenario_params(s)
+        rng = q[4]
+        mem.append(dict(h=q[0], alpha=q[1], friction_W=q[2], period=q[3],
+                        T0=20.0 + rng.uniform(-0.5, 0.5, size=pb.N)))
+    outs, st, _ = run_batch(pb, mem, 2)
+    print(f"  inner iterations {st['pcg_iters']} refinements {st['refine_steps']}", flush=True)
+    assert st["refine_steps"] > 0
+    for s in (5, 63):
+        mb = mem[s]
+        ref, _ = oracle.run(pb, nsteps=2, T0=mb["T0"], h=mb["h"], alpha=mb["alpha"],
+                            friction_W=mb["friction_W"], period=mb["period"])
+        e = rel(outs[s], ref)
+        print(f"  member {s}: rel_l2={e:.3e}", flush=True)
+        assert e <= TOL32
