@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--profile", action="store_true",
                     help="event timing of kernel classes inside the timed region (adds overhead)")
     ap.add_argument("--op-reps", type=int, default=200, help="operator timing launches")
+    ap.add_argument("--ensemble-precision", type=int, default=1, choices=[0, 1],
+                    help="form of the stand-alone ensemble run: 0 FP64, 1 FP32+refine")
     ap.add_argument("--ensemble-steps", type=int, default=6,
                     help="macro-steps of the 64-member 7.5 mm ensemble (0: skip)")
     ap.add_argument("--precision-steps", type=int, default=24,
@@ -96,7 +98,7 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU"
     if args.config == "ensemble":
-        print(json.dumps(ensemble(pkg, args)), flush=True)
+        print(json.dumps(ensemble(pkg, args, args.ensemble_precision)), flush=True)
         return
     if args.config == "serve":
         print(json.dumps(serving(pkg, args)), flush=True)

@@ -101,7 +101,9 @@ def box(L, nodes, k: float, rho_c: float, robin_faces=()) -> Body:
     n = nx * ny * nz
 
     tri = [sp.diags([np.ones(m - 1), np.ones(m), np.ones(m - 1)], [-1, 0, 1]) for m in (nx, ny, nz)]
-    P = sp.kron(tri[2], sp.kron(tri[1], tri[0])).tocsr()
+    # CSR throughout: scipy's default block (BSR) path for small factors would
+    # store explicit zeros beyond the 27-point pattern
+    P = sp.kron(tri[2], sp.kron(tri[1], tri[0], format="csr"), format="csr")
     P.sort_indices()
     rowptr = P.indptr.astype(np.int64)
     col = P.indices.astype(np.int32)

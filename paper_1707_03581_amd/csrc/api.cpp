@@ -245,46 +245,104 @@ mrsdc_status band_coeffs(mrsdc_ctx *c, const std::vector<double> &x, const std::
 // Batched contexts: shared operators in row-major form (one row per
 // wavefront), per-scenario parameters, and the argument block of the batch
 // kernels over the scenario-interleaved vectors allocated by prepare().
+// Tiles for the LDS-staged operator: the largest TR (rows per tile) whose
+// every tile has at most kStageSlots distinct columns over its entries (K
+// and R).  The tiling depends on the mesh only (not on S or precision), so a
+// scenario's arithmetic is the same in any batch.  col: global column of
+// every merged entry.
+mrsdc_status build_stage_tiles(mrsdc_ctx *c, int64_t N, const std::vector<int64_t> &rowptr,
+                               const std::vector<int64_t> &col, BatchArgs &a) {
+  static const int kTry[] = {32, 24, 16, 12, 10, 8, 6, 4, 3, 2, 1};  // at most 4 kMaxR rows
+  std::vector<int64_t> cols;
+  std::vector<int> nslots, slot_row;
+  std::vector<int> slot(col.size());
+  std::vector<uint16_t> oslot(N);
+  for (int TR : kTry) {
+    const int64_t T = (N + TR - 1) / TR;
+    nslots.assign(T, 0);
+    slot_row.assign((size_t)T * kStageSlots, 0);
+    bool fits = true;
+    for (int64_t t = 0; t < T && fits; ++t) {
+      const int64_t e0 = rowptr[t * TR], e1 = rowptr[std::min<int64_t>(N, (t + 1) * TR)];
+      if (e1 - e0 > kMaxTileEntries) {
+        fits = false;
+        break;
+      }
+      cols.assign(col.begin() + e0, col.begin() + e1);
+      std::sort(cols.begin(), cols.end());
+      cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+      if ((int64_t)cols.size() > kStageSlots) {
+        fits = false;
+        break;
+      }
+      nslots[t] = (int)cols.size();
+      for (size_t k = 0; k < cols.size(); ++k) slot_row[(size_t)t * kStageSlots + k] = (int)cols[k];
+      for (int64_t e = e0; e < e1; ++e)
+        slot[e] = (int)(std::lower_bound(cols.begin(), cols.end(), col[e]) - cols.begin());
+      for (int64_t r = t * TR; r < std::min<int64_t>(N, (t + 1) * TR); ++r) {
+        const auto it = std::lower_bound(cols.begin(), cols.end(), r);
+        if (it == cols.end() || *it != r)
+          return fail(c, MRSDC_EINVAL, "row %lld has no diagonal entry", (long long)r);
+        oslot[r] = (uint16_t)(it - cols.begin());
+      }
+    }
+    if (!fits) continue;
+    mrsdc_status st;
+    int *pi;
+    uint16_t *pu;
+    if ((st = upload(c, &pi, nslots))) return st;
+    a.op.nslots = pi;
+    if ((st = upload(c, &pi, slot_row))) return st;
+    a.op.slot_row = pi;
+    if ((st = upload(c, &pi, slot))) return st;
+    a.op.slot32 = pi;
+    if ((st = upload(c, &pu, oslot))) return st;
+    a.op.oslot = pu;
+    a.op.TR = TR;
+    a.op.ntiles = (int)T;
+    // every workgroup resident: two FP64 or three FP32 staging buffers per CU
+    // on 256 CUs
+    a.sgrid64 = (int)std::min<int64_t>((T + 7) / 8 * 8, 512);
+    a.sgrid32 = (int)std::min<int64_t>((T + 7) / 8 * 8, 768);
+    return MRSDC_OK;
+  }
+  return fail(c, MRSDC_EINVAL, "a row block exceeds the staging capacity of %d columns", kStageSlots);
+}
+
 mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
   DevState &d = c->d;
   const int S = c->S;
   mrsdc_status st;
-  // K as int16 column offsets; R only over the rows that carry a Robin term
-  std::vector<int64_t> rowptr(N + 1, 0), rptr(1, 0);
-  std::vector<int16_t> d16, rd16;
-  std::vector<int> rrow(N, -1);
-  std::vector<double> Kv, Rv, Kd(N, 0.0), Rd(N, 0.0), gbase(N, 0.0);
+  // merged rows: the row's K entries, then its nonzero R entries (nk[row] = K
+  // count); columns stay on the host (the device addresses staged slots)
+  std::vector<int64_t> rowptr(N + 1, 0), col;
+  std::vector<int> nk(N, 0);
+  std::vector<double> val, Kd(N, 0.0), Rd(N, 0.0), gbase(N, 0.0);
   for (int b = 0; b < c->nbody; ++b) {
     const HostBody &B = c->body[b];
     for (int64_t i = 0; i < B.n; ++i) {
-      const int64_t row = c->off[b] + i;
+      const int64_t row = c->off[b] + i, base = c->off[b];
       gbase[row] = B.Tenv * (B.rload.empty() ? 0.0 : B.rload[i]);
-      bool any_r = false;
       for (int64_t e = B.rowptr[i]; e < B.rowptr[i + 1]; ++e) {
-        const int64_t delta = (int64_t)B.col[e] - i;
-        if (delta < -32768 || delta > 32767)
-          return fail(c, MRSDC_EINVAL, "batched contexts need |column - row| < 32768");
-        const double kv = B.K[e], rv = B.R.empty() ? 0.0 : B.R[e];
-        d16.push_back((int16_t)delta);
-        Kv.push_back(kv);
-        any_r |= rv != 0.0;
         if (B.col[e] == i) {
-          Kd[row] += kv;
-          Rd[row] += rv;
+          Kd[row] += B.K[e];
+          if (!B.R.empty()) Rd[row] += B.R[e];
+        } else if (B.K[e] == 0.0) {
+          continue;  // stored zero (e.g. face neighbours on cubic cells): no arithmetic
         }
+        col.push_back(base + B.col[e]);
+        val.push_back(B.K[e]);
       }
-      rowptr[row + 1] = (int64_t)d16.size();
-      if (rowptr[row + 1] - rowptr[row] > 64)
-        return fail(c, MRSDC_EINVAL, "batched contexts need rows of at most 64 entries");
-      if (any_r) {
-        rrow[row] = (int)(rptr.size() - 1);
+      nk[row] = (int)(col.size() - rowptr[row]);
+      if (!B.R.empty())
         for (int64_t e = B.rowptr[i]; e < B.rowptr[i + 1]; ++e) {
           if (B.R[e] == 0.0) continue;
-          rd16.push_back((int16_t)((int64_t)B.col[e] - i));
-          Rv.push_back(B.R[e]);
+          col.push_back(base + B.col[e]);
+          val.push_back(B.R[e]);
         }
-        rptr.push_back((int64_t)rd16.size());
-      }
+      rowptr[row + 1] = (int64_t)col.size();
+      if (rowptr[row + 1] - rowptr[row] > 64)
+        return fail(c, MRSDC_EINVAL, "batched contexts need at most 64 K and R entries per row");
     }
   }
   BatchArgs &a = c->ba;
@@ -297,24 +355,16 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
   a.grid = (int)std::min<int64_t>(((N + 3) / 4 + 7) / 8 * 8, 1024);
   for (int m = 0; m <= c->cfg.M; ++m) a.dtau_h[m] = c->w.dtau[m];
   int64_t *prp;
-  int16_t *pd;
   int *pi;
   double *pv;
   if ((st = upload(c, &prp, rowptr))) return st;
   a.op.rowptr = prp;
-  if ((st = upload(c, &pd, d16))) return st;
-  a.op.d16 = pd;
-  if ((st = upload(c, &pv, Kv))) return st;
-  a.op.Kv = pv;
-  if ((st = upload(c, &pi, rrow))) return st;
-  a.op.rrow = pi;
-  if ((st = upload(c, &prp, rptr))) return st;
-  a.op.rptr = prp;
-  if ((st = upload(c, &pd, rd16))) return st;
-  a.op.rd16 = pd;
-  if ((st = upload(c, &pv, Rv))) return st;
-  a.op.Rv = pv;
+  if ((st = upload(c, &pi, nk))) return st;
+  a.op.nk = pi;
+  if ((st = upload(c, &pv, val))) return st;
+  a.op.val = pv;
   a.op.N = N;
+  if ((st = build_stage_tiles(c, N, rowptr, col, a))) return st;
   if ((st = upload(c, &pv, Kd))) return st;
   a.Kd = pv;
   if ((st = upload(c, &pv, Rd))) return st;
@@ -346,7 +396,9 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
   if ((st = dalloc(c, &a.sc, 1))) return st;
   HIPCHK(hipMemset(a.sc, 0, sizeof(BatchScalars)));
   HIPCHK(hipMemcpy(a.sc->active, act.data(), sizeof(int) * S, hipMemcpyHostToDevice));
-  if ((st = dalloc(c, &a.partial, 3 * (size_t)a.grid * S))) return st;
+  if ((st = dalloc(c, &a.partial,
+                   3 * (size_t)std::max(a.grid, std::max(a.sgrid64, a.sgrid32)) * S)))
+    return st;
   if ((st = dalloc(c, &c->stage, N))) return st;
   a.w = d.w;
   a.ifpos = d.ifc.kind ? d.ifpos : nullptr;
@@ -364,12 +416,10 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
     // FP32 copies of the shared operator values for the inner solves; FP32
     // inner vectors and the FP64 refinement residual, scenario-interleaved
     a.fp32 = 1;
-    std::vector<float> k32(Kv.begin(), Kv.end()), r32(Rv.begin(), Rv.end());
+    std::vector<float> v32(val.begin(), val.end());
     float *pf32;
-    if ((st = upload(c, &pf32, k32))) return st;
-    a.op.Kv32 = pf32;
-    if ((st = upload(c, &pf32, r32))) return st;
-    a.op.Rv32 = pf32;
+    if ((st = upload(c, &pf32, v32))) return st;
+    a.op.val32 = pf32;
     const size_t NS = (size_t)N * S;
     if ((st = dalloc(c, &a.x32, NS)) || (st = dalloc(c, &a.r32, NS)) ||
         (st = dalloc(c, &a.p32, NS)) || (st = dalloc(c, &a.q32, NS)) ||

@@ -6,19 +6,30 @@ namespace mrsdc {
 
 constexpr int kMaxS = 64;  // scenarios per batch = lanes of a wavefront
 
-// Shared operators of the batch in row-major form: one row per wavefront, the
-// row's entries are wave-uniform.
+// Shared operators of the batch, row-major: each row lists its K entries and
+// then its nonzero R entries (the Robin rows), at most 64 in all, so one
+// coalesced load fetches a row.  Entries address LDS-staged rows: tiles of TR
+// consecutive rows; the union of the columns of a tile's rows is copied into
+// at most kStageSlots LDS rows; slot_row[t][sl] = global row staged in slot
+// sl of tile t, slot[e] = slot of entry e's column within its row's tile.
 struct BatchOp {
   int64_t N = 0;
-  const int64_t *rowptr = nullptr;  // K: [N+1]
-  const int16_t *d16 = nullptr;     // column - row
-  const double *Kv = nullptr;
-  const int *rrow = nullptr;        // [N] index into rptr, -1 for rows without R entries
-  const int64_t *rptr = nullptr;    // R over the Robin rows only
-  const int16_t *rd16 = nullptr;
-  const double *Rv = nullptr;
-  const float *Kv32 = nullptr, *Rv32 = nullptr;
+  const int64_t *rowptr = nullptr;  // [N+1] over the merged entries
+  const int *nk = nullptr;          // [N] K entries of the row (the rest are R)
+  const double *val = nullptr;      // entry values
+  const float *val32 = nullptr;     // FP32 copy (FP32 form)
+  const int *slot32 = nullptr;      // entry -> LDS slot within the row's tile
+  const uint16_t *oslot = nullptr;  // [N] slot of the row itself within its tile
+  int TR = 0, ntiles = 0;
+  const int *nslots = nullptr;    // [ntiles]
+  const int *slot_row = nullptr;  // [ntiles][kStageSlots]
 };
+
+// Staging buffer of the tiled kernels: 64 KB per workgroup (two workgroups
+// fit in one CU's LDS), rows of up to 64 FP64 scenario values.
+constexpr int kStageBytes = 65536;
+constexpr int kStageSlots = (kStageBytes / 8 - 64) / 64;  // 127, with a 64-value tail
+constexpr int kMaxTileEntries = 1024;                      // matrix entries of a tile
 
 // Per-scenario solver scalars (index s fastest).  In the FP32 form, tol2 and
 // done belong to the inner FP32 solve and ref_* to the FP64 refinement around
@@ -52,6 +63,7 @@ struct BSolve {
 
 struct BatchArgs {
   int S = 0, M = 0, P = 0, grid = 0;
+  int sgrid64 = 0, sgrid32 = 0;  // workgroups of the tiled kernels (FP64 / FP32 staging)
   int64_t N = 0;
   double dtau_h[kMaxM + 1] = {};
   BatchOp op;
@@ -69,7 +81,7 @@ struct BatchArgs {
   float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr;
   double *r64 = nullptr;
   int fp32 = 0;
-  double *partial = nullptr;  // [3][grid][S]
+  double *partial = nullptr;  // [3][max(grid, sgrid64, sgrid32)][S]
   BatchScalars *sc = nullptr;
   double *Eold = nullptr, *Enew = nullptr;  // [(M+1)(P+1)][n_if][S]
   double *Tbuf[2] = {};                     // [n_if][S]

@@ -44,6 +44,23 @@ __device__ inline RowRange xcd_rows(int64_t N) {
   for (RowRange rr_ = xcd_rows(N); rr_.row < rr_.end; rr_.row += rr_.stride) \
     if (const int64_t row = rr_.row; true)
 
+// Tiles of the LDS-staged kernels, dealt the same way: XCD x walks the
+// contiguous tiles [x T/8, (x+1) T/8), its workgroups side by side.
+struct TileRange {
+  int t, end, stride;
+};
+__device__ inline TileRange xcd_tiles(int T) {
+  const int xcd = blockIdx.x % kXcd, local = blockIdx.x / kXcd, per = gridDim.x / kXcd;
+  TileRange r;
+  r.t = (int)((int64_t)T * xcd / kXcd) + local;
+  r.end = (int)((int64_t)T * (xcd + 1) / kXcd);
+  r.stride = per;
+  return r;
+}
+#define FOR_TILES(t, T)                                                        \
+  for (TileRange tr_ = xcd_tiles(T); tr_.t < tr_.end; tr_.t += tr_.stride) \
+    if (const int t = tr_.t; true)
+
 // sum the per-wave (per-lane = per-scenario) values of the block into
 // partial[k][blk][s]
 template <int K>
@@ -79,78 +96,214 @@ __device__ inline float readlane_t<float>(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-// multi-RHS row product: K x_s + h_s R x_s for lane s.  The row's entries
-// (at most 64) are fetched with one coalesced load, lane e holding entry e
-// (int16 column offset, K value), and broadcast with readlane, so the gathers
-// of all entries are independent.  R lives in its own CSR over the Robin
-// rows only.  Must be called by the whole wavefront (no divergence): every
-// lane loads its entry; lanes with on == false gather a valid dummy element
-// and their result is to be ignored.  AT accumulates, VT is the stored value
-// type, XT the vector type (FP64 form: all double; FP32 inner solves: all
-// float; FP64 refinement of an FP32 correction: double, double, float).
-constexpr int kChunk = 16;  // gathers issued before the first is consumed
+// ---------------------------------------------------------------------------
+// LDS-staged multi-RHS operator.  A workgroup takes one tile (TR consecutive
+// rows) at a time: it copies the rows of x its tile reads (the union of the
+// tile's columns, at most kStageSlots rows of S values) and the tile's matrix
+// entries (LDS slot, value) into LDS with direct global-to-LDS loads, then
+// forms the rows from LDS.  The union of a hexahedral tile is about nine
+// short runs of rows, so each x row is read from L2 about nine times per
+// product instead of once per matrix entry.
+//
+// Lane mapping ("rows per wavefront"): a lane owns VEC consecutive scenarios
+// (one 16-byte LDS read: 4 FP32 or 2 FP64 staged values), LPR = 64 / VEC
+// lanes cover 64 scenarios of a row, so a wave forms RPW = VEC rows at once,
+// each lane walking its own row's entries (no cross-lane broadcast).  The
+// mapping does not depend on S, so neither does any summation order.
+// ---------------------------------------------------------------------------
+constexpr int kMaxR = 8;  // tiles hold at most 4 kMaxR rows
 
-// sum over entries [0, n) of row of v_e * x[(row + c_e) S + s], entries held
-// one per lane (lanes >= n hold v = 0); chunks of kChunk independent gathers
-template <typename AT, typename VT, typename XT>
-__device__ __attribute__((always_inline)) inline AT brow_part(int64_t row, int n, int c, VT v,
-                                                              int S, int s, bool on,
-                                                              const XT *__restrict__ x) {
-  AT acc = 0;
-  for (int e0 = 0; e0 < n; e0 += kChunk) {
-    XT xv[kChunk];
-#pragma unroll
-    for (int j = 0; j < kChunk; ++j) {
-      const int e = e0 + j < 63 ? e0 + j : 63;
-      const int ce = __builtin_amdgcn_readlane(c, e);
-      xv[j] = x[(on && e0 + j < n) ? (row + ce) * S + s : 0];
-    }
-#pragma unroll
-    for (int j = 0; j < kChunk; ++j) {
-      const int e = e0 + j < 63 ? e0 + j : 63;
-      const VT ve = readlane_t<VT>(v, e);
-      // entries past the row end gathered a placeholder value that may be
-      // any bit pattern (another scenario's slot): skip them, do not scale
-      // them by zero (n is the same for the whole wave)
-      if (e0 + j < n) acc += (AT)ve * (AT)xv[j];
-    }
-  }
-  return acc;
-}
+template <typename XT>
+struct Lanes {
+  static constexpr int VEC = 16 / (int)sizeof(XT);
+  static constexpr int LPR = 64 / VEC;
+  static constexpr int RPW = VEC;
+  // wave iterations per tile: tiles hold at most 4 kMaxR rows
+  static constexpr int NI = (4 * kMaxR + 4 * RPW - 1) / (4 * RPW);
+};
 
-template <typename AT, typename VT, typename XT>
-__device__ __attribute__((always_inline)) inline AT brow(const BatchOp &op, const VT *__restrict__ Kv,
-                                                         const VT *__restrict__ Rv, int64_t row,
-                                                         int S, int s, bool on, AT h,
-                                                         const XT *__restrict__ x) {
+constexpr int kMaxEnt = kMaxTileEntries;
+
+// LDS of a tiled kernel: staged x rows (+ a 64-value tail), the tile's
+// entries (+ tail) and its slot rows
+template <typename XT, typename VT>
+struct StageLds {
+  XT x[(kStageSlots + 1) * 64];
+  int eslot[kMaxEnt + 64];
+  VT eval[kMaxEnt + 64];
+  int ssl[kStageSlots + 1];
+};
+
+// direct global-to-LDS copy of n contiguous 4-byte units; wave w moves units
+// [base, base + 64) for base = 64 w, 64 w + 256, ...; lanes past the end
+// repeat a valid unit into the tail
+__device__ __attribute__((always_inline)) inline void dma_contig(const void *src, void *dst,
+                                                                 int n) {
   const int lane = threadIdx.x & 63;
-  const int64_t e0 = op.rowptr[row];
-  const int n = (int)(op.rowptr[row + 1] - e0);
-  int c = 0;
-  VT kv = 0;
-  if (lane < n) {
-    c = op.d16[e0 + lane];
-    kv = Kv[e0 + lane];
+  const char *sb = reinterpret_cast<const char *>(src);
+  char *db = reinterpret_cast<char *>(dst);
+  for (int base = (threadIdx.x >> 6) * 64; base < n; base += kBlock) {
+    const int u = base + lane < n ? base + lane : base;
+    __builtin_amdgcn_global_load_lds((const void *)(sb + (size_t)u * 4),
+                                     (__attribute__((address_space(3))) void *)(db + (size_t)base * 4),
+                                     4, 0, 0);
   }
-  const AT k = brow_part<AT>(row, n, c, kv, S, s, on, x);
-  const int rb = op.rrow[row];
-  if (rb < 0) return k;
-  const int64_t f0 = op.rptr[rb];
-  const int nr = (int)(op.rptr[rb + 1] - f0);
-  int cr = 0;
-  VT rv = 0;
-  if (lane < nr) {
-    cr = op.rd16[f0 + lane];
-    rv = Rv[f0 + lane];
-  }
-  return k + h * brow_part<AT>(row, nr, cr, rv, S, s, on, x);
 }
 
-// FP64 operator on an FP64 vector
-__device__ __attribute__((always_inline)) inline double brow64(const BatchArgs &a, int64_t row,
-                                                               int s, bool on, double h,
-                                                               const double *__restrict__ x) {
-  return brow<double>(a.op, a.op.Kv, a.op.Rv, row, a.S, s, on, h, x);
+// Issue the copies of the staged rows of a tile, LDS row sl <- x[ssl[sl]][0..S),
+// in UB-byte units (16 when a row of S values is a multiple of 16 bytes, else
+// 4); the slot rows come from LDS, so no copy waits on another.  When a row
+// holds upr units and upr divides 64, one load instruction moves 64 / upr
+// whole rows (lane -> row lane / upr, unit lane % upr); otherwise wave w
+// fills units [base, base + 64) for base = 64 w, 64 w + 256, ....  Lanes past
+// the end repeat a valid load into the unused tail of the buffer.
+template <typename XT, int UB>
+__device__ __attribute__((always_inline)) inline void stage_issue(int nslots,
+                                                                  const XT *__restrict__ x, int S,
+                                                                  XT *lds, const int *ssl) {
+  const int upr = S * (int)sizeof(XT) / UB;  // units per row (wave-uniform)
+  const char *xb = reinterpret_cast<const char *>(x);
+  char *lb = reinterpret_cast<char *>(lds);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  auto issue = [&](const char *src, int base_unit) {
+    auto *dst = (__attribute__((address_space(3))) void *)(lb + (size_t)base_unit * UB);
+    if constexpr (UB == 16) __builtin_amdgcn_global_load_lds((const void *)src, dst, 16, 0, 0);
+    else __builtin_amdgcn_global_load_lds((const void *)src, dst, 4, 0, 0);
+  };
+  if (64 % upr == 0) {
+    const int rpi = 64 / upr;  // rows per load instruction
+    const int lr = lane / upr, lu = lane - lr * upr;
+    for (int r0 = w * rpi; r0 < nslots; r0 += (kBlock / 64) * rpi) {
+      const int sl = r0 + lr < nslots ? r0 + lr : r0;
+      issue(xb + ((size_t)ssl[sl] * upr + lu) * UB, r0 * upr);
+    }
+    return;
+  }
+  const int total = nslots * upr;
+  for (int base = w * 64; base < total; base += kBlock) {
+    const int u = base + lane < total ? base + lane : base;
+    const int sl = u / upr;
+    issue(xb + ((size_t)ssl[sl] * upr + (u - sl * upr)) * UB, base);
+  }
+}
+
+// VEC staged values of LDS row sl starting at scenario s0 (AL: 16-byte aligned)
+template <typename XT, int VEC, bool AL>
+__device__ __attribute__((always_inline)) inline void xrow(const XT *lx, int sl, int S, int s0,
+                                                           XT (&o)[VEC]) {
+  const XT *q = lx + sl * S + s0;
+  if constexpr (AL) {
+    if constexpr (VEC == 4) {
+      const float4 f = *reinterpret_cast<const float4 *>(q);
+      o[0] = f.x; o[1] = f.y; o[2] = f.z; o[3] = f.w;
+    } else {
+      const double2 d = *reinterpret_cast<const double2 *>(q);
+      o[0] = d.x; o[1] = d.y;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) o[i] = q[i];
+  }
+}
+
+// One tile of a staged product.  For each row of the tile and each of the
+// lane's scenarios s = s0 + i < S: epi(row, i, s, y, own, mass) with y =
+// (K + h_s R) x (K entries, then R entries, each summed in entry order),
+// own = x[row][s] (from LDS) and the lumped mass.  Two memory round trips:
+// (1) the tile's slot rows and the extents of the lane's rows; (2) the
+// staging copies of x and of the tile's entries.
+template <typename AT, typename VT, typename XT, int UB, bool AL, typename Epi>
+__device__ __attribute__((always_inline)) inline void tile_apply(
+    const BatchArgs &a, int t, const VT *__restrict__ val, const XT *__restrict__ x,
+    const AT (&h)[Lanes<XT>::VEC], StageLds<XT, VT> &L, Epi &&epi) {
+  using LY = Lanes<XT>;
+  constexpr int VEC = LY::VEC, NI = LY::NI;
+  const BatchOp &op = a.op;
+  const int S = a.S;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lr = lane / LY::LPR, s0 = (lane % LY::LPR) * VEC;
+  const int64_t r0 = (int64_t)t * op.TR, r1 = r0 + op.TR < a.N ? r0 + op.TR : a.N;
+  // (1) slot rows, entry range, and the lane's rows
+  int srv = 0;
+  if (tid < kStageSlots) srv = op.slot_row[(size_t)t * kStageSlots + tid];
+  const int ns = op.nslots[t];
+  const int64_t E0 = op.rowptr[r0], E1 = op.rowptr[r1];
+  int64_t lo[NI], hi[NI];
+  int nk[NI], os[NI];
+  double ms[NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    int64_t row = r0 + (int64_t)(w + 4 * i) * LY::RPW + lr;
+    row = row < r1 ? row : r1 - 1;
+    lo[i] = op.rowptr[row];
+    hi[i] = op.rowptr[row + 1];
+    nk[i] = op.nk[row];
+    os[i] = op.oslot[row];
+    ms[i] = a.mass[row];
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  if (tid < kStageSlots) L.ssl[tid] = srv;
+  __syncthreads();
+  // (2) staged rows and the tile's entries
+  stage_issue<XT, UB>(ns, x, S, L.x, L.ssl);
+  const int ne = (int)(E1 - E0);
+  dma_contig(op.slot32 + E0, L.eslot, ne);
+  dma_contig(val + E0, L.eval, ne * (int)(sizeof(VT) / 4));
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int64_t row = r0 + (int64_t)(w + 4 * i) * LY::RPW + lr;
+    if (row >= r1) continue;
+    const int rel = (int)(lo[i] - E0), n = (int)(hi[i] - lo[i]);
+    AT acc[VEC] = {}, accr[VEC] = {};
+    for (int e = 0; e < nk[i]; ++e) {
+      XT xv[VEC];
+      xrow<XT, VEC, AL>(L.x, L.eslot[rel + e], S, s0, xv);
+      const AT v = (AT)L.eval[rel + e];
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) acc[k] += v * (AT)xv[k];
+    }
+    for (int e = nk[i]; e < n; ++e) {
+      XT xv[VEC];
+      xrow<XT, VEC, AL>(L.x, L.eslot[rel + e], S, s0, xv);
+      const AT v = (AT)L.eval[rel + e];
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) accr[k] += v * (AT)xv[k];
+    }
+    XT own[VEC];
+    xrow<XT, VEC, AL>(L.x, os[i], S, s0, own);
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      if (s0 + k >= S) continue;
+      const AT y = n == nk[i] ? acc[k] : acc[k] + h[k] * accr[k];
+      epi(row, k, s0 + k, y, own[k], ms[i]);
+    }
+  }
+  __syncthreads();
+}
+
+// per-scenario block sums of the lanes' partials (v[k][i] for scenario
+// s0 + i) into partial[k][blk][s]: fixed order over waves and row slots
+template <int K, typename XT, typename VT>
+__device__ inline void publish_lanes(const double (&v)[K][Lanes<XT>::VEC], double *partial,
+                                     int grid, int S, StageLds<XT, VT> &L) {
+  using LY = Lanes<XT>;
+  double *sh = reinterpret_cast<double *>(L.x);  // [4][RPW][64] per k
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane / LY::LPR, s0 = (lane % LY::LPR) * LY::VEC;
+  __syncthreads();
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int i = 0; i < LY::VEC; ++i) sh[(w * LY::RPW + lr) * 64 + s0 + i] = v[k][i];
+    __syncthreads();
+    if (threadIdx.x < (unsigned)S) {
+      double acc = 0.0;
+      for (int j = 0; j < 4 * LY::RPW; ++j) acc += sh[j * 64 + threadIdx.x];
+      partial[((size_t)k * grid + blockIdx.x) * S + threadIdx.x] = acc;
+    }
+    __syncthreads();
+  }
 }
 
 // CG vectors and stored operator values of the FP64 (double) or FP32 (float) form
@@ -158,8 +311,7 @@ template <typename V>
 struct BV;
 template <>
 struct BV<double> {
-  __device__ static const double *K(const BatchArgs &a) { return a.op.Kv; }
-  __device__ static const double *R(const BatchArgs &a) { return a.op.Rv; }
+  __device__ static const double *vals(const BatchArgs &a) { return a.op.val; }
   __device__ static double *x(const BatchArgs &a, int m) { return a.T[m]; }
   __device__ static double *r(const BatchArgs &a) { return a.r; }
   __device__ static double *p(const BatchArgs &a) { return a.p; }
@@ -167,8 +319,7 @@ struct BV<double> {
 };
 template <>
 struct BV<float> {
-  __device__ static const float *K(const BatchArgs &a) { return a.op.Kv32; }
-  __device__ static const float *R(const BatchArgs &a) { return a.op.Rv32; }
+  __device__ static const float *vals(const BatchArgs &a) { return a.op.val32; }
   __device__ static float *x(const BatchArgs &a, int) { return a.x32; }
   __device__ static float *r(const BatchArgs &a) { return a.r32; }
   __device__ static float *p(const BatchArgs &a) { return a.p32; }
@@ -182,15 +333,22 @@ __device__ inline bool lane_on(const BatchScalars *sc, int s, int S) {
 // ---------------------------------------------------------------------------
 // F_j = g - L_s T_j (several standard nodes j), all scenarios
 // ---------------------------------------------------------------------------
+template <int UB, bool AL>
 __global__ __launch_bounds__(kBlock) void kb_f_multi(BatchArgs a, int j0, int j1) {
-  const int s = threadIdx.x & 63, S = a.S;
-  const bool on = s < S;
-  const double h = on ? a.h[s] : 0.0;
-  FOR_ROWS(row, a.N) {
-    const double g = h * a.gbase[row];
+  using LY = Lanes<double>;
+  __shared__ StageLds<double, double> L;
+  const int S = a.S, s0 = (threadIdx.x & 63) % LY::LPR * LY::VEC;
+  double h[LY::VEC];
+#pragma unroll
+  for (int i = 0; i < LY::VEC; ++i) h[i] = s0 + i < S ? a.h[s0 + i] : 0.0;
+  FOR_TILES(t, a.op.ntiles) {
     for (int j = j0; j <= j1; ++j) {
-      const double L = brow64(a, row, s, on, h, a.T[j]);
-      if (on) a.F[j][row * S + s] = g - L;
+      double *F = a.F[j];
+      tile_apply<double, double, double, UB, AL>(
+          a, t, a.op.val, a.T[j], h, L,
+          [&](int64_t row, int i, int s, double y, double, double) {
+            F[row * S + s] = h[i] * a.gbase[row] - y;
+          });
     }
   }
 }
@@ -260,70 +418,93 @@ __device__ inline double bdinv(const BatchArgs &a, int64_t row, double h, double
   return 1.0 / (a.mass[row] + dtau * (a.Kd[row] + h * a.Rd[row]));
 }
 
+// Solve initialisation of one row.  Predictor: x0 = T_{m-1}, b = M T_{m-1} +
+// dtau g, r = b - A x0 (Lx = L T_{m-1} from the staged product).
+// Correction: b = M T_{m-1} + dtau (g - F_m) + I_m and r = M (T_{m-1} - x0) +
+// I_m without a product (L T^k_m = g - F_m).
 template <bool PRED>
-__global__ __launch_bounds__(kBlock) void kb_init(BatchArgs a, int m, double dtau) {
-  const int s = threadIdx.x & 63, S = a.S;
-  double v[3] = {0.0, 0.0, 0.0};
-  const bool on = s < S && a.sc->active[s];
-  const double h = on ? a.h[s] : 0.0;
-  double *x = a.T[m];
-  const double *Tp = a.T[m - 1];
-  FOR_ROWS(row, a.N) {
-    const double Lx = PRED ? brow64(a, row, s, on, h, Tp) : 0.0;
-    if (!on) continue;
-    const int64_t i = row * S + s;
-    const double mi = a.mass[row], tp = Tp[i], g = h * a.gbase[row];
-    double b, r;
-    if (PRED) {
-      b = mi * tp + dtau * g;
-      r = b - (mi * tp + dtau * Lx);
-      x[i] = tp;
-    } else {
-      const double Im = a.I[m][i];
-      b = mi * tp + dtau * (g - a.F[m][i]) + Im;
-      r = mi * (tp - x[i]) + Im;
-    }
-    const double z = bdinv(a, row, h, dtau) * r;
-    a.r[i] = r;
-    a.p[i] = z;
-    v[0] += r * z;
-    v[1] += r * r;
-    v[2] += b * b;
+__device__ inline void init_rhs(const BatchArgs &a, int m, double dtau, int64_t i, int64_t row,
+                                double h, double Lx, double *b, double *r) {
+  const double mi = a.mass[row], tp = a.T[m - 1][i], g = h * a.gbase[row];
+  if (PRED) {
+    *b = mi * tp + dtau * g;
+    *r = *b - (mi * tp + dtau * Lx);
+    a.T[m][i] = tp;
+  } else {
+    const double Im = a.I[m][i];
+    *b = mi * tp + dtau * (g - a.F[m][i]) + Im;
+    *r = mi * (tp - a.T[m][i]) + Im;
   }
-  bpublish<3>(v, a.partial, a.grid, S);
 }
 
-// ---- FP64 iterative refinement around FP32 inner solves (per scenario) ----
-// init: b and r64 = b - A x0 in FP64 (corrections without an SpMV, as above);
-// partial r.r, b.b
+// FP64 form: r, p = z; partial r.z, r.r, b.b
 template <bool PRED>
-__global__ __launch_bounds__(kBlock) void kb_rinit(BatchArgs a, int m, double dtau) {
-  const int s = threadIdx.x & 63, S = a.S;
-  double v[2] = {0.0, 0.0};
-  const bool on = s < S && a.sc->active[s];
-  const double h = on ? a.h[s] : 0.0;
-  double *x = a.T[m];
-  const double *Tp = a.T[m - 1];
-  FOR_ROWS(row, a.N) {
-    const double Lx = PRED ? brow64(a, row, s, on, h, Tp) : 0.0;
-    if (!on) continue;
-    const int64_t i = row * S + s;
-    const double mi = a.mass[row], tp = Tp[i], g = h * a.gbase[row];
-    double b, r;
-    if (PRED) {
-      b = mi * tp + dtau * g;
-      r = b - (mi * tp + dtau * Lx);
-      x[i] = tp;
-    } else {
-      const double Im = a.I[m][i];
-      b = mi * tp + dtau * (g - a.F[m][i]) + Im;
-      r = mi * (tp - x[i]) + Im;
-    }
-    a.r64[i] = r;
-    v[0] += r * r;
-    v[1] += b * b;
+__device__ inline void init64_row(const BatchArgs &a, int m, double dtau, int64_t row, int s,
+                                  double h, double Lx, double (&v)[3]) {
+  const int64_t i = row * a.S + s;
+  double b, r;
+  init_rhs<PRED>(a, m, dtau, i, row, h, Lx, &b, &r);
+  const double z = bdinv(a, row, h, dtau) * r;
+  a.r[i] = r;
+  a.p[i] = z;
+  v[0] += r * z;
+  v[1] += r * r;
+  v[2] += b * b;
+}
+
+// FP32 form (refinement init): r64; partial r.r, b.b
+template <bool PRED>
+__device__ inline void init32_row(const BatchArgs &a, int m, double dtau, int64_t row, int s,
+                                  double h, double Lx, double (&v)[2]) {
+  const int64_t i = row * a.S + s;
+  double b, r;
+  init_rhs<PRED>(a, m, dtau, i, row, h, Lx, &b, &r);
+  a.r64[i] = r;
+  v[0] += r * r;
+  v[1] += b * b;
+}
+
+// predictor initialisation: tiled, L T_{m-1} from the staged rows
+template <int NV, int UB, bool AL>
+__global__ __launch_bounds__(kBlock) void kb_init_pred(BatchArgs a, int m, double dtau) {
+  using LY = Lanes<double>;
+  __shared__ StageLds<double, double> L;
+  const int S = a.S, s0 = (threadIdx.x & 63) % LY::LPR * LY::VEC;
+  double h[LY::VEC], v[NV][LY::VEC] = {};
+  bool on[LY::VEC];
+#pragma unroll
+  for (int i = 0; i < LY::VEC; ++i) {
+    on[i] = s0 + i < S && a.sc->active[s0 + i];
+    h[i] = on[i] ? a.h[s0 + i] : 0.0;
   }
-  bpublish<2>(v, a.partial, a.grid, S);
+  FOR_TILES(t, a.op.ntiles) {
+    tile_apply<double, double, double, UB, AL>(
+        a, t, a.op.val, a.T[m - 1], h, L,
+        [&](int64_t row, int i, int s, double Lx, double, double) {
+          if (!on[i]) return;
+          double vv[NV] = {};
+          if constexpr (NV == 3) init64_row<true>(a, m, dtau, row, s, h[i], Lx, vv);
+          else init32_row<true>(a, m, dtau, row, s, h[i], Lx, vv);
+#pragma unroll
+          for (int k = 0; k < NV; ++k) v[k][i] += vv[k];
+        });
+  }
+  publish_lanes<NV>(v, a.partial, gridDim.x, S, L);
+}
+
+// correction initialisation: no product, row-parallel
+template <int NV>
+__global__ __launch_bounds__(kBlock) void kb_init_corr(BatchArgs a, int m, double dtau) {
+  const int s = threadIdx.x & 63, S = a.S;
+  double v[NV] = {};
+  if (s < S && a.sc->active[s]) {
+    const double h = a.h[s];
+    FOR_ROWS(row, a.N) {
+      if constexpr (NV == 3) init64_row<false>(a, m, dtau, row, s, h, 0.0, v);
+      else init32_row<false>(a, m, dtau, row, s, h, 0.0, v);
+    }
+  }
+  bpublish<NV>(v, a.partial, gridDim.x, S);
 }
 
 // inner init: r32 = r64, d = 0, p = dinv r32; partial r.z, r.r
@@ -343,29 +524,42 @@ __global__ __launch_bounds__(kBlock) void kb_inner_init(BatchArgs a, double dtau
       v[1] += (double)r * (double)r;
     }
   }
-  bpublish<2>(v, a.partial, a.grid, S);
+  bpublish<2>(v, a.partial, gridDim.x, S);
 }
 
-// x64 += d; r64 -= A d with the FP64 operator on the FP32 correction d;
-// partial r.r
+// x64 += d; r64 -= A d with the FP64 operator on the FP32 correction d
+// (staged as FP32); partial r.r
+template <int UB, bool AL>
 __global__ __launch_bounds__(kBlock) void kb_refine_update(BatchArgs a, int m, double dtau) {
-  const int s = threadIdx.x & 63, S = a.S;
-  double v[1] = {0.0};
-  const bool on = s < S && a.sc->active[s] && !a.sc->ref_done[s];
-  const double h = on ? a.h[s] : 0.0;
-  double *x = a.T[m];
-  FOR_ROWS(row, a.N) {
-    const double Ld = brow<double>(a.op, a.op.Kv, a.op.Rv, row, S, s, on, h, a.x32);
-    if (!on) continue;
-    const int64_t i = row * S + s;
-    const double d = (double)a.x32[i];
-    const double Ad = a.mass[row] * d + dtau * Ld;
-    x[i] += d;
-    const double r = a.r64[i] - Ad;
-    a.r64[i] = r;
-    v[0] += r * r;
+  using LY = Lanes<float>;
+  __shared__ StageLds<float, double> L;
+  const int S = a.S, s0 = (threadIdx.x & 63) % LY::LPR * LY::VEC;
+  double h[LY::VEC], v[1][LY::VEC] = {};
+  bool on[LY::VEC], any = false;
+#pragma unroll
+  for (int i = 0; i < LY::VEC; ++i) {
+    const int s = s0 + i;
+    on[i] = s < S && a.sc->active[s] && !a.sc->ref_done[s];
+    h[i] = on[i] ? a.h[s] : 0.0;
+    any |= on[i];
   }
-  bpublish<1>(v, a.partial, a.grid, S);
+  double *x = a.T[m];
+  if (__syncthreads_or(any)) {
+    FOR_TILES(t, a.op.ntiles) {
+      tile_apply<double, double, float, UB, AL>(
+          a, t, a.op.val, a.x32, h, L,
+          [&](int64_t row, int i, int s, double Ld, float own, double mass) {
+            if (!on[i]) return;
+            const int64_t ix = row * S + s;
+            const double d = (double)own;
+            x[ix] += d;
+            const double r = a.r64[ix] - (mass * d + dtau * Ld);
+            a.r64[ix] = r;
+            v[0][i] += r * r;
+          });
+    }
+  }
+  publish_lanes<1>(v, a.partial, gridDim.x, S, L);
 }
 
 // Per-scenario scalars from the block partials.  Modes:
@@ -373,8 +567,9 @@ __global__ __launch_bounds__(kBlock) void kb_refine_update(BatchArgs a, int m, d
 //   2 FP64 convergence (r.z, r.r)    3 refinement init (r.r, b.b)
 //   4 inner init (r.z, r.r)          5 refinement check (r.r), it = round
 //   6 inner convergence (r.z, r.r)
-// Fixed-order sums: wave w adds blocks w, w+16, ..., then wave 0 adds the waves.
-__global__ __launch_bounds__(64 * kRedWaves) void kb_reduce(BatchArgs a, int mode, int it,
+// np = workgroups of the producing kernel.  Fixed-order sums: wave w adds
+// blocks w, w+16, ..., then wave 0 adds the waves.
+__global__ __launch_bounds__(64 * kRedWaves) void kb_reduce(BatchArgs a, int np, int mode, int it,
                                                             int last, int slot, double rtol) {
   __shared__ double sh[3][kRedWaves][64];
   const int s = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -383,8 +578,7 @@ __global__ __launch_bounds__(64 * kRedWaves) void kb_reduce(BatchArgs a, int mod
   for (int k = 0; k < nk; ++k) {
     double acc = 0.0;
     if (s < a.S)
-      for (int b = w; b < a.grid; b += kRedWaves)
-        acc += a.partial[((size_t)k * a.grid + b) * a.S + s];
+      for (int b = w; b < np; b += kRedWaves) acc += a.partial[((size_t)k * np + b) * a.S + s];
     sh[k][w][s] = acc;
   }
   __syncthreads();
@@ -452,26 +646,37 @@ __global__ __launch_bounds__(64 * kRedWaves) void kb_reduce(BatchArgs a, int mod
 // (a) q = diag(m) p + dtau (K + h R) p, partial p.q.  V = double: the FP64
 // form; V = float: the inner solves of the FP32 form (FP32 values, vectors,
 // products and row sums; dot products summed in FP64).  TIMING: stand-alone
-// timing launches that ignore the convergence flags.
-template <int TIMING, typename V>
+// timing launches that ignore the convergence flags.  Tiled; a workgroup
+// with no scenario left to iterate skips the product.
+template <int TIMING, typename V, int UB, bool AL>
 __global__ __launch_bounds__(kBlock) void kb_pcg_a(BatchArgs a, int m, double dtau) {
-  const int s = threadIdx.x & 63, S = a.S;
-  double v[1] = {0.0};
-  const bool on = TIMING ? s < S : lane_on(a.sc, s, S);
-  const V h = on ? (V)a.h[s] : (V)0;
-  const V dt = (V)dtau;
-  const V *p = BV<V>::p(a);
-  V *q = BV<V>::q(a);
-  FOR_ROWS(row, a.N) {
-    const V Lp = brow<V>(a.op, BV<V>::K(a), BV<V>::R(a), row, S, s, on, h, p);
-    if (!on) continue;
-    const int64_t i = row * S + s;
-    const V pi = p[i];
-    const V qi = (V)a.mass[row] * pi + dt * Lp;
-    q[i] = qi;
-    v[0] += (double)pi * (double)qi;
+  using LY = Lanes<V>;
+  __shared__ StageLds<V, V> L;
+  const int S = a.S, s0 = (threadIdx.x & 63) % LY::LPR * LY::VEC;
+  V h[LY::VEC];
+  double v[1][LY::VEC] = {};
+  bool on[LY::VEC], any = false;
+#pragma unroll
+  for (int i = 0; i < LY::VEC; ++i) {
+    const int s = s0 + i;
+    on[i] = TIMING ? s < S : lane_on(a.sc, s, S);
+    h[i] = on[i] ? (V)a.h[s] : (V)0;
+    any |= on[i];
   }
-  bpublish<1>(v, a.partial, a.grid, S);
+  const V dt = (V)dtau;
+  V *q = BV<V>::q(a);
+  if (__syncthreads_or(any)) {
+    FOR_TILES(t, a.op.ntiles) {
+      tile_apply<V, V, V, UB, AL>(a, t, BV<V>::vals(a), BV<V>::p(a), h, L,
+                                  [&](int64_t row, int i, int s, V y, V pi, double mass) {
+                                    if (!on[i]) return;
+                                    const V qi = (V)mass * pi + dt * y;
+                                    q[row * S + s] = qi;
+                                    v[0][i] += (double)pi * (double)qi;
+                                  });
+    }
+  }
+  publish_lanes<1>(v, a.partial, gridDim.x, S, L);
 }
 
 // (b) x += alpha p; r -= alpha q; partial r.z, r.r
@@ -494,7 +699,7 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_b(BatchArgs a, int m, double dt
       v[1] += (double)r * (double)r;
     }
   }
-  bpublish<2>(v, a.partial, a.grid, S);
+  bpublish<2>(v, a.partial, gridDim.x, S);
 }
 
 // (c) p = z + beta p
@@ -768,8 +973,25 @@ void blaunch_iface_coeffs(const BatchArgs &a, hipStream_t st) {
   kb_iface_coeffs<<<(a.M + 1) * (a.P + 1) * a.S, kBlock, 0, st>>>(a);
 }
 
+// 16-byte staging units and aligned lane reads when a row of S values is a
+// multiple of 16 bytes
+template <typename XT>
+static bool vec16(const BatchArgs &a) {
+  return (a.S * sizeof(XT)) % 16 == 0;
+}
+
+// workgroups of a tiled kernel staging XT values: as many as are resident
+// (two FP64 or three FP32 staging buffers per CU), fixed per mesh
+template <typename XT>
+static int tgrid(const BatchArgs &a) {
+  return sizeof(XT) == 8 ? a.sgrid64 : a.sgrid32;
+}
+
+#define RED(np, ...) kb_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, np, __VA_ARGS__)
+
 void blaunch_f_multi(const BatchArgs &a, int j0, int j1, hipStream_t st) {
-  kb_f_multi<<<a.grid, kBlock, 0, st>>>(a, j0, j1);
+  if (vec16<double>(a)) kb_f_multi<16, true><<<a.sgrid64, kBlock, 0, st>>>(a, j0, j1);
+  else kb_f_multi<4, false><<<a.sgrid64, kBlock, 0, st>>>(a, j0, j1);
 }
 
 void blaunch_quad_resid(const BatchArgs &a, int k, hipStream_t st) {
@@ -778,46 +1000,68 @@ void blaunch_quad_resid(const BatchArgs &a, int k, hipStream_t st) {
 }
 
 template <typename V>
+static void launch_pcg_a(const BatchArgs &a, int timing, int m, double dtau, hipStream_t st) {
+  const int g = tgrid<V>(a);
+  if (vec16<V>(a)) {
+    if (timing) kb_pcg_a<1, V, 16, true><<<g, kBlock, 0, st>>>(a, m, dtau);
+    else kb_pcg_a<0, V, 16, true><<<g, kBlock, 0, st>>>(a, m, dtau);
+  } else {
+    if (timing) kb_pcg_a<1, V, 4, false><<<g, kBlock, 0, st>>>(a, m, dtau);
+    else kb_pcg_a<0, V, 4, false><<<g, kBlock, 0, st>>>(a, m, dtau);
+  }
+}
+
+template <typename V>
 static void cg_iterations(const BatchArgs &a, int m, double dtau, int slot, int budget,
                           double rtol, hipStream_t st) {
   const int conv = std::is_same<V, float>::value ? 6 : 2;
   for (int it = 0; it < budget; ++it) {
-    kb_pcg_a<0, V><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
-    kb_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, 1, it, 0, slot, rtol);
+    launch_pcg_a<V>(a, 0, m, dtau, st);
+    RED(tgrid<V>(a), 1, it, 0, slot, rtol);
     kb_pcg_b<V><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
-    kb_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, conv, it, it == budget - 1, slot, rtol);
+    RED(a.grid, conv, it, it == budget - 1, slot, rtol);
     kb_pcg_c<V><<<a.grid, kBlock, 0, st>>>(a, dtau);
   }
+}
+
+template <int NV>
+static void launch_init(const BatchArgs &a, bool pred, int m, double dtau, hipStream_t st) {
+  if (!pred) {
+    kb_init_corr<NV><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
+    return;
+  }
+  if (vec16<double>(a)) kb_init_pred<NV, 16, true><<<a.sgrid64, kBlock, 0, st>>>(a, m, dtau);
+  else kb_init_pred<NV, 4, false><<<a.sgrid64, kBlock, 0, st>>>(a, m, dtau);
 }
 
 void blaunch_solve(const BatchArgs &a, const BSolve &sv, hipStream_t st) {
   const int m = sv.m;
   const double dtau = a.dtau_h[m];
+  const int npi = sv.pred ? a.sgrid64 : a.grid;  // workgroups of the init kernel
   if (!a.fp32) {
-    if (sv.pred) kb_init<true><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
-    else kb_init<false><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
-    kb_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, 0, 0, 0, sv.slot, sv.rtol);
+    launch_init<3>(a, sv.pred, m, dtau, st);
+    RED(npi, 0, 0, 0, sv.slot, sv.rtol);
     cg_iterations<double>(a, m, dtau, sv.slot, sv.budget, sv.rtol, st);
     return;
   }
   // FP32 inner solves inside FP64 refinement rounds
-  if (sv.pred) kb_rinit<true><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
-  else kb_rinit<false><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
-  kb_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, 3, 0, 0, sv.slot, sv.refine_rtol);
+  launch_init<2>(a, sv.pred, m, dtau, st);
+  RED(npi, 3, 0, 0, sv.slot, sv.refine_rtol);
   for (int r = 0; r < sv.rounds; ++r) {
     kb_inner_init<<<a.grid, kBlock, 0, st>>>(a, dtau);
-    kb_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, 4, 0, 0, sv.slot, sv.inner_rtol);
+    RED(a.grid, 4, 0, 0, sv.slot, sv.inner_rtol);
     cg_iterations<float>(a, m, dtau, sv.slot, sv.budget, sv.inner_rtol, st);
-    kb_refine_update<<<a.grid, kBlock, 0, st>>>(a, m, dtau);
-    kb_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, 5, r, r == sv.rounds - 1, sv.slot,
-                                            sv.refine_rtol);
+    if (vec16<float>(a)) kb_refine_update<16, true><<<a.sgrid32, kBlock, 0, st>>>(a, m, dtau);
+    else kb_refine_update<4, false><<<a.sgrid32, kBlock, 0, st>>>(a, m, dtau);
+    RED(a.sgrid32, 5, r, r == sv.rounds - 1, sv.slot, sv.refine_rtol);
   }
 }
+#undef RED
 
 void blaunch_operator_timing(const BatchArgs &a, int m, int reps, hipStream_t st) {
   for (int i = 0; i < reps; ++i) {
-    if (a.fp32) kb_pcg_a<1, float><<<a.grid, kBlock, 0, st>>>(a, m, a.dtau_h[m]);
-    else kb_pcg_a<1, double><<<a.grid, kBlock, 0, st>>>(a, m, a.dtau_h[m]);
+    if (a.fp32) launch_pcg_a<float>(a, 1, m, a.dtau_h[m], st);
+    else launch_pcg_a<double>(a, 1, m, a.dtau_h[m], st);
   }
 }
 
