@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--config", default="machine", choices=["box", "machine", "machine-fp32", "ensemble", "serve"],
                     help="ensemble: only the 64-member ensemble; serve: only the serving replay")
     ap.add_argument("--serve-requests", type=int, default=24, help="requests replayed (serve)")
+    ap.add_argument("--serve-precision", type=int, default=1, choices=[0, 1],
+                    help="form of the served simulations: 0 FP64, 1 FP32+refine")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="finish with a device-to-device copy of this many MiB (counter scale)")
     ap.add_argument("--serve-max-steps", type=int, default=12,
@@ -245,6 +247,7 @@ def serving(pkg, args):
         stand, stock = mi.MESH_LEVELS[name]
         levels[name] = mi.machine(stand_nodes=stand, stock_nodes=stock, nsteps=1,
                                   name=f"machine_{name}")
+        levels[name].scheme.precision = args.serve_precision
         print(f"[bench] level {name}: N={levels[name].N}", file=sys.stderr, flush=True)
     reqs = []
     for r in trace:
@@ -256,6 +259,17 @@ def serving(pkg, args):
     srv = Server(levels, slots_per_level=64)
     done = srv.run(reqs)
     out = summarize(done, 5.0, {k: v.N for k, v in levels.items()})
+    out["dtype"] = "f64" if args.serve_precision == 0 else "f32+f64-refine"
+    if not args.no_cpu_baseline:
+        # oracle on the smallest level's first request: error of a served result
+        import oracle
+        small = min(levels, key=lambda k: levels[k].N)
+        r = next(q for q in done if q.level == small)
+        ref, _ = oracle.run(levels[small], nsteps=r.nsteps, T0=r.T0, h=r.h, alpha=r.alpha,
+                            friction_W=r.friction_W, period=r.period)
+        out["rel_l2_vs_oracle_sample"] = {
+            "request": r.id, "level": small, "steps": r.nsteps,
+            "value": float(np.linalg.norm(r.result - ref) / np.linalg.norm(ref))}
     out.update({"metric": "serving: p50/p99 macro-step latency, per-request eta, DOF*steps/s",
                 "workload": f"first {len(reqs)} requests of the 20 req/s trace, <= "
                             f"{args.serve_max_steps} steps each",

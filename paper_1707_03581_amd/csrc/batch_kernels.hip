@@ -206,6 +206,40 @@ __device__ __attribute__((always_inline)) inline void xrow(const XT *lx, int sl,
   }
 }
 
+// acc[k] += sum over entries e in [e0, e1) of the row (in order) of
+// value_e * x[slot_e][s0 + k]; four entries' LDS reads go out together
+template <typename AT, typename VT, typename XT, bool AL>
+__device__ __attribute__((always_inline)) inline void entry_sum(const StageLds<XT, VT> &L,
+                                                                int rel, int e0, int e1, int S,
+                                                                int s0,
+                                                                AT (&acc)[Lanes<XT>::VEC]) {
+  constexpr int VEC = Lanes<XT>::VEC;
+  int e = e0;
+  for (; e + 4 <= e1; e += 4) {
+    int sl[4];
+    AT v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      sl[j] = L.eslot[rel + e + j];
+      v[j] = (AT)L.eval[rel + e + j];
+    }
+    XT xv[4][VEC];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xrow<XT, VEC, AL>(L.x, sl[j], S, s0, xv[j]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) acc[k] += v[j] * (AT)xv[j][k];
+  }
+  for (; e < e1; ++e) {
+    XT xv[VEC];
+    xrow<XT, VEC, AL>(L.x, L.eslot[rel + e], S, s0, xv);
+    const AT v = (AT)L.eval[rel + e];
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) acc[k] += v * (AT)xv[k];
+  }
+}
+
 // One tile of a staged product.  For each row of the tile and each of the
 // lane's scenarios s = s0 + i < S: epi(row, i, s, y, own, mass) with y =
 // (K + h_s R) x (K entries, then R entries, each summed in entry order),
@@ -257,20 +291,8 @@ __device__ __attribute__((always_inline)) inline void tile_apply(
     if (row >= r1) continue;
     const int rel = (int)(lo[i] - E0), n = (int)(hi[i] - lo[i]);
     AT acc[VEC] = {}, accr[VEC] = {};
-    for (int e = 0; e < nk[i]; ++e) {
-      XT xv[VEC];
-      xrow<XT, VEC, AL>(L.x, L.eslot[rel + e], S, s0, xv);
-      const AT v = (AT)L.eval[rel + e];
-#pragma unroll
-      for (int k = 0; k < VEC; ++k) acc[k] += v * (AT)xv[k];
-    }
-    for (int e = nk[i]; e < n; ++e) {
-      XT xv[VEC];
-      xrow<XT, VEC, AL>(L.x, L.eslot[rel + e], S, s0, xv);
-      const AT v = (AT)L.eval[rel + e];
-#pragma unroll
-      for (int k = 0; k < VEC; ++k) accr[k] += v * (AT)xv[k];
-    }
+    entry_sum<AT, VT, XT, AL>(L, rel, 0, nk[i], S, s0, acc);
+    entry_sum<AT, VT, XT, AL>(L, rel, nk[i], n, S, s0, accr);
     XT own[VEC];
     xrow<XT, VEC, AL>(L.x, os[i], S, s0, own);
 #pragma unroll

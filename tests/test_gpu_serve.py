@@ -19,8 +19,8 @@ def _announce(request):
     yield
 
 
-def levels():
-    sc = mi.Scheme(M=5, family=mi.LOBATTO, P=5, K=4, dt=5.0)
+def levels(precision=mi.FP64):
+    sc = mi.Scheme(M=5, family=mi.LOBATTO, P=5, K=4, dt=5.0, precision=precision)
     a = mi.machine(stand_nodes=(5, 7, 19), stock_nodes=(4, 5, 7), stand_L=(0.2, 0.3, 0.9),
                    stock_L=(0.15, 0.2, 0.3), y_offset=0.05, period=3.0, stroke=0.5, scheme=sc)
     b = mi.machine(stand_nodes=(6, 9, 23), stock_nodes=(5, 6, 9), stand_L=(0.2, 0.3, 0.9),
@@ -44,10 +44,11 @@ def trace(lv, n=10, seed=7):
     return out
 
 
-def test_served_results_equal_alone_and_oracle():
+@pytest.mark.parametrize("precision,tol", [(mi.FP64, 1e-10), (mi.FP32_REFINE, 1e-7)])
+def test_served_results_equal_alone_and_oracle(precision, tol):
     import paper_1707_03581_amd as m
     from paper_1707_03581_amd.serve import Server, summarize
-    lv = levels()
+    lv = levels(precision)
     reqs = Server(lv, slots_per_level=4).run(trace(lv))
     summ = summarize(reqs, 5.0, {k: v.N for k, v in lv.items()})
     print("  ", {k: round(v, 4) for k, v in summ.items()}, flush=True)
@@ -68,4 +69,4 @@ def test_served_results_equal_alone_and_oracle():
                             friction_W=r.friction_W, period=r.period)
         e = float(np.linalg.norm(r.result - ref) / np.linalg.norm(ref))
         print(f"  request {r.id} ({r.level}, {r.nsteps} steps): rel_l2={e:.3e}", flush=True)
-        assert e <= 1e-10
+        assert e <= tol
