@@ -86,6 +86,7 @@ struct mrsdc_ctx {
   int rounds[kSlots];   // refinement round budget per slot
   int64_t matrix_bytes = 0;
   int64_t nnz = 0;
+  int64_t batch_entries = 0;  // merged K and R entries of a batched operator
   // event timing of kernel classes
   bool prof = false;
   std::vector<hipEvent_t> ev;   // pairs
@@ -359,6 +360,7 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
   double *pv;
   if ((st = upload(c, &prp, rowptr))) return st;
   a.op.rowptr = prp;
+  c->batch_entries = rowptr[N];
   if ((st = upload(c, &pi, nk))) return st;
   a.op.nk = pi;
   if ((st = upload(c, &pv, val))) return st;
@@ -1344,12 +1346,13 @@ mrsdc_status mrsdc_time_operator(mrsdc_ctx *c, int reps, double *avg_us, int64_t
   hipEventDestroy(e1);
   *avg_us = 1e3 * ms / reps;
   if (bytes) {
-    // batched: shared K rows (int16 offset + FP64 value) once, S right-hand
-    // sides read and written (the few Robin rows' R entries are left out)
-    // (FP32 form: FP32 values and right-hand sides)
+    // batched: every stored entry (4-byte slot + value) once, per row its
+    // extent, K count, own slot and mass (22 bytes), and the S right-hand
+    // sides read once and written once (FP32 form: FP32 values and vectors)
     const bool f32 = c->cfg.precision == MRSDC_FP32_REFINE;
-    *bytes = c->S > 0 ? c->nnz * (f32 ? 6 : 10) + 8 * (c->ba.N + 1) +
-                            ((f32 ? 8 : 16) * (int64_t)c->S + 8) * c->ba.N
+    const int64_t vb = f32 ? 4 : 8;
+    *bytes = c->S > 0 ? c->batch_entries * (4 + vb) + 22 * c->ba.N +
+                            2 * vb * (int64_t)c->S * c->ba.N
                       : c->times.cg_spmv_bytes;
   }
   return MRSDC_OK;
