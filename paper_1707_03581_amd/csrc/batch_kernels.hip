@@ -62,7 +62,7 @@ __device__ inline TileRange xcd_tiles(int T) {
     if (const int t = tr_.t; true)
 
 // sum the per-wave (per-lane = per-scenario) values of the block into
-// partial[k][blk][s]
+// partial[k][s][blk]
 template <int K>
 __device__ inline void bpublish(double (&v)[K], double *partial, int grid, int S) {
   __shared__ double sh[kBlock / 64][K][64];
@@ -73,7 +73,7 @@ __device__ inline void bpublish(double (&v)[K], double *partial, int grid, int S
     for (int k = 0; k < K; ++k) {
       double acc = 0.0;
       for (int ww = 0; ww < kBlock / 64; ++ww) acc += sh[ww][k][lane];
-      partial[((size_t)k * grid + blockIdx.x) * S + lane] = acc;
+      partial[((size_t)k * S + lane) * grid + blockIdx.x] = acc;
     }
   }
 }
@@ -306,7 +306,7 @@ __device__ __attribute__((always_inline)) inline void tile_apply(
 }
 
 // per-scenario block sums of the lanes' partials (v[k][i] for scenario
-// s0 + i) into partial[k][blk][s]: fixed order over waves and row slots
+// s0 + i) into partial[k][s][blk]: fixed order over waves and row slots
 template <int K, typename XT, typename VT>
 __device__ inline void publish_lanes(const double (&v)[K][Lanes<XT>::VEC], double *partial,
                                      int grid, int S, StageLds<XT, VT> &L) {
@@ -322,7 +322,7 @@ __device__ inline void publish_lanes(const double (&v)[K][Lanes<XT>::VEC], doubl
     if (threadIdx.x < (unsigned)S) {
       double acc = 0.0;
       for (int j = 0; j < 4 * LY::RPW; ++j) acc += sh[j * 64 + threadIdx.x];
-      partial[((size_t)k * grid + blockIdx.x) * S + threadIdx.x] = acc;
+      partial[((size_t)k * S + threadIdx.x) * grid + blockIdx.x] = acc;
     }
     __syncthreads();
   }
@@ -589,25 +589,30 @@ __global__ __launch_bounds__(kBlock) void kb_refine_update(BatchArgs a, int m, d
 //   2 FP64 convergence (r.z, r.r)    3 refinement init (r.r, b.b)
 //   4 inner init (r.z, r.r)          5 refinement check (r.r), it = round
 //   6 inner convergence (r.z, r.r)
-// np = workgroups of the producing kernel.  Fixed-order sums: wave w adds
-// blocks w, w+16, ..., then wave 0 adds the waves.
-__global__ __launch_bounds__(64 * kRedWaves) void kb_reduce(BatchArgs a, int np, int mode, int it,
-                                                            int last, int slot, double rtol) {
-  __shared__ double sh[3][kRedWaves][64];
-  const int s = threadIdx.x & 63, w = threadIdx.x >> 6;
+// One workgroup per scenario s = blockIdx.x; np = workgroups of the
+// producing kernel, whose partials of scenario s are contiguous.  Fixed-order
+// sums: thread j adds blocks j, j + 256, ..., then a fixed halving tree.
+__global__ __launch_bounds__(kBlock) void kb_reduce(BatchArgs a, int np, int mode, int it,
+                                                    int last, int slot, double rtol) {
+  __shared__ double sh[3][kBlock];
+  const int s = blockIdx.x, j = threadIdx.x;
   BatchScalars *sc = a.sc;
   const int nk = mode == 0 ? 3 : ((mode == 1 || mode == 5) ? 1 : 2);
   for (int k = 0; k < nk; ++k) {
+    const double *pp = a.partial + ((size_t)k * a.S + s) * np;
     double acc = 0.0;
-    if (s < a.S)
-      for (int b = w; b < np; b += kRedWaves) acc += a.partial[((size_t)k * np + b) * a.S + s];
-    sh[k][w][s] = acc;
+    for (int b = j; b < np; b += kBlock) acc += pp[b];
+    sh[k][j] = acc;
   }
   __syncthreads();
-  if (w != 0 || s >= a.S) return;
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if (j < h)
+      for (int k = 0; k < nk; ++k) sh[k][j] += sh[k][j + h];
+    __syncthreads();
+  }
+  if (j != 0) return;
   double o[3] = {0.0, 0.0, 0.0};
-  for (int k = 0; k < nk; ++k)
-    for (int ww = 0; ww < kRedWaves; ++ww) o[k] += sh[k][ww][s];
+  for (int k = 0; k < nk; ++k) o[k] = sh[k][0];
   if (!sc->active[s]) return;
   if (mode == 0) {
     sc->rz[0][s] = o[0];
@@ -701,6 +706,11 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_a(BatchArgs a, int m, double dt
   publish_lanes<1>(v, a.partial, gridDim.x, S, L);
 }
 
+// The row-parallel CG updates take the wave's rows (the FOR_ROWS sequence)
+// four at a time, every load of the four issued before the first use; rows
+// are still accumulated in sequence order.
+constexpr int kRowsAhead = 4;
+
 // (b) x += alpha p; r -= alpha q; partial r.z, r.r
 template <typename V>
 __global__ __launch_bounds__(kBlock) void kb_pcg_b(BatchArgs a, int m, double dtau) {
@@ -711,14 +721,32 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_b(BatchArgs a, int m, double dt
     const V alpha = (V)a.sc->alpha[s];
     V *x = BV<V>::x(a, m), *rv = BV<V>::r(a);
     const V *p = BV<V>::p(a), *q = BV<V>::q(a);
-    FOR_ROWS(row, a.N) {
-      const int64_t i = row * S + s;
-      x[i] += alpha * p[i];
-      const V r = rv[i] - alpha * q[i];
-      rv[i] = r;
-      const V z = (V)bdinv(a, row, h, dtau) * r;
-      v[0] += (double)r * (double)z;
-      v[1] += (double)r * (double)r;
+    for (RowRange rr = xcd_rows(a.N); rr.row < rr.end; rr.row += kRowsAhead * rr.stride) {
+      V xs[kRowsAhead], ps[kRowsAhead], qs[kRowsAhead], rs[kRowsAhead];
+      double di[kRowsAhead];
+#pragma unroll
+      for (int u = 0; u < kRowsAhead; ++u) {
+        const int64_t row = rr.row + u * rr.stride;
+        if (row >= rr.end) continue;
+        const int64_t i = row * S + s;
+        xs[u] = x[i];
+        ps[u] = p[i];
+        qs[u] = q[i];
+        rs[u] = rv[i];
+        di[u] = bdinv(a, row, h, dtau);
+      }
+#pragma unroll
+      for (int u = 0; u < kRowsAhead; ++u) {
+        const int64_t row = rr.row + u * rr.stride;
+        if (row >= rr.end) continue;
+        const int64_t i = row * S + s;
+        x[i] = xs[u] + alpha * ps[u];
+        const V r = rs[u] - alpha * qs[u];
+        rv[i] = r;
+        const V z = (V)di[u] * r;
+        v[0] += (double)r * (double)z;
+        v[1] += (double)r * (double)r;
+      }
     }
   }
   bpublish<2>(v, a.partial, gridDim.x, S);
@@ -733,9 +761,23 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_c(BatchArgs a, double dtau) {
   const V beta = (V)a.sc->beta[s];
   V *p = BV<V>::p(a);
   const V *rv = BV<V>::r(a);
-  FOR_ROWS(row, a.N) {
-    const int64_t i = row * S + s;
-    p[i] = (V)bdinv(a, row, h, dtau) * rv[i] + beta * p[i];
+  for (RowRange rr = xcd_rows(a.N); rr.row < rr.end; rr.row += kRowsAhead * rr.stride) {
+    V ps[kRowsAhead], rs[kRowsAhead];
+    double di[kRowsAhead];
+#pragma unroll
+    for (int u = 0; u < kRowsAhead; ++u) {
+      const int64_t row = rr.row + u * rr.stride;
+      if (row >= rr.end) continue;
+      ps[u] = p[row * S + s];
+      rs[u] = rv[row * S + s];
+      di[u] = bdinv(a, row, h, dtau);
+    }
+#pragma unroll
+    for (int u = 0; u < kRowsAhead; ++u) {
+      const int64_t row = rr.row + u * rr.stride;
+      if (row >= rr.end) continue;
+      p[row * S + s] = (V)di[u] * rs[u] + beta * ps[u];
+    }
   }
 }
 
@@ -1009,7 +1051,7 @@ static int tgrid(const BatchArgs &a) {
   return sizeof(XT) == 8 ? a.sgrid64 : a.sgrid32;
 }
 
-#define RED(np, ...) kb_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, np, __VA_ARGS__)
+#define RED(np, ...) kb_reduce<<<a.S, kBlock, 0, st>>>(a, np, __VA_ARGS__)
 
 void blaunch_f_multi(const BatchArgs &a, int j0, int j1, hipStream_t st) {
   if (vec16<double>(a)) kb_f_multi<16, true><<<a.sgrid64, kBlock, 0, st>>>(a, j0, j1);
