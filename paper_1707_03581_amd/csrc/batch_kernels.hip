@@ -752,15 +752,60 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_b(BatchArgs a, int m, double dt
   bpublish<2>(v, a.partial, gridDim.x, S);
 }
 
-// (c) p = z + beta p
+// p_new = dinv r + beta p with one explicit rounding pattern, whatever code
+// path (and therefore contraction choice) computes it
+__device__ __forceinline__ float pupdate(float di, float r, float beta, float p) {
+  return __builtin_fmaf(di, r, beta * p);
+}
+__device__ __forceinline__ double pupdate(double di, double r, double beta, double p) {
+  return __builtin_fma(di, r, beta * p);
+}
+
+// (c) p = z + beta p.  No sums here, so the vector is streamed flat:
+// VEC = 16 / sizeof(V) consecutive values (one row, scenarios s0..s0+VEC-1)
+// per lane and load when S is a power of two and a multiple of VEC (lshift =
+// log2 S); otherwise row by row with one scenario per lane.
 template <typename V>
-__global__ __launch_bounds__(kBlock) void kb_pcg_c(BatchArgs a, double dtau) {
-  const int s = threadIdx.x & 63, S = a.S;
+__global__ __launch_bounds__(kBlock) void kb_pcg_c(BatchArgs a, double dtau, int lshift) {
+  const int S = a.S;
+  V *p = BV<V>::p(a);
+  const V *rv = BV<V>::r(a);
+  if (lshift >= 0) {
+    constexpr int VEC = 16 / (int)sizeof(V);
+    using V4 = typename std::conditional<sizeof(V) == 4, float4, double2>::type;
+    const int64_t nvec = a.N * S / VEC;
+    const int64_t k0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    // the stride (a multiple of 1024 values) is a multiple of S, so every
+    // value this thread touches belongs to scenarios s0 .. s0 + VEC - 1
+    const int s0 = (int)((k0 * VEC) & (S - 1));
+    bool on[VEC], any = false;
+    double h[VEC];
+    V beta[VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+      on[j] = lane_on(a.sc, s0 + j, S);
+      any |= on[j];
+      h[j] = on[j] ? a.h[s0 + j] : 0.0;
+      beta[j] = on[j] ? (V)a.sc->beta[s0 + j] : (V)0;
+    }
+    if (!any) return;
+    for (int64_t k = k0; k < nvec; k += (int64_t)gridDim.x * kBlock) {
+      const int64_t row = (k * VEC) >> lshift;
+      V4 pv = reinterpret_cast<V4 *>(p)[k];
+      const V4 r4 = reinterpret_cast<const V4 *>(rv)[k];
+      V *pp = reinterpret_cast<V *>(&pv);
+      const V *rr = reinterpret_cast<const V *>(&r4);
+#pragma unroll
+      for (int j = 0; j < VEC; ++j)
+        if (on[j]) pp[j] = pupdate((V)bdinv(a, row, h[j], dtau), rr[j], beta[j], pp[j]);
+      reinterpret_cast<V4 *>(p)[k] = pv;
+    }
+    return;
+  }
+  const int s = threadIdx.x & 63;
   if (!lane_on(a.sc, s, S)) return;
   const double h = a.h[s];
   const V beta = (V)a.sc->beta[s];
-  V *p = BV<V>::p(a);
-  const V *rv = BV<V>::r(a);
   for (RowRange rr = xcd_rows(a.N); rr.row < rr.end; rr.row += kRowsAhead * rr.stride) {
     V ps[kRowsAhead], rs[kRowsAhead];
     double di[kRowsAhead];
@@ -776,7 +821,7 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_c(BatchArgs a, double dtau) {
     for (int u = 0; u < kRowsAhead; ++u) {
       const int64_t row = rr.row + u * rr.stride;
       if (row >= rr.end) continue;
-      p[row * S + s] = (V)di[u] * rs[u] + beta * ps[u];
+      p[row * S + s] = pupdate((V)di[u], rs[u], beta, ps[u]);
     }
   }
 }
@@ -1053,6 +1098,16 @@ static int tgrid(const BatchArgs &a) {
 
 #define RED(np, ...) kb_reduce<<<a.S, kBlock, 0, st>>>(a, np, __VA_ARGS__)
 
+// log2 S when S is a power of two and a multiple of 16 / sizeof(V), else -1
+template <typename V>
+static int flat_shift(const BatchArgs &a) {
+  const int vec = 16 / (int)sizeof(V);
+  if (a.S % vec != 0 || (a.S & (a.S - 1)) != 0) return -1;
+  int l = 0;
+  while ((1 << l) < a.S) ++l;
+  return l;
+}
+
 void blaunch_f_multi(const BatchArgs &a, int j0, int j1, hipStream_t st) {
   if (vec16<double>(a)) kb_f_multi<16, true><<<a.sgrid64, kBlock, 0, st>>>(a, j0, j1);
   else kb_f_multi<4, false><<<a.sgrid64, kBlock, 0, st>>>(a, j0, j1);
@@ -1084,7 +1139,8 @@ static void cg_iterations(const BatchArgs &a, int m, double dtau, int slot, int 
     RED(tgrid<V>(a), 1, it, 0, slot, rtol);
     kb_pcg_b<V><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
     RED(a.grid, conv, it, it == budget - 1, slot, rtol);
-    kb_pcg_c<V><<<a.grid, kBlock, 0, st>>>(a, dtau);
+    kb_pcg_c<V><<<flat_shift<V>(a) >= 0 ? 4 * a.grid : a.grid, kBlock, 0, st>>>(a, dtau,
+                                                                          flat_shift<V>(a));
   }
 }
 

@@ -66,9 +66,10 @@ def test_batch_members_match_oracle(S):
         assert e <= 1e-10
 
 
-def test_member_alone_equals_member_in_batch():
+@pytest.mark.parametrize("S", [5, 8])
+def test_member_alone_equals_member_in_batch(S):
     pb = small_machine()
-    mem = members_for(pb, 5)
+    mem = members_for(pb, S)
     outs, _, _ = run_batch(pb, mem, 2)
     for s in (0, 3):
         alone, _, _ = run_batch(pb, [mem[s]], 2)
@@ -171,9 +172,10 @@ def test_batch_fp32_refine_members_match_oracle(S):
         assert e <= TOL32
 
 
-def test_batch_fp32_member_alone_equals_member_in_batch():
+@pytest.mark.parametrize("S", [6, 8])
+def test_batch_fp32_member_alone_equals_member_in_batch(S):
     pb = small_machine()
-    mem = members_for(pb, 6, seed0=1500)
+    mem = members_for(pb, S, seed0=1500)
     outs, _, _ = run_batch(pb, mem, 2, precision=1)
     for s in (0, 4):
         alone, _, _ = run_batch(pb, [mem[s]], 2, precision=1)
