@@ -192,6 +192,8 @@ def main():
         out["rel_l2_sample_steps"] = S
     if args.precision_steps > 0 and args.config == "machine":
         out["fp32_refine"] = precision_form(pkg, args)
+    if args.config == "machine":
+        out["stationary"] = stationary_form(pkg, args)
     if args.ensemble_steps > 0 and args.config == "machine":
         import mrsdc_inputs as mi
         out["ensemble"] = ensemble(pkg, args, mi.FP32_REFINE)
@@ -211,6 +213,22 @@ def calibrate_copy(mib):
     dst.copy_(src)
     torch.cuda.synchronize()
     print(f"[bench] calibration copy of {mib} MiB done", file=sys.stderr, flush=True)
+
+
+def stationary_form(pkg, args):
+    """The stationary initial field (K + h R) T = g on the benchmark machine:
+    one Jacobi-PCG solve on the device, timed; its closed form is T_env."""
+    import mrsdc_inputs as mi
+    pb = mi.machine_310k(nsteps=1)
+    ctx = pkg.simulation(pb, device=0)
+    ctx.advance(0.0)  # build the device state outside the timed region
+    t = time.perf_counter()
+    it = ctx.set_stationary(rtol=1e-12, maxit=200000)
+    wall = time.perf_counter() - t
+    T = pkg.get_state(ctx, pb)
+    ctx.destroy()
+    return {"workload": pb.name, "cg_iters": it, "ms": wall * 1e3,
+            "max_abs_err_vs_closed_form": float(np.abs(T - 20.0).max())}
 
 
 def precision_form(pkg, args):

@@ -151,6 +151,17 @@ mrsdc_status mrsdc_get_time(const mrsdc_ctx *ctx, double *t);
  * at the last completed step. */
 mrsdc_status mrsdc_advance(mrsdc_ctx *ctx, double horizon, mrsdc_stats *stats);
 
+/* Replace the field by the stationary one of the conduction and Robin part,
+ * (K + h R) T = g with g = h T_env r (the initial data of the numerical
+ * example, §5: the machine at rest, coupled only to its environment; the
+ * mass term printed there is read as zero, since a stationary field has no
+ * time derivative).  Jacobi-PCG warm-started from the current field (zero if
+ * none was set) until ||r||_2 <= rtol ||g||_2, at most maxit iterations;
+ * iters (nullable) receives the count.  Single contexts only (ESTATE for a
+ * batched one).  EINVAL for rtol <= 0, maxit < 1, or a body without a
+ * Robin term (singular problem); ENOCONV leaves the last iterate in place. */
+mrsdc_status mrsdc_set_stationary(mrsdc_ctx *ctx, double rtol, int maxit, int *iters);
+
 /* Copy the temperature of one body to a host array of n values. */
 mrsdc_status mrsdc_get_temperature(mrsdc_ctx *ctx, int body, double *out, int64_t n);
 

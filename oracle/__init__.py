@@ -84,6 +84,7 @@ def lib():
         L.orc_fE.argtypes = [P, C.c_double, P, P]
         L.orc_solve.argtypes = [P, C.c_double, P, P, C.c_double, C.c_int]
         L.orc_run.argtypes = [P, P, C.c_double, C.c_int, P, P, P]
+        L.orc_stationary.argtypes = [P, P, C.c_double, C.c_int]
         L.orc_max_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -192,6 +193,17 @@ def solve(pb, dtau, b, x0=None, rtol=1e-13, maxit=1000):
     if it < 0:
         raise RuntimeError("oracle PCG did not converge")
     return x, it
+
+
+def stationary(pb, T0=None, rtol=1e-13, maxit=100000, **over):
+    """Stationary field (K + h R) T = g of pb's conduction and Robin part
+    (no mass term), warm-started from T0 (default zeros); returns (T, iters)."""
+    s, keep = make_problem(pb, **over)
+    T = np.zeros(pb.N) if T0 is None else np.array(T0, dtype=np.float64)
+    it = lib().orc_stationary(C.byref(s), _ptr(T), rtol, maxit)
+    if it < 0:
+        raise RuntimeError("oracle stationary PCG did not converge")
+    return T, it
 
 
 def run(pb, nsteps=None, T0=None, t0=None, residuals=False, scheme=None, **over):

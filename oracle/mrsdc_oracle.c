@@ -406,6 +406,24 @@ int orc_solve(const orc_problem *pb, double dtau, const double *b, double *x, do
   return it;
 }
 
+/* Stationary field of the conduction and Robin part (the initial data of the
+ * numerical example, section 5, read with the time derivative zero):
+ * (K + h R) T = g, g = h T_env r, by the same Jacobi-PCG with no mass term. */
+int orc_stationary(const orc_problem *pb, double *T, double rtol, int maxit) {
+  solver S;
+  memset(&S, 0, sizeof S);
+  if (solver_init(&S, pb)) { solver_free(&S); return -1; }
+  const int64_t N = S.N;
+  for (int64_t i = 0; i < N; ++i) S.mass[i] = 0.0;
+  double *g = malloc(sizeof(double) * N);
+  if (!g) { solver_free(&S); return -1; }
+  source_g(pb, g);
+  int it = pcg(&S, 1.0, g, T, rtol, maxit);
+  free(g);
+  solver_free(&S);
+  return it;
+}
+
 /* ------------------------------------------------------------------------ */
 /* The time stepper: Alg. 1 (predictor) and Alg. 2 (correction sweep)        */
 /* ------------------------------------------------------------------------ */

@@ -108,6 +108,11 @@ int orc_solve(const orc_problem *pb, double dtau, const double *b, double *x,
 int orc_run(const orc_problem *pb, const orc_scheme *sc, double t0, int nsteps,
             double *T, double *residuals, orc_stats *stats);
 
+/* Stationary field (K + h R) T = g, g = h T_env r (no mass term), by
+ * Jacobi-PCG warm-started from T.  Returns iterations, or -1 on no
+ * convergence. */
+int orc_stationary(const orc_problem *pb, double *T, double rtol, int maxit);
+
 int orc_max_threads(void);
 
 #ifdef __cplusplus

@@ -74,6 +74,7 @@ _SIGS = {
                                   C.c_double, C.c_double, C.c_double, C.c_double]),
     "mrsdc_set_temperature": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int64]),
     "mrsdc_set_time": (C.c_int, [C.c_void_p, C.c_double]),
+    "mrsdc_set_stationary": (C.c_int, [C.c_void_p, C.c_double, C.c_int, C.POINTER(C.c_int)]),
     "mrsdc_get_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "mrsdc_advance": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p]),
     "mrsdc_get_temperature": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int64]),
@@ -201,6 +202,13 @@ class Context:
 
     def set_time(self, t):
         return self._chk(self._L.mrsdc_set_time(self._h, t))
+
+    def set_stationary(self, rtol=1e-13, maxit=100000):
+        """Replace the field by the stationary one, (K + h R) T = g; returns
+        the CG iteration count."""
+        it = C.c_int(0)
+        self._chk(self._L.mrsdc_set_stationary(self._h, rtol, maxit, C.byref(it)))
+        return it.value
 
     def get_time(self):
         t = C.c_double()

@@ -1277,6 +1277,90 @@ mrsdc_status mrsdc_advance(mrsdc_ctx *c, double horizon, mrsdc_stats *stats) {
   return MRSDC_OK;
 }
 
+mrsdc_status mrsdc_set_stationary(mrsdc_ctx *c, double rtol, int maxit, int *iters) {
+  if (!c) return MRSDC_EINVAL;
+  if (iters) *iters = 0;
+  if (c->S > 0) return fail(c, MRSDC_ESTATE, "batched context: set each scenario's field instead");
+  if (!(rtol > 0) || !std::isfinite(rtol) || maxit < 1)
+    return fail(c, MRSDC_EINVAL, "bad tolerance or iteration cap");
+  if (!c->body[0].set) return fail(c, MRSDC_ESTATE, "body 0 not set");
+  for (int b = 0; b < 2; ++b) {
+    const HostBody &B = c->body[b];
+    if (!B.set) continue;
+    bool robin = B.h > 0 && !B.R.empty() && !B.rload.empty();
+    if (robin) {
+      robin = false;
+      for (double r : B.rload) robin |= r > 0;
+    }
+    if (!robin) return fail(c, MRSDC_EINVAL, "body %d has no Robin term: the stationary problem is singular", b);
+  }
+  // start from the current field (zero where none was set)
+  for (int b = 0; b < 2; ++b) {
+    HostBody &B = c->body[b];
+    if (B.set && !B.hasT) {
+      B.T.assign(B.n, 0.0);
+      B.hasT = true;
+      c->dirty_T = true;
+    }
+  }
+  mrsdc_status st = prepare(c);
+  if (st) return st;
+  if ((st = upload_T(c))) return st;
+  // Jacobi inverse of L = K + h R and a zero mass vector
+  const int64_t N = c->d.N;
+  std::vector<double> dinv(N, 0.0);
+  for (int b = 0; b < c->nbody; ++b) {
+    const HostBody &B = c->body[b];
+    for (int64_t i = 0; i < B.n; ++i) {
+      double dl = 0.0;
+      for (int64_t e = B.rowptr[i]; e < B.rowptr[i + 1]; ++e)
+        if (B.col[e] == i) dl += B.K[e] + (B.R.empty() ? 0.0 : B.h * B.R[e]);
+      dinv[c->off[b] + i] = 1.0 / dl;
+    }
+  }
+  double *ddinv = nullptr, *dzero = nullptr;
+  auto release = [&]() {
+    if (ddinv) hipFree(ddinv);
+    if (dzero) hipFree(dzero);
+  };
+  if (hipMalloc((void **)&ddinv, sizeof(double) * N) != hipSuccess ||
+      hipMalloc((void **)&dzero, sizeof(double) * N) != hipSuccess) {
+    release();
+    hipGetLastError();
+    return fail(c, MRSDC_ENOMEM, "device allocation failed");
+  }
+  auto hipfail = [&](hipError_t e) {
+    release();
+    return fail(c, MRSDC_EDEVICE, "HIP: %s", hipGetErrorString(e));
+  };
+  hipError_t he;
+  if ((he = hipMemcpy(ddinv, dinv.data(), sizeof(double) * N, hipMemcpyHostToDevice)) ||
+      (he = hipMemset(dzero, 0, sizeof(double) * N)))
+    return hipfail(he);
+  launch_clear_counters(c->d, c->stream);
+  if ((he = hipMemsetAsync(c->d.sc, 0, sizeof(SolveScalars), c->stream))) return hipfail(he);
+  launch_stationary_init(c->d, dzero, ddinv, 0, rtol, c->stream);
+  SolveScalars sc;
+  int it = 0;
+  for (;;) {
+    if ((he = hipMemcpyAsync(&sc, c->d.sc, sizeof sc, hipMemcpyDeviceToHost, c->stream)) ||
+        (he = hipStreamSynchronize(c->stream)))
+      return hipfail(he);
+    if (sc.done) break;
+    if (it >= maxit) {
+      release();
+      return fail(c, MRSDC_ENOCONV, "stationary solve did not converge in %d iterations", maxit);
+    }
+    const int n = std::min(64, maxit - it);
+    launch_stationary_iters(c->d, dzero, ddinv, 0, it, n, maxit - 1, c->stream);
+    if ((he = hipGetLastError())) return hipfail(he);
+    it += n;
+  }
+  if (iters) *iters = sc.iters;
+  release();
+  return MRSDC_OK;
+}
+
 mrsdc_status mrsdc_get_temperature(mrsdc_ctx *c, int body, double *out, int64_t n) {
   if (!c) return MRSDC_EINVAL;
   if (body < 0 || body > 1 || !c->body[body].set) return fail(c, MRSDC_ESTATE, "body not set");

@@ -657,6 +657,36 @@ void launch_pcg_iter(const DevState &d, int m, int slot, int it, bool last, bool
   pcg_iter(d, cg64(d, m, slot), it, last, tail, st, ev0, ev1);
 }
 
+// Stationary field (K + h R) T = g: the CG kernels with a zero mass, dtau = 1
+// and the Jacobi inverse of L, on T_n in place.
+static CgArgs<double> stationary_args(const DevState &d, const double *zeros, const double *dinv,
+                                      int slot) {
+  CgArgs<double> a = cg64(d, 1, slot);
+  a.mass = zeros;
+  a.dinv = dinv;
+  a.dtau = 1.0;
+  a.x = d.T[0];
+  a.x64 = d.T[0];
+  a.Tprev = d.T[0];
+  a.g = d.g;
+  return a;
+}
+
+void launch_stationary_init(const DevState &d, const double *zeros, const double *dinv, int slot,
+                            double rtol, hipStream_t st) {
+  const CgArgs<double> a = stationary_args(d, zeros, dinv, slot);
+  if (d.op.d16) k_init_pred<true><<<d.grid, kBlock, 0, st>>>(a);
+  else k_init_pred<false><<<d.grid, kBlock, 0, st>>>(a);
+  solve_reduce(d, slot, 0, rtol, 0, false, st);
+}
+
+void launch_stationary_iters(const DevState &d, const double *zeros, const double *dinv, int slot,
+                             int it0, int n, int last_it, hipStream_t st) {
+  const CgArgs<double> a = stationary_args(d, zeros, dinv, slot);
+  for (int it = it0; it < it0 + n; ++it)
+    pcg_iter(d, a, it, it == last_it, false, st, nullptr, nullptr);
+}
+
 // reps back-to-back operator applications q = A p of interval m (timing only;
 // p holds the last solve's direction, q and the partials are scratch)
 void launch_operator_timing(const DevState &d, int m, bool fp32, int reps, hipStream_t st) {

@@ -151,6 +151,10 @@ void launch_f_multi(const DevState &d, int j0, int j1, hipStream_t st);
 void launch_quad_resid(const DevState &d, int k, hipStream_t st);
 void launch_init_pred(const DevState &d, int m, int slot, double rtol, hipStream_t st);
 void launch_init_corr(const DevState &d, int m, int slot, double rtol, hipStream_t st);
+void launch_stationary_init(const DevState &d, const double *zeros, const double *dinv, int slot,
+                            double rtol, hipStream_t st);
+void launch_stationary_iters(const DevState &d, const double *zeros, const double *dinv, int slot,
+                             int it0, int n, int last_it, hipStream_t st);
 void launch_pcg_iter(const DevState &d, int m, int slot, int it, bool last, bool tail,
                      hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_refine_init(const DevState &d, int m, int slot, bool pred, double rtol,

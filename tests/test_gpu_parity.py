@@ -220,3 +220,63 @@ def test_fp32_refine_deterministic():
     a, _ = run_gpu(pb, 3, precision=1)
     b, _ = run_gpu(pb, 3, precision=1)
     assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# Stationary initial field (K + h R) T = g (the numerical example's initial
+# data): against the oracle's solve, and against its closed form T = T_env
+# (K 1 = 0, R 1 = r) at the full machine size.
+# ---------------------------------------------------------------------------
+def test_stationary_matches_oracle_then_steps():
+    m = lib()
+    pb = small_machine()
+    pb.T_amb = [15.0, 35.0]
+    ctx = m.simulation(pb)
+    it = ctx.set_stationary(rtol=1e-13)
+    T = m.get_state(ctx, pb)
+    ref, _ = oracle.stationary(pb, T0=pb.T0)
+    print(f"  iterations {it}, rel_l2 vs oracle {rel(T, ref):.3e}", flush=True)
+    assert it > 0
+    assert rel(T, ref) <= TOL
+    n0 = pb.bodies[0].n
+    assert np.abs(T[:n0] - 15.0).max() < 1e-9 and np.abs(T[n0:] - 35.0).max() < 1e-9
+    # the stationary field then steps like any other initial field
+    ctx.advance(2 * pb.scheme.dt)
+    got = m.get_state(ctx, pb)
+    ctx.destroy()
+    ref2, _ = oracle.run(pb, nsteps=2, T0=ref)
+    assert rel(got, ref2) <= TOL
+
+
+def test_stationary_machine_310k_closed_form():
+    m = lib()
+    pb = mi.machine_310k(nsteps=1)
+    ctx = m.simulation(pb)
+    it = ctx.set_stationary(rtol=1e-12, maxit=200000)
+    T = m.get_state(ctx, pb)
+    ctx.destroy()
+    err = float(np.abs(T - 20.0).max())
+    print(f"  iterations {it}, max |T - T_env| = {err:.3e}", flush=True)
+    assert err < 1e-8
+
+
+def test_stationary_error_paths():
+    m = lib()
+    pb = small_machine(h=0.0)
+    ctx = m.simulation(pb)
+    with pytest.raises(m.MrsdcError) as e:
+        ctx.set_stationary()
+    assert e.value.status == m.EINVAL
+    ctx.destroy()
+    pb = small_machine()
+    ctx = m.simulation(pb)
+    with pytest.raises(m.MrsdcError) as e:
+        ctx.set_stationary(maxit=1)
+    assert e.value.status == m.ENOCONV
+    ctx.destroy()
+    bctx = m.batch_simulation(pb, [dict(h=10.0, alpha=1000.0, friction_W=100.0, period=3.0,
+                                        T0=pb.T0)])
+    with pytest.raises(m.MrsdcError) as e:
+        bctx.set_stationary()
+    assert e.value.status == m.ESTATE
+    bctx.destroy()
