@@ -69,7 +69,12 @@ typedef struct {
   int refine_maxit;   /* FP32_REFINE: outer refinement cap per solve */
   double inner_rtol;  /* FP32_REFINE: relative tolerance of each FP32 inner solve */
   int final_residual; /* nonzero: also evaluate the residual of the last sweep */
-  int use_graph;      /* nonzero: capture each time step as a HIP graph */
+  int use_graph;      /* reserved, keep 0 */
+  double sweep_tol;   /* > 0: residual control, a step stops sweeping once the
+                         residual (eq. residual, max-norm) of its latest iterate
+                         is <= sweep_tol (at most K sweeps; §3 states that each
+                         sweep reduces it by a factor proportional to dt);
+                         0: always K sweeps.  Per scenario in batched contexts */
   void *stream;       /* hipStream_t to run on, or NULL for a library-owned stream */
 } mrsdc_config;
 
@@ -84,6 +89,7 @@ typedef struct {
                               last step; k = K only with final_residual */
   double wall_s;           /* host wall time of the advance, to device completion */
   int64_t bytes_moved;     /* algorithmic device bytes of the advance (see docs) */
+  int64_t sweeps;          /* correction sweeps run (over active scenarios) */
 } mrsdc_stats;
 
 /* Fill *cfg with defaults: FP64, Lobatto M=3, P=2, K=2, dt=1, pcg_rtol 1e-13. */

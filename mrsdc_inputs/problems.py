@@ -93,6 +93,7 @@ class Scheme:
     refine_rtol: float = 1e-10
     refine_maxit: int = 20
     inner_rtol: float = 1e-6
+    sweep_tol: float = 0.0  # > 0: residual-controlled number of sweeps (at most K)
 
 
 @dataclass

@@ -58,13 +58,13 @@ class _Problem(C.Structure):
 
 class _Scheme(C.Structure):
     _fields_ = [("M", C.c_int), ("family", C.c_int), ("P", C.c_int), ("K", C.c_int),
-                ("dt", C.c_double), ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int)]
+                ("dt", C.c_double), ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int), ("sweep_tol", C.c_double)]
 
 
 class Stats(C.Structure):
     _fields_ = [("solves", C.c_int64), ("pcg_iters", C.c_int64), ("fE_evals", C.c_int64),
                 ("max_iters", C.c_int), ("t_pcg", C.c_double), ("t_embedded", C.c_double),
-                ("t_total", C.c_double), ("threads", C.c_int)]
+                ("t_total", C.c_double), ("threads", C.c_int), ("sweeps", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -161,6 +161,7 @@ def _scheme(sc):
     s = _Scheme()
     s.M, s.family, s.P, s.K = sc.M, sc.family, sc.P, sc.K
     s.dt, s.pcg_rtol, s.pcg_maxit = sc.dt, sc.pcg_rtol, sc.pcg_maxit
+    s.sweep_tol = getattr(sc, "sweep_tol", 0.0)
     return s
 
 

@@ -556,8 +556,10 @@ int orc_run(const orc_problem *pb, const orc_scheme *sc, double t0, int nsteps, 
           }
         }
       }
-      /* residual of iterate k-1 (eq. residual): max_m |M T_m - M T_n - sum_{l<=m} I_l| */
-      if (residuals) {
+      /* residual of iterate k-1 (eq. residual): max_m |M T_m - M T_n - sum_{l<=m} I_l|;
+         with sweep_tol > 0 it also decides whether sweep k runs (the residual
+         control of section 3: each sweep should reduce it) */
+      if (residuals || sc->sweep_tol > 0) {
         double rmax = 0;
         for (int64_t i = 0; i < N; ++i) {
           double cum = 0;
@@ -567,9 +569,11 @@ int orc_run(const orc_problem *pb, const orc_scheme *sc, double t0, int nsteps, 
             if (r > rmax) rmax = r;
           }
         }
-        residuals[(size_t)n * (Ksw + 1) + (k - 1)] = rmax;
+        if (residuals) residuals[(size_t)n * (Ksw + 1) + (k - 1)] = rmax;
+        if (sc->sweep_tol > 0 && rmax <= sc->sweep_tol) break;
       }
       if (k > Ksw) break;
+      st.sweeps++;
 
       memcpy(V(Tstn, 0), Tn, sizeof(double) * nv);
       for (int m = 1; m <= M; ++m) {

@@ -74,6 +74,7 @@ typedef struct {
   double dt;      /* time step */
   double pcg_rtol;
   int pcg_maxit;
+  double sweep_tol; /* > 0: stop a step's sweeps once its residual is <= sweep_tol */
 } orc_scheme;
 
 typedef struct {
@@ -81,6 +82,7 @@ typedef struct {
   int max_iters;
   double t_pcg, t_embedded, t_total;   /* seconds */
   int threads;
+  int64_t sweeps;                      /* correction sweeps run */
 } orc_stats;
 
 /* Quadrature nodes and weights for one step of length dt.

@@ -33,14 +33,15 @@ class Config(C.Structure):
                 ("node_family", C.c_int), ("P", C.c_int), ("K", C.c_int), ("dt", C.c_double),
                 ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int), ("refine_rtol", C.c_double),
                 ("refine_maxit", C.c_int), ("inner_rtol", C.c_double),
-                ("final_residual", C.c_int), ("use_graph", C.c_int), ("stream", C.c_void_p)]
+                ("final_residual", C.c_int), ("use_graph", C.c_int), ("sweep_tol", C.c_double),
+                ("stream", C.c_void_p)]
 
 
 class Stats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("solves", C.c_int64), ("pcg_iters", C.c_int64),
                 ("refine_steps", C.c_int64), ("max_iters", C.c_int32),
                 ("redone_steps", C.c_int32), ("residual", C.c_double * 17),
-                ("wall_s", C.c_double), ("bytes_moved", C.c_int64)]
+                ("wall_s", C.c_double), ("bytes_moved", C.c_int64), ("sweeps", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "residual"}
@@ -315,7 +316,8 @@ def config_from_scheme(scheme, device=0, **over) -> Config:
                          node_family=scheme.family, P=scheme.P, K=scheme.K, dt=scheme.dt,
                          pcg_rtol=scheme.pcg_rtol, pcg_maxit=scheme.pcg_maxit,
                          refine_rtol=scheme.refine_rtol, refine_maxit=scheme.refine_maxit,
-                         inner_rtol=scheme.inner_rtol)
+                         inner_rtol=scheme.inner_rtol,
+                         sweep_tol=getattr(scheme, "sweep_tol", 0.0))
     for k, v in over.items():
         setattr(cfg, k, v)
     return cfg

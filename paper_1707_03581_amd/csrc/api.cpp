@@ -187,6 +187,7 @@ bool valid_scheme(const mrsdc_config *cfg) {
   if (cfg->node_family != MRSDC_LOBATTO && cfg->node_family != MRSDC_EQUI_NOLEFT) return false;
   if (cfg->precision != MRSDC_FP64 && cfg->precision != MRSDC_FP32_REFINE) return false;
   if (!(cfg->pcg_rtol > 0) || cfg->pcg_maxit < 1) return false;
+  if (!(cfg->sweep_tol >= 0) || !std::isfinite(cfg->sweep_tol)) return false;
   if (cfg->precision == MRSDC_FP32_REFINE &&
       (!(cfg->refine_rtol > 0) || cfg->refine_maxit < 1 || !(cfg->inner_rtol > 0)))
     return false;
@@ -352,6 +353,7 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
   a.N = N;
   a.M = c->cfg.M;
   a.P = c->cfg.P;
+  a.sweep_tol = c->cfg.sweep_tol;
   // blocks of 4 rows, a multiple of the 8 XCDs
   a.grid = (int)std::min<int64_t>(((N + 3) / 4 + 7) / 8 * 8, 1024);
   for (int m = 0; m <= c->cfg.M; ++m) a.dtau_h[m] = c->w.dtau[m];
@@ -475,6 +477,7 @@ mrsdc_status prepare(mrsdc_ctx *c) {
   d.M = cfg.M;
   d.P = cfg.P;
   d.K = cfg.K;
+  d.sweep_tol = cfg.sweep_tol;
   for (int m = 0; m <= cfg.M; ++m) d.dtau_h[m] = c->w.dtau[m];
   d.grid = (int)std::min<int64_t>((N + kBlock - 1) / kBlock, 1024);
   if (d.grid < 1) d.grid = 1;
@@ -1214,6 +1217,7 @@ mrsdc_status mrsdc_advance(mrsdc_ctx *c, double horizon, mrsdc_stats *stats) {
       const bool fp32 = c->cfg.precision == MRSDC_FP32_REFINE;
       if (h.fail == 0) {
         acc.pcg_iters += h.pcg_iters;
+        acc.sweeps += h.stop ? h.sweeps : Kc;
         acc.refine_steps += h.refine_steps;
         acc.max_iters = std::max(acc.max_iters, h.max_iters);
         for (int k = 0; k <= Kc; ++k) acc.residual[k] = h.resid[k];
@@ -1584,6 +1588,7 @@ mrsdc_status mrsdc_batch_advance(mrsdc_ctx *c, int nsteps, mrsdc_stats *stats) {
           if (!c->sc_active[s]) continue;
           acc.pcg_iters += h.iters_total[s];
           acc.refine_steps += h.refine_total[s];
+          acc.sweeps += h.stop[s] ? h.sweeps[s] : Kc;
         }
         for (int k = 0; k <= Kc; ++k) {
           double r = 0.0;

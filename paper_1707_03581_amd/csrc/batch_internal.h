@@ -45,6 +45,8 @@ struct BatchScalars {
   int done[kMaxS];
   int ref_done[kMaxS];
   int fail[kMaxS];
+  int stop[kMaxS];                // residual control: no further sweeps this step
+  int sweeps[kMaxS];              // sweeps run when stop was set
   long long iters_total[kMaxS];   // CG iterations of the step (inner ones in FP32)
   long long refine_total[kMaxS];  // refinement rounds of the step
   int slot_iters[kSlots][kMaxS];  // FP64: iterations (-1 budget hit); FP32: largest inner count
@@ -81,6 +83,7 @@ struct BatchArgs {
   float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr;
   double *r64 = nullptr;
   int fp32 = 0;
+  double sweep_tol = 0.0;  // > 0: residual-controlled sweeps, per scenario
   double *partial = nullptr;  // [3][max(grid, sgrid64, sgrid32)][S]
   BatchScalars *sc = nullptr;
   double *Eold = nullptr, *Enew = nullptr;  // [(M+1)(P+1)][n_if][S]

@@ -349,7 +349,12 @@ struct BV<float> {
 };
 
 __device__ inline bool lane_on(const BatchScalars *sc, int s, int S) {
-  return s < S && sc->active[s] && !sc->done[s] && !sc->ref_done[s];
+  return s < S && sc->active[s] && !sc->done[s] && !sc->ref_done[s] && !sc->stop[s];
+}
+
+// scenario s still sweeping this step (active, not stopped by residual control)
+__device__ inline bool sweeping(const BatchScalars *sc, int s, int S) {
+  return s < S && sc->active[s] && !sc->stop[s];
 }
 
 // ---------------------------------------------------------------------------
@@ -428,7 +433,14 @@ __global__ __launch_bounds__(64 * kRedWaves) void kb_resid_reduce(BatchArgs a, i
   __syncthreads();
   if (w == 0 && s < a.S) {
     for (int ww = 1; ww < kRedWaves; ++ww) mx = fmax(mx, sh[ww][s]);
-    a.sc->resid[k][s] = mx;
+    BatchScalars *sc = a.sc;
+    sc->resid[k][s] = mx;
+    // residual control: the first iterate at or below the tolerance ends the
+    // scenario's sweeps for this step
+    if (a.sweep_tol > 0 && sc->active[s] && !sc->stop[s] && mx <= a.sweep_tol) {
+      sc->stop[s] = 1;
+      sc->sweeps[s] = k;
+    }
   }
 }
 
@@ -519,7 +531,7 @@ template <int NV>
 __global__ __launch_bounds__(kBlock) void kb_init_corr(BatchArgs a, int m, double dtau) {
   const int s = threadIdx.x & 63, S = a.S;
   double v[NV] = {};
-  if (s < S && a.sc->active[s]) {
+  if (sweeping(a.sc, s, S)) {
     const double h = a.h[s];
     FOR_ROWS(row, a.N) {
       if constexpr (NV == 3) init64_row<false>(a, m, dtau, row, s, h, 0.0, v);
@@ -533,7 +545,7 @@ __global__ __launch_bounds__(kBlock) void kb_init_corr(BatchArgs a, int m, doubl
 __global__ __launch_bounds__(kBlock) void kb_inner_init(BatchArgs a, double dtau) {
   const int s = threadIdx.x & 63, S = a.S;
   double v[2] = {0.0, 0.0};
-  if (s < S && a.sc->active[s] && !a.sc->ref_done[s]) {
+  if (sweeping(a.sc, s, S) && !a.sc->ref_done[s]) {
     const double h = a.h[s];
     FOR_ROWS(row, a.N) {
       const int64_t i = row * S + s;
@@ -561,7 +573,7 @@ __global__ __launch_bounds__(kBlock) void kb_refine_update(BatchArgs a, int m, d
 #pragma unroll
   for (int i = 0; i < LY::VEC; ++i) {
     const int s = s0 + i;
-    on[i] = s < S && a.sc->active[s] && !a.sc->ref_done[s];
+    on[i] = sweeping(a.sc, s, S) && !a.sc->ref_done[s];
     h[i] = on[i] ? a.h[s] : 0.0;
     any |= on[i];
   }
@@ -613,7 +625,7 @@ __global__ __launch_bounds__(kBlock) void kb_reduce(BatchArgs a, int np, int mod
   if (j != 0) return;
   double o[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < nk; ++k) o[k] = sh[k][0];
-  if (!sc->active[s]) return;
+  if (!sweeping(sc, s, a.S)) return;
   if (mode == 0) {
     sc->rz[0][s] = o[0];
     sc->tol2[s] = rtol * rtol * o[2];
@@ -989,7 +1001,7 @@ __global__ __launch_bounds__(kBlock) void kb_iface_sub(BatchArgs a, int m, int p
   const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const IfaceDev &f = a.f;
   const int n = f.n_if;
-  if (i >= n || s >= S || !a.sc->active[s]) return;
+  if (i >= n || !sweeping(a.sc, s, S)) return;
   const Weights &w = *a.w;
   const int P = a.P, P1 = P + 1;
   const CoefLayout L{f.nvf, f.nvm};
@@ -1038,6 +1050,8 @@ __global__ void kb_clear(BatchArgs a) {
   const int s = threadIdx.x;
   if (s >= a.S) return;
   sc->fail[s] = 0;
+  sc->stop[s] = 0;
+  sc->sweeps[s] = 0;
   sc->iters_total[s] = 0;
   sc->refine_total[s] = 0;
   for (int k = 0; k < 17; ++k) sc->resid[k][s] = 0.0;

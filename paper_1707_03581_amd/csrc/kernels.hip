@@ -188,12 +188,19 @@ __global__ __launch_bounds__(kBlock) void k_quad_resid(int64_t N, QArgs a) {
   if (threadIdx.x == 0) a.partial[blockIdx.x] = rmax;
 }
 
-__global__ void k_reduce_max(const double *part, int n, double *out) {
+// residual of iterate k; with residual control (tol > 0) the first iterate
+// at or below tol ends the step's sweeps
+__global__ void k_reduce_max(const double *part, int n, StepCounters *ctr, int k, double tol) {
   __shared__ double sh[17];
   double v = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) v = fmax(v, part[i]);
   v = block_max(v, sh);
-  if (threadIdx.x == 0) *out = v;
+  if (threadIdx.x != 0) return;
+  ctr->resid[k] = v;
+  if (tol > 0 && !ctr->stop && v <= tol) {
+    ctr->stop = 1;
+    ctr->sweeps = k;
+  }
 }
 
 void launch_quad_resid(const DevState &d, int k, hipStream_t st) {
@@ -212,7 +219,7 @@ void launch_quad_resid(const DevState &d, int k, hipStream_t st) {
   a.P = d.P;
   a.partial = d.partial;
   k_quad_resid<<<d.grid, kBlock, 0, st>>>(d.N, a);
-  k_reduce_max<<<1, kBlock, 0, st>>>(d.partial, d.grid, &d.ctr->resid[k]);
+  k_reduce_max<<<1, kBlock, 0, st>>>(d.partial, d.grid, d.ctr, k, d.sweep_tol);
 }
 
 // ---------------------------------------------------------------------------
@@ -309,7 +316,9 @@ __device__ inline double sell_row_mixed(const SellDev &op, int64_t s, int lane, 
   return acc;
 }
 
-__device__ inline bool solve_done(const SolveScalars *sc) { return sc->done || sc->ref_done; }
+__device__ inline bool solve_done(const SolveScalars *sc, const StepCounters *ctr) {
+  return sc->done || sc->ref_done || ctr->stop;
+}
 
 // scalars of a fresh CG solve from the sums r.z, r.r, b.b
 __device__ inline void init_finish(SolveScalars *sc, StepCounters *ctr, int slot, int inner,
@@ -358,6 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_init_pred(CgArgs<double> a) {
 // and since L x0 = g - F_m the initial residual needs no SpMV:
 // r = M (T^{k+1}_{m-1} - T^k_m) + I_m.
 __global__ __launch_bounds__(kBlock) void k_init_corr(CgArgs<double> a) {
+  if (a.ctr->stop) return;
   __shared__ double sh[17];
   double v[3] = {0.0, 0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.N;
@@ -380,6 +390,7 @@ __global__ __launch_bounds__(kBlock) void k_init_corr(CgArgs<double> a) {
 // mode 2: inner FP32 CG init (r.z, r.r)  3: refinement update (r.r)
 __global__ void k_solve_reduce(const double *part, int grid, SolveScalars *sc, StepCounters *ctr,
                                int slot, int mode, double rtol, int round, int last_round) {
+  if (ctr->stop) return;  // residual control ended this step's sweeps
   __shared__ double sh[17];
   const int nk = (mode == 0) ? 3 : (mode == 3 ? 1 : 2);
   double o[3] = {0.0, 0.0, 0.0};
@@ -417,7 +428,7 @@ __global__ void k_solve_reduce(const double *part, int grid, SolveScalars *sc, S
 // launches (which ignore the convergence flag); both kept apart in profiles.
 template <bool D16, int TAIL, typename R>
 __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
-  if (TAIL != 2 && solve_done(a.sc)) return;
+  if (TAIL != 2 && solve_done(a.sc, a.ctr)) return;
   __shared__ double sh[17];
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
@@ -438,7 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
 // (b) alpha = r.z / p.q; x += alpha p; r -= alpha q; partial r.z, r.r
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_pcg_b(CgArgs<R> a, int it) {
-  if (solve_done(a.sc)) return;
+  if (solve_done(a.sc, a.ctr)) return;
   __shared__ double sh[17];
   const double pq = sum_partials(a.partial, a.grid, sh);
   const R alpha = (R)(a.sc->rz[it & 1] / pq);
@@ -462,7 +473,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_b(CgArgs<R> a, int it) {
 // (c) convergence test; beta = r.z_new / r.z; p = z + beta p
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_pcg_c(CgArgs<R> a, int it, int last) {
-  if (solve_done(a.sc)) return;
+  if (solve_done(a.sc, a.ctr)) return;
   __shared__ double sh[17];
   const double rz = sum_partials(a.partial + a.grid, a.grid, sh);
   const double rr = sum_partials(a.partial + 2 * a.grid, a.grid, sh);
@@ -500,6 +511,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_c(CgArgs<R> a, int it, int last)
 // init: b and r = b - A x0 in FP64 (corrections without SpMV as above)
 template <bool D16, bool PRED>
 __global__ __launch_bounds__(kBlock) void k_rinit(CgArgs<float> a, const double *mass64) {
+  if (a.ctr->stop) return;
   __shared__ double sh[17];
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
@@ -530,7 +542,7 @@ __global__ __launch_bounds__(kBlock) void k_rinit(CgArgs<float> a, const double 
 
 // inner init: r32 = r64, d = 0, p = dinv r32; tolerance relative to ||r32||
 __global__ __launch_bounds__(kBlock) void k_inner_init(CgArgs<float> a) {
-  if (a.sc->ref_done) return;
+  if (a.sc->ref_done || a.ctr->stop) return;
   __shared__ double sh[17];
   double v[2] = {0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.N;
@@ -549,7 +561,7 @@ __global__ __launch_bounds__(kBlock) void k_inner_init(CgArgs<float> a) {
 // x64 += d; r64 -= A d (FP64 operator); ||r64|| -> refinement converged?
 template <bool D16>
 __global__ __launch_bounds__(kBlock) void k_refine_update(CgArgs<float> a, const double *mass64) {
-  if (a.sc->ref_done) return;
+  if (a.sc->ref_done || a.ctr->stop) return;
   __shared__ double sh[17];
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
@@ -845,6 +857,7 @@ __global__ __launch_bounds__(kBlock) void k_iface_coeffs(IfaceDev f, const Weigh
 
 struct SubArgs {
   IfaceDev f;
+  const StepCounters *ctr;
   const Weights *w;
   int m, p, P, M, corr;
   const double *coefD;
@@ -934,6 +947,7 @@ __device__ double iface_fE(const SubArgs &A, const double *D, const int *I, cons
 // Substep p of interval m (p = P+1: only f^E at tau_m and the write-back).
 template <bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_iface_sub(SubArgs A) {
+  if (A.ctr->stop) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const IfaceDev &f = A.f;
   const int n = f.n_if;
@@ -986,6 +1000,7 @@ void launch_iface(const DevState &d, int m, bool corr, hipStream_t st) {
   if (!d.ifc.kind || d.ifc.n_if == 0) return;
   SubArgs A;
   A.f = d.ifc;
+  A.ctr = d.ctr;
   A.w = d.w;
   A.m = m;
   A.P = d.P;

@@ -64,7 +64,8 @@ struct StepCounters {
   long long refine_steps;
   int max_iters;
   int fail;                 // solves that hit their budget
-  int pad[2];
+  int stop;                 // residual control: no further sweeps this step
+  int sweeps;               // sweeps run when stop was set
   double resid[17];         // residual of iterate k
   int slot_iters[kSlots];   // iterations of each solve of the step (-1: budget hit)
   int slot_rounds[kSlots];  // refinement rounds of each solve (-1: failed)
@@ -117,6 +118,7 @@ struct CoefLayout {
 
 // Everything the kernels of one context touch.
 struct DevState {
+  double sweep_tol = 0.0;  // > 0: residual-controlled sweeps
   int64_t N = 0;
   int M = 0, P = 0, K = 0;
   double dtau_h[kMaxM + 1] = {};      // host copy of the interval lengths
