@@ -194,6 +194,7 @@ def main():
         out["fp32_refine"] = precision_form(pkg, args)
     if args.config == "machine":
         out["stationary"] = stationary_form(pkg, args)
+        out["residual_control"] = residual_control_form(pkg, args, wall / args.steps)
     if args.ensemble_steps > 0 and args.config == "machine":
         import mrsdc_inputs as mi
         out["ensemble"] = ensemble(pkg, args, mi.FP32_REFINE)
@@ -213,6 +214,41 @@ def calibrate_copy(mib):
     dst.copy_(src)
     torch.cuda.synchronize()
     print(f"[bench] calibration copy of {mib} MiB done", file=sys.stderr, flush=True)
+
+
+def residual_control_form(pkg, args, fixed_step_s):
+    """The machine with residual-controlled sweeps: the tolerance sits between
+    the residuals of iterates 1 and 2 of the first step; eta and sweeps per
+    step beside the fixed-K run, and (CPU leg) the error against the oracle
+    run with the same rule."""
+    import dataclasses
+    import mrsdc_inputs as mi
+    pb = mi.machine_310k(nsteps=args.steps)
+    probe = pkg.simulation(pb, device=0, final_residual=1)
+    r = probe.advance(pb.scheme.dt)["residual"]
+    probe.destroy()
+    tol = float(np.sqrt(r[1] * r[2]))
+    sc = dataclasses.replace(pb.scheme, sweep_tol=tol)
+    ctx = pkg.simulation(dataclasses.replace(pb, scheme=sc), device=0)
+    ctx.advance(args.warmup * pb.scheme.dt)
+    t = time.perf_counter()
+    st = ctx.advance(args.steps * pb.scheme.dt)
+    wall = time.perf_counter() - t
+    ctx.destroy()
+    out = {"sweep_tol": tol, "sweeps_per_step": st["sweeps"] / args.steps,
+           "ms_per_step": wall / args.steps * 1e3, "eta": pb.scheme.dt * args.steps / wall,
+           "speedup_vs_fixed_K": fixed_step_s / (wall / args.steps)}
+    if not args.no_cpu_baseline:
+        import oracle
+        S = args.cpu_steps
+        g = pkg.simulation(dataclasses.replace(pb, scheme=sc), device=0)
+        g.advance(S * pb.scheme.dt)
+        Tg = pkg.get_state(g, pb)
+        g.destroy()
+        Tref, ost = oracle.run(pb, nsteps=S, scheme=sc)
+        out["rel_l2_vs_oracle"] = float(np.linalg.norm(Tg - Tref) / np.linalg.norm(Tref))
+        out["oracle_sweeps_per_step"] = ost["sweeps"] / S
+    return out
 
 
 def stationary_form(pkg, args):
