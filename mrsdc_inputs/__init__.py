@@ -6,7 +6,8 @@ contains none of the time-stepping method's arithmetic.
 """
 from .mesh import FACES, Body, Face, box  # noqa: F401
 from .problems import (  # noqa: F401
-    EQUI_NOLEFT, FP32_REFINE, FP64, LOBATTO, MESH_LEVELS, Contact, Motion, Patch, Problem,
+    EQUI_NOLEFT, FP32_REFINE, FP64, LOBATTO, MESH_LEVELS, MULTIRATE, SINGLE_RATE, Contact, Motion,
+    Patch, Problem,
     Scheme, box_patch_2673, machine_310k, machine_310k_fp32, ensemble_member, machine, noise_T0, patch_box,
     scenario_params, serving_trace,
 )

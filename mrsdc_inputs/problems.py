@@ -31,6 +31,8 @@ LOBATTO = 0
 EQUI_NOLEFT = 1
 FP64 = 0
 FP32_REFINE = 1
+MULTIRATE = 0  # the method of section 3
+SINGLE_RATE = 1  # single-rate SDC with the coupling implicit (section 5 comparison)
 
 
 @dataclass
@@ -94,6 +96,7 @@ class Scheme:
     refine_maxit: int = 20
     inner_rtol: float = 1e-6
     sweep_tol: float = 0.0  # > 0: residual-controlled number of sweeps (at most K)
+    method: int = MULTIRATE
 
 
 @dataclass

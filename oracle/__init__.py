@@ -58,7 +58,8 @@ class _Problem(C.Structure):
 
 class _Scheme(C.Structure):
     _fields_ = [("M", C.c_int), ("family", C.c_int), ("P", C.c_int), ("K", C.c_int),
-                ("dt", C.c_double), ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int), ("sweep_tol", C.c_double)]
+                ("dt", C.c_double), ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int), ("sweep_tol", C.c_double),
+                ("method", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -162,6 +163,7 @@ def _scheme(sc):
     s.M, s.family, s.P, s.K = sc.M, sc.family, sc.P, sc.K
     s.dt, s.pcg_rtol, s.pcg_maxit = sc.dt, sc.pcg_rtol, sc.pcg_maxit
     s.sweep_tol = getattr(sc, "sweep_tol", 0.0)
+    s.method = getattr(sc, "method", 0)
     return s
 
 

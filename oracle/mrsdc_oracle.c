@@ -324,10 +324,19 @@ typedef struct {
   const orc_problem *pb;
   int64_t N;
   double *mass, *Ldiag, *r, *z, *p, *q, *diag;
+  /* single-rate method: with cpl set, the part of f^E(., t_cpl) linear in T
+   * joins the operator; e0 = f^E(0, t_cpl), e1 scratch */
+  int cpl;
+  double t_cpl;
+  double *e0, *e1;
 } solver;
 
 static void apply_A(solver *S, double dtau, const double *x, double *y) {
   apply_L(S->pb, x, y);
+  if (S->cpl) { /* (K + h R) x - (f^E(x, t) - f^E(0, t)) */
+    orc_fE(S->pb, S->t_cpl, x, S->e1);
+    for (int64_t i = 0; i < S->N; ++i) y[i] -= S->e1[i] - S->e0[i];
+  }
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < S->N; ++i) y[i] = S->mass[i] * x[i] + dtau * y[i];
 }
@@ -394,6 +403,7 @@ static int solver_init(solver *S, const orc_problem *pb) {
 
 static void solver_free(solver *S) {
   free(S->mass); free(S->Ldiag); free(S->r); free(S->z); free(S->p); free(S->q); free(S->diag);
+  free(S->e0); free(S->e1);
 }
 
 int orc_solve(const orc_problem *pb, double dtau, const double *b, double *x, double rtol,
@@ -430,15 +440,153 @@ int orc_stationary(const orc_problem *pb, double *T, double rtol, int maxit) {
 
 static int validate(const orc_problem *pb, const orc_scheme *sc) {
   if (!pb || !sc || pb->nbody < 1 || pb->nbody > 2) return -1;
-  if (sc->M < 2 || sc->P < 1 || sc->K < 0 || !(sc->dt > 0)) return -1;
+  if (sc->M < 1 || sc->P < 1 || sc->K < 0 || !(sc->dt > 0)) return -1;
+  if (sc->M < 2 && sc->family == ORC_LOBATTO) return -1;
+  if (sc->method != ORC_MULTIRATE && sc->method != ORC_SINGLE_RATE) return -1;
   if (sc->family == ORC_LOBATTO && sc->M > 5) return -1;
   if (pb->cpl.kind != ORC_NONE && !(pb->cpl.period > 0)) return -1;
   return 0;
 }
 
+/* Single-rate SDC (§3, "Single-rate spectral deferred correction") in the
+ * form the work-precision study of §5 compares against: the part of f^E that
+ * is linear in T joins f^I, so the implicit function at node tau_m is
+ *     J_m(x) = f^I(x) + f^E(x, tau_m) - f^E(0, tau_m),
+ * and the rest, f^E(0, tau_m) (friction or patch flux), is a source taken at
+ * the node time like g.  Nothing explicit is left: the predictor is implicit
+ * Euler from node to node, and eq. sdc_sweep loses its f^E difference term.
+ * The quadrature I_{m-1}^m = sum_j s_{m,j} F(T^k_j, tau_j) uses the full
+ * right-hand side.  One equidistant node with K = 0 is implicit Euler for the
+ * whole coupled system. */
+static int run_single_rate(const orc_problem *pb, const orc_scheme *sc, double t0, int nsteps,
+                           double *T, double *residuals, orc_stats *stats) {
+  const double tstart = now_s();
+  const int M = sc->M, P = sc->P, Ksw = sc->K, M1 = M + 1, P1 = P + 1;
+  const int64_t N = total_n(pb);
+  const size_t nv = (size_t)N;
+  double tau[64], dtau[64];
+  double *s = malloc(sizeof(double) * M1 * M1), *shat = malloc(sizeof(double) * M1 * P1);
+  double *stil = malloc(sizeof(double) * M1 * P1 * M1), *spq = malloc(sizeof(double) * M1 * P1 * P1);
+  double *g = malloc(sizeof(double) * nv), *Tn = malloc(sizeof(double) * nv);
+  double *Tst = malloc(sizeof(double) * nv * M1), *Tstn = malloc(sizeof(double) * nv * M1);
+  double *F = malloc(sizeof(double) * nv * M1), *Im = malloc(sizeof(double) * nv * M1);
+  double *b = malloc(sizeof(double) * nv), *Jk = malloc(sizeof(double) * nv);
+  double *zero = calloc(nv, sizeof(double)); /* f^E(0, t) is the coupling source */
+  solver S;
+  memset(&S, 0, sizeof S);
+  int rc = 0;
+  if (!s || !shat || !stil || !spq || !g || !Tn || !Tst || !Tstn || !F || !Im || !b || !Jk ||
+      !zero || orc_weights(M, sc->family, P, sc->dt, tau, s, shat, stil, spq) ||
+      solver_init(&S, pb) || !(S.e0 = malloc(sizeof(double) * nv)) ||
+      !(S.e1 = malloc(sizeof(double) * nv))) {
+    rc = -1;
+    goto done;
+  }
+  for (int m = 1; m <= M; ++m) dtau[m] = tau[m] - tau[m - 1];
+#define V(base, k) ((base) + (size_t)(k) * nv)
+  source_g(pb, g);
+  S.cpl = 1;
+  orc_stats st;
+  memset(&st, 0, sizeof st);
+  st.threads = orc_max_threads();
+  double tp = 0;
+
+  for (int n = 0; n < nsteps; ++n) {
+    const double tn = t0 + n * sc->dt;
+    memcpy(Tn, T, sizeof(double) * nv);
+    /* predictor: M T_m = M T_{m-1} + dtau_m (J_m(T_m) + g + f^E(0, tau_m)) */
+    memcpy(V(Tst, 0), Tn, sizeof(double) * nv);
+    for (int m = 1; m <= M; ++m) {
+      const double *Tprev = V(Tst, m - 1);
+      double *xs = V(Tst, m);
+      memcpy(xs, Tprev, sizeof(double) * nv);
+      if (dtau[m] == 0.0) continue;
+      S.t_cpl = tn + tau[m];
+      orc_fE(pb, S.t_cpl, zero, S.e0);
+      for (int64_t i = 0; i < N; ++i) b[i] = S.mass[i] * Tprev[i] + dtau[m] * (g[i] + S.e0[i]);
+      double t1 = now_s();
+      int it = pcg(&S, dtau[m], b, xs, sc->pcg_rtol, sc->pcg_maxit);
+      tp += now_s() - t1;
+      if (it < 0) { rc = -2; goto done; }
+      st.solves++; st.pcg_iters += it; if (it > st.max_iters) st.max_iters = it;
+    }
+    const int passes = residuals ? Ksw + 1 : Ksw;
+    for (int k = 1; k <= passes; ++k) {
+      /* F_j = f^I(T^k_j) + f^E(T^k_j, tau_j) + g at every standard node */
+      for (int j = 1; j <= M; ++j) {
+        double *Fj = V(F, j);
+        orc_fE(pb, tn + tau[j], V(Tst, j), b);
+        st.fE_evals++;
+        apply_L(pb, V(Tst, j), Fj);
+        for (int64_t i = 0; i < N; ++i) Fj[i] = -Fj[i] + g[i] + b[i];
+      }
+      /* I_{m-1}^m = sum_j s_{m,j} F_j, and the residual of iterate k-1 */
+      for (int m = 1; m <= M; ++m)
+        for (int64_t i = 0; i < N; ++i) {
+          double acc = 0;
+          for (int j = 1; j <= M; ++j) acc += s[m * M1 + j] * F[(size_t)j * nv + i];
+          Im[(size_t)m * nv + i] = acc;
+        }
+      if (residuals || sc->sweep_tol > 0) {
+        double rmax = 0;
+        for (int64_t i = 0; i < N; ++i) {
+          double cum = 0;
+          for (int m = 1; m <= M; ++m) {
+            if (dtau[m] == 0.0) continue;
+            cum += Im[(size_t)m * nv + i];
+            double r = fabs(S.mass[i] * Tst[(size_t)m * nv + i] - S.mass[i] * Tn[i] - cum);
+            if (r > rmax) rmax = r;
+          }
+        }
+        if (residuals) residuals[(size_t)n * (Ksw + 1) + (k - 1)] = rmax;
+        if (sc->sweep_tol > 0 && rmax <= sc->sweep_tol) break;
+      }
+      if (k > Ksw) break;
+      st.sweeps++;
+      /* eq. sdc_sweep: M T^{k+1}_m = M T^{k+1}_{m-1}
+       *                 + dtau_m (J_m(T^{k+1}_m) - J_m(T^k_m)) + I_{m-1}^m */
+      memcpy(V(Tstn, 0), Tn, sizeof(double) * nv);
+      for (int m = 1; m <= M; ++m) {
+        const double *Tprev = V(Tstn, m - 1), *Tk = V(Tst, m);
+        double *xs = V(Tstn, m);
+        if (dtau[m] == 0.0) {
+          memcpy(xs, Tprev, sizeof(double) * nv);
+          continue;
+        }
+        S.t_cpl = tn + tau[m];
+        orc_fE(pb, S.t_cpl, zero, S.e0);
+        orc_fE(pb, S.t_cpl, Tk, S.e1);
+        apply_L(pb, Tk, Jk);
+        for (int64_t i = 0; i < N; ++i) Jk[i] = -Jk[i] + (S.e1[i] - S.e0[i]);
+        const double *Imm = V(Im, m);
+        for (int64_t i = 0; i < N; ++i) b[i] = S.mass[i] * Tprev[i] - dtau[m] * Jk[i] + Imm[i];
+        memcpy(xs, Tk, sizeof(double) * nv);
+        double t1 = now_s();
+        int it = pcg(&S, dtau[m], b, xs, sc->pcg_rtol, sc->pcg_maxit);
+        tp += now_s() - t1;
+        if (it < 0) { rc = -2; goto done; }
+        st.solves++; st.pcg_iters += it; if (it > st.max_iters) st.max_iters = it;
+      }
+      double *sw = Tst; Tst = Tstn; Tstn = sw;
+    }
+    memcpy(T, V(Tst, M), sizeof(double) * nv);
+  }
+#undef V
+  st.t_pcg = tp;
+  st.t_total = now_s() - tstart;
+  if (stats) *stats = st;
+done:
+  free(zero);
+  solver_free(&S);
+  free(s); free(shat); free(stil); free(spq);
+  free(g); free(Tn); free(Tst); free(Tstn); free(F); free(Im); free(b); free(Jk);
+  return rc;
+}
+
 int orc_run(const orc_problem *pb, const orc_scheme *sc, double t0, int nsteps, double *T,
             double *residuals, orc_stats *stats) {
   if (validate(pb, sc) || nsteps < 0) return -1;
+  if (sc->method == ORC_SINGLE_RATE) return run_single_rate(pb, sc, t0, nsteps, T, residuals, stats);
   const double tstart = now_s();
   const int M = sc->M, P = sc->P, Ksw = sc->K;
   const int M1 = M + 1, P1 = P + 1;

@@ -20,6 +20,7 @@ extern "C" {
 #endif
 
 enum { ORC_LOBATTO = 0, ORC_EQUI_NOLEFT = 1 };
+enum { ORC_MULTIRATE = 0, ORC_SINGLE_RATE = 1 };
 enum { ORC_NONE = 0, ORC_CONTACT = 1, ORC_PATCH = 2 };
 
 /* One body: linear finite element operators on its own mesh (paper §2). */
@@ -75,6 +76,8 @@ typedef struct {
   double pcg_rtol;
   int pcg_maxit;
   double sweep_tol; /* > 0: stop a step's sweeps once its residual is <= sweep_tol */
+  int method;       /* ORC_MULTIRATE (Alg. 1/2) | ORC_SINGLE_RATE (single-rate SDC of
+                       §3 with the whole coupling f^E in the implicit part; P unused) */
 } orc_scheme;
 
 typedef struct {
