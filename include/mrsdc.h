@@ -51,12 +51,15 @@ typedef enum {
 
 enum { MRSDC_FP64 = 0, MRSDC_FP32_REFINE = 1 };
 enum { MRSDC_LOBATTO = 0, MRSDC_EQUI_NOLEFT = 1 };
+enum { MRSDC_MULTIRATE = 0, MRSDC_SINGLE_RATE = 1 };
 
 typedef struct {
   int device;         /* HIP device ordinal */
   int precision;      /* MRSDC_FP64, or MRSDC_FP32_REFINE: FP32 inner CG with FP64
                          iterative refinement (FP64 residual, FP64 node states) */
-  int M;              /* standard nodes, 2..8 (§3: tau_1 < ... < tau_M = t_{n+1}) */
+  int M;              /* standard nodes, 2..8 (§3: tau_1 < ... < tau_M = t_{n+1});
+                         1 is accepted for MRSDC_EQUI_NOLEFT (then the predictor
+                         of the single-rate method is implicit Euler) */
   int node_family;    /* MRSDC_LOBATTO (tau_1 = t_n, first interval skipped) or
                          MRSDC_EQUI_NOLEFT (tau_m = t_n + m dt / M, §3) */
   int P;              /* embedded nodes per standard interval, 1..32 (equidistant,
@@ -75,6 +78,14 @@ typedef struct {
                          is <= sweep_tol (at most K sweeps; §3 states that each
                          sweep reduces it by a factor proportional to dt);
                          0: always K sweeps.  Per scenario in batched contexts */
+  int method;         /* MRSDC_MULTIRATE: the method of §3 (f^E explicit on P
+                         embedded substeps).  MRSDC_SINGLE_RATE: the single-rate
+                         SDC used as comparison in §5, with the coupling f^E
+                         taken into the implicit part (each node solve is
+                         (diag(m) + dtau (K + h R + A_c(tau))) T = rhs, A_c the
+                         linear exchange operator of f^E at the node time) and
+                         no substeps; P is then unused.  FP64 only, single
+                         (non-batched) contexts only */
   void *stream;       /* hipStream_t to run on, or NULL for a library-owned stream */
 } mrsdc_config;
 

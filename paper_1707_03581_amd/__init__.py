@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libmrsdc.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5
 FP64, FP32_REFINE = 0, 1
 LOBATTO, EQUI_NOLEFT = 0, 1
+MULTIRATE, SINGLE_RATE = 0, 1
 FACE_TAGS = {"x0": 0, "x1": 1, "y0": 2, "y1": 3, "z0": 4, "z1": 5}
 _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOCONV: "ENOCONV",
           ESTATE: "ESTATE"}
@@ -34,7 +35,7 @@ class Config(C.Structure):
                 ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int), ("refine_rtol", C.c_double),
                 ("refine_maxit", C.c_int), ("inner_rtol", C.c_double),
                 ("final_residual", C.c_int), ("use_graph", C.c_int), ("sweep_tol", C.c_double),
-                ("stream", C.c_void_p)]
+                ("method", C.c_int), ("stream", C.c_void_p)]
 
 
 class Stats(C.Structure):
@@ -317,7 +318,8 @@ def config_from_scheme(scheme, device=0, **over) -> Config:
                          pcg_rtol=scheme.pcg_rtol, pcg_maxit=scheme.pcg_maxit,
                          refine_rtol=scheme.refine_rtol, refine_maxit=scheme.refine_maxit,
                          inner_rtol=scheme.inner_rtol,
-                         sweep_tol=getattr(scheme, "sweep_tol", 0.0))
+                         sweep_tol=getattr(scheme, "sweep_tol", 0.0),
+                         method=getattr(scheme, "method", MULTIRATE))
     for k, v in over.items():
         setattr(cfg, k, v)
     return cfg

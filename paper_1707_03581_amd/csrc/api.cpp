@@ -182,7 +182,10 @@ void free_device(mrsdc_ctx *c) {
 }
 
 bool valid_scheme(const mrsdc_config *cfg) {
-  if (cfg->M < 2 || cfg->M > kMaxM || cfg->P < 1 || cfg->P > kMaxP) return false;
+  if (cfg->M < 1 || cfg->M > kMaxM || cfg->P < 1 || cfg->P > kMaxP) return false;
+  if (cfg->M < 2 && cfg->node_family == MRSDC_LOBATTO) return false;
+  if (cfg->method != MRSDC_MULTIRATE && cfg->method != MRSDC_SINGLE_RATE) return false;
+  if (cfg->method == MRSDC_SINGLE_RATE && cfg->precision != MRSDC_FP64) return false;
   if (cfg->K < 0 || cfg->K > 16 || !(cfg->dt > 0) || !std::isfinite(cfg->dt)) return false;
   if (cfg->node_family != MRSDC_LOBATTO && cfg->node_family != MRSDC_EQUI_NOLEFT) return false;
   if (cfg->precision != MRSDC_FP64 && cfg->precision != MRSDC_FP32_REFINE) return false;
@@ -478,6 +481,7 @@ mrsdc_status prepare(mrsdc_ctx *c) {
   d.P = cfg.P;
   d.K = cfg.K;
   d.sweep_tol = cfg.sweep_tol;
+  d.single_rate = cfg.method == MRSDC_SINGLE_RATE;
   for (int m = 0; m <= cfg.M; ++m) d.dtau_h[m] = c->w.dtau[m];
   d.grid = (int)std::min<int64_t>((N + kBlock - 1) / kBlock, 1024);
   if (d.grid < 1) d.grid = 1;
@@ -485,6 +489,8 @@ mrsdc_status prepare(mrsdc_ctx *c) {
   const int S = batch ? c->S : 1;
   if (batch && c->cpl.kind == 2)
     return fail(c, MRSDC_EINVAL, "batched contexts support the contact coupling only");
+  if (batch && cfg.method != MRSDC_MULTIRATE)
+    return fail(c, MRSDC_EINVAL, "batched contexts run the multi-rate method");
 
   // ---- operator L = K + h R in SELL-64 ----
   const int64_t nslices = (N + kSlice - 1) / kSlice;
@@ -774,6 +780,9 @@ mrsdc_status prepare(mrsdc_ctx *c) {
     if ((st = dalloc(c, &d.Tbuf[0], (size_t)f.n_if * S)) ||
         (st = dalloc(c, &d.Tbuf[1], (size_t)f.n_if * S)) || (st = dalloc(c, &d.fst, (size_t)f.n_if * S)))
       return st;
+    if (d.single_rate &&
+        ((st = dalloc(c, &d.ifc_lin, (size_t)f.n_if)) || (st = dalloc(c, &d.ifc_src, (size_t)f.n_if))))
+      return st;
     const size_t ntab = (size_t)(cfg.M + 1) * (cfg.P + 1) * S;
     if ((st = dalloc(c, &d.coefD, ntab * coef_table_doubles(f))) ||
         (st = dalloc(c, &d.coefI, ntab * coef_table_ints(f))))
@@ -906,6 +915,34 @@ void enqueue_step(mrsdc_ctx *c) {
       if (e1) hipEventRecord(e1, st);
     }
     std::swap(d.Eold, d.Enew);
+  }
+  launch_step_end(d, c->cfg.dt, st);
+}
+
+// Single-rate SDC (the comparison method of §5): f^E joins the implicit part,
+// so every node solve carries the exchange operator A_c(tau_m) and the
+// coupling source at tau_m, and there are no embedded substeps.  The
+// predictor is implicit Euler node by node; a sweep evaluates the full right
+// hand side F_j = f^I(T_j) + g + f^E(T_j, tau_j) at the standard nodes and
+// integrates it with the weights s_mj alone.
+void enqueue_step_single(mrsdc_ctx *c) {
+  DevState &d = c->d;
+  const int M = c->cfg.M, K = c->cfg.K;
+  const bool lob = c->cfg.node_family == MRSDC_LOBATTO;
+  hipStream_t st = c->stream;
+  launch_clear_counters(d, st);
+  launch_iface_coeffs(d, st);
+  for (int m = 1; m <= M; ++m)
+    if (c->w.dtau[m] != 0.0) enqueue_solve(c, 0, m);
+  const int passes = c->cfg.final_residual ? K + 1 : K;
+  for (int k = 1; k <= passes; ++k) {
+    const int j0 = (lob && k > 1) ? 2 : 1;  // Lobatto T_1 = T_n: once per step
+    launch_f_multi(d, j0, M, st);
+    for (int j = j0; j <= M; ++j) launch_iface_F(d, j, st);
+    launch_quad_resid(d, k - 1, st);
+    if (k > K) break;
+    for (int m = 1; m <= M; ++m)
+      if (c->w.dtau[m] != 0.0) enqueue_solve(c, k, m);
   }
   launch_step_end(d, c->cfg.dt, st);
 }
@@ -1208,7 +1245,8 @@ mrsdc_status mrsdc_advance(mrsdc_ctx *c, double horizon, mrsdc_stats *stats) {
   const int Kc = c->cfg.K;
   for (int64_t n = 0; n < nsteps; ++n) {
     for (;;) {
-      enqueue_step(c);
+      if (c->d.single_rate) enqueue_step_single(c);
+      else enqueue_step(c);
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(c->ctr_host, c->d.ctr, sizeof(StepCounters), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(hipStreamSynchronize(c->stream));
@@ -1470,6 +1508,7 @@ mrsdc_status mrsdc_batch_create(mrsdc_ctx **out, const mrsdc_config *cfg, int S)
   if (!out) return MRSDC_EINVAL;
   *out = nullptr;
   if (S < 1 || S > kMaxS) return MRSDC_EINVAL;
+  if (cfg && cfg->method != MRSDC_MULTIRATE) return MRSDC_EINVAL;  // batches run the method of §3
   mrsdc_status st = mrsdc_create(out, cfg);
   if (st) return st;
   mrsdc_ctx *c = *out;

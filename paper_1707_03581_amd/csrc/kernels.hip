@@ -212,7 +212,7 @@ void launch_quad_resid(const DevState &d, int k, hipStream_t st) {
     a.I[m] = d.I[m];
   }
   a.mass = d.mass;
-  a.ifpos = d.ifc.kind ? d.ifpos : nullptr;
+  a.ifpos = (d.ifc.kind && !d.single_rate) ? d.ifpos : nullptr;  // embedded terms
   a.Eold = d.Eold;
   a.n_if = d.ifc.n_if;
   a.M = d.M;
@@ -258,6 +258,12 @@ struct CgArgs {
   // init / refinement
   double *x64, *b64, *r64;
   const double *Tprev, *F, *I;
+  // single-rate method: interface coupling of the implicit operator at this
+  // node (ifc_lin = dtau A_c(tau_m) x for the vector x last passed to the
+  // interface kernel, ifc_src = dtau times the coupling source), else null
+  int m;
+  const int *ifpos;
+  const double *ifc_lin, *ifc_src;
 };
 
 template <bool D16, typename R>
@@ -350,8 +356,16 @@ __global__ __launch_bounds__(kBlock) void k_init_pred(CgArgs<double> a) {
     if (row >= a.N) continue;
     const double Lx = sell_row<D16>(a.op, s, lane, row, a.Tprev);
     const double x0 = a.Tprev[row], mi = a.mass[row];
-    const double b = mi * x0 + a.dtau * a.g[row];
-    const double r = b - (mi * x0 + a.dtau * Lx);
+    double b = mi * x0 + a.dtau * a.g[row];
+    double Ax = mi * x0 + a.dtau * Lx;
+    if (a.ifc_lin) {
+      const int ip = a.ifpos[row];
+      if (ip >= 0) {
+        b += a.ifc_src[ip];
+        Ax += a.ifc_lin[ip];
+      }
+    }
+    const double r = b - Ax;
     const double z = a.dinv[row] * r;
     a.x[row] = x0;
     a.r[row] = r;
@@ -373,7 +387,11 @@ __global__ __launch_bounds__(kBlock) void k_init_corr(CgArgs<double> a) {
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.N;
        i += (int64_t)gridDim.x * kBlock) {
     const double mi = a.mass[i], tp = a.Tprev[i], x0 = a.x[i], Im = a.I[i];
-    const double b = mi * tp + a.dtau * (a.g[i] - a.F[i]) + Im;
+    double b = mi * tp + a.dtau * (a.g[i] - a.F[i]) + Im;
+    if (a.ifc_src) {
+      const int ip = a.ifpos[i];
+      if (ip >= 0) b += a.ifc_src[ip];
+    }
     const double r = mi * (tp - x0) + Im;
     const double z = a.dinv[i] * r;
     a.r[i] = r;
@@ -439,7 +457,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
     if (row >= a.N) continue;
     const R Lp = (R)sell_row_t<D16, R>(a.op, s, lane, row, a.p);
     const R pi = a.p[row];
-    const R qi = a.mass[row] * pi + (R)a.dtau * Lp;
+    R qi = a.mass[row] * pi + (R)a.dtau * Lp;
+    if (a.ifc_lin) {
+      const int ip = a.ifpos[row];
+      if (ip >= 0) qi += (R)a.ifc_lin[ip];
+    }
     a.q[row] = qi;
     v[0] += (double)pi * (double)qi;
   }
@@ -604,6 +626,11 @@ static CgArgs<double> cg64(const DevState &d, int m, int slot) {
   a.Tprev = d.T[m - 1];
   a.F = d.F[m];
   a.I = d.I[m];
+  a.m = m;
+  const bool cpl = d.single_rate && d.ifc.kind && d.ifc.n_if > 0;
+  a.ifpos = cpl ? d.ifpos : nullptr;
+  a.ifc_lin = cpl ? d.ifc_lin : nullptr;
+  a.ifc_src = cpl ? d.ifc_src : nullptr;
   return a;
 }
 
@@ -631,6 +658,10 @@ static CgArgs<float> cg32(const DevState &d, int m, int slot) {
   a.Tprev = d.T[m - 1];
   a.F = d.F[m];
   a.I = d.I[m];
+  a.m = m;
+  a.ifpos = nullptr;
+  a.ifc_lin = nullptr;
+  a.ifc_src = nullptr;
   return a;
 }
 
@@ -642,13 +673,16 @@ static void solve_reduce(const DevState &d, int slot, int mode, double rtol, int
 
 void launch_init_pred(const DevState &d, int m, int slot, double rtol, hipStream_t st) {
   CgArgs<double> a = cg64(d, m, slot);
+  if (a.ifc_lin) launch_iface_lin(d, m, d.T[m - 1], st);  // coupling of A x0 and its source
   if (d.op.d16) k_init_pred<true><<<d.grid, kBlock, 0, st>>>(a);
   else k_init_pred<false><<<d.grid, kBlock, 0, st>>>(a);
   solve_reduce(d, slot, 0, rtol, 0, false, st);
 }
 
 void launch_init_corr(const DevState &d, int m, int slot, double rtol, hipStream_t st) {
-  k_init_corr<<<d.grid, kBlock, 0, st>>>(cg64(d, m, slot));
+  const CgArgs<double> a = cg64(d, m, slot);
+  if (a.ifc_src) launch_iface_lin(d, m, d.T[m], st);  // the coupling source at tau_m
+  k_init_corr<<<d.grid, kBlock, 0, st>>>(a);
   solve_reduce(d, slot, 0, rtol, 0, false, st);
 }
 
@@ -658,6 +692,7 @@ static void pcg_iter(const DevState &d, const CgArgs<R> &a, int it, bool last, b
   // with events: the dispatch's own start/end timestamps (AMD launch extension)
   auto kern = d.op.d16 ? (tail ? k_pcg_a<true, 1, R> : k_pcg_a<true, 0, R>)
                        : (tail ? k_pcg_a<false, 1, R> : k_pcg_a<false, 0, R>);
+  if (a.ifc_lin) launch_iface_lin(d, a.m, (const double *)a.p, st);  // coupling of A p
   if (ev0) hipExtLaunchKernelGGL(kern, dim3(d.grid), dim3(kBlock), 0, st, ev0, ev1, 0, a, it);
   else kern<<<d.grid, kBlock, 0, st>>>(a, it);
   k_pcg_b<R><<<d.grid, kBlock, 0, st>>>(a, it);
@@ -681,6 +716,9 @@ static CgArgs<double> stationary_args(const DevState &d, const double *zeros, co
   a.x64 = d.T[0];
   a.Tprev = d.T[0];
   a.g = d.g;
+  a.ifpos = nullptr;  // conduction and Robin part only
+  a.ifc_lin = nullptr;
+  a.ifc_src = nullptr;
   return a;
 }
 
@@ -786,9 +824,12 @@ __device__ double motion_s(const IfaceDev &f, double t) {
 // v-extent of Gamma_R(t) (contact) or of the patch, and the friction density.
 __global__ __launch_bounds__(kBlock) void k_iface_coeffs(IfaceDev f, const Weights *w,
                                                         const double *tn, int P,
-                                                        double *coefD, int *coefI) {
+                                                        double *coefD, int *coefI,
+                                                        int nodes_only) {
   const int P1 = P + 1, tp = blockIdx.x, m = tp / P1, q = tp - m * P1;
-  if (m == 0 || w->dtau[m] == 0.0) return;
+  // nodes_only (single-rate method): the tables at the standard node times
+  // tau_m = tau_{m-1} + dtau_m (q = P), degenerate first interval included
+  if (nodes_only ? (m == 0 || q != P) : (m == 0 || w->dtau[m] == 0.0)) return;
   const CoefLayout L{f.nvf, f.nvm};
   double *D = coefD + (size_t)tp * L.dstride();
   int *I = coefI + (size_t)tp * L.istride();
@@ -881,9 +922,10 @@ __device__ inline double tif(const SubArgs &A, const double *Tin, int j) {
 }
 
 // f^E at interface point i (fixed-face points first, then moving-face points)
+// as the part linear in T (exchange) and the source (friction, patch flux)
 template <bool FIRST>
-__device__ double iface_fE(const SubArgs &A, const double *D, const int *I, const double *Tin,
-                           int i) {
+__device__ void iface_fE_parts(const SubArgs &A, const double *D, const int *I,
+                               const double *Tin, int i, double *lin, double *src) {
   const IfaceDev &f = A.f;
   const CoefLayout L{f.nvf, f.nvm};
   const double qf = D[0];
@@ -903,7 +945,11 @@ __device__ double iface_fE(const SubArgs &A, const double *D, const int *I, cons
       self += mu * acc;
     }
     const double hub = f.Hu[a] * D[L.Hv() + b];
-    if (f.kind == 2) return (f.q0 + f.alpha * f.Tfix) * hub - f.alpha * self;
+    if (f.kind == 2) {
+      *lin = -(f.alpha * self);
+      *src = (f.q0 + f.alpha * f.Tfix) * hub;
+      return;
+    }
     double cross = 0.0;
     const int c0 = f.clo[a], nc = f.ccnt[a];
     const int d0 = I[L.dlo() + b], nd = I[L.dcnt() + b];
@@ -914,7 +960,9 @@ __device__ double iface_fE(const SubArgs &A, const double *D, const int *I, cons
         acc += D[L.Cv() + kBand * b + id] * tif<FIRST>(A, Tin, f.nfix + c * f.nvm + d0 + id);
       cross += f.Cu[kBand * a + ic] * acc;
     }
-    return f.alpha * (cross - self) + f.split * qf * hub;
+    *lin = f.alpha * (cross - self);
+    *src = f.split * qf * hub;
+    return;
   }
   const int k = i - f.nfix;
   const int c = k / f.nvm, d = k - c * f.nvm;
@@ -941,7 +989,16 @@ __device__ double iface_fE(const SubArgs &A, const double *D, const int *I, cons
       acc += D[L.CvT() + kBand * d + ib] * tif<FIRST>(A, Tin, a * f.nvf + b0 + ib);
     cross += f.CuT[kBand * c + ia] * acc;
   }
-  return f.alpha * (cross - self) + (1.0 - f.split) * qf * f.Gu[c] * D[L.Gv() + d];
+  *lin = f.alpha * (cross - self);
+  *src = (1.0 - f.split) * qf * f.Gu[c] * D[L.Gv() + d];
+}
+
+template <bool FIRST>
+__device__ double iface_fE(const SubArgs &A, const double *D, const int *I, const double *Tin,
+                           int i) {
+  double lin, src;
+  iface_fE_parts<FIRST>(A, D, I, Tin, i, &lin, &src);
+  return src + lin;
 }
 
 // Substep p of interval m (p = P+1: only f^E at tau_m and the write-back).
@@ -993,7 +1050,63 @@ __global__ __launch_bounds__(kBlock) void k_iface_sub(SubArgs A) {
 void launch_iface_coeffs(const DevState &d, hipStream_t st) {
   if (!d.ifc.kind || d.ifc.n_if == 0) return;
   k_iface_coeffs<<<(d.M + 1) * (d.P + 1), kBlock, 0, st>>>(d.ifc, d.w, d.tn, d.P, d.coefD,
-                                                           d.coefI);
+                                                           d.coefI, d.single_rate);
+}
+
+// ---------------------------------------------------------------------------
+// single-rate method: the coupling at the standard node times, in the
+// implicit part.  MODE 0: F[m] += f^E(x, tau_m) on the interface rows (the
+// node values of the quadrature); MODE 1: ifc_lin = -dtau_m (exchange part
+// of f^E(x, tau_m)) = dtau_m A_c(tau_m) x and ifc_src = dtau_m (source part).
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_iface_node(SubArgs A, double dtau, double *F,
+                                                       double *lin, double *src) {
+  // node values stay whole after residual control ends the sweeps: the
+  // residual of the last iterate is still evaluated from them
+  if (MODE == 1 && A.ctr->stop) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.f.n_if) return;
+  const CoefLayout L{A.f.nvf, A.f.nvm};
+  const int tp = A.m * (A.P + 1) + A.P;
+  const double *D = A.coefD + (size_t)tp * L.dstride();
+  const int *I = A.coefI + (size_t)tp * L.istride();
+  double el, es;
+  iface_fE_parts<true>(A, D, I, nullptr, i, &el, &es);
+  if (MODE == 0) {
+    F[A.f.rows[i]] += es + el;
+  } else {
+    lin[i] = -(dtau * el);
+    src[i] = dtau * es;
+  }
+}
+
+static SubArgs node_args(const DevState &d, int m, const double *x) {
+  SubArgs A{};
+  A.f = d.ifc;
+  A.ctr = d.ctr;
+  A.w = d.w;
+  A.m = m;
+  A.P = d.P;
+  A.M = d.M;
+  A.coefD = d.coefD;
+  A.coefI = d.coefI;
+  A.Tprev = x;
+  return A;
+}
+
+void launch_iface_F(const DevState &d, int j, hipStream_t st) {
+  if (!d.ifc.kind || d.ifc.n_if == 0) return;
+  const int grid = (d.ifc.n_if + kBlock - 1) / kBlock;
+  k_iface_node<0><<<grid, kBlock, 0, st>>>(node_args(d, j, d.T[j]), 0.0, d.F[j], nullptr,
+                                           nullptr);
+}
+
+void launch_iface_lin(const DevState &d, int m, const double *x, hipStream_t st) {
+  if (!d.ifc.kind || d.ifc.n_if == 0) return;
+  const int grid = (d.ifc.n_if + kBlock - 1) / kBlock;
+  k_iface_node<1><<<grid, kBlock, 0, st>>>(node_args(d, m, x), d.dtau_h[m], nullptr, d.ifc_lin,
+                                           d.ifc_src);
 }
 
 void launch_iface(const DevState &d, int m, bool corr, hipStream_t st) {

@@ -118,6 +118,9 @@ struct CoefLayout {
 
 // Everything the kernels of one context touch.
 struct DevState {
+  int single_rate = 0;        // coupling in the implicit part, no embedded substeps
+  double *ifc_lin = nullptr;  // [n_if] single-rate: dtau A_c x of the last interface call
+  double *ifc_src = nullptr;  // [n_if] single-rate: dtau times the coupling source
   double sweep_tol = 0.0;  // > 0: residual-controlled sweeps
   int64_t N = 0;
   int M = 0, P = 0, K = 0;
@@ -153,6 +156,8 @@ void launch_f_multi(const DevState &d, int j0, int j1, hipStream_t st);
 void launch_quad_resid(const DevState &d, int k, hipStream_t st);
 void launch_init_pred(const DevState &d, int m, int slot, double rtol, hipStream_t st);
 void launch_init_corr(const DevState &d, int m, int slot, double rtol, hipStream_t st);
+void launch_iface_F(const DevState &d, int j, hipStream_t st);
+void launch_iface_lin(const DevState &d, int m, const double *x, hipStream_t st);
 void launch_stationary_init(const DevState &d, const double *zeros, const double *dinv, int slot,
                             double rtol, hipStream_t st);
 void launch_stationary_iters(const DevState &d, const double *zeros, const double *dinv, int slot,

@@ -107,7 +107,7 @@ bool standard_nodes01(int M, int family, long double *x) {
 }
 
 bool build_weights(int M, int family, int P, double dt, Weights *w) {
-  if (M < 2 || M > kMaxM || P < 1 || P > kMaxP || !(dt > 0)) return false;
+  if (M < 1 || M > kMaxM || P < 1 || P > kMaxP || !(dt > 0)) return false;
   gauss_legendre();
   ld x[kMaxM + 1];
   if (!standard_nodes01(M, family, x)) return false;

@@ -61,3 +61,22 @@ def test_config_defaults_and_create_validation():
     with pytest.raises(m.MrsdcError) as e:
         m.Context(bad)
     assert e.value.status == m.EINVAL
+    assert cfg.method == m.MULTIRATE
+
+
+@pytest.mark.parametrize("over", [dict(method=m_) for m_ in (2, -1)] +
+                         [dict(method=1, precision=1), dict(method=1, M=1, node_family=0)])
+def test_create_rejects_bad_method(over):
+    """Unknown methods, the single-rate method outside FP64, and one Lobatto
+    node are rejected before any device is touched."""
+    import paper_1707_03581_amd as m
+    with pytest.raises(m.MrsdcError) as e:
+        m.Context(m.default_config(**over))
+    assert e.value.status == m.EINVAL
+
+
+def test_batch_rejects_single_rate():
+    import paper_1707_03581_amd as m
+    with pytest.raises(m.MrsdcError) as e:
+        m.BatchContext(m.default_config(method=m.SINGLE_RATE), 4)
+    assert e.value.status == m.EINVAL
