@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--profile", action="store_true",
                     help="event timing of kernel classes inside the timed region (adds overhead)")
     ap.add_argument("--op-reps", type=int, default=200, help="operator timing launches")
+    ap.add_argument("--wp-levels", type=int, default=5,
+                    help="work-precision study: time-step levels per method (0: skip)")
     ap.add_argument("--ensemble-precision", type=int, default=1, choices=[0, 1],
                     help="form of the stand-alone ensemble run: 0 FP64, 1 FP32+refine")
     ap.add_argument("--ensemble-steps", type=int, default=6,
@@ -194,6 +196,8 @@ def main():
         out["fp32_refine"] = precision_form(pkg, args)
     if args.config == "machine":
         out["stationary"] = stationary_form(pkg, args)
+        if args.wp_levels > 0:
+            out["work_precision"] = work_precision_form(pkg, args)
         out["residual_control"] = residual_control_form(pkg, args, wall / args.steps)
     if args.ensemble_steps > 0 and args.config == "machine":
         import mrsdc_inputs as mi
@@ -249,6 +253,61 @@ def residual_control_form(pkg, args, fixed_step_s):
         out["rel_l2_vs_oracle"] = float(np.linalg.norm(Tg - Tref) / np.linalg.norm(Tref))
         out["oracle_sweeps_per_step"] = ost["sweeps"] / S
     return out
+
+
+def work_precision_form(pkg, args):
+    """Time-discretisation error against look-ahead factor for the three
+    method classes of the work-precision study: MRSDC (Lobatto M=3, P=2,
+    K=0,1,2), single-rate SDC (M=3, coupling implicit, K=0,1,2) and implicit
+    Euler, on the benchmark machine from its stationary field (uniform T_env)
+    over 10 motion periods.  The error is the max-norm difference at the end
+    time to a reference run of MRSDC with Lobatto M=5, P=8, K=7 at a quarter
+    of the finest level's dt; eta = simulated time / wall time of the advance."""
+    import dataclasses
+    import mrsdc_inputs as mi
+    base = mi.machine_310k(nsteps=1)
+    base.T0 = np.full(base.N, 20.0)
+    t_end = 10.0 * base.motion.period
+    n0 = 4  # steps per period at the coarsest level
+    levels = [n0 * 2**i for i in range(args.wp_levels)]
+
+    def run(sc):
+        pb = dataclasses.replace(base, scheme=sc)
+        ctx = pkg.simulation(pb, device=0)
+        ctx.advance(0.0)  # device state built outside the timed advance
+        st = ctx.advance(t_end)
+        T = pkg.get_state(ctx, pb)
+        ctx.destroy()
+        return T, st
+
+    dt_ref = base.motion.period / (4 * levels[-1])
+    t = time.perf_counter()
+    Tref, _ = run(mi.Scheme(M=5, family=mi.LOBATTO, P=8, K=7, dt=dt_ref))
+    print(f"[bench] work-precision reference ({t_end / dt_ref:.0f} steps) "
+          f"{time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
+    rise = float(np.abs(Tref - 20.0).max())
+    methods = [(f"MRSDC(3,2) k={k}", dict(M=3, family=mi.LOBATTO, P=2, K=k)) for k in (0, 1, 2)]
+    methods += [(f"SDC(3) k={k}", dict(M=3, family=mi.LOBATTO, P=1, K=k, method=mi.SINGLE_RATE))
+                for k in (0, 1, 2)]
+    methods += [("implicit Euler", dict(M=1, family=mi.EQUI_NOLEFT, P=1, K=0,
+                                        method=mi.SINGLE_RATE))]
+    curves = []
+    for name, kw in methods:
+        pts = []
+        for n in levels:
+            dt = base.motion.period / n
+            T, st = run(mi.Scheme(dt=dt, **kw))
+            err = float(np.abs(T - Tref).max())
+            pts.append({"dt_s": dt, "steps": st["steps"], "eta": t_end / st["wall_s"],
+                        "max_err_K": err, "rel_err": err / rise,
+                        "cg_iters": st["pcg_iters"]})
+        curves.append({"method": name, "points": pts})
+        print(f"[bench] work-precision {name}: " +
+              " ".join(f"(eta {p['eta']:.0f}, err {p['rel_err']:.1e})" for p in pts),
+              file=sys.stderr, flush=True)
+    return {"workload": base.name, "t_end_s": t_end, "initial": "stationary (uniform T_env)",
+            "reference": {"method": "MRSDC Lobatto M=5 P=8 K=7", "dt_s": dt_ref},
+            "max_temperature_rise_K": rise, "curves": curves}
 
 
 def stationary_form(pkg, args):
