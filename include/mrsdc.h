@@ -270,6 +270,59 @@ mrsdc_status mrsdc_profile_read(const mrsdc_ctx *ctx, mrsdc_kernel_times *out);
  * advance); overwrites only CG scratch vectors.  For roofline measurement. */
 mrsdc_status mrsdc_time_operator(mrsdc_ctx *ctx, int reps, double *avg_us, int64_t *bytes);
 
+/* ---- thermo-elastic deformation of one body (§5, deformation paragraphs) ----
+ *
+ * Linear elasticity driven by the temperature field: K_u u = G (T - T_ref),
+ * with K_u the symmetric positive definite stiffness over the free
+ * displacement DOFs (the caller assembles it and removes the Dirichlet DOFs)
+ * and G the thermal load operator (n x nodes of the body).  As in §5 the
+ * matrix is factorised once and every output is a forward and a backward
+ * solve.  The factorisation is a block LU of K_u seen as block tridiagonal:
+ * the rows are cut into blocks of the matrix half-bandwidth b (so only
+ * neighbouring blocks couple), S_0 = A_00, S_k = A_kk - A_{k,k-1} S_{k-1}^{-1}
+ * A_{k-1,k}, and the device keeps W_k = S_k^{-1} as dense FP64 blocks padded
+ * to a multiple of 64 (about n (b + 64) 8 bytes; number DOFs so that b is
+ * small, e.g. plane by plane).  Forward: w_k = W_k (f_k - A_{k,k-1} w_{k-1});
+ * backward: u_k = w_k - W_k A_{k,k+1} u_{k+1}.  FP64 throughout. */
+typedef struct {
+  int64_t n;            /* free displacement DOFs */
+  int64_t block;        /* block size b = half-bandwidth of K_u */
+  int64_t padded_block; /* b rounded up to a multiple of 64 */
+  int64_t nblocks;      /* ceil(n / b) */
+  int64_t factor_bytes; /* device bytes of the W_k */
+  double factor_ms;     /* wall time of the factorisation (device work included) */
+} mrsdc_deform_info;
+
+/* Register the deformation problem of `body` and factorise it on the device
+ * (synchronous).  rowptr[n+1] (int64), col (int32, sorted, in [0,n)) and Ku
+ * give K_u in CSR (full symmetric pattern); growptr[n+1], gcol (int32, in
+ * [0, nodes of the body)) and G give the thermal load operator.  Replaces an
+ * earlier registration.  EINVAL: bad CSR, non-finite values, or a
+ * non-positive pivot met during the factorisation (K_u not SPD); ENOMEM: the
+ * blocks do not fit; ESTATE: the body is not set or the context is batched. */
+mrsdc_status mrsdc_deform_setup(mrsdc_ctx *ctx, int body, int64_t n, int64_t nnz,
+                                const int64_t *rowptr, const int32_t *col, const double *Ku,
+                                int64_t gnnz, const int64_t *growptr, const int32_t *gcol,
+                                const double *G, double T_ref);
+
+/* Displacement u (n values, host array) of the registered body for the
+ * context's current temperature.  ESTATE before mrsdc_deform_setup. */
+mrsdc_status mrsdc_deform(mrsdc_ctx *ctx, double *u, int64_t n);
+
+/* Same, written to device memory dptr (n doubles); the copy is ordered after
+ * the solve on `stream` (hipStream_t, NULL: the context's stream). */
+mrsdc_status mrsdc_deform_device(mrsdc_ctx *ctx, void *dptr, int64_t n, void *stream);
+
+mrsdc_status mrsdc_deform_get_info(const mrsdc_ctx *ctx, mrsdc_deform_info *out);
+
+/* Run reps forward/backward solves back to back between HIP events on the
+ * context's stream: average microseconds per solve, and the average duration
+ * of the dense block product u = W_k v (the solve's dominant kernel, timed per
+ * launch with its own events) with its algorithmic bytes per launch
+ * (padded_block^2 * 8 + vectors).  For roofline measurement. */
+mrsdc_status mrsdc_deform_time(mrsdc_ctx *ctx, int reps, double *solve_us, double *gemv_us,
+                               int64_t *gemv_bytes);
+
 /* Library version string. */
 const char *mrsdc_version(void);
 

@@ -101,7 +101,23 @@ _SIGS = {
     "mrsdc_profile_read": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mrsdc_time_operator": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int64)]),
+    "mrsdc_deform_setup": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_double]),
+    "mrsdc_deform": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
+    "mrsdc_deform_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "mrsdc_deform_get_info": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mrsdc_deform_time": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }
+
+
+class DeformInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("block", C.c_int64), ("padded_block", C.c_int64),
+                ("nblocks", C.c_int64), ("factor_bytes", C.c_int64), ("factor_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 def lib():
@@ -246,6 +262,39 @@ class Context:
         kt = KernelTimes()
         self._chk(self._L.mrsdc_profile_read(self._h, C.byref(kt)))
         return kt.as_dict()
+
+    def deform_setup(self, el, body=0):
+        """Register and factorise the thermo-elastic problem of a body (an
+        object with n, rowptr, col, K, g_rowptr, g_col, G, T_ref)."""
+        rp = np.ascontiguousarray(el.rowptr, dtype=np.int64)
+        col = np.ascontiguousarray(el.col, dtype=np.int32)
+        K = np.ascontiguousarray(el.K, dtype=np.float64)
+        grp = np.ascontiguousarray(el.g_rowptr, dtype=np.int64)
+        gcol = np.ascontiguousarray(el.g_col, dtype=np.int32)
+        G = np.ascontiguousarray(el.G, dtype=np.float64)
+        self._chk(self._L.mrsdc_deform_setup(self._h, body, int(el.n), int(rp[-1]), _p(rp), _p(col),
+                                             _p(K), int(grp[-1]), _p(grp), _p(gcol), _p(G),
+                                             float(el.T_ref)))
+        self._df_n = int(el.n)
+        return self.deform_info()
+
+    def deform(self):
+        """Displacement of the registered body for the current temperature."""
+        out = np.empty(self._df_n)
+        self._chk(self._L.mrsdc_deform(self._h, _p(out), self._df_n))
+        return out
+
+    def deform_info(self):
+        info = DeformInfo()
+        self._chk(self._L.mrsdc_deform_get_info(self._h, C.byref(info)))
+        return info.as_dict()
+
+    def deform_time(self, reps=5):
+        """(microseconds per solve, microseconds per dense block product,
+        algorithmic bytes per block product)."""
+        a, b, n = C.c_double(), C.c_double(), C.c_int64()
+        self._chk(self._L.mrsdc_deform_time(self._h, reps, C.byref(a), C.byref(b), C.byref(n)))
+        return a.value, b.value, n.value
 
     def time_operator(self, reps=200):
         """(average microseconds per launch, algorithmic bytes per launch)."""

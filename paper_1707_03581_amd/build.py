@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmrsdc.so")
-SOURCES = ["api.cpp", "quadrature.cpp", "kernels.hip", "batch_kernels.hip"]
+SOURCES = ["api.cpp", "quadrature.cpp", "kernels.hip", "batch_kernels.hip", "deform_kernels.hip"]
 ARCH = os.environ.get("MRSDC_OFFLOAD_ARCH", "gfx950")
 
 

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "batch_internal.h"
+#include "deform_internal.h"
 #include "mrsdc_internal.h"
 
 using namespace mrsdc;
@@ -101,6 +102,15 @@ struct mrsdc_ctx {
   BatchArgs ba;
   BatchScalars *bsc_host = nullptr;       // pinned
   double *stage = nullptr;                // device staging vector [N]
+  // thermo-elastic deformation of one body (independent of the stepper's
+  // device state: kept when the operators change)
+  DeformDev df;
+  bool df_ready = false;
+  int df_body = 0;
+  int64_t df_nodes = 0;
+  std::vector<void *> df_allocs;
+  int64_t df_bytes = 0;
+  double df_factor_ms = 0.0;
 };
 
 namespace {
@@ -1497,6 +1507,7 @@ mrsdc_status mrsdc_destroy(mrsdc_ctx *c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   free_device(c);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  for (void *p : c->df_allocs) hipFree(p);
   if (c->ctr_host) hipHostFree(c->ctr_host);
   if (c->bsc_host) hipHostFree(c->bsc_host);
   for (hipEvent_t e : c->ev) hipEventDestroy(e);
@@ -1713,6 +1724,267 @@ mrsdc_status mrsdc_quadrature(int M, int node_family, int P, double dt, double *
   }
   delete w;
   return MRSDC_OK;
+}
+
+}  // extern "C"
+
+// ---- thermo-elastic deformation ----
+
+static mrsdc_status df_alloc_bytes(mrsdc_ctx *c, void **p, size_t bytes) {
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, std::max<size_t>(bytes, 8));
+  if (e != hipSuccess) {
+    hipGetLastError();
+    return fail(c, MRSDC_ENOMEM, "hipMalloc(%zu) for the deformation blocks failed: %s", bytes,
+                hipGetErrorString(e));
+  }
+  c->df_allocs.push_back(q);
+  c->df_bytes += (int64_t)bytes;
+  *p = q;
+  return MRSDC_OK;
+}
+
+template <typename T>
+static mrsdc_status df_upload(mrsdc_ctx *c, const T **p, const T *h, size_t n) {
+  void *q;
+  mrsdc_status s = df_alloc_bytes(c, &q, n * sizeof(T));
+  if (s) return s;
+  if (n) HIPCHK(hipMemcpy(q, h, n * sizeof(T), hipMemcpyHostToDevice));
+  *p = static_cast<const T *>(q);
+  return MRSDC_OK;
+}
+
+static void df_release(mrsdc_ctx *c) {
+  if (c->stream) hipStreamSynchronize(c->stream);
+  for (void *p : c->df_allocs) hipFree(p);
+  c->df_allocs.clear();
+  c->df_bytes = 0;
+  c->df_ready = false;
+  c->df = DeformDev();
+}
+
+static bool valid_csr(int64_t n, int64_t ncols, int64_t nnz, const int64_t *rowptr,
+                      const int32_t *col, bool sorted) {
+  if (rowptr[0] != 0 || rowptr[n] != nnz) return false;
+  for (int64_t i = 0; i < n; ++i) {
+    if (rowptr[i + 1] < rowptr[i]) return false;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+      if (col[e] < 0 || col[e] >= ncols) return false;
+      if (sorted && e > rowptr[i] && col[e] <= col[e - 1]) return false;
+    }
+  }
+  return true;
+}
+
+extern "C" {
+
+mrsdc_status mrsdc_deform_setup(mrsdc_ctx *c, int body, int64_t n, int64_t nnz,
+                                const int64_t *rowptr, const int32_t *col, const double *Ku,
+                                int64_t gnnz, const int64_t *growptr, const int32_t *gcol,
+                                const double *G, double T_ref) {
+  if (!c) return MRSDC_EINVAL;
+  if (c->S > 0) return fail(c, MRSDC_ESTATE, "batched context: deformation is per simulation");
+  if (body < 0 || body > 1 || !c->body[body].set) return fail(c, MRSDC_ESTATE, "body not set");
+  if (n < 1 || nnz < n || gnnz < 0 || !rowptr || !col || !Ku || !growptr || (gnnz && (!gcol || !G)))
+    return fail(c, MRSDC_EINVAL, "bad deformation operator arguments");
+  const int64_t nodes = c->body[body].n;
+  if (!valid_csr(n, n, nnz, rowptr, col, true) || !valid_csr(n, nodes, gnnz, growptr, gcol, false))
+    return fail(c, MRSDC_EINVAL, "malformed CSR of the stiffness or the thermal load operator");
+  if (!finite_all(Ku, nnz) || !finite_all(G, gnnz) || !std::isfinite(T_ref))
+    return fail(c, MRSDC_EINVAL, "non-finite deformation operator values");
+  df_release(c);
+  // blocks of the half-bandwidth: only neighbouring blocks couple
+  int64_t hb = 0;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) hb = std::max<int64_t>(hb, std::llabs(col[e] - i));
+  DeformDev D;
+  D.n = n;
+  D.bs = std::min<int64_t>(n, std::max<int64_t>(hb, 1));
+  D.bp = (D.bs + kGjTile - 1) / kGjTile * kGjTile;
+  D.nblk = (n + D.bs - 1) / D.bs;
+  if (D.bp > kMaxDeformBlock)
+    return fail(c, MRSDC_EINVAL, "half-bandwidth %lld exceeds the block limit %lld (renumber the DOFs)",
+                (long long)hb, (long long)kMaxDeformBlock);
+  D.toff = c->off[body];
+  D.T_ref = T_ref;
+  // ELL of the couplings to the previous and the next block
+  std::vector<int> cntB(n, 0), cntU(n, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t k = i / D.bs, lo = k * D.bs, hi = std::min(n, lo + D.bs);
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+      cntB[i] += col[e] < lo;
+      cntU[i] += col[e] >= hi;
+    }
+  }
+  D.ellB = std::max(1, *std::max_element(cntB.begin(), cntB.end()));
+  D.ellU = std::max(1, *std::max_element(cntU.begin(), cntU.end()));
+  if (D.ellB > 128 || D.ellU > 128)
+    return fail(c, MRSDC_EINVAL, "more than 128 couplings of a row to a neighbouring block");
+  const size_t ellB = (size_t)D.nblk * D.ellB * D.bp, ellU = (size_t)D.nblk * D.ellU * D.bp;
+  std::vector<int32_t> bcol(ellB, 0), ucol(ellU, 0);
+  std::vector<double> bval(ellB, 0.0), uval(ellU, 0.0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t k = i / D.bs, lo = k * D.bs, hi = std::min(n, lo + D.bs), r = i - lo;
+    int qb = 0, qu = 0;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+      if (col[e] < lo) {
+        const size_t at = ((size_t)k * D.ellB + qb++) * D.bp + r;
+        bcol[at] = (int32_t)(col[e] - (lo - D.bs));
+        bval[at] = Ku[e];
+      } else if (col[e] >= hi) {
+        const size_t at = ((size_t)k * D.ellU + qu++) * D.bp + r;
+        ucol[at] = (int32_t)(col[e] - hi);
+        uval[at] = Ku[e];
+      }
+    }
+  }
+  // device and stream (the stepper's own state is built lazily elsewhere)
+  hipError_t he = hipSetDevice(c->cfg.device);
+  if (he != hipSuccess) return fail(c, MRSDC_EDEVICE, "hipSetDevice: %s", hipGetErrorString(he));
+  if (!c->stream) {
+    if (c->cfg.stream) {
+      c->stream = (hipStream_t)c->cfg.stream;
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
+    }
+  }
+  mrsdc_status st;
+  void *q;
+  if ((st = df_upload(c, &D.rowptr, rowptr, (size_t)n + 1)) || (st = df_upload(c, &D.col, col, (size_t)nnz)) ||
+      (st = df_upload(c, &D.val, Ku, (size_t)nnz)) ||
+      (st = df_upload(c, &D.growptr, growptr, (size_t)n + 1)) ||
+      (st = df_upload(c, &D.gcol, gcol, (size_t)gnnz)) || (st = df_upload(c, &D.gval, G, (size_t)gnnz)) ||
+      (st = df_upload(c, &D.bcol, bcol.data(), ellB)) || (st = df_upload(c, &D.bval, bval.data(), ellB)) ||
+      (st = df_upload(c, &D.ucol, ucol.data(), ellU)) || (st = df_upload(c, &D.uval, uval.data(), ellU))) {
+    df_release(c);
+    return st;
+  }
+  const size_t blk = (size_t)D.bp * D.bp * sizeof(double);
+  if ((st = df_alloc_bytes(c, &q, blk * D.nblk))) { df_release(c); return st; }
+  D.W = (double *)q;
+  if ((st = df_alloc_bytes(c, &q, blk))) { df_release(c); return st; }
+  D.T1 = (double *)q;
+  if ((st = df_alloc_bytes(c, &q, sizeof(double) * kGjTile * kGjTile))) { df_release(c); return st; }
+  D.piv = (double *)q;
+  if ((st = df_alloc_bytes(c, &q, sizeof(int)))) { df_release(c); return st; }
+  D.flag = (int *)q;
+  double *vec[4];
+  for (int v = 0; v < 4; ++v) {
+    if ((st = df_alloc_bytes(c, &q, sizeof(double) * (v == 3 ? D.bp : n)))) { df_release(c); return st; }
+    vec[v] = (double *)q;
+  }
+  D.f = vec[0];
+  D.w = vec[1];
+  D.x = vec[2];
+  D.c = vec[3];
+  auto t0 = std::chrono::steady_clock::now();
+  deform_factor(D, c->stream);
+  he = hipGetLastError();
+  if (he != hipSuccess) { df_release(c); return fail(c, MRSDC_EDEVICE, "factorisation launch: %s", hipGetErrorString(he)); }
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, D.flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->df_factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (bad) {
+    df_release(c);
+    return fail(c, MRSDC_EINVAL, "stiffness is not positive definite (%d non-positive pivots)", bad);
+  }
+  c->df = D;
+  c->df_ready = true;
+  c->df_body = body;
+  c->df_nodes = nodes;
+  return MRSDC_OK;
+}
+
+static mrsdc_status deform_run(mrsdc_ctx *c, int64_t n, hipEvent_t *ev) {
+  if (!c->df_ready) return fail(c, MRSDC_ESTATE, "no deformation problem registered");
+  if (n != c->df.n) return fail(c, MRSDC_EINVAL, "length mismatch (%lld DOFs)", (long long)c->df.n);
+  if (!c->body[c->df_body].set || c->body[c->df_body].n != c->df_nodes)
+    return fail(c, MRSDC_ESTATE, "the body changed since the deformation was registered");
+  mrsdc_status s = prepare(c);
+  if (s) return s;
+  if ((s = upload_T(c))) return s;
+  c->df.toff = c->off[c->df_body];
+  deform_solve(c->df, c->d.T[0], c->stream, ev);
+  HIPCHK(hipGetLastError());
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_deform(mrsdc_ctx *c, double *u, int64_t n) {
+  if (!c) return MRSDC_EINVAL;
+  if (!u) return fail(c, MRSDC_EINVAL, "null output");
+  mrsdc_status s = deform_run(c, n, nullptr);
+  if (s) return s;
+  HIPCHK(hipMemcpyAsync(u, c->df.x, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_deform_device(mrsdc_ctx *c, void *dptr, int64_t n, void *stream) {
+  if (!c) return MRSDC_EINVAL;
+  if (!dptr) return fail(c, MRSDC_EINVAL, "null output");
+  mrsdc_status s = deform_run(c, n, nullptr);
+  if (s) return s;
+  hipStream_t st = stream ? (hipStream_t)stream : c->stream;
+  if (st != c->stream) HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpyAsync(dptr, c->df.x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_deform_get_info(const mrsdc_ctx *c, mrsdc_deform_info *out) {
+  if (!c || !out) return MRSDC_EINVAL;
+  if (!c->df_ready) return MRSDC_ESTATE;
+  out->n = c->df.n;
+  out->block = c->df.bs;
+  out->padded_block = c->df.bp;
+  out->nblocks = c->df.nblk;
+  out->factor_bytes = c->df.nblk * c->df.bp * c->df.bp * (int64_t)sizeof(double);
+  out->factor_ms = c->df_factor_ms;
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_deform_time(mrsdc_ctx *c, int reps, double *solve_us, double *gemv_us,
+                               int64_t *gemv_bytes) {
+  if (!c) return MRSDC_EINVAL;
+  if (reps < 1 || !solve_us || !gemv_us || !gemv_bytes) return fail(c, MRSDC_EINVAL, "bad arguments");
+  if (!c->df_ready) return fail(c, MRSDC_ESTATE, "no deformation problem registered");
+  const DeformDev &D = c->df;
+  const int ng = (int)(2 * D.nblk - 1);
+  std::vector<hipEvent_t> ev(2 * (size_t)ng);
+  for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  mrsdc_status s = deform_run(c, D.n, nullptr);  // warm
+  if (!s) {
+    HIPCHK(hipEventRecord(a, c->stream));
+    for (int r = 0; r < reps && !s; ++r) s = deform_run(c, D.n, nullptr);
+    HIPCHK(hipEventRecord(b, c->stream));
+  }
+  if (!s) s = deform_run(c, D.n, ev.data());
+  if (!s) HIPCHK(hipStreamSynchronize(c->stream));
+  double gsum = 0.0;
+  int64_t bytes = 0;
+  if (!s) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    *solve_us = 1e3 * ms / reps;
+    for (int g = 0; g < ng; ++g) {
+      float m = 0.f;
+      HIPCHK(hipEventElapsedTime(&m, ev[2 * g], ev[2 * g + 1]));
+      gsum += 1e3 * m;
+      // forward k = g, backward k = 2 nblk - 2 - g: W rows read in full, v, out (+ base)
+      const int64_t k = g < D.nblk ? g : 2 * D.nblk - 2 - g;
+      bytes += D.rows(k) * D.bp * 8 + D.bp * 8 + D.rows(k) * 8 * (g < D.nblk ? 1 : 2);
+    }
+    *gemv_us = gsum / ng;
+    *gemv_bytes = bytes / ng;
+  }
+  for (auto &e : ev) hipEventDestroy(e);
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return s;
 }
 
 }  // extern "C"

@@ -1,0 +1,55 @@
+// Device state of the thermo-elastic deformation solve (block LU of the
+// banded stiffness, factorised once; forward/backward block solves).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mrsdc {
+
+constexpr int kGjTile = 64;              // Gauss-Jordan pivot width and tile size
+constexpr int64_t kMaxDeformBlock = 8192;  // padded block: one row of it in LDS (64 KB)
+
+struct DeformDev {
+  int64_t n = 0;     // free displacement DOFs
+  int64_t bs = 0;    // block size (>= half-bandwidth)
+  int64_t bp = 0;    // bs rounded up to a multiple of kGjTile
+  int64_t nblk = 0;  // ceil(n / bs)
+  int ellB = 0;      // ELL width of A_{k,k-1}
+  int ellU = 0;      // ELL width of A_{k,k+1}
+  int64_t toff = 0;  // first node of the body in the temperature vector
+  double T_ref = 0.0;
+  // K_u (CSR, full symmetric pattern) and the thermal load operator G (CSR)
+  const int64_t *rowptr = nullptr;
+  const int32_t *col = nullptr;
+  const double *val = nullptr;
+  const int64_t *growptr = nullptr;
+  const int32_t *gcol = nullptr;
+  const double *gval = nullptr;
+  // couplings of block k to block k-1 (B) and k+1 (U): ELL [nblk][ell][bp],
+  // columns local to the neighbouring block, padding entries (0, 0)
+  const int32_t *bcol = nullptr;
+  const double *bval = nullptr;
+  const int32_t *ucol = nullptr;
+  const double *uval = nullptr;
+  double *W = nullptr;    // [nblk][bp][bp]: S_k^{-1}
+  double *T1 = nullptr;   // [bp][bp]: A_{k,k-1} W_{k-1}
+  double *piv = nullptr;  // [64][64]: inverse of the current pivot tile
+  int *flag = nullptr;    // count of non-positive pivots
+  double *f = nullptr;    // [n] thermal load
+  double *w = nullptr;    // [n] forward results W_k c_k
+  double *x = nullptr;    // [n] displacement
+  double *c = nullptr;    // [bp] block right-hand side
+
+  __host__ __device__ int64_t lo(int64_t k) const { return k * bs; }
+  __host__ __device__ int64_t rows(int64_t k) const { return (k + 1) * bs < n ? bs : n - k * bs; }
+};
+
+// Factorise: for every block the Schur complement S_k, inverted in place by
+// blocked Gauss-Jordan elimination into W_k.
+void deform_factor(const DeformDev &D, hipStream_t st);
+// u = K_u^{-1} G (T - T_ref) into D.x.  With gemv_ev (2 events per dense
+// block product, 2 nblk - 1 products) every product is timed.
+void deform_solve(const DeformDev &D, const double *T, hipStream_t st, hipEvent_t *gemv_ev);
+
+}  // namespace mrsdc

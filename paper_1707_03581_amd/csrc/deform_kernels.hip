@@ -1,0 +1,345 @@
+// Thermo-elastic deformation on the device: the stiffness K_u is banded with
+// half-bandwidth <= bs, so cut into blocks of bs rows it is block tridiagonal.
+// Block LU (block Gaussian elimination):
+//   S_0 = A_00,  S_k = A_kk - A_{k,k-1} W_{k-1} A_{k-1,k},  W_k = S_k^{-1}
+//   forward   w_k = W_k (f_k - A_{k,k-1} w_{k-1})
+//   backward  u_k = w_k - W_k A_{k,k+1} u_{k+1}   (u_last = w_last)
+// W_k is dense (the fill of the band), kept padded to bp (a multiple of 64)
+// with an identity in the padding.  S_k is inverted in place by blocked
+// Gauss-Jordan elimination with 64 x 64 pivot tiles; no pivoting is needed
+// because S_k is symmetric positive definite (a Schur complement of an SPD
+// matrix).  The solves are bandwidth-bound dense products with the W_k.
+#include <hip/hip_ext.h>
+
+#include "deform_internal.h"
+
+namespace mrsdc {
+
+namespace {
+
+constexpr int kT = kGjTile;
+constexpr int kThreads = 256;
+
+// ---------------------------------------------------------------------------
+// factorisation
+// ---------------------------------------------------------------------------
+
+// T1 = A_{k,k-1} W_{k-1}: row i of T1 combines the W_{k-1} rows named by the
+// entries of row i of the coupling block.
+__global__ __launch_bounds__(kThreads) void k_schur_t(DeformDev D, int64_t k) {
+  __shared__ double sv[128];
+  __shared__ int sc[128];
+  const int64_t i = blockIdx.x;
+  const int64_t bp = D.bp;
+  const int E = D.ellB;
+  const int64_t eb = k * (int64_t)E * bp;
+  for (int e = threadIdx.x; e < E; e += kThreads) {
+    sv[e] = D.bval[eb + e * bp + i];
+    sc[e] = D.bcol[eb + e * bp + i];
+  }
+  __syncthreads();
+  const double *Wp = D.W + (k - 1) * bp * bp;
+  double *out = D.T1 + i * bp;
+  for (int64_t j = threadIdx.x; j < bp; j += kThreads) {
+    double a = 0.0;
+    for (int e = 0; e < E; ++e) a = fma(sv[e], Wp[(int64_t)sc[e] * bp + j], a);
+    out[j] = a;
+  }
+}
+
+// Row i of S_k = A_kk - T1 A_{k,k-1}^T (k > 0), padded with the identity.
+__global__ __launch_bounds__(kThreads) void k_schur_s(DeformDev D, int64_t k) {
+  extern __shared__ double trow[];
+  const int64_t i = blockIdx.x;
+  const int64_t bp = D.bp, bk = D.rows(k), lo = D.lo(k);
+  double *S = D.W + k * bp * bp + i * bp;
+  if (i >= bk) {
+    for (int64_t j = threadIdx.x; j < bp; j += kThreads) S[j] = (j == i) ? 1.0 : 0.0;
+    return;
+  }
+  if (k > 0) {
+    for (int64_t j = threadIdx.x; j < bp; j += kThreads) trow[j] = D.T1[i * bp + j];
+    __syncthreads();
+  }
+  const int E = D.ellB;
+  const int64_t eb = k * (int64_t)E * bp;
+  for (int64_t j = threadIdx.x; j < bp; j += kThreads) {
+    double s = 0.0;
+    if (k > 0 && j < bk)
+      for (int e = 0; e < E; ++e) s = fma(-D.bval[eb + e * bp + j], trow[D.bcol[eb + e * bp + j]], s);
+    S[j] = s;
+  }
+  __syncthreads();  // the row's own entries land after every thread wrote its part
+  const int64_t r = lo + i;
+  const int64_t e0 = D.rowptr[r], e1 = D.rowptr[r + 1];
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
+    const int64_t cidx = D.col[e];
+    if (cidx >= lo && cidx < lo + bk) S[cidx - lo] += D.val[e];
+  }
+}
+
+// Invert the 64 x 64 pivot tile (p, p) of S in LDS by Gauss-Jordan steps;
+// the result goes to piv.  A pivot that is not positive is counted.
+__global__ __launch_bounds__(kThreads) void k_gj_pivot(const double *S, int64_t ld, int p,
+                                                       double *piv, int *flag) {
+  __shared__ double A[kT][kT + 1];
+  const int t = threadIdx.x;
+  const double *P = S + (int64_t)p * kT * ld + (int64_t)p * kT;
+  for (int e = t; e < kT * kT; e += kThreads) A[e / kT][e % kT] = P[(int64_t)(e / kT) * ld + e % kT];
+  __syncthreads();
+  const int i = t >> 2, j0 = (t & 3) * 16;
+  int bad = 0;
+  for (int r = 0; r < kT; ++r) {
+    const double arr = A[r][r];
+    bad += !(arr > 0.0);
+    const double pr = 1.0 / arr;
+    const double air = A[i][r];
+    double arj[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) arj[q] = A[r][j0 + q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int j = j0 + q;
+      double v;
+      if (i == r) v = (j == r) ? pr : arj[q] * pr;
+      else v = (j == r) ? -air * pr : A[i][j] - air * (arj[q] * pr);
+      A[i][j] = v;
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < kT * kT; e += kThreads) piv[e] = A[e / kT][e % kT];
+  if (t == 0 && bad) atomicAdd(flag, bad);
+}
+
+// Row panel: S(p, j) = piv S(p, j) for every tile column j != p.
+__global__ __launch_bounds__(kThreads) void k_gj_row(double *S, int64_t ld, int p,
+                                                     const double *piv) {
+  __shared__ double Pi[kT][kT + 1];
+  __shared__ double X[kT][kT + 1];
+  const int t = threadIdx.x;
+  const int jt = blockIdx.x < p ? blockIdx.x : blockIdx.x + 1;
+  double *tile = S + (int64_t)p * kT * ld + (int64_t)jt * kT;
+  for (int e = t; e < kT * kT; e += kThreads) {
+    Pi[e / kT][e % kT] = piv[e];
+    X[e / kT][e % kT] = tile[(int64_t)(e / kT) * ld + e % kT];
+  }
+  __syncthreads();
+  const int i = t >> 2, j0 = (t & 3) * 16;
+  double out[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) out[q] = 0.0;
+  for (int kk = 0; kk < kT; ++kk) {
+    const double a = Pi[i][kk];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) out[q] = fma(a, X[kk][j0 + q], out[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) tile[(int64_t)i * ld + j0 + q] = out[q];
+}
+
+// Trailing update: S(I, J) -= S(I, p) S(p, J) for every tile I != p, J != p.
+__global__ __launch_bounds__(kThreads) void k_gj_update(double *S, int64_t ld, int p, int nt) {
+  __shared__ double L[kT][kT + 1];  // L[k][i] = S(I, p)[i][k]
+  __shared__ double R[kT][kT + 1];  // R[k][j] = S(p, J)[k][j]
+  const int t = threadIdx.x;
+  const int m = nt - 1;
+  const int bi = blockIdx.x / m, bj = blockIdx.x - bi * m;
+  const int it = bi < p ? bi : bi + 1, jt = bj < p ? bj : bj + 1;
+  const double *SI = S + (int64_t)it * kT * ld + (int64_t)p * kT;
+  const double *SJ = S + (int64_t)p * kT * ld + (int64_t)jt * kT;
+  for (int e = t; e < kT * kT; e += kThreads) {
+    const int r = e / kT, c = e % kT;
+    L[c][r] = SI[(int64_t)r * ld + c];
+    R[r][c] = SJ[(int64_t)r * ld + c];
+  }
+  __syncthreads();
+  const int i0 = (t >> 4) * 4, j0 = (t & 15) * 4;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int kk = 0; kk < kT; ++kk) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) av[a] = L[kk][i0 + a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bv[b] = R[kk][j0 + b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+  }
+  double *O = S + (int64_t)it * kT * ld + (int64_t)jt * kT;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) O[(int64_t)(i0 + a) * ld + j0 + b] -= acc[a][b];
+}
+
+// Column panel: S(I, p) = -S(I, p) piv for I != p; S(p, p) = piv.
+__global__ __launch_bounds__(kThreads) void k_gj_col(double *S, int64_t ld, int p,
+                                                     const double *piv) {
+  __shared__ double Pi[kT][kT + 1];
+  __shared__ double X[kT][kT + 1];
+  const int t = threadIdx.x;
+  const int it = blockIdx.x;
+  double *tile = S + (int64_t)it * kT * ld + (int64_t)p * kT;
+  if (it == p) {
+    for (int e = t; e < kT * kT; e += kThreads) tile[(int64_t)(e / kT) * ld + e % kT] = piv[e];
+    return;
+  }
+  for (int e = t; e < kT * kT; e += kThreads) {
+    Pi[e / kT][e % kT] = piv[e];
+    X[e / kT][e % kT] = tile[(int64_t)(e / kT) * ld + e % kT];
+  }
+  __syncthreads();
+  const int i = t >> 2, j0 = (t & 3) * 16;
+  double out[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) out[q] = 0.0;
+  for (int kk = 0; kk < kT; ++kk) {
+    const double a = X[i][kk];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) out[q] = fma(a, Pi[kk][j0 + q], out[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) tile[(int64_t)i * ld + j0 + q] = -out[q];
+}
+
+// ---------------------------------------------------------------------------
+// solves
+// ---------------------------------------------------------------------------
+
+// f = G (T - T_ref), one thread per displacement DOF.
+__global__ __launch_bounds__(kThreads) void k_thermal_load(DeformDev D, const double *T) {
+  for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < D.n;
+       r += (int64_t)gridDim.x * kThreads) {
+    double a = 0.0;
+    for (int64_t e = D.growptr[r]; e < D.growptr[r + 1]; ++e)
+      a = fma(D.gval[e], T[D.toff + D.gcol[e]] - D.T_ref, a);
+    D.f[r] = a;
+  }
+}
+
+// Forward right-hand side c = f_k - A_{k,k-1} w_{k-1} (zero in the padding).
+__global__ __launch_bounds__(kThreads) void k_fwd_rhs(DeformDev D, int64_t k) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= D.bp) return;
+  const int64_t bk = D.rows(k);
+  if (i >= bk) {
+    D.c[i] = 0.0;
+    return;
+  }
+  double a = D.f[D.lo(k) + i];
+  if (k > 0) {
+    const int64_t eb = k * (int64_t)D.ellB * D.bp, pl = D.lo(k - 1);
+    for (int e = 0; e < D.ellB; ++e)
+      a = fma(-D.bval[eb + e * D.bp + i], D.w[pl + D.bcol[eb + e * D.bp + i]], a);
+  }
+  D.c[i] = a;
+}
+
+// Backward right-hand side c = A_{k,k+1} u_{k+1} (zero in the padding).
+__global__ __launch_bounds__(kThreads) void k_bwd_rhs(DeformDev D, int64_t k) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= D.bp) return;
+  if (i >= D.rows(k)) {
+    D.c[i] = 0.0;
+    return;
+  }
+  const int64_t eb = k * (int64_t)D.ellU * D.bp, nl = D.lo(k + 1);
+  double a = 0.0;
+  for (int e = 0; e < D.ellU; ++e)
+    a = fma(D.uval[eb + e * D.bp + i], D.x[nl + D.ucol[eb + e * D.bp + i]], a);
+  D.c[i] = a;
+}
+
+// Dense block product, one wavefront per row: MODE 0 out = W v, MODE 1
+// out = base - W v.  ld is a multiple of 64.
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_gemv(const double *W, int64_t ld, int64_t rows,
+                                                   const double *v, double *out,
+                                                   const double *base) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const double *wr = W + row * ld;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int64_t j = lane;
+  for (; j + 192 < ld; j += 256) {
+    a0 = fma(wr[j], v[j], a0);
+    a1 = fma(wr[j + 64], v[j + 64], a1);
+    a2 = fma(wr[j + 128], v[j + 128], a2);
+    a3 = fma(wr[j + 192], v[j + 192], a3);
+  }
+  for (; j < ld; j += 64) a0 = fma(wr[j], v[j], a0);
+  double s = (a0 + a1) + (a2 + a3);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) out[row] = MODE == 0 ? s : base[row] - s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_copy(double *dst, const double *src, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    dst[i] = src[i];
+}
+
+inline unsigned blocks_for(int64_t n) {
+  int64_t b = (n + kThreads - 1) / kThreads;
+  return (unsigned)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+}  // namespace
+
+void deform_factor(const DeformDev &D, hipStream_t st) {
+  const int nt = (int)(D.bp / kT);
+  hipMemsetAsync(D.flag, 0, sizeof(int), st);
+  for (int64_t k = 0; k < D.nblk; ++k) {
+    if (k > 0) k_schur_t<<<(unsigned)D.rows(k), kThreads, 0, st>>>(D, k);
+    k_schur_s<<<(unsigned)D.bp, kThreads, (size_t)D.bp * sizeof(double), st>>>(D, k);
+    double *S = D.W + k * D.bp * D.bp;
+    for (int p = 0; p < nt; ++p) {
+      k_gj_pivot<<<1, kThreads, 0, st>>>(S, D.bp, p, D.piv, D.flag);
+      if (nt > 1) {
+        k_gj_row<<<nt - 1, kThreads, 0, st>>>(S, D.bp, p, D.piv);
+        k_gj_update<<<(nt - 1) * (nt - 1), kThreads, 0, st>>>(S, D.bp, p, nt);
+      }
+      k_gj_col<<<nt, kThreads, 0, st>>>(S, D.bp, p, D.piv);
+    }
+  }
+}
+
+void deform_solve(const DeformDev &D, const double *T, hipStream_t st, hipEvent_t *ev) {
+  k_thermal_load<<<blocks_for(D.n), kThreads, 0, st>>>(D, T);
+  const unsigned cb = (unsigned)((D.bp + kThreads - 1) / kThreads);
+  int g = 0;
+  auto gemv = [&](int mode, int64_t k, double *out, const double *base) {
+    const double *W = D.W + k * D.bp * D.bp;
+    const int64_t rows = D.rows(k);
+    const unsigned grid = (unsigned)((rows + 3) / 4);
+    auto kern = mode == 0 ? k_gemv<0> : k_gemv<1>;
+    if (ev) {
+      hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, ev[2 * g], ev[2 * g + 1], 0,
+                            W, D.bp, rows, (const double *)D.c, out, base);
+    } else {
+      kern<<<grid, kThreads, 0, st>>>(W, D.bp, rows, D.c, out, base);
+    }
+    ++g;
+  };
+  for (int64_t k = 0; k < D.nblk; ++k) {
+    k_fwd_rhs<<<cb, kThreads, 0, st>>>(D, k);
+    gemv(0, k, D.w + D.lo(k), nullptr);
+  }
+  const int64_t last = D.nblk - 1;
+  k_copy<<<blocks_for(D.rows(last)), kThreads, 0, st>>>(D.x + D.lo(last), D.w + D.lo(last),
+                                                        D.rows(last));
+  for (int64_t k = D.nblk - 2; k >= 0; --k) {
+    k_bwd_rhs<<<cb, kThreads, 0, st>>>(D, k);
+    gemv(1, k, D.x + D.lo(k), D.w + D.lo(k));
+  }
+}
+
+}  // namespace mrsdc
