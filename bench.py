@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--profile", action="store_true",
                     help="event timing of kernel classes inside the timed region (adds overhead)")
     ap.add_argument("--op-reps", type=int, default=200, help="operator timing launches")
+    ap.add_argument("--deform-reps", type=int, default=5,
+                    help="thermo-elastic deformation: timed solves on the 1 cm stand (0: skip)")
     ap.add_argument("--wp-levels", type=int, default=5,
                     help="work-precision study: time-step levels per method (0: skip)")
     ap.add_argument("--ensemble-precision", type=int, default=1, choices=[0, 1],
@@ -198,6 +200,8 @@ def main():
         out["stationary"] = stationary_form(pkg, args)
         if args.wp_levels > 0:
             out["work_precision"] = work_precision_form(pkg, args)
+        if args.deform_reps > 0:
+            out["deformation"] = deformation_form(pkg, args)
         out["residual_control"] = residual_control_form(pkg, args, wall / args.steps)
     if args.ensemble_steps > 0 and args.config == "machine":
         import mrsdc_inputs as mi
@@ -312,6 +316,44 @@ def work_precision_form(pkg, args):
             "reference": {"method": "MRSDC Lobatto M=5 P=8 K=7", "dt_s": dt_ref,
                           "max_diff_K_vs_twice_dt": ref_err},
             "max_temperature_rise_K": rise, "curves": curves}
+
+
+def deformation_form(pkg, args):
+    """Thermo-elastic deformation of the benchmark machine's stand (41 x 41 x
+    161 nodes, floor clamped, 806,880 displacement DOFs) from its temperature
+    after 4 steps: the one-off factorisation, the forward/backward solve per
+    output, and the solve's dominant kernel (dense block product) timed per
+    launch with HIP events against the HBM peak.  The residual
+    ||K_u u - f|| / ||f|| is checked on the host."""
+    from mrsdc_inputs.elastic import elastic_box
+    import mrsdc_inputs as mi
+    pb = mi.machine_310k(nsteps=4)
+    el = elastic_box(pb.bodies[0])
+    ctx = pkg.simulation(pb, device=0)
+    t = time.perf_counter()
+    st = ctx.advance(4 * pb.scheme.dt)
+    step_ms = (time.perf_counter() - t) / 4 * 1e3
+    info = ctx.deform_setup(el)
+    solve_us, gemv_us, gemv_bytes = ctx.deform_time(args.deform_reps)
+    u = ctx.deform()
+    T = ctx.get_temperature(0, pb.bodies[0].n)
+    ctx.destroy()
+    f = el.gcsr() @ (T - el.T_ref)
+    res = float(np.linalg.norm(el.csr() @ u - f) / np.linalg.norm(f))
+    gbps = gemv_bytes / (gemv_us * 1e-6) / 1e9
+    print(f"[bench] deformation: factor {info['factor_ms']:.0f} ms, solve {solve_us / 1e3:.2f} ms, "
+          f"block product {gemv_us:.1f} us = {gbps:.0f} GB/s", file=sys.stderr, flush=True)
+    return {"workload": "stand 41x41x161 nodes, clamped floor", "dof": el.n, "nnz": el.nnz,
+            "block": info["block"], "padded_block": info["padded_block"],
+            "blocks": info["nblocks"], "factor_ms": info["factor_ms"],
+            "factor_GiB": info["factor_bytes"] / 2**30, "solve_ms": solve_us / 1e3,
+            "solve_per_macro_step": solve_us / 1e3 / step_ms,
+            "max_displacement_um": float(np.abs(u).max() * 1e6),
+            "relative_residual": res,
+            "roofline": {"bound": "hbm", "kernel": "k_gemv (dense block product)",
+                         "achieved": gbps, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbps / HBM_PEAK_GBS, "avg_launch_us": gemv_us,
+                         "bytes_per_launch": gemv_bytes, "traffic": None}}
 
 
 def stationary_form(pkg, args):

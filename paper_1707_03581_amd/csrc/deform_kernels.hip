@@ -87,23 +87,25 @@ __global__ __launch_bounds__(kThreads) void k_gj_pivot(const double *S, int64_t 
   const double *P = S + (int64_t)p * kT * ld + (int64_t)p * kT;
   for (int e = t; e < kT * kT; e += kThreads) A[e / kT][e % kT] = P[(int64_t)(e / kT) * ld + e % kT];
   __syncthreads();
-  const int i = t >> 2, j0 = (t & 3) * 16;
+  // a wavefront owns 16 rows i = w + 4q, its lanes the 64 columns j: LDS
+  // accesses along a row are conflict-free, column values are broadcast
+  const int j = t & 63, w = t >> 6;
   int bad = 0;
   for (int r = 0; r < kT; ++r) {
     const double arr = A[r][r];
     bad += !(arr > 0.0);
     const double pr = 1.0 / arr;
-    const double air = A[i][r];
-    double arj[16];
+    const double arj = A[r][j];
+    double air[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) arj[q] = A[r][j0 + q];
+    for (int q = 0; q < 16; ++q) air[q] = A[w + 4 * q][r];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int j = j0 + q;
+      const int i = w + 4 * q;
       double v;
-      if (i == r) v = (j == r) ? pr : arj[q] * pr;
-      else v = (j == r) ? -air * pr : A[i][j] - air * (arj[q] * pr);
+      if (i == r) v = (j == r) ? pr : arj * pr;
+      else v = (j == r) ? -air[q] * pr : A[i][j] - air[q] * (arj * pr);
       A[i][j] = v;
     }
     __syncthreads();
@@ -125,17 +127,17 @@ __global__ __launch_bounds__(kThreads) void k_gj_row(double *S, int64_t ld, int 
     X[e / kT][e % kT] = tile[(int64_t)(e / kT) * ld + e % kT];
   }
   __syncthreads();
-  const int i = t >> 2, j0 = (t & 3) * 16;
+  const int j = t & 63, w = t >> 6;  // rows w + 4q, column j
   double out[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) out[q] = 0.0;
   for (int kk = 0; kk < kT; ++kk) {
-    const double a = Pi[i][kk];
+    const double x = X[kk][j];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) out[q] = fma(a, X[kk][j0 + q], out[q]);
+    for (int q = 0; q < 16; ++q) out[q] = fma(Pi[w + 4 * q][kk], x, out[q]);
   }
 #pragma unroll
-  for (int q = 0; q < 16; ++q) tile[(int64_t)i * ld + j0 + q] = out[q];
+  for (int q = 0; q < 16; ++q) tile[(int64_t)(w + 4 * q) * ld + j] = out[q];
 }
 
 // Trailing update: S(I, J) -= S(I, p) S(p, J) for every tile I != p, J != p.
@@ -154,7 +156,9 @@ __global__ __launch_bounds__(kThreads) void k_gj_update(double *S, int64_t ld, i
     R[r][c] = SJ[(int64_t)r * ld + c];
   }
   __syncthreads();
-  const int i0 = (t >> 4) * 4, j0 = (t & 15) * 4;
+  // rows i0 + a (4 consecutive), columns j0 + 16 b (16 lanes side by side:
+  // conflict-free LDS reads, 128-byte global runs)
+  const int i0 = (t >> 4) * 4, j0 = t & 15;
   double acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -165,7 +169,7 @@ __global__ __launch_bounds__(kThreads) void k_gj_update(double *S, int64_t ld, i
 #pragma unroll
     for (int a = 0; a < 4; ++a) av[a] = L[kk][i0 + a];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) bv[b] = R[kk][j0 + b];
+    for (int b = 0; b < 4; ++b) bv[b] = R[kk][j0 + 16 * b];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -175,7 +179,7 @@ __global__ __launch_bounds__(kThreads) void k_gj_update(double *S, int64_t ld, i
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) O[(int64_t)(i0 + a) * ld + j0 + b] -= acc[a][b];
+    for (int b = 0; b < 4; ++b) O[(int64_t)(i0 + a) * ld + j0 + 16 * b] -= acc[a][b];
 }
 
 // Column panel: S(I, p) = -S(I, p) piv for I != p; S(p, p) = piv.
@@ -195,17 +199,17 @@ __global__ __launch_bounds__(kThreads) void k_gj_col(double *S, int64_t ld, int 
     X[e / kT][e % kT] = tile[(int64_t)(e / kT) * ld + e % kT];
   }
   __syncthreads();
-  const int i = t >> 2, j0 = (t & 3) * 16;
+  const int j = t & 63, w = t >> 6;  // rows w + 4q, column j
   double out[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) out[q] = 0.0;
   for (int kk = 0; kk < kT; ++kk) {
-    const double a = X[i][kk];
+    const double pk = Pi[kk][j];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) out[q] = fma(a, Pi[kk][j0 + q], out[q]);
+    for (int q = 0; q < 16; ++q) out[q] = fma(X[w + 4 * q][kk], pk, out[q]);
   }
 #pragma unroll
-  for (int q = 0; q < 16; ++q) tile[(int64_t)i * ld + j0 + q] = -out[q];
+  for (int q = 0; q < 16; ++q) tile[(int64_t)(w + 4 * q) * ld + j] = -out[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -223,59 +227,89 @@ __global__ __launch_bounds__(kThreads) void k_thermal_load(DeformDev D, const do
   }
 }
 
+// Coupling product of one row of an ELL block with a neighbouring block's
+// vector: 4 lanes per row, each over every 4th entry, loads issued two at a
+// time, then summed across the 4 lanes.
+constexpr int kSub = 4;
+__device__ inline double ell_row(const double *val, const int32_t *col, int64_t bp, int E,
+                                 int64_t i, int sub, const double *x) {
+  double a0 = 0.0, a1 = 0.0;
+  int e = sub;
+  for (; e + kSub < E; e += 2 * kSub) {
+    const double v0 = val[e * bp + i], v1 = val[(e + kSub) * bp + i];
+    const int c0 = col[e * bp + i], c1 = col[(e + kSub) * bp + i];
+    a0 = fma(v0, x[c0], a0);
+    a1 = fma(v1, x[c1], a1);
+  }
+  if (e < E) a0 = fma(val[e * bp + i], x[col[e * bp + i]], a0);
+  double s = a0 + a1;
+  s += __shfl_xor(s, 1, 64);
+  s += __shfl_xor(s, 2, 64);
+  return s;
+}
+
 // Forward right-hand side c = f_k - A_{k,k-1} w_{k-1} (zero in the padding).
 __global__ __launch_bounds__(kThreads) void k_fwd_rhs(DeformDev D, int64_t k) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t i = g / kSub;
+  const int sub = (int)(g % kSub);
   if (i >= D.bp) return;
   const int64_t bk = D.rows(k);
   if (i >= bk) {
-    D.c[i] = 0.0;
+    if (sub == 0) D.c[i] = 0.0;
     return;
   }
-  double a = D.f[D.lo(k) + i];
+  double a = 0.0;
   if (k > 0) {
-    const int64_t eb = k * (int64_t)D.ellB * D.bp, pl = D.lo(k - 1);
-    for (int e = 0; e < D.ellB; ++e)
-      a = fma(-D.bval[eb + e * D.bp + i], D.w[pl + D.bcol[eb + e * D.bp + i]], a);
+    const int64_t eb = k * (int64_t)D.ellB * D.bp;
+    a = ell_row(D.bval + eb, D.bcol + eb, D.bp, D.ellB, i, sub, D.w + D.lo(k - 1));
   }
-  D.c[i] = a;
+  if (sub == 0) D.c[i] = D.f[D.lo(k) + i] - a;
 }
 
 // Backward right-hand side c = A_{k,k+1} u_{k+1} (zero in the padding).
 __global__ __launch_bounds__(kThreads) void k_bwd_rhs(DeformDev D, int64_t k) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t i = g / kSub;
+  const int sub = (int)(g % kSub);
   if (i >= D.bp) return;
   if (i >= D.rows(k)) {
-    D.c[i] = 0.0;
+    if (sub == 0) D.c[i] = 0.0;
     return;
   }
-  const int64_t eb = k * (int64_t)D.ellU * D.bp, nl = D.lo(k + 1);
-  double a = 0.0;
-  for (int e = 0; e < D.ellU; ++e)
-    a = fma(D.uval[eb + e * D.bp + i], D.x[nl + D.ucol[eb + e * D.bp + i]], a);
-  D.c[i] = a;
+  const int64_t eb = k * (int64_t)D.ellU * D.bp;
+  const double a = ell_row(D.uval + eb, D.ucol + eb, D.bp, D.ellU, i, sub, D.x + D.lo(k + 1));
+  if (sub == 0) D.c[i] = a;
 }
 
 // Dense block product, one wavefront per row: MODE 0 out = W v, MODE 1
 // out = base - W v.  ld is a multiple of 64.
+// The vector sits in LDS; W is streamed once with non-temporal loads, eight
+// 512-byte loads in flight per wavefront.
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_gemv(const double *W, int64_t ld, int64_t rows,
                                                    const double *v, double *out,
                                                    const double *base) {
+  extern __shared__ double vs[];
+  for (int64_t j = threadIdx.x; j < ld; j += kThreads) vs[j] = v[j];
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   if (row >= rows) return;
   const double *wr = W + row * ld;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  double a[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) a[u] = 0.0;
   int64_t j = lane;
-  for (; j + 192 < ld; j += 256) {
-    a0 = fma(wr[j], v[j], a0);
-    a1 = fma(wr[j + 64], v[j + 64], a1);
-    a2 = fma(wr[j + 128], v[j + 128], a2);
-    a3 = fma(wr[j + 192], v[j + 192], a3);
+  for (; j + 7 * 64 < ld; j += 8 * 64) {
+    double wv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) wv[u] = __builtin_nontemporal_load(wr + j + 64 * u);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = fma(wv[u], vs[j + 64 * u], a[u]);
   }
-  for (; j < ld; j += 64) a0 = fma(wr[j], v[j], a0);
-  double s = (a0 + a1) + (a2 + a3);
+  for (; j < ld; j += 64) a[0] = fma(__builtin_nontemporal_load(wr + j), vs[j], a[0]);
+  double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if (lane == 0) out[row] = MODE == 0 ? s : base[row] - s;
@@ -314,7 +348,8 @@ void deform_factor(const DeformDev &D, hipStream_t st) {
 
 void deform_solve(const DeformDev &D, const double *T, hipStream_t st, hipEvent_t *ev) {
   k_thermal_load<<<blocks_for(D.n), kThreads, 0, st>>>(D, T);
-  const unsigned cb = (unsigned)((D.bp + kThreads - 1) / kThreads);
+  const unsigned cb = (unsigned)((D.bp * kSub + kThreads - 1) / kThreads);
+  const size_t vlds = (size_t)D.bp * sizeof(double);
   int g = 0;
   auto gemv = [&](int mode, int64_t k, double *out, const double *base) {
     const double *W = D.W + k * D.bp * D.bp;
@@ -322,10 +357,10 @@ void deform_solve(const DeformDev &D, const double *T, hipStream_t st, hipEvent_
     const unsigned grid = (unsigned)((rows + 3) / 4);
     auto kern = mode == 0 ? k_gemv<0> : k_gemv<1>;
     if (ev) {
-      hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, ev[2 * g], ev[2 * g + 1], 0,
-                            W, D.bp, rows, (const double *)D.c, out, base);
+      hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), vlds, st, ev[2 * g], ev[2 * g + 1],
+                            0, W, D.bp, rows, (const double *)D.c, out, base);
     } else {
-      kern<<<grid, kThreads, 0, st>>>(W, D.bp, rows, D.c, out, base);
+      kern<<<grid, kThreads, vlds, st>>>(W, D.bp, rows, D.c, out, base);
     }
     ++g;
   };
