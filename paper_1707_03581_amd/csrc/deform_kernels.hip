@@ -282,10 +282,11 @@ __global__ __launch_bounds__(kThreads) void k_bwd_rhs(DeformDev D, int64_t k) {
   if (sub == 0) D.c[i] = a;
 }
 
-// Dense block product, one wavefront per row: MODE 0 out = W v, MODE 1
-// out = base - W v.  ld is a multiple of 64.
-// The vector sits in LDS; W is streamed once with non-temporal loads, eight
-// 512-byte loads in flight per wavefront.
+// Dense block product: MODE 0 out = W v, MODE 1 out = base - W v; ld is a
+// multiple of 64.  The vector sits in LDS; W is streamed once with
+// non-temporal loads.  A wavefront forms two rows, sixteen 512-byte loads in
+// flight.
+constexpr int kGemvRows = 2;
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_gemv(const double *W, int64_t ld, int64_t rows,
                                                    const double *v, double *out,
@@ -294,25 +295,44 @@ __global__ __launch_bounds__(kThreads) void k_gemv(const double *W, int64_t ld, 
   for (int64_t j = threadIdx.x; j < ld; j += kThreads) vs[j] = v[j];
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
-  if (row >= rows) return;
-  const double *wr = W + row * ld;
-  double a[8];
+  const int64_t r0 = ((int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) * kGemvRows;
+  if (r0 >= rows) return;
+  const bool two = r0 + 1 < rows;
+  const double *w0 = W + r0 * ld;
+  const double *w1 = two ? w0 + ld : w0;  // a lone last row reads its own row twice
+  double a[8], b[8];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) a[u] = 0.0;
+  for (int u = 0; u < 8; ++u) a[u] = b[u] = 0.0;
   int64_t j = lane;
   for (; j + 7 * 64 < ld; j += 8 * 64) {
-    double wv[8];
+    double x0[8], x1[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) wv[u] = __builtin_nontemporal_load(wr + j + 64 * u);
+    for (int u = 0; u < 8; ++u) {
+      x0[u] = __builtin_nontemporal_load(w0 + j + 64 * u);
+      x1[u] = __builtin_nontemporal_load(w1 + j + 64 * u);
+    }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] = fma(wv[u], vs[j + 64 * u], a[u]);
+    for (int u = 0; u < 8; ++u) {
+      const double vv = vs[j + 64 * u];
+      a[u] = fma(x0[u], vv, a[u]);
+      b[u] = fma(x1[u], vv, b[u]);
+    }
   }
-  for (; j < ld; j += 64) a[0] = fma(__builtin_nontemporal_load(wr + j), vs[j], a[0]);
-  double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  for (; j < ld; j += 64) {
+    a[0] = fma(__builtin_nontemporal_load(w0 + j), vs[j], a[0]);
+    b[0] = fma(__builtin_nontemporal_load(w1 + j), vs[j], b[0]);
+  }
+  double s0 = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  double s1 = ((b[0] + b[1]) + (b[2] + b[3])) + ((b[4] + b[5]) + (b[6] + b[7]));
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (lane == 0) out[row] = MODE == 0 ? s : base[row] - s;
+  for (int off = 32; off > 0; off >>= 1) {
+    s0 += __shfl_xor(s0, off, 64);
+    s1 += __shfl_xor(s1, off, 64);
+  }
+  if (lane == 0) {
+    out[r0] = MODE == 0 ? s0 : base[r0] - s0;
+    if (two) out[r0 + 1] = MODE == 0 ? s1 : base[r0 + 1] - s1;
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_copy(double *dst, const double *src, int64_t n) {
@@ -354,7 +374,8 @@ void deform_solve(const DeformDev &D, const double *T, hipStream_t st, hipEvent_
   auto gemv = [&](int mode, int64_t k, double *out, const double *base) {
     const double *W = D.W + k * D.bp * D.bp;
     const int64_t rows = D.rows(k);
-    const unsigned grid = (unsigned)((rows + 3) / 4);
+    const int64_t per = (kThreads / 64) * kGemvRows;
+    const unsigned grid = (unsigned)((rows + per - 1) / per);
     auto kern = mode == 0 ? k_gemv<0> : k_gemv<1>;
     if (ev) {
       hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), vlds, st, ev[2 * g], ev[2 * g + 1],
