@@ -793,6 +793,7 @@ mrsdc_status prepare(mrsdc_ctx *c) {
     if (d.single_rate &&
         ((st = dalloc(c, &d.ifc_lin, (size_t)f.n_if)) || (st = dalloc(c, &d.ifc_src, (size_t)f.n_if))))
       return st;
+    if (!batch && !d.single_rate && (st = dalloc(c, &d.Ipre, ncache))) return st;
     const size_t ntab = (size_t)(cfg.M + 1) * (cfg.P + 1) * S;
     if ((st = dalloc(c, &d.coefD, ntab * coef_table_doubles(f))) ||
         (st = dalloc(c, &d.coefI, ntab * coef_table_ints(f))))
@@ -916,6 +917,7 @@ void enqueue_step(mrsdc_ctx *c) {
     launch_f_multi(d, j0, M, st);
     launch_quad_resid(d, k - 1, st);
     if (k > K) break;
+    launch_iface_quad(d, st);
     for (int m = 1; m <= M; ++m) {
       if (c->w.dtau[m] == 0.0) continue;
       enqueue_solve(c, k, m);

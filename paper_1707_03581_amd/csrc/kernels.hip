@@ -42,6 +42,30 @@ __device__ inline double block_sum(double v, double *sh) {
   __syncthreads();
   return sh[16];
 }
+// Two sums at once (the same order as two block_sum calls).  sh: >= 34 doubles.
+__device__ inline void block_sum2(double &v0, double &v1, double *sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v0 = wave_sum(v0);
+  v1 = wave_sum(v1);
+  __syncthreads();
+  if (lane == 0) {
+    sh[w] = v0;
+    sh[17 + w] = v1;
+  }
+  __syncthreads();
+  if (w == 0) {
+    double t0 = lane < nw ? sh[lane] : 0.0, t1 = lane < nw ? sh[17 + lane] : 0.0;
+    t0 = wave_sum(t0);
+    t1 = wave_sum(t1);
+    if (lane == 0) {
+      sh[16] = t0;
+      sh[33] = t1;
+    }
+  }
+  __syncthreads();
+  v0 = sh[16];
+  v1 = sh[33];
+}
 __device__ inline double block_max(double v, double *sh) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   v = wave_max(v);
@@ -444,7 +468,7 @@ __global__ void k_solve_reduce(const double *part, int grid, SolveScalars *sc, S
 // (a) q = A p, partial p.q.  TAIL = 1 marks launches past the iteration count
 // of the previous step (usually early exits), TAIL = 2 the stand-alone timing
 // launches (which ignore the convergence flag); both kept apart in profiles.
-template <bool D16, int TAIL, typename R>
+template <bool D16, int TAIL, typename R, bool CPL = false>
 __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
   if (TAIL != 2 && solve_done(a.sc, a.ctr)) return;
   __shared__ double sh[17];
@@ -458,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
     const R Lp = (R)sell_row_t<D16, R>(a.op, s, lane, row, a.p);
     const R pi = a.p[row];
     R qi = a.mass[row] * pi + (R)a.dtau * Lp;
-    if (a.ifc_lin) {
+    if (CPL) {  // single-rate method: the coupling of the node operator
       const int ip = a.ifpos[row];
       if (ip >= 0) qi += (R)a.ifc_lin[ip];
     }
@@ -473,11 +497,28 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_pcg_b(CgArgs<R> a, int it) {
   if (solve_done(a.sc, a.ctr)) return;
   __shared__ double sh[17];
+  // the first row's operands are requested before the reduction of p.q
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool first = i < a.N;
+  R x0 = 0, p0 = 0, r0 = 0, q0 = 0, d0 = 0;
+  if (first) {
+    x0 = a.x[i];
+    p0 = a.p[i];
+    r0 = a.r[i];
+    q0 = a.q[i];
+    d0 = a.dinv[i];
+  }
   const double pq = sum_partials(a.partial, a.grid, sh);
   const R alpha = (R)(a.sc->rz[it & 1] / pq);
   double v[2] = {0.0, 0.0};
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.N;
-       i += (int64_t)gridDim.x * kBlock) {
+  if (first) {
+    a.x[i] = x0 + alpha * p0;
+    const R r = r0 - alpha * q0;
+    a.r[i] = r;
+    v[0] += (double)r * (double)(d0 * r);
+    v[1] += (double)r * (double)r;
+  }
+  for (i += (int64_t)gridDim.x * kBlock; i < a.N; i += (int64_t)gridDim.x * kBlock) {
     a.x[i] += alpha * a.p[i];
     const R r = a.r[i] - alpha * a.q[i];
     a.r[i] = r;
@@ -496,9 +537,22 @@ __global__ __launch_bounds__(kBlock) void k_pcg_b(CgArgs<R> a, int it) {
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_pcg_c(CgArgs<R> a, int it, int last) {
   if (solve_done(a.sc, a.ctr)) return;
-  __shared__ double sh[17];
-  const double rz = sum_partials(a.partial + a.grid, a.grid, sh);
-  const double rr = sum_partials(a.partial + 2 * a.grid, a.grid, sh);
+  __shared__ double sh[34];
+  // the first row's operands are requested before the reductions
+  const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool first = i0 < a.N;
+  R d0 = 0, r0 = 0, p0 = 0;
+  if (first) {
+    d0 = a.dinv[i0];
+    r0 = a.r[i0];
+    p0 = a.p[i0];
+  }
+  double rz = 0.0, rr = 0.0;
+  for (int j = threadIdx.x; j < a.grid; j += blockDim.x) {
+    rz += a.partial[a.grid + j];
+    rr += a.partial[2 * a.grid + j];
+  }
+  block_sum2(rz, rr, sh);
   SolveScalars *sc = a.sc;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if (rr <= sc->tol2) {
@@ -515,8 +569,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_c(CgArgs<R> a, int it, int last)
     return;
   }
   const R beta = (R)(rz / sc->rz[it & 1]);
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.N;
-       i += (int64_t)gridDim.x * kBlock)
+  if (first) a.p[i0] = d0 * r0 + beta * p0;
+  for (int64_t i = i0 + (int64_t)gridDim.x * kBlock; i < a.N; i += (int64_t)gridDim.x * kBlock)
     a.p[i] = a.dinv[i] * a.r[i] + beta * a.p[i];
   if (lead) {
     sc->rz[(it + 1) & 1] = rz;
@@ -692,6 +746,9 @@ static void pcg_iter(const DevState &d, const CgArgs<R> &a, int it, bool last, b
   // with events: the dispatch's own start/end timestamps (AMD launch extension)
   auto kern = d.op.d16 ? (tail ? k_pcg_a<true, 1, R> : k_pcg_a<true, 0, R>)
                        : (tail ? k_pcg_a<false, 1, R> : k_pcg_a<false, 0, R>);
+  if (a.ifc_lin)
+    kern = d.op.d16 ? (tail ? k_pcg_a<true, 1, R, true> : k_pcg_a<true, 0, R, true>)
+                    : (tail ? k_pcg_a<false, 1, R, true> : k_pcg_a<false, 0, R, true>);
   if (a.ifc_lin) launch_iface_lin(d, a.m, (const double *)a.p, st);  // coupling of A p
   if (ev0) hipExtLaunchKernelGGL(kern, dim3(d.grid), dim3(kBlock), 0, st, ev0, ev1, 0, a, it);
   else kern<<<d.grid, kBlock, 0, st>>>(a, it);
@@ -910,6 +967,7 @@ struct SubArgs {
   const double *F[kMaxM + 1];
   const double *Eold;  // [(M+1)(P+1) n_if]
   double *Enew;
+  double *Ipre;        // [(M+1)(P+1) n_if] embedded quadratures of the sweep
   double *Tbuf[2];
   double *fst;
 };
@@ -1037,9 +1095,7 @@ __global__ __launch_bounds__(kBlock) void k_iface_sub(SubArgs A) {
   double inc;
   if (A.corr) {
     const double *Eo = A.Eold + (size_t)m * P1 * n;
-    double Ip = 0.0;
-    for (int j = 1; j <= A.M; ++j) Ip += w.stil[m][p][j] * A.F[j][row];
-    for (int q = 1; q <= P; ++q) Ip += w.spq[m][p][q] * Eo[(size_t)q * n + i];
+    const double Ip = A.Ipre[((size_t)m * P1 + p) * n + i];
     inc = dtp * (fs + E - Eo[(size_t)(p - 1) * n + i]) + Ip;
   } else {
     inc = dtp * (fs + E);
@@ -1109,6 +1165,46 @@ void launch_iface_lin(const DevState &d, int m, const double *x, hipStream_t st)
                                            d.ifc_src);
 }
 
+// Embedded quadratures I_{m,p} (eq. embedded_quad) of the interface rows for
+// every interval and substep of a sweep: they depend only on the previous
+// iterate (F_j at the sweep start, the previous sweep's E cache), so one pass
+// at the sweep start replaces M + P scattered loads per point and substep.
+__global__ __launch_bounds__(kBlock) void k_iface_quad(SubArgs A) {
+  if (A.ctr->stop) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = A.f.n_if;
+  if (i >= n) return;
+  const Weights &w = *A.w;
+  const int P = A.P, P1 = P + 1;
+  const int64_t row = A.f.rows[i];
+  double F[kMaxM + 1];
+  for (int j = 1; j <= A.M; ++j) F[j] = A.F[j][row];
+  for (int m = 1; m <= A.M; ++m) {
+    if (w.dtau[m] == 0.0) continue;
+    const double *Eo = A.Eold + (size_t)m * P1 * n;
+    for (int p = 1; p <= P; ++p) {
+      double Ip = 0.0;
+      for (int j = 1; j <= A.M; ++j) Ip += w.stil[m][p][j] * F[j];
+      for (int q = 1; q <= P; ++q) Ip += w.spq[m][p][q] * Eo[(size_t)q * n + i];
+      A.Ipre[((size_t)m * P1 + p) * n + i] = Ip;
+    }
+  }
+}
+
+void launch_iface_quad(const DevState &d, hipStream_t st) {
+  if (!d.ifc.kind || d.ifc.n_if == 0) return;
+  SubArgs A{};
+  A.f = d.ifc;
+  A.ctr = d.ctr;
+  A.w = d.w;
+  A.P = d.P;
+  A.M = d.M;
+  for (int j = 0; j <= kMaxM; ++j) A.F[j] = d.F[j];
+  A.Eold = d.Eold;
+  A.Ipre = d.Ipre;
+  k_iface_quad<<<(d.ifc.n_if + kBlock - 1) / kBlock, kBlock, 0, st>>>(A);
+}
+
 void launch_iface(const DevState &d, int m, bool corr, hipStream_t st) {
   if (!d.ifc.kind || d.ifc.n_if == 0) return;
   SubArgs A;
@@ -1128,6 +1224,7 @@ void launch_iface(const DevState &d, int m, bool corr, hipStream_t st) {
   for (int j = 0; j <= kMaxM; ++j) A.F[j] = d.F[j];
   A.Eold = d.Eold;
   A.Enew = d.Enew;
+  A.Ipre = d.Ipre;
   A.Tbuf[0] = d.Tbuf[0];
   A.Tbuf[1] = d.Tbuf[1];
   A.fst = d.fst;

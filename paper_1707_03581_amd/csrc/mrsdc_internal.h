@@ -145,6 +145,7 @@ struct DevState {
   double *tn = nullptr;               // device scalar: t_n of the current step
   IfaceDev ifc;
   double *Eold = nullptr, *Enew = nullptr;  // [(M+1)*(P+1)*n_if]
+  double *Ipre = nullptr;  // [(M+1)*(P+1)*n_if] I_{m,p} of the interface rows, per sweep
   double *Tbuf[2] = {};                     // [n_if] interface state, double buffered
   double *fst = nullptr;                    // [n_if] f*_m on the interface
   double *coefD = nullptr;                  // [(M+1)(P+1)] tables of v-direction integrals
@@ -157,6 +158,7 @@ void launch_quad_resid(const DevState &d, int k, hipStream_t st);
 void launch_init_pred(const DevState &d, int m, int slot, double rtol, hipStream_t st);
 void launch_init_corr(const DevState &d, int m, int slot, double rtol, hipStream_t st);
 void launch_iface_F(const DevState &d, int j, hipStream_t st);
+void launch_iface_quad(const DevState &d, hipStream_t st);
 void launch_iface_lin(const DevState &d, int m, const double *x, hipStream_t st);
 void launch_stationary_init(const DevState &d, const double *zeros, const double *dinv, int slot,
                             double rtol, hipStream_t st);
