@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "batch_internal.h"
@@ -586,14 +587,51 @@ mrsdc_status prepare(mrsdc_ctx *c) {
     if ((st = upload(c, &p, val32))) return st;
     d.op.val32 = p;
   }
+  // value dictionary for the CG operator: exact, when the operator holds at
+  // most kDictMax distinct values (bit patterns), as on structured meshes
+  bool dict = false;
+  if (!batch) {
+    std::unordered_map<uint64_t, int> keys;
+    std::vector<uint8_t> vid(nelem);
+    std::vector<double> vdict;
+    dict = true;
+    for (int64_t e = 0; e < nelem; ++e) {
+      uint64_t k;
+      std::memcpy(&k, &val[e], sizeof k);
+      auto it = keys.find(k);
+      if (it == keys.end()) {
+        if ((int)vdict.size() == kDictMax) {
+          dict = false;
+          break;
+        }
+        it = keys.emplace(k, (int)vdict.size()).first;
+        vdict.push_back(val[e]);
+      }
+      vid[e] = (uint8_t)it->second;
+    }
+    if (dict) {
+      uint8_t *pv;
+      double *pd;
+      if ((st = upload(c, &pv, vid)) || (st = upload(c, &pd, vdict))) return st;
+      d.op.vid = pv;
+      d.op.vdict = pd;
+      d.op.ndict = (int)vdict.size();
+      if (cfg.precision == MRSDC_FP32_REFINE) {
+        std::vector<float> vd32(vdict.size());
+        for (size_t j = 0; j < vdict.size(); ++j) vd32[j] = (float)vdict[j];
+        float *pf;
+        if ((st = upload(c, &pf, vd32))) return st;
+        d.op.vdict32 = pf;
+      }
+    }
+  }
   c->matrix_bytes = nnz_total * (8 + (use16 ? 2 : 4)) + 8 * (nslices + 1);
   c->nnz = nnz_total;
-  // CG operator application: FP64 values (FP32 for the inner solves of the
-  // FP32 path) + column offsets + p, mass, q
-  c->times.cg_spmv_bytes =
-      cfg.precision == MRSDC_FP32_REFINE
-          ? nnz_total * (4 + (use16 ? 2 : 4)) + 8 * (nslices + 1) + 12 * N
-          : c->matrix_bytes + 24 * N;
+  // CG operator application: values (1-byte dictionary indices, or FP64 /
+  // FP32 for the inner solves of the FP32 path) + column offsets + p, mass, q
+  const int64_t vb = dict ? 1 : (cfg.precision == MRSDC_FP32_REFINE ? 4 : 8);
+  c->times.cg_spmv_bytes = nnz_total * (vb + (use16 ? 2 : 4)) + 8 * (nslices + 1) +
+                           (cfg.precision == MRSDC_FP32_REFINE ? 12 : 24) * N;
   c->times.nnz = nnz_total;
   c->times.n = N;
 
@@ -1324,7 +1362,7 @@ mrsdc_status mrsdc_advance(mrsdc_ctx *c, double horizon, mrsdc_stats *stats) {
   // algorithmic bytes: CG iteration = matrix + 14 vector reads/writes per row;
   // init/solve ~ 8 passes; per sweep one multi-RHS SpMV and (3M+2) passes.
   const int64_t N = c->d.N;
-  acc.bytes_moved = acc.pcg_iters * (c->matrix_bytes + 112 * N) + acc.solves * 64 * N +
+  acc.bytes_moved = acc.pcg_iters * (c->times.cg_spmv_bytes + 88 * N) + acc.solves * 64 * N +
                     nsteps * Kc * (c->matrix_bytes + 16 * (int64_t)c->cfg.M * N +
                                    8 * (3 * (int64_t)c->cfg.M + 2) * N);
   if (stats) *stats = acc;

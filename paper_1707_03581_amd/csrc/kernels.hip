@@ -290,6 +290,24 @@ struct CgArgs {
   const double *ifc_lin, *ifc_src;
 };
 
+// Row of the operator through the value dictionary held in LDS (sd): the
+// same products and sums as the value array, in the same order.
+template <bool D16, typename R>
+__device__ inline double sell_row_dict(const SellDev &op, int64_t s, int lane, int64_t row,
+                                       const R *__restrict__ x, const R *sd) {
+  const int64_t end = op.off[s + 1];
+  int64_t e = op.off[s] + lane;
+  R acc = 0;
+  if (D16) {
+#pragma unroll 8
+    for (; e < end; e += kSlice) acc += sd[op.vid[e]] * x[row + op.d16[e]];
+  } else {
+#pragma unroll 8
+    for (; e < end; e += kSlice) acc += sd[op.vid[e]] * x[op.c32[e]];
+  }
+  return acc;
+}
+
 template <bool D16, typename R>
 __device__ inline double sell_row_t(const SellDev &op, int64_t s, int lane, int64_t row,
                                     const R *__restrict__ x);
@@ -468,10 +486,16 @@ __global__ void k_solve_reduce(const double *part, int grid, SolveScalars *sc, S
 // (a) q = A p, partial p.q.  TAIL = 1 marks launches past the iteration count
 // of the previous step (usually early exits), TAIL = 2 the stand-alone timing
 // launches (which ignore the convergence flag); both kept apart in profiles.
-template <bool D16, int TAIL, typename R, bool CPL = false>
+template <bool D16, int TAIL, typename R, bool CPL = false, bool DICT = false>
 __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
   if (TAIL != 2 && solve_done(a.sc, a.ctr)) return;
   __shared__ double sh[17];
+  __shared__ R sd[DICT ? kDictMax : 1];
+  if (DICT) {
+    const R *dict = sizeof(R) == 8 ? (const R *)a.op.vdict : (const R *)a.op.vdict32;
+    for (int j = threadIdx.x; j < a.op.ndict; j += kBlock) sd[j] = dict[j];
+    __syncthreads();
+  }
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
@@ -479,7 +503,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
   for (int64_t s = wave; s < a.op.nslices; s += nw) {
     const int64_t row = s * kSlice + lane;
     if (row >= a.N) continue;
-    const R Lp = (R)sell_row_t<D16, R>(a.op, s, lane, row, a.p);
+    const R Lp = DICT ? (R)sell_row_dict<D16, R>(a.op, s, lane, row, a.p, sd)
+                      : (R)sell_row_t<D16, R>(a.op, s, lane, row, a.p);
     const R pi = a.p[row];
     R qi = a.mass[row] * pi + (R)a.dtau * Lp;
     if (CPL) {  // single-rate method: the coupling of the node operator
@@ -746,6 +771,9 @@ static void pcg_iter(const DevState &d, const CgArgs<R> &a, int it, bool last, b
   // with events: the dispatch's own start/end timestamps (AMD launch extension)
   auto kern = d.op.d16 ? (tail ? k_pcg_a<true, 1, R> : k_pcg_a<true, 0, R>)
                        : (tail ? k_pcg_a<false, 1, R> : k_pcg_a<false, 0, R>);
+  if (d.op.vid)
+    kern = d.op.d16 ? (tail ? k_pcg_a<true, 1, R, false, true> : k_pcg_a<true, 0, R, false, true>)
+                    : (tail ? k_pcg_a<false, 1, R, false, true> : k_pcg_a<false, 0, R, false, true>);
   if (a.ifc_lin)
     kern = d.op.d16 ? (tail ? k_pcg_a<true, 1, R, true> : k_pcg_a<true, 0, R, true>)
                     : (tail ? k_pcg_a<false, 1, R, true> : k_pcg_a<false, 0, R, true>);
@@ -800,14 +828,18 @@ void launch_operator_timing(const DevState &d, int m, bool fp32, int reps, hipSt
   if (fp32) {
     CgArgs<float> a = cg32(d, m, 0);
     for (int i = 0; i < reps; ++i) {
-      if (d.op.d16) k_pcg_a<true, 2, float><<<d.grid, kBlock, 0, st>>>(a, 0);
+      if (d.op.vid && d.op.d16) k_pcg_a<true, 2, float, false, true><<<d.grid, kBlock, 0, st>>>(a, 0);
+      else if (d.op.vid) k_pcg_a<false, 2, float, false, true><<<d.grid, kBlock, 0, st>>>(a, 0);
+      else if (d.op.d16) k_pcg_a<true, 2, float><<<d.grid, kBlock, 0, st>>>(a, 0);
       else k_pcg_a<false, 2, float><<<d.grid, kBlock, 0, st>>>(a, 0);
     }
   } else {
     CgArgs<double> a = cg64(d, m, 0);
     a.x = nullptr;
     for (int i = 0; i < reps; ++i) {
-      if (d.op.d16) k_pcg_a<true, 2, double><<<d.grid, kBlock, 0, st>>>(a, 0);
+      if (d.op.vid && d.op.d16) k_pcg_a<true, 2, double, false, true><<<d.grid, kBlock, 0, st>>>(a, 0);
+      else if (d.op.vid) k_pcg_a<false, 2, double, false, true><<<d.grid, kBlock, 0, st>>>(a, 0);
+      else if (d.op.d16) k_pcg_a<true, 2, double><<<d.grid, kBlock, 0, st>>>(a, 0);
       else k_pcg_a<false, 2, double><<<d.grid, kBlock, 0, st>>>(a, 0);
     }
   }

@@ -43,7 +43,15 @@ struct SellDev {
   const float *val32 = nullptr;   // [nelem] (FP32_REFINE)
   const int16_t *d16 = nullptr;   // [nelem] or null
   const int32_t *c32 = nullptr;   // [nelem] or null
+  // value dictionary: when the operator holds at most kDictMax distinct
+  // values, vid[e] indexes vdict (FP64) / vdict32 (FP32) with vdict[vid[e]]
+  // bitwise equal to val[e]; the CG operator then reads 1 byte per entry
+  const uint8_t *vid = nullptr;   // [nelem] or null
+  const double *vdict = nullptr;  // [ndict]
+  const float *vdict32 = nullptr; // [ndict] (FP32_REFINE)
+  int ndict = 0;
 };
+constexpr int kDictMax = 256;
 
 // Per-solve device scalars of the CG iteration and of the refinement loop.
 struct SolveScalars {
