@@ -616,6 +616,13 @@ mrsdc_status prepare(mrsdc_ctx *c) {
       d.op.vid = pv;
       d.op.vdict = pd;
       d.op.ndict = (int)vdict.size();
+      if (use16 && maxdelta <= 2047 && vdict.size() <= 16) {
+        std::vector<int16_t> pk(nelem);
+        for (int64_t e = 0; e < nelem; ++e) pk[e] = (int16_t)(d16[e] * 16 + vid[e]);
+        int16_t *pp;
+        if ((st = upload(c, &pp, pk))) return st;
+        d.op.pk16 = pp;
+      }
       if (cfg.precision == MRSDC_FP32_REFINE) {
         std::vector<float> vd32(vdict.size());
         for (size_t j = 0; j < vdict.size(); ++j) vd32[j] = (float)vdict[j];
@@ -630,7 +637,8 @@ mrsdc_status prepare(mrsdc_ctx *c) {
   // CG operator application: values (1-byte dictionary indices, or FP64 /
   // FP32 for the inner solves of the FP32 path) + column offsets + p, mass, q
   const int64_t vb = dict ? 1 : (cfg.precision == MRSDC_FP32_REFINE ? 4 : 8);
-  c->times.cg_spmv_bytes = nnz_total * (vb + (use16 ? 2 : 4)) + 8 * (nslices + 1) +
+  const int64_t eb = d.op.pk16 ? 2 : vb + (use16 ? 2 : 4);  // bytes per entry
+  c->times.cg_spmv_bytes = nnz_total * eb + 8 * (nslices + 1) +
                            (cfg.precision == MRSDC_FP32_REFINE ? 12 : 24) * N;
   c->times.nnz = nnz_total;
   c->times.n = N;

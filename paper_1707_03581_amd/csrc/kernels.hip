@@ -308,6 +308,22 @@ __device__ inline double sell_row_dict(const SellDev &op, int64_t s, int lane, i
   return acc;
 }
 
+// Same through the packed entries: offset in the upper 12 bits, dictionary
+// index in the lower 4.
+template <typename R>
+__device__ inline double sell_row_pk(const SellDev &op, int64_t s, int lane, int64_t row,
+                                     const R *__restrict__ x, const R *sd) {
+  const int64_t end = op.off[s + 1];
+  int64_t e = op.off[s] + lane;
+  R acc = 0;
+#pragma unroll 8
+  for (; e < end; e += kSlice) {
+    const int w = op.pk16[e];
+    acc += sd[w & 15] * x[row + (w >> 4)];
+  }
+  return acc;
+}
+
 template <bool D16, typename R>
 __device__ inline double sell_row_t(const SellDev &op, int64_t s, int lane, int64_t row,
                                     const R *__restrict__ x);
@@ -486,8 +502,10 @@ __global__ void k_solve_reduce(const double *part, int grid, SolveScalars *sc, S
 // (a) q = A p, partial p.q.  TAIL = 1 marks launches past the iteration count
 // of the previous step (usually early exits), TAIL = 2 the stand-alone timing
 // launches (which ignore the convergence flag); both kept apart in profiles.
-template <bool D16, int TAIL, typename R, bool CPL = false, bool DICT = false>
+// FMT: 0 value array, 1 value dictionary, 2 packed entries
+template <bool D16, int TAIL, typename R, bool CPL = false, int FMT = 0>
 __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
+  constexpr bool DICT = FMT != 0;
   if (TAIL != 2 && solve_done(a.sc, a.ctr)) return;
   __shared__ double sh[17];
   __shared__ R sd[DICT ? kDictMax : 1];
@@ -503,8 +521,9 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
   for (int64_t s = wave; s < a.op.nslices; s += nw) {
     const int64_t row = s * kSlice + lane;
     if (row >= a.N) continue;
-    const R Lp = DICT ? (R)sell_row_dict<D16, R>(a.op, s, lane, row, a.p, sd)
-                      : (R)sell_row_t<D16, R>(a.op, s, lane, row, a.p);
+    const R Lp = FMT == 2   ? (R)sell_row_pk<R>(a.op, s, lane, row, a.p, sd)
+                 : FMT == 1 ? (R)sell_row_dict<D16, R>(a.op, s, lane, row, a.p, sd)
+                            : (R)sell_row_t<D16, R>(a.op, s, lane, row, a.p);
     const R pi = a.p[row];
     R qi = a.mass[row] * pi + (R)a.dtau * Lp;
     if (CPL) {  // single-rate method: the coupling of the node operator
@@ -771,9 +790,11 @@ static void pcg_iter(const DevState &d, const CgArgs<R> &a, int it, bool last, b
   // with events: the dispatch's own start/end timestamps (AMD launch extension)
   auto kern = d.op.d16 ? (tail ? k_pcg_a<true, 1, R> : k_pcg_a<true, 0, R>)
                        : (tail ? k_pcg_a<false, 1, R> : k_pcg_a<false, 0, R>);
-  if (d.op.vid)
-    kern = d.op.d16 ? (tail ? k_pcg_a<true, 1, R, false, true> : k_pcg_a<true, 0, R, false, true>)
-                    : (tail ? k_pcg_a<false, 1, R, false, true> : k_pcg_a<false, 0, R, false, true>);
+  if (d.op.pk16)
+    kern = tail ? k_pcg_a<true, 1, R, false, 2> : k_pcg_a<true, 0, R, false, 2>;
+  else if (d.op.vid)
+    kern = d.op.d16 ? (tail ? k_pcg_a<true, 1, R, false, 1> : k_pcg_a<true, 0, R, false, 1>)
+                    : (tail ? k_pcg_a<false, 1, R, false, 1> : k_pcg_a<false, 0, R, false, 1>);
   if (a.ifc_lin)
     kern = d.op.d16 ? (tail ? k_pcg_a<true, 1, R, true> : k_pcg_a<true, 0, R, true>)
                     : (tail ? k_pcg_a<false, 1, R, true> : k_pcg_a<false, 0, R, true>);
@@ -828,8 +849,9 @@ void launch_operator_timing(const DevState &d, int m, bool fp32, int reps, hipSt
   if (fp32) {
     CgArgs<float> a = cg32(d, m, 0);
     for (int i = 0; i < reps; ++i) {
-      if (d.op.vid && d.op.d16) k_pcg_a<true, 2, float, false, true><<<d.grid, kBlock, 0, st>>>(a, 0);
-      else if (d.op.vid) k_pcg_a<false, 2, float, false, true><<<d.grid, kBlock, 0, st>>>(a, 0);
+      if (d.op.pk16) k_pcg_a<true, 2, float, false, 2><<<d.grid, kBlock, 0, st>>>(a, 0);
+      else if (d.op.vid && d.op.d16) k_pcg_a<true, 2, float, false, 1><<<d.grid, kBlock, 0, st>>>(a, 0);
+      else if (d.op.vid) k_pcg_a<false, 2, float, false, 1><<<d.grid, kBlock, 0, st>>>(a, 0);
       else if (d.op.d16) k_pcg_a<true, 2, float><<<d.grid, kBlock, 0, st>>>(a, 0);
       else k_pcg_a<false, 2, float><<<d.grid, kBlock, 0, st>>>(a, 0);
     }
@@ -837,8 +859,9 @@ void launch_operator_timing(const DevState &d, int m, bool fp32, int reps, hipSt
     CgArgs<double> a = cg64(d, m, 0);
     a.x = nullptr;
     for (int i = 0; i < reps; ++i) {
-      if (d.op.vid && d.op.d16) k_pcg_a<true, 2, double, false, true><<<d.grid, kBlock, 0, st>>>(a, 0);
-      else if (d.op.vid) k_pcg_a<false, 2, double, false, true><<<d.grid, kBlock, 0, st>>>(a, 0);
+      if (d.op.pk16) k_pcg_a<true, 2, double, false, 2><<<d.grid, kBlock, 0, st>>>(a, 0);
+      else if (d.op.vid && d.op.d16) k_pcg_a<true, 2, double, false, 1><<<d.grid, kBlock, 0, st>>>(a, 0);
+      else if (d.op.vid) k_pcg_a<false, 2, double, false, 1><<<d.grid, kBlock, 0, st>>>(a, 0);
       else if (d.op.d16) k_pcg_a<true, 2, double><<<d.grid, kBlock, 0, st>>>(a, 0);
       else k_pcg_a<false, 2, double><<<d.grid, kBlock, 0, st>>>(a, 0);
     }

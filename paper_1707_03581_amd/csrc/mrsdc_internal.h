@@ -50,6 +50,9 @@ struct SellDev {
   const double *vdict = nullptr;  // [ndict]
   const float *vdict32 = nullptr; // [ndict] (FP32_REFINE)
   int ndict = 0;
+  // packed entries (at most 16 dictionary values, |col - row| <= 2047):
+  // pk16[e] = (col - row) * 16 + vid[e], one 2-byte load per entry
+  const int16_t *pk16 = nullptr;  // [nelem] or null
 };
 constexpr int kDictMax = 256;
 
