@@ -116,8 +116,13 @@ struct FArgs {
   const double *g;
 };
 
-template <bool D16, int J>
+template <bool D16, int J, bool PK = false>
 __global__ __launch_bounds__(kBlock) void k_f_multi(SellDev op, FArgs a) {
+  __shared__ double sd[PK ? 16 : 1];
+  if (PK) {
+    if (threadIdx.x < op.ndict) sd[threadIdx.x] = op.vdict[threadIdx.x];
+    __syncthreads();
+  }
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
@@ -129,8 +134,16 @@ __global__ __launch_bounds__(kBlock) void k_f_multi(SellDev op, FArgs a) {
     for (int j = 0; j < J; ++j) acc[j] = 0.0;
     const int64_t end = op.off[s + 1];
     for (int64_t e = op.off[s] + lane; e < end; e += kSlice) {
-      const double v = op.val[e];
-      const int64_t c = D16 ? row + op.d16[e] : (int64_t)op.c32[e];
+      double v;
+      int64_t c;
+      if (PK) {  // packed entry: same value, same column
+        const int w = op.pk16[e];
+        v = sd[w & 15];
+        c = row + (w >> 4);
+      } else {
+        v = op.val[e];
+        c = D16 ? row + op.d16[e] : (int64_t)op.c32[e];
+      }
 #pragma unroll
       for (int j = 0; j < J; ++j) acc[j] += v * a.T[j][c];
     }
@@ -145,7 +158,10 @@ static void f_multi_dispatch(const DevState &d, FArgs a, int J, hipStream_t st) 
   const int grid = d.grid;
   switch (J) {
 #define CASE(n) \
-  case n: k_f_multi<D16, n><<<grid, kBlock, 0, st>>>(d.op, a); break;
+  case n:                                                                   \
+    if (d.op.pk16) k_f_multi<D16, n, true><<<grid, kBlock, 0, st>>>(d.op, a); \
+    else k_f_multi<D16, n><<<grid, kBlock, 0, st>>>(d.op, a);               \
+    break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     default: break;
@@ -402,9 +418,14 @@ __device__ inline void init_finish(SolveScalars *sc, StepCounters *ctr, int slot
 }
 
 // predictor: x0 = T_{m-1}, b = M T_{m-1} + dtau g, r = b - A x0 (one SpMV)
-template <bool D16>
+template <bool D16, bool PK = false>
 __global__ __launch_bounds__(kBlock) void k_init_pred(CgArgs<double> a) {
   __shared__ double sh[17];
+  __shared__ double sd[PK ? 16 : 1];
+  if (PK) {
+    if (threadIdx.x < a.op.ndict) sd[threadIdx.x] = a.op.vdict[threadIdx.x];
+    __syncthreads();
+  }
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
@@ -412,7 +433,8 @@ __global__ __launch_bounds__(kBlock) void k_init_pred(CgArgs<double> a) {
   for (int64_t s = wave; s < a.op.nslices; s += nw) {
     const int64_t row = s * kSlice + lane;
     if (row >= a.N) continue;
-    const double Lx = sell_row<D16>(a.op, s, lane, row, a.Tprev);
+    const double Lx = PK ? sell_row_pk<double>(a.op, s, lane, row, a.Tprev, sd)
+                         : sell_row<D16>(a.op, s, lane, row, a.Tprev);
     const double x0 = a.Tprev[row], mi = a.mass[row];
     double b = mi * x0 + a.dtau * a.g[row];
     double Ax = mi * x0 + a.dtau * Lx;
@@ -772,7 +794,8 @@ static void solve_reduce(const DevState &d, int slot, int mode, double rtol, int
 void launch_init_pred(const DevState &d, int m, int slot, double rtol, hipStream_t st) {
   CgArgs<double> a = cg64(d, m, slot);
   if (a.ifc_lin) launch_iface_lin(d, m, d.T[m - 1], st);  // coupling of A x0 and its source
-  if (d.op.d16) k_init_pred<true><<<d.grid, kBlock, 0, st>>>(a);
+  if (d.op.pk16) k_init_pred<true, true><<<d.grid, kBlock, 0, st>>>(a);
+  else if (d.op.d16) k_init_pred<true><<<d.grid, kBlock, 0, st>>>(a);
   else k_init_pred<false><<<d.grid, kBlock, 0, st>>>(a);
   solve_reduce(d, slot, 0, rtol, 0, false, st);
 }
@@ -831,7 +854,8 @@ static CgArgs<double> stationary_args(const DevState &d, const double *zeros, co
 void launch_stationary_init(const DevState &d, const double *zeros, const double *dinv, int slot,
                             double rtol, hipStream_t st) {
   const CgArgs<double> a = stationary_args(d, zeros, dinv, slot);
-  if (d.op.d16) k_init_pred<true><<<d.grid, kBlock, 0, st>>>(a);
+  if (d.op.pk16) k_init_pred<true, true><<<d.grid, kBlock, 0, st>>>(a);
+  else if (d.op.d16) k_init_pred<true><<<d.grid, kBlock, 0, st>>>(a);
   else k_init_pred<false><<<d.grid, kBlock, 0, st>>>(a);
   solve_reduce(d, slot, 0, rtol, 0, false, st);
 }
