@@ -266,46 +266,134 @@ mrsdc_status band_coeffs(mrsdc_ctx *c, const std::vector<double> &x, const std::
 // and R).  The tiling depends on the mesh only (not on S or precision), so a
 // scenario's arithmetic is the same in any batch.  col: global column of
 // every merged entry.
+// Grid dimensions of a body whose pattern is the 27-point stencil of an
+// nx x ny x nz node grid numbered x fastest (the box bodies), else false.
+bool box_dims(const HostBody &B, int64_t dims[3]) {
+  if (B.n < 8 || B.rowptr[1] - B.rowptr[0] != 8) return false;
+  const int64_t nx = B.col[B.rowptr[0] + 2], nxy = B.col[B.rowptr[0] + 4];
+  if (nx < 2 || nxy % nx != 0 || B.n % nxy != 0) return false;
+  const int64_t ny = nxy / nx, nz = B.n / nxy;
+  if (ny < 2 || nz < 2) return false;
+  for (int64_t i = 0; i < B.n; ++i) {
+    const int64_t ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
+    int64_t e = B.rowptr[i];
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int64_t x = ix + dx, y = iy + dy, z = iz + dz;
+          if (x < 0 || x >= nx || y < 0 || y >= ny || z < 0 || z >= nz) continue;
+          if (e >= B.rowptr[i + 1] || B.col[e] != x + nx * (y + ny * z)) return false;
+          ++e;
+        }
+    if (e != B.rowptr[i + 1]) return false;
+  }
+  dims[0] = nx;
+  dims[1] = ny;
+  dims[2] = nz;
+  return true;
+}
+
+// Tiles of the staged products and the operator stored in tile order.  On
+// box bodies a tile is a block of up to 3 x 3 x 3 nodes: its column union is
+// at most 5 x 5 x 5 = 125 rows for 27 rows (about 4.6 staged rows per row,
+// against 10.5 for a run of 12 consecutive rows); otherwise tiles are runs of
+// consecutive rows.  rowptr / col / val / nk are by row; the device gets them
+// by tile position (row prow[pos]), tile t holding positions
+// [tstart[t], tstart[t+1]).
 mrsdc_status build_stage_tiles(mrsdc_ctx *c, int64_t N, const std::vector<int64_t> &rowptr,
-                               const std::vector<int64_t> &col, BatchArgs &a) {
+                               const std::vector<int64_t> &col, const std::vector<double> &val,
+                               const std::vector<int> &nk, BatchArgs &a) {
+  std::vector<int64_t> order, tstart;
+  // block tiling when every body is a box
+  bool blocks = true;
+  for (int b = 0; b < c->nbody && blocks; ++b) {
+    int64_t dm[3];
+    if (!box_dims(c->body[b], dm)) {
+      blocks = false;
+      break;
+    }
+    for (int64_t bz = 0; bz < dm[2]; bz += 3)
+      for (int64_t by = 0; by < dm[1]; by += 3)
+        for (int64_t bx = 0; bx < dm[0]; bx += 3) {
+          tstart.push_back((int64_t)order.size());
+          for (int64_t z = bz; z < std::min(bz + 3, dm[2]); ++z)
+            for (int64_t y = by; y < std::min(by + 3, dm[1]); ++y)
+              for (int64_t x = bx; x < std::min(bx + 3, dm[0]); ++x)
+                order.push_back(c->off[b] + x + dm[0] * (y + dm[1] * z));
+        }
+  }
   static const int kTry[] = {32, 24, 16, 12, 10, 8, 6, 4, 3, 2, 1};  // at most 4 kMaxR rows
   std::vector<int64_t> cols;
-  std::vector<int> nslots, slot_row;
-  std::vector<int> slot(col.size());
-  std::vector<uint16_t> oslot(N);
-  for (int TR : kTry) {
-    const int64_t T = (N + TR - 1) / TR;
-    nslots.assign(T, 0);
-    slot_row.assign((size_t)T * kStageSlots, 0);
+  for (int attempt = blocks ? -1 : 0; attempt < (int)(sizeof kTry / sizeof kTry[0]); ++attempt) {
+    if (attempt >= 0) {  // runs of consecutive rows
+      const int TR = kTry[attempt];
+      order.resize(N);
+      for (int64_t r = 0; r < N; ++r) order[r] = r;
+      tstart.clear();
+      for (int64_t r = 0; r < N; r += TR) tstart.push_back(r);
+    }
+    if (tstart.empty() || tstart.back() != N) tstart.push_back(N);
+    const int64_t T = (int64_t)tstart.size() - 1;
+    std::vector<int> nslots(T, 0), slot_row((size_t)T * kStageSlots, 0);
+    std::vector<int64_t> prp(N + 1, 0);
+    std::vector<int> pnk(N), slot;
+    std::vector<uint16_t> oslot(N);
+    std::vector<double> pval, pmass(N), rmass(N);
+    for (int b = 0; b < c->nbody; ++b)
+      for (int64_t i = 0; i < c->body[b].n; ++i) rmass[c->off[b] + i] = c->body[b].mass[i];
+    slot.reserve(col.size());
+    pval.reserve(col.size());
     bool fits = true;
     for (int64_t t = 0; t < T && fits; ++t) {
-      const int64_t e0 = rowptr[t * TR], e1 = rowptr[std::min<int64_t>(N, (t + 1) * TR)];
-      if (e1 - e0 > kMaxTileEntries) {
-        fits = false;
-        break;
+      if (tstart[t + 1] - tstart[t] > 4 * kMaxR) fits = false;
+      cols.clear();
+      int64_t ne = 0;
+      for (int64_t q = tstart[t]; q < tstart[t + 1]; ++q) {
+        const int64_t r = order[q];
+        ne += rowptr[r + 1] - rowptr[r];
+        cols.insert(cols.end(), col.begin() + rowptr[r], col.begin() + rowptr[r + 1]);
       }
-      cols.assign(col.begin() + e0, col.begin() + e1);
       std::sort(cols.begin(), cols.end());
       cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
-      if ((int64_t)cols.size() > kStageSlots) {
+      if (ne > kMaxTileEntries || (int64_t)cols.size() > kStageSlots) {
         fits = false;
         break;
       }
       nslots[t] = (int)cols.size();
       for (size_t k = 0; k < cols.size(); ++k) slot_row[(size_t)t * kStageSlots + k] = (int)cols[k];
-      for (int64_t e = e0; e < e1; ++e)
-        slot[e] = (int)(std::lower_bound(cols.begin(), cols.end(), col[e]) - cols.begin());
-      for (int64_t r = t * TR; r < std::min<int64_t>(N, (t + 1) * TR); ++r) {
+      for (int64_t q = tstart[t]; q < tstart[t + 1]; ++q) {
+        const int64_t r = order[q];
+        for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+          slot.push_back((int)(std::lower_bound(cols.begin(), cols.end(), col[e]) - cols.begin()));
+          pval.push_back(val[e]);
+        }
+        prp[q + 1] = (int64_t)slot.size();
+        pnk[q] = nk[r];
+        pmass[q] = rmass[r];
         const auto it = std::lower_bound(cols.begin(), cols.end(), r);
         if (it == cols.end() || *it != r)
           return fail(c, MRSDC_EINVAL, "row %lld has no diagonal entry", (long long)r);
-        oslot[r] = (uint16_t)(it - cols.begin());
+        oslot[q] = (uint16_t)(it - cols.begin());
       }
     }
     if (!fits) continue;
     mrsdc_status st;
     int *pi;
+    int64_t *pl;
     uint16_t *pu;
+    double *pv;
+    if ((st = upload(c, &pl, prp))) return st;
+    a.op.rowptr = pl;
+    if ((st = upload(c, &pi, pnk))) return st;
+    a.op.nk = pi;
+    if ((st = upload(c, &pv, pval))) return st;
+    a.op.val = pv;
+    if (c->cfg.precision == MRSDC_FP32_REFINE) {
+      std::vector<float> v32(pval.begin(), pval.end());
+      float *pf32;
+      if ((st = upload(c, &pf32, v32))) return st;
+      a.op.val32 = pf32;
+    }
     if ((st = upload(c, &pi, nslots))) return st;
     a.op.nslots = pi;
     if ((st = upload(c, &pi, slot_row))) return st;
@@ -314,8 +402,15 @@ mrsdc_status build_stage_tiles(mrsdc_ctx *c, int64_t N, const std::vector<int64_
     a.op.slot32 = pi;
     if ((st = upload(c, &pu, oslot))) return st;
     a.op.oslot = pu;
-    a.op.TR = TR;
+    if ((st = upload(c, &pl, tstart))) return st;
+    a.op.tstart = pl;
+    if ((st = upload(c, &pl, order))) return st;
+    a.op.prow = pl;
+    if ((st = upload(c, &pv, pmass))) return st;
+    a.op.pmass = pv;
+    a.op.TR = attempt >= 0 ? kTry[attempt] : 0;  // 0: node blocks
     a.op.ntiles = (int)T;
+    c->batch_entries = (int64_t)slot.size();
     // every workgroup resident: two FP64 or three FP32 staging buffers per CU
     // on 256 CUs
     a.sgrid64 = (int)std::min<int64_t>((T + 7) / 8 * 8, 512);
@@ -371,18 +466,9 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
   // blocks of 4 rows, a multiple of the 8 XCDs
   a.grid = (int)std::min<int64_t>(((N + 3) / 4 + 7) / 8 * 8, 1024);
   for (int m = 0; m <= c->cfg.M; ++m) a.dtau_h[m] = c->w.dtau[m];
-  int64_t *prp;
-  int *pi;
   double *pv;
-  if ((st = upload(c, &prp, rowptr))) return st;
-  a.op.rowptr = prp;
-  c->batch_entries = rowptr[N];
-  if ((st = upload(c, &pi, nk))) return st;
-  a.op.nk = pi;
-  if ((st = upload(c, &pv, val))) return st;
-  a.op.val = pv;
   a.op.N = N;
-  if ((st = build_stage_tiles(c, N, rowptr, col, a))) return st;
+  if ((st = build_stage_tiles(c, N, rowptr, col, val, nk, a))) return st;
   if ((st = upload(c, &pv, Kd))) return st;
   a.Kd = pv;
   if ((st = upload(c, &pv, Rd))) return st;
@@ -434,10 +520,6 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
     // FP32 copies of the shared operator values for the inner solves; FP32
     // inner vectors and the FP64 refinement residual, scenario-interleaved
     a.fp32 = 1;
-    std::vector<float> v32(val.begin(), val.end());
-    float *pf32;
-    if ((st = upload(c, &pf32, v32))) return st;
-    a.op.val32 = pf32;
     const size_t NS = (size_t)N * S;
     if ((st = dalloc(c, &a.x32, NS)) || (st = dalloc(c, &a.r32, NS)) ||
         (st = dalloc(c, &a.p32, NS)) || (st = dalloc(c, &a.q32, NS)) ||

@@ -14,7 +14,7 @@ constexpr int kMaxS = 64;  // scenarios per batch = lanes of a wavefront
 // sl of tile t, slot[e] = slot of entry e's column within its row's tile.
 struct BatchOp {
   int64_t N = 0;
-  const int64_t *rowptr = nullptr;  // [N+1] over the merged entries
+  const int64_t *rowptr = nullptr;  // [N+1] over the merged entries, by tile position
   const int *nk = nullptr;          // [N] K entries of the row (the rest are R)
   const double *val = nullptr;      // entry values
   const float *val32 = nullptr;     // FP32 copy (FP32 form)
@@ -23,7 +23,13 @@ struct BatchOp {
   int TR = 0, ntiles = 0;
   const int *nslots = nullptr;    // [ntiles]
   const int *slot_row = nullptr;  // [ntiles][kStageSlots]
+  // rows in tile order: tile t holds positions [tstart[t], tstart[t+1]);
+  // rowptr, nk and oslot are indexed by position, prow[pos] is the row
+  const int64_t *tstart = nullptr;  // [ntiles + 1]
+  const int64_t *prow = nullptr;    // [N]
+  const double *pmass = nullptr;    // [N] lumped mass of row prow[pos]
 };
+constexpr int kMaxR = 8;  // tiles hold at most 4 kMaxR rows
 
 // Staging buffer of the tiled kernels: 64 KB per workgroup (two workgroups
 // fit in one CU's LDS), rows of up to 64 FP64 scenario values.

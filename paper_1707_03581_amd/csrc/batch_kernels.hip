@@ -111,7 +111,6 @@ __device__ inline float readlane_t<float>(float v, int l) {
 // each lane walking its own row's entries (no cross-lane broadcast).  The
 // mapping does not depend on S, so neither does any summation order.
 // ---------------------------------------------------------------------------
-constexpr int kMaxR = 8;  // tiles hold at most 4 kMaxR rows
 
 template <typename XT>
 struct Lanes {
@@ -256,24 +255,25 @@ __device__ __attribute__((always_inline)) inline void tile_apply(
   const int S = a.S;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane / LY::LPR, s0 = (lane % LY::LPR) * VEC;
-  const int64_t r0 = (int64_t)t * op.TR, r1 = r0 + op.TR < a.N ? r0 + op.TR : a.N;
+  const int64_t r0 = op.tstart[t], r1 = op.tstart[t + 1];  // tile positions
   // (1) slot rows, entry range, and the lane's rows
   int srv = 0;
   if (tid < kStageSlots) srv = op.slot_row[(size_t)t * kStageSlots + tid];
   const int ns = op.nslots[t];
   const int64_t E0 = op.rowptr[r0], E1 = op.rowptr[r1];
-  int64_t lo[NI], hi[NI];
+  int64_t lo[NI], hi[NI], rw[NI];
   int nk[NI], os[NI];
   double ms[NI];
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
-    int64_t row = r0 + (int64_t)(w + 4 * i) * LY::RPW + lr;
-    row = row < r1 ? row : r1 - 1;
-    lo[i] = op.rowptr[row];
-    hi[i] = op.rowptr[row + 1];
-    nk[i] = op.nk[row];
-    os[i] = op.oslot[row];
-    ms[i] = a.mass[row];
+    int64_t pos = r0 + (int64_t)(w + 4 * i) * LY::RPW + lr;
+    pos = pos < r1 ? pos : r1 - 1;
+    lo[i] = op.rowptr[pos];
+    hi[i] = op.rowptr[pos + 1];
+    nk[i] = op.nk[pos];
+    os[i] = op.oslot[pos];
+    rw[i] = op.prow[pos];
+    ms[i] = op.pmass[pos];
   }
   __builtin_amdgcn_s_waitcnt(0);
   if (tid < kStageSlots) L.ssl[tid] = srv;
@@ -287,8 +287,9 @@ __device__ __attribute__((always_inline)) inline void tile_apply(
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
-    const int64_t row = r0 + (int64_t)(w + 4 * i) * LY::RPW + lr;
-    if (row >= r1) continue;
+    const int64_t pos = r0 + (int64_t)(w + 4 * i) * LY::RPW + lr;
+    if (pos >= r1) continue;
+    const int64_t row = rw[i];
     const int rel = (int)(lo[i] - E0), n = (int)(hi[i] - lo[i]);
     AT acc[VEC] = {}, accr[VEC] = {};
     entry_sum<AT, VT, XT, AL>(L, rel, 0, nk[i], S, s0, acc);
