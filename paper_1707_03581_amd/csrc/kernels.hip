@@ -651,10 +651,15 @@ __global__ __launch_bounds__(kBlock) void k_pcg_c(CgArgs<R> a, int it, int last)
 
 // ---- FP64 iterative refinement around FP32 inner solves ----
 // init: b and r = b - A x0 in FP64 (corrections without SpMV as above)
-template <bool D16, bool PRED>
+template <bool D16, bool PRED, bool PK = false>
 __global__ __launch_bounds__(kBlock) void k_rinit(CgArgs<float> a, const double *mass64) {
   if (a.ctr->stop) return;
   __shared__ double sh[17];
+  __shared__ double sd[PK ? 16 : 1];
+  if (PK) {
+    if (threadIdx.x < a.op.ndict) sd[threadIdx.x] = a.op.vdict[threadIdx.x];
+    __syncthreads();
+  }
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
@@ -665,7 +670,8 @@ __global__ __launch_bounds__(kBlock) void k_rinit(CgArgs<float> a, const double 
     const double mi = mass64[row], tp = a.Tprev[row];
     double b, r;
     if (PRED) {
-      const double Lx = sell_row<D16>(a.op, s, lane, row, a.Tprev);
+      const double Lx = PK ? sell_row_pk<double>(a.op, s, lane, row, a.Tprev, sd)
+                           : sell_row<D16>(a.op, s, lane, row, a.Tprev);
       b = mi * tp + a.dtau * a.g[row];
       r = b - (mi * tp + a.dtau * Lx);
       a.x64[row] = tp;
@@ -700,11 +706,30 @@ __global__ __launch_bounds__(kBlock) void k_inner_init(CgArgs<float> a) {
   publish<2>(v, a.partial, a.grid, sh);
 }
 
+// FP64 operator on an FP32 vector through the packed entries
+__device__ inline double sell_row_pk_mixed(const SellDev &op, int64_t s, int lane, int64_t row,
+                                           const float *__restrict__ x, const double *sd) {
+  const int64_t end = op.off[s + 1];
+  int64_t e = op.off[s] + lane;
+  double acc = 0.0;
+#pragma unroll 4
+  for (; e < end; e += kSlice) {
+    const int w = op.pk16[e];
+    acc += sd[w & 15] * (double)x[row + (w >> 4)];
+  }
+  return acc;
+}
+
 // x64 += d; r64 -= A d (FP64 operator); ||r64|| -> refinement converged?
-template <bool D16>
+template <bool D16, bool PK = false>
 __global__ __launch_bounds__(kBlock) void k_refine_update(CgArgs<float> a, const double *mass64) {
   if (a.sc->ref_done || a.ctr->stop) return;
   __shared__ double sh[17];
+  __shared__ double sd[PK ? 16 : 1];
+  if (PK) {
+    if (threadIdx.x < a.op.ndict) sd[threadIdx.x] = a.op.vdict[threadIdx.x];
+    __syncthreads();
+  }
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
@@ -713,7 +738,9 @@ __global__ __launch_bounds__(kBlock) void k_refine_update(CgArgs<float> a, const
     const int64_t row = s * kSlice + lane;
     if (row >= a.N) continue;
     const double d = (double)a.x[row];
-    const double Ad = mass64[row] * d + a.dtau * sell_row_mixed<D16>(a.op, s, lane, row, a.x);
+    const double Ld = PK ? sell_row_pk_mixed(a.op, s, lane, row, a.x, sd)
+                         : sell_row_mixed<D16>(a.op, s, lane, row, a.x);
+    const double Ad = mass64[row] * d + a.dtau * Ld;
     a.x64[row] += d;
     const double r = a.r64[row] - Ad;
     a.r64[row] = r;
@@ -895,7 +922,10 @@ void launch_operator_timing(const DevState &d, int m, bool fp32, int reps, hipSt
 void launch_refine_init(const DevState &d, int m, int slot, bool pred, double rtol,
                         hipStream_t st) {
   CgArgs<float> a = cg32(d, m, slot);
-  if (d.op.d16) {
+  if (d.op.pk16) {
+    if (pred) k_rinit<true, true, true><<<d.grid, kBlock, 0, st>>>(a, d.mass);
+    else k_rinit<true, false, true><<<d.grid, kBlock, 0, st>>>(a, d.mass);
+  } else if (d.op.d16) {
     if (pred) k_rinit<true, true><<<d.grid, kBlock, 0, st>>>(a, d.mass);
     else k_rinit<true, false><<<d.grid, kBlock, 0, st>>>(a, d.mass);
   } else {
@@ -918,7 +948,8 @@ void launch_pcg32_iter(const DevState &d, int m, int slot, int it, bool last, bo
 void launch_refine_update(const DevState &d, int m, int slot, int round, bool last_round,
                           hipStream_t st) {
   CgArgs<float> a = cg32(d, m, slot);
-  if (d.op.d16) k_refine_update<true><<<d.grid, kBlock, 0, st>>>(a, d.mass);
+  if (d.op.pk16) k_refine_update<true, true><<<d.grid, kBlock, 0, st>>>(a, d.mass);
+  else if (d.op.d16) k_refine_update<true><<<d.grid, kBlock, 0, st>>>(a, d.mass);
   else k_refine_update<false><<<d.grid, kBlock, 0, st>>>(a, d.mass);
   solve_reduce(d, slot, 3, 0.0, round, last_round, st);
 }
