@@ -1286,18 +1286,17 @@ __global__ __launch_bounds__(kBlock) void k_iface_quad(SubArgs A) {
   if (i >= n) return;
   const Weights &w = *A.w;
   const int P = A.P, P1 = P + 1;
+  const int m = blockIdx.y + 1;  // one interval per grid row
+  if (w.dtau[m] == 0.0) return;
   const int64_t row = A.f.rows[i];
   double F[kMaxM + 1];
   for (int j = 1; j <= A.M; ++j) F[j] = A.F[j][row];
-  for (int m = 1; m <= A.M; ++m) {
-    if (w.dtau[m] == 0.0) continue;
-    const double *Eo = A.Eold + (size_t)m * P1 * n;
-    for (int p = 1; p <= P; ++p) {
-      double Ip = 0.0;
-      for (int j = 1; j <= A.M; ++j) Ip += w.stil[m][p][j] * F[j];
-      for (int q = 1; q <= P; ++q) Ip += w.spq[m][p][q] * Eo[(size_t)q * n + i];
-      A.Ipre[((size_t)m * P1 + p) * n + i] = Ip;
-    }
+  const double *Eo = A.Eold + (size_t)m * P1 * n;
+  for (int p = 1; p <= P; ++p) {
+    double Ip = 0.0;
+    for (int j = 1; j <= A.M; ++j) Ip += w.stil[m][p][j] * F[j];
+    for (int q = 1; q <= P; ++q) Ip += w.spq[m][p][q] * Eo[(size_t)q * n + i];
+    A.Ipre[((size_t)m * P1 + p) * n + i] = Ip;
   }
 }
 
@@ -1312,7 +1311,7 @@ void launch_iface_quad(const DevState &d, hipStream_t st) {
   for (int j = 0; j <= kMaxM; ++j) A.F[j] = d.F[j];
   A.Eold = d.Eold;
   A.Ipre = d.Ipre;
-  k_iface_quad<<<(d.ifc.n_if + kBlock - 1) / kBlock, kBlock, 0, st>>>(A);
+  k_iface_quad<<<dim3((d.ifc.n_if + kBlock - 1) / kBlock, d.M), kBlock, 0, st>>>(A);
 }
 
 void launch_iface(const DevState &d, int m, bool corr, hipStream_t st) {

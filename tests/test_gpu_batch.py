@@ -202,3 +202,26 @@ def test_ensemble_7p5mm_fp32_refine_sampled():
         e = rel(outs[s], ref)
         print(f"  member {s}: rel_l2={e:.3e}", flush=True)
         assert e <= TOL32
+
+
+def test_node_block_tiles_equal_row_run_tiles():
+    """Box bodies are tiled by 3 x 3 x 3 node blocks, other operators by runs
+    of consecutive rows.  A stored zero outside the 27-point pattern (it adds
+    no arithmetic) turns the stand into a general operator, so the same
+    problem runs through both tilings: every row keeps its entry order, so
+    the results must agree bitwise."""
+    from dataclasses import replace
+    pb = small_machine()
+    mem = members_for(pb, 5, seed0=1700)
+    blocks, _, _ = run_batch(pb, mem, 2)
+    b = pb.bodies[0]
+    n = b.n
+    rp = b.rowptr.copy()
+    rp[1:] += 1
+    col = np.insert(b.col, int(b.rowptr[1]), n - 1).astype(np.int32)
+    K = np.insert(b.K, int(b.rowptr[1]), 0.0)
+    R = np.insert(b.R, int(b.rowptr[1]), 0.0)
+    pb2 = replace(pb, bodies=[replace(b, rowptr=rp, col=col, K=K, R=R), pb.bodies[1]])
+    runs, _, _ = run_batch(pb2, mem, 2)
+    for s in range(len(mem)):
+        assert np.array_equal(blocks[s], runs[s]), s
