@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <map>
 #include <unordered_map>
 #include <vector>
 
@@ -698,6 +699,51 @@ mrsdc_status prepare(mrsdc_ctx *c) {
       d.op.vid = pv;
       d.op.vdict = pd;
       d.op.ndict = (int)vdict.size();
+      if (use16) {  // row patterns
+        std::map<std::vector<int>, int> forms;
+        std::vector<uint8_t> rcls(N, 0);
+        std::vector<std::vector<int>> list;
+        bool ok = true;
+        std::vector<int> key;
+        for (int64_t r = 0; r < N && ok; ++r) {
+          const int64_t s = r / kSlice, lane = r % kSlice;
+          key.clear();
+          for (int64_t e = off[s] + lane; e < off[s + 1]; e += kSlice)
+            key.push_back((int)d16[e] * 256 + (int)vid[e]);
+          if ((int)key.size() > kMaxClsWidth) {
+            ok = false;
+            break;
+          }
+          auto it = forms.find(key);
+          if (it == forms.end()) {
+            if ((int)list.size() == kMaxCls) {
+              ok = false;
+              break;
+            }
+            it = forms.emplace(key, (int)list.size()).first;
+            list.push_back(key);
+          }
+          rcls[r] = (uint8_t)it->second;
+        }
+        if (ok) {
+          int cw = 1;
+          for (auto &l : list) cw = std::max(cw, (int)l.size());
+          std::vector<int> ctab(list.size() * (size_t)cw, 0), clen(list.size());
+          for (size_t cI = 0; cI < list.size(); ++cI) {
+            clen[cI] = (int)list[cI].size();
+            std::copy(list[cI].begin(), list[cI].end(), ctab.begin() + cI * cw);
+          }
+          uint8_t *pr;
+          int *pt, *pl;
+          if ((st = upload(c, &pr, rcls)) || (st = upload(c, &pt, ctab)) || (st = upload(c, &pl, clen)))
+            return st;
+          d.op.rcls = pr;
+          d.op.ctab = pt;
+          d.op.clen = pl;
+          d.op.ncls = (int)list.size();
+          d.op.cw = cw;
+        }
+      }
       if (use16 && maxdelta <= 2047 && vdict.size() <= 16) {
         std::vector<int16_t> pk(nelem);
         for (int64_t e = 0; e < nelem; ++e) pk[e] = (int16_t)(d16[e] * 16 + vid[e]);
@@ -720,7 +766,7 @@ mrsdc_status prepare(mrsdc_ctx *c) {
   // FP32 for the inner solves of the FP32 path) + column offsets + p, mass, q
   const int64_t vb = dict ? 1 : (cfg.precision == MRSDC_FP32_REFINE ? 4 : 8);
   const int64_t eb = d.op.pk16 ? 2 : vb + (use16 ? 2 : 4);  // bytes per entry
-  c->times.cg_spmv_bytes = nnz_total * eb + 8 * (nslices + 1) +
+  c->times.cg_spmv_bytes = (d.op.rcls ? N : nnz_total * eb) + 8 * (nslices + 1) +
                            (cfg.precision == MRSDC_FP32_REFINE ? 12 : 24) * N;
   c->times.nnz = nnz_total;
   c->times.n = N;

@@ -340,6 +340,23 @@ __device__ inline double sell_row_pk(const SellDev &op, int64_t s, int lane, int
   return acc;
 }
 
+// Same through the row patterns (form table in LDS): the same entries, in the
+// same order, slice padding included, so the same sums.
+template <typename R>
+__device__ inline double sell_row_cls(const SellDev &op, int64_t row, const R *__restrict__ x,
+                                      const R *sd, const int *sct, const int *slen) {
+  const int c = op.rcls[row];
+  const int n = slen[c];
+  const int *t = sct + c * op.cw;
+  R acc = 0;
+#pragma unroll 8
+  for (int k = 0; k < n; ++k) {
+    const int w = t[k];
+    acc += sd[w & 255] * x[row + (w >> 8)];
+  }
+  return acc;
+}
+
 template <bool D16, typename R>
 __device__ inline double sell_row_t(const SellDev &op, int64_t s, int lane, int64_t row,
                                     const R *__restrict__ x);
@@ -524,16 +541,22 @@ __global__ void k_solve_reduce(const double *part, int grid, SolveScalars *sc, S
 // (a) q = A p, partial p.q.  TAIL = 1 marks launches past the iteration count
 // of the previous step (usually early exits), TAIL = 2 the stand-alone timing
 // launches (which ignore the convergence flag); both kept apart in profiles.
-// FMT: 0 value array, 1 value dictionary, 2 packed entries
+// FMT: 0 value array, 1 value dictionary, 2 packed entries, 3 row patterns
 template <bool D16, int TAIL, typename R, bool CPL = false, int FMT = 0>
 __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
   constexpr bool DICT = FMT != 0;
   if (TAIL != 2 && solve_done(a.sc, a.ctr)) return;
   __shared__ double sh[17];
   __shared__ R sd[DICT ? kDictMax : 1];
+  __shared__ int sct[FMT == 3 ? kMaxCls * kMaxClsWidth : 1];
+  __shared__ int slen[FMT == 3 ? kMaxCls : 1];
   if (DICT) {
     const R *dict = sizeof(R) == 8 ? (const R *)a.op.vdict : (const R *)a.op.vdict32;
     for (int j = threadIdx.x; j < a.op.ndict; j += kBlock) sd[j] = dict[j];
+    if (FMT == 3) {
+      for (int j = threadIdx.x; j < a.op.ncls * a.op.cw; j += kBlock) sct[j] = a.op.ctab[j];
+      for (int j = threadIdx.x; j < a.op.ncls; j += kBlock) slen[j] = a.op.clen[j];
+    }
     __syncthreads();
   }
   const int lane = threadIdx.x & 63;
@@ -543,7 +566,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
   for (int64_t s = wave; s < a.op.nslices; s += nw) {
     const int64_t row = s * kSlice + lane;
     if (row >= a.N) continue;
-    const R Lp = FMT == 2   ? (R)sell_row_pk<R>(a.op, s, lane, row, a.p, sd)
+    const R Lp = FMT == 3   ? (R)sell_row_cls<R>(a.op, row, a.p, sd, sct, slen)
+                 : FMT == 2 ? (R)sell_row_pk<R>(a.op, s, lane, row, a.p, sd)
                  : FMT == 1 ? (R)sell_row_dict<D16, R>(a.op, s, lane, row, a.p, sd)
                             : (R)sell_row_t<D16, R>(a.op, s, lane, row, a.p);
     const R pi = a.p[row];
@@ -840,7 +864,9 @@ static void pcg_iter(const DevState &d, const CgArgs<R> &a, int it, bool last, b
   // with events: the dispatch's own start/end timestamps (AMD launch extension)
   auto kern = d.op.d16 ? (tail ? k_pcg_a<true, 1, R> : k_pcg_a<true, 0, R>)
                        : (tail ? k_pcg_a<false, 1, R> : k_pcg_a<false, 0, R>);
-  if (d.op.pk16)
+  if (d.op.rcls)
+    kern = tail ? k_pcg_a<true, 1, R, false, 3> : k_pcg_a<true, 0, R, false, 3>;
+  else if (d.op.pk16)
     kern = tail ? k_pcg_a<true, 1, R, false, 2> : k_pcg_a<true, 0, R, false, 2>;
   else if (d.op.vid)
     kern = d.op.d16 ? (tail ? k_pcg_a<true, 1, R, false, 1> : k_pcg_a<true, 0, R, false, 1>)
@@ -900,7 +926,8 @@ void launch_operator_timing(const DevState &d, int m, bool fp32, int reps, hipSt
   if (fp32) {
     CgArgs<float> a = cg32(d, m, 0);
     for (int i = 0; i < reps; ++i) {
-      if (d.op.pk16) k_pcg_a<true, 2, float, false, 2><<<d.grid, kBlock, 0, st>>>(a, 0);
+      if (d.op.rcls) k_pcg_a<true, 2, float, false, 3><<<d.grid, kBlock, 0, st>>>(a, 0);
+      else if (d.op.pk16) k_pcg_a<true, 2, float, false, 2><<<d.grid, kBlock, 0, st>>>(a, 0);
       else if (d.op.vid && d.op.d16) k_pcg_a<true, 2, float, false, 1><<<d.grid, kBlock, 0, st>>>(a, 0);
       else if (d.op.vid) k_pcg_a<false, 2, float, false, 1><<<d.grid, kBlock, 0, st>>>(a, 0);
       else if (d.op.d16) k_pcg_a<true, 2, float><<<d.grid, kBlock, 0, st>>>(a, 0);
@@ -910,7 +937,8 @@ void launch_operator_timing(const DevState &d, int m, bool fp32, int reps, hipSt
     CgArgs<double> a = cg64(d, m, 0);
     a.x = nullptr;
     for (int i = 0; i < reps; ++i) {
-      if (d.op.pk16) k_pcg_a<true, 2, double, false, 2><<<d.grid, kBlock, 0, st>>>(a, 0);
+      if (d.op.rcls) k_pcg_a<true, 2, double, false, 3><<<d.grid, kBlock, 0, st>>>(a, 0);
+      else if (d.op.pk16) k_pcg_a<true, 2, double, false, 2><<<d.grid, kBlock, 0, st>>>(a, 0);
       else if (d.op.vid && d.op.d16) k_pcg_a<true, 2, double, false, 1><<<d.grid, kBlock, 0, st>>>(a, 0);
       else if (d.op.vid) k_pcg_a<false, 2, double, false, 1><<<d.grid, kBlock, 0, st>>>(a, 0);
       else if (d.op.d16) k_pcg_a<true, 2, double><<<d.grid, kBlock, 0, st>>>(a, 0);

@@ -53,8 +53,17 @@ struct SellDev {
   // packed entries (at most 16 dictionary values, |col - row| <= 2047):
   // pk16[e] = (col - row) * 16 + vid[e], one 2-byte load per entry
   const int16_t *pk16 = nullptr;  // [nelem] or null
+  // row patterns: when the rows' lists of (col - row, dictionary index),
+  // slice padding included, take at most kMaxCls distinct forms, row r reads
+  // form rcls[r]: clen[c] words ctab[c * cw + k] = (col - row) * 256 + index
+  const uint8_t *rcls = nullptr;  // [nrows] or null
+  const int *ctab = nullptr;      // [ncls][cw]
+  const int *clen = nullptr;      // [ncls]
+  int ncls = 0, cw = 0;
 };
 constexpr int kDictMax = 256;
+constexpr int kMaxCls = 128;
+constexpr int kMaxClsWidth = 32;
 
 // Per-solve device scalars of the CG iteration and of the refinement loop.
 struct SolveScalars {
