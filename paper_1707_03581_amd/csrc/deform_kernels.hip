@@ -283,55 +283,51 @@ __global__ __launch_bounds__(kThreads) void k_bwd_rhs(DeformDev D, int64_t k) {
 }
 
 // Dense block product: MODE 0 out = W v, MODE 1 out = base - W v; ld is a
-// multiple of 64.  The vector sits in LDS; W is streamed once with
-// non-temporal loads.  A wavefront forms two rows, sixteen 512-byte loads in
-// flight.
-constexpr int kGemvRows = 2;
+// multiple of 64.  A wavefront forms kGemvRows rows; W is streamed once with
+// non-temporal loads, the vector (one block, L2-resident) is read through the
+// caches and shared by the rows.
+constexpr int kGemvRows = 4;
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_gemv(const double *W, int64_t ld, int64_t rows,
                                                    const double *v, double *out,
                                                    const double *base) {
-  extern __shared__ double vs[];
-  for (int64_t j = threadIdx.x; j < ld; j += kThreads) vs[j] = v[j];
-  __syncthreads();
+  constexpr int RW = kGemvRows;
   const int lane = threadIdx.x & 63;
-  const int64_t r0 = ((int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) * kGemvRows;
+  const int64_t r0 = ((int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) * RW;
   if (r0 >= rows) return;
-  const bool two = r0 + 1 < rows;
-  const double *w0 = W + r0 * ld;
-  const double *w1 = two ? w0 + ld : w0;  // a lone last row reads its own row twice
-  double a[8], b[8];
+  const double *wr[RW];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) a[u] = b[u] = 0.0;
+  for (int q = 0; q < RW; ++q) wr[q] = W + (r0 + q < rows ? r0 + q : rows - 1) * ld;
+  double acc[RW][4];
+#pragma unroll
+  for (int q = 0; q < RW; ++q)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[q][u] = 0.0;
   int64_t j = lane;
-  for (; j + 7 * 64 < ld; j += 8 * 64) {
-    double x0[8], x1[8];
+  for (; j + 3 * 64 < ld; j += 4 * 64) {
+    double vv[4], x[RW][4];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      x0[u] = __builtin_nontemporal_load(w0 + j + 64 * u);
-      x1[u] = __builtin_nontemporal_load(w1 + j + 64 * u);
-    }
+    for (int u = 0; u < 4; ++u) vv[u] = v[j + 64 * u];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const double vv = vs[j + 64 * u];
-      a[u] = fma(x0[u], vv, a[u]);
-      b[u] = fma(x1[u], vv, b[u]);
-    }
+    for (int q = 0; q < RW; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[q][u] = __builtin_nontemporal_load(wr[q] + j + 64 * u);
+#pragma unroll
+    for (int q = 0; q < RW; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[q][u] = fma(x[q][u], vv[u], acc[q][u]);
   }
   for (; j < ld; j += 64) {
-    a[0] = fma(__builtin_nontemporal_load(w0 + j), vs[j], a[0]);
-    b[0] = fma(__builtin_nontemporal_load(w1 + j), vs[j], b[0]);
-  }
-  double s0 = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-  double s1 = ((b[0] + b[1]) + (b[2] + b[3])) + ((b[4] + b[5]) + (b[6] + b[7]));
+    const double vv = v[j];
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    s0 += __shfl_xor(s0, off, 64);
-    s1 += __shfl_xor(s1, off, 64);
+    for (int q = 0; q < RW; ++q) acc[q][0] = fma(__builtin_nontemporal_load(wr[q] + j), vv, acc[q][0]);
   }
-  if (lane == 0) {
-    out[r0] = MODE == 0 ? s0 : base[r0] - s0;
-    if (two) out[r0 + 1] = MODE == 0 ? s1 : base[r0 + 1] - s1;
+#pragma unroll
+  for (int q = 0; q < RW; ++q) {
+    double sq = (acc[q][0] + acc[q][1]) + (acc[q][2] + acc[q][3]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off, 64);
+    if (lane == 0 && r0 + q < rows) out[r0 + q] = MODE == 0 ? sq : base[r0 + q] - sq;
   }
 }
 
@@ -369,7 +365,6 @@ void deform_factor(const DeformDev &D, hipStream_t st) {
 void deform_solve(const DeformDev &D, const double *T, hipStream_t st, hipEvent_t *ev) {
   k_thermal_load<<<blocks_for(D.n), kThreads, 0, st>>>(D, T);
   const unsigned cb = (unsigned)((D.bp * kSub + kThreads - 1) / kThreads);
-  const size_t vlds = (size_t)D.bp * sizeof(double);
   int g = 0;
   auto gemv = [&](int mode, int64_t k, double *out, const double *base) {
     const double *W = D.W + k * D.bp * D.bp;
@@ -378,10 +373,10 @@ void deform_solve(const DeformDev &D, const double *T, hipStream_t st, hipEvent_
     const unsigned grid = (unsigned)((rows + per - 1) / per);
     auto kern = mode == 0 ? k_gemv<0> : k_gemv<1>;
     if (ev) {
-      hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), vlds, st, ev[2 * g], ev[2 * g + 1],
+      hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, ev[2 * g], ev[2 * g + 1],
                             0, W, D.bp, rows, (const double *)D.c, out, base);
     } else {
-      kern<<<grid, kThreads, vlds, st>>>(W, D.bp, rows, D.c, out, base);
+      kern<<<grid, kThreads, 0, st>>>(W, D.bp, rows, D.c, out, base);
     }
     ++g;
   };
