@@ -2041,7 +2041,7 @@ mrsdc_status mrsdc_deform_setup(mrsdc_ctx *c, int body, int64_t n, int64_t nnz,
   D.W = (double *)q;
   if ((st = df_alloc_bytes(c, &q, blk))) { df_release(c); return st; }
   D.T1 = (double *)q;
-  if ((st = df_alloc_bytes(c, &q, sizeof(double) * kGjTile * kGjTile))) { df_release(c); return st; }
+  if ((st = df_alloc_bytes(c, &q, sizeof(double) * 2 * kGjTile * kGjTile))) { df_release(c); return st; }
   D.piv = (double *)q;
   if ((st = df_alloc_bytes(c, &q, sizeof(int)))) { df_release(c); return st; }
   D.flag = (int *)q;

@@ -34,7 +34,7 @@ struct DeformDev {
   const double *uval = nullptr;
   double *W = nullptr;    // [nblk][bp][bp]: S_k^{-1}
   double *T1 = nullptr;   // [bp][bp]: A_{k,k-1} W_{k-1}
-  double *piv = nullptr;  // [64][64]: inverse of the current pivot tile
+  double *piv = nullptr;  // [2][64][64]: inverses of the current and next pivot tiles
   int *flag = nullptr;    // count of non-positive pivots
   double *f = nullptr;    // [n] thermal load
   double *w = nullptr;    // [n] forward results W_k c_k

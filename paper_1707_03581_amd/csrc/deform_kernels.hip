@@ -78,17 +78,12 @@ __global__ __launch_bounds__(kThreads) void k_schur_s(DeformDev D, int64_t k) {
   }
 }
 
-// Invert the 64 x 64 pivot tile (p, p) of S in LDS by Gauss-Jordan steps;
-// the result goes to piv.  A pivot that is not positive is counted.
-__global__ __launch_bounds__(kThreads) void k_gj_pivot(const double *S, int64_t ld, int p,
-                                                       double *piv, int *flag) {
-  __shared__ double A[kT][kT + 1];
+// Gauss-Jordan inversion of a 64 x 64 tile held in LDS, in place; returns the
+// number of pivots that were not positive.  A wavefront owns 16 rows
+// i = w + 4q, its lanes the 64 columns j: LDS accesses along a row are
+// conflict-free, column values are broadcast.
+__device__ inline int gj_invert_tile(double (&A)[kT][kT + 1]) {
   const int t = threadIdx.x;
-  const double *P = S + (int64_t)p * kT * ld + (int64_t)p * kT;
-  for (int e = t; e < kT * kT; e += kThreads) A[e / kT][e % kT] = P[(int64_t)(e / kT) * ld + e % kT];
-  __syncthreads();
-  // a wavefront owns 16 rows i = w + 4q, its lanes the 64 columns j: LDS
-  // accesses along a row are conflict-free, column values are broadcast
   const int j = t & 63, w = t >> 6;
   int bad = 0;
   for (int r = 0; r < kT; ++r) {
@@ -110,6 +105,18 @@ __global__ __launch_bounds__(kThreads) void k_gj_pivot(const double *S, int64_t 
     }
     __syncthreads();
   }
+  return bad;
+}
+
+// Invert the first pivot tile (p, p) of S into piv.
+__global__ __launch_bounds__(kThreads) void k_gj_pivot(const double *S, int64_t ld, int p,
+                                                       double *piv, int *flag) {
+  __shared__ double A[kT][kT + 1];
+  const int t = threadIdx.x;
+  const double *P = S + (int64_t)p * kT * ld + (int64_t)p * kT;
+  for (int e = t; e < kT * kT; e += kThreads) A[e / kT][e % kT] = P[(int64_t)(e / kT) * ld + e % kT];
+  __syncthreads();
+  const int bad = gj_invert_tile(A);
   for (int e = t; e < kT * kT; e += kThreads) piv[e] = A[e / kT][e % kT];
   if (t == 0 && bad) atomicAdd(flag, bad);
 }
@@ -141,12 +148,17 @@ __global__ __launch_bounds__(kThreads) void k_gj_row(double *S, int64_t ld, int 
 }
 
 // Trailing update: S(I, J) -= S(I, p) S(p, J) for every tile I != p, J != p.
-__global__ __launch_bounds__(kThreads) void k_gj_update(double *S, int64_t ld, int p, int nt) {
+// The workgroup of tile (p+1, p+1), the next pivot tile, goes first and then
+// inverts it into piv_next, hidden behind the other tiles' updates.
+__global__ __launch_bounds__(kThreads) void k_gj_update(double *S, int64_t ld, int p, int nt,
+                                                        double *piv_next, int *flag) {
   __shared__ double L[kT][kT + 1];  // L[k][i] = S(I, p)[i][k]
   __shared__ double R[kT][kT + 1];  // R[k][j] = S(p, J)[k][j]
   const int t = threadIdx.x;
   const int m = nt - 1;
-  const int bi = blockIdx.x / m, bj = blockIdx.x - bi * m;
+  const int rot = p + 1 < nt ? p * m + p : 0;  // position of tile (p+1, p+1)
+  const int lin = (int)((blockIdx.x + (unsigned)rot) % (unsigned)(m * m));
+  const int bi = lin / m, bj = lin - bi * m;
   const int it = bi < p ? bi : bi + 1, jt = bj < p ? bj : bj + 1;
   const double *SI = S + (int64_t)it * kT * ld + (int64_t)p * kT;
   const double *SJ = S + (int64_t)p * kT * ld + (int64_t)jt * kT;
@@ -176,10 +188,22 @@ __global__ __launch_bounds__(kThreads) void k_gj_update(double *S, int64_t ld, i
       for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
   }
   double *O = S + (int64_t)it * kT * ld + (int64_t)jt * kT;
+  const bool next = it == p + 1 && jt == p + 1;  // uniform over the workgroup
+  if (next) __syncthreads();                     // L is reused below
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) O[(int64_t)(i0 + a) * ld + j0 + 16 * b] -= acc[a][b];
+    for (int b = 0; b < 4; ++b) {
+      const double o = O[(int64_t)(i0 + a) * ld + j0 + 16 * b] - acc[a][b];
+      O[(int64_t)(i0 + a) * ld + j0 + 16 * b] = o;
+      if (next) L[i0 + a][j0 + 16 * b] = o;
+    }
+  if (next) {
+    __syncthreads();
+    const int bad = gj_invert_tile(L);
+    for (int e = t; e < kT * kT; e += kThreads) piv_next[e] = L[e / kT][e % kT];
+    if (t == 0 && bad) atomicAdd(flag, bad);
+  }
 }
 
 // Column panel: S(I, p) = -S(I, p) piv for I != p; S(p, p) = piv.
@@ -351,13 +375,16 @@ void deform_factor(const DeformDev &D, hipStream_t st) {
     if (k > 0) k_schur_t<<<(unsigned)D.rows(k), kThreads, 0, st>>>(D, k);
     k_schur_s<<<(unsigned)D.bp, kThreads, (size_t)D.bp * sizeof(double), st>>>(D, k);
     double *S = D.W + k * D.bp * D.bp;
+    // pivot inverses alternate between two buffers: pass p reads piv[p % 2]
+    // while its trailing update inverts the next pivot tile into the other
+    k_gj_pivot<<<1, kThreads, 0, st>>>(S, D.bp, 0, D.piv, D.flag);
     for (int p = 0; p < nt; ++p) {
-      k_gj_pivot<<<1, kThreads, 0, st>>>(S, D.bp, p, D.piv, D.flag);
+      double *pc = D.piv + (p & 1) * kT * kT, *pn = D.piv + ((p + 1) & 1) * kT * kT;
       if (nt > 1) {
-        k_gj_row<<<nt - 1, kThreads, 0, st>>>(S, D.bp, p, D.piv);
-        k_gj_update<<<(nt - 1) * (nt - 1), kThreads, 0, st>>>(S, D.bp, p, nt);
+        k_gj_row<<<nt - 1, kThreads, 0, st>>>(S, D.bp, p, pc);
+        k_gj_update<<<(nt - 1) * (nt - 1), kThreads, 0, st>>>(S, D.bp, p, nt, pn, D.flag);
       }
-      k_gj_col<<<nt, kThreads, 0, st>>>(S, D.bp, p, D.piv);
+      k_gj_col<<<nt, kThreads, 0, st>>>(S, D.bp, p, pc);
     }
   }
 }
