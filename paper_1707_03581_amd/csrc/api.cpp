@@ -798,6 +798,7 @@ mrsdc_status prepare(mrsdc_ctx *c) {
     d.mass32 = pm;
     if ((st = dalloc(c, &d.x32, N)) || (st = dalloc(c, &d.r32, N)) ||
         (st = dalloc(c, &d.p32, N)) || (st = dalloc(c, &d.q32, N)) ||
+        (st = dalloc(c, &d.u32, N)) || (st = dalloc(c, &d.s32, N)) ||
         (st = dalloc(c, &d.b64, N)) || (st = dalloc(c, &d.r64, N)))
       return st;
   }
@@ -821,7 +822,8 @@ mrsdc_status prepare(mrsdc_ctx *c) {
     if (m >= 1 && c->w.dtau[m] != 0.0 && (st = dalloc(c, &d.I[m], NS))) return st;
   }
   if (!(batch && fp32) &&
-      ((st = dalloc(c, &d.r, NS)) || (st = dalloc(c, &d.p, NS)) || (st = dalloc(c, &d.q, NS))))
+      ((st = dalloc(c, &d.r, NS)) || (st = dalloc(c, &d.p, NS)) || (st = dalloc(c, &d.q, NS)) ||
+       (!batch && ((st = dalloc(c, &d.u, NS)) || (st = dalloc(c, &d.s, NS))))))
     return st;
   if (batch) {  // inactive scenarios keep finite zeros
     for (int m = 0; m <= cfg.M; ++m) {
@@ -835,7 +837,7 @@ mrsdc_status prepare(mrsdc_ctx *c) {
       HIPCHK(hipMemset(d.q, 0, NS * sizeof(double)));
     }
   }
-  if ((st = dalloc(c, &d.partial, 3 * (size_t)d.grid))) return st;
+  if ((st = dalloc(c, &d.partial, 6 * (size_t)d.grid))) return st;
   if ((st = dalloc(c, &d.sc, 1)) || (st = dalloc(c, &d.ctr, 1)) || (st = dalloc(c, &d.tn, 1)))
     return st;
   HIPCHK(hipMemset(d.sc, 0, sizeof(SolveScalars)));
@@ -1043,6 +1045,7 @@ void enqueue_cg(mrsdc_ctx *c, int slot, int m, bool fp32) {
     if (fp32) launch_pcg32_iter(d, m, slot, it, it == B - 1, tail, c->stream, e0, e1);
     else launch_pcg_iter(d, m, slot, it, it == B - 1, tail, c->stream, e0, e1);
   }
+  launch_pcg_final(d, m, slot, B, fp32, c->stream);
 }
 
 // One implicit node solve of interval m (x = T[m] in place).

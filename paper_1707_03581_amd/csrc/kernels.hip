@@ -291,6 +291,7 @@ struct CgArgs {
   const R *mass, *dinv;
   const double *g;
   R *x, *r, *p, *q;
+  R *u, *s;  // single-reduction form: u = M^{-1} r, s = A p (q holds w = A u)
   double *partial;  // [3*grid]
   SolveScalars *sc;
   StepCounters *ctr;
@@ -467,6 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_init_pred(CgArgs<double> a) {
     a.x[row] = x0;
     a.r[row] = r;
     a.p[row] = z;
+    if (a.u) a.u[row] = z;
     v[0] += r * z;
     v[1] += r * r;
     v[2] += b * b;
@@ -493,6 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_init_corr(CgArgs<double> a) {
     const double z = a.dinv[i] * r;
     a.r[i] = r;
     a.p[i] = z;
+    if (a.u) a.u[i] = z;
     v[0] += r * z;
     v[1] += r * r;
     v[2] += b * b;
@@ -542,11 +545,35 @@ __global__ void k_solve_reduce(const double *part, int grid, SolveScalars *sc, S
 // of the previous step (usually early exits), TAIL = 2 the stand-alone timing
 // launches (which ignore the convergence flag); both kept apart in profiles.
 // FMT: 0 value array, 1 value dictionary, 2 packed entries, 3 row patterns
-template <bool D16, int TAIL, typename R, bool CPL = false, int FMT = 0>
+// CG2: the operator step of the single-reduction iteration (w = A u, partial
+// u.w into slot 5), which first ends the solve if ||r_it||^2, summed from
+// the previous update's partials, is below the tolerance.
+template <typename R>
+__device__ inline void cg_converged(const CgArgs<R> &a, int iters) {
+  SolveScalars *sc = a.sc;
+  StepCounters *ctr = a.ctr;
+  sc->done = 1;
+  sc->iters = iters;
+  ctr->pcg_iters += iters;
+  if (!a.inner) ctr->slot_iters[a.slot] = iters;
+  else if (ctr->slot_iters[a.slot] >= 0 && iters > ctr->slot_iters[a.slot])
+    ctr->slot_iters[a.slot] = iters;
+  if (iters > ctr->max_iters) ctr->max_iters = iters;
+}
+
+template <bool D16, int TAIL, typename R, bool CPL = false, int FMT = 0, bool CG2 = false>
 __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
   constexpr bool DICT = FMT != 0;
   if (TAIL != 2 && solve_done(a.sc, a.ctr)) return;
   __shared__ double sh[17];
+  if (CG2 && TAIL != 2 && it > 0) {
+    const double rr = sum_partials(a.partial + ((it & 1) ? 4 : 1) * a.grid, a.grid, sh);
+    if (rr <= a.sc->tol2) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) cg_converged(a, it);
+      return;
+    }
+  }
+  const R *__restrict__ xin = CG2 ? a.u : a.p;
   __shared__ R sd[DICT ? kDictMax : 1];
   __shared__ int sct[FMT == 3 ? kMaxCls * kMaxClsWidth : 1];
   __shared__ int slen[FMT == 3 ? kMaxCls : 1];
@@ -566,11 +593,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
   for (int64_t s = wave; s < a.op.nslices; s += nw) {
     const int64_t row = s * kSlice + lane;
     if (row >= a.N) continue;
-    const R Lp = FMT == 3   ? (R)sell_row_cls<R>(a.op, row, a.p, sd, sct, slen)
-                 : FMT == 2 ? (R)sell_row_pk<R>(a.op, s, lane, row, a.p, sd)
-                 : FMT == 1 ? (R)sell_row_dict<D16, R>(a.op, s, lane, row, a.p, sd)
-                            : (R)sell_row_t<D16, R>(a.op, s, lane, row, a.p);
-    const R pi = a.p[row];
+    const R Lp = FMT == 3   ? (R)sell_row_cls<R>(a.op, row, xin, sd, sct, slen)
+                 : FMT == 2 ? (R)sell_row_pk<R>(a.op, s, lane, row, xin, sd)
+                 : FMT == 1 ? (R)sell_row_dict<D16, R>(a.op, s, lane, row, xin, sd)
+                            : (R)sell_row_t<D16, R>(a.op, s, lane, row, xin);
+    const R pi = xin[row];
     R qi = a.mass[row] * pi + (R)a.dtau * Lp;
     if (CPL) {  // single-rate method: the coupling of the node operator
       const int ip = a.ifpos[row];
@@ -579,7 +606,94 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
     a.q[row] = qi;
     v[0] += (double)pi * (double)qi;
   }
-  publish<1>(v, a.partial, a.grid, sh);
+  publish<1>(v, a.partial + (CG2 ? 5 * a.grid : 0), a.grid, sh);
+}
+
+// Single-reduction (Chronopoulos-Gear) update of iteration it: with
+// gamma = r.u (previous update's partials) and delta = u.w (operator step's):
+// beta = gamma / gamma_prev, alpha = gamma / (delta - beta gamma / alpha_prev)
+// (it = 0: beta = 0, alpha = gamma / delta); p = u + beta p, s = w + beta s,
+// x += alpha p, r -= alpha s, u = M^{-1} r; partials of the next r.u, r.r.
+// Mathematically the Jacobi-PCG iteration, with one reduction point instead
+// of two, so one launch fewer per iteration.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_cg_upd(CgArgs<R> a, int it) {
+  if (solve_done(a.sc, a.ctr)) return;
+  __shared__ double sh[34];
+  const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool first = i0 < a.N;
+  R u0 = 0, w0 = 0, p0 = 0, s0 = 0, x0 = 0, r0 = 0, d0 = 0;
+  if (first) {  // requested before the reductions
+    u0 = a.u[i0];
+    w0 = a.q[i0];
+    if (it > 0) {
+      p0 = a.p[i0];
+      s0 = a.s[i0];
+    }
+    x0 = a.x[i0];
+    r0 = a.r[i0];
+    d0 = a.dinv[i0];
+  }
+  const double *pg = a.partial + ((it & 1) ? 3 : 0) * a.grid, *pd = a.partial + 5 * a.grid;
+  double gam = 0.0, del = 0.0;
+  for (int j = threadIdx.x; j < a.grid; j += blockDim.x) {
+    gam += pg[j];
+    del += pd[j];
+  }
+  block_sum2(gam, del, sh);
+  SolveScalars *sc = a.sc;
+  double beta = 0.0, alpha;
+  if (it == 0) {
+    alpha = gam / del;
+  } else {
+    beta = gam / sc->gam[(it - 1) & 1];
+    alpha = gam / (del - beta * gam / sc->alp[(it - 1) & 1]);
+  }
+  const R al = (R)alpha, be = (R)beta;
+  double v0 = 0.0, v1 = 0.0;
+  auto upd = [&](int64_t i, R u, R w, R p, R s, R x, R r, R d) {
+    const R pn = it == 0 ? u : u + be * p;
+    const R sn = it == 0 ? w : w + be * s;
+    a.p[i] = pn;
+    a.s[i] = sn;
+    a.x[i] = x + al * pn;
+    const R rn = r - al * sn;
+    a.r[i] = rn;
+    const R un = d * rn;
+    a.u[i] = un;
+    v0 += (double)rn * (double)un;
+    v1 += (double)rn * (double)rn;
+  };
+  if (first) upd(i0, u0, w0, p0, s0, x0, r0, d0);
+  for (int64_t i = i0 + (int64_t)gridDim.x * kBlock; i < a.N; i += (int64_t)gridDim.x * kBlock)
+    upd(i, a.u[i], a.q[i], it > 0 ? a.p[i] : (R)0, it > 0 ? a.s[i] : (R)0, a.x[i], a.r[i],
+        a.dinv[i]);
+  block_sum2(v0, v1, sh);
+  double *po = a.partial + (((it + 1) & 1) ? 3 : 0) * a.grid;  // gamma, rho of it + 1
+  if (threadIdx.x == 0) {
+    po[blockIdx.x] = v0;
+    po[a.grid + blockIdx.x] = v1;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->gam[it & 1] = gam;
+    sc->alp[it & 1] = alpha;
+  }
+}
+
+// After the launch budget: converged at iteration it, or the solve failed.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_cg_check(CgArgs<R> a, int it) {
+  if (solve_done(a.sc, a.ctr)) return;
+  __shared__ double sh[17];
+  const double rr = sum_partials(a.partial + ((it & 1) ? 4 : 1) * a.grid, a.grid, sh);
+  if (threadIdx.x != 0) return;
+  if (rr <= a.sc->tol2) {
+    cg_converged(a, it);
+  } else {  // budget exhausted: the FP64 solve failed; an inner solve only signals it
+    a.ctr->slot_iters[a.slot] = -1;
+    a.ctr->pcg_iters += it;
+    if (!a.inner) a.ctr->fail += 1;
+  }
 }
 
 // (b) alpha = r.z / p.q; x += alpha p; r -= alpha q; partial r.z, r.r
@@ -724,6 +838,7 @@ __global__ __launch_bounds__(kBlock) void k_inner_init(CgArgs<float> a) {
     a.r[i] = r;
     a.x[i] = 0.0f;
     a.p[i] = z;
+    if (a.u) a.u[i] = z;
     v[0] += (double)r * (double)z;
     v[1] += (double)r * (double)r;
   }
@@ -785,6 +900,8 @@ static CgArgs<double> cg64(const DevState &d, int m, int slot) {
   a.r = d.r;
   a.p = d.p;
   a.q = d.q;
+  a.u = d.u;
+  a.s = d.s;
   a.partial = d.partial;
   a.sc = d.sc;
   a.ctr = d.ctr;
@@ -817,6 +934,8 @@ static CgArgs<float> cg32(const DevState &d, int m, int slot) {
   a.r = d.r32;
   a.p = d.p32;
   a.q = d.q32;
+  a.u = d.u32;
+  a.s = d.s32;
   a.partial = d.partial;
   a.sc = d.sc;
   a.ctr = d.ctr;
@@ -881,9 +1000,39 @@ static void pcg_iter(const DevState &d, const CgArgs<R> &a, int it, bool last, b
   k_pcg_c<R><<<d.grid, kBlock, 0, st>>>(a, it, last ? 1 : 0);
 }
 
+// One iteration of the single-reduction form: operator step, then update.
+template <typename R>
+static void pcg2_iter(const DevState &d, const CgArgs<R> &a, int it, bool tail, hipStream_t st,
+                      hipEvent_t ev0, hipEvent_t ev1) {
+  void (*kern)(CgArgs<R>, int);
+  if (a.ifc_lin)
+    kern = d.op.d16 ? (tail ? k_pcg_a<true, 1, R, true, 0, true> : k_pcg_a<true, 0, R, true, 0, true>)
+                    : (tail ? k_pcg_a<false, 1, R, true, 0, true> : k_pcg_a<false, 0, R, true, 0, true>);
+  else if (d.op.rcls)
+    kern = tail ? k_pcg_a<true, 1, R, false, 3, true> : k_pcg_a<true, 0, R, false, 3, true>;
+  else if (d.op.pk16)
+    kern = tail ? k_pcg_a<true, 1, R, false, 2, true> : k_pcg_a<true, 0, R, false, 2, true>;
+  else if (d.op.vid)
+    kern = d.op.d16 ? (tail ? k_pcg_a<true, 1, R, false, 1, true> : k_pcg_a<true, 0, R, false, 1, true>)
+                    : (tail ? k_pcg_a<false, 1, R, false, 1, true> : k_pcg_a<false, 0, R, false, 1, true>);
+  else
+    kern = d.op.d16 ? (tail ? k_pcg_a<true, 1, R, false, 0, true> : k_pcg_a<true, 0, R, false, 0, true>)
+                    : (tail ? k_pcg_a<false, 1, R, false, 0, true> : k_pcg_a<false, 0, R, false, 0, true>);
+  if (a.ifc_lin) launch_iface_lin(d, a.m, (const double *)a.u, st);  // coupling of A u
+  if (ev0) hipExtLaunchKernelGGL(kern, dim3(d.grid), dim3(kBlock), 0, st, ev0, ev1, 0, a, it);
+  else kern<<<d.grid, kBlock, 0, st>>>(a, it);
+  k_cg_upd<R><<<d.grid, kBlock, 0, st>>>(a, it);
+}
+
 void launch_pcg_iter(const DevState &d, int m, int slot, int it, bool last, bool tail,
                      hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  pcg_iter(d, cg64(d, m, slot), it, last, tail, st, ev0, ev1);
+  (void)last;  // the budget's end is judged by launch_pcg_final
+  pcg2_iter(d, cg64(d, m, slot), it, tail, st, ev0, ev1);
+}
+
+void launch_pcg_final(const DevState &d, int m, int slot, int it, bool fp32, hipStream_t st) {
+  if (fp32) k_cg_check<float><<<1, kBlock, 0, st>>>(cg32(d, m, slot), it);
+  else k_cg_check<double><<<1, kBlock, 0, st>>>(cg64(d, m, slot), it);
 }
 
 // Stationary field (K + h R) T = g: the CG kernels with a zero mass, dtau = 1
@@ -926,7 +1075,7 @@ void launch_operator_timing(const DevState &d, int m, bool fp32, int reps, hipSt
   if (fp32) {
     CgArgs<float> a = cg32(d, m, 0);
     for (int i = 0; i < reps; ++i) {
-      if (d.op.rcls) k_pcg_a<true, 2, float, false, 3><<<d.grid, kBlock, 0, st>>>(a, 0);
+      if (d.op.rcls) k_pcg_a<true, 2, float, false, 3, true><<<d.grid, kBlock, 0, st>>>(a, 0);
       else if (d.op.pk16) k_pcg_a<true, 2, float, false, 2><<<d.grid, kBlock, 0, st>>>(a, 0);
       else if (d.op.vid && d.op.d16) k_pcg_a<true, 2, float, false, 1><<<d.grid, kBlock, 0, st>>>(a, 0);
       else if (d.op.vid) k_pcg_a<false, 2, float, false, 1><<<d.grid, kBlock, 0, st>>>(a, 0);
@@ -937,7 +1086,7 @@ void launch_operator_timing(const DevState &d, int m, bool fp32, int reps, hipSt
     CgArgs<double> a = cg64(d, m, 0);
     a.x = nullptr;
     for (int i = 0; i < reps; ++i) {
-      if (d.op.rcls) k_pcg_a<true, 2, double, false, 3><<<d.grid, kBlock, 0, st>>>(a, 0);
+      if (d.op.rcls) k_pcg_a<true, 2, double, false, 3, true><<<d.grid, kBlock, 0, st>>>(a, 0);
       else if (d.op.pk16) k_pcg_a<true, 2, double, false, 2><<<d.grid, kBlock, 0, st>>>(a, 0);
       else if (d.op.vid && d.op.d16) k_pcg_a<true, 2, double, false, 1><<<d.grid, kBlock, 0, st>>>(a, 0);
       else if (d.op.vid) k_pcg_a<false, 2, double, false, 1><<<d.grid, kBlock, 0, st>>>(a, 0);
@@ -970,7 +1119,8 @@ void launch_inner_init(const DevState &d, int m, int slot, double inner_rtol, hi
 
 void launch_pcg32_iter(const DevState &d, int m, int slot, int it, bool last, bool tail,
                        hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  pcg_iter(d, cg32(d, m, slot), it, last, tail, st, ev0, ev1);
+  (void)last;
+  pcg2_iter(d, cg32(d, m, slot), it, tail, st, ev0, ev1);
 }
 
 void launch_refine_update(const DevState &d, int m, int slot, int round, bool last_round,

@@ -68,6 +68,8 @@ constexpr int kMaxClsWidth = 32;
 // Per-solve device scalars of the CG iteration and of the refinement loop.
 struct SolveScalars {
   double rz[2];      // r.z of the current/next iteration, by parity
+  double gam[2];     // single-reduction form: r.u and alpha of iteration it,
+  double alp[2];     // by parity (it - 1 is read while it is written)
   double tol2;       // CG stopping threshold on ||r||^2
   double bb;         // ||b||^2
   double alpha, beta;
@@ -157,9 +159,11 @@ struct DevState {
   double *F[kMaxM + 1] = {};          // f^I(T_j) + g
   double *I[kMaxM + 1] = {};          // I_{m-1}^m
   double *r = nullptr, *p = nullptr, *q = nullptr;  // CG work
+  double *u = nullptr, *s = nullptr;                // single-reduction form
   float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *x32 = nullptr;
+  float *u32 = nullptr, *s32 = nullptr;
   double *b64 = nullptr, *r64 = nullptr;  // refinement right-hand side and residual
-  double *partial = nullptr;          // [3 * grid]
+  double *partial = nullptr;          // [6 * grid]
   SolveScalars *sc = nullptr;
   StepCounters *ctr = nullptr;
   double *tn = nullptr;               // device scalar: t_n of the current step
@@ -178,6 +182,7 @@ void launch_quad_resid(const DevState &d, int k, hipStream_t st);
 void launch_init_pred(const DevState &d, int m, int slot, double rtol, hipStream_t st);
 void launch_init_corr(const DevState &d, int m, int slot, double rtol, hipStream_t st);
 void launch_iface_F(const DevState &d, int j, hipStream_t st);
+void launch_pcg_final(const DevState &d, int m, int slot, int it, bool fp32, hipStream_t st);
 void launch_iface_quad(const DevState &d, hipStream_t st);
 void launch_iface_lin(const DevState &d, int m, const double *x, hipStream_t st);
 void launch_stationary_init(const DevState &d, const double *zeros, const double *dinv, int slot,
