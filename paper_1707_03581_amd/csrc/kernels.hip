@@ -1267,6 +1267,81 @@ __device__ inline double tif(const SubArgs &A, const double *Tin, int j) {
   return FIRST ? A.Tprev[A.f.rows[j]] : Tin[j];
 }
 
+// Separable coupling sums of one interface point.  The 3 x 3 self stencil
+// and, when both band counts are at most kFastBand, the cross band are formed
+// with fixed trip counts: indices are clamped into the face grid and the
+// weights of the clamped terms are zero, so every gather is issued before the
+// first is waited for.  A point whose band is wider takes the general loop.
+// Every sum adds the same products in the same order as the plain loops
+// (a clamped term adds an exact zero).
+constexpr int kFastBand = 4;
+
+template <bool FIRST>
+__device__ inline double self_sum(const SubArgs &A, const double *Tin, const double *wu,
+                                  const double *wv, int nu, int nv, int base, int a, int b) {
+  double w0[3], w1[3];
+  int ra[3], cb[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int aa = a - 1 + q, bb = b - 1 + q;
+    const bool ia = aa >= 0 && aa < nu, ib = bb >= 0 && bb < nv;
+    ra[q] = ia ? aa : a;
+    cb[q] = ib ? bb : b;
+    w0[q] = ia ? wu[3 * a + q] : 0.0;
+    w1[q] = ib ? wv[3 * b + q] : 0.0;
+  }
+  double t[3][3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) t[q][r] = tif<FIRST>(A, Tin, base + ra[q] * nv + cb[r]);
+  double self = 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) acc += w1[r] * t[q][r];
+    self += w0[q] * acc;
+  }
+  return self;
+}
+
+// sum_{i < nu} cu[i] sum_{j < nv} cv[j] T(base + (u0 + i) * ld + v0 + j)
+template <bool FIRST>
+__device__ inline double cross_sum(const SubArgs &A, const double *Tin, const double *cu,
+                                   const double *cv, int u0, int nu, int v0, int nv, int ld,
+                                   int base) {
+  double cross = 0.0;
+  if (nu <= 0 || nv <= 0) return cross;  // no overlap: the band start may lie off the grid
+  if (nu <= kFastBand && nv <= kFastBand) {
+    double wu[kFastBand], wv[kFastBand], t[kFastBand][kFastBand];
+#pragma unroll
+    for (int q = 0; q < kFastBand; ++q) {
+      wu[q] = q < nu ? cu[q] : 0.0;
+      wv[q] = q < nv ? cv[q] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kFastBand; ++q)
+#pragma unroll
+      for (int r = 0; r < kFastBand; ++r)
+        t[q][r] = tif<FIRST>(A, Tin, base + (u0 + (q < nu ? q : 0)) * ld + v0 + (r < nv ? r : 0));
+#pragma unroll
+    for (int q = 0; q < kFastBand; ++q) {
+      double acc = 0.0;
+#pragma unroll
+      for (int r = 0; r < kFastBand; ++r) acc += wv[r] * t[q][r];
+      cross += wu[q] * acc;
+    }
+    return cross;
+  }
+  for (int q = 0; q < nu; ++q) {
+    double acc = 0.0;
+    for (int r = 0; r < nv; ++r) acc += cv[r] * tif<FIRST>(A, Tin, base + (u0 + q) * ld + v0 + r);
+    cross += cu[q] * acc;
+  }
+  return cross;
+}
+
 // f^E at interface point i (fixed-face points first, then moving-face points)
 // as the part linear in T (exchange) and the source (friction, patch flux)
 template <bool FIRST>
@@ -1277,64 +1352,26 @@ __device__ void iface_fE_parts(const SubArgs &A, const double *D, const int *I,
   const double qf = D[0];
   if (i < f.nfix) {
     const int a = i / f.nvf, b = i - a * f.nvf;
-    double self = 0.0;
-    for (int ia = 0; ia < 3; ++ia) {
-      const int aa = a - 1 + ia;
-      const double mu = f.Mu[3 * a + ia];
-      if (aa < 0 || aa >= f.nuf || mu == 0.0) continue;
-      double acc = 0.0;
-      for (int ib = 0; ib < 3; ++ib) {
-        const int bb = b - 1 + ib;
-        if (bb < 0 || bb >= f.nvf) continue;
-        acc += D[L.Mv() + 3 * b + ib] * tif<FIRST>(A, Tin, aa * f.nvf + bb);
-      }
-      self += mu * acc;
-    }
+    const double self = self_sum<FIRST>(A, Tin, f.Mu, D + L.Mv(), f.nuf, f.nvf, 0, a, b);
     const double hub = f.Hu[a] * D[L.Hv() + b];
     if (f.kind == 2) {
       *lin = -(f.alpha * self);
       *src = (f.q0 + f.alpha * f.Tfix) * hub;
       return;
     }
-    double cross = 0.0;
-    const int c0 = f.clo[a], nc = f.ccnt[a];
-    const int d0 = I[L.dlo() + b], nd = I[L.dcnt() + b];
-    for (int ic = 0; ic < nc; ++ic) {
-      const int c = c0 + ic;
-      double acc = 0.0;
-      for (int id = 0; id < nd; ++id)
-        acc += D[L.Cv() + kBand * b + id] * tif<FIRST>(A, Tin, f.nfix + c * f.nvm + d0 + id);
-      cross += f.Cu[kBand * a + ic] * acc;
-    }
+    const double cross =
+        cross_sum<FIRST>(A, Tin, f.Cu + kBand * a, D + L.Cv() + kBand * b, f.clo[a], f.ccnt[a],
+                         I[L.dlo() + b], I[L.dcnt() + b], f.nvm, f.nfix);
     *lin = f.alpha * (cross - self);
     *src = f.split * qf * hub;
     return;
   }
   const int k = i - f.nfix;
   const int c = k / f.nvm, d = k - c * f.nvm;
-  double self = 0.0;
-  for (int ic = 0; ic < 3; ++ic) {
-    const int cc = c - 1 + ic;
-    const double nu = f.Nu[3 * c + ic];
-    if (cc < 0 || cc >= f.num || nu == 0.0) continue;
-    double acc = 0.0;
-    for (int id = 0; id < 3; ++id) {
-      const int dd = d - 1 + id;
-      if (dd < 0 || dd >= f.nvm) continue;
-      acc += D[L.Nv() + 3 * d + id] * tif<FIRST>(A, Tin, f.nfix + cc * f.nvm + dd);
-    }
-    self += nu * acc;
-  }
-  double cross = 0.0;
-  const int a0 = f.alo[c], na = f.acnt[c];
-  const int b0 = I[L.blo() + d], nb = I[L.bcnt() + d];
-  for (int ia = 0; ia < na; ++ia) {
-    const int a = a0 + ia;
-    double acc = 0.0;
-    for (int ib = 0; ib < nb; ++ib)
-      acc += D[L.CvT() + kBand * d + ib] * tif<FIRST>(A, Tin, a * f.nvf + b0 + ib);
-    cross += f.CuT[kBand * c + ia] * acc;
-  }
+  const double self = self_sum<FIRST>(A, Tin, f.Nu, D + L.Nv(), f.num, f.nvm, f.nfix, c, d);
+  const double cross =
+      cross_sum<FIRST>(A, Tin, f.CuT + kBand * c, D + L.CvT() + kBand * d, f.alo[c], f.acnt[c],
+                       I[L.blo() + d], I[L.bcnt() + d], f.nvf, 0);
   *lin = f.alpha * (cross - self);
   *src = (1.0 - f.split) * qf * f.Gu[c] * D[L.Gv() + d];
 }
