@@ -128,12 +128,14 @@ def main():
     torch.cuda.synchronize()
     lat = []
     iters = 0
+    redone = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
         s0 = time.perf_counter()
         st = ctx.advance(dt)
         lat.append(time.perf_counter() - s0)
         iters += st["pcg_iters"]
+        redone += st["redone_steps"]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kt = ctx.profile_read() if args.profile else None
@@ -163,6 +165,7 @@ def main():
         "p50_step_ms": float(np.percentile(lat_ms, 50)),
         "p99_step_ms": float(np.percentile(lat_ms, 99)),
         "cg_iters_per_step": iters / args.steps,
+        "redone_steps": redone,
     }
     # dominant kernel: the CG operator application, timed with HIP events over
     # back-to-back launches on the library's stream (its own kernel symbol,

@@ -85,6 +85,7 @@ struct mrsdc_ctx {
   int64_t off[3] = {0, 0, 0};
   StepCounters *ctr_host = nullptr;  // pinned
   int budget[kSlots];   // CG launch budget per solve slot (inner CG for FP32_REFINE)
+  int last_it[kSlots];  // FP64: the slot's iteration count one step earlier
   int expect[kSlots];   // iterations the slot took in the last step
   int rounds[kSlots];   // refinement round budget per slot
   int64_t matrix_bytes = 0;
@@ -981,6 +982,7 @@ mrsdc_status prepare(mrsdc_ctx *c) {
   for (int i = 0; i < kSlots; ++i) {
     c->budget[i] = b0;
     c->expect[i] = b0;
+    c->last_it[i] = 0;
     c->rounds[i] = std::min(cfg.refine_maxit, 3);
   }
   c->prepared = true;
@@ -1450,7 +1452,14 @@ mrsdc_status mrsdc_advance(mrsdc_ctx *c, double horizon, mrsdc_stats *stats) {
         for (int k = 0; k <= Kc; ++k) acc.residual[k] = h.resid[k];
         for (int i = 0; i < kSlots; ++i) {
           const int it = h.slot_iters[i];
-          if (it > 0) {
+          if (it > 0 && !fp32) {
+            // a slot's count repeats from step to step within one or two: one
+            // launch pair beyond the larger of its last two counts (a solve
+            // that still runs out repeats the step with a doubled budget)
+            c->budget[i] = std::min(c->cfg.pcg_maxit, std::max(it, c->last_it[i]) + 1);
+            c->last_it[i] = it;
+            c->expect[i] = it;
+          } else if (it > 0) {
             c->budget[i] = std::min(c->cfg.pcg_maxit, it + std::max(2, it / 5));
             c->expect[i] = it;
           } else if (it < 0 && fp32 && c->budget[i] < c->cfg.pcg_maxit) {

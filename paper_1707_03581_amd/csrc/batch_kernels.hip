@@ -928,6 +928,84 @@ __device__ inline double btif(const BatchArgs &a, const double *Tprev, const dou
   return FIRST ? Tprev[a.f.rows[j] * a.S + s] : Tin[(size_t)j * a.S + s];
 }
 
+// Coupling sums of one interface point for scenario s, with the fixed trip
+// counts of the single-simulation form: clamped indices with zero weights for
+// the 3 x 3 self stencil and for a cross band of at most kBFastBand by
+// kBFastBand (the general loop otherwise), so every gather is issued before
+// the first is waited for; the products are added in the plain loops' order.
+constexpr int kBFastBand = 4;
+
+template <bool FIRST>
+__device__ inline double bself(const BatchArgs &a, const double *Tprev, const double *Tin,
+                               const double *wu, const double *D, int kv, int nu, int nv,
+                               int base, int ua, int b, int s) {
+  const int S = a.S;
+  double w0[3], w1[3];
+  int ra[3], cb[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int aa = ua - 1 + q, bb = b - 1 + q;
+    const bool ia = aa >= 0 && aa < nu, ib = bb >= 0 && bb < nv;
+    ra[q] = ia ? aa : ua;
+    cb[q] = ib ? bb : b;
+    w0[q] = ia ? wu[3 * ua + q] : 0.0;
+    w1[q] = ib ? D[(size_t)(kv + 3 * b + q) * S + s] : 0.0;
+  }
+  double t[3][3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) t[q][r] = btif<FIRST>(a, Tprev, Tin, base + ra[q] * nv + cb[r], s);
+  double self = 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) acc += w1[r] * t[q][r];
+    self += w0[q] * acc;
+  }
+  return self;
+}
+
+// sum_{q < nu} cu[q] sum_{r < nv} D(kv + r) T(base + (u0 + q) * ld + v0 + r)
+template <bool FIRST>
+__device__ inline double bcross(const BatchArgs &a, const double *Tprev, const double *Tin,
+                                const double *cu, const double *D, int kv, int u0, int nu, int v0,
+                                int nv, int ld, int base, int s) {
+  const int S = a.S;
+  double cross = 0.0;
+  if (nu <= 0 || nv <= 0) return cross;  // no overlap: the band start may lie off the grid
+  if (nu <= kBFastBand && nv <= kBFastBand) {
+    double wu[kBFastBand], wv[kBFastBand], t[kBFastBand][kBFastBand];
+#pragma unroll
+    for (int q = 0; q < kBFastBand; ++q) {
+      wu[q] = q < nu ? cu[q] : 0.0;
+      wv[q] = q < nv ? D[(size_t)(kv + q) * S + s] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kBFastBand; ++q)
+#pragma unroll
+      for (int r = 0; r < kBFastBand; ++r)
+        t[q][r] = btif<FIRST>(a, Tprev, Tin,
+                              base + (u0 + (q < nu ? q : 0)) * ld + v0 + (r < nv ? r : 0), s);
+#pragma unroll
+    for (int q = 0; q < kBFastBand; ++q) {
+      double acc = 0.0;
+#pragma unroll
+      for (int r = 0; r < kBFastBand; ++r) acc += wv[r] * t[q][r];
+      cross += wu[q] * acc;
+    }
+    return cross;
+  }
+  for (int q = 0; q < nu; ++q) {
+    double acc = 0.0;
+    for (int r = 0; r < nv; ++r)
+      acc += D[(size_t)(kv + r) * S + s] * btif<FIRST>(a, Tprev, Tin, base + (u0 + q) * ld + v0 + r, s);
+    cross += cu[q] * acc;
+  }
+  return cross;
+}
+
 template <bool FIRST>
 __device__ double bfE(const BatchArgs &a, const double *D, const int *I, const double *Tprev,
                       const double *Tin, int i, int s) {
@@ -939,57 +1017,18 @@ __device__ double bfE(const BatchArgs &a, const double *D, const int *I, const d
 #define II(k) I[(size_t)(k) * S + s]
   if (i < f.nfix) {
     const int ua = i / f.nvf, b = i - ua * f.nvf;
-    double self = 0.0;
-    for (int ia = 0; ia < 3; ++ia) {
-      const int aa = ua - 1 + ia;
-      const double mu = f.Mu[3 * ua + ia];
-      if (aa < 0 || aa >= f.nuf || mu == 0.0) continue;
-      double acc = 0.0;
-      for (int ib = 0; ib < 3; ++ib) {
-        const int bb = b - 1 + ib;
-        if (bb < 0 || bb >= f.nvf) continue;
-        acc += DD(L.Mv() + 3 * b + ib) * btif<FIRST>(a, Tprev, Tin, aa * f.nvf + bb, s);
-      }
-      self += mu * acc;
-    }
-    double cross = 0.0;
-    const int c0 = f.clo[ua], nc = f.ccnt[ua];
-    const int d0 = II(L.dlo() + b), nd = II(L.dcnt() + b);
-    for (int ic = 0; ic < nc; ++ic) {
-      const int c = c0 + ic;
-      double acc = 0.0;
-      for (int id = 0; id < nd; ++id)
-        acc += DD(L.Cv() + kBand * b + id) *
-               btif<FIRST>(a, Tprev, Tin, f.nfix + c * f.nvm + d0 + id, s);
-      cross += f.Cu[kBand * ua + ic] * acc;
-    }
+    const double self = bself<FIRST>(a, Tprev, Tin, f.Mu, D, L.Mv(), f.nuf, f.nvf, 0, ua, b, s);
+    const double cross =
+        bcross<FIRST>(a, Tprev, Tin, f.Cu + kBand * ua, D, L.Cv() + kBand * b, f.clo[ua],
+                      f.ccnt[ua], II(L.dlo() + b), II(L.dcnt() + b), f.nvm, f.nfix, s);
     return alpha * (cross - self) + f.split * qf * f.Hu[ua] * DD(L.Hv() + b);
   }
   const int k = i - f.nfix;
   const int c = k / f.nvm, d = k - c * f.nvm;
-  double self = 0.0;
-  for (int ic = 0; ic < 3; ++ic) {
-    const int cc = c - 1 + ic;
-    const double nu = f.Nu[3 * c + ic];
-    if (cc < 0 || cc >= f.num || nu == 0.0) continue;
-    double acc = 0.0;
-    for (int id = 0; id < 3; ++id) {
-      const int dd = d - 1 + id;
-      if (dd < 0 || dd >= f.nvm) continue;
-      acc += DD(L.Nv() + 3 * d + id) * btif<FIRST>(a, Tprev, Tin, f.nfix + cc * f.nvm + dd, s);
-    }
-    self += nu * acc;
-  }
-  double cross = 0.0;
-  const int a0 = f.alo[c], na = f.acnt[c];
-  const int b0 = II(L.blo() + d), nb = II(L.bcnt() + d);
-  for (int ia = 0; ia < na; ++ia) {
-    const int ua = a0 + ia;
-    double acc = 0.0;
-    for (int ib = 0; ib < nb; ++ib)
-      acc += DD(L.CvT() + kBand * d + ib) * btif<FIRST>(a, Tprev, Tin, ua * f.nvf + b0 + ib, s);
-    cross += f.CuT[kBand * c + ia] * acc;
-  }
+  const double self = bself<FIRST>(a, Tprev, Tin, f.Nu, D, L.Nv(), f.num, f.nvm, f.nfix, c, d, s);
+  const double cross =
+      bcross<FIRST>(a, Tprev, Tin, f.CuT + kBand * c, D, L.CvT() + kBand * d, f.alo[c],
+                    f.acnt[c], II(L.blo() + d), II(L.bcnt() + d), f.nvf, 0, s);
   return alpha * (cross - self) + (1.0 - f.split) * qf * f.Gu[c] * DD(L.Gv() + d);
 #undef DD
 #undef II
