@@ -292,10 +292,14 @@ struct CgArgs {
   const double *g;
   R *x, *r, *p, *q;
   R *u, *s;  // single-reduction form: u = M^{-1} r, s = A p (q holds w = A u)
-  double *partial;  // [3*grid]
+  double *partial;  // [6*grid]: per-block partial sums of the current solve
   SolveScalars *sc;
   StepCounters *ctr;
   int slot, grid, inner;
+  // > 0: the first operator step of a single-reduction solve also forms the
+  // solve's scalars from the init kernel's partials (r.z, r.r, b.b) with this
+  // relative tolerance, in place of a separate reduction launch
+  double init_rtol;
   // init / refinement
   double *x64, *b64, *r64;
   const double *Tprev, *F, *I;
@@ -564,8 +568,25 @@ __device__ inline void cg_converged(const CgArgs<R> &a, int iters) {
 template <bool D16, int TAIL, typename R, bool CPL = false, int FMT = 0, bool CG2 = false>
 __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
   constexpr bool DICT = FMT != 0;
-  if (TAIL != 2 && solve_done(a.sc, a.ctr)) return;
-  __shared__ double sh[17];
+  __shared__ double sh[34];
+  if (CG2 && TAIL != 2 && it == 0 && a.init_rtol > 0.0) {
+    // a fresh solve: its scalars from the init partials (every block decides
+    // the same way; block 0 stores them, the previous solve's flags are not read)
+    if (a.ctr->stop) return;
+    double rz = 0.0, rr = 0.0, bb = 0.0;
+    for (int j = threadIdx.x; j < a.grid; j += blockDim.x) {
+      rz += a.partial[j];
+      rr += a.partial[a.grid + j];
+      bb += a.partial[2 * a.grid + j];
+    }
+    block_sum2(rr, bb, sh);
+    rz = block_sum(rz, sh);
+    const double o[3] = {rz, rr, bb};
+    if (blockIdx.x == 0 && threadIdx.x == 0) init_finish(a.sc, a.ctr, a.slot, 0, a.init_rtol, o);
+    if (rr <= a.init_rtol * a.init_rtol * bb) return;  // the warm start meets the tolerance
+  } else if (TAIL != 2 && solve_done(a.sc, a.ctr)) {
+    return;
+  }
   if (CG2 && TAIL != 2 && it > 0) {
     const double rr = sum_partials(a.partial + ((it & 1) ? 4 : 1) * a.grid, a.grid, sh);
     if (rr <= a.sc->tol2) {
@@ -890,6 +911,7 @@ __global__ __launch_bounds__(kBlock) void k_refine_update(CgArgs<float> a, const
 
 static CgArgs<double> cg64(const DevState &d, int m, int slot) {
   CgArgs<double> a;
+  a.init_rtol = 0.0;
   a.op = d.op;
   a.N = d.N;
   a.dtau = d.dtau_h[m];
@@ -924,6 +946,7 @@ static CgArgs<double> cg64(const DevState &d, int m, int slot) {
 
 static CgArgs<float> cg32(const DevState &d, int m, int slot) {
   CgArgs<float> a;
+  a.init_rtol = 0.0;
   a.op = d.op;
   a.N = d.N;
   a.dtau = d.dtau_h[m];
@@ -967,14 +990,14 @@ void launch_init_pred(const DevState &d, int m, int slot, double rtol, hipStream
   if (d.op.pk16) k_init_pred<true, true><<<d.grid, kBlock, 0, st>>>(a);
   else if (d.op.d16) k_init_pred<true><<<d.grid, kBlock, 0, st>>>(a);
   else k_init_pred<false><<<d.grid, kBlock, 0, st>>>(a);
-  solve_reduce(d, slot, 0, rtol, 0, false, st);
+  (void)rtol;  // the solve's scalars are formed by its first operator step
 }
 
 void launch_init_corr(const DevState &d, int m, int slot, double rtol, hipStream_t st) {
   const CgArgs<double> a = cg64(d, m, slot);
   if (a.ifc_src) launch_iface_lin(d, m, d.T[m], st);  // the coupling source at tau_m
   k_init_corr<<<d.grid, kBlock, 0, st>>>(a);
-  solve_reduce(d, slot, 0, rtol, 0, false, st);
+  (void)rtol;  // the solve's scalars are formed by its first operator step
 }
 
 template <typename R>
@@ -1025,9 +1048,11 @@ static void pcg2_iter(const DevState &d, const CgArgs<R> &a, int it, bool tail, 
 }
 
 void launch_pcg_iter(const DevState &d, int m, int slot, int it, bool last, bool tail,
-                     hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                     double rtol, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   (void)last;  // the budget's end is judged by launch_pcg_final
-  pcg2_iter(d, cg64(d, m, slot), it, tail, st, ev0, ev1);
+  CgArgs<double> a = cg64(d, m, slot);
+  a.init_rtol = rtol;
+  pcg2_iter(d, a, it, tail, st, ev0, ev1);
 }
 
 void launch_pcg_final(const DevState &d, int m, int slot, int it, bool fp32, hipStream_t st) {

@@ -189,8 +189,11 @@ void launch_stationary_init(const DevState &d, const double *zeros, const double
                             double rtol, hipStream_t st);
 void launch_stationary_iters(const DevState &d, const double *zeros, const double *dinv, int slot,
                              int it0, int n, int last_it, hipStream_t st);
+// rtol: the solve's relative tolerance; its first launch (it = 0) forms the
+// solve's scalars from the partials of launch_init_pred / launch_init_corr
 void launch_pcg_iter(const DevState &d, int m, int slot, int it, bool last, bool tail,
-                     hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                     double rtol, hipStream_t st, hipEvent_t ev0 = nullptr,
+                     hipEvent_t ev1 = nullptr);
 void launch_refine_init(const DevState &d, int m, int slot, bool pred, double rtol,
                         hipStream_t st);
 void launch_inner_init(const DevState &d, int m, int slot, double inner_rtol, hipStream_t st);
