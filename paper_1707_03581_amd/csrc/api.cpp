@@ -1036,8 +1036,9 @@ void collect_events(mrsdc_ctx *c) {
   c->ev_used = 0;
 }
 
-// CG iterations of one solve within its launch budget.
-void enqueue_cg(mrsdc_ctx *c, int slot, int m, bool fp32) {
+// CG iterations of one solve within its launch budget, which is returned.
+// defer: the check after the budget is left to the caller.
+int enqueue_cg(mrsdc_ctx *c, int slot, int m, bool fp32, bool defer = false) {
   const DevState &d = c->d;
   const int B = c->budget[slot];
   for (int it = 0; it < B; ++it) {
@@ -1047,19 +1048,22 @@ void enqueue_cg(mrsdc_ctx *c, int slot, int m, bool fp32) {
     if (fp32) launch_pcg32_iter(d, m, slot, it, it == B - 1, tail, c->stream, e0, e1);
     else launch_pcg_iter(d, m, slot, it, it == B - 1, tail, c->cfg.pcg_rtol, c->stream, e0, e1);
   }
-  launch_pcg_final(d, m, slot, B, fp32, c->stream);
+  if (!defer) launch_pcg_final(d, m, slot, B, fp32, c->stream);
+  return B;
 }
 
-// One implicit node solve of interval m (x = T[m] in place).
-void enqueue_solve(mrsdc_ctx *c, int k, int m) {
+// One implicit node solve of interval m (x = T[m] in place).  defer: an FP64
+// solve leaves its final check to the caller and returns its launch budget
+// (-1 when nothing is left to check).
+int enqueue_solve(mrsdc_ctx *c, int k, int m, bool defer = false) {
   const DevState &d = c->d;
   const mrsdc_config &cfg = c->cfg;
   const int slot = slot_of(k, m);
   if (cfg.precision == MRSDC_FP64) {
     if (k == 0) launch_init_pred(d, m, slot, cfg.pcg_rtol, c->stream);
     else launch_init_corr(d, m, slot, cfg.pcg_rtol, c->stream);
-    enqueue_cg(c, slot, m, false);
-    return;
+    const int B = enqueue_cg(c, slot, m, false, defer);
+    return defer ? B : -1;
   }
   // FP32 inner CG, FP64 refinement: rounds within a budget
   launch_refine_init(d, m, slot, k == 0, cfg.refine_rtol, c->stream);
@@ -1069,6 +1073,7 @@ void enqueue_solve(mrsdc_ctx *c, int k, int m) {
     enqueue_cg(c, slot, m, true);
     launch_refine_update(d, m, slot, r, r == R - 1, c->stream);
   }
+  return -1;
 }
 
 void enqueue_step(mrsdc_ctx *c) {
@@ -1081,10 +1086,10 @@ void enqueue_step(mrsdc_ctx *c) {
   // predictor (Alg. 1)
   for (int m = 1; m <= M; ++m) {
     if (c->w.dtau[m] == 0.0) continue;
-    enqueue_solve(c, 0, m);
+    const int chk = enqueue_solve(c, 0, m, true);
     hipEvent_t e0, e1;
     if (take_events(c, 1, &e0, &e1)) hipEventRecord(e0, st);
-    launch_iface(d, m, false, st);
+    launch_iface(d, m, false, slot_of(0, m), chk, st);
     if (e1) hipEventRecord(e1, st);
   }
   std::swap(d.Eold, d.Enew);
@@ -1099,10 +1104,10 @@ void enqueue_step(mrsdc_ctx *c) {
     launch_iface_quad(d, st);
     for (int m = 1; m <= M; ++m) {
       if (c->w.dtau[m] == 0.0) continue;
-      enqueue_solve(c, k, m);
+      const int chk = enqueue_solve(c, k, m, true);
       hipEvent_t e0, e1;
       if (take_events(c, 1, &e0, &e1)) hipEventRecord(e0, st);
-      launch_iface(d, m, true, st);
+      launch_iface(d, m, true, slot_of(k, m), chk, st);
       if (e1) hipEventRecord(e1, st);
     }
     std::swap(d.Eold, d.Enew);

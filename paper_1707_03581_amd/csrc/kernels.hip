@@ -702,10 +702,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_upd(CgArgs<R> a, int it) {
 }
 
 // After the launch budget: converged at iteration it, or the solve failed.
+// Executed by one whole block.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_cg_check(CgArgs<R> a, int it) {
+__device__ inline void cg_check_block(const CgArgs<R> &a, int it, double *sh) {
   if (solve_done(a.sc, a.ctr)) return;
-  __shared__ double sh[17];
   const double rr = sum_partials(a.partial + ((it & 1) ? 4 : 1) * a.grid, a.grid, sh);
   if (threadIdx.x != 0) return;
   if (rr <= a.sc->tol2) {
@@ -715,6 +715,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_check(CgArgs<R> a, int it) {
     a.ctr->pcg_iters += it;
     if (!a.inner) a.ctr->fail += 1;
   }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_cg_check(CgArgs<R> a, int it) {
+  __shared__ double sh[17];
+  cg_check_block(a, it, sh);
 }
 
 // (b) alpha = r.z / p.q; x += alpha p; r -= alpha q; partial r.z, r.r
@@ -1283,6 +1289,12 @@ struct SubArgs {
   double *Ipre;        // [(M+1)(P+1) n_if] embedded quadratures of the sweep
   double *Tbuf[2];
   double *fst;
+  // first substep only: f^E at tau_{m-1} with the previous interval's table
+  // (its q = P value; prev_m = 0: none) and the check after the node solve's
+  // launch budget (chk_it < 0: none)
+  int prev_m;
+  int chk_it;
+  CgArgs<double> chk;
 };
 
 // interface state: on the first substep T_{m,0} = T_{m-1} is read from the
@@ -1409,9 +1421,17 @@ __device__ double iface_fE(const SubArgs &A, const double *D, const int *I, cons
   return src + lin;
 }
 
-// Substep p of interval m (p = P+1: only f^E at tau_m and the write-back).
+// Substep p of interval m; p = P also writes T^{k+1}_m <- T_{m,P} back.
+// p = P+1 (last interval only): f^E at tau_m.  The other intervals' f^E at
+// their end point is formed by the next interval's first substep, from the
+// same state with the same table.  The first substep launch also takes over
+// the convergence check of the node solve it follows (block 0).
 template <bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_iface_sub(SubArgs A) {
+  if (FIRST && A.chk_it >= 0 && blockIdx.x == 0) {
+    __shared__ double sh[17];
+    cg_check_block(A.chk, A.chk_it, sh);
+  }
   if (A.ctr->stop) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const IfaceDev &f = A.f;
@@ -1427,10 +1447,16 @@ __global__ __launch_bounds__(kBlock) void k_iface_sub(SubArgs A) {
   const double E = iface_fE<FIRST>(A, D, I, Tin, i);
   double *En = A.Enew + (size_t)m * P1 * n;
   En[(size_t)(p - 1) * n + i] = E;
+  if (FIRST && A.prev_m > 0) {
+    const int tq = A.prev_m * P1 + P;
+    A.Enew[((size_t)A.prev_m * P1 + P) * n + i] =
+        iface_fE<true>(A, A.coefD + (size_t)tq * L.dstride(), A.coefI + (size_t)tq * L.istride(),
+                       Tin, i);
+  }
   const double Ti = tif<FIRST>(A, Tin, i);
   const int64_t row = f.rows[i];
   if (p == P + 1) {
-    A.Tm[row] = Ti;  // T^{k+1}_m <- T_{m,P}
+    A.Tm[row] = Ti;  // T^{k+1}_m <- T_{m,P} (already written by substep P)
     return;
   }
   const double mi = A.mass[row], dtm = w.dtau[m], dtp = dtm / P;
@@ -1450,7 +1476,9 @@ __global__ __launch_bounds__(kBlock) void k_iface_sub(SubArgs A) {
   } else {
     inc = dtp * (fs + E);
   }
-  A.Tbuf[p & 1][i] = Ti + inc / mi;
+  const double Tn = Ti + inc / mi;
+  A.Tbuf[p & 1][i] = Tn;
+  if (p == P) A.Tm[row] = Tn;  // T^{k+1}_m <- T_{m,P}
 }
 
 void launch_iface_coeffs(const DevState &d, hipStream_t st) {
@@ -1554,8 +1582,11 @@ void launch_iface_quad(const DevState &d, hipStream_t st) {
   k_iface_quad<<<dim3((d.ifc.n_if + kBlock - 1) / kBlock, d.M), kBlock, 0, st>>>(A);
 }
 
-void launch_iface(const DevState &d, int m, bool corr, hipStream_t st) {
-  if (!d.ifc.kind || d.ifc.n_if == 0) return;
+void launch_iface(const DevState &d, int m, bool corr, int slot, int chk_it, hipStream_t st) {
+  if (!d.ifc.kind || d.ifc.n_if == 0) {
+    if (chk_it >= 0) launch_pcg_final(d, m, slot, chk_it, false, st);
+    return;
+  }
   SubArgs A;
   A.f = d.ifc;
   A.ctr = d.ctr;
@@ -1577,8 +1608,12 @@ void launch_iface(const DevState &d, int m, bool corr, hipStream_t st) {
   A.Tbuf[0] = d.Tbuf[0];
   A.Tbuf[1] = d.Tbuf[1];
   A.fst = d.fst;
+  A.prev_m = (m > 1 && d.dtau_h[m - 1] != 0.0) ? m - 1 : 0;
+  A.chk_it = chk_it;
+  A.chk = cg64(d, m, slot);
   const int grid = (d.ifc.n_if + kBlock - 1) / kBlock;
-  for (int p = 1; p <= d.P + 1; ++p) {
+  const int last = m == d.M ? d.P + 1 : d.P;
+  for (int p = 1; p <= last; ++p) {
     A.p = p;
     if (p == 1) k_iface_sub<true><<<grid, kBlock, 0, st>>>(A);
     else k_iface_sub<false><<<grid, kBlock, 0, st>>>(A);

@@ -206,7 +206,9 @@ void launch_clear_counters(const DevState &d, hipStream_t st);
 size_t coef_table_doubles(const IfaceDev &f);
 size_t coef_table_ints(const IfaceDev &f);
 void launch_iface_coeffs(const DevState &d, hipStream_t st);
-void launch_iface(const DevState &d, int m, bool corr, hipStream_t st);
+// The embedded substeps of interval m after its node solve; chk_it >= 0: the
+// solve's check after its launch budget (launch_pcg_final) is left to this call.
+void launch_iface(const DevState &d, int m, bool corr, int slot, int chk_it, hipStream_t st);
 void launch_step_end(const DevState &d, double dt, hipStream_t st);
 void launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
 
