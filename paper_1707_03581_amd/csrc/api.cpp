@@ -578,7 +578,7 @@ mrsdc_status prepare(mrsdc_ctx *c) {
   d.sweep_tol = cfg.sweep_tol;
   d.single_rate = cfg.method == MRSDC_SINGLE_RATE;
   for (int m = 0; m <= cfg.M; ++m) d.dtau_h[m] = c->w.dtau[m];
-  d.grid = (int)std::min<int64_t>((N + kBlock - 1) / kBlock, 1024);
+  d.grid = (int)std::min<int64_t>((N + kBlock - 1) / kBlock, kMaxGrid);
   if (d.grid < 1) d.grid = 1;
   const bool batch = c->S > 0;
   const int S = batch ? c->S : 1;

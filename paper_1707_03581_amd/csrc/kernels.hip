@@ -300,6 +300,9 @@ struct CgArgs {
   // solve's scalars from the init kernel's partials (r.z, r.r, b.b) with this
   // relative tolerance, in place of a separate reduction launch
   double init_rtol;
+  // residual-controlled sweeps: test the stop flag before anything else, so
+  // the launches of sweeps that are no longer run return at once
+  int early_stop;
   // init / refinement
   double *x64, *b64, *r64;
   const double *Tprev, *F, *I;
@@ -348,9 +351,9 @@ __device__ inline double sell_row_pk(const SellDev &op, int64_t s, int lane, int
 // Same through the row patterns (form table in LDS): the same entries, in the
 // same order, slice padding included, so the same sums.
 template <typename R>
-__device__ inline double sell_row_cls(const SellDev &op, int64_t row, const R *__restrict__ x,
-                                      const R *sd, const int *sct, const int *slen) {
-  const int c = op.rcls[row];
+__device__ inline double sell_row_cls(const SellDev &op, int64_t row, int c,
+                                      const R *__restrict__ x, const R *sd, const int *sct,
+                                      const int *slen) {
   const int n = slen[c];
   const int *t = sct + c * op.cw;
   R acc = 0;
@@ -565,61 +568,125 @@ __device__ inline void cg_converged(const CgArgs<R> &a, int iters) {
   if (iters > ctr->max_iters) ctr->max_iters = iters;
 }
 
+static_assert(kDictMax <= kBlock && kMaxCls <= kBlock && kMaxGrid % kBlock == 0 &&
+                  (kMaxCls * kMaxClsWidth) % kBlock == 0,
+              "the operator kernel stages one dictionary entry and one form length per thread");
+
 template <bool D16, int TAIL, typename R, bool CPL = false, int FMT = 0, bool CG2 = false>
 __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
   constexpr bool DICT = FMT != 0;
   __shared__ double sh[34];
-  if (CG2 && TAIL != 2 && it == 0 && a.init_rtol > 0.0) {
-    // a fresh solve: its scalars from the init partials (every block decides
-    // the same way; block 0 stores them, the previous solve's flags are not read)
-    if (a.ctr->stop) return;
-    double rz = 0.0, rr = 0.0, bb = 0.0;
-    for (int j = threadIdx.x; j < a.grid; j += blockDim.x) {
-      rz += a.partial[j];
-      rr += a.partial[a.grid + j];
-      bb += a.partial[2 * a.grid + j];
+  __shared__ R sd[DICT ? kDictMax : 1];
+  __shared__ int sct[FMT == 3 ? kMaxCls * kMaxClsWidth : 1];
+  __shared__ int slen[FMT == 3 ? kMaxCls : 1];
+  constexpr int kTab = FMT == 3 ? kMaxCls * kMaxClsWidth / kBlock : 1;
+  constexpr int kPart = kMaxGrid / kBlock;
+  // fresh: the first operator step of a solve, which forms the solve's
+  // scalars from the init kernel's partials (r.z, r.r, b.b) and reads none of
+  // the previous solve's flags; check: the convergence test on ||r_it||^2
+  const bool fresh = CG2 && TAIL != 2 && it == 0 && a.init_rtol > 0.0;
+  const bool check = CG2 && TAIL != 2 && it > 0;
+  const R *__restrict__ xin = CG2 ? a.u : a.p;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+  if (a.early_stop && a.ctr->stop) return;
+  // Every request that does not depend on another is issued before the first
+  // wait: the solve flags, the partials of the reductions, the table entries
+  // and the first slice's row data.
+  int stop = 0;
+  if (TAIL != 2)
+    stop = fresh ? a.ctr->stop : (a.sc->done | a.sc->ref_done | a.ctr->stop);
+  // (loaded first, summed afterwards; a term past the grid is an exact zero)
+  double t0[kPart], t1[kPart], t2[kPart];
+#pragma unroll
+  for (int q = 0; q < kPart; ++q) t0[q] = t1[q] = t2[q] = 0.0;
+  if (fresh || check) {
+    const double *p0 = a.partial + (fresh ? 0 : ((it & 1) ? 4 : 1) * a.grid);
+#pragma unroll
+    for (int q = 0; q < kPart; ++q) {
+      const int j = (int)threadIdx.x + q * kBlock;
+      if (j < a.grid) t0[q] = p0[j];
     }
+  }
+  if (fresh) {
+#pragma unroll
+    for (int q = 0; q < kPart; ++q) {
+      const int j = (int)threadIdx.x + q * kBlock;
+      if (j < a.grid) {
+        t1[q] = a.partial[a.grid + j];
+        t2[q] = a.partial[2 * a.grid + j];
+      }
+    }
+  }
+  int tab[kTab];
+  R dv = 0;
+  int lv = 0;
+  if (DICT) {
+    const R *dict = sizeof(R) == 8 ? (const R *)a.op.vdict : (const R *)a.op.vdict32;
+    if ((int)threadIdx.x < a.op.ndict) dv = dict[threadIdx.x];
+    if (FMT == 3) {
+      const int nt = a.op.ncls * a.op.cw;
+#pragma unroll
+      for (int q = 0; q < kTab; ++q) {
+        const int j = (int)threadIdx.x + q * kBlock;
+        tab[q] = j < nt ? a.op.ctab[j] : 0;
+      }
+      if ((int)threadIdx.x < a.op.ncls) lv = a.op.clen[threadIdx.x];
+    }
+  }
+  const int64_t row0 = wave * kSlice + lane;
+  const bool have0 = wave < a.op.nslices && row0 < a.N;
+  int c0 = 0;
+  R u0 = 0, m0 = 0;
+  if (have0) {
+    if (FMT == 3) c0 = a.op.rcls[row0];
+    u0 = xin[row0];
+    m0 = a.mass[row0];
+  }
+  if (stop) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < kPart; ++q) {
+    s0 += t0[q];
+    s1 += t1[q];
+    s2 += t2[q];
+  }
+  if (fresh) {
+    const double rz = s0;
+    double rr = s1, bb = s2;
     block_sum2(rr, bb, sh);
-    rz = block_sum(rz, sh);
-    const double o[3] = {rz, rr, bb};
+    const double o[3] = {block_sum(rz, sh), rr, bb};
     if (blockIdx.x == 0 && threadIdx.x == 0) init_finish(a.sc, a.ctr, a.slot, 0, a.init_rtol, o);
     if (rr <= a.init_rtol * a.init_rtol * bb) return;  // the warm start meets the tolerance
-  } else if (TAIL != 2 && solve_done(a.sc, a.ctr)) {
-    return;
-  }
-  if (CG2 && TAIL != 2 && it > 0) {
-    const double rr = sum_partials(a.partial + ((it & 1) ? 4 : 1) * a.grid, a.grid, sh);
+  } else if (check) {
+    const double rr = block_sum(s0, sh);
     if (rr <= a.sc->tol2) {
       if (blockIdx.x == 0 && threadIdx.x == 0) cg_converged(a, it);
       return;
     }
   }
-  const R *__restrict__ xin = CG2 ? a.u : a.p;
-  __shared__ R sd[DICT ? kDictMax : 1];
-  __shared__ int sct[FMT == 3 ? kMaxCls * kMaxClsWidth : 1];
-  __shared__ int slen[FMT == 3 ? kMaxCls : 1];
   if (DICT) {
-    const R *dict = sizeof(R) == 8 ? (const R *)a.op.vdict : (const R *)a.op.vdict32;
-    for (int j = threadIdx.x; j < a.op.ndict; j += kBlock) sd[j] = dict[j];
+    if ((int)threadIdx.x < a.op.ndict) sd[threadIdx.x] = dv;
     if (FMT == 3) {
-      for (int j = threadIdx.x; j < a.op.ncls * a.op.cw; j += kBlock) sct[j] = a.op.ctab[j];
-      for (int j = threadIdx.x; j < a.op.ncls; j += kBlock) slen[j] = a.op.clen[j];
+#pragma unroll
+      for (int q = 0; q < kTab; ++q) sct[threadIdx.x + q * kBlock] = tab[q];
+      if ((int)threadIdx.x < a.op.ncls) slen[threadIdx.x] = lv;
     }
     __syncthreads();
   }
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
   double v[1] = {0.0};
   for (int64_t s = wave; s < a.op.nslices; s += nw) {
     const int64_t row = s * kSlice + lane;
     if (row >= a.N) continue;
-    const R Lp = FMT == 3   ? (R)sell_row_cls<R>(a.op, row, xin, sd, sct, slen)
+    const bool first = s == wave;
+    const R Lp = FMT == 3 ? (R)sell_row_cls<R>(a.op, row, first ? c0 : (int)a.op.rcls[row], xin,
+                                                 sd, sct, slen)
                  : FMT == 2 ? (R)sell_row_pk<R>(a.op, s, lane, row, xin, sd)
                  : FMT == 1 ? (R)sell_row_dict<D16, R>(a.op, s, lane, row, xin, sd)
                             : (R)sell_row_t<D16, R>(a.op, s, lane, row, xin);
-    const R pi = xin[row];
-    R qi = a.mass[row] * pi + (R)a.dtau * Lp;
+    const R pi = first ? u0 : xin[row];
+    R qi = (first ? m0 : a.mass[row]) * pi + (R)a.dtau * Lp;
     if (CPL) {  // single-rate method: the coupling of the node operator
       const int ip = a.ifpos[row];
       if (ip >= 0) qi += (R)a.ifc_lin[ip];
@@ -639,12 +706,15 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
 // of two, so one launch fewer per iteration.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_cg_upd(CgArgs<R> a, int it) {
-  if (solve_done(a.sc, a.ctr)) return;
+  if (a.early_stop && a.ctr->stop) return;
+  // the solve flags, the first row's operands and the partials are all
+  // requested before the first wait
+  const int stop = a.sc->done | a.sc->ref_done | a.ctr->stop;
   __shared__ double sh[34];
   const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool first = i0 < a.N;
   R u0 = 0, w0 = 0, p0 = 0, s0 = 0, x0 = 0, r0 = 0, d0 = 0;
-  if (first) {  // requested before the reductions
+  if (first) {
     u0 = a.u[i0];
     w0 = a.q[i0];
     if (it > 0) {
@@ -656,10 +726,19 @@ __global__ __launch_bounds__(kBlock) void k_cg_upd(CgArgs<R> a, int it) {
     d0 = a.dinv[i0];
   }
   const double *pg = a.partial + ((it & 1) ? 3 : 0) * a.grid, *pd = a.partial + 5 * a.grid;
+  double tg[kMaxGrid / kBlock], td[kMaxGrid / kBlock];  // loaded first, summed afterwards
+#pragma unroll
+  for (int q = 0; q < kMaxGrid / kBlock; ++q) {
+    const int j = (int)threadIdx.x + q * kBlock;
+    tg[q] = j < a.grid ? pg[j] : 0.0;
+    td[q] = j < a.grid ? pd[j] : 0.0;
+  }
+  if (stop) return;
   double gam = 0.0, del = 0.0;
-  for (int j = threadIdx.x; j < a.grid; j += blockDim.x) {
-    gam += pg[j];
-    del += pd[j];
+#pragma unroll
+  for (int q = 0; q < kMaxGrid / kBlock; ++q) {
+    gam += tg[q];
+    del += td[q];
   }
   block_sum2(gam, del, sh);
   SolveScalars *sc = a.sc;
@@ -918,6 +997,7 @@ __global__ __launch_bounds__(kBlock) void k_refine_update(CgArgs<float> a, const
 static CgArgs<double> cg64(const DevState &d, int m, int slot) {
   CgArgs<double> a;
   a.init_rtol = 0.0;
+  a.early_stop = d.sweep_tol > 0.0 ? 1 : 0;
   a.op = d.op;
   a.N = d.N;
   a.dtau = d.dtau_h[m];
@@ -953,6 +1033,7 @@ static CgArgs<double> cg64(const DevState &d, int m, int slot) {
 static CgArgs<float> cg32(const DevState &d, int m, int slot) {
   CgArgs<float> a;
   a.init_rtol = 0.0;
+  a.early_stop = d.sweep_tol > 0.0 ? 1 : 0;
   a.op = d.op;
   a.N = d.N;
   a.dtau = d.dtau_h[m];

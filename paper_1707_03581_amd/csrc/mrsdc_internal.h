@@ -15,6 +15,7 @@ constexpr int kMaxP = 32;
 constexpr int kBand = 8;        // max coupled nodes per face node and direction
 constexpr int kSlice = 64;      // SELL slice height = one wavefront
 constexpr int kBlock = 256;     // threads per block of the vector kernels
+constexpr int kMaxGrid = 1024;  // blocks (and reduction partials) of a solve's kernels
 constexpr int kIfaceBlock = 1024;
 constexpr int kMaxJ = 8;        // right-hand sides of the multi-vector SpMV
 
