@@ -172,9 +172,23 @@ __device__ __attribute__((always_inline)) inline void stage_issue(int nslots,
   if (64 % upr == 0) {
     const int rpi = 64 / upr;  // rows per load instruction
     const int lr = lane / upr, lu = lane - lr * upr;
-    for (int r0 = w * rpi; r0 < nslots; r0 += (kBlock / 64) * rpi) {
-      const int sl = r0 + lr < nslots ? r0 + lr : r0;
-      issue(xb + ((size_t)ssl[sl] * upr + lu) * UB, r0 * upr);
+    const int step = (kBlock / 64) * rpi;
+    // An LDS read after a copy into LDS waits for every copy in flight, so
+    // the slot rows of kBatch copies are read first and their copies issued
+    // together: one wait per batch instead of one per copy.
+    constexpr int kBatch = 8;
+    for (int rb = w * rpi; rb < nslots; rb += kBatch * step) {
+      int src[kBatch];
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        const int r0 = rb + k * step;
+        src[k] = r0 < nslots ? ssl[r0 + lr < nslots ? r0 + lr : r0] : 0;
+      }
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        const int r0 = rb + k * step;
+        if (r0 < nslots) issue(xb + ((size_t)src[k] * upr + lu) * UB, r0 * upr);
+      }
     }
     return;
   }
@@ -349,13 +363,24 @@ struct BV<float> {
   __device__ static float *q(const BatchArgs &a) { return a.q32; }
 };
 
+// (the flags are read at a clamped index without short-circuit evaluation,
+// so all of them are requested at once)
 __device__ inline bool lane_on(const BatchScalars *sc, int s, int S) {
-  return s < S && sc->active[s] && !sc->done[s] && !sc->ref_done[s] && !sc->stop[s];
+  const int k = s < S ? s : 0;
+  const int off = sc->done[k] | sc->ref_done[k] | sc->stop[k];
+  return (s < S) & (sc->active[k] != 0) & (off == 0);
 }
 
 // scenario s still sweeping this step (active, not stopped by residual control)
 __device__ inline bool sweeping(const BatchScalars *sc, int s, int S) {
-  return s < S && sc->active[s] && !sc->stop[s];
+  const int k = s < S ? s : 0;
+  return (s < S) & (sc->active[k] != 0) & (sc->stop[k] == 0);
+}
+
+// the scenario's h, read at a clamped index (zero for a lane past S)
+__device__ inline double lane_h(const BatchArgs &a, int s) {
+  const double h = a.h[s < a.S ? s : 0];
+  return s < a.S ? h : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -574,8 +599,9 @@ __global__ __launch_bounds__(kBlock) void kb_refine_update(BatchArgs a, int m, d
 #pragma unroll
   for (int i = 0; i < LY::VEC; ++i) {
     const int s = s0 + i;
-    on[i] = sweeping(a.sc, s, S) && !a.sc->ref_done[s];
-    h[i] = on[i] ? a.h[s] : 0.0;
+    on[i] = sweeping(a.sc, s, S) & (a.sc->ref_done[s < S ? s : 0] == 0);
+    const double hs = lane_h(a, s);
+    h[i] = on[i] ? hs : 0.0;
     any |= on[i];
   }
   double *x = a.T[m];
@@ -700,7 +726,8 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_a(BatchArgs a, int m, double dt
   for (int i = 0; i < LY::VEC; ++i) {
     const int s = s0 + i;
     on[i] = TIMING ? s < S : lane_on(a.sc, s, S);
-    h[i] = on[i] ? (V)a.h[s] : (V)0;
+    const V hs = (V)lane_h(a, s);
+    h[i] = on[i] ? hs : (V)0;
     any |= on[i];
   }
   const V dt = (V)dtau;
