@@ -200,28 +200,47 @@ struct QArgs {
   double *partial;
 };
 
-__global__ __launch_bounds__(kBlock) void k_quad_resid(int64_t N, QArgs a) {
+// (the weights come as a restrict-qualified parameter: read-only and alias
+// free for the kernel, so they are read through the scalar cache)
+__global__ __launch_bounds__(kBlock) void k_quad_resid(int64_t N, QArgs a,
+                                                       const Weights *__restrict__ wp) {
   __shared__ double sh[17];
-  const Weights &w = *a.w;
+  const Weights &w = *wp;
   const int P1 = a.P + 1;
   double rmax = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * kBlock) {
+    // every operand of the row is requested before the first store (a store
+    // may alias them, which would order the loads after it)
     const double mi = a.mass[i];
     const double Tn = a.T[0][i];
     const int pos = a.ifpos ? a.ifpos[i] : -1;
-    double cum = 0.0;
-    for (int m = 1; m <= a.M; ++m) {
-      if (w.dtau[m] == 0.0) continue;
-      double acc = 0.0;
-      for (int j = 1; j <= a.M; ++j) acc += w.s[m][j] * a.F[j][i];
+    double F[kMaxM + 1], T[kMaxM + 1], acc[kMaxM + 1];
+#pragma unroll
+    for (int j = 1; j <= kMaxM; ++j) {
+      F[j] = j <= a.M ? a.F[j][i] : 0.0;
+      T[j] = j <= a.M ? a.T[j][i] : 0.0;
+    }
+#pragma unroll
+    for (int m = 1; m <= kMaxM; ++m) {
+      acc[m] = 0.0;
+      if (m > a.M || w.dtau[m] == 0.0) continue;
+#pragma unroll
+      for (int j = 1; j <= kMaxM; ++j)
+        if (j <= a.M) acc[m] += w.s[m][j] * F[j];
       if (pos >= 0) {
         const double *E = a.Eold + (size_t)m * P1 * a.n_if + pos;
-        for (int q = 1; q <= a.P; ++q) acc += w.shat[m][q] * E[(size_t)q * a.n_if];
+#pragma unroll 4
+        for (int q = 1; q <= a.P; ++q) acc[m] += w.shat[m][q] * E[(size_t)q * a.n_if];
       }
-      a.I[m][i] = acc;
-      cum += acc;
-      rmax = fmax(rmax, fabs(mi * a.T[m][i] - mi * Tn - cum));
+    }
+    double cum = 0.0;
+#pragma unroll
+    for (int m = 1; m <= kMaxM; ++m) {
+      if (m > a.M || w.dtau[m] == 0.0) continue;
+      a.I[m][i] = acc[m];
+      cum += acc[m];
+      rmax = fmax(rmax, fabs(mi * T[m] - mi * Tn - cum));
     }
   }
   rmax = block_max(rmax, sh);
@@ -258,7 +277,7 @@ void launch_quad_resid(const DevState &d, int k, hipStream_t st) {
   a.M = d.M;
   a.P = d.P;
   a.partial = d.partial;
-  k_quad_resid<<<d.grid, kBlock, 0, st>>>(d.N, a);
+  k_quad_resid<<<d.grid, kBlock, 0, st>>>(d.N, a, d.w);
   k_reduce_max<<<1, kBlock, 0, st>>>(d.partial, d.grid, d.ctr, k, d.sweep_tol);
 }
 
@@ -1628,24 +1647,43 @@ void launch_iface_lin(const DevState &d, int m, const double *x, hipStream_t st)
 // every interval and substep of a sweep: they depend only on the previous
 // iterate (F_j at the sweep start, the previous sweep's E cache), so one pass
 // at the sweep start replaces M + P scattered loads per point and substep.
-__global__ __launch_bounds__(kBlock) void k_iface_quad(SubArgs A) {
+// (restrict-qualified weights, cache and output: the weights are read
+// through the scalar cache, and every operand of a point is loaded before its
+// first store)
+__global__ __launch_bounds__(kBlock) void k_iface_quad(SubArgs A, const Weights *__restrict__ wp,
+                                                       const double *__restrict__ Eold,
+                                                       double *__restrict__ Ipre) {
   if (A.ctr->stop) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = A.f.n_if;
   if (i >= n) return;
-  const Weights &w = *A.w;
+  const Weights &w = *wp;
   const int P = A.P, P1 = P + 1;
   const int m = blockIdx.y + 1;  // one interval per grid row
   if (w.dtau[m] == 0.0) return;
   const int64_t row = A.f.rows[i];
-  double F[kMaxM + 1];
-  for (int j = 1; j <= A.M; ++j) F[j] = A.F[j][row];
-  const double *Eo = A.Eold + (size_t)m * P1 * n;
+  const double *Eo = Eold + (size_t)m * P1 * n;
+  // loads at clamped indices (no branch between them), zero past M and P
+  double F[kMaxM + 1], E[kMaxP + 1];
+#pragma unroll
+  for (int j = 1; j <= kMaxM; ++j) {
+    const double v = A.F[j <= A.M ? j : 1][row];
+    F[j] = j <= A.M ? v : 0.0;
+  }
+#pragma unroll
+  for (int q = 1; q <= kMaxP; ++q) {
+    const double v = Eo[(size_t)(q <= P ? q : P) * n + i];
+    E[q] = q <= P ? v : 0.0;
+  }
   for (int p = 1; p <= P; ++p) {
     double Ip = 0.0;
-    for (int j = 1; j <= A.M; ++j) Ip += w.stil[m][p][j] * F[j];
-    for (int q = 1; q <= P; ++q) Ip += w.spq[m][p][q] * Eo[(size_t)q * n + i];
-    A.Ipre[((size_t)m * P1 + p) * n + i] = Ip;
+#pragma unroll
+    for (int j = 1; j <= kMaxM; ++j)
+      if (j <= A.M) Ip += w.stil[m][p][j] * F[j];
+#pragma unroll
+    for (int q = 1; q <= kMaxP; ++q)
+      if (q <= P) Ip += w.spq[m][p][q] * E[q];
+    Ipre[((size_t)m * P1 + p) * n + i] = Ip;
   }
 }
 
@@ -1660,7 +1698,8 @@ void launch_iface_quad(const DevState &d, hipStream_t st) {
   for (int j = 0; j <= kMaxM; ++j) A.F[j] = d.F[j];
   A.Eold = d.Eold;
   A.Ipre = d.Ipre;
-  k_iface_quad<<<dim3((d.ifc.n_if + kBlock - 1) / kBlock, d.M), kBlock, 0, st>>>(A);
+  k_iface_quad<<<dim3((d.ifc.n_if + kBlock - 1) / kBlock, d.M), kBlock, 0, st>>>(A, d.w, d.Eold,
+                                                                                 d.Ipre);
 }
 
 void launch_iface(const DevState &d, int m, bool corr, int slot, int chk_it, hipStream_t st) {
