@@ -153,13 +153,76 @@ __global__ __launch_bounds__(kBlock) void k_f_multi(SellDev op, FArgs a) {
   }
 }
 
+// Row-pattern tables into LDS: the value dictionary, the forms (offset * 256
+// + value id) and their lengths; every table load is issued before the
+// first store, then one barrier.
+template <typename R>
+__device__ inline void stage_forms(const SellDev &op, R *sd, int *sct, int *slen) {
+  constexpr int kTab = kMaxCls * kMaxClsWidth / kBlock;
+  const R *dict = sizeof(R) == 8 ? (const R *)op.vdict : (const R *)op.vdict32;
+  const int nt = op.ncls * op.cw;
+  int tab[kTab];
+  R dv = 0;
+  int lv = 0;
+  if ((int)threadIdx.x < op.ndict) dv = dict[threadIdx.x];
+#pragma unroll
+  for (int q = 0; q < kTab; ++q) {
+    const int j = (int)threadIdx.x + q * kBlock;
+    tab[q] = j < nt ? op.ctab[j] : 0;
+  }
+  if ((int)threadIdx.x < op.ncls) lv = op.clen[threadIdx.x];
+  if ((int)threadIdx.x < op.ndict) sd[threadIdx.x] = dv;
+#pragma unroll
+  for (int q = 0; q < kTab; ++q) sct[threadIdx.x + q * kBlock] = tab[q];
+  if ((int)threadIdx.x < op.ncls) slen[threadIdx.x] = lv;
+  __syncthreads();
+}
+
+// F_j = g - L T_j for J nodes through the row patterns: each form entry's
+// value and column serve all J vectors; entries in the row's order, as in
+// the other formats.
+template <int J>
+__global__ __launch_bounds__(kBlock) void k_f_multi_cls(SellDev op, FArgs a) {
+  __shared__ double sd[kDictMax];
+  __shared__ int sct[kMaxCls * kMaxClsWidth];
+  __shared__ int slen[kMaxCls];
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+  const int64_t row0 = wave * kSlice + lane;
+  const int c0 = (wave < op.nslices && row0 < op.nrows) ? (int)op.rcls[row0] : 0;
+  stage_forms<double>(op, sd, sct, slen);
+  for (int64_t s = wave; s < op.nslices; s += nw) {
+    const int64_t row = s * kSlice + lane;
+    if (row >= op.nrows) continue;
+    const int c = s == wave ? c0 : (int)op.rcls[row];
+    const int n = slen[c];
+    const int *t = sct + c * op.cw;
+    double acc[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) acc[j] = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < n; ++k) {
+      const int w = t[k];
+      const double v = sd[w & 255];
+      const int64_t col = row + (w >> 8);
+#pragma unroll
+      for (int j = 0; j < J; ++j) acc[j] += v * a.T[j][col];
+    }
+    const double gi = a.g[row];
+#pragma unroll
+    for (int j = 0; j < J; ++j) a.F[j][row] = gi - acc[j];
+  }
+}
+
 template <bool D16>
 static void f_multi_dispatch(const DevState &d, FArgs a, int J, hipStream_t st) {
   const int grid = d.grid;
   switch (J) {
 #define CASE(n) \
   case n:                                                                   \
-    if (d.op.pk16) k_f_multi<D16, n, true><<<grid, kBlock, 0, st>>>(d.op, a); \
+    if (d.op.rcls) k_f_multi_cls<n><<<grid, kBlock, 0, st>>>(d.op, a);      \
+    else if (d.op.pk16) k_f_multi<D16, n, true><<<grid, kBlock, 0, st>>>(d.op, a); \
     else k_f_multi<D16, n><<<grid, kBlock, 0, st>>>(d.op, a);               \
     break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
@@ -462,23 +525,30 @@ __device__ inline void init_finish(SolveScalars *sc, StepCounters *ctr, int slot
 }
 
 // predictor: x0 = T_{m-1}, b = M T_{m-1} + dtau g, r = b - A x0 (one SpMV)
-template <bool D16, bool PK = false>
+// CLS: row patterns (the tables staged once per block)
+template <bool D16, bool PK = false, bool CLS = false>
 __global__ __launch_bounds__(kBlock) void k_init_pred(CgArgs<double> a) {
   __shared__ double sh[17];
-  __shared__ double sd[PK ? 16 : 1];
-  if (PK) {
-    if (threadIdx.x < a.op.ndict) sd[threadIdx.x] = a.op.vdict[threadIdx.x];
-    __syncthreads();
-  }
+  __shared__ double sd[CLS ? kDictMax : (PK ? 16 : 1)];
+  __shared__ int sct[CLS ? kMaxCls * kMaxClsWidth : 1];
+  __shared__ int slen[CLS ? kMaxCls : 1];
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+  if (CLS) {
+    stage_forms<double>(a.op, sd, sct, slen);
+  } else if (PK) {
+    if (threadIdx.x < a.op.ndict) sd[threadIdx.x] = a.op.vdict[threadIdx.x];
+    __syncthreads();
+  }
   double v[3] = {0.0, 0.0, 0.0};
   for (int64_t s = wave; s < a.op.nslices; s += nw) {
     const int64_t row = s * kSlice + lane;
     if (row >= a.N) continue;
-    const double Lx = PK ? sell_row_pk<double>(a.op, s, lane, row, a.Tprev, sd)
-                         : sell_row<D16>(a.op, s, lane, row, a.Tprev);
+    const double Lx =
+        CLS ? sell_row_cls<double>(a.op, row, a.op.rcls[row], a.Tprev, sd, sct, slen)
+        : PK ? sell_row_pk<double>(a.op, s, lane, row, a.Tprev, sd)
+             : sell_row<D16>(a.op, s, lane, row, a.Tprev);
     const double x0 = a.Tprev[row], mi = a.mass[row];
     double b = mi * x0 + a.dtau * a.g[row];
     double Ax = mi * x0 + a.dtau * Lx;
@@ -1093,7 +1163,8 @@ static void solve_reduce(const DevState &d, int slot, int mode, double rtol, int
 void launch_init_pred(const DevState &d, int m, int slot, double rtol, hipStream_t st) {
   CgArgs<double> a = cg64(d, m, slot);
   if (a.ifc_lin) launch_iface_lin(d, m, d.T[m - 1], st);  // coupling of A x0 and its source
-  if (d.op.pk16) k_init_pred<true, true><<<d.grid, kBlock, 0, st>>>(a);
+  if (d.op.rcls) k_init_pred<true, false, true><<<d.grid, kBlock, 0, st>>>(a);
+  else if (d.op.pk16) k_init_pred<true, true><<<d.grid, kBlock, 0, st>>>(a);
   else if (d.op.d16) k_init_pred<true><<<d.grid, kBlock, 0, st>>>(a);
   else k_init_pred<false><<<d.grid, kBlock, 0, st>>>(a);
   (void)rtol;  // the solve's scalars are formed by its first operator step
@@ -1187,7 +1258,8 @@ static CgArgs<double> stationary_args(const DevState &d, const double *zeros, co
 void launch_stationary_init(const DevState &d, const double *zeros, const double *dinv, int slot,
                             double rtol, hipStream_t st) {
   const CgArgs<double> a = stationary_args(d, zeros, dinv, slot);
-  if (d.op.pk16) k_init_pred<true, true><<<d.grid, kBlock, 0, st>>>(a);
+  if (d.op.rcls) k_init_pred<true, false, true><<<d.grid, kBlock, 0, st>>>(a);
+  else if (d.op.pk16) k_init_pred<true, true><<<d.grid, kBlock, 0, st>>>(a);
   else if (d.op.d16) k_init_pred<true><<<d.grid, kBlock, 0, st>>>(a);
   else k_init_pred<false><<<d.grid, kBlock, 0, st>>>(a);
   solve_reduce(d, slot, 0, rtol, 0, false, st);
