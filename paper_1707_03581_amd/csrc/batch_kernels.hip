@@ -409,9 +409,13 @@ __global__ __launch_bounds__(kBlock) void kb_f_multi(BatchArgs a, int j0, int j1
 // ---------------------------------------------------------------------------
 // I_{m-1}^m for all m and the residual per scenario (max-norm)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void kb_quad_resid(BatchArgs a) {
+// (weights as a restrict-qualified parameter, read through the scalar cache;
+// every operand of a row is loaded, at clamped node indices, before the
+// row's first store)
+__global__ __launch_bounds__(kBlock) void kb_quad_resid(BatchArgs a,
+                                                        const Weights *__restrict__ wp) {
   const int s = threadIdx.x & 63, S = a.S;
-  const Weights &w = *a.w;
+  const Weights &w = *wp;
   const int P1 = a.P + 1;
   double rmax = 0.0;
   if (s < S) {
@@ -419,18 +423,34 @@ __global__ __launch_bounds__(kBlock) void kb_quad_resid(BatchArgs a) {
       const int64_t i = row * S + s;
       const double mi = a.mass[row], Tn = a.T[0][i];
       const int pos = a.ifpos ? a.ifpos[row] : -1;
-      double cum = 0.0;
-      for (int m = 1; m <= a.M; ++m) {
-        if (w.dtau[m] == 0.0) continue;
-        double acc = 0.0;
-        for (int j = 1; j <= a.M; ++j) acc += w.s[m][j] * a.F[j][i];
+      double F[kMaxM + 1], T[kMaxM + 1], acc[kMaxM + 1];
+#pragma unroll
+      for (int j = 1; j <= kMaxM; ++j) {
+        const int jj = j <= a.M ? j : 1;
+        const double f = a.F[jj][i], t = a.T[jj][i];
+        F[j] = j <= a.M ? f : 0.0;
+        T[j] = j <= a.M ? t : 0.0;
+      }
+#pragma unroll
+      for (int m = 1; m <= kMaxM; ++m) {
+        acc[m] = 0.0;
+        if (m > a.M || w.dtau[m] == 0.0) continue;
+#pragma unroll
+        for (int j = 1; j <= kMaxM; ++j)
+          if (j <= a.M) acc[m] += w.s[m][j] * F[j];
         if (pos >= 0) {
           const double *E = a.Eold + ((size_t)m * P1 * a.n_if + pos) * S + s;
-          for (int q = 1; q <= a.P; ++q) acc += w.shat[m][q] * E[(size_t)q * a.n_if * S];
+#pragma unroll 4
+          for (int q = 1; q <= a.P; ++q) acc[m] += w.shat[m][q] * E[(size_t)q * a.n_if * S];
         }
-        a.I[m][i] = acc;
-        cum += acc;
-        rmax = fmax(rmax, fabs(mi * a.T[m][i] - mi * Tn - cum));
+      }
+      double cum = 0.0;
+#pragma unroll
+      for (int m = 1; m <= kMaxM; ++m) {
+        if (m > a.M || w.dtau[m] == 0.0) continue;
+        a.I[m][i] = acc[m];
+        cum += acc[m];
+        rmax = fmax(rmax, fabs(mi * T[m] - mi * Tn - cum));
       }
     }
   }
@@ -829,16 +849,36 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_c(BatchArgs a, double dtau, int
       beta[j] = on[j] ? (V)a.sc->beta[s0 + j] : (V)0;
     }
     if (!any) return;
-    for (int64_t k = k0; k < nvec; k += (int64_t)gridDim.x * kBlock) {
-      const int64_t row = (k * VEC) >> lshift;
-      V4 pv = reinterpret_cast<V4 *>(p)[k];
-      const V4 r4 = reinterpret_cast<const V4 *>(rv)[k];
-      V *pp = reinterpret_cast<V *>(&pv);
-      const V *rr = reinterpret_cast<const V *>(&r4);
+    // kRowsAhead vectors per pass, every load of the pass issued before the
+    // first use
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t k = k0; k < nvec; k += kRowsAhead * stride) {
+      V4 pv[kRowsAhead], r4[kRowsAhead];
+      double ms[kRowsAhead], kd[kRowsAhead], rd[kRowsAhead];
 #pragma unroll
-      for (int j = 0; j < VEC; ++j)
-        if (on[j]) pp[j] = pupdate((V)bdinv(a, row, h[j], dtau), rr[j], beta[j], pp[j]);
-      reinterpret_cast<V4 *>(p)[k] = pv;
+      for (int u = 0; u < kRowsAhead; ++u) {
+        const int64_t kk = k + u * stride;
+        if (kk >= nvec) continue;
+        const int64_t row = (kk * VEC) >> lshift;
+        pv[u] = reinterpret_cast<V4 *>(p)[kk];
+        r4[u] = reinterpret_cast<const V4 *>(rv)[kk];
+        ms[u] = a.mass[row];
+        kd[u] = a.Kd[row];
+        rd[u] = a.Rd[row];
+      }
+#pragma unroll
+      for (int u = 0; u < kRowsAhead; ++u) {
+        const int64_t kk = k + u * stride;
+        if (kk >= nvec) continue;
+        V *pp = reinterpret_cast<V *>(&pv[u]);
+        const V *rr = reinterpret_cast<const V *>(&r4[u]);
+#pragma unroll
+        for (int j = 0; j < VEC; ++j)
+          if (on[j])  // the diagonal inverse of bdinv, from the loaded row data
+            pp[j] = pupdate((V)(1.0 / (ms[u] + dtau * (kd[u] + h[j] * rd[u]))), rr[j], beta[j],
+                            pp[j]);
+        reinterpret_cast<V4 *>(p)[kk] = pv[u];
+      }
     }
     return;
   }
@@ -1195,7 +1235,7 @@ void blaunch_f_multi(const BatchArgs &a, int j0, int j1, hipStream_t st) {
 }
 
 void blaunch_quad_resid(const BatchArgs &a, int k, hipStream_t st) {
-  kb_quad_resid<<<a.grid, kBlock, 0, st>>>(a);
+  kb_quad_resid<<<a.grid, kBlock, 0, st>>>(a, a.w);
   kb_resid_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, k);
 }
 
