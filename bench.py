@@ -353,7 +353,8 @@ def deformation_form(pkg, args):
             "solve_per_macro_step": solve_us / 1e3 / step_ms,
             "max_displacement_um": float(np.abs(u).max() * 1e6),
             "relative_residual": res,
-            "roofline": {"bound": "hbm", "kernel": "k_gemv (dense block product)",
+            "roofline": {"bound": "hbm",
+                         "kernel": "k_symv + k_symv_reduce (symmetric block product, upper-triangle tiles)",
                          "achieved": gbps, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": gbps / HBM_PEAK_GBS, "avg_launch_us": gemv_us,
                          "bytes_per_launch": gemv_bytes, "traffic": None}}

@@ -2071,6 +2071,24 @@ mrsdc_status mrsdc_deform_setup(mrsdc_ctx *c, int body, int64_t n, int64_t nnz,
   D.w = vec[1];
   D.x = vec[2];
   D.c = vec[3];
+  {  // strips of the symmetric block product and its partials
+    const int nt = D.tiles();
+    std::vector<int> strip;
+    for (int I = 0; I < nt; ++I)
+      for (int J0 = I; J0 < nt; J0 += kSymStrip) {
+        strip.push_back(I);
+        strip.push_back(J0);
+      }
+    D.nstrip = (int)(strip.size() / 2);
+    const int *sp = nullptr;
+    if ((st = df_upload(c, &sp, strip.data(), strip.size()))) { df_release(c); return st; }
+    D.strip = sp;
+    if ((st = df_alloc_bytes(c, &q, sizeof(double) * 64 * (size_t)nt * D.slots()))) {
+      df_release(c);
+      return st;
+    }
+    D.part = (double *)q;
+  }
   auto t0 = std::chrono::steady_clock::now();
   deform_factor(D, c->stream);
   he = hipGetLastError();
@@ -2167,9 +2185,12 @@ mrsdc_status mrsdc_deform_time(mrsdc_ctx *c, int reps, double *solve_us, double 
       float m = 0.f;
       HIPCHK(hipEventElapsedTime(&m, ev[2 * g], ev[2 * g + 1]));
       gsum += 1e3 * m;
-      // forward k = g, backward k = 2 nblk - 2 - g: W rows read in full, v, out (+ base)
+      // forward k = g, backward k = 2 nblk - 2 - g: the upper-triangle tiles of
+      // W, v, the partials written and read back, out (+ base)
       const int64_t k = g < D.nblk ? g : 2 * D.nblk - 2 - g;
-      bytes += D.rows(k) * D.bp * 8 + D.bp * 8 + D.rows(k) * 8 * (g < D.nblk ? 1 : 2);
+      const int64_t nt = D.tiles(), nparts = nt * (nt - 1) / 2 + D.nstrip;
+      bytes += nt * (nt + 1) / 2 * 64 * 64 * 8 + D.bp * 8 + 2 * nparts * 64 * 8 +
+               D.rows(k) * 8 * (g < D.nblk ? 1 : 2);
     }
     *gemv_us = gsum / ng;
     *gemv_bytes = bytes / ng;

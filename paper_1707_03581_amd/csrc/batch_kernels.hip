@@ -651,17 +651,38 @@ __global__ __launch_bounds__(kBlock) void kb_refine_update(BatchArgs a, int m, d
 // One workgroup per scenario s = blockIdx.x; np = workgroups of the
 // producing kernel, whose partials of scenario s are contiguous.  Fixed-order
 // sums: thread j adds blocks j, j + 256, ..., then a fixed halving tree.
+constexpr int kBatchMaxGrid = 1024;  // workgroups of the batched row kernels
+
 __global__ __launch_bounds__(kBlock) void kb_reduce(BatchArgs a, int np, int mode, int it,
                                                     int last, int slot, double rtol) {
   __shared__ double sh[3][kBlock];
   const int s = blockIdx.x, j = threadIdx.x;
   BatchScalars *sc = a.sc;
   const int nk = mode == 0 ? 3 : ((mode == 1 || mode == 5) ? 1 : 2);
-  for (int k = 0; k < nk; ++k) {
-    const double *pp = a.partial + ((size_t)k * a.S + s) * np;
-    double acc = 0.0;
-    for (int b = j; b < np; b += kBlock) acc += pp[b];
-    sh[k][j] = acc;
+  if (np <= kBatchMaxGrid) {  // every partial requested before the first sum
+    constexpr int kq = kBatchMaxGrid / kBlock;
+    double t[3][kq];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int q = 0; q < kq; ++q) {
+        const int b = j + q * kBlock;
+        t[k][q] = (k < nk && b < np) ? a.partial[((size_t)k * a.S + s) * np + b] : 0.0;
+      }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < kq; ++q) acc += t[k][q];
+      if (k < nk) sh[k][j] = acc;
+    }
+  } else {
+    for (int k = 0; k < nk; ++k) {
+      const double *pp = a.partial + ((size_t)k * a.S + s) * np;
+      double acc = 0.0;
+      for (int b = j; b < np; b += kBlock) acc += pp[b];
+      sh[k][j] = acc;
+    }
   }
   __syncthreads();
   for (int h = kBlock / 2; h > 0; h >>= 1) {

@@ -9,6 +9,7 @@ namespace mrsdc {
 
 constexpr int kGjTile = 64;              // Gauss-Jordan pivot width and tile size
 constexpr int64_t kMaxDeformBlock = 8192;  // padded block: one row of it in LDS (64 KB)
+constexpr int kSymStrip = 4;               // tiles per workgroup of the symmetric block product
 
 struct DeformDev {
   int64_t n = 0;     // free displacement DOFs
@@ -40,6 +41,17 @@ struct DeformDev {
   double *w = nullptr;    // [n] forward results W_k c_k
   double *x = nullptr;    // [n] displacement
   double *c = nullptr;    // [bp] block right-hand side
+  // symmetric block product over the upper triangle of 64 x 64 tiles: one
+  // workgroup per strip of kSymStrip tiles of a tile row, strip[2 b] = tile
+  // row, strip[2 b + 1] = first tile column; part[K][slot][64] holds the
+  // contributions to output tile K (slots 0..K-1: the transposed tiles (I, K)
+  // of the rows above, slots nt + s: strip s of tile row K)
+  const int *strip = nullptr;
+  int nstrip = 0;
+  double *part = nullptr;
+
+  __host__ __device__ int tiles() const { return (int)(bp / 64); }
+  __host__ __device__ int slots() const { return tiles() + (tiles() + kSymStrip - 1) / kSymStrip; }
 
   __host__ __device__ int64_t lo(int64_t k) const { return k * bs; }
   __host__ __device__ int64_t rows(int64_t k) const { return (k + 1) * bs < n ? bs : n - k * bs; }

@@ -306,53 +306,102 @@ __global__ __launch_bounds__(kThreads) void k_bwd_rhs(DeformDev D, int64_t k) {
   if (sub == 0) D.c[i] = a;
 }
 
-// Dense block product: MODE 0 out = W v, MODE 1 out = base - W v; ld is a
-// multiple of 64.  A wavefront forms kGemvRows rows; W is streamed once with
-// non-temporal loads, the vector (one block, L2-resident) is read through the
-// caches and shared by the rows.
-constexpr int kGemvRows = 4;
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+static_assert(kThreads == 256, "k_symv maps 16 x 16 threads onto a 64 x 64 tile");
+
+__global__ __launch_bounds__(kThreads) void k_symv(const double *W, int64_t ld, int nt, int ns,
+                                                   const int *strip, const double *v,
+                                                   double *part) {
+  __shared__ double shc[kSymStrip][kThreads / 64][64];
+  const int I = strip[2 * blockIdx.x], J0 = strip[2 * blockIdx.x + 1];
+  const int J1 = J0 + kSymStrip < nt ? J0 + kSymStrip : nt;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, cg = t & 15, rg = t >> 4;
+  double vi[4], rs[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) vi[q] = v[I * 64 + rg * 4 + q];
+  const double *rowp = W + (int64_t)(I * 64 + rg * 4) * ld + cg * 4;
+  for (int J = J0; J < J1; ++J) {
+    double a[4][4], vj[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const dvec2 lo =
+          __builtin_nontemporal_load(reinterpret_cast<const dvec2 *>(rowp + (int64_t)q * ld + J * 64));
+      const dvec2 hi = __builtin_nontemporal_load(
+          reinterpret_cast<const dvec2 *>(rowp + (int64_t)q * ld + J * 64 + 2));
+      a[q][0] = lo[0];
+      a[q][1] = lo[1];
+      a[q][2] = hi[0];
+      a[q][3] = hi[1];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) vj[k] = v[J * 64 + cg * 4 + k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) rs[q] = fma(a[q][k], vj[k], rs[q]);
+    if (J > I) {
+      double cs[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        double c = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c = fma(a[q][k], vi[q], c);
+        c += __shfl_xor(c, 16, 64);
+        c += __shfl_xor(c, 32, 64);
+        cs[k] = c;
+      }
+      if (lane < 16)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) shc[J - J0][w][cg * 4 + k] = cs[k];
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < (J1 - J0) * 64; i += kThreads) {
+    const int tj = i >> 6, c = i & 63, J = J0 + tj;
+    if (J > I)
+      part[((int64_t)J * ns + I) * 64 + c] =
+          ((shc[tj][0][c] + shc[tj][1][c]) + shc[tj][2][c]) + shc[tj][3][c];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double r = rs[q];
+    r += __shfl_xor(r, 1, 64);
+    r += __shfl_xor(r, 2, 64);
+    r += __shfl_xor(r, 4, 64);
+    r += __shfl_xor(r, 8, 64);
+    rs[q] = r;
+  }
+  if (cg == 0) {
+    const int sidx = nt + (J0 - I) / kSymStrip;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) part[((int64_t)I * ns + sidx) * 64 + rg * 4 + q] = rs[q];
+  }
+}
+
+// out = W v (MODE 0) or base - W v (MODE 1) for the first rows of output
+// tile K = blockIdx.x: the transposed contributions of tile rows 0..K-1, then
+// the strips of tile row K, in that order; 4 thread groups take every 4th
+// slot, summed in group order.
 template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_gemv(const double *W, int64_t ld, int64_t rows,
-                                                   const double *v, double *out,
-                                                   const double *base) {
-  constexpr int RW = kGemvRows;
-  const int lane = threadIdx.x & 63;
-  const int64_t r0 = ((int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) * RW;
-  if (r0 >= rows) return;
-  const double *wr[RW];
-#pragma unroll
-  for (int q = 0; q < RW; ++q) wr[q] = W + (r0 + q < rows ? r0 + q : rows - 1) * ld;
-  double acc[RW][4];
-#pragma unroll
-  for (int q = 0; q < RW; ++q)
-#pragma unroll
-    for (int u = 0; u < 4; ++u) acc[q][u] = 0.0;
-  int64_t j = lane;
-  for (; j + 3 * 64 < ld; j += 4 * 64) {
-    double vv[4], x[RW][4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) vv[u] = v[j + 64 * u];
-#pragma unroll
-    for (int q = 0; q < RW; ++q)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) x[q][u] = __builtin_nontemporal_load(wr[q] + j + 64 * u);
-#pragma unroll
-    for (int q = 0; q < RW; ++q)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc[q][u] = fma(x[q][u], vv[u], acc[q][u]);
+__global__ __launch_bounds__(kThreads) void k_symv_reduce(const double *part, int nt, int ns,
+                                                          int64_t rows, double *out,
+                                                          const double *base) {
+  __shared__ double sg[kThreads / 64][64];
+  const int K = blockIdx.x, c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int nsK = (nt - K + kSymStrip - 1) / kSymStrip;
+  const int n = K + nsK;
+  double acc = 0.0;
+#pragma unroll 8
+  for (int j = g; j < n; j += kThreads / 64) {
+    const int slot = j < K ? j : nt + (j - K);
+    acc += part[((int64_t)K * ns + slot) * 64 + c];
   }
-  for (; j < ld; j += 64) {
-    const double vv = v[j];
-#pragma unroll
-    for (int q = 0; q < RW; ++q) acc[q][0] = fma(__builtin_nontemporal_load(wr[q] + j), vv, acc[q][0]);
-  }
-#pragma unroll
-  for (int q = 0; q < RW; ++q) {
-    double sq = (acc[q][0] + acc[q][1]) + (acc[q][2] + acc[q][3]);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off, 64);
-    if (lane == 0 && r0 + q < rows) out[r0 + q] = MODE == 0 ? sq : base[r0 + q] - sq;
-  }
+  sg[g][c] = acc;
+  __syncthreads();
+  if (g != 0) return;
+  const double y = ((sg[0][c] + sg[1][c]) + sg[2][c]) + sg[3][c];
+  const int64_t r = (int64_t)K * 64 + c;
+  if (r < rows) out[r] = MODE == 0 ? y : base[r] - y;
 }
 
 __global__ __launch_bounds__(kThreads) void k_copy(double *dst, const double *src, int64_t n) {
@@ -393,17 +442,21 @@ void deform_solve(const DeformDev &D, const double *T, hipStream_t st, hipEvent_
   k_thermal_load<<<blocks_for(D.n), kThreads, 0, st>>>(D, T);
   const unsigned cb = (unsigned)((D.bp * kSub + kThreads - 1) / kThreads);
   int g = 0;
+  // block product: the symmetric form over the upper triangle, then its
+  // fixed-order reduction (with events: the pair is timed as one product)
   auto gemv = [&](int mode, int64_t k, double *out, const double *base) {
     const double *W = D.W + k * D.bp * D.bp;
     const int64_t rows = D.rows(k);
-    const int64_t per = (kThreads / 64) * kGemvRows;
-    const unsigned grid = (unsigned)((rows + per - 1) / per);
-    auto kern = mode == 0 ? k_gemv<0> : k_gemv<1>;
+    const int nt = D.tiles(), ns = D.slots();
+    auto red = mode == 0 ? k_symv_reduce<0> : k_symv_reduce<1>;
     if (ev) {
-      hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, ev[2 * g], ev[2 * g + 1],
-                            0, W, D.bp, rows, (const double *)D.c, out, base);
+      hipExtLaunchKernelGGL(k_symv, dim3(D.nstrip), dim3(kThreads), 0, st, ev[2 * g], nullptr, 0,
+                            W, D.bp, nt, ns, D.strip, (const double *)D.c, D.part);
+      hipExtLaunchKernelGGL(red, dim3(nt), dim3(kThreads), 0, st, nullptr, ev[2 * g + 1], 0,
+                            (const double *)D.part, nt, ns, rows, out, base);
     } else {
-      kern<<<grid, kThreads, 0, st>>>(W, D.bp, rows, D.c, out, base);
+      k_symv<<<D.nstrip, kThreads, 0, st>>>(W, D.bp, nt, ns, D.strip, D.c, D.part);
+      red<<<nt, kThreads, 0, st>>>(D.part, nt, ns, rows, out, base);
     }
     ++g;
   };
