@@ -40,6 +40,11 @@ __device__ inline RowRange xcd_rows(int64_t N) {
   r.stride = (int64_t)per * (kBlock / 64);
   return r;
 }
+// The row-parallel updates take the wave's rows (the FOR_ROWS sequence)
+// kRowsAhead at a time, every load of the group issued before the first use;
+// rows are still accumulated in sequence order.
+constexpr int kRowsAhead = 4;
+
 #define FOR_ROWS(row, N)                  \
   for (RowRange rr_ = xcd_rows(N); rr_.row < rr_.end; rr_.row += rr_.stride) \
     if (const int64_t row = rr_.row; true)
@@ -593,15 +598,29 @@ __global__ __launch_bounds__(kBlock) void kb_inner_init(BatchArgs a, double dtau
   double v[2] = {0.0, 0.0};
   if (sweeping(a.sc, s, S) && !a.sc->ref_done[s]) {
     const double h = a.h[s];
-    FOR_ROWS(row, a.N) {
-      const int64_t i = row * S + s;
-      const float r = (float)a.r64[i];
-      const float z = (float)bdinv(a, row, h, dtau) * r;
-      a.r32[i] = r;
-      a.x32[i] = 0.0f;
-      a.p32[i] = z;
-      v[0] += (double)r * (double)z;
-      v[1] += (double)r * (double)r;
+    // kRowsAhead rows per pass, their loads issued before the first store
+    for (RowRange rr = xcd_rows(a.N); rr.row < rr.end; rr.row += kRowsAhead * rr.stride) {
+      double r64[kRowsAhead], di[kRowsAhead];
+#pragma unroll
+      for (int u = 0; u < kRowsAhead; ++u) {
+        const int64_t row = rr.row + u * rr.stride;
+        if (row >= rr.end) continue;
+        r64[u] = a.r64[row * S + s];
+        di[u] = bdinv(a, row, h, dtau);
+      }
+#pragma unroll
+      for (int u = 0; u < kRowsAhead; ++u) {
+        const int64_t row = rr.row + u * rr.stride;
+        if (row >= rr.end) continue;
+        const int64_t i = row * S + s;
+        const float r = (float)r64[u];
+        const float z = (float)di[u] * r;
+        a.r32[i] = r;
+        a.x32[i] = 0.0f;
+        a.p32[i] = z;
+        v[0] += (double)r * (double)z;
+        v[1] += (double)r * (double)r;
+      }
     }
   }
   bpublish<2>(v, a.partial, gridDim.x, S);
@@ -787,10 +806,6 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_a(BatchArgs a, int m, double dt
   publish_lanes<1>(v, a.partial, gridDim.x, S, L);
 }
 
-// The row-parallel CG updates take the wave's rows (the FOR_ROWS sequence)
-// four at a time, every load of the four issued before the first use; rows
-// are still accumulated in sequence order.
-constexpr int kRowsAhead = 4;
 
 // (b) x += alpha p; r -= alpha q; partial r.z, r.r
 template <typename V>
