@@ -1045,7 +1045,8 @@ int enqueue_cg(mrsdc_ctx *c, int slot, int m, bool fp32, bool defer = false) {
     const bool tail = it >= c->expect[slot];
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (!tail) take_events(c, 0, &e0, &e1);
-    if (fp32) launch_pcg32_iter(d, m, slot, it, it == B - 1, tail, c->stream, e0, e1);
+    if (fp32)
+      launch_pcg32_iter(d, m, slot, it, it == B - 1, tail, c->cfg.inner_rtol, c->stream, e0, e1);
     else launch_pcg_iter(d, m, slot, it, it == B - 1, tail, c->cfg.pcg_rtol, c->stream, e0, e1);
   }
   if (!defer) launch_pcg_final(d, m, slot, B, fp32, c->stream);

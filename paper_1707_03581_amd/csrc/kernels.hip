@@ -378,9 +378,10 @@ struct CgArgs {
   SolveScalars *sc;
   StepCounters *ctr;
   int slot, grid, inner;
-  // > 0: the first operator step of a single-reduction solve also forms the
-  // solve's scalars from the init kernel's partials (r.z, r.r, b.b) with this
-  // relative tolerance, in place of a separate reduction launch
+  // init_fold: the first operator step of a single-reduction solve also forms
+  // the solve's scalars from the init kernel's partials (r.z, r.r, b.b) with
+  // the relative tolerance init_rtol, in place of a separate reduction launch
+  int init_fold;
   double init_rtol;
   // residual-controlled sweeps: test the stop flag before anything else, so
   // the launches of sweeps that are no longer run return at once
@@ -673,7 +674,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
   // fresh: the first operator step of a solve, which forms the solve's
   // scalars from the init kernel's partials (r.z, r.r, b.b) and reads none of
   // the previous solve's flags; check: the convergence test on ||r_it||^2
-  const bool fresh = CG2 && TAIL != 2 && it == 0 && a.init_rtol > 0.0;
+  const bool fresh = CG2 && TAIL != 2 && it == 0 && a.init_fold;
   const bool check = CG2 && TAIL != 2 && it > 0;
   const R *__restrict__ xin = CG2 ? a.u : a.p;
   const int lane = threadIdx.x & 63;
@@ -684,8 +685,9 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
   // wait: the solve flags, the partials of the reductions, the table entries
   // and the first slice's row data.
   int stop = 0;
-  if (TAIL != 2)
-    stop = fresh ? a.ctr->stop : (a.sc->done | a.sc->ref_done | a.ctr->stop);
+  if (TAIL != 2)  // (an inner solve of the refinement also ends with its refinement)
+    stop = fresh ? (a.ctr->stop | (a.inner ? a.sc->ref_done : 0))
+                 : (a.sc->done | a.sc->ref_done | a.ctr->stop);
   // (loaded first, summed afterwards; a term past the grid is an exact zero)
   double t0[kPart], t1[kPart], t2[kPart];
 #pragma unroll
@@ -746,8 +748,10 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
     double rr = s1, bb = s2;
     block_sum2(rr, bb, sh);
     const double o[3] = {block_sum(rz, sh), rr, bb};
-    if (blockIdx.x == 0 && threadIdx.x == 0) init_finish(a.sc, a.ctr, a.slot, 0, a.init_rtol, o);
-    if (rr <= a.init_rtol * a.init_rtol * bb) return;  // the warm start meets the tolerance
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+      init_finish(a.sc, a.ctr, a.slot, a.inner, a.init_rtol, o);
+    // the warm start meets the tolerance (an inner solve: a zero right-hand side)
+    if (a.inner ? rr == 0.0 : rr <= a.init_rtol * a.init_rtol * bb) return;
   } else if (check) {
     const double rr = block_sum(s0, sh);
     if (rr <= a.sc->tol2) {
@@ -1054,13 +1058,34 @@ __device__ inline double sell_row_pk_mixed(const SellDev &op, int64_t s, int lan
   return acc;
 }
 
+// FP64 operator on an FP32 vector through the row forms (the same products
+// and order as the packed entries)
+__device__ inline double sell_row_cls_mixed(const SellDev &op, int64_t row, int c,
+                                            const float *__restrict__ x, const double *sd,
+                                            const int *sct, const int *slen) {
+  const int n = slen[c];
+  const int *t = sct + c * op.cw;
+  double acc = 0.0;
+#pragma unroll 8
+  for (int k = 0; k < n; ++k) {
+    const int w = t[k];
+    acc += sd[w & 255] * (double)x[row + (w >> 8)];
+  }
+  return acc;
+}
+
 // x64 += d; r64 -= A d (FP64 operator); ||r64|| -> refinement converged?
-template <bool D16, bool PK = false>
+// CLS: row forms (tables staged once per block)
+template <bool D16, bool PK = false, bool CLS = false>
 __global__ __launch_bounds__(kBlock) void k_refine_update(CgArgs<float> a, const double *mass64) {
   if (a.sc->ref_done || a.ctr->stop) return;
   __shared__ double sh[17];
-  __shared__ double sd[PK ? 16 : 1];
-  if (PK) {
+  __shared__ double sd[CLS ? kDictMax : (PK ? 16 : 1)];
+  __shared__ int sct[CLS ? kMaxCls * kMaxClsWidth : 1];
+  __shared__ int slen[CLS ? kMaxCls : 1];
+  if (CLS) {
+    stage_forms<double>(a.op, sd, sct, slen);
+  } else if (PK) {
     if (threadIdx.x < a.op.ndict) sd[threadIdx.x] = a.op.vdict[threadIdx.x];
     __syncthreads();
   }
@@ -1072,8 +1097,9 @@ __global__ __launch_bounds__(kBlock) void k_refine_update(CgArgs<float> a, const
     const int64_t row = s * kSlice + lane;
     if (row >= a.N) continue;
     const double d = (double)a.x[row];
-    const double Ld = PK ? sell_row_pk_mixed(a.op, s, lane, row, a.x, sd)
-                         : sell_row_mixed<D16>(a.op, s, lane, row, a.x);
+    const double Ld = CLS  ? sell_row_cls_mixed(a.op, row, a.op.rcls[row], a.x, sd, sct, slen)
+                      : PK ? sell_row_pk_mixed(a.op, s, lane, row, a.x, sd)
+                           : sell_row_mixed<D16>(a.op, s, lane, row, a.x);
     const double Ad = mass64[row] * d + a.dtau * Ld;
     a.x64[row] += d;
     const double r = a.r64[row] - Ad;
@@ -1085,6 +1111,7 @@ __global__ __launch_bounds__(kBlock) void k_refine_update(CgArgs<float> a, const
 
 static CgArgs<double> cg64(const DevState &d, int m, int slot) {
   CgArgs<double> a;
+  a.init_fold = 0;
   a.init_rtol = 0.0;
   a.early_stop = d.sweep_tol > 0.0 ? 1 : 0;
   a.op = d.op;
@@ -1121,6 +1148,7 @@ static CgArgs<double> cg64(const DevState &d, int m, int slot) {
 
 static CgArgs<float> cg32(const DevState &d, int m, int slot) {
   CgArgs<float> a;
+  a.init_fold = 0;
   a.init_rtol = 0.0;
   a.early_stop = d.sweep_tol > 0.0 ? 1 : 0;
   a.op = d.op;
@@ -1228,6 +1256,7 @@ void launch_pcg_iter(const DevState &d, int m, int slot, int it, bool last, bool
                      double rtol, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   (void)last;  // the budget's end is judged by launch_pcg_final
   CgArgs<double> a = cg64(d, m, slot);
+  a.init_fold = 1;
   a.init_rtol = rtol;
   pcg2_iter(d, a, it, tail, st, ev0, ev1);
 }
@@ -1317,19 +1346,23 @@ void launch_refine_init(const DevState &d, int m, int slot, bool pred, double rt
 
 void launch_inner_init(const DevState &d, int m, int slot, double inner_rtol, hipStream_t st) {
   k_inner_init<<<d.grid, kBlock, 0, st>>>(cg32(d, m, slot));
-  solve_reduce(d, slot, 2, inner_rtol, 0, false, st);
+  (void)inner_rtol;  // the inner solve's scalars are formed by its first operator step
 }
 
 void launch_pcg32_iter(const DevState &d, int m, int slot, int it, bool last, bool tail,
-                       hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                       double inner_rtol, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   (void)last;
-  pcg2_iter(d, cg32(d, m, slot), it, tail, st, ev0, ev1);
+  CgArgs<float> a = cg32(d, m, slot);
+  a.init_fold = 1;
+  a.init_rtol = inner_rtol;
+  pcg2_iter(d, a, it, tail, st, ev0, ev1);
 }
 
 void launch_refine_update(const DevState &d, int m, int slot, int round, bool last_round,
                           hipStream_t st) {
   CgArgs<float> a = cg32(d, m, slot);
-  if (d.op.pk16) k_refine_update<true, true><<<d.grid, kBlock, 0, st>>>(a, d.mass);
+  if (d.op.rcls) k_refine_update<true, false, true><<<d.grid, kBlock, 0, st>>>(a, d.mass);
+  else if (d.op.pk16) k_refine_update<true, true><<<d.grid, kBlock, 0, st>>>(a, d.mass);
   else if (d.op.d16) k_refine_update<true><<<d.grid, kBlock, 0, st>>>(a, d.mass);
   else k_refine_update<false><<<d.grid, kBlock, 0, st>>>(a, d.mass);
   solve_reduce(d, slot, 3, 0.0, round, last_round, st);

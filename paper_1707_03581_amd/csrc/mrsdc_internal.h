@@ -199,7 +199,8 @@ void launch_refine_init(const DevState &d, int m, int slot, bool pred, double rt
                         hipStream_t st);
 void launch_inner_init(const DevState &d, int m, int slot, double inner_rtol, hipStream_t st);
 void launch_pcg32_iter(const DevState &d, int m, int slot, int it, bool last, bool tail,
-                       hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                       double inner_rtol, hipStream_t st, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr);
 void launch_refine_update(const DevState &d, int m, int slot, int round, bool last_round,
                           hipStream_t st);
 void launch_operator_timing(const DevState &d, int m, bool fp32, int reps, hipStream_t st);
