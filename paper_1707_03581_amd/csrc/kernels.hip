@@ -688,7 +688,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
   if (TAIL != 2)  // (an inner solve of the refinement also ends with its refinement)
     stop = fresh ? (a.ctr->stop | (a.inner ? a.sc->ref_done : 0))
                  : (a.sc->done | a.sc->ref_done | a.ctr->stop);
-  // (loaded first, summed afterwards; a term past the grid is an exact zero)
+  // (loaded first at clamped indices, summed afterwards over the valid ones)
   double t0[kPart], t1[kPart], t2[kPart];
 #pragma unroll
   for (int q = 0; q < kPart; ++q) t0[q] = t1[q] = t2[q] = 0.0;
@@ -697,17 +697,16 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
 #pragma unroll
     for (int q = 0; q < kPart; ++q) {
       const int j = (int)threadIdx.x + q * kBlock;
-      if (j < a.grid) t0[q] = p0[j];
+      t0[q] = p0[j < a.grid ? j : a.grid - 1];
     }
   }
   if (fresh) {
 #pragma unroll
     for (int q = 0; q < kPart; ++q) {
       const int j = (int)threadIdx.x + q * kBlock;
-      if (j < a.grid) {
-        t1[q] = a.partial[a.grid + j];
-        t2[q] = a.partial[2 * a.grid + j];
-      }
+      const int jc = j < a.grid ? j : a.grid - 1;
+      t1[q] = a.partial[a.grid + jc];
+      t2[q] = a.partial[2 * a.grid + jc];
     }
   }
   int tab[kTab];
@@ -739,9 +738,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
   for (int q = 0; q < kPart; ++q) {
-    s0 += t0[q];
-    s1 += t1[q];
-    s2 += t2[q];
+    if ((int)threadIdx.x + q * kBlock < a.grid) {
+      s0 += t0[q];
+      s1 += t1[q];
+      s2 += t2[q];
+    }
   }
   if (fresh) {
     const double rz = s0;
@@ -819,19 +820,24 @@ __global__ __launch_bounds__(kBlock) void k_cg_upd(CgArgs<R> a, int it) {
     d0 = a.dinv[i0];
   }
   const double *pg = a.partial + ((it & 1) ? 3 : 0) * a.grid, *pd = a.partial + 5 * a.grid;
-  double tg[kMaxGrid / kBlock], td[kMaxGrid / kBlock];  // loaded first, summed afterwards
+  // loaded first at clamped indices (no branch between the loads), summed
+  // afterwards over the valid ones
+  double tg[kMaxGrid / kBlock], td[kMaxGrid / kBlock];
 #pragma unroll
   for (int q = 0; q < kMaxGrid / kBlock; ++q) {
     const int j = (int)threadIdx.x + q * kBlock;
-    tg[q] = j < a.grid ? pg[j] : 0.0;
-    td[q] = j < a.grid ? pd[j] : 0.0;
+    const int jc = j < a.grid ? j : a.grid - 1;
+    tg[q] = pg[jc];
+    td[q] = pd[jc];
   }
   if (stop) return;
   double gam = 0.0, del = 0.0;
 #pragma unroll
   for (int q = 0; q < kMaxGrid / kBlock; ++q) {
-    gam += tg[q];
-    del += td[q];
+    if ((int)threadIdx.x + q * kBlock < a.grid) {
+      gam += tg[q];
+      del += td[q];
+    }
   }
   block_sum2(gam, del, sh);
   SolveScalars *sc = a.sc;
