@@ -1523,20 +1523,25 @@ __device__ inline double tif(const SubArgs &A, const double *Tin, int j) {
 // Every sum adds the same products in the same order as the plain loops
 // (a clamped term adds an exact zero).
 constexpr int kFastBand = 4;
+static_assert(kFastBand <= kBand, "the fast cross band reads kFastBand table entries per point");
 
 template <bool FIRST>
 __device__ inline double self_sum(const SubArgs &A, const double *Tin, const double *wu,
                                   const double *wv, int nu, int nv, int base, int a, int b) {
+  // (the weights are read unconditionally, their tables hold 3 per point,
+  // and masked when used, so no load waits on a branch)
   double w0[3], w1[3];
   int ra[3], cb[3];
+  bool ia[3], ib[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const int aa = a - 1 + q, bb = b - 1 + q;
-    const bool ia = aa >= 0 && aa < nu, ib = bb >= 0 && bb < nv;
-    ra[q] = ia ? aa : a;
-    cb[q] = ib ? bb : b;
-    w0[q] = ia ? wu[3 * a + q] : 0.0;
-    w1[q] = ib ? wv[3 * b + q] : 0.0;
+    ia[q] = aa >= 0 && aa < nu;
+    ib[q] = bb >= 0 && bb < nv;
+    ra[q] = ia[q] ? aa : a;
+    cb[q] = ib[q] ? bb : b;
+    w0[q] = wu[3 * a + q];
+    w1[q] = wv[3 * b + q];
   }
   double t[3][3];
 #pragma unroll
@@ -1548,8 +1553,8 @@ __device__ inline double self_sum(const SubArgs &A, const double *Tin, const dou
   for (int q = 0; q < 3; ++q) {
     double acc = 0.0;
 #pragma unroll
-    for (int r = 0; r < 3; ++r) acc += w1[r] * t[q][r];
-    self += w0[q] * acc;
+    for (int r = 0; r < 3; ++r) acc += (ib[r] ? w1[r] : 0.0) * t[q][r];
+    self += (ia[q] ? w0[q] : 0.0) * acc;
   }
   return self;
 }
@@ -1562,11 +1567,13 @@ __device__ inline double cross_sum(const SubArgs &A, const double *Tin, const do
   double cross = 0.0;
   if (nu <= 0 || nv <= 0) return cross;  // no overlap: the band start may lie off the grid
   if (nu <= kFastBand && nv <= kFastBand) {
+    // (band tables hold kBand >= kFastBand weights per point: read
+    // unconditionally, masked when used)
     double wu[kFastBand], wv[kFastBand], t[kFastBand][kFastBand];
 #pragma unroll
     for (int q = 0; q < kFastBand; ++q) {
-      wu[q] = q < nu ? cu[q] : 0.0;
-      wv[q] = q < nv ? cv[q] : 0.0;
+      wu[q] = cu[q];
+      wv[q] = cv[q];
     }
 #pragma unroll
     for (int q = 0; q < kFastBand; ++q)
@@ -1577,8 +1584,8 @@ __device__ inline double cross_sum(const SubArgs &A, const double *Tin, const do
     for (int q = 0; q < kFastBand; ++q) {
       double acc = 0.0;
 #pragma unroll
-      for (int r = 0; r < kFastBand; ++r) acc += wv[r] * t[q][r];
-      cross += wu[q] * acc;
+      for (int r = 0; r < kFastBand; ++r) acc += (r < nv ? wv[r] : 0.0) * t[q][r];
+      cross += (q < nu ? wu[q] : 0.0) * acc;
     }
     return cross;
   }
