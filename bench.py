@@ -325,8 +325,8 @@ def deformation_form(pkg, args):
     """Thermo-elastic deformation of the benchmark machine's stand (41 x 41 x
     161 nodes, floor clamped, 806,880 displacement DOFs) from its temperature
     after 4 steps: the one-off factorisation, the forward/backward solve per
-    output, and the solve's dominant kernel (dense block product) timed per
-    launch with HIP events against the HBM peak.  The residual
+    output, and the solve's dominant step (the symmetric block product and its
+    partial sums) timed per product with HIP events against the HBM peak.  The residual
     ||K_u u - f|| / ||f|| is checked on the host."""
     from mrsdc_inputs.elastic import elastic_box
     import mrsdc_inputs as mi

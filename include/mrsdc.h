@@ -317,9 +317,11 @@ mrsdc_status mrsdc_deform_get_info(const mrsdc_ctx *ctx, mrsdc_deform_info *out)
 
 /* Run reps forward/backward solves back to back between HIP events on the
  * context's stream: average microseconds per solve, and the average duration
- * of the dense block product u = W_k v (the solve's dominant kernel, timed per
- * launch with its own events) with its algorithmic bytes per launch
- * (padded_block^2 * 8 + vectors).  For roofline measurement. */
+ * of the block product u = W_k v (the solve's dominant step: the symmetric
+ * product over the upper-triangle 64 x 64 tiles of W_k and the fixed-order
+ * sum of its tile partials, timed as one with its own events) with its
+ * algorithmic bytes per product (the upper-triangle tiles, the vectors, and
+ * the partials written and read back).  For roofline measurement. */
 mrsdc_status mrsdc_deform_time(mrsdc_ctx *ctx, int reps, double *solve_us, double *gemv_us,
                                int64_t *gemv_bytes);
 

@@ -290,7 +290,7 @@ class Context:
         return info.as_dict()
 
     def deform_time(self, reps=5):
-        """(microseconds per solve, microseconds per dense block product,
+        """(microseconds per solve, microseconds per symmetric block product,
         algorithmic bytes per block product)."""
         a, b, n = C.c_double(), C.c_double(), C.c_int64()
         self._chk(self._L.mrsdc_deform_time(self._h, reps, C.byref(a), C.byref(b), C.byref(n)))

@@ -3,7 +3,8 @@ forward and backward block solves per output) through the C-ABI.
 
 Bar: relative L2 <= 1e-10 against the oracle's sparse direct solve on meshes
 it solves in milliseconds (several blocks, a ragged last block, padding, a
-single pivot tile), both bodies of a machine, outputs after time steps on one
+single pivot tile, and 7 or 8 tiles of 64 per block, so that the symmetric
+block product has full and ragged strips of tiles), both bodies of a machine, outputs after time steps on one
 factorisation; the closed-form free expansion under uniform heating; and on
 the 270,641-node stand (811,923 DOFs) the relative residual
 ||K_u u - f|| / ||f||, which a backward-stable solve keeps near
@@ -40,7 +41,8 @@ def single(nodes, L=(0.2, 0.25, 0.5), seed=0):
     return pb
 
 
-@pytest.mark.parametrize("nodes", [(5, 6, 9), (2, 2, 3), (7, 5, 12), (4, 4, 2)])
+@pytest.mark.parametrize("nodes", [(5, 6, 9), (2, 2, 3), (7, 5, 12), (4, 4, 2), (12, 10, 8),
+                                   (14, 11, 9)])
 def test_deformation_matches_oracle(nodes):
     import paper_1707_03581_amd as m
     pb = single(nodes)
