@@ -578,8 +578,9 @@ mrsdc_status prepare(mrsdc_ctx *c) {
   d.sweep_tol = cfg.sweep_tol;
   d.single_rate = cfg.method == MRSDC_SINGLE_RATE;
   for (int m = 0; m <= cfg.M; ++m) d.dtau_h[m] = c->w.dtau[m];
+  // a multiple of the 8 XCDs (the solve kernels deal their rows per XCD)
   d.grid = (int)std::min<int64_t>((N + kBlock - 1) / kBlock, kMaxGrid);
-  if (d.grid < 1) d.grid = 1;
+  d.grid = (d.grid + 7) / 8 * 8;
   const bool batch = c->S > 0;
   const int S = batch ? c->S : 1;
   if (batch && c->cpl.kind == 2)

@@ -89,6 +89,39 @@ __device__ inline double sum_partials(const double *part, int n, double *sh) {
 }
 
 // ---------------------------------------------------------------------------
+// XCD-aware row spans of the solve kernels: workgroup b runs on XCD b % 8
+// (round robin), and XCD x takes the x-th eighth of the 64-row slices, so the
+// vectors one kernel writes stay in that XCD's L2 for the next, whose
+// neighbour reads fall mostly in the same eighth.  Workgroups past the last
+// multiple of 8 get nothing (launch grids are multiples of 8).
+// ---------------------------------------------------------------------------
+constexpr int kXcd = 8;
+struct Span {
+  int64_t first, end, step;
+};
+// this wave's slices
+__device__ inline Span xcd_slices(int64_t nslices) {
+  const int x = blockIdx.x % kXcd, l = blockIdx.x / kXcd, per = gridDim.x / kXcd;
+  const int64_t s1 = nslices * (x + 1) / kXcd;
+  Span sp;
+  sp.first = nslices * x / kXcd + (int64_t)l * (kBlock / 64) + (threadIdx.x >> 6);
+  sp.end = (int)blockIdx.x < per * kXcd ? s1 : 0;
+  sp.step = (int64_t)per * (kBlock / 64);
+  return sp;
+}
+// this thread's rows: those of the same slices (N rows, ceil(N / 64) slices)
+__device__ inline Span xcd_rows(int64_t N) {
+  const int64_t ns = (N + kSlice - 1) / kSlice;
+  const int x = blockIdx.x % kXcd, l = blockIdx.x / kXcd, per = gridDim.x / kXcd;
+  const int64_t r1 = ns * (x + 1) / kXcd * kSlice;
+  Span sp;
+  sp.first = ns * x / kXcd * kSlice + (int64_t)l * kBlock + threadIdx.x;
+  sp.end = (int)blockIdx.x < per * kXcd ? (r1 < N ? r1 : N) : 0;
+  sp.step = (int64_t)per * kBlock;
+  return sp;
+}
+
+// ---------------------------------------------------------------------------
 // SELL-64 row product
 // ---------------------------------------------------------------------------
 template <bool D16>
@@ -187,15 +220,14 @@ __global__ __launch_bounds__(kBlock) void k_f_multi_cls(SellDev op, FArgs a) {
   __shared__ int sct[kMaxCls * kMaxClsWidth];
   __shared__ int slen[kMaxCls];
   const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
-  const int64_t row0 = wave * kSlice + lane;
-  const int c0 = (wave < op.nslices && row0 < op.nrows) ? (int)op.rcls[row0] : 0;
+  const Span sp = xcd_slices(op.nslices);
+  const int64_t row0 = sp.first * kSlice + lane;
+  const int c0 = (sp.first < sp.end && row0 < op.nrows) ? (int)op.rcls[row0] : 0;
   stage_forms<double>(op, sd, sct, slen);
-  for (int64_t s = wave; s < op.nslices; s += nw) {
+  for (int64_t s = sp.first; s < sp.end; s += sp.step) {
     const int64_t row = s * kSlice + lane;
     if (row >= op.nrows) continue;
-    const int c = s == wave ? c0 : (int)op.rcls[row];
+    const int c = s == sp.first ? c0 : (int)op.rcls[row];
     const int n = slen[c];
     const int *t = sct + c * op.cw;
     double acc[J];
@@ -271,8 +303,8 @@ __global__ __launch_bounds__(kBlock) void k_quad_resid(int64_t N, QArgs a,
   const Weights &w = *wp;
   const int P1 = a.P + 1;
   double rmax = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * kBlock) {
+  const Span sp = xcd_rows(N);
+  for (int64_t i = sp.first; i < sp.end; i += sp.step) {
     // every operand of the row is requested before the first store (a store
     // may alias them, which would order the loads after it)
     const double mi = a.mass[i];
@@ -534,8 +566,7 @@ __global__ __launch_bounds__(kBlock) void k_init_pred(CgArgs<double> a) {
   __shared__ int sct[CLS ? kMaxCls * kMaxClsWidth : 1];
   __shared__ int slen[CLS ? kMaxCls : 1];
   const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+  const Span sp = xcd_slices(a.op.nslices);
   if (CLS) {
     stage_forms<double>(a.op, sd, sct, slen);
   } else if (PK) {
@@ -543,7 +574,7 @@ __global__ __launch_bounds__(kBlock) void k_init_pred(CgArgs<double> a) {
     __syncthreads();
   }
   double v[3] = {0.0, 0.0, 0.0};
-  for (int64_t s = wave; s < a.op.nslices; s += nw) {
+  for (int64_t s = sp.first; s < sp.end; s += sp.step) {
     const int64_t row = s * kSlice + lane;
     if (row >= a.N) continue;
     const double Lx =
@@ -580,8 +611,8 @@ __global__ __launch_bounds__(kBlock) void k_init_corr(CgArgs<double> a) {
   if (a.ctr->stop) return;
   __shared__ double sh[17];
   double v[3] = {0.0, 0.0, 0.0};
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.N;
-       i += (int64_t)gridDim.x * kBlock) {
+  const Span sp = xcd_rows(a.N);
+  for (int64_t i = sp.first; i < sp.end; i += sp.step) {
     const double mi = a.mass[i], tp = a.Tprev[i], x0 = a.x[i], Im = a.I[i];
     double b = mi * tp + a.dtau * (a.g[i] - a.F[i]) + Im;
     if (a.ifc_src) {
@@ -678,8 +709,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
   const bool check = CG2 && TAIL != 2 && it > 0;
   const R *__restrict__ xin = CG2 ? a.u : a.p;
   const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+  const Span sp = xcd_slices(a.op.nslices);
   if (a.early_stop && a.ctr->stop) return;
   // Every request that does not depend on another is issued before the first
   // wait: the solve flags, the partials of the reductions, the table entries
@@ -725,8 +755,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
       if ((int)threadIdx.x < a.op.ncls) lv = a.op.clen[threadIdx.x];
     }
   }
-  const int64_t row0 = wave * kSlice + lane;
-  const bool have0 = wave < a.op.nslices && row0 < a.N;
+  const int64_t row0 = sp.first * kSlice + lane;
+  const bool have0 = sp.first < sp.end && row0 < a.N;
   int c0 = 0;
   R u0 = 0, m0 = 0;
   if (have0) {
@@ -770,10 +800,10 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs<R> a, int it) {
     __syncthreads();
   }
   double v[1] = {0.0};
-  for (int64_t s = wave; s < a.op.nslices; s += nw) {
+  for (int64_t s = sp.first; s < sp.end; s += sp.step) {
     const int64_t row = s * kSlice + lane;
     if (row >= a.N) continue;
-    const bool first = s == wave;
+    const bool first = s == sp.first;
     const R Lp = FMT == 3 ? (R)sell_row_cls<R>(a.op, row, first ? c0 : (int)a.op.rcls[row], xin,
                                                  sd, sct, slen)
                  : FMT == 2 ? (R)sell_row_pk<R>(a.op, s, lane, row, xin, sd)
@@ -805,8 +835,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_upd(CgArgs<R> a, int it) {
   // requested before the first wait
   const int stop = a.sc->done | a.sc->ref_done | a.ctr->stop;
   __shared__ double sh[34];
-  const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool first = i0 < a.N;
+  const Span sp = xcd_rows(a.N);
+  const int64_t i0 = sp.first;
+  const bool first = i0 < sp.end;
   R u0 = 0, w0 = 0, p0 = 0, s0 = 0, x0 = 0, r0 = 0, d0 = 0;
   if (first) {
     u0 = a.u[i0];
@@ -864,7 +895,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_upd(CgArgs<R> a, int it) {
     v1 += (double)rn * (double)rn;
   };
   if (first) upd(i0, u0, w0, p0, s0, x0, r0, d0);
-  for (int64_t i = i0 + (int64_t)gridDim.x * kBlock; i < a.N; i += (int64_t)gridDim.x * kBlock)
+  for (int64_t i = i0 + sp.step; i < sp.end; i += sp.step)
     upd(i, a.u[i], a.q[i], it > 0 ? a.p[i] : (R)0, it > 0 ? a.s[i] : (R)0, a.x[i], a.r[i],
         a.dinv[i]);
   block_sum2(v0, v1, sh);
@@ -1036,8 +1067,8 @@ __global__ __launch_bounds__(kBlock) void k_inner_init(CgArgs<float> a) {
   if (a.sc->ref_done || a.ctr->stop) return;
   __shared__ double sh[17];
   double v[2] = {0.0, 0.0};
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.N;
-       i += (int64_t)gridDim.x * kBlock) {
+  const Span sp = xcd_rows(a.N);
+  for (int64_t i = sp.first; i < sp.end; i += sp.step) {
     const float r = (float)a.r64[i];
     const float z = a.dinv[i] * r;
     a.r[i] = r;
@@ -1096,10 +1127,9 @@ __global__ __launch_bounds__(kBlock) void k_refine_update(CgArgs<float> a, const
     __syncthreads();
   }
   const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+  const Span sp = xcd_slices(a.op.nslices);
   double v[1] = {0.0};
-  for (int64_t s = wave; s < a.op.nslices; s += nw) {
+  for (int64_t s = sp.first; s < sp.end; s += sp.step) {
     const int64_t row = s * kSlice + lane;
     if (row >= a.N) continue;
     const double d = (double)a.x[row];
