@@ -938,8 +938,9 @@ __global__ __launch_bounds__(kBlock) void k_pcg_b(CgArgs<R> a, int it) {
   if (solve_done(a.sc, a.ctr)) return;
   __shared__ double sh[17];
   // the first row's operands are requested before the reduction of p.q
-  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool first = i < a.N;
+  const Span sp = xcd_rows(a.N);
+  int64_t i = sp.first;
+  const bool first = i < sp.end;
   R x0 = 0, p0 = 0, r0 = 0, q0 = 0, d0 = 0;
   if (first) {
     x0 = a.x[i];
@@ -958,7 +959,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_b(CgArgs<R> a, int it) {
     v[0] += (double)r * (double)(d0 * r);
     v[1] += (double)r * (double)r;
   }
-  for (i += (int64_t)gridDim.x * kBlock; i < a.N; i += (int64_t)gridDim.x * kBlock) {
+  for (i += sp.step; i < sp.end; i += sp.step) {
     a.x[i] += alpha * a.p[i];
     const R r = a.r[i] - alpha * a.q[i];
     a.r[i] = r;
@@ -979,8 +980,9 @@ __global__ __launch_bounds__(kBlock) void k_pcg_c(CgArgs<R> a, int it, int last)
   if (solve_done(a.sc, a.ctr)) return;
   __shared__ double sh[34];
   // the first row's operands are requested before the reductions
-  const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool first = i0 < a.N;
+  const Span sp = xcd_rows(a.N);
+  const int64_t i0 = sp.first;
+  const bool first = i0 < sp.end;
   R d0 = 0, r0 = 0, p0 = 0;
   if (first) {
     d0 = a.dinv[i0];
@@ -1010,7 +1012,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_c(CgArgs<R> a, int it, int last)
   }
   const R beta = (R)(rz / sc->rz[it & 1]);
   if (first) a.p[i0] = d0 * r0 + beta * p0;
-  for (int64_t i = i0 + (int64_t)gridDim.x * kBlock; i < a.N; i += (int64_t)gridDim.x * kBlock)
+  for (int64_t i = i0 + sp.step; i < sp.end; i += sp.step)
     a.p[i] = a.dinv[i] * a.r[i] + beta * a.p[i];
   if (lead) {
     sc->rz[(it + 1) & 1] = rz;
