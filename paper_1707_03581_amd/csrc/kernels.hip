@@ -1676,14 +1676,21 @@ __device__ double iface_fE(const SubArgs &A, const double *D, const int *I, cons
 // their end point is formed by the next interval's first substep, from the
 // same state with the same table.  The first substep launch also takes over
 // the convergence check of the node solve it follows (block 0).
+//
+// The launch has kXcd workgroups per point block and only those on XCD 0
+// (b % kXcd == 0) work, so the substeps' state (the interface buffers, the
+// f^E cache and the coefficient tables) stays in one L2 from launch to
+// launch.
 template <bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_iface_sub(SubArgs A) {
-  if (FIRST && A.chk_it >= 0 && blockIdx.x == 0) {
+  if (blockIdx.x % kXcd) return;
+  const int bx = blockIdx.x / kXcd;
+  if (FIRST && A.chk_it >= 0 && bx == 0) {
     __shared__ double sh[17];
     cg_check_block(A.chk, A.chk_it, sh);
   }
   if (A.ctr->stop) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = bx * blockDim.x + threadIdx.x;
   const IfaceDev &f = A.f;
   const int n = f.n_if;
   if (i >= n) return;
@@ -1885,8 +1892,8 @@ void launch_iface(const DevState &d, int m, bool corr, int slot, int chk_it, hip
   const int last = m == d.M ? d.P + 1 : d.P;
   for (int p = 1; p <= last; ++p) {
     A.p = p;
-    if (p == 1) k_iface_sub<true><<<grid, kBlock, 0, st>>>(A);
-    else k_iface_sub<false><<<grid, kBlock, 0, st>>>(A);
+    if (p == 1) k_iface_sub<true><<<grid * kXcd, kBlock, 0, st>>>(A);
+    else k_iface_sub<false><<<grid * kXcd, kBlock, 0, st>>>(A);
   }
 }
 
