@@ -85,7 +85,8 @@ struct mrsdc_ctx {
   int64_t off[3] = {0, 0, 0};
   StepCounters *ctr_host = nullptr;  // pinned
   int budget[kSlots];   // CG launch budget per solve slot (inner CG for FP32_REFINE)
-  int last_it[kSlots];  // FP64: the slot's iteration count one step earlier
+  int last_it[kSlots];      // the slot's iteration count one step earlier
+  int last_rounds[kSlots];  // FP32: the slot's refinement rounds one step earlier
   int expect[kSlots];   // iterations the slot took in the last step
   int rounds[kSlots];   // refinement round budget per slot
   int64_t matrix_bytes = 0;
@@ -984,6 +985,7 @@ mrsdc_status prepare(mrsdc_ctx *c) {
     c->budget[i] = b0;
     c->expect[i] = b0;
     c->last_it[i] = 0;
+    c->last_rounds[i] = 0;
     c->rounds[i] = std::min(cfg.refine_maxit, 3);
   }
   c->prepared = true;
@@ -1459,21 +1461,24 @@ mrsdc_status mrsdc_advance(mrsdc_ctx *c, double horizon, mrsdc_stats *stats) {
         for (int k = 0; k <= Kc; ++k) acc.residual[k] = h.resid[k];
         for (int i = 0; i < kSlots; ++i) {
           const int it = h.slot_iters[i];
-          if (it > 0 && !fp32) {
+          if (it > 0) {
             // a slot's count repeats from step to step within one or two: one
-            // launch pair beyond the larger of its last two counts (a solve
-            // that still runs out repeats the step with a doubled budget)
+            // launch pair beyond the larger of its last two counts (FP64: a
+            // solve that still runs out repeats the step with a doubled
+            // budget; FP32: an inner solve cut short leaves the rest to the
+            // refinement, and its budget doubles)
             c->budget[i] = std::min(c->cfg.pcg_maxit, std::max(it, c->last_it[i]) + 1);
             c->last_it[i] = it;
-            c->expect[i] = it;
-          } else if (it > 0) {
-            c->budget[i] = std::min(c->cfg.pcg_maxit, it + std::max(2, it / 5));
             c->expect[i] = it;
           } else if (it < 0 && fp32 && c->budget[i] < c->cfg.pcg_maxit) {
             c->budget[i] = std::min(c->cfg.pcg_maxit, 2 * c->budget[i]);  // inner solve cut short
           }
-          if (fp32 && h.slot_rounds[i] > 0)
-            c->rounds[i] = std::min(c->cfg.refine_maxit, h.slot_rounds[i] + 1);
+          if (fp32 && h.slot_rounds[i] > 0) {
+            // the larger of the slot's last two round counts; a solve that
+            // needs more repeats the step with twice the rounds
+            c->rounds[i] = std::min(c->cfg.refine_maxit, std::max(h.slot_rounds[i], c->last_rounds[i]));
+            c->last_rounds[i] = h.slot_rounds[i];
+          }
         }
         break;
       }
