@@ -102,6 +102,9 @@ struct mrsdc_ctx {
   int S = 0;
   std::vector<double> sc_h, sc_alpha, sc_Pf, sc_period, sc_t;
   std::vector<int> sc_active;
+  // a scenario joined since the last step: its solves may need more than the
+  // budgets learned from the others, so the next step widens them
+  bool batch_joined = false;
   std::vector<std::vector<double>> sc_T;  // pending host temperatures (empty: none)
   BatchArgs ba;
   BatchScalars *bsc_host = nullptr;       // pinned
@@ -1778,6 +1781,7 @@ mrsdc_status mrsdc_batch_set_time(mrsdc_ctx *c, int s, double t) {
 mrsdc_status mrsdc_batch_set_active(mrsdc_ctx *c, int s, int active) {
   mrsdc_status st = need_batch(c, s);
   if (st) return st;
+  if (active && !c->sc_active[s]) c->batch_joined = true;
   c->sc_active[s] = active ? 1 : 0;
   return batch_upload_params(c);
 }
@@ -1803,6 +1807,13 @@ mrsdc_status mrsdc_batch_advance(mrsdc_ctx *c, int nsteps, mrsdc_stats *stats) {
   std::memset(&acc, 0, sizeof acc);
   const int S = c->S, Kc = c->cfg.K;
   for (int n = 0; n < nsteps; ++n) {
+    if (c->batch_joined) {
+      for (int i = 0; i < kSlots; ++i) {
+        c->budget[i] = std::min(c->cfg.pcg_maxit, c->budget[i] + std::max(2, c->budget[i] / 5));
+        c->rounds[i] = std::min(c->cfg.refine_maxit, c->rounds[i] + 1);
+      }
+      c->batch_joined = false;
+    }
     for (;;) {
       enqueue_batch_step(c);
       HIPCHK(hipGetLastError());
@@ -1824,14 +1835,21 @@ mrsdc_status mrsdc_batch_advance(mrsdc_ctx *c, int nsteps, mrsdc_stats *stats) {
             else mx = std::max(mx, it);
             rmx = std::max(rmx, h.slot_rounds[i][s]);
           }
+          // as for one simulation: one launch pair beyond the larger of the
+          // slot's last two counts (largest over the scenarios), and the
+          // larger of its last two round counts
           if (cut && fp32) {
             if (c->budget[i] < c->cfg.pcg_maxit)
               c->budget[i] = std::min(c->cfg.pcg_maxit, 2 * c->budget[i]);
           } else if (mx > 0) {
-            c->budget[i] = std::min(c->cfg.pcg_maxit, mx + std::max(2, mx / 5));
+            c->budget[i] = std::min(c->cfg.pcg_maxit, std::max(mx, c->last_it[i]) + 1);
+            c->last_it[i] = mx;
             c->expect[i] = mx;
           }
-          if (fp32 && rmx > 0) c->rounds[i] = std::min(c->cfg.refine_maxit, rmx + 1);
+          if (fp32 && rmx > 0) {
+            c->rounds[i] = std::min(c->cfg.refine_maxit, std::max(rmx, c->last_rounds[i]));
+            c->last_rounds[i] = rmx;
+          }
           acc.max_iters = std::max(acc.max_iters, mx);
         }
         for (int s = 0; s < S; ++s) {
