@@ -1077,8 +1077,8 @@ int enqueue_solve(mrsdc_ctx *c, int k, int m, bool defer = false) {
   const int R = c->rounds[slot];
   for (int r = 0; r < R; ++r) {
     launch_inner_init(d, m, slot, cfg.inner_rtol, c->stream);
-    enqueue_cg(c, slot, m, true);
-    launch_refine_update(d, m, slot, r, r == R - 1, c->stream);
+    const int B = enqueue_cg(c, slot, m, true, true);
+    launch_refine_update(d, m, slot, r, r == R - 1, B, c->stream);
   }
   return -1;
 }

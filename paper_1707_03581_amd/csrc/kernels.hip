@@ -1114,11 +1114,14 @@ __device__ inline double sell_row_cls_mixed(const SellDev &op, int64_t row, int 
 }
 
 // x64 += d; r64 -= A d (FP64 operator); ||r64|| -> refinement converged?
-// CLS: row forms (tables staged once per block)
+// CLS: row forms (tables staged once per block).  chk_it >= 0: block 0 first
+// takes over the check of the inner solve after its launch budget.
 template <bool D16, bool PK = false, bool CLS = false>
-__global__ __launch_bounds__(kBlock) void k_refine_update(CgArgs<float> a, const double *mass64) {
-  if (a.sc->ref_done || a.ctr->stop) return;
+__global__ __launch_bounds__(kBlock) void k_refine_update(CgArgs<float> a, const double *mass64,
+                                                          int chk_it) {
   __shared__ double sh[17];
+  if (chk_it >= 0 && blockIdx.x == 0) cg_check_block(a, chk_it, sh);
+  if (a.sc->ref_done || a.ctr->stop) return;
   __shared__ double sd[CLS ? kDictMax : (PK ? 16 : 1)];
   __shared__ int sct[CLS ? kMaxCls * kMaxClsWidth : 1];
   __shared__ int slen[CLS ? kMaxCls : 1];
@@ -1397,12 +1400,12 @@ void launch_pcg32_iter(const DevState &d, int m, int slot, int it, bool last, bo
 }
 
 void launch_refine_update(const DevState &d, int m, int slot, int round, bool last_round,
-                          hipStream_t st) {
+                          int chk_it, hipStream_t st) {
   CgArgs<float> a = cg32(d, m, slot);
-  if (d.op.rcls) k_refine_update<true, false, true><<<d.grid, kBlock, 0, st>>>(a, d.mass);
-  else if (d.op.pk16) k_refine_update<true, true><<<d.grid, kBlock, 0, st>>>(a, d.mass);
-  else if (d.op.d16) k_refine_update<true><<<d.grid, kBlock, 0, st>>>(a, d.mass);
-  else k_refine_update<false><<<d.grid, kBlock, 0, st>>>(a, d.mass);
+  if (d.op.rcls) k_refine_update<true, false, true><<<d.grid, kBlock, 0, st>>>(a, d.mass, chk_it);
+  else if (d.op.pk16) k_refine_update<true, true><<<d.grid, kBlock, 0, st>>>(a, d.mass, chk_it);
+  else if (d.op.d16) k_refine_update<true><<<d.grid, kBlock, 0, st>>>(a, d.mass, chk_it);
+  else k_refine_update<false><<<d.grid, kBlock, 0, st>>>(a, d.mass, chk_it);
   solve_reduce(d, slot, 3, 0.0, round, last_round, st);
 }
 

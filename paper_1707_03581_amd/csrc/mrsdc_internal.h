@@ -201,8 +201,10 @@ void launch_inner_init(const DevState &d, int m, int slot, double inner_rtol, hi
 void launch_pcg32_iter(const DevState &d, int m, int slot, int it, bool last, bool tail,
                        double inner_rtol, hipStream_t st, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
+// chk_it >= 0: the check of the round's inner solve after its launch budget
+// (launch_pcg_final) is taken over by the update kernel
 void launch_refine_update(const DevState &d, int m, int slot, int round, bool last_round,
-                          hipStream_t st);
+                          int chk_it, hipStream_t st);
 void launch_operator_timing(const DevState &d, int m, bool fp32, int reps, hipStream_t st);
 void launch_clear_counters(const DevState &d, hipStream_t st);
 size_t coef_table_doubles(const IfaceDev &f);
