@@ -1076,7 +1076,7 @@ int enqueue_solve(mrsdc_ctx *c, int k, int m, bool defer = false) {
   launch_refine_init(d, m, slot, k == 0, cfg.refine_rtol, c->stream);
   const int R = c->rounds[slot];
   for (int r = 0; r < R; ++r) {
-    launch_inner_init(d, m, slot, cfg.inner_rtol, c->stream);
+    launch_inner_init(d, m, slot, cfg.inner_rtol, r, cfg.refine_rtol, c->stream);
     const int B = enqueue_cg(c, slot, m, true, true);
     launch_refine_update(d, m, slot, r, r == R - 1, B, c->stream);
   }

@@ -639,8 +639,10 @@ __global__ void k_solve_reduce(const double *part, int grid, SolveScalars *sc, S
   if (ctr->stop) return;  // residual control ended this step's sweeps
   __shared__ double sh[17];
   const int nk = (mode == 0) ? 3 : (mode == 3 ? 1 : 2);
+  // the refinement's partials (modes 1, 3) are in slots 2, 3
+  const double *base = part + ((mode == 1 || mode == 3) ? 2 * grid : 0);
   double o[3] = {0.0, 0.0, 0.0};
-  for (int k = 0; k < nk; ++k) o[k] = sum_partials(part + k * grid, grid, sh);
+  for (int k = 0; k < nk; ++k) o[k] = sum_partials(base + k * grid, grid, sh);
   if (threadIdx.x != 0) return;
   if (mode == 0) {
     init_finish(sc, ctr, slot, 0, rtol, o);
@@ -1061,13 +1063,49 @@ __global__ __launch_bounds__(kBlock) void k_rinit(CgArgs<float> a, const double 
     v[0] += r * r;
     v[1] += b * b;
   }
-  publish<2>(v, a.partial, a.grid, sh);
+  publish<2>(v, a.partial + 2 * a.grid, a.grid, sh);  // slots 2, 3: r.r, b.b
 }
 
 // inner init: r32 = r64, d = 0, p = dinv r32; tolerance relative to ||r32||
-__global__ __launch_bounds__(kBlock) void k_inner_init(CgArgs<float> a) {
-  if (a.sc->ref_done || a.ctr->stop) return;
+// Round 0 first forms the refinement's scalars from the refinement init's
+// partials (r.r, b.b in slots 2, 3); a later round first takes the previous
+// round's refinement check from the update's partials (r.r in slot 2).  Every
+// block decides alike; block 0 stores the scalars.  The last round's check
+// stays with k_solve_reduce (mode 3), which also records a failure.
+__global__ __launch_bounds__(kBlock) void k_inner_init(CgArgs<float> a, int round,
+                                                       double refine_rtol) {
   __shared__ double sh[17];
+  if (a.ctr->stop) return;
+  if (round > 0 && a.sc->ref_done) return;  // an earlier round met the tolerance
+  SolveScalars *sc = a.sc;
+  const double rr = sum_partials(a.partial + 2 * a.grid, a.grid, sh);
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (round == 0) {
+    const double bb = sum_partials(a.partial + 3 * a.grid, a.grid, sh);
+    const double tol2 = refine_rtol * refine_rtol * bb;
+    const bool met = rr <= tol2;
+    if (lead) {
+      sc->ref_bb = bb;
+      sc->ref_tol2 = tol2;
+      sc->ref_done = met ? 1 : 0;
+      sc->ref_rounds = 0;
+      sc->done = 0;
+      a.ctr->slot_iters[a.slot] = 0;  // largest inner iteration count of the solve
+      if (met) a.ctr->slot_rounds[a.slot] = 0;
+    }
+    if (met) return;
+  } else {
+    const bool met = rr <= sc->ref_tol2;
+    if (lead) {
+      sc->ref_rounds = round;
+      a.ctr->refine_steps += 1;
+      if (met) {
+        sc->ref_done = 1;
+        a.ctr->slot_rounds[a.slot] = round;
+      }
+    }
+    if (met) return;
+  }
   double v[2] = {0.0, 0.0};
   const Span sp = xcd_rows(a.N);
   for (int64_t i = sp.first; i < sp.end; i += sp.step) {
@@ -1147,7 +1185,7 @@ __global__ __launch_bounds__(kBlock) void k_refine_update(CgArgs<float> a, const
     a.r64[row] = r;
     v[0] += r * r;
   }
-  publish<1>(v, a.partial, a.grid, sh);
+  publish<1>(v, a.partial + 2 * a.grid, a.grid, sh);  // slot 2: r.r
 }
 
 static CgArgs<double> cg64(const DevState &d, int m, int slot) {
@@ -1382,11 +1420,12 @@ void launch_refine_init(const DevState &d, int m, int slot, bool pred, double rt
     if (pred) k_rinit<false, true><<<d.grid, kBlock, 0, st>>>(a, d.mass);
     else k_rinit<false, false><<<d.grid, kBlock, 0, st>>>(a, d.mass);
   }
-  solve_reduce(d, slot, 1, rtol, 0, false, st);
+  (void)rtol;  // the refinement's scalars are formed by the first round's inner init
 }
 
-void launch_inner_init(const DevState &d, int m, int slot, double inner_rtol, hipStream_t st) {
-  k_inner_init<<<d.grid, kBlock, 0, st>>>(cg32(d, m, slot));
+void launch_inner_init(const DevState &d, int m, int slot, double inner_rtol, int round,
+                       double refine_rtol, hipStream_t st) {
+  k_inner_init<<<d.grid, kBlock, 0, st>>>(cg32(d, m, slot), round, refine_rtol);
   (void)inner_rtol;  // the inner solve's scalars are formed by its first operator step
 }
 
@@ -1406,7 +1445,8 @@ void launch_refine_update(const DevState &d, int m, int slot, int round, bool la
   else if (d.op.pk16) k_refine_update<true, true><<<d.grid, kBlock, 0, st>>>(a, d.mass, chk_it);
   else if (d.op.d16) k_refine_update<true><<<d.grid, kBlock, 0, st>>>(a, d.mass, chk_it);
   else k_refine_update<false><<<d.grid, kBlock, 0, st>>>(a, d.mass, chk_it);
-  solve_reduce(d, slot, 3, 0.0, round, last_round, st);
+  // the other rounds' checks are taken by the next round's inner init
+  if (last_round) solve_reduce(d, slot, 3, 0.0, round, last_round, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -197,7 +197,10 @@ void launch_pcg_iter(const DevState &d, int m, int slot, int it, bool last, bool
                      hipEvent_t ev1 = nullptr);
 void launch_refine_init(const DevState &d, int m, int slot, bool pred, double rtol,
                         hipStream_t st);
-void launch_inner_init(const DevState &d, int m, int slot, double inner_rtol, hipStream_t st);
+// round 0 also forms the refinement's scalars (tolerance refine_rtol); a later
+// round first takes the previous round's refinement check
+void launch_inner_init(const DevState &d, int m, int slot, double inner_rtol, int round,
+                       double refine_rtol, hipStream_t st);
 void launch_pcg32_iter(const DevState &d, int m, int slot, int it, bool last, bool tail,
                        double inner_rtol, hipStream_t st, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
