@@ -215,6 +215,43 @@ def test_fp32_refine_machine_310k_sampled_steps():
     assert e <= TOL32
 
 
+def test_fp32_refine_round_cap():
+    """One refinement round with a loose inner solve (1e-2) cannot reach the
+    FP64 tolerance (1e-10): ENOCONV, and the state stays at the start."""
+    m = lib()
+    pb = small_machine()
+    ctx = m.simulation(pb, precision=1, refine_maxit=1, inner_rtol=1e-2)
+    with pytest.raises(m.MrsdcError) as e:
+        ctx.advance(pb.scheme.dt)
+    assert e.value.status == m.ENOCONV
+    assert np.array_equal(m.get_state(ctx, pb), pb.T0)
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_budgets_regrow_after_a_harder_state(precision):
+    """The launch budgets (and FP32 refinement rounds) learned on a smooth state
+    are too small for a rough one set mid-run: the steps that run out are
+    repeated with larger budgets, and the result still matches the oracle run
+    from the same state and time."""
+    m = lib()
+    pb = small_machine()
+    dt = pb.scheme.dt
+    ctx = m.simulation(pb, precision=precision)
+    ctx.advance(3 * dt)
+    rough = pb.T0 + np.random.default_rng(7).uniform(-40.0, 40.0, size=pb.N)
+    off = pb.offsets
+    for i in range(len(pb.bodies)):
+        ctx.set_temperature(i, rough[off[i]:off[i + 1]])
+    st = ctx.advance(2 * dt)
+    T = m.get_state(ctx, pb)
+    ctx.destroy()
+    ref, _ = oracle.run(pb, nsteps=2, T0=rough, t0=pb.t0 + 3 * dt)
+    e = rel(T, ref)
+    print(f"  precision={precision} redone={st['redone_steps']} rel_l2={e:.3e}", flush=True)
+    assert e <= (TOL32 if precision else TOL)
+
+
 def test_fp32_refine_deterministic():
     pb = small_machine()
     a, _ = run_gpu(pb, 3, precision=1)
