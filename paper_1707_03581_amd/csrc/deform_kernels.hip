@@ -240,21 +240,39 @@ __global__ __launch_bounds__(kThreads) void k_gj_col(double *S, int64_t ld, int 
 // solves
 // ---------------------------------------------------------------------------
 
-// f = G (T - T_ref), one thread per displacement DOF.
+// f = G (T - T_ref), one thread per displacement DOF; the row's entries are
+// taken eight at a time, their columns, values and gathers all requested
+// before the first product (the products are added in the row's order).
 __global__ __launch_bounds__(kThreads) void k_thermal_load(DeformDev D, const double *T) {
+  constexpr int U = 8;
   for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < D.n;
        r += (int64_t)gridDim.x * kThreads) {
     double a = 0.0;
-    for (int64_t e = D.growptr[r]; e < D.growptr[r + 1]; ++e)
-      a = fma(D.gval[e], T[D.toff + D.gcol[e]] - D.T_ref, a);
+    int64_t e = D.growptr[r];
+    const int64_t e1 = D.growptr[r + 1];
+    for (; e + U <= e1; e += U) {
+      int c[U];
+      double v[U], t[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        c[k] = D.gcol[e + k];
+        v[k] = D.gval[e + k];
+      }
+#pragma unroll
+      for (int k = 0; k < U; ++k) t[k] = T[D.toff + c[k]];
+#pragma unroll
+      for (int k = 0; k < U; ++k) a = fma(v[k], t[k] - D.T_ref, a);
+    }
+    for (; e < e1; ++e) a = fma(D.gval[e], T[D.toff + D.gcol[e]] - D.T_ref, a);
     D.f[r] = a;
   }
 }
 
 // Coupling product of one row of an ELL block with a neighbouring block's
-// vector: 4 lanes per row, each over every 4th entry, loads issued two at a
-// time, then summed across the 4 lanes.
-constexpr int kSub = 4;
+// vector: kSub lanes per row, each over every kSub-th entry (at most 6 of the
+// 81 a row can hold), loads issued two at a time, then summed across the
+// lanes.
+constexpr int kSub = 16;
 __device__ inline double ell_row(const double *val, const int32_t *col, int64_t bp, int E,
                                  int64_t i, int sub, const double *x) {
   double a0 = 0.0, a1 = 0.0;
@@ -267,8 +285,8 @@ __device__ inline double ell_row(const double *val, const int32_t *col, int64_t 
   }
   if (e < E) a0 = fma(val[e * bp + i], x[col[e * bp + i]], a0);
   double s = a0 + a1;
-  s += __shfl_xor(s, 1, 64);
-  s += __shfl_xor(s, 2, 64);
+#pragma unroll
+  for (int o = 1; o < kSub; o <<= 1) s += __shfl_xor(s, o, 64);
   return s;
 }
 
