@@ -398,26 +398,30 @@ __global__ __launch_bounds__(kThreads) void k_symv(const double *W, int64_t ld, 
 
 // out = W v (MODE 0) or base - W v (MODE 1) for the first rows of output
 // tile K = blockIdx.x: the transposed contributions of tile rows 0..K-1, then
-// the strips of tile row K, in that order; 4 thread groups take every 4th
-// slot, summed in group order.
+// the strips of tile row K, in that order; kRedGroups thread groups of 64
+// take every kRedGroups-th slot (at most 6 on the 81 tiles of the 1 cm stand, all
+// requested at once), summed in group order.
+constexpr int kRedGroups = 16;
 template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_symv_reduce(const double *part, int nt, int ns,
-                                                          int64_t rows, double *out,
-                                                          const double *base) {
-  __shared__ double sg[kThreads / 64][64];
+__global__ __launch_bounds__(64 * kRedGroups) void k_symv_reduce(const double *part, int nt,
+                                                                 int ns, int64_t rows,
+                                                                 double *out, const double *base) {
+  __shared__ double sg[kRedGroups][64];
   const int K = blockIdx.x, c = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int nsK = (nt - K + kSymStrip - 1) / kSymStrip;
   const int n = K + nsK;
   double acc = 0.0;
 #pragma unroll 8
-  for (int j = g; j < n; j += kThreads / 64) {
+  for (int j = g; j < n; j += kRedGroups) {
     const int slot = j < K ? j : nt + (j - K);
     acc += part[((int64_t)K * ns + slot) * 64 + c];
   }
   sg[g][c] = acc;
   __syncthreads();
   if (g != 0) return;
-  const double y = ((sg[0][c] + sg[1][c]) + sg[2][c]) + sg[3][c];
+  double y = 0.0;
+#pragma unroll
+  for (int q = 0; q < kRedGroups; ++q) y += sg[q][c];
   const int64_t r = (int64_t)K * 64 + c;
   if (r < rows) out[r] = MODE == 0 ? y : base[r] - y;
 }
@@ -470,11 +474,11 @@ void deform_solve(const DeformDev &D, const double *T, hipStream_t st, hipEvent_
     if (ev) {
       hipExtLaunchKernelGGL(k_symv, dim3(D.nstrip), dim3(kThreads), 0, st, ev[2 * g], nullptr, 0,
                             W, D.bp, nt, ns, D.strip, (const double *)D.c, D.part);
-      hipExtLaunchKernelGGL(red, dim3(nt), dim3(kThreads), 0, st, nullptr, ev[2 * g + 1], 0,
+      hipExtLaunchKernelGGL(red, dim3(nt), dim3(64 * kRedGroups), 0, st, nullptr, ev[2 * g + 1], 0,
                             (const double *)D.part, nt, ns, rows, out, base);
     } else {
       k_symv<<<D.nstrip, kThreads, 0, st>>>(W, D.bp, nt, ns, D.strip, D.c, D.part);
-      red<<<nt, kThreads, 0, st>>>(D.part, nt, ns, rows, out, base);
+      red<<<nt, 64 * kRedGroups, 0, st>>>(D.part, nt, ns, rows, out, base);
     }
     ++g;
   };
