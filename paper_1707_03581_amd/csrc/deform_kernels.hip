@@ -150,6 +150,7 @@ __global__ __launch_bounds__(kThreads) void k_gj_row(double *S, int64_t ld, int 
 // Trailing update: S(I, J) -= S(I, p) S(p, J) for every tile I != p, J != p.
 // The workgroup of tile (p+1, p+1), the next pivot tile, goes first and then
 // inverts it into piv_next, hidden behind the other tiles' updates.
+static_assert(kT * kT % kThreads == 0, "the update stages whole tiles");
 __global__ __launch_bounds__(kThreads) void k_gj_update(double *S, int64_t ld, int p, int nt,
                                                         double *piv_next, int *flag) {
   __shared__ double L[kT][kT + 1];  // L[k][i] = S(I, p)[i][k]
@@ -162,15 +163,31 @@ __global__ __launch_bounds__(kThreads) void k_gj_update(double *S, int64_t ld, i
   const int it = bi < p ? bi : bi + 1, jt = bj < p ? bj : bj + 1;
   const double *SI = S + (int64_t)it * kT * ld + (int64_t)p * kT;
   const double *SJ = S + (int64_t)p * kT * ld + (int64_t)jt * kT;
-  for (int e = t; e < kT * kT; e += kThreads) {
-    const int r = e / kT, c = e % kT;
-    L[c][r] = SI[(int64_t)r * ld + c];
-    R[r][c] = SJ[(int64_t)r * ld + c];
-  }
-  __syncthreads();
+  double *O = S + (int64_t)it * kT * ld + (int64_t)jt * kT;
   // rows i0 + a (4 consecutive), columns j0 + 16 b (16 lanes side by side:
   // conflict-free LDS reads, 128-byte global runs)
   const int i0 = (t >> 4) * 4, j0 = t & 15;
+  // every global load of the workgroup (both operand tiles and this thread's
+  // part of the output tile) is issued before the first wait
+  constexpr int kE = kT * kT / kThreads;
+  double lv[kE], rv[kE], ov[4][4];
+#pragma unroll
+  for (int q = 0; q < kE; ++q) {
+    const int e = t + q * kThreads, r = e / kT, c = e % kT;
+    lv[q] = SI[(int64_t)r * ld + c];
+    rv[q] = SJ[(int64_t)r * ld + c];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) ov[a][b] = O[(int64_t)(i0 + a) * ld + j0 + 16 * b];
+#pragma unroll
+  for (int q = 0; q < kE; ++q) {
+    const int e = t + q * kThreads, r = e / kT, c = e % kT;
+    L[c][r] = lv[q];
+    R[r][c] = rv[q];
+  }
+  __syncthreads();
   double acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -187,14 +204,13 @@ __global__ __launch_bounds__(kThreads) void k_gj_update(double *S, int64_t ld, i
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
   }
-  double *O = S + (int64_t)it * kT * ld + (int64_t)jt * kT;
   const bool next = it == p + 1 && jt == p + 1;  // uniform over the workgroup
   if (next) __syncthreads();                     // L is reused below
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const double o = O[(int64_t)(i0 + a) * ld + j0 + 16 * b] - acc[a][b];
+      const double o = ov[a][b] - acc[a][b];
       O[(int64_t)(i0 + a) * ld + j0 + 16 * b] = o;
       if (next) L[i0 + a][j0 + 16 * b] = o;
     }
