@@ -121,6 +121,27 @@ __global__ __launch_bounds__(kThreads) void k_gj_pivot(const double *S, int64_t 
   if (t == 0 && bad) atomicAdd(flag, bad);
 }
 
+// The pivot inverse (contiguous) and a tile of S into LDS: every load is
+// issued before the first store, then one barrier.
+__device__ inline void stage_pair(const double *piv, const double *tile, int64_t ld,
+                                  double (*Pi)[kT + 1], double (*X)[kT + 1]) {
+  constexpr int kE = kT * kT / kThreads;
+  double pv[kE], xv[kE];
+#pragma unroll
+  for (int q = 0; q < kE; ++q) {
+    const int e = (int)threadIdx.x + q * kThreads;
+    pv[q] = piv[e];
+    xv[q] = tile[(int64_t)(e / kT) * ld + e % kT];
+  }
+#pragma unroll
+  for (int q = 0; q < kE; ++q) {
+    const int e = (int)threadIdx.x + q * kThreads;
+    Pi[e / kT][e % kT] = pv[q];
+    X[e / kT][e % kT] = xv[q];
+  }
+  __syncthreads();
+}
+
 // Row panel: S(p, j) = piv S(p, j) for every tile column j != p.
 __global__ __launch_bounds__(kThreads) void k_gj_row(double *S, int64_t ld, int p,
                                                      const double *piv) {
@@ -129,11 +150,7 @@ __global__ __launch_bounds__(kThreads) void k_gj_row(double *S, int64_t ld, int 
   const int t = threadIdx.x;
   const int jt = blockIdx.x < p ? blockIdx.x : blockIdx.x + 1;
   double *tile = S + (int64_t)p * kT * ld + (int64_t)jt * kT;
-  for (int e = t; e < kT * kT; e += kThreads) {
-    Pi[e / kT][e % kT] = piv[e];
-    X[e / kT][e % kT] = tile[(int64_t)(e / kT) * ld + e % kT];
-  }
-  __syncthreads();
+  stage_pair(piv, tile, ld, Pi, X);
   const int j = t & 63, w = t >> 6;  // rows w + 4q, column j
   double out[16];
 #pragma unroll
@@ -234,11 +251,7 @@ __global__ __launch_bounds__(kThreads) void k_gj_col(double *S, int64_t ld, int 
     for (int e = t; e < kT * kT; e += kThreads) tile[(int64_t)(e / kT) * ld + e % kT] = piv[e];
     return;
   }
-  for (int e = t; e < kT * kT; e += kThreads) {
-    Pi[e / kT][e % kT] = piv[e];
-    X[e / kT][e % kT] = tile[(int64_t)(e / kT) * ld + e % kT];
-  }
-  __syncthreads();
+  stage_pair(piv, tile, ld, Pi, X);
   const int j = t & 63, w = t >> 6;  // rows w + 4q, column j
   double out[16];
 #pragma unroll
