@@ -470,7 +470,7 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
   a.P = c->cfg.P;
   a.sweep_tol = c->cfg.sweep_tol;
   // blocks of 4 rows, a multiple of the 8 XCDs
-  a.grid = (int)std::min<int64_t>(((N + 3) / 4 + 7) / 8 * 8, 1024);
+  a.grid = (int)std::min<int64_t>(((N + 3) / 4 + 7) / 8 * 8, kBatchMaxGrid);
   for (int m = 0; m <= c->cfg.M; ++m) a.dtau_h[m] = c->w.dtau[m];
   double *pv;
   a.op.N = N;

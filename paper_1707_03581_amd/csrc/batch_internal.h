@@ -36,6 +36,7 @@ constexpr int kMaxR = 8;  // tiles hold at most 4 kMaxR rows
 constexpr int kStageBytes = 65536;
 constexpr int kStageSlots = (kStageBytes / 8 - 64) / 64;  // 127, with a 64-value tail
 constexpr int kMaxTileEntries = 1024;                      // matrix entries of a tile
+constexpr int kBatchMaxGrid = 1024;  // workgroups of the batched kernels (a multiple of 8)
 
 // Per-scenario solver scalars (index s fastest).  In the FP32 form, tol2 and
 // done belong to the inner FP32 solve and ref_* to the FP64 refinement around

@@ -670,8 +670,6 @@ __global__ __launch_bounds__(kBlock) void kb_refine_update(BatchArgs a, int m, d
 // One workgroup per scenario s = blockIdx.x; np = workgroups of the
 // producing kernel, whose partials of scenario s are contiguous.  Fixed-order
 // sums: thread j adds blocks j, j + 256, ..., then a fixed halving tree.
-constexpr int kBatchMaxGrid = 1024;  // workgroups of the batched row kernels
-
 __global__ __launch_bounds__(kBlock) void kb_reduce(BatchArgs a, int np, int mode, int it,
                                                     int last, int slot, double rtol) {
   __shared__ double sh[3][kBlock];
