@@ -9,7 +9,7 @@ namespace mrsdc {
 
 constexpr int kGjTile = 64;              // Gauss-Jordan pivot width and tile size
 constexpr int64_t kMaxDeformBlock = 8192;  // padded block: one row of it in LDS (64 KB)
-constexpr int kSymStrip = 4;               // tiles per workgroup of the symmetric block product
+constexpr int kSymStrip = 1;               // tiles per workgroup of the symmetric block product
 
 struct DeformDev {
   int64_t n = 0;     // free displacement DOFs
