@@ -371,10 +371,8 @@ __global__ __launch_bounds__(kThreads) void k_symv(const double *W, int64_t ld, 
     double a[4][4], vj[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const dvec2 lo =
-          __builtin_nontemporal_load(reinterpret_cast<const dvec2 *>(rowp + (int64_t)q * ld + J * 64));
-      const dvec2 hi = __builtin_nontemporal_load(
-          reinterpret_cast<const dvec2 *>(rowp + (int64_t)q * ld + J * 64 + 2));
+      const dvec2 lo = *reinterpret_cast<const dvec2 *>(rowp + (int64_t)q * ld + J * 64);
+      const dvec2 hi = *reinterpret_cast<const dvec2 *>(rowp + (int64_t)q * ld + J * 64 + 2);
       a[q][0] = lo[0];
       a[q][1] = lo[1];
       a[q][2] = hi[0];
