@@ -96,7 +96,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the time step of "
-              "one simulation does not shard across GPUs in this build", file=sys.stderr)
+              "one simulation is not sharded across GPUs", file=sys.stderr)
         sys.exit(2)
     import torch
 
