@@ -426,9 +426,9 @@ __global__ __launch_bounds__(kThreads) void k_symv(const double *W, int64_t ld, 
 // out = W v (MODE 0) or base - W v (MODE 1) for the first rows of output
 // tile K = blockIdx.x: the transposed contributions of tile rows 0..K-1, then
 // the strips of tile row K, in that order; kRedGroups thread groups of 64
-// take every kRedGroups-th slot (at most 6 on the 81 tiles of the 1 cm stand, all
-// requested at once), summed in group order.
-constexpr int kRedGroups = 16;
+// take every kRedGroups-th slot (at most 11 on the 81 tiles of the 1 cm stand,
+// requested eight at a time), summed in group order.
+constexpr int kRedGroups = 8;
 template <int MODE>
 __global__ __launch_bounds__(64 * kRedGroups) void k_symv_reduce(const double *part, int nt,
                                                                  int ns, int64_t rows,
