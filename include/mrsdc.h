@@ -87,7 +87,34 @@ typedef struct {
                          no substeps; P is then unused.  FP64 only, single
                          (non-batched) contexts only */
   void *stream;       /* hipStream_t to run on, or NULL for a library-owned stream */
+  int op_form;        /* storage of L = K + h R (§2, eq. femDiscr) read by the CG
+                         product of single contexts.  Every form holds the same
+                         entries in the same order, so every form gives the same
+                         sums, bit for bit:
+                           MRSDC_OP_AUTO     the most compact form that applies
+                           MRSDC_OP_VALUES   value array (8 B per entry; FP32
+                                             copy for the inner solves)
+                           MRSDC_OP_DICT     1-byte index into the distinct
+                                             values (at most 256 of them)
+                           MRSDC_OP_PACKED   2-byte word: column offset and
+                                             value index (at most 16 values,
+                                             |col - row| <= 2047)
+                           MRSDC_OP_PATTERNS 1-byte row form per row (at most
+                                             128 distinct rows)
+                         OR-ed with MRSDC_OP_COL32: int32 columns even where
+                         16-bit offsets fit.  The first advance (or stationary
+                         solve) returns EINVAL when the form does not apply.
+                         Batched contexts take MRSDC_OP_AUTO only. */
 } mrsdc_config;
+
+enum {
+  MRSDC_OP_AUTO = 0,
+  MRSDC_OP_VALUES = 1,
+  MRSDC_OP_DICT = 2,
+  MRSDC_OP_PACKED = 3,
+  MRSDC_OP_PATTERNS = 4,
+  MRSDC_OP_COL32 = 0x100
+};
 
 typedef struct {
   int64_t steps;           /* completed time steps in the last advance */
@@ -101,6 +128,9 @@ typedef struct {
   double wall_s;           /* host wall time of the advance, to device completion */
   int64_t bytes_moved;     /* algorithmic device bytes of the advance (see docs) */
   int64_t sweeps;          /* correction sweeps run (over active scenarios) */
+  int32_t op_form;         /* operator form the CG product read (MRSDC_OP_VALUES ..
+                              MRSDC_OP_PATTERNS; 0 in batched contexts) */
+  int32_t col_bytes;       /* bytes per stored column: 2 (offset) or 4 (int32) */
 } mrsdc_stats;
 
 /* Fill *cfg with defaults: FP64, Lobatto M=3, P=2, K=2, dt=1, pcg_rtol 1e-13. */

@@ -30,17 +30,31 @@ import scipy.sparse as sp
 FACES = {"x0": (0, 0), "x1": (0, 1), "y0": (1, 0), "y1": (1, 1), "z0": (2, 0), "z1": (2, 1)}
 
 
-def _one_d(n: int, L: float):
-    """Dense 1D stiffness, consistent mass and lumped mass on n uniform nodes."""
-    h = L / (n - 1)
+def _one_d(n: int, L: float, x=None):
+    """Dense 1D stiffness, consistent mass and lumped mass on n nodes (uniform
+    on [0, L] unless the sorted node coordinates x are given)."""
+    uniform = x is None
+    x = np.linspace(0.0, L, n) if uniform else np.asarray(x, dtype=np.float64)
+    assert len(x) == n and np.all(np.diff(x) > 0)
     Kd = np.zeros((n, n))
     Md = np.zeros((n, n))
     for e in range(n - 1):
+        # one spacing for a uniform grid: every cell's entries the same numbers
+        h = L / (n - 1) if uniform else x[e + 1] - x[e]
         i = np.array([e, e + 1])
         Kd[np.ix_(i, i)] += np.array([[1.0, -1.0], [-1.0, 1.0]]) / h
         Md[np.ix_(i, i)] += np.array([[2.0, 1.0], [1.0, 2.0]]) * h / 6.0
-    x = np.linspace(0.0, L, n)
     return Kd, Md, Md.sum(axis=1), x
+
+
+def jittered_nodes(n: int, L: float, rng, amp: float = 0.2):
+    """n sorted node coordinates on [0, L]: the uniform ones with every interior
+    node moved by U[-amp, amp] times the spacing (a graded, irregular 1D mesh;
+    amp < 0.5 keeps the order)."""
+    x = np.linspace(0.0, L, n)
+    if n > 2:
+        x[1:-1] += rng.uniform(-amp, amp, size=n - 2) * (L / (n - 1))
+    return x
 
 
 @dataclass
@@ -88,8 +102,9 @@ class Body:
         return sp.csr_matrix((vals, self.col, self.rowptr), shape=(self.n, self.n))
 
 
-def box(L, nodes, k: float, rho_c: float, robin_faces=()) -> Body:
-    """Q1 operators of the box [0,Lx]x[0,Ly]x[0,Lz] on nx*ny*nz uniform nodes.
+def box(L, nodes, k: float, rho_c: float, robin_faces=(), axes=None) -> Body:
+    """Q1 operators of the box [0,Lx]x[0,Ly]x[0,Lz] on nx*ny*nz nodes (a tensor
+    grid: uniform, or the sorted per-axis coordinates in axes).
 
     robin_faces: names from FACES on which the unit Robin mass is assembled.
     The stored pattern is the full structural 27-point pattern (explicit zeros
@@ -97,7 +112,8 @@ def box(L, nodes, k: float, rho_c: float, robin_faces=()) -> Body:
     """
     Lx, Ly, Lz = L
     nx, ny, nz = nodes
-    one = [_one_d(nx, Lx), _one_d(ny, Ly), _one_d(nz, Lz)]
+    axes = axes or (None, None, None)
+    one = [_one_d(nx, Lx, axes[0]), _one_d(ny, Ly, axes[1]), _one_d(nz, Lz, axes[2])]
     n = nx * ny * nz
 
     tri = [sp.diags([np.ones(m - 1), np.ones(m), np.ones(m - 1)], [-1, 0, 1]) for m in (nx, ny, nz)]
@@ -168,3 +184,23 @@ def box(L, nodes, k: float, rho_c: float, robin_faces=()) -> Body:
 
     return Body(n=n, rowptr=rowptr, col=col, K=Kv, R=Rv, mass=mass, rload=rload,
                 coords=coords, faces=faces, dims=(nx, ny, nz), lengths=(Lx, Ly, Lz))
+
+
+def permute(b: Body, perm) -> Body:
+    """The same body with its nodes renumbered: new node i is old node perm[i]
+    (a caller's own numbering; the operators are the same up to that
+    relabelling).  Rows keep their columns sorted."""
+    perm = np.asarray(perm, dtype=np.int64)
+    n = b.n
+    inv = np.empty(n, dtype=np.int64)
+    inv[perm] = np.arange(n)
+    A = sp.csr_matrix((np.arange(b.nnz, dtype=np.float64) + 1.0, b.col, b.rowptr), shape=(n, n))
+    Ap = A[perm][:, perm].tocsr()
+    Ap.sort_indices()
+    src = Ap.data.astype(np.int64) - 1  # old entry index of each new entry
+    faces = {name: Face(u=f.u.copy(), v=f.v.copy(), ids=inv[f.ids].astype(np.int32))
+             for name, f in b.faces.items()}
+    return Body(n=n, rowptr=Ap.indptr.astype(np.int64), col=Ap.indices.astype(np.int32),
+                K=b.K[src].copy(), R=b.R[src].copy(), mass=b.mass[perm].copy(),
+                rload=b.rload[perm].copy(), coords=b.coords[perm].copy(), faces=faces,
+                dims=(), lengths=b.lengths)

@@ -22,7 +22,7 @@ from dataclasses import dataclass, field, replace
 
 import numpy as np
 
-from .mesh import FACES, Body, Face, box
+from .mesh import FACES, Body, Face, box, jittered_nodes, permute
 
 K_STEEL = 15.0  # W/(m K)
 RHO_C_STEEL = 3.6e6  # J/(m^3 K)
@@ -157,12 +157,28 @@ def patch_box(L=(0.2, 0.2, 0.8), nodes=(9, 9, 33), h=10.0, T_amb=20.0, q0=2000.0
 def machine(stand_nodes=(41, 41, 161), stock_nodes=(31, 31, 41), stand_L=(0.4, 0.4, 1.6),
             stock_L=(0.3, 0.3, 0.4), y_offset=0.05, h=10.0, T_amb=20.0, alpha=1000.0,
             friction_W=200.0, period=4.0, stroke=1.0, scheme=None, nsteps=120, seed=0,
-            robin=True, name="machine") -> Problem:
-    """Stand + sliding stock.  Stock centre z_c(t) = Lz_stand/2 + stroke/2 sin(2 pi t/period)."""
+            robin=True, jitter=0.0, mesh_seed=7, renumber=False,
+            name="machine") -> Problem:
+    """Stand + sliding stock.  Stock centre z_c(t) = Lz_stand/2 + stroke/2 sin(2 pi t/period).
+
+    jitter > 0: irregular tensor meshes, every interior node coordinate moved
+    by U[-jitter, jitter] grid spacings (default_rng(mesh_seed)), so the
+    operators hold a different value in nearly every entry.  renumber: each
+    body's nodes in a seeded random order (default_rng(mesh_seed + 1)), as
+    an unstructured mesh generator may number them."""
     stand_faces = _robin_except("x1") if robin else ()
     stock_faces = _robin_except("x0") if robin else ()
-    stand = box(stand_L, stand_nodes, K_STEEL, RHO_C_STEEL, stand_faces)
-    stock = box(stock_L, stock_nodes, K_STEEL, RHO_C_STEEL, stock_faces)
+    mrng = np.random.default_rng(mesh_seed)
+    axes = [None, None]
+    if jitter > 0:
+        axes = [tuple(jittered_nodes(n, L, mrng, jitter) for n, L in zip(nodes, Ls))
+                for nodes, Ls in ((stand_nodes, stand_L), (stock_nodes, stock_L))]
+    stand = box(stand_L, stand_nodes, K_STEEL, RHO_C_STEEL, stand_faces, axes=axes[0])
+    stock = box(stock_L, stock_nodes, K_STEEL, RHO_C_STEEL, stock_faces, axes=axes[1])
+    if renumber:
+        prng = np.random.default_rng(mesh_seed + 1)
+        stand = permute(stand, prng.permutation(stand.n))
+        stock = permute(stock, prng.permutation(stock.n))
     f = stock.faces["x0"]
     cpl = Contact(fix_body=0, fix_face="x1", mov_body=1, mov_face="x0",
                   mov_u=f.u + y_offset, mov_v=f.v.copy(), alpha=alpha, friction_W=friction_W)
@@ -190,6 +206,14 @@ def box_patch_2673() -> Problem:
 def machine_310k(nsteps=120) -> Problem:
     """FP64 two-body machine, stand 41x41x161 + stock 31x31x41 (310,042 nodes)."""
     return machine(nsteps=nsteps, name="machine-310k")
+
+
+def machine_310k_irregular(nsteps=120, renumber=False) -> Problem:
+    """The 310,042-node machine on irregular tensor meshes (interior node
+    coordinates moved by up to 0.2 grid spacings); with renumber, every
+    body's nodes in a seeded random order."""
+    return machine(nsteps=nsteps, jitter=0.2, renumber=renumber,
+                   name="machine-310k-irregular" + ("-renumbered" if renumber else ""))
 
 
 def machine_310k_fp32(nsteps=120) -> Problem:

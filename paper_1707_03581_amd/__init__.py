@@ -18,6 +18,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5
 FP64, FP32_REFINE = 0, 1
 LOBATTO, EQUI_NOLEFT = 0, 1
 MULTIRATE, SINGLE_RATE = 0, 1
+OP_AUTO, OP_VALUES, OP_DICT, OP_PACKED, OP_PATTERNS, OP_COL32 = 0, 1, 2, 3, 4, 0x100
 FACE_TAGS = {"x0": 0, "x1": 1, "y0": 2, "y1": 3, "z0": 4, "z1": 5}
 _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOCONV: "ENOCONV",
           ESTATE: "ESTATE"}
@@ -35,14 +36,15 @@ class Config(C.Structure):
                 ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int), ("refine_rtol", C.c_double),
                 ("refine_maxit", C.c_int), ("inner_rtol", C.c_double),
                 ("final_residual", C.c_int), ("use_graph", C.c_int), ("sweep_tol", C.c_double),
-                ("method", C.c_int), ("stream", C.c_void_p)]
+                ("method", C.c_int), ("stream", C.c_void_p), ("op_form", C.c_int)]
 
 
 class Stats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("solves", C.c_int64), ("pcg_iters", C.c_int64),
                 ("refine_steps", C.c_int64), ("max_iters", C.c_int32),
                 ("redone_steps", C.c_int32), ("residual", C.c_double * 17),
-                ("wall_s", C.c_double), ("bytes_moved", C.c_int64), ("sweeps", C.c_int64)]
+                ("wall_s", C.c_double), ("bytes_moved", C.c_int64), ("sweeps", C.c_int64),
+                ("op_form", C.c_int32), ("col_bytes", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "residual"}

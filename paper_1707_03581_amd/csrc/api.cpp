@@ -92,6 +92,8 @@ struct mrsdc_ctx {
   int64_t matrix_bytes = 0;
   int64_t nnz = 0;
   int64_t batch_entries = 0;  // merged K and R entries of a batched operator
+  int op_form_used = 0;       // MRSDC_OP_* the CG product reads (single contexts)
+  int col_bytes = 0;          // 2: 16-bit column offsets, 4: int32 columns
   // event timing of kernel classes
   bool prof = false;
   std::vector<hipEvent_t> ev;   // pairs
@@ -205,6 +207,8 @@ bool valid_scheme(const mrsdc_config *cfg) {
   if (cfg->method == MRSDC_SINGLE_RATE && cfg->precision != MRSDC_FP64) return false;
   if (cfg->K < 0 || cfg->K > 16 || !(cfg->dt > 0) || !std::isfinite(cfg->dt)) return false;
   if (cfg->node_family != MRSDC_LOBATTO && cfg->node_family != MRSDC_EQUI_NOLEFT) return false;
+  if ((cfg->op_form & ~(0xff | MRSDC_OP_COL32)) != 0 || (cfg->op_form & 0xff) > MRSDC_OP_PATTERNS)
+    return false;
   if (cfg->precision != MRSDC_FP64 && cfg->precision != MRSDC_FP32_REFINE) return false;
   if (!(cfg->pcg_rtol > 0) || cfg->pcg_maxit < 1) return false;
   if (!(cfg->sweep_tol >= 0) || !std::isfinite(cfg->sweep_tol)) return false;
@@ -591,6 +595,10 @@ mrsdc_status prepare(mrsdc_ctx *c) {
     return fail(c, MRSDC_EINVAL, "batched contexts support the contact coupling only");
   if (batch && cfg.method != MRSDC_MULTIRATE)
     return fail(c, MRSDC_EINVAL, "batched contexts run the multi-rate method");
+  if (batch && cfg.op_form != MRSDC_OP_AUTO)
+    return fail(c, MRSDC_EINVAL, "batched contexts keep their own operator form (MRSDC_OP_AUTO)");
+  const int form = cfg.op_form & 0xff;  // requested operator form of the CG product
+  const bool want_dict = form == MRSDC_OP_AUTO || form >= MRSDC_OP_DICT;
 
   // ---- operator L = K + h R in SELL-64 ----
   const int64_t nslices = (N + kSlice - 1) / kSlice;
@@ -619,7 +627,7 @@ mrsdc_status prepare(mrsdc_ctx *c) {
     off[s + 1] = off[s] + w * kSlice;
   }
   const int64_t nelem = off[nslices];
-  const bool use16 = maxdelta <= 32767;
+  const bool use16 = maxdelta <= 32767 && !(cfg.op_form & MRSDC_OP_COL32);
   std::vector<double> val(nelem, 0.0);
   std::vector<float> val32;
   std::vector<int16_t> d16;
@@ -679,7 +687,7 @@ mrsdc_status prepare(mrsdc_ctx *c) {
   // value dictionary for the CG operator: exact, when the operator holds at
   // most kDictMax distinct values (bit patterns), as on structured meshes
   bool dict = false;
-  if (!batch) {
+  if (!batch && want_dict) {
     std::unordered_map<uint64_t, int> keys;
     std::vector<uint8_t> vid(nelem);
     std::vector<double> vdict;
@@ -705,7 +713,7 @@ mrsdc_status prepare(mrsdc_ctx *c) {
       d.op.vid = pv;
       d.op.vdict = pd;
       d.op.ndict = (int)vdict.size();
-      if (use16) {  // row patterns
+      if (use16 && (form == MRSDC_OP_AUTO || form == MRSDC_OP_PATTERNS)) {  // row patterns
         std::map<std::vector<int>, int> forms;
         std::vector<uint8_t> rcls(N, 0);
         std::vector<std::vector<int>> list;
@@ -750,7 +758,8 @@ mrsdc_status prepare(mrsdc_ctx *c) {
           d.op.cw = cw;
         }
       }
-      if (use16 && maxdelta <= 2047 && vdict.size() <= 16) {
+      if (use16 && maxdelta <= 2047 && vdict.size() <= 16 &&
+          (form == MRSDC_OP_AUTO || form == MRSDC_OP_PACKED)) {
         std::vector<int16_t> pk(nelem);
         for (int64_t e = 0; e < nelem; ++e) pk[e] = (int16_t)(d16[e] * 16 + vid[e]);
         int16_t *pp;
@@ -765,6 +774,19 @@ mrsdc_status prepare(mrsdc_ctx *c) {
         d.op.vdict32 = pf;
       }
     }
+  }
+  if (!batch) {
+    c->op_form_used = d.op.rcls ? MRSDC_OP_PATTERNS
+                      : d.op.pk16 ? MRSDC_OP_PACKED
+                      : d.op.vid ? MRSDC_OP_DICT
+                                 : MRSDC_OP_VALUES;
+    c->col_bytes = use16 ? 2 : 4;
+    if (form != MRSDC_OP_AUTO && form != c->op_form_used)
+      return fail(c, MRSDC_EINVAL,
+                  "operator form %d does not apply to this operator (%zu-value limit, %d row forms,"
+                  " |col - row| up to %lld)",
+                  form, form == MRSDC_OP_PACKED ? (size_t)16 : (size_t)kDictMax, kMaxCls,
+                  (long long)maxdelta);
   }
   c->matrix_bytes = nnz_total * (8 + (use16 ? 2 : 4)) + 8 * (nslices + 1);
   c->nnz = nnz_total;
@@ -1445,6 +1467,8 @@ mrsdc_status mrsdc_advance(mrsdc_ctx *c, double horizon, mrsdc_stats *stats) {
   auto t0 = std::chrono::steady_clock::now();
   mrsdc_stats acc;
   std::memset(&acc, 0, sizeof acc);
+  acc.op_form = c->op_form_used;
+  acc.col_bytes = c->col_bytes;
   const int Kc = c->cfg.K;
   for (int64_t n = 0; n < nsteps; ++n) {
     for (;;) {
