@@ -72,7 +72,16 @@ typedef struct {
   int refine_maxit;   /* FP32_REFINE: outer refinement cap per solve */
   double inner_rtol;  /* FP32_REFINE: relative tolerance of each FP32 inner solve */
   int final_residual; /* nonzero: also evaluate the residual of the last sweep */
-  int use_graph;      /* reserved, keep 0 */
+  int use_graph;      /* nonzero: each time step is captured once into a HIP graph
+                         and replayed (one launch per step instead of hundreds);
+                         the learned CG launch budgets then only grow, and the
+                         step is captured again when one does (a converged
+                         solve's spare launches return at once:
+                         FP64 results bit for bit those of use_graph = 0; in
+                         FP32_REFINE an inner solve that a smaller budget would
+                         have cut short runs on to its tolerance).  Needs a stream
+                         that can be captured: with the legacy default stream
+                         the context runs without graphs. */
   double sweep_tol;   /* > 0: residual control, a step stops sweeping once the
                          residual (eq. residual, max-norm) of its latest iterate
                          is <= sweep_tol (at most K sweeps; §3 states that each
@@ -131,6 +140,8 @@ typedef struct {
   int32_t op_form;         /* operator form the CG product read (MRSDC_OP_VALUES ..
                               MRSDC_OP_PATTERNS; 0 in batched contexts) */
   int32_t col_bytes;       /* bytes per stored column: 2 (offset) or 4 (int32) */
+  int32_t graph_captures;  /* steps captured into a HIP graph in this call (use_graph) */
+  int32_t graph_launches;  /* graph launches (steps replayed) in this call */
 } mrsdc_stats;
 
 /* Fill *cfg with defaults: FP64, Lobatto M=3, P=2, K=2, dt=1, pcg_rtol 1e-13. */
@@ -219,6 +230,16 @@ mrsdc_status mrsdc_get_temperature_device(mrsdc_ctx *ctx, int body, void *dptr, 
 
 /* Device bytes the context holds once prepared (operators, states, caches). */
 mrsdc_status mrsdc_footprint_bytes(const mrsdc_ctx *ctx, int64_t *bytes);
+
+/* Split of a prepared batched context's footprint for admission by HBM
+ * footprint (a serving loop keeps each request's node states resident):
+ * *per_scenario = device bytes that grow with the scenario count, per
+ * scenario (node states T_m, F_j, I_m, CG vectors, interface caches and
+ * coefficient tables, reduction partials); *shared = the rest (operators,
+ * tiles, weights), held once.  footprint = shared + S * per_scenario, up to
+ * the rounding of the division.  ESTATE for a single or unprepared context. */
+mrsdc_status mrsdc_batch_slot_bytes(const mrsdc_ctx *ctx, int64_t *per_scenario,
+                                    int64_t *shared);
 
 /* Description of the last error of this context ("" if none). */
 const char *mrsdc_last_error(const mrsdc_ctx *ctx);
@@ -321,6 +342,7 @@ typedef struct {
   int64_t nblocks;      /* ceil(n / b) */
   int64_t factor_bytes; /* device bytes of the W_k */
   double factor_ms;     /* wall time of the factorisation (device work included) */
+  int64_t factor_launches; /* kernels the factorisation launched */
 } mrsdc_deform_info;
 
 /* Register the deformation problem of `body` and factorise it on the device

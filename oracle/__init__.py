@@ -87,6 +87,7 @@ def lib():
         L.orc_run.argtypes = [P, P, C.c_double, C.c_int, P, P, P]
         L.orc_stationary.argtypes = [P, P, C.c_double, C.c_int]
         L.orc_max_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -228,3 +229,8 @@ def run(pb, nsteps=None, T0=None, t0=None, residuals=False, scheme=None, **over)
 
 def max_threads() -> int:
     return lib().orc_max_threads()
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's later calls."""
+    lib().orc_set_threads(int(n))

@@ -50,6 +50,15 @@ int orc_max_threads(void) {
 #endif
 }
 
+/* threads of the following parallel regions (timing at a stated core count) */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Quadrature (§3, Multi-rate SDC: node sets and weight definitions)         */
 /* ------------------------------------------------------------------------ */

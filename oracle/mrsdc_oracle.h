@@ -119,6 +119,7 @@ int orc_run(const orc_problem *pb, const orc_scheme *sc, double t0, int nsteps,
 int orc_stationary(const orc_problem *pb, double *T, double rtol, int maxit);
 
 int orc_max_threads(void);
+void orc_set_threads(int n);
 
 #ifdef __cplusplus
 }

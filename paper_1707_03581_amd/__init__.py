@@ -44,7 +44,8 @@ class Stats(C.Structure):
                 ("refine_steps", C.c_int64), ("max_iters", C.c_int32),
                 ("redone_steps", C.c_int32), ("residual", C.c_double * 17),
                 ("wall_s", C.c_double), ("bytes_moved", C.c_int64), ("sweeps", C.c_int64),
-                ("op_form", C.c_int32), ("col_bytes", C.c_int32)]
+                ("op_form", C.c_int32), ("col_bytes", C.c_int32),
+                ("graph_captures", C.c_int32), ("graph_launches", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "residual"}
@@ -85,6 +86,8 @@ _SIGS = {
     "mrsdc_get_temperature_device": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int64,
                                                C.c_void_p]),
     "mrsdc_footprint_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "mrsdc_batch_slot_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64),
+                                         C.POINTER(C.c_int64)]),
     "mrsdc_last_error": (C.c_char_p, [C.c_void_p]),
     "mrsdc_destroy": (C.c_int, [C.c_void_p]),
     "mrsdc_quadrature": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double, C.c_void_p, C.c_void_p,
@@ -116,7 +119,8 @@ _SIGS = {
 
 class DeformInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("block", C.c_int64), ("padded_block", C.c_int64),
-                ("nblocks", C.c_int64), ("factor_bytes", C.c_int64), ("factor_ms", C.c_double)]
+                ("nblocks", C.c_int64), ("factor_bytes", C.c_int64), ("factor_ms", C.c_double),
+                ("factor_launches", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -355,6 +359,13 @@ class BatchContext(Context):
         st = Stats()
         self._chk(self._L.mrsdc_batch_advance(self._h, nsteps, C.byref(st)))
         return st.as_dict()
+
+    def slot_bytes(self):
+        """(device bytes per scenario slot, shared device bytes) of the
+        prepared context."""
+        a, b = C.c_int64(), C.c_int64()
+        self._chk(self._L.mrsdc_batch_slot_bytes(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def get_scenario_temperature(self, s, n):
         out = np.empty(n)

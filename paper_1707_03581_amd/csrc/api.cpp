@@ -79,6 +79,7 @@ struct mrsdc_ctx {
   bool own_stream = false;
   std::vector<void *> allocs;
   int64_t footprint = 0;
+  int64_t scen_bytes = 0;  // part of footprint that grows with the scenario count
   DevState d;
   Weights w;
   int nbody = 0;
@@ -92,6 +93,11 @@ struct mrsdc_ctx {
   int64_t matrix_bytes = 0;
   int64_t nnz = 0;
   int64_t batch_entries = 0;  // merged K and R entries of a batched operator
+  // captured time step (use_graph): valid for the budgets in graph_key
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<int> graph_key;
+  bool graph_off = false;
+  int64_t graph_captures = 0, graph_replays = 0;
   int op_form_used = 0;       // MRSDC_OP_* the CG product reads (single contexts)
   int col_bytes = 0;          // 2: 16-bit column offsets, 4: int32 columns
   // event timing of kernel classes
@@ -120,6 +126,7 @@ struct mrsdc_ctx {
   std::vector<void *> df_allocs;
   int64_t df_bytes = 0;
   double df_factor_ms = 0.0;
+  int64_t df_dispatches = 0;  // kernels the factorisation launched
 };
 
 namespace {
@@ -148,8 +155,10 @@ bool finite_all(const double *p, int64_t n) {
   return true;
 }
 
+// per_scenario: the allocation grows with the batch's scenario count (its
+// bytes are counted apart for admission by footprint)
 template <typename T>
-mrsdc_status dalloc(mrsdc_ctx *c, T **p, size_t count) {
+mrsdc_status dalloc(mrsdc_ctx *c, T **p, size_t count, bool per_scenario = false) {
   void *q = nullptr;
   size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
   hipError_t e = hipMalloc(&q, bytes);
@@ -159,13 +168,14 @@ mrsdc_status dalloc(mrsdc_ctx *c, T **p, size_t count) {
   }
   c->allocs.push_back(q);
   c->footprint += (int64_t)bytes;
+  if (per_scenario) c->scen_bytes += (int64_t)bytes;
   *p = static_cast<T *>(q);
   return MRSDC_OK;
 }
 
 template <typename T>
-mrsdc_status upload(mrsdc_ctx *c, T **p, const std::vector<T> &h) {
-  mrsdc_status s = dalloc(c, p, h.size());
+mrsdc_status upload(mrsdc_ctx *c, T **p, const std::vector<T> &h, bool per_scenario = false) {
+  mrsdc_status s = dalloc(c, p, h.size(), per_scenario);
   if (s) return s;
   if (!h.empty()) HIPCHK(hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
   return MRSDC_OK;
@@ -194,9 +204,14 @@ void free_device(mrsdc_ctx *c) {
     }
     c->dirty_T = true;
   }
+  // a captured step refers to the buffers freed below
+  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+  c->graph_exec = nullptr;
+  c->graph_key.clear();
   for (void *p : c->allocs) hipFree(p);
   c->allocs.clear();
   c->footprint = 0;
+  c->scen_bytes = 0;
   c->prepared = false;
 }
 
@@ -497,21 +512,21 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
     t[s] = c->sc_t[s];
     act[s] = c->sc_active[s];
   }
-  if ((st = upload(c, &pv, h))) return st;
+  if ((st = upload(c, &pv, h, true))) return st;
   a.h = pv;
-  if ((st = upload(c, &pv, al))) return st;
+  if ((st = upload(c, &pv, al, true))) return st;
   a.alpha = pv;
-  if ((st = upload(c, &pv, pf))) return st;
+  if ((st = upload(c, &pv, pf, true))) return st;
   a.Pf = pv;
-  if ((st = upload(c, &pv, per))) return st;
+  if ((st = upload(c, &pv, per, true))) return st;
   a.period = pv;
-  if ((st = upload(c, &pv, t))) return st;
+  if ((st = upload(c, &pv, t, true))) return st;
   a.tn = pv;
   if ((st = dalloc(c, &a.sc, 1))) return st;
   HIPCHK(hipMemset(a.sc, 0, sizeof(BatchScalars)));
   HIPCHK(hipMemcpy(a.sc->active, act.data(), sizeof(int) * S, hipMemcpyHostToDevice));
   if ((st = dalloc(c, &a.partial,
-                   3 * (size_t)std::max(a.grid, std::max(a.sgrid64, a.sgrid32)) * S)))
+                   3 * (size_t)std::max(a.grid, std::max(a.sgrid64, a.sgrid32)) * S, true)))
     return st;
   if ((st = dalloc(c, &c->stage, N))) return st;
   a.w = d.w;
@@ -531,9 +546,9 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
     // inner vectors and the FP64 refinement residual, scenario-interleaved
     a.fp32 = 1;
     const size_t NS = (size_t)N * S;
-    if ((st = dalloc(c, &a.x32, NS)) || (st = dalloc(c, &a.r32, NS)) ||
-        (st = dalloc(c, &a.p32, NS)) || (st = dalloc(c, &a.q32, NS)) ||
-        (st = dalloc(c, &a.r64, NS)))
+    if ((st = dalloc(c, &a.x32, NS, true)) || (st = dalloc(c, &a.r32, NS, true)) ||
+        (st = dalloc(c, &a.p32, NS, true)) || (st = dalloc(c, &a.q32, NS, true)) ||
+        (st = dalloc(c, &a.r64, NS, true)))
       return st;
     HIPCHK(hipMemset(a.x32, 0, NS * sizeof(float)));
     HIPCHK(hipMemset(a.r32, 0, NS * sizeof(float)));
@@ -843,15 +858,16 @@ mrsdc_status prepare(mrsdc_ctx *c) {
   for (int m = 0; m <= cfg.M; ++m) {
     if (lob && m == 1) {
       d.T[1] = d.T[0];
-    } else if ((st = dalloc(c, &d.T[m], NS))) {
+    } else if ((st = dalloc(c, &d.T[m], NS, true))) {
       return st;
     }
-    if (m >= 1 && (st = dalloc(c, &d.F[m], NS))) return st;
-    if (m >= 1 && c->w.dtau[m] != 0.0 && (st = dalloc(c, &d.I[m], NS))) return st;
+    if (m >= 1 && (st = dalloc(c, &d.F[m], NS, true))) return st;
+    if (m >= 1 && c->w.dtau[m] != 0.0 && (st = dalloc(c, &d.I[m], NS, true))) return st;
   }
   if (!(batch && fp32) &&
-      ((st = dalloc(c, &d.r, NS)) || (st = dalloc(c, &d.p, NS)) || (st = dalloc(c, &d.q, NS)) ||
-       (!batch && ((st = dalloc(c, &d.u, NS)) || (st = dalloc(c, &d.s, NS))))))
+      ((st = dalloc(c, &d.r, NS, true)) || (st = dalloc(c, &d.p, NS, true)) ||
+       (st = dalloc(c, &d.q, NS, true)) ||
+       (!batch && ((st = dalloc(c, &d.u, NS, true)) || (st = dalloc(c, &d.s, NS, true))))))
     return st;
   if (batch) {  // inactive scenarios keep finite zeros
     for (int m = 0; m <= cfg.M; ++m) {
@@ -987,20 +1003,21 @@ mrsdc_status prepare(mrsdc_ctx *c) {
     if ((st = upload(c, &pi, ifpos))) return st;
     d.ifpos = pi;
     const size_t ncache = (size_t)(cfg.M + 1) * (cfg.P + 1) * f.n_if * S;
-    if ((st = dalloc(c, &d.Eold, ncache)) || (st = dalloc(c, &d.Enew, ncache)))
+    if ((st = dalloc(c, &d.Eold, ncache, true)) || (st = dalloc(c, &d.Enew, ncache, true)))
       return st;
     HIPCHK(hipMemset(d.Eold, 0, ncache * sizeof(double)));
     HIPCHK(hipMemset(d.Enew, 0, ncache * sizeof(double)));
-    if ((st = dalloc(c, &d.Tbuf[0], (size_t)f.n_if * S)) ||
-        (st = dalloc(c, &d.Tbuf[1], (size_t)f.n_if * S)) || (st = dalloc(c, &d.fst, (size_t)f.n_if * S)))
+    if ((st = dalloc(c, &d.Tbuf[0], (size_t)f.n_if * S, true)) ||
+        (st = dalloc(c, &d.Tbuf[1], (size_t)f.n_if * S, true)) ||
+        (st = dalloc(c, &d.fst, (size_t)f.n_if * S, true)))
       return st;
     if (d.single_rate &&
         ((st = dalloc(c, &d.ifc_lin, (size_t)f.n_if)) || (st = dalloc(c, &d.ifc_src, (size_t)f.n_if))))
       return st;
     if (!batch && !d.single_rate && (st = dalloc(c, &d.Ipre, ncache))) return st;
     const size_t ntab = (size_t)(cfg.M + 1) * (cfg.P + 1) * S;
-    if ((st = dalloc(c, &d.coefD, ntab * coef_table_doubles(f))) ||
-        (st = dalloc(c, &d.coefI, ntab * coef_table_ints(f))))
+    if ((st = dalloc(c, &d.coefD, ntab * coef_table_doubles(f), true)) ||
+        (st = dalloc(c, &d.coefI, ntab * coef_table_ints(f), true)))
       return st;
   }
   if (!c->ctr_host) HIPCHK(hipHostMalloc((void **)&c->ctr_host, sizeof(StepCounters), 0));
@@ -1084,6 +1101,19 @@ int enqueue_cg(mrsdc_ctx *c, int slot, int m, bool fp32, bool defer = false) {
 // One implicit node solve of interval m (x = T[m] in place).  defer: an FP64
 // solve leaves its final check to the caller and returns its launch budget
 // (-1 when nothing is left to check).
+// Learned launch budgets.  Without graphs a slot's budget follows its recent
+// iteration counts both ways; with a captured step it only grows, so the
+// captured launch sequence stays valid (a converged solve's spare launches
+// return at once) and the step is re-captured only when a budget grows.
+void learn_budget(mrsdc_ctx *c, int i, int v) {
+  v = std::min(c->cfg.pcg_maxit, v);
+  c->budget[i] = c->cfg.use_graph ? std::max(c->budget[i], v) : v;
+}
+void learn_rounds(mrsdc_ctx *c, int i, int v) {
+  v = std::min(c->cfg.refine_maxit, v);
+  c->rounds[i] = c->cfg.use_graph ? std::max(c->rounds[i], v) : v;
+}
+
 int enqueue_solve(mrsdc_ctx *c, int k, int m, bool defer = false) {
   const DevState &d = c->d;
   const mrsdc_config &cfg = c->cfg;
@@ -1247,6 +1277,46 @@ void enqueue_batch_step(mrsdc_ctx *c) {
     std::swap(a.Eold, a.Enew);
   }
   blaunch_commit(a, c->cfg.dt, st);
+}
+
+// One time step on the context's stream: its launches directly, or (use_graph)
+// the step captured once into a HIP graph and replayed while the launch
+// budgets stay as they were at capture.  A stream that cannot be captured
+// (the legacy default stream) turns graphs off for the context.
+hipError_t run_step(mrsdc_ctx *c, void (*enqueue)(mrsdc_ctx *)) {
+  if (!c->cfg.use_graph || c->graph_off || c->prof) {
+    enqueue(c);
+    return hipGetLastError();
+  }
+  std::vector<int> key(c->budget, c->budget + kSlots);
+  key.insert(key.end(), c->rounds, c->rounds + kSlots);
+  if (!c->graph_exec || key != c->graph_key) {
+    if (c->graph_exec) {
+      hipGraphExecDestroy(c->graph_exec);
+      c->graph_exec = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      hipGetLastError();
+      c->graph_off = true;
+      enqueue(c);
+      return hipGetLastError();
+    }
+    enqueue(c);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->stream, &g);
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      c->graph_exec = nullptr;
+      return e;
+    }
+    c->graph_key = key;
+    c->graph_captures++;
+  }
+  c->graph_replays++;
+  return hipGraphLaunch(c->graph_exec, c->stream);
 }
 
 }  // namespace
@@ -1469,12 +1539,11 @@ mrsdc_status mrsdc_advance(mrsdc_ctx *c, double horizon, mrsdc_stats *stats) {
   std::memset(&acc, 0, sizeof acc);
   acc.op_form = c->op_form_used;
   acc.col_bytes = c->col_bytes;
+  const int64_t cap0 = c->graph_captures, rep0 = c->graph_replays;
   const int Kc = c->cfg.K;
   for (int64_t n = 0; n < nsteps; ++n) {
     for (;;) {
-      if (c->d.single_rate) enqueue_step_single(c);
-      else enqueue_step(c);
-      HIPCHK(hipGetLastError());
+      HIPCHK(run_step(c, c->d.single_rate ? enqueue_step_single : enqueue_step));
       HIPCHK(hipMemcpyAsync(c->ctr_host, c->d.ctr, sizeof(StepCounters), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(hipStreamSynchronize(c->stream));
       const StepCounters &h = *c->ctr_host;
@@ -1494,7 +1563,7 @@ mrsdc_status mrsdc_advance(mrsdc_ctx *c, double horizon, mrsdc_stats *stats) {
             // solve that still runs out repeats the step with a doubled
             // budget; FP32: an inner solve cut short leaves the rest to the
             // refinement, and its budget doubles)
-            c->budget[i] = std::min(c->cfg.pcg_maxit, std::max(it, c->last_it[i]) + 1);
+            learn_budget(c, i, std::max(it, c->last_it[i]) + 1);
             c->last_it[i] = it;
             c->expect[i] = it;
           } else if (it < 0 && fp32 && c->budget[i] < c->cfg.pcg_maxit) {
@@ -1503,7 +1572,7 @@ mrsdc_status mrsdc_advance(mrsdc_ctx *c, double horizon, mrsdc_stats *stats) {
           if (fp32 && h.slot_rounds[i] > 0) {
             // the larger of the slot's last two round counts; a solve that
             // needs more repeats the step with twice the rounds
-            c->rounds[i] = std::min(c->cfg.refine_maxit, std::max(h.slot_rounds[i], c->last_rounds[i]));
+            learn_rounds(c, i, std::max(h.slot_rounds[i], c->last_rounds[i]));
             c->last_rounds[i] = h.slot_rounds[i];
           }
         }
@@ -1552,12 +1621,18 @@ mrsdc_status mrsdc_advance(mrsdc_ctx *c, double horizon, mrsdc_stats *stats) {
   acc.bytes_moved = acc.pcg_iters * (c->times.cg_spmv_bytes + 88 * N) + acc.solves * 64 * N +
                     nsteps * Kc * (c->matrix_bytes + 16 * (int64_t)c->cfg.M * N +
                                    8 * (3 * (int64_t)c->cfg.M + 2) * N);
+  acc.graph_captures = (int32_t)(c->graph_captures - cap0);
+  acc.graph_launches = (int32_t)(c->graph_replays - rep0);
   if (stats) *stats = acc;
   return MRSDC_OK;
 }
 
-mrsdc_status mrsdc_set_stationary(mrsdc_ctx *c, double rtol, int maxit, int *iters) {
-  if (!c) return MRSDC_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Checks and device preparation shared by both stationary entry points.
+mrsdc_status stationary_begin(mrsdc_ctx *c, double rtol, int maxit, int *iters) {
   if (iters) *iters = 0;
   if (c->S > 0) return fail(c, MRSDC_ESTATE, "batched context: set each scenario's field instead");
   if (!(rtol > 0) || !std::isfinite(rtol) || maxit < 1)
@@ -1582,8 +1657,45 @@ mrsdc_status mrsdc_set_stationary(mrsdc_ctx *c, double rtol, int maxit, int *ite
       c->dirty_T = true;
     }
   }
-  mrsdc_status st = prepare(c);
+  return MRSDC_OK;
+}
+
+// Jacobi-PCG on (K + h R) T = g from the current field, with the Jacobi
+// inverse ddinv of L and a zero mass vector dzero (device, N values each).
+mrsdc_status stationary_iterate(mrsdc_ctx *c, double rtol, int maxit, int *iters,
+                                const double *ddinv, const double *dzero) {
+  hipError_t he;
+  launch_clear_counters(c->d, c->stream);
+  if ((he = hipMemsetAsync(c->d.sc, 0, sizeof(SolveScalars), c->stream)))
+    return fail(c, MRSDC_EDEVICE, "HIP: %s", hipGetErrorString(he));
+  launch_stationary_init(c->d, dzero, ddinv, 0, rtol, c->stream);
+  SolveScalars sc;
+  int it = 0;
+  for (;;) {
+    if ((he = hipMemcpyAsync(&sc, c->d.sc, sizeof sc, hipMemcpyDeviceToHost, c->stream)) ||
+        (he = hipStreamSynchronize(c->stream)))
+      return fail(c, MRSDC_EDEVICE, "HIP: %s", hipGetErrorString(he));
+    if (sc.done) break;
+    if (it >= maxit)
+      return fail(c, MRSDC_ENOCONV, "stationary solve did not converge in %d iterations", maxit);
+    const int n = std::min(64, maxit - it);
+    launch_stationary_iters(c->d, dzero, ddinv, 0, it, n, maxit - 1, c->stream);
+    if ((he = hipGetLastError())) return fail(c, MRSDC_EDEVICE, "HIP: %s", hipGetErrorString(he));
+    it += n;
+  }
+  if (iters) *iters = sc.iters;
+  return MRSDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mrsdc_status mrsdc_set_stationary(mrsdc_ctx *c, double rtol, int maxit, int *iters) {
+  if (!c) return MRSDC_EINVAL;
+  mrsdc_status st = stationary_begin(c, rtol, maxit, iters);
   if (st) return st;
+  if ((st = prepare(c))) return st;
   if ((st = upload_T(c))) return st;
   // Jacobi inverse of L = K + h R and a zero mass vector
   const int64_t N = c->d.N;
@@ -1608,36 +1720,17 @@ mrsdc_status mrsdc_set_stationary(mrsdc_ctx *c, double rtol, int maxit, int *ite
     hipGetLastError();
     return fail(c, MRSDC_ENOMEM, "device allocation failed");
   }
-  auto hipfail = [&](hipError_t e) {
-    release();
-    return fail(c, MRSDC_EDEVICE, "HIP: %s", hipGetErrorString(e));
-  };
   hipError_t he;
   if ((he = hipMemcpy(ddinv, dinv.data(), sizeof(double) * N, hipMemcpyHostToDevice)) ||
-      (he = hipMemset(dzero, 0, sizeof(double) * N)))
-    return hipfail(he);
-  launch_clear_counters(c->d, c->stream);
-  if ((he = hipMemsetAsync(c->d.sc, 0, sizeof(SolveScalars), c->stream))) return hipfail(he);
-  launch_stationary_init(c->d, dzero, ddinv, 0, rtol, c->stream);
-  SolveScalars sc;
-  int it = 0;
-  for (;;) {
-    if ((he = hipMemcpyAsync(&sc, c->d.sc, sizeof sc, hipMemcpyDeviceToHost, c->stream)) ||
-        (he = hipStreamSynchronize(c->stream)))
-      return hipfail(he);
-    if (sc.done) break;
-    if (it >= maxit) {
-      release();
-      return fail(c, MRSDC_ENOCONV, "stationary solve did not converge in %d iterations", maxit);
-    }
-    const int n = std::min(64, maxit - it);
-    launch_stationary_iters(c->d, dzero, ddinv, 0, it, n, maxit - 1, c->stream);
-    if ((he = hipGetLastError())) return hipfail(he);
-    it += n;
+      (he = hipMemset(dzero, 0, sizeof(double) * N))) {
+    release();
+    return fail(c, MRSDC_EDEVICE, "HIP: %s", hipGetErrorString(he));
   }
-  if (iters) *iters = sc.iters;
+  st = stationary_iterate(c, rtol, maxit, iters, ddinv, dzero);
+  // the loop above synchronised the stream (or failed): nothing still reads them
+  hipStreamSynchronize(c->stream);
   release();
-  return MRSDC_OK;
+  return st;
 }
 
 mrsdc_status mrsdc_get_temperature(mrsdc_ctx *c, int body, double *out, int64_t n) {
@@ -1724,6 +1817,15 @@ mrsdc_status mrsdc_time_operator(mrsdc_ctx *c, int reps, double *avg_us, int64_t
 mrsdc_status mrsdc_footprint_bytes(const mrsdc_ctx *c, int64_t *bytes) {
   if (!c || !bytes) return MRSDC_EINVAL;
   *bytes = c->footprint;
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_batch_slot_bytes(const mrsdc_ctx *c, int64_t *per_scenario, int64_t *shared) {
+  if (!c || !per_scenario || !shared) return MRSDC_EINVAL;
+  if (c->S <= 0) return MRSDC_ESTATE;
+  if (!c->prepared) return MRSDC_ESTATE;
+  *per_scenario = (c->scen_bytes + c->S - 1) / c->S;
+  *shared = c->footprint - c->scen_bytes;
   return MRSDC_OK;
 }
 
@@ -1829,6 +1931,7 @@ mrsdc_status mrsdc_batch_advance(mrsdc_ctx *c, int nsteps, mrsdc_stats *stats) {
   auto t0 = std::chrono::steady_clock::now();
   mrsdc_stats acc;
   std::memset(&acc, 0, sizeof acc);
+  const int64_t cap0 = c->graph_captures, rep0 = c->graph_replays;
   const int S = c->S, Kc = c->cfg.K;
   for (int n = 0; n < nsteps; ++n) {
     if (c->batch_joined) {
@@ -1839,8 +1942,7 @@ mrsdc_status mrsdc_batch_advance(mrsdc_ctx *c, int nsteps, mrsdc_stats *stats) {
       c->batch_joined = false;
     }
     for (;;) {
-      enqueue_batch_step(c);
-      HIPCHK(hipGetLastError());
+      HIPCHK(run_step(c, enqueue_batch_step));
       HIPCHK(hipMemcpyAsync(c->bsc_host, c->ba.sc, sizeof(BatchScalars), hipMemcpyDeviceToHost,
                             c->stream));
       HIPCHK(hipStreamSynchronize(c->stream));
@@ -1866,12 +1968,12 @@ mrsdc_status mrsdc_batch_advance(mrsdc_ctx *c, int nsteps, mrsdc_stats *stats) {
             if (c->budget[i] < c->cfg.pcg_maxit)
               c->budget[i] = std::min(c->cfg.pcg_maxit, 2 * c->budget[i]);
           } else if (mx > 0) {
-            c->budget[i] = std::min(c->cfg.pcg_maxit, std::max(mx, c->last_it[i]) + 1);
+            learn_budget(c, i, std::max(mx, c->last_it[i]) + 1);
             c->last_it[i] = mx;
             c->expect[i] = mx;
           }
           if (fp32 && rmx > 0) {
-            c->rounds[i] = std::min(c->cfg.refine_maxit, std::max(rmx, c->last_rounds[i]));
+            learn_rounds(c, i, std::max(rmx, c->last_rounds[i]));
             c->last_rounds[i] = rmx;
           }
           acc.max_iters = std::max(acc.max_iters, mx);
@@ -1926,6 +2028,8 @@ mrsdc_status mrsdc_batch_advance(mrsdc_ctx *c, int nsteps, mrsdc_stats *stats) {
   acc.steps = nsteps;
   acc.solves = (int64_t)nsteps * nint * (Kc + 1) * nact;
   acc.wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  acc.graph_captures = (int32_t)(c->graph_captures - cap0);
+  acc.graph_launches = (int32_t)(c->graph_replays - rep0);
   if (stats) *stats = acc;
   return MRSDC_OK;
 }
@@ -2139,9 +2243,16 @@ mrsdc_status mrsdc_deform_setup(mrsdc_ctx *c, int body, int64_t n, int64_t nnz,
     D.part = (double *)q;
   }
   auto t0 = std::chrono::steady_clock::now();
-  deform_factor(D, c->stream);
-  he = hipGetLastError();
-  if (he != hipSuccess) { df_release(c); return fail(c, MRSDC_EDEVICE, "factorisation launch: %s", hipGetErrorString(he)); }
+  int64_t dispatches = 0;
+  he = deform_factor(D, c->stream, &dispatches);
+  if (he != hipSuccess) {
+    hipStreamSynchronize(c->stream);
+    df_release(c);
+    return fail(c, he == hipErrorInvalidValue ? MRSDC_EINVAL : MRSDC_EDEVICE,
+                "factorisation (after %lld launches): %s", (long long)dispatches,
+                hipGetErrorString(he));
+  }
+  c->df_dispatches = dispatches;
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, D.flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -2201,6 +2312,7 @@ mrsdc_status mrsdc_deform_get_info(const mrsdc_ctx *c, mrsdc_deform_info *out) {
   out->nblocks = c->df.nblk;
   out->factor_bytes = c->df.nblk * c->df.bp * c->df.bp * (int64_t)sizeof(double);
   out->factor_ms = c->df_factor_ms;
+  out->factor_launches = c->df_dispatches;
   return MRSDC_OK;
 }
 

@@ -805,45 +805,143 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_a(BatchArgs a, int m, double dt
 }
 
 
-// (b) x += alpha p; r -= alpha q; partial r.z, r.r
-template <typename V>
-__global__ __launch_bounds__(kBlock) void kb_pcg_b(BatchArgs a, int m, double dtau) {
-  const int s = threadIdx.x & 63, S = a.S;
-  double v[2] = {0.0, 0.0};
-  if (lane_on(a.sc, s, S)) {
-    const double h = a.h[s];
-    const V alpha = (V)a.sc->alpha[s];
-    V *x = BV<V>::x(a, m), *rv = BV<V>::r(a);
-    const V *p = BV<V>::p(a), *q = BV<V>::q(a);
-    for (RowRange rr = xcd_rows(a.N); rr.row < rr.end; rr.row += kRowsAhead * rr.stride) {
-      V xs[kRowsAhead], ps[kRowsAhead], qs[kRowsAhead], rs[kRowsAhead];
-      double di[kRowsAhead];
+// ---------------------------------------------------------------------------
+// Row-group kernels: the CG vector updates with the lane mapping of the tiled
+// kernels (a lane owns VEC consecutive scenarios of a row, a wave RPW
+// consecutive rows at once), so each load moves 16 bytes per lane and a wave
+// touches RPW whole scenario lines.  Groups of RPW rows are dealt per XCD like
+// the rows of xcd_rows; a lane's partial sums run over its own rows in
+// sequence, whatever S is.
+// ---------------------------------------------------------------------------
+struct GroupRange {
+  int64_t g, end, stride;
+};
+__device__ inline GroupRange xcd_groups(int64_t G) {
+  const int xcd = blockIdx.x % kXcd, local = blockIdx.x / kXcd, per = gridDim.x / kXcd;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  GroupRange r;
+  r.g = G * xcd / kXcd + (int64_t)local * (kBlock / 64) + w;
+  r.end = G * (xcd + 1) / kXcd;
+  r.stride = (int64_t)per * (kBlock / 64);
+  return r;
+}
+constexpr int kGroupsAhead = 4;  // row groups of a lane in flight
+
+// VEC values of scenarios s0.. of element base (AL: one 16-byte access; else
+// element by element, lanes past S untouched)
+template <typename V, int VEC, bool AL>
+__device__ __forceinline__ void vload(const V *p, int64_t base, int s0, int S, V (&o)[VEC]) {
+  if constexpr (AL) {
+    if constexpr (VEC == 4) {
+      const float4 f = *reinterpret_cast<const float4 *>(p + base);
+      o[0] = f.x; o[1] = f.y; o[2] = f.z; o[3] = f.w;
+    } else {
+      const double2 d = *reinterpret_cast<const double2 *>(p + base);
+      o[0] = d.x; o[1] = d.y;
+    }
+  } else {
 #pragma unroll
-      for (int u = 0; u < kRowsAhead; ++u) {
-        const int64_t row = rr.row + u * rr.stride;
-        if (row >= rr.end) continue;
-        const int64_t i = row * S + s;
-        xs[u] = x[i];
-        ps[u] = p[i];
-        qs[u] = q[i];
-        rs[u] = rv[i];
-        di[u] = bdinv(a, row, h, dtau);
+    for (int k = 0; k < VEC; ++k) o[k] = s0 + k < S ? p[base + k] : (V)0;
+  }
+}
+template <typename V, int VEC, bool AL>
+__device__ __forceinline__ void vstore(V *p, int64_t base, int s0, int S, const V (&o)[VEC]) {
+  if constexpr (AL) {
+    if constexpr (VEC == 4) {
+      *reinterpret_cast<float4 *>(p + base) = make_float4(o[0], o[1], o[2], o[3]);
+    } else {
+      *reinterpret_cast<double2 *>(p + base) = make_double2(o[0], o[1]);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < VEC; ++k)
+      if (s0 + k < S) p[base + k] = o[k];
+  }
+}
+
+// per-scenario block sums of the lanes' partials (v[k][i] for scenario s0 + i)
+// into partial[k][s][blk]: fixed order over waves and row slots
+template <int K, int VEC, int RPW>
+__device__ inline void publish_groups(const double (&v)[K][VEC], double *partial, int grid,
+                                      int S) {
+  __shared__ double sh[4 * RPW * 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane / (64 / VEC), s0 = (lane % (64 / VEC)) * VEC;
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) sh[(w * RPW + lr) * 64 + s0 + i] = v[k][i];
+    __syncthreads();
+    if (threadIdx.x < (unsigned)S) {
+      double acc = 0.0;
+      for (int j = 0; j < 4 * RPW; ++j) acc += sh[j * 64 + threadIdx.x];
+      partial[((size_t)k * S + threadIdx.x) * grid + blockIdx.x] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// (b) x += alpha p; r -= alpha q; partial r.z, r.r
+template <typename V, bool AL>
+__global__ __launch_bounds__(kBlock) void kb_pcg_b(BatchArgs a, int m, double dtau) {
+  using LY = Lanes<V>;
+  constexpr int VEC = LY::VEC, RPW = LY::RPW;
+  const int S = a.S, lane = threadIdx.x & 63;
+  const int lr = lane / LY::LPR, s0 = (lane % LY::LPR) * VEC;
+  bool on[VEC], any = false;
+  double h[VEC];
+  V alpha[VEC];
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) {
+    const int s = s0 + k, sc = s < S ? s : 0;
+    on[k] = lane_on(a.sc, s, S);
+    h[k] = on[k] ? a.h[sc] : 0.0;
+    alpha[k] = on[k] ? (V)a.sc->alpha[sc] : (V)0;
+    any |= on[k];
+  }
+  double v[2][VEC] = {};
+  V *x = BV<V>::x(a, m), *rv = BV<V>::r(a);
+  const V *p = BV<V>::p(a), *q = BV<V>::q(a);
+  const int64_t N = a.N, G = (N + RPW - 1) / RPW;
+  if (__ballot(any) != 0ull) {  // some lane of the wave has work
+    for (GroupRange gr = xcd_groups(G); gr.g < gr.end; gr.g += kGroupsAhead * gr.stride) {
+      V xs[kGroupsAhead][VEC], ps[kGroupsAhead][VEC], qs[kGroupsAhead][VEC],
+          rs[kGroupsAhead][VEC];
+      double ms[kGroupsAhead], kd[kGroupsAhead], rd[kGroupsAhead];
+      bool ok[kGroupsAhead];
+#pragma unroll
+      for (int u = 0; u < kGroupsAhead; ++u) {
+        const int64_t g = gr.g + u * gr.stride, row = g * RPW + lr;
+        ok[u] = (g < gr.end) & (row < N) & (s0 < S);
+        const int64_t rw = ok[u] ? row : 0, base = rw * S + (s0 < S ? s0 : 0);
+        vload<V, VEC, AL>(x, base, s0, S, xs[u]);
+        vload<V, VEC, AL>(p, base, s0, S, ps[u]);
+        vload<V, VEC, AL>(q, base, s0, S, qs[u]);
+        vload<V, VEC, AL>(rv, base, s0, S, rs[u]);
+        ms[u] = a.mass[rw];
+        kd[u] = a.Kd[rw];
+        rd[u] = a.Rd[rw];
       }
 #pragma unroll
-      for (int u = 0; u < kRowsAhead; ++u) {
-        const int64_t row = rr.row + u * rr.stride;
-        if (row >= rr.end) continue;
-        const int64_t i = row * S + s;
-        x[i] = xs[u] + alpha * ps[u];
-        const V r = rs[u] - alpha * qs[u];
-        rv[i] = r;
-        const V z = (V)di[u] * r;
-        v[0] += (double)r * (double)z;
-        v[1] += (double)r * (double)r;
+      for (int u = 0; u < kGroupsAhead; ++u) {
+        if (!ok[u]) continue;
+        const int64_t row = (gr.g + u * gr.stride) * RPW + lr, base = row * S + s0;
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+          if (!on[k]) continue;  // idle scenarios keep their values
+          xs[u][k] = xs[u][k] + alpha[k] * ps[u][k];
+          const V r = rs[u][k] - alpha[k] * qs[u][k];
+          rs[u][k] = r;
+          // the diagonal inverse of bdinv, from the loaded row data
+          const V z = (V)(1.0 / (ms[u] + dtau * (kd[u] + h[k] * rd[u]))) * r;
+          v[0][k] += (double)r * (double)z;
+          v[1][k] += (double)r * (double)r;
+        }
+        vstore<V, VEC, AL>(x, base, s0, S, xs[u]);
+        vstore<V, VEC, AL>(rv, base, s0, S, rs[u]);
       }
     }
   }
-  bpublish<2>(v, a.partial, gridDim.x, S);
+  publish_groups<2, VEC, RPW>(v, a.partial, gridDim.x, S);
 }
 
 // p_new = dinv r + beta p with one explicit rounding pattern, whatever code
@@ -855,87 +953,53 @@ __device__ __forceinline__ double pupdate(double di, double r, double beta, doub
   return __builtin_fma(di, r, beta * p);
 }
 
-// (c) p = z + beta p.  No sums here, so the vector is streamed flat:
-// VEC = 16 / sizeof(V) consecutive values (one row, scenarios s0..s0+VEC-1)
-// per lane and load when S is a power of two and a multiple of VEC (lshift =
-// log2 S); otherwise row by row with one scenario per lane.
-template <typename V>
-__global__ __launch_bounds__(kBlock) void kb_pcg_c(BatchArgs a, double dtau, int lshift) {
-  const int S = a.S;
+// (c) p = z + beta p, row groups as in (b)
+template <typename V, bool AL>
+__global__ __launch_bounds__(kBlock) void kb_pcg_c(BatchArgs a, double dtau) {
+  using LY = Lanes<V>;
+  constexpr int VEC = LY::VEC, RPW = LY::RPW;
+  const int S = a.S, lane = threadIdx.x & 63;
+  const int lr = lane / LY::LPR, s0 = (lane % LY::LPR) * VEC;
+  bool on[VEC], any = false;
+  double h[VEC];
+  V beta[VEC];
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) {
+    const int s = s0 + k, sc = s < S ? s : 0;
+    on[k] = lane_on(a.sc, s, S);
+    h[k] = on[k] ? a.h[sc] : 0.0;
+    beta[k] = on[k] ? (V)a.sc->beta[sc] : (V)0;
+    any |= on[k];
+  }
+  if (__ballot(any) == 0ull) return;  // no lane of the wave has work
   V *p = BV<V>::p(a);
   const V *rv = BV<V>::r(a);
-  if (lshift >= 0) {
-    constexpr int VEC = 16 / (int)sizeof(V);
-    using V4 = typename std::conditional<sizeof(V) == 4, float4, double2>::type;
-    const int64_t nvec = a.N * S / VEC;
-    const int64_t k0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    // the stride (a multiple of 1024 values) is a multiple of S, so every
-    // value this thread touches belongs to scenarios s0 .. s0 + VEC - 1
-    const int s0 = (int)((k0 * VEC) & (S - 1));
-    bool on[VEC], any = false;
-    double h[VEC];
-    V beta[VEC];
+  const int64_t N = a.N, G = (N + RPW - 1) / RPW;
+  for (GroupRange gr = xcd_groups(G); gr.g < gr.end; gr.g += kGroupsAhead * gr.stride) {
+    V ps[kGroupsAhead][VEC], rs[kGroupsAhead][VEC];
+    double ms[kGroupsAhead], kd[kGroupsAhead], rd[kGroupsAhead];
+    bool ok[kGroupsAhead];
 #pragma unroll
-    for (int j = 0; j < VEC; ++j) {
-      on[j] = lane_on(a.sc, s0 + j, S);
-      any |= on[j];
-      h[j] = on[j] ? a.h[s0 + j] : 0.0;
-      beta[j] = on[j] ? (V)a.sc->beta[s0 + j] : (V)0;
-    }
-    if (!any) return;
-    // kRowsAhead vectors per pass, every load of the pass issued before the
-    // first use
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t k = k0; k < nvec; k += kRowsAhead * stride) {
-      V4 pv[kRowsAhead], r4[kRowsAhead];
-      double ms[kRowsAhead], kd[kRowsAhead], rd[kRowsAhead];
-#pragma unroll
-      for (int u = 0; u < kRowsAhead; ++u) {
-        const int64_t kk = k + u * stride;
-        if (kk >= nvec) continue;
-        const int64_t row = (kk * VEC) >> lshift;
-        pv[u] = reinterpret_cast<V4 *>(p)[kk];
-        r4[u] = reinterpret_cast<const V4 *>(rv)[kk];
-        ms[u] = a.mass[row];
-        kd[u] = a.Kd[row];
-        rd[u] = a.Rd[row];
-      }
-#pragma unroll
-      for (int u = 0; u < kRowsAhead; ++u) {
-        const int64_t kk = k + u * stride;
-        if (kk >= nvec) continue;
-        V *pp = reinterpret_cast<V *>(&pv[u]);
-        const V *rr = reinterpret_cast<const V *>(&r4[u]);
-#pragma unroll
-        for (int j = 0; j < VEC; ++j)
-          if (on[j])  // the diagonal inverse of bdinv, from the loaded row data
-            pp[j] = pupdate((V)(1.0 / (ms[u] + dtau * (kd[u] + h[j] * rd[u]))), rr[j], beta[j],
-                            pp[j]);
-        reinterpret_cast<V4 *>(p)[kk] = pv[u];
-      }
-    }
-    return;
-  }
-  const int s = threadIdx.x & 63;
-  if (!lane_on(a.sc, s, S)) return;
-  const double h = a.h[s];
-  const V beta = (V)a.sc->beta[s];
-  for (RowRange rr = xcd_rows(a.N); rr.row < rr.end; rr.row += kRowsAhead * rr.stride) {
-    V ps[kRowsAhead], rs[kRowsAhead];
-    double di[kRowsAhead];
-#pragma unroll
-    for (int u = 0; u < kRowsAhead; ++u) {
-      const int64_t row = rr.row + u * rr.stride;
-      if (row >= rr.end) continue;
-      ps[u] = p[row * S + s];
-      rs[u] = rv[row * S + s];
-      di[u] = bdinv(a, row, h, dtau);
+    for (int u = 0; u < kGroupsAhead; ++u) {
+      const int64_t g = gr.g + u * gr.stride, row = g * RPW + lr;
+      ok[u] = (g < gr.end) & (row < N) & (s0 < S);
+      const int64_t rw = ok[u] ? row : 0, base = rw * S + (s0 < S ? s0 : 0);
+      vload<V, VEC, AL>(p, base, s0, S, ps[u]);
+      vload<V, VEC, AL>(rv, base, s0, S, rs[u]);
+      ms[u] = a.mass[rw];
+      kd[u] = a.Kd[rw];
+      rd[u] = a.Rd[rw];
     }
 #pragma unroll
-    for (int u = 0; u < kRowsAhead; ++u) {
-      const int64_t row = rr.row + u * rr.stride;
-      if (row >= rr.end) continue;
-      p[row * S + s] = pupdate((V)di[u], rs[u], beta, ps[u]);
+    for (int u = 0; u < kGroupsAhead; ++u) {
+      if (!ok[u]) continue;
+      const int64_t row = (gr.g + u * gr.stride) * RPW + lr, base = row * S + s0;
+#pragma unroll
+      for (int k = 0; k < VEC; ++k)
+        if (on[k])  // the diagonal inverse of bdinv, from the loaded row data
+          ps[u][k] = pupdate((V)(1.0 / (ms[u] + dtau * (kd[u] + h[k] * rd[u]))), rs[u][k],
+                             beta[k], ps[u][k]);
+      vstore<V, VEC, AL>(p, base, s0, S, ps[u]);
     }
   }
 }
@@ -1253,16 +1317,6 @@ static int tgrid(const BatchArgs &a) {
 
 #define RED(np, ...) kb_reduce<<<a.S, kBlock, 0, st>>>(a, np, __VA_ARGS__)
 
-// log2 S when S is a power of two and a multiple of 16 / sizeof(V), else -1
-template <typename V>
-static int flat_shift(const BatchArgs &a) {
-  const int vec = 16 / (int)sizeof(V);
-  if (a.S % vec != 0 || (a.S & (a.S - 1)) != 0) return -1;
-  int l = 0;
-  while ((1 << l) < a.S) ++l;
-  return l;
-}
-
 void blaunch_f_multi(const BatchArgs &a, int j0, int j1, hipStream_t st) {
   if (vec16<double>(a)) kb_f_multi<16, true><<<a.sgrid64, kBlock, 0, st>>>(a, j0, j1);
   else kb_f_multi<4, false><<<a.sgrid64, kBlock, 0, st>>>(a, j0, j1);
@@ -1292,10 +1346,11 @@ static void cg_iterations(const BatchArgs &a, int m, double dtau, int slot, int 
   for (int it = 0; it < budget; ++it) {
     launch_pcg_a<V>(a, 0, m, dtau, st);
     RED(tgrid<V>(a), 1, it, 0, slot, rtol);
-    kb_pcg_b<V><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
+    if (vec16<V>(a)) kb_pcg_b<V, true><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
+    else kb_pcg_b<V, false><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
     RED(a.grid, conv, it, it == budget - 1, slot, rtol);
-    kb_pcg_c<V><<<flat_shift<V>(a) >= 0 ? 4 * a.grid : a.grid, kBlock, 0, st>>>(a, dtau,
-                                                                          flat_shift<V>(a));
+    if (vec16<V>(a)) kb_pcg_c<V, true><<<a.grid, kBlock, 0, st>>>(a, dtau);
+    else kb_pcg_c<V, false><<<a.grid, kBlock, 0, st>>>(a, dtau);
   }
 }
 

@@ -58,8 +58,10 @@ struct DeformDev {
 };
 
 // Factorise: for every block the Schur complement S_k, inverted in place by
-// blocked Gauss-Jordan elimination into W_k.
-void deform_factor(const DeformDev &D, hipStream_t st);
+// blocked Gauss-Jordan elimination into W_k.  Checks the launch shapes on the
+// host first (hipErrorInvalidValue, nothing launched) and the launches of
+// every block; *dispatches counts the kernels launched.
+hipError_t deform_factor(const DeformDev &D, hipStream_t st, int64_t *dispatches);
 // u = K_u^{-1} G (T - T_ref) into D.x.  With gemv_ev (2 events per dense
 // block product, 2 nblk - 1 products) every product is timed.
 void deform_solve(const DeformDev &D, const double *T, hipStream_t st, hipEvent_t *gemv_ev);

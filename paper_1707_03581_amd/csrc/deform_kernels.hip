@@ -466,25 +466,50 @@ inline unsigned blocks_for(int64_t n) {
 
 }  // namespace
 
-void deform_factor(const DeformDev &D, hipStream_t st) {
+hipError_t deform_factor(const DeformDev &D, hipStream_t st, int64_t *dispatches) {
+  *dispatches = 0;
   const int nt = (int)(D.bp / kT);
-  hipMemsetAsync(D.flag, 0, sizeof(int), st);
+  // launch shapes checked on the host before the first launch: every grid
+  // non-empty and within the 32-bit grid limit, the row staged by k_schur_s
+  // within the 64 KB of dynamic LDS a workgroup may take without an attribute
+  if (D.bp <= 0 || D.bp % kT != 0 || D.bp > kMaxDeformBlock || D.nblk <= 0 || nt < 1 ||
+      (int64_t)(nt - 1) * (nt - 1) > 0x7fffffffLL || D.bs <= 0 || D.bs > D.bp ||
+      (size_t)D.bp * sizeof(double) > 65536)
+    return hipErrorInvalidValue;
+  for (int64_t k = 0; k < D.nblk; ++k)
+    if (D.rows(k) <= 0 || D.rows(k) > D.bp) return hipErrorInvalidValue;
+  hipError_t e = hipMemsetAsync(D.flag, 0, sizeof(int), st);
+  if (e != hipSuccess) return e;
+  int64_t n = 0;
   for (int64_t k = 0; k < D.nblk; ++k) {
-    if (k > 0) k_schur_t<<<(unsigned)D.rows(k), kThreads, 0, st>>>(D, k);
+    if (k > 0) {
+      k_schur_t<<<(unsigned)D.rows(k), kThreads, 0, st>>>(D, k);
+      ++n;
+    }
     k_schur_s<<<(unsigned)D.bp, kThreads, (size_t)D.bp * sizeof(double), st>>>(D, k);
     double *S = D.W + k * D.bp * D.bp;
     // pivot inverses alternate between two buffers: pass p reads piv[p % 2]
     // while its trailing update inverts the next pivot tile into the other
     k_gj_pivot<<<1, kThreads, 0, st>>>(S, D.bp, 0, D.piv, D.flag);
+    n += 2;
     for (int p = 0; p < nt; ++p) {
       double *pc = D.piv + (p & 1) * kT * kT, *pn = D.piv + ((p + 1) & 1) * kT * kT;
       if (nt > 1) {
         k_gj_row<<<nt - 1, kThreads, 0, st>>>(S, D.bp, p, pc);
         k_gj_update<<<(nt - 1) * (nt - 1), kThreads, 0, st>>>(S, D.bp, p, nt, pn, D.flag);
+        n += 2;
       }
       k_gj_col<<<nt, kThreads, 0, st>>>(S, D.bp, p, pc);
+      ++n;
+    }
+    // a launch error stops the factorisation at the block it occurred in
+    if ((e = hipGetLastError()) != hipSuccess) {
+      *dispatches = n;
+      return e;
     }
   }
+  *dispatches = n;
+  return hipSuccess;
 }
 
 void deform_solve(const DeformDev &D, const double *T, hipStream_t st, hipEvent_t *ev) {

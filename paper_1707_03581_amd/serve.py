@@ -3,13 +3,22 @@
 Requests (a machine at one of a few mesh levels, a horizon, and its own
 Robin h, contact alpha, friction power, motion period and initial field)
 arrive over time.  Each mesh level has one batched context (shared operators,
-up to 64 slots) driven by its own host thread, so the levels' kernels run
-concurrently on separate HIP streams.  A request is admitted into a free slot
-of its level as soon as it has arrived and the level's context fits the HBM
-budget; every scheduler tick advances all active slots of a level by one
-macro-step (predictor + K sweeps); a request leaves when its horizon is done
-and its slot is reused.  All arithmetic runs in libmrsdc.so; this module only
-schedules and records latencies.
+a pool of scenario slots whose node states stay resident on the device)
+driven by its own host thread, so the levels' kernels run concurrently on
+separate HIP streams.
+
+Admission by HBM footprint: before the replay, each configured level's
+footprint is taken from the library (bytes shared by the level, bytes per
+scenario slot) and the levels' slot pools are sized so that their device
+memory together stays within the HBM budget (default: 90 % of the device
+memory free at start).  A level that cannot hold its operators and one slot
+within what is left gets no pool, and its requests are rejected on arrival.
+A request of a pooled level is admitted into a free slot as soon as it has
+arrived; while every slot is taken it waits in its level's queue.  Every
+scheduler tick advances all active slots of a level by one macro-step
+(predictor + K sweeps); a request leaves when its horizon is done and its slot
+is reused.  All arithmetic runs in libmrsdc.so; this module only schedules,
+accounts memory and records latencies.
 """
 from __future__ import annotations
 
@@ -37,22 +46,50 @@ class Request:
     # filled by the server
     admitted: float = float("nan")
     finished: float = float("nan")
+    rejected: bool = False
     step_ms: list = field(default_factory=list)
     result: np.ndarray = None
     slot: int = -1
 
 
-def slot_bytes(pb) -> int:
-    """Device bytes one scenario slot needs on a level (state vectors, caches)."""
-    sc = pb.scheme
-    n_if = 0
-    c = pb.coupling
-    if c is not None:
-        F = pb.bodies[c.fix_body].faces[c.fix_face]
-        G = pb.bodies[c.mov_body].faces[c.mov_face]
-        n_if = F.nu * F.nv + G.nu * G.nv
-    vectors = 3 * sc.M + 6
-    return int(8 * pb.N * vectors + 16 * (sc.M + 1) * (sc.P + 1) * n_if)
+def plan_pools(level_bytes: dict, budget: int, slots_per_level: int) -> dict:
+    """Slots per level within an HBM budget.
+
+    level_bytes: name -> (shared bytes, bytes per slot) as the library reports
+    them.  Levels are served in order of their one-slot footprint (smallest
+    first), each taking up to slots_per_level slots of what is left of the
+    budget; a level that cannot hold its shared bytes and one slot gets 0
+    (its requests are rejected).  The order and the sizes depend only on the
+    configured levels, never on the requests to come."""
+    plan = {}
+    left = int(budget)
+    for name in sorted(level_bytes, key=lambda n: sum(level_bytes[n])):
+        shared, per = level_bytes[name]
+        fit = (left - shared) // per if left >= shared + per else 0
+        slots = int(min(slots_per_level, fit))
+        plan[name] = slots
+        if slots:
+            left -= shared + slots * per
+    return plan
+
+
+def level_bytes(pb, device=0):
+    """(shared, per-slot) device bytes of a level, from a one-slot context."""
+    ctx = BatchContext(config_from_scheme(pb.scheme, device=device), 1)
+    try:
+        load_problem(ctx, pb, temperature=False)
+        ctx.set_active(0, False)
+        ctx.advance_steps(0)  # builds the device state
+        per, shared = ctx.slot_bytes()
+    finally:
+        ctx.destroy()
+    return shared, per
+
+
+def default_budget(device=0) -> int:
+    import torch
+    free, _ = torch.cuda.mem_get_info(device)
+    return int(0.9 * free)
 
 
 class _Level:
@@ -70,34 +107,45 @@ class _Level:
 
 
 class Server:
-    """levels: name -> problem description (shared mesh, scheme) of that level."""
+    """levels: name -> problem description (shared mesh, scheme) of that level.
+    hbm_budget_bytes: device memory the pools may hold (None: 90 % of the
+    device memory free when run() starts)."""
 
-    def __init__(self, levels: dict, slots_per_level: int = 64, hbm_budget_bytes: int = 200 << 30,
+    def __init__(self, levels: dict, slots_per_level: int = 64, hbm_budget_bytes=None,
                  device: int = 0):
         self.levels_pb = levels
         self.slots = slots_per_level
         self.budget = hbm_budget_bytes
         self.device = device
 
+    def size_pools(self):
+        """Footprints from the library and the slot plan within the budget."""
+        if self.budget is None:
+            self.budget = default_budget(self.device)
+        self.level_bytes = {n: level_bytes(pb, self.device) for n, pb in self.levels_pb.items()}
+        self.plan = plan_pools(self.level_bytes, self.budget, self.slots)
+        return self.plan
+
     def run(self, requests: list, time_limit: float = 600.0):
-        """Replay requests (sorted by arrival); returns them with timings and results."""
+        """Replay requests (sorted by arrival); returns them with timings and
+        results (rejected requests keep result None)."""
         reqs = sorted(requests, key=lambda r: r.arrival)
-        by_level = {name: [r for r in reqs if r.level == name] for name in self.levels_pb}
+        if not hasattr(self, "plan"):
+            self.size_pools()
         levels = {}
-        used = 0
-        for name, pb in self.levels_pb.items():
-            if not by_level[name]:
-                continue
-            slots = min(self.slots, len(by_level[name]))
-            need = slots * slot_bytes(pb) + 40 * pb.nnz
-            while slots > 1 and used + need > self.budget:
-                slots //= 2
-                need = slots * slot_bytes(pb) + 40 * pb.nnz
-            if used + need > self.budget:
-                raise MemoryError(f"level {name} does not fit the HBM budget")
-            used += need
-            levels[name] = _Level(name, pb, slots, self.device)
+        for name, slots in self.plan.items():
+            if slots:
+                levels[name] = _Level(name, self.levels_pb[name], slots, self.device)
         self.footprint = {n: lv.ctx.footprint_bytes() for n, lv in levels.items()}
+        self.held_bytes = sum(self.footprint.values())
+        if self.held_bytes > self.budget:
+            for lv in levels.values():
+                lv.ctx.destroy()
+            raise MemoryError(f"pools hold {self.held_bytes} bytes, budget {self.budget}")
+        by_level = {name: [r for r in reqs if r.level == name] for name in levels}
+        for r in reqs:
+            if r.level not in levels:
+                r.rejected = True
         t0 = time.perf_counter()
         errors = []
 
@@ -152,15 +200,19 @@ class Server:
 
 
 def summarize(reqs, dt, dof_of_level):
-    """Latency and throughput figures of a finished run."""
-    lat = np.concatenate([np.asarray(r.step_ms) for r in reqs])
-    wall = max(r.finished for r in reqs) - min(r.arrival for r in reqs)
-    dof_steps = sum(dof_of_level[r.level] * r.nsteps for r in reqs)
-    eta = [r.nsteps * dt / (r.finished - r.arrival) for r in reqs]
-    eta_service = [r.nsteps * dt / (r.finished - r.admitted) for r in reqs]
-    queue = [r.admitted - r.arrival for r in reqs]
-    return {
-        "requests": len(reqs),
+    """Latency and throughput figures of a finished run (served requests;
+    rejected ones are counted apart)."""
+    served = [r for r in reqs if not r.rejected]
+    out = {"requests": len(reqs), "served": len(served), "rejected": len(reqs) - len(served)}
+    if not served:
+        return out
+    lat = np.concatenate([np.asarray(r.step_ms) for r in served])
+    wall = max(r.finished for r in served) - min(r.arrival for r in served)
+    dof_steps = sum(dof_of_level[r.level] * r.nsteps for r in served)
+    eta = [r.nsteps * dt / (r.finished - r.arrival) for r in served]
+    eta_service = [r.nsteps * dt / (r.finished - r.admitted) for r in served]
+    queue = [r.admitted - r.arrival for r in served]
+    out.update({
         "p50_step_ms": float(np.percentile(lat, 50)),
         "p99_step_ms": float(np.percentile(lat, 99)),
         "dof_steps_per_s": dof_steps / wall,
@@ -170,4 +222,5 @@ def summarize(reqs, dt, dof_of_level):
         "eta_service_p50": float(np.percentile(eta_service, 50)),
         "queue_p50_s": float(np.percentile(queue, 50)),
         "queue_max_s": float(np.max(queue)),
-    }
+    })
+    return out

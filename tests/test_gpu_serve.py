@@ -28,14 +28,14 @@ def levels(precision=mi.FP64):
     return {"coarse": a, "fine": b}
 
 
-def trace(lv, n=10, seed=7):
+def trace(lv, n=10, seed=7, gap=0.05):
     from paper_1707_03581_amd.serve import Request
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
     names = list(lv)
     for i in range(n):
-        t += rng.exponential(0.05)
+        t += rng.exponential(gap)
         name = names[int(rng.integers(0, len(names)))]
         h, alpha, pf, period, r2 = mi.scenario_params(500 + i)
         out.append(Request(id=i, arrival=t, level=name, nsteps=int(rng.integers(2, 6)), h=h,
@@ -70,3 +70,57 @@ def test_served_results_equal_alone_and_oracle(precision, tol):
         e = float(np.linalg.norm(r.result - ref) / np.linalg.norm(ref))
         print(f"  request {r.id} ({r.level}, {r.nsteps} steps): rel_l2={e:.3e}", flush=True)
         assert e <= tol
+
+
+def test_small_budget_queues_and_rejects():
+    """An HBM budget that holds two slots of the coarse level, one of the fine
+    one and no pool of a large level: requests queue for the slots, the
+    large level's requests are rejected, and every served result is still the
+    same as its run alone."""
+    import paper_1707_03581_amd as m
+    from paper_1707_03581_amd.serve import Server, level_bytes, summarize
+    lv = levels()
+    sc = lv["coarse"].scheme
+    lv["large"] = mi.machine(stand_nodes=(9, 11, 31), stock_nodes=(7, 8, 11),
+                             stand_L=(0.2, 0.3, 0.9), stock_L=(0.15, 0.2, 0.3), y_offset=0.05,
+                             period=3.0, stroke=0.5, scheme=sc)
+    lb = {n: level_bytes(pb) for n, pb in lv.items()}
+    print("  level bytes (shared, per slot):", lb, flush=True)
+    budget = lb["coarse"][0] + 2 * lb["coarse"][1] + lb["fine"][0] + lb["fine"][1]
+    assert budget < sum(lb["large"])  # the large level cannot fit even alone
+    srv = Server(lv, slots_per_level=2, hbm_budget_bytes=budget)
+    plan = srv.size_pools()
+    assert plan == {"coarse": 2, "fine": 1, "large": 0}
+    reqs = srv.run(trace(lv, n=12, seed=11, gap=0.002))  # a burst
+    assert srv.held_bytes <= budget
+    summ = summarize(reqs, 5.0, {k: v.N for k, v in lv.items()})
+    print("  ", summ, flush=True)
+    rejected = [r for r in reqs if r.rejected]
+    served = [r for r in reqs if not r.rejected]
+    assert rejected and all(r.level == "large" and r.result is None for r in rejected)
+    assert all(r.level != "large" for r in served)
+    # a request that arrived while its level's slots were taken waited for one
+    assert any(r.admitted - r.arrival > 0.02 for r in served)
+    for r in served:
+        pb = lv[r.level]
+        ctx = m.batch_simulation(pb, [dict(h=r.h, alpha=r.alpha, friction_W=r.friction_W,
+                                           period=r.period, T0=r.T0)])
+        ctx.advance_steps(r.nsteps)
+        alone = ctx.get_scenario_temperature(0, pb.N)
+        ctx.destroy()
+        assert np.array_equal(alone, r.result), r.id
+
+
+def test_slot_bytes_add_up_to_the_footprint():
+    import paper_1707_03581_amd as m
+    pb = levels()["fine"]
+    for S in (1, 3):
+        ctx = m.batch_simulation(pb, [dict(h=10.0, alpha=900.0, friction_W=100.0, period=3.0,
+                                           T0=pb.T0)] * S)
+        ctx.advance_steps(0)
+        per, shared = ctx.slot_bytes()
+        fp = ctx.footprint_bytes()
+        ctx.destroy()
+        print(f"  S={S}: per slot {per}, shared {shared}, footprint {fp}", flush=True)
+        assert per > 8 * pb.N and shared > 0
+        assert 0 <= shared + S * per - fp < S
