@@ -220,6 +220,20 @@ mrsdc_status mrsdc_advance(mrsdc_ctx *ctx, double horizon, mrsdc_stats *stats);
  * Robin term (singular problem); ENOCONV leaves the last iterate in place. */
 mrsdc_status mrsdc_set_stationary(mrsdc_ctx *ctx, double rtol, int maxit, int *iters);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): mrsdc_set_stationary
+ * without any allocation.  Its two work vectors (the Jacobi inverse of
+ * K + h R and a zero mass vector) live in a fixed scratch array of
+ * 2 * MRSDC_NOALLOC_MAX_ROWS doubles (64 MiB) that each device holds until
+ * the process ends; the same kernels run, so the field and the iteration
+ * count are those of mrsdc_set_stationary, bit for bit.  Requires a context
+ * whose device state exists (an earlier advance or stationary solve; ESTATE
+ * otherwise) and at most MRSDC_NOALLOC_MAX_ROWS rows (EINVAL otherwise).  All
+ * calls on one device share the scratch: calls that overlap on one device
+ * (from several host threads) race and must be serialised by the caller. */
+#define MRSDC_NOALLOC_MAX_ROWS 4194304
+mrsdc_status mrsdc_set_stationary_noalloc(mrsdc_ctx *ctx, double rtol, int maxit, int *iters);
+
 /* Copy the temperature of one body to a host array of n values. */
 mrsdc_status mrsdc_get_temperature(mrsdc_ctx *ctx, int body, double *out, int64_t n);
 

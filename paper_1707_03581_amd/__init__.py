@@ -80,6 +80,8 @@ _SIGS = {
     "mrsdc_set_temperature": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int64]),
     "mrsdc_set_time": (C.c_int, [C.c_void_p, C.c_double]),
     "mrsdc_set_stationary": (C.c_int, [C.c_void_p, C.c_double, C.c_int, C.POINTER(C.c_int)]),
+    "mrsdc_set_stationary_noalloc": (C.c_int, [C.c_void_p, C.c_double, C.c_int,
+                                               C.POINTER(C.c_int)]),
     "mrsdc_get_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "mrsdc_advance": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p]),
     "mrsdc_get_temperature": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int64]),
@@ -232,6 +234,13 @@ class Context:
         the CG iteration count."""
         it = C.c_int(0)
         self._chk(self._L.mrsdc_set_stationary(self._h, rtol, maxit, C.byref(it)))
+        return it.value
+
+    def set_stationary_noalloc(self, rtol=1e-13, maxit=100000):
+        """set_stationary without any device allocation (fixed library
+        scratch; the context's device state must exist)."""
+        it = C.c_int(0)
+        self._chk(self._L.mrsdc_set_stationary_noalloc(self._h, rtol, maxit, C.byref(it)))
         return it.value
 
     def get_time(self):

@@ -1733,6 +1733,32 @@ mrsdc_status mrsdc_set_stationary(mrsdc_ctx *c, double rtol, int maxit, int *ite
   return st;
 }
 
+mrsdc_status mrsdc_set_stationary_noalloc(mrsdc_ctx *c, double rtol, int maxit, int *iters) {
+  if (!c) return MRSDC_EINVAL;
+  mrsdc_status st = stationary_begin(c, rtol, maxit, iters);
+  if (st) return st;
+  if (!c->prepared)
+    return fail(c, MRSDC_ESTATE,
+                "device state not prepared: advance (or call mrsdc_set_stationary) once first");
+  const int64_t N = c->d.N;
+  if (N > MRSDC_NOALLOC_MAX_ROWS)
+    return fail(c, MRSDC_EINVAL, "%lld rows exceed the fixed scratch of %lld rows",
+                (long long)N, (long long)MRSDC_NOALLOC_MAX_ROWS);
+  hipError_t he = hipSetDevice(c->cfg.device);
+  double *scr = nullptr;
+  if (he == hipSuccess) he = stationary_scratch(c->cfg.device, &scr);
+  if (he != hipSuccess) return fail(c, MRSDC_EDEVICE, "HIP: %s", hipGetErrorString(he));
+  if ((st = upload_T(c))) return st;
+  // the Jacobi inverse of L from its device diagonal and a zero mass vector,
+  // written over whatever an earlier call left in the scratch
+  double *ddinv = scr, *dzero = scr + N;
+  launch_stationary_scratch(ddinv, dzero, c->d.Ldiag, N, c->stream);
+  if ((he = hipGetLastError())) return fail(c, MRSDC_EDEVICE, "HIP: %s", hipGetErrorString(he));
+  st = stationary_iterate(c, rtol, maxit, iters, ddinv, dzero);
+  hipStreamSynchronize(c->stream);  // the scratch is free for the next call on this device
+  return st;
+}
+
 mrsdc_status mrsdc_get_temperature(mrsdc_ctx *c, int body, double *out, int64_t n) {
   if (!c) return MRSDC_EINVAL;
   if (body < 0 || body > 1 || !c->body[body].set) return fail(c, MRSDC_ESTATE, "body not set");

@@ -9,6 +9,9 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <mutex>
+
 #include "mrsdc_internal.h"
 
 namespace mrsdc {
@@ -1979,6 +1982,52 @@ void launch_step_end(const DevState &d, double dt, hipStream_t st) {
 
 void launch_clear_counters(const DevState &d, hipStream_t st) {
   k_clear<<<1, kBlock, 0, st>>>(d.ctr);
+}
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free stationary solve: the Jacobi
+// inverse of L and a zero mass vector, MRSDC_NOALLOC_MAX_ROWS values each
+// (64 MiB).  Each device the library runs on holds its own copy until the
+// process ends; every call on a device shares it and leaves its contents.
+// Host code reaches it only through the address hipGetSymbolAddress returns
+// for that device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[2 * (size_t)MRSDC_NOALLOC_MAX_ROWS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
+}  // namespace
+
+hipError_t stationary_scratch(int device, double **ptr) {
+  *ptr = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {  // first call on this device (the caller made it current)
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[device] = static_cast<double *>(p);
+  }
+  *ptr = g_scratch[device];
+  return hipSuccess;
+}
+
+__global__ void k_stationary_scratch(double *__restrict__ dinv, double *__restrict__ zeros,
+                                     const double *__restrict__ Ldiag, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    dinv[i] = 1.0 / Ldiag[i];
+    zeros[i] = 0.0;
+  }
+}
+
+void launch_stationary_scratch(double *dinv, double *zeros, const double *Ldiag, int64_t n,
+                               hipStream_t st) {
+  int grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 2048);
+  if (grid < 1) grid = 1;
+  k_stationary_scratch<<<grid, kBlock, 0, st>>>(dinv, zeros, Ldiag, n);
 }
 
 }  // namespace mrsdc

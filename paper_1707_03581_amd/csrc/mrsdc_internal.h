@@ -218,5 +218,11 @@ void launch_iface_coeffs(const DevState &d, hipStream_t st);
 void launch_iface(const DevState &d, int m, bool corr, int slot, int chk_it, hipStream_t st);
 void launch_step_end(const DevState &d, double dt, hipStream_t st);
 void launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
+// device address of the allocation-free stationary solve's fixed scratch
+// (2 MRSDC_NOALLOC_MAX_ROWS doubles) on `device`, which must be current
+hipError_t stationary_scratch(int device, double **ptr);
+// dinv = 1 / Ldiag, zeros = 0 (n values each)
+void launch_stationary_scratch(double *dinv, double *zeros, const double *Ldiag, int64_t n,
+                               hipStream_t st);
 
 }  // namespace mrsdc
