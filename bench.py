@@ -39,6 +39,12 @@ COUNTER_TRAFFIC = {
         "fetch_kib": 2725.9, "fetch_scale": 1.99974,
         "write_kib": 2454.2, "write_scale": 1.0,
     },
+    ("ensemble-64x714798", 1): {
+        "source": "batch_kernels.hip",
+        "sha256": "d081761db2de9265f79ade6de8c8ab7d4589aa4149ddd513084e4994da97cc1e",
+        "fetch_kib": 241652.6, "fetch_scale": 1.99975,
+        "write_kib": 180285.7, "write_scale": 1.0,
+    },
 }
 
 
