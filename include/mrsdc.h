@@ -31,6 +31,7 @@
  */
 #ifndef MRSDC_H
 #define MRSDC_H
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -52,6 +53,18 @@ typedef enum {
 enum { MRSDC_FP64 = 0, MRSDC_FP32_REFINE = 1 };
 enum { MRSDC_LOBATTO = 0, MRSDC_EQUI_NOLEFT = 1 };
 enum { MRSDC_MULTIRATE = 0, MRSDC_SINGLE_RATE = 1 };
+
+/* Optional device allocator (for example a framework's caching allocator, so
+ * that the framework owns and accounts the memory): alloc returns `bytes` of
+ * device memory usable on `stream` (the context's hipStream_t) or NULL;
+ * release takes back a pointer alloc returned.  The library calls them from
+ * the thread that calls into the context; it copies this struct at
+ * mrsdc_create. */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *stream, void *user);
+  void (*release)(void *ptr, void *stream, void *user);
+  void *user;
+} mrsdc_allocator;
 
 typedef struct {
   int device;         /* HIP device ordinal */
@@ -114,6 +127,10 @@ typedef struct {
                          16-bit offsets fit.  The first advance (or stationary
                          solve) returns EINVAL when the form does not apply.
                          Batched contexts take MRSDC_OP_AUTO only. */
+  const mrsdc_allocator *alloc; /* NULL: hipMalloc / hipFree.  Otherwise every
+                         device buffer of the context (and of its deformation
+                         solve) comes from alloc and goes back through release;
+                         both must be set */
 } mrsdc_config;
 
 enum {
@@ -309,6 +326,21 @@ mrsdc_status mrsdc_batch_advance(mrsdc_ctx *ctx, int nsteps, mrsdc_stats *stats)
 /* Temperature of scenario s over all nodes (n = total nodes) into a host array. */
 mrsdc_status mrsdc_batch_get_temperature(mrsdc_ctx *ctx, int s, double *out, int64_t n);
 
+/* Copy scenario s's temperature (n = N doubles, both bodies) to DEVICE memory
+ * dptr on stream (a hipStream_t, or NULL for the context's stream);
+ * asynchronous on that stream.  ESTATE before the first advance. */
+mrsdc_status mrsdc_batch_get_temperature_device(mrsdc_ctx *ctx, int s, void *dptr, int64_t n,
+                                                void *stream);
+
+/* Advance every active scenario s by its own horizon[s] seconds (an integer
+ * multiple of dt, relative tolerance 1e-9; inactive scenarios are skipped):
+ * the batch steps until the longest horizon is reached, each scenario leaving
+ * it once its own is, and every scenario that was active is active again on
+ * return.  stats sum over the steps.  Errors as mrsdc_batch_advance (ENOCONV
+ * leaves each scenario at its last committed step). */
+mrsdc_status mrsdc_batch_advance_horizons(mrsdc_ctx *ctx, const double *horizon,
+                                          mrsdc_stats *stats);
+
 /* Per-kernel-class device time measured with HIP events on the context's
  * stream while profiling is on (mrsdc_profile).  cg_spmv: the operator
  * application q = (diag(m) + dtau L) p of every CG iteration within the
@@ -331,8 +363,10 @@ mrsdc_status mrsdc_profile_read(const mrsdc_ctx *ctx, mrsdc_kernel_times *out);
 /* Launch the CG operator application q = (diag(m) + dtau L) p (FP32 operator
  * for FP32_REFINE) reps times back to back between two HIP events on the
  * context's stream and report the average time per launch in microseconds and
- * its algorithmic bytes (as cg_spmv_bytes).  Needs a prepared context (one
- * advance); overwrites only CG scratch vectors.  For roofline measurement. */
+ * the bytes its storage reads and writes once (single contexts: as
+ * cg_spmv_bytes; batched: the stored operator form and the S right-hand sides
+ * in and out).  Needs a prepared context (one advance); overwrites only CG
+ * scratch vectors.  For roofline measurement. */
 mrsdc_status mrsdc_time_operator(mrsdc_ctx *ctx, int reps, double *avg_us, int64_t *bytes);
 
 /* ---- thermo-elastic deformation of one body (§5, deformation paragraphs) ----

@@ -36,7 +36,36 @@ class Config(C.Structure):
                 ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int), ("refine_rtol", C.c_double),
                 ("refine_maxit", C.c_int), ("inner_rtol", C.c_double),
                 ("final_residual", C.c_int), ("use_graph", C.c_int), ("sweep_tol", C.c_double),
-                ("method", C.c_int), ("stream", C.c_void_p), ("op_form", C.c_int)]
+                ("method", C.c_int), ("stream", C.c_void_p), ("op_form", C.c_int),
+                ("alloc", C.c_void_p)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("release", RELEASE_FN), ("user", C.c_void_p)]
+
+
+def torch_allocator(device=0):
+    """An mrsdc_allocator over torch's caching allocator: the library's device
+    buffers are then torch's (counted by torch.cuda.memory_allocated).  Keep
+    the returned object alive as long as any context created with it."""
+    import torch
+
+    def _alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream or 0)
+        except RuntimeError:
+            return None
+
+    def _release(ptr, stream, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a = Allocator(ALLOC_FN(_alloc), RELEASE_FN(_release), None)
+    a._keep = (_alloc, _release)
+    return a
 
 
 class Stats(C.Structure):
@@ -105,6 +134,9 @@ _SIGS = {
     "mrsdc_batch_set_active": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "mrsdc_batch_advance": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "mrsdc_batch_get_temperature": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int64]),
+    "mrsdc_batch_get_temperature_device": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int64,
+                                                     C.c_void_p]),
+    "mrsdc_batch_advance_horizons": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "mrsdc_profile_read": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mrsdc_time_operator": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int64)]),
@@ -168,6 +200,9 @@ def default_config(**kw) -> Config:
     cfg = Config()
     lib().mrsdc_config_init(C.byref(cfg))
     for k, v in kw.items():
+        if k == "alloc" and isinstance(v, Allocator):
+            cfg._allocator = v  # the config (and the caller) keep it alive
+            v = C.cast(C.pointer(v), C.c_void_p).value
         setattr(cfg, k, v)
     return cfg
 
@@ -376,6 +411,21 @@ class BatchContext(Context):
         self._chk(self._L.mrsdc_batch_slot_bytes(self._h, C.byref(a), C.byref(b)))
         return a.value, b.value
 
+    def advance_horizons(self, horizons):
+        """Advance each scenario by its own horizon (seconds; one per scenario)."""
+        h = np.ascontiguousarray(horizons, np.float64)
+        if len(h) != self.S:
+            raise ValueError("one horizon per scenario")
+        st = Stats()
+        self._chk(self._L.mrsdc_batch_advance_horizons(self._h, _p(h), C.byref(st)))
+        return st.as_dict()
+
+    def get_scenario_temperature_device(self, s, tensor, stream=None):
+        """Copy scenario s's field into a contiguous float64 device tensor."""
+        st = None if stream is None else C.c_void_p(stream)
+        return self._chk(self._L.mrsdc_batch_get_temperature_device(
+            self._h, s, C.c_void_p(tensor.data_ptr()), tensor.numel(), st))
+
     def get_scenario_temperature(self, s, n):
         out = np.empty(n)
         self._chk(self._L.mrsdc_batch_get_temperature(self._h, s, _p(out), n))
@@ -384,16 +434,14 @@ class BatchContext(Context):
 
 def config_from_scheme(scheme, device=0, **over) -> Config:
     """Config from an object with M, family, P, K, dt, pcg_rtol, pcg_maxit, precision..."""
-    cfg = default_config(device=device, precision=scheme.precision, M=scheme.M,
-                         node_family=scheme.family, P=scheme.P, K=scheme.K, dt=scheme.dt,
-                         pcg_rtol=scheme.pcg_rtol, pcg_maxit=scheme.pcg_maxit,
-                         refine_rtol=scheme.refine_rtol, refine_maxit=scheme.refine_maxit,
-                         inner_rtol=scheme.inner_rtol,
-                         sweep_tol=getattr(scheme, "sweep_tol", 0.0),
-                         method=getattr(scheme, "method", MULTIRATE))
-    for k, v in over.items():
-        setattr(cfg, k, v)
-    return cfg
+    kw = dict(device=device, precision=scheme.precision, M=scheme.M, node_family=scheme.family,
+              P=scheme.P, K=scheme.K, dt=scheme.dt, pcg_rtol=scheme.pcg_rtol,
+              pcg_maxit=scheme.pcg_maxit, refine_rtol=scheme.refine_rtol,
+              refine_maxit=scheme.refine_maxit, inner_rtol=scheme.inner_rtol,
+              sweep_tol=getattr(scheme, "sweep_tol", 0.0),
+              method=getattr(scheme, "method", MULTIRATE))
+    kw.update(over)
+    return default_config(**kw)
 
 
 def load_problem(ctx: Context, pb, h=None, alpha=None, friction_W=None, period=None, T0=None,

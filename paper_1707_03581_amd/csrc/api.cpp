@@ -22,6 +22,7 @@
 #include <cstring>
 #include <string>
 #include <map>
+#include <queue>
 #include <unordered_map>
 #include <vector>
 
@@ -67,6 +68,7 @@ struct Motion {
 
 struct mrsdc_ctx {
   mrsdc_config cfg;
+  mrsdc_allocator allocator = {};  // copy of cfg.alloc (cfg.alloc points here when set)
   std::string err;
   HostBody body[2];
   HostFace face[2][8];
@@ -93,6 +95,7 @@ struct mrsdc_ctx {
   int64_t matrix_bytes = 0;
   int64_t nnz = 0;
   int64_t batch_entries = 0;  // merged K and R entries of a batched operator
+  int64_t col_stored_bytes = 0;  // stencil records and work items of the column sweep
   // captured time step (use_graph): valid for the budgets in graph_key
   hipGraphExec_t graph_exec = nullptr;
   std::vector<int> graph_key;
@@ -157,15 +160,28 @@ bool finite_all(const double *p, int64_t n) {
 
 // per_scenario: the allocation grows with the batch's scenario count (its
 // bytes are counted apart for admission by footprint)
+// Device memory of a context: through the caller's allocator when one was
+// given, else hipMalloc / hipFree.
+void *dev_malloc(mrsdc_ctx *c, size_t bytes) {
+  if (c->cfg.alloc) return c->allocator.alloc(bytes, (void *)c->stream, c->allocator.user);
+  void *q = nullptr;
+  if (hipMalloc(&q, bytes) != hipSuccess) {
+    hipGetLastError();
+    return nullptr;
+  }
+  return q;
+}
+void dev_free(mrsdc_ctx *c, void *p) {
+  if (!p) return;
+  if (c->cfg.alloc) c->allocator.release(p, (void *)c->stream, c->allocator.user);
+  else hipFree(p);
+}
+
 template <typename T>
 mrsdc_status dalloc(mrsdc_ctx *c, T **p, size_t count, bool per_scenario = false) {
-  void *q = nullptr;
   size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-  hipError_t e = hipMalloc(&q, bytes);
-  if (e != hipSuccess) {
-    hipGetLastError();
-    return fail(c, MRSDC_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
-  }
+  void *q = dev_malloc(c, bytes);
+  if (!q) return fail(c, MRSDC_ENOMEM, "device allocation of %zu bytes failed", bytes);
   c->allocs.push_back(q);
   c->footprint += (int64_t)bytes;
   if (per_scenario) c->scen_bytes += (int64_t)bytes;
@@ -208,7 +224,7 @@ void free_device(mrsdc_ctx *c) {
   if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
   c->graph_exec = nullptr;
   c->graph_key.clear();
-  for (void *p : c->allocs) hipFree(p);
+  for (void *p : c->allocs) dev_free(c, p);
   c->allocs.clear();
   c->footprint = 0;
   c->scen_bytes = 0;
@@ -445,6 +461,143 @@ mrsdc_status build_stage_tiles(mrsdc_ctx *c, int64_t N, const std::vector<int64_
   return fail(c, MRSDC_EINVAL, "a row block exceeds the staging capacity of %d columns", kStageSlots);
 }
 
+// Column sweep of the FP32 operator when every body is a box of the 27-point
+// pattern: work items of kColFX x kColFY nodes of one body over a run of z
+// planes, and per item plane a record of the footprint rows' K stencils
+// (value k = entry of neighbour (dz+1) 9 + (dy+1) 3 + (dx+1); value 27 = the
+// row's FP32 mass, negated where the row has R entries) plus, for the planes
+// where a row has R entries, a record of their R stencils.  Items run body by
+// body, then by z run, then by footprint row and column, so neighbouring
+// footprints (which share halo rows) are dealt to the same XCD and run side
+// by side.
+// Leaves ncol_items = 0 (tiles only) for any other mesh and for vectors of
+// 2 GB or more.
+mrsdc_status build_columns(mrsdc_ctx *c, int64_t N, BatchArgs &a) {
+  if (c->cfg.precision != MRSDC_FP32_REFINE) return MRSDC_OK;  // the FP32 operator only
+  if (N * c->S * 4 >= ((int64_t)1 << 31)) return MRSDC_OK;
+  int64_t dm[2][3];
+  for (int b = 0; b < c->nbody; ++b)
+    if (!box_dims(c->body[b], dm[b])) return MRSDC_OK;
+  // per-row stencils in natural row order
+  std::vector<double> ks((size_t)N * kStencil, 0.0), rs;
+  std::vector<int> ridx(N, -1);
+  std::vector<float> mass32(N);
+  int64_t colplanes = 0;
+  for (int b = 0; b < c->nbody; ++b) {
+    const HostBody &B = c->body[b];
+    const int64_t nx = dm[b][0], ny = dm[b][1];
+    colplanes += ((dm[b][0] + kColFX - 1) / kColFX) * ((dm[b][1] + kColFY - 1) / kColFY) * dm[b][2];
+    for (int64_t i = 0; i < B.n; ++i) {
+      const int64_t row = c->off[b] + i;
+      const int64_t ix = i % nx, iy = (i / nx) % ny, iz = i / (nx * ny);
+      mass32[row] = (float)B.mass[i];
+      bool hasR = false;
+      for (int64_t e = B.rowptr[i]; e < B.rowptr[i + 1]; ++e) {
+        const int64_t j = B.col[e];
+        const int64_t jx = j % nx, jy = (j / nx) % ny, jz = j / (nx * ny);
+        const int k = (int)((jz - iz + 1) * 9 + (jy - iy + 1) * 3 + (jx - ix + 1));
+        ks[(size_t)row * kStencil + k] = B.K[e];
+        hasR |= !B.R.empty() && B.R[e] != 0.0;
+      }
+      if (!hasR) continue;
+      ridx[row] = (int)(rs.size() / kStencil);
+      rs.resize(rs.size() + kStencil, 0.0);
+      double *r = rs.data() + rs.size() - kStencil;
+      for (int64_t e = B.rowptr[i]; e < B.rowptr[i + 1]; ++e) {
+        const int64_t j = B.col[e];
+        const int64_t jx = j % nx, jy = (j / nx) % ny, jz = j / (nx * ny);
+        r[(jz - iz + 1) * 9 + (jy - iy + 1) * 3 + (jx - ix + 1)] = B.R[e];
+      }
+    }
+  }
+  // Run length: the one (8 .. 64 planes) with the shortest simulated
+  // makespan when XCD x deals its eighth of the items, in order, to its
+  // resident workgroups as they come free, an item costing its planes plus
+  // the steps that fill its pipeline.
+  const int64_t slots = std::max<int64_t>(1, 256 * (int64_t)col_workgroups_per_cu() / 8);
+  auto makespan = [&](int64_t zr) {
+    std::vector<int64_t> cost;
+    for (int b = 0; b < c->nbody; ++b) {
+      const int64_t fp = ((dm[b][0] + kColFX - 1) / kColFX) * ((dm[b][1] + kColFY - 1) / kColFY);
+      for (int64_t z0 = 0; z0 < dm[b][2]; z0 += zr)
+        cost.insert(cost.end(), fp, std::min(dm[b][2], z0 + zr) - z0 + 3 + kColDepth);
+    }
+    const int64_t T = (int64_t)cost.size();
+    int64_t worst = 0;
+    for (int x = 0; x < 8; ++x) {
+      std::priority_queue<int64_t, std::vector<int64_t>, std::greater<int64_t>> free_at;
+      for (int64_t i = 0; i < slots; ++i) free_at.push(0);
+      for (int64_t t = T * x / 8; t < T * (x + 1) / 8; ++t) {
+        const int64_t s0 = free_at.top();
+        free_at.pop();
+        free_at.push(s0 + cost[t]);
+        worst = std::max(worst, s0 + cost[t]);
+      }
+    }
+    return worst;
+  };
+  int64_t zrun = 64, best = makespan(64);
+  for (int64_t zr = 63; zr >= 8; --zr) {
+    const int64_t ms = makespan(zr);
+    if (ms < best) best = ms, zrun = zr;
+  }
+  std::vector<int> items;
+  std::vector<float> krec, rrec;
+  const size_t rec = (size_t)kColRows * kStencil;
+  for (int b = 0; b < c->nbody; ++b)
+    for (int64_t z0 = 0; z0 < dm[b][2]; z0 += zrun)
+      for (int64_t y0 = 0; y0 < dm[b][1]; y0 += kColFY)
+        for (int64_t x0 = 0; x0 < dm[b][0]; x0 += kColFX) {
+          const int64_t z1 = std::min(dm[b][2], z0 + zrun);
+          const int kb = (int)(krec.size() / rec), rb = (int)(rrec.size() / rec);
+          uint64_t mask = 0;
+          for (int64_t z = z0; z < z1; ++z) {
+            krec.resize(krec.size() + rec, 0.0f);
+            float *kr = krec.data() + krec.size() - rec;
+            std::vector<float> rr(rec, 0.0f);
+            bool anyR = false;
+            for (int r = 0; r < kColRows; ++r) {
+              const int64_t gx = x0 + r % kColFX, gy = y0 + r / kColFX;
+              if (gx >= dm[b][0] || gy >= dm[b][1]) continue;  // outside the body: zeros
+              const int64_t row = c->off[b] + gx + dm[b][0] * (gy + dm[b][1] * z);
+              for (int k = 0; k < 27; ++k)
+                kr[r * kStencil + k] = (float)ks[(size_t)row * kStencil + k];
+              const bool hasR = ridx[row] >= 0;
+              kr[r * kStencil + 27] = hasR ? -mass32[row] : mass32[row];
+              if (!hasR) continue;
+              anyR = true;
+              for (int k = 0; k < 27; ++k)
+                rr[r * kStencil + k] = (float)rs[(size_t)ridx[row] * kStencil + k];
+            }
+            if (anyR) {
+              mask |= 1ull << (z - z0);
+              rrec.insert(rrec.end(), rr.begin(), rr.end());
+            }
+          }
+          const int it[kColItem] = {(int)c->off[b], (int)dm[b][0], (int)dm[b][1], (int)dm[b][2],
+                                    (int)x0, (int)y0, (int)z0, (int)z1, kb, rb,
+                                    (int)(uint32_t)mask, (int)(uint32_t)(mask >> 32)};
+          items.insert(items.end(), it, it + kColItem);
+        }
+  c->col_stored_bytes = (int64_t)(krec.size() + rrec.size()) * 4 + (int64_t)items.size() * 4;
+  if (rrec.empty()) rrec.assign(rec, 0.0f);
+  mrsdc_status st;
+  int *pi;
+  float *pf;
+  if ((st = upload(c, &pi, items))) return st;
+  a.op.col_items = pi;
+  a.op.ncol_items = (int)(items.size() / kColItem);
+  if ((st = upload(c, &pf, krec))) return st;
+  a.op.kcol32 = pf;
+  if ((st = upload(c, &pf, rrec))) return st;
+  a.op.rcol32 = pf;
+  if ((st = upload(c, &pf, std::vector<float>(64, 0.0f)))) return st;
+  a.op.col_zero = pf;
+  // one workgroup per item: the dispatcher balances the items over the CUs
+  a.cgrid64 = a.cgrid32 = (a.op.ncol_items + 7) / 8 * 8 + 8;
+  return MRSDC_OK;
+}
+
 mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
   DevState &d = c->d;
   const int S = c->S;
@@ -494,6 +647,7 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
   double *pv;
   a.op.N = N;
   if ((st = build_stage_tiles(c, N, rowptr, col, val, nk, a))) return st;
+  if ((st = build_columns(c, N, a))) return st;
   if ((st = upload(c, &pv, Kd))) return st;
   a.Kd = pv;
   if ((st = upload(c, &pv, Rd))) return st;
@@ -525,8 +679,8 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
   if ((st = dalloc(c, &a.sc, 1))) return st;
   HIPCHK(hipMemset(a.sc, 0, sizeof(BatchScalars)));
   HIPCHK(hipMemcpy(a.sc->active, act.data(), sizeof(int) * S, hipMemcpyHostToDevice));
-  if ((st = dalloc(c, &a.partial,
-                   3 * (size_t)std::max(a.grid, std::max(a.sgrid64, a.sgrid32)) * S, true)))
+  const int maxgrid = std::max({a.grid, a.sgrid64, a.sgrid32, a.cgrid64, a.cgrid32});
+  if ((st = dalloc(c, &a.partial, 3 * (size_t)maxgrid * S, true)))
     return st;
   if ((st = dalloc(c, &c->stage, N))) return st;
   a.w = d.w;
@@ -1357,9 +1511,14 @@ mrsdc_status mrsdc_create(mrsdc_ctx **out, const mrsdc_config *cfg) {
     hipGetLastError();
     return MRSDC_EDEVICE;
   }
+  if (cfg->alloc && (!cfg->alloc->alloc || !cfg->alloc->release)) return MRSDC_EINVAL;
   mrsdc_ctx *c = new (std::nothrow) mrsdc_ctx();
   if (!c) return MRSDC_ENOMEM;
   c->cfg = *cfg;
+  if (cfg->alloc) {
+    c->allocator = *cfg->alloc;
+    c->cfg.alloc = &c->allocator;
+  }
   *out = c;
   return MRSDC_OK;
 }
@@ -1709,15 +1868,14 @@ mrsdc_status mrsdc_set_stationary(mrsdc_ctx *c, double rtol, int maxit, int *ite
       dinv[c->off[b] + i] = 1.0 / dl;
     }
   }
-  double *ddinv = nullptr, *dzero = nullptr;
+  double *ddinv = (double *)dev_malloc(c, sizeof(double) * N);
+  double *dzero = (double *)dev_malloc(c, sizeof(double) * N);
   auto release = [&]() {
-    if (ddinv) hipFree(ddinv);
-    if (dzero) hipFree(dzero);
+    dev_free(c, ddinv);
+    dev_free(c, dzero);
   };
-  if (hipMalloc((void **)&ddinv, sizeof(double) * N) != hipSuccess ||
-      hipMalloc((void **)&dzero, sizeof(double) * N) != hipSuccess) {
+  if (!ddinv || !dzero) {
     release();
-    hipGetLastError();
     return fail(c, MRSDC_ENOMEM, "device allocation failed");
   }
   hipError_t he;
@@ -1828,14 +1986,16 @@ mrsdc_status mrsdc_time_operator(mrsdc_ctx *c, int reps, double *avg_us, int64_t
   hipEventDestroy(e1);
   *avg_us = 1e3 * ms / reps;
   if (bytes) {
-    // batched: every stored entry (4-byte slot + value) once, per row its
-    // extent, K count, own slot and mass (22 bytes), and the S right-hand
-    // sides read once and written once (FP32 form: FP32 values and vectors)
+    // batched, tiled: every stored entry (4-byte slot + value) once, per row
+    // its extent, K count, own slot and mass (22 bytes), and the S right-hand
+    // sides read once and written once (FP32 form: FP32 values and vectors);
+    // column sweep: the stencil records and work items once, and the S
+    // right-hand sides read once and written once
     const bool f32 = c->cfg.precision == MRSDC_FP32_REFINE;
-    const int64_t vb = f32 ? 4 : 8;
-    *bytes = c->S > 0 ? c->batch_entries * (4 + vb) + 22 * c->ba.N +
-                            2 * vb * (int64_t)c->S * c->ba.N
-                      : c->times.cg_spmv_bytes;
+    const int64_t vb = f32 ? 4 : 8, rhs = 2 * vb * (int64_t)c->S * c->ba.N;
+    *bytes = c->S == 0                 ? c->times.cg_spmv_bytes
+             : c->ba.op.ncol_items > 0 ? c->col_stored_bytes + rhs
+                                       : c->batch_entries * (4 + vb) + 22 * c->ba.N + rhs;
   }
   return MRSDC_OK;
 }
@@ -1861,8 +2021,8 @@ mrsdc_status mrsdc_destroy(mrsdc_ctx *c) {
   if (!c) return MRSDC_OK;
   if (c->stream) hipStreamSynchronize(c->stream);
   free_device(c);
+  for (void *p : c->df_allocs) dev_free(c, p);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
-  for (void *p : c->df_allocs) hipFree(p);
   if (c->ctr_host) hipHostFree(c->ctr_host);
   if (c->bsc_host) hipHostFree(c->bsc_host);
   for (hipEvent_t e : c->ev) hipEventDestroy(e);
@@ -2076,6 +2236,74 @@ mrsdc_status mrsdc_batch_get_temperature(mrsdc_ctx *c, int s, double *out, int64
   return MRSDC_OK;
 }
 
+mrsdc_status mrsdc_batch_get_temperature_device(mrsdc_ctx *c, int s, void *dptr, int64_t n,
+                                                void *stream) {
+  mrsdc_status st = need_batch(c, s);
+  if (st) return st;
+  if (!dptr) return fail(c, MRSDC_EINVAL, "null output");
+  if (!c->prepared) return fail(c, MRSDC_ESTATE, "no device state yet (advance once first)");
+  if ((st = batch_upload_pending(c))) return st;
+  if (n != c->ba.N) return fail(c, MRSDC_EINVAL, "length mismatch");
+  hipStream_t hs = stream ? (hipStream_t)stream : c->stream;
+  if (hs != c->stream) HIPCHK(hipStreamSynchronize(c->stream));  // the state is complete
+  blaunch_gather((double *)dptr, c->d.T[0], n, c->S, s, hs);
+  HIPCHK(hipGetLastError());
+  return MRSDC_OK;
+}
+
+mrsdc_status mrsdc_batch_advance_horizons(mrsdc_ctx *c, const double *horizon, mrsdc_stats *stats) {
+  mrsdc_status st = need_batch(c, 0);
+  if (st) return st;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (!horizon) return fail(c, MRSDC_EINVAL, "null horizons");
+  const int S = c->S;
+  const double dt = c->cfg.dt;
+  std::vector<int64_t> n(S, 0);
+  int64_t nmax = 0;
+  for (int s = 0; s < S; ++s) {
+    if (!c->sc_active[s]) continue;
+    const double h = horizon[s];
+    if (!(h >= 0) || !std::isfinite(h)) return fail(c, MRSDC_EINVAL, "bad horizon of scenario %d", s);
+    const double ns = h / dt;
+    n[s] = (int64_t)std::llround(ns);
+    if (std::fabs(ns - (double)n[s]) > 1e-9 * std::max(1.0, ns))
+      return fail(c, MRSDC_EINVAL, "horizon %.17g of scenario %d is not a multiple of dt %.17g",
+                  h, s, dt);
+    nmax = std::max(nmax, n[s]);
+  }
+  // a scenario leaves the batch once its horizon is reached; the others go on
+  std::vector<int> was(c->sc_active);
+  const bool joined = c->batch_joined;
+  mrsdc_stats acc;
+  std::memset(&acc, 0, sizeof acc);
+  for (int64_t k = 0; k < nmax && !st; ++k) {
+    for (int s = 0; s < S; ++s)
+      if (was[s] && k == n[s] && (st = mrsdc_batch_set_active(c, s, 0))) break;
+    if (st) break;
+    mrsdc_stats one;
+    if ((st = mrsdc_batch_advance(c, 1, &one))) break;
+    acc.steps += one.steps;
+    acc.solves += one.solves;
+    acc.pcg_iters += one.pcg_iters;
+    acc.refine_steps += one.refine_steps;
+    acc.max_iters = std::max(acc.max_iters, one.max_iters);
+    acc.redone_steps += one.redone_steps;
+    acc.wall_s += one.wall_s;
+    acc.sweeps += one.sweeps;
+    acc.graph_captures += one.graph_captures;
+    acc.graph_launches += one.graph_launches;
+    for (int r = 0; r < 17; ++r) acc.residual[r] = one.residual[r];
+  }
+  for (int s = 0; s < S; ++s)  // every scenario active again as it was
+    if (was[s] && !c->sc_active[s]) {
+      const mrsdc_status e = mrsdc_batch_set_active(c, s, 1);
+      if (!st) st = e;
+    }
+  c->batch_joined = joined;  // they rejoin with states the learned budgets fit
+  if (stats) *stats = acc;
+  return st;
+}
+
 mrsdc_status mrsdc_quadrature(int M, int node_family, int P, double dt, double *tau, double *s,
                               double *shat, double *stil, double *spq) {
   Weights *w = new (std::nothrow) Weights;
@@ -2103,13 +2331,10 @@ mrsdc_status mrsdc_quadrature(int M, int node_family, int P, double dt, double *
 // ---- thermo-elastic deformation ----
 
 static mrsdc_status df_alloc_bytes(mrsdc_ctx *c, void **p, size_t bytes) {
-  void *q = nullptr;
-  hipError_t e = hipMalloc(&q, std::max<size_t>(bytes, 8));
-  if (e != hipSuccess) {
-    hipGetLastError();
-    return fail(c, MRSDC_ENOMEM, "hipMalloc(%zu) for the deformation blocks failed: %s", bytes,
-                hipGetErrorString(e));
-  }
+  void *q = dev_malloc(c, std::max<size_t>(bytes, 8));
+  if (!q)
+    return fail(c, MRSDC_ENOMEM, "device allocation of %zu bytes for the deformation failed",
+                bytes);
   c->df_allocs.push_back(q);
   c->df_bytes += (int64_t)bytes;
   *p = q;
@@ -2128,7 +2353,7 @@ static mrsdc_status df_upload(mrsdc_ctx *c, const T **p, const T *h, size_t n) {
 
 static void df_release(mrsdc_ctx *c) {
   if (c->stream) hipStreamSynchronize(c->stream);
-  for (void *p : c->df_allocs) hipFree(p);
+  for (void *p : c->df_allocs) dev_free(c, p);
   c->df_allocs.clear();
   c->df_bytes = 0;
   c->df_ready = false;

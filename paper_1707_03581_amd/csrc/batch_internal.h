@@ -28,7 +28,29 @@ struct BatchOp {
   const int64_t *tstart = nullptr;  // [ntiles + 1]
   const int64_t *prow = nullptr;    // [N]
   const double *pmass = nullptr;    // [N] lumped mass of row prow[pos]
+  // Column sweep (FP32 operator, every body a box of the 27-point pattern).
+  // Work items are footprints of kColFX x kColFY nodes of one body over a run
+  // of z planes.  Each plane of an item has one record of its footprint rows'
+  // K stencils (kColRows rows of kStencil values, row r = node (x0 + r %
+  // kColFX, y0 + r / kColFX)): value k is the entry of neighbour
+  // k = (dz+1) 9 + (dy+1) 3 + (dx+1), 0 where there is none, and value 27 is
+  // the row's lumped mass in FP32, negated when the row has R entries (rows
+  // outside the body are all zeros).  The planes where a row has R entries
+  // also have one record of the rows' R stencils (same layout, no mass).
+  int ncol_items = 0;
+  // [ncol_items][kColItem]: row offset, nx, ny, nz, x0, y0, z0, z1, first K
+  // record, first R record, R plane mask (bit z - z0; two words)
+  const int *col_items = nullptr;
+  const float *kcol32 = nullptr;    // [K records][kColRows][kStencil]
+  const float *rcol32 = nullptr;    // [R records][kColRows][kStencil]
+  const float *col_zero = nullptr;  // 64 zeros: the halo rows outside a body
 };
+constexpr int kColFX = 4, kColFY = 4;                // footprint of a column item
+constexpr int kColRows = kColFX * kColFY;            // rows of a plane of an item
+constexpr int kColPL = (kColFX + 2) * (kColFY + 2);  // staged rows per plane (halo included)
+constexpr int kColDepth = 2;                         // stages in flight beyond the one read
+constexpr int kColItem = 12;                         // ints per work item
+constexpr int kStencil = 28;                         // 27 neighbours + the mass
 constexpr int kMaxR = 8;  // tiles hold at most 4 kMaxR rows
 
 // Staging buffer of the tiled kernels: 64 KB per workgroup (two workgroups
@@ -73,6 +95,7 @@ struct BSolve {
 struct BatchArgs {
   int S = 0, M = 0, P = 0, grid = 0;
   int sgrid64 = 0, sgrid32 = 0;  // workgroups of the tiled kernels (FP64 / FP32 staging)
+  int cgrid64 = 0, cgrid32 = 0;  // workgroups of the column-sweep kernels (0: tiles)
   int64_t N = 0;
   double dtau_h[kMaxM + 1] = {};
   BatchOp op;
@@ -111,5 +134,7 @@ void blaunch_operator_timing(const BatchArgs &a, int m, int reps, hipStream_t st
 void blaunch_commit(const BatchArgs &a, double dt, hipStream_t st);
 void blaunch_scatter(double *dst, const double *src, int64_t n, int S, int s, hipStream_t st);
 void blaunch_gather(double *dst, const double *src, int64_t n, int S, int s, hipStream_t st);
+// workgroups of the column-sweep operator resident per CU (set by its LDS ring)
+int col_workgroups_per_cu();
 
 }  // namespace mrsdc

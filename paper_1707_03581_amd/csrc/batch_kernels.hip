@@ -101,6 +101,10 @@ __device__ inline float readlane_t<float>(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
+// one rounding per product-sum, in every kernel that forms a row of the operator
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // ---------------------------------------------------------------------------
 // LDS-staged multi-RHS operator.  A workgroup takes one tile (TR consecutive
 // rows) at a time: it copies the rows of x its tile reads (the union of the
@@ -247,14 +251,14 @@ __device__ __attribute__((always_inline)) inline void entry_sum(const StageLds<X
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int k = 0; k < VEC; ++k) acc[k] += v[j] * (AT)xv[j][k];
+      for (int k = 0; k < VEC; ++k) acc[k] = fma_t(v[j], (AT)xv[j][k], acc[k]);
   }
   for (; e < e1; ++e) {
     XT xv[VEC];
     xrow<XT, VEC, AL>(L.x, L.eslot[rel + e], S, s0, xv);
     const AT v = (AT)L.eval[rel + e];
 #pragma unroll
-    for (int k = 0; k < VEC; ++k) acc[k] += v * (AT)xv[k];
+    for (int k = 0; k < VEC; ++k) acc[k] = fma_t(v, (AT)xv[k], acc[k]);
   }
 }
 
@@ -345,6 +349,198 @@ __device__ inline void publish_lanes(const double (&v)[K][Lanes<XT>::VEC], doubl
       partial[((size_t)k * S + threadIdx.x) * grid + blockIdx.x] = acc;
     }
     __syncthreads();
+  }
+}
+
+// per-scenario block sums of the lanes' partials (v[k][i] for scenario s0 + i)
+// into partial[k][s][blk]: fixed order over waves and row slots
+template <int K, int VEC, int RPW>
+__device__ inline void publish_groups_in(const double (&v)[K][VEC], double *partial, int grid,
+                                         int S, double *sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane / (64 / VEC), s0 = (lane % (64 / VEC)) * VEC;
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) sh[(w * RPW + lr) * 64 + s0 + i] = v[k][i];
+    __syncthreads();
+    if (threadIdx.x < (unsigned)S) {
+      double acc = 0.0;
+      for (int j = 0; j < 4 * RPW; ++j) acc += sh[j * 64 + threadIdx.x];
+      partial[((size_t)k * S + threadIdx.x) * grid + blockIdx.x] = acc;
+    }
+    __syncthreads();
+  }
+}
+template <int K, int VEC, int RPW>
+__device__ inline void publish_groups(const double (&v)[K][VEC], double *partial, int grid,
+                                      int S) {
+  __shared__ double sh[4 * RPW * 64];
+  publish_groups_in<K, VEC, RPW>(v, partial, grid, S, sh);
+}
+
+// ---------------------------------------------------------------------------
+// Column-sweep multi-RHS operator (FP32 form; every body a box of the
+// 27-point pattern).  A work item is a footprint of kColFX x kColFY nodes of
+// one body over a run of z planes.  The workgroup streams up the run one
+// staged plane at a time (the footprint and its one-node halo: kColPL rows,
+// 64 values apart whatever S is): a lane reads the 3 x 3 neighbourhood of
+// its column in plane P once and adds it to the three rows it touches, the
+// neighbour-below part (dz = -1) of row P + 1, the dz = 0 part of row P and
+// the dz = +1 part of row P - 1, which is then complete.  Each row so gets
+// its stencil values in stencil order (dz, then dy, then dx), which is the
+// CSR order of its entries, with exact zeros where a neighbour or entry is
+// missing: the same sums, rounded the same way, as the tiled product (K and
+// R apart, then K + h R).  Each staged value is read from LDS once per
+// lane instead of three times, each staged row is copied once per item
+// instead of once per tile that touches it, and each matrix entry is found
+// from its stencil position instead of a stored column.  The planes (and the
+// rows' stencil records) arrive by direct global-to-LDS copies that hold no
+// registers, kColDepth stages ahead, waited for by count one stage at a time.
+//
+// Lane mapping as in the tiled product: a lane owns four consecutive
+// scenarios of a row, a wave the four rows w 4 .. w 4 + 3 of the plane.
+// ---------------------------------------------------------------------------
+constexpr int kColPlaneUnits = kColPL * 16;                     // 16-byte units of a plane
+constexpr int kColRecUnits = kColRows * kStencil * 4 / 16;      // of a K (or R) record
+constexpr int kColRecSlot = (2 * kColRecUnits + 63) / 64 * 64;  // K, R and the copy tail
+static_assert(kColPlaneUnits % 64 == 0, "a plane is whole wave-wide copies");
+static_assert(kColRows == 16 && kBlock == 256, "four waves of four rows");
+// Wave-wide copies per plane: the staged rows in UB-byte units (16 when a row
+// of S values is a multiple of 16 bytes, else 4), then the records in 16-byte
+// units; copy j is issued by wave j % 4, so wave 0 issues C0 and the others C1
+template <int UB>
+struct ColCopies {
+  static constexpr int X = kColPlaneUnits * 16 / UB / 64;
+  static constexpr int N = X + kColRecSlot / 64;
+  static constexpr int C0 = (N + 3) / 4, C1 = N / 4;
+};
+
+// Stage s = staged plane s + 1 (read in step s) and the stencil record of
+// plane s + 2 (read in steps s .. s + 2).  With D stages in flight beyond
+// the one being read: D + 1 plane slots and D + 3 record slots.
+template <int D>
+struct ColLds {
+  static constexpr int NX = D + 1, NR = D + 3;
+  uint4 x[NX][kColPlaneUnits];
+  uint4 rec[NR][kColRecSlot];
+};
+// workgroups per CU that the ring leaves room for (160 KB of LDS)
+template <int D>
+struct ColOcc {
+  static constexpr int W = 3 * sizeof(ColLds<D>) + 768 <= 160 * 1024   ? 3
+                           : 2 * sizeof(ColLds<D>) + 512 <= 160 * 1024 ? 2
+                                                                        : 1;
+};
+
+struct ColItem {
+  int off, nx, ny, nz, x0, y0, z0, z1, kb, rb;
+  unsigned mlo, mhi;
+};
+// (wave-uniform: kept in scalar registers)
+__device__ inline ColItem col_item(const BatchOp &op, int t) {
+  const int *p = op.col_items + (size_t)kColItem * t;
+  int v[kColItem];
+#pragma unroll
+  for (int k = 0; k < kColItem; ++k) v[k] = __builtin_amdgcn_readfirstlane(p[k]);
+  return ColItem{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], v[9],
+                 (unsigned)v[10], (unsigned)v[11]};
+}
+template <int N>
+__device__ inline int col_slot(int p) { return (p + 4 * N) % N; }  // p >= -2
+
+// Issue wave w's copies of stage s >= z0 - 2: plane P = s + 1 (staged as
+// zeros outside the body and past the run's top neighbour z1) and the
+// record of plane s + 2 (the run's first record past the run).  Every lane
+// copies from a valid address: halo rows outside the body and the values
+// past S of a row come from 64 zeros; the records' tail repeats the first K
+// unit.
+template <int UB, int D>
+__device__ __forceinline__ void col_issue(const BatchOp &op, const ColItem &it, int s,
+                                          const float *__restrict__ x, int S, ColLds<D> &L,
+                                          int w) {
+  using CC = ColCopies<UB>;
+  constexpr int UPH = 64 * 4 / UB;  // units per staged row (64 values)
+  const int lane = threadIdx.x & 63, upr = S * 4 / UB, P = s + 1, R = s + 2;
+  const bool pin = (P >= 0) & (P < it.nz) & (P <= it.z1);
+  const int pr = ((R >= it.z0) & (R < it.z1)) ? R - it.z0 : 0;
+  const unsigned long long mask = ((unsigned long long)it.mhi << 32) | it.mlo;
+  const bool hasr = (mask >> pr) & 1ull;
+  const int kr = it.kb + pr, rr = it.rb + __builtin_popcountll(mask & ((1ull << pr) - 1ull));
+  const char *xb = reinterpret_cast<const char *>(x);
+  const char *zb = reinterpret_cast<const char *>(op.col_zero);
+  const char *kb = reinterpret_cast<const char *>(op.kcol32) + (size_t)kr * kColRecUnits * 16;
+  const char *rb = reinterpret_cast<const char *>(op.rcol32) + (size_t)rr * kColRecUnits * 16;
+  auto *lx = reinterpret_cast<char *>(L.x[col_slot<ColLds<D>::NX>(s)]);
+  uint4 *lr = L.rec[col_slot<ColLds<D>::NR>(R)];
+#pragma unroll
+  for (int i = 0; i < CC::C0; ++i) {
+    const int j = w + 4 * i;  // wave-uniform
+    if (j >= CC::N) break;
+    if (j < CC::X) {
+      const int u = j * 64 + lane, hs = u / UPH, part = u % UPH;
+      const int hx = hs % (kColFX + 2), hy = hs / (kColFX + 2);
+      const int gx = it.x0 - 1 + hx, gy = it.y0 - 1 + hy;
+      const bool in = pin & ((unsigned)gx < (unsigned)it.nx) & ((unsigned)gy < (unsigned)it.ny) &
+                      (part < upr);
+      // (32-bit offsets: the column sweep runs only on vectors below 2 GB)
+      const unsigned row = (unsigned)(it.off + gx + it.nx * (gy + it.ny * P));
+      const char *src = in ? xb + (row * (unsigned)upr + (unsigned)part) * (unsigned)UB
+                           : zb + part * UB;
+      auto *dst = (__attribute__((address_space(3))) void *)(lx + j * 64 * UB);
+      if constexpr (UB == 16) __builtin_amdgcn_global_load_lds((const void *)src, dst, 16, 0, 0);
+      else __builtin_amdgcn_global_load_lds((const void *)src, dst, 4, 0, 0);
+    } else {
+      const int u = (j - CC::X) * 64 + lane;
+      const bool isr = hasr & (u >= kColRecUnits) & (u < 2 * kColRecUnits);
+      const int uk = u < kColRecUnits ? u : (u < 2 * kColRecUnits ? u - kColRecUnits : 0);
+      const char *src = (isr ? rb : kb) + uk * 16;
+      __builtin_amdgcn_global_load_lds(
+          (const void *)src, (__attribute__((address_space(3))) void *)&lr[(j - CC::X) * 64], 16,
+          0, 0);
+    }
+  }
+}
+
+// s_waitcnt vmcnt(N) lgkmcnt(0) (gfx9 encoding: vmcnt in bits 3:0 and 15:14)
+template <int N>
+__device__ __forceinline__ void col_wait() {
+  static_assert(N >= 0 && N < 64, "vmcnt holds six bits");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | ((N >> 4) << 14));
+}
+// Workgroup barrier that orders the LDS accesses around it but leaves the
+// copies in flight (a fence would wait for every one of them).
+__device__ __forceinline__ void col_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+// Wait until this wave's copies of plane z + 2 have landed, k + 1 planes
+// (k = min(z - z0, D - 1)) into the run, with D planes in flight beyond
+// z + 1, C copies per plane and ST stores per plane formed by this wave.  In
+// issue order, what follows those copies is exactly: the copies of the D - 1
+// later planes and the stores of the last k + 1 planes formed (the stores
+// are unconditional buffer stores, so the count is exact), and vmcnt counts
+// them in order.
+template <int C, int ST, int D, int K = 0>
+__device__ __forceinline__ void col_wait_plane(int k) {
+  if constexpr (K == D - 1) {
+    col_wait<(D - 1) * C + ST * D>();
+  } else {
+    if (k == K) col_wait<(D - 1) * C + ST * (K + 1)>();
+    else col_wait_plane<C, ST, D, K + 1>(k);
+  }
+}
+
+// acc[q] += sum over the nine positions j = 3 dy + dx of one plane (in
+// order) of c[j] xv[j][q]
+__device__ __forceinline__ void col_part(const float *c, const float4 (&xv)[9], float (&acc)[4]) {
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    const float w = c[j];
+    acc[0] = fma_t(w, xv[j].x, acc[0]);
+    acc[1] = fma_t(w, xv[j].y, acc[1]);
+    acc[2] = fma_t(w, xv[j].z, acc[2]);
+    acc[3] = fma_t(w, xv[j].w, acc[3]);
   }
 }
 
@@ -805,6 +1001,121 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_a(BatchArgs a, int m, double dt
 }
 
 
+// (a) in the column sweep: q = M p + dtau (K + h R) p and the partial p.q,
+// one item per workgroup, XCD x taking the x-th eighth of the items (their
+// footprints are neighbours: shared halo rows stay in that XCD's L2).  Where
+// a row of S values is a multiple of 16 bytes, a lane stores its four values
+// at once (the values of idle scenarios too, which no later step reads);
+// otherwise each value apart, only where its scenario is on.
+template <int TIMING, int UB, int D>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ColOcc<D>::W)))
+void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
+  using CC = ColCopies<UB>;
+  constexpr int ST = UB == 16 ? 1 : 4;  // stores per step
+  constexpr int NX = ColLds<D>::NX, NR = ColLds<D>::NR;
+  __shared__ ColLds<D> L;
+  const int S = a.S, lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lr = lane >> 4, s0 = (lane & 15) * 4;
+  float h[4];
+  double v[1][4] = {};
+  bool on[4], any = false;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int s = s0 + i;
+    on[i] = TIMING ? s < S : lane_on(a.sc, s, S);
+    const float hs = (float)lane_h(a, s);
+    h[i] = on[i] ? hs : 0.0f;
+    any |= on[i];
+  }
+  const float dt = (float)dtau;
+  const float *p = a.p32;
+  const __amdgpu_buffer_rsrc_t qres =
+      __builtin_amdgcn_make_buffer_rsrc(a.q32, 0, (int)(a.N * S * 4), 0x00020000);
+  const int T = a.op.ncol_items, xcd = blockIdx.x % kXcd, local = blockIdx.x / kXcd;
+  const int t = (int)((int64_t)T * xcd / kXcd) + local;
+  const bool has = t < (int)((int64_t)T * (xcd + 1) / kXcd);
+  if (__syncthreads_or(any) && has) {
+    const ColItem it = col_item(a.op, t);
+    const int r = w * 4 + lr, lx = r % kColFX, ly = r / kColFX;
+    const int lb = (ly * (kColFX + 2) + lx) * 64 + s0;  // the row's (-1, -1) halo row
+    const bool rok = (it.x0 + lx < it.nx) & (it.y0 + ly < it.ny);
+    // Step z reads plane z + 1 and completes row z; steps z0 - 2 and z0 - 1
+    // only start rows z0 and z0 + 1 (what they add to rows below z0 is never
+    // used).
+    const int zb = it.z0 - 2;
+    for (int q = zb; q <= zb + D; ++q) col_issue<UB, D>(a.op, it, q, p, S, L, w);
+    if (w == 0) col_wait<D * CC::C0>();
+    else col_wait<D * CC::C1>();
+    col_barrier();
+    // K and R sums of rows z, z + 1, z + 2 (a: z, b: z + 1, c: z + 2)
+    float ka[4] = {}, kb4[4] = {}, ra[4] = {}, rb4[4] = {};
+    float4 own = make_float4(0.f, 0.f, 0.f, 0.f);  // x of row z (plane z's centre)
+    for (int z = zb; z < it.z1; ++z) {
+      const float *xs = reinterpret_cast<const float *>(L.x[col_slot<NX>(z)]) + lb;
+      float4 xv[9];
+#pragma unroll
+      for (int j = 0; j < 9; ++j)
+        xv[j] = *reinterpret_cast<const float4 *>(xs + ((j / 3) * (kColFX + 2) + j % 3) * 64);
+      const float *c2 = reinterpret_cast<const float *>(L.rec[col_slot<NR>(z + 2)]) + r * kStencil;
+      const float *c1 = reinterpret_cast<const float *>(L.rec[col_slot<NR>(z + 1)]) + r * kStencil;
+      const float *c0 = reinterpret_cast<const float *>(L.rec[col_slot<NR>(z)]) + r * kStencil;
+      constexpr int RO = kColRows * kStencil;  // the R record after the K record
+      float kc[4] = {}, rc[4] = {};
+      col_part(c2, xv, kc);       // row z + 2: dz = -1
+      col_part(c1 + 9, xv, kb4);  // row z + 1: dz = 0
+      col_part(c0 + 18, xv, ka);  // row z: dz = +1
+      const float m2 = c2[kStencil - 1], m1 = c1[kStencil - 1], m0 = c0[kStencil - 1];
+      if (m2 < 0.0f) col_part(c2 + RO, xv, rc);  // rows with R entries: mass < 0
+      if (m1 < 0.0f) col_part(c1 + RO + 9, xv, rb4);
+      if (m0 < 0.0f) col_part(c0 + RO + 18, xv, ra);
+      // row z complete
+      const float ow[4] = {own.x, own.y, own.z, own.w};
+      const float mass = fabsf(m0);
+      const bool row_in = rok & (z >= it.z0);
+      const unsigned row = (unsigned)(it.off + it.x0 + lx + it.nx * (it.y0 + ly + it.ny * z));
+      float qv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float y = m0 < 0.0f ? ka[q] + h[q] * ra[q] : ka[q];
+        qv[q] = mass * ow[q] + dt * y;
+        if (row_in & on[q]) v[0][q] += (double)ow[q] * (double)qv[q];
+      }
+      // a fixed number of stores per step whatever the masks (a masked
+      // store's offset lies past the buffer, so it is dropped)
+      const unsigned off = (row * (unsigned)S + (unsigned)s0) * 4u;
+      if constexpr (ST == 1) {
+        typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+        const u32x4 val = {__float_as_uint(qv[0]), __float_as_uint(qv[1]), __float_as_uint(qv[2]),
+                           __float_as_uint(qv[3])};
+        const bool st = row_in & (s0 < S);
+        __builtin_amdgcn_raw_buffer_store_b128(val, qres, (int)(off | ((unsigned)!st << 31)), 0, 0);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const bool st = row_in & on[q];
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(qv[q]), qres,
+                                                (int)((off + 4u * q) | ((unsigned)!st << 31)), 0, 0);
+        }
+      }
+      own = xv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ka[q] = kb4[q];
+        kb4[q] = kc[q];
+        ra[q] = rb4[q];
+        rb4[q] = rc[q];
+      }
+      if (w == 0) col_wait_plane<CC::C0, ST, D>(min(z - zb, D - 1));
+      else col_wait_plane<CC::C1, ST, D>(min(z - zb, D - 1));
+      col_barrier();  // stage z + 1 landed; plane z + 1 and the record of z free
+      col_issue<UB, D>(a.op, it, z + 1 + D, p, S, L, w);
+    }
+  }
+  __syncthreads();  // every copy landed before the LDS is reused
+  publish_groups_in<1, 4, 4>(v, a.partial, gridDim.x, S, reinterpret_cast<double *>(L.x[0]));
+}
+
 // ---------------------------------------------------------------------------
 // Row-group kernels: the CG vector updates with the lane mapping of the tiled
 // kernels (a lane owns VEC consecutive scenarios of a row, a wave RPW
@@ -856,27 +1167,6 @@ __device__ __forceinline__ void vstore(V *p, int64_t base, int s0, int S, const 
 #pragma unroll
     for (int k = 0; k < VEC; ++k)
       if (s0 + k < S) p[base + k] = o[k];
-  }
-}
-
-// per-scenario block sums of the lanes' partials (v[k][i] for scenario s0 + i)
-// into partial[k][s][blk]: fixed order over waves and row slots
-template <int K, int VEC, int RPW>
-__device__ inline void publish_groups(const double (&v)[K][VEC], double *partial, int grid,
-                                      int S) {
-  __shared__ double sh[4 * RPW * 64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int lr = lane / (64 / VEC), s0 = (lane % (64 / VEC)) * VEC;
-  for (int k = 0; k < K; ++k) {
-#pragma unroll
-    for (int i = 0; i < VEC; ++i) sh[(w * RPW + lr) * 64 + s0 + i] = v[k][i];
-    __syncthreads();
-    if (threadIdx.x < (unsigned)S) {
-      double acc = 0.0;
-      for (int j = 0; j < 4 * RPW; ++j) acc += sh[j * 64 + threadIdx.x];
-      partial[((size_t)k * S + threadIdx.x) * grid + blockIdx.x] = acc;
-    }
-    __syncthreads();
   }
 }
 
@@ -1327,8 +1617,37 @@ void blaunch_quad_resid(const BatchArgs &a, int k, hipStream_t st) {
   kb_resid_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, k);
 }
 
+// The column sweep runs the FP32 operator (its three staged planes of 64 FP64
+// values would leave one workgroup per CU); FP64 keeps the tiles.
+int col_workgroups_per_cu() { return ColOcc<kColDepth>::W; }
+
+template <typename V>
+static bool use_columns(const BatchArgs &a) {
+  return sizeof(V) == 4 && a.op.ncol_items > 0;
+}
+
+// workgroups of the operator launch
+template <typename V>
+static int pcg_a_grid(const BatchArgs &a) {
+  return use_columns<V>(a) ? a.cgrid32 : tgrid<V>(a);
+}
+
 template <typename V>
 static void launch_pcg_a(const BatchArgs &a, int timing, int m, double dtau, hipStream_t st) {
+  if constexpr (sizeof(V) == 4) {
+    if (use_columns<V>(a)) {
+      const int g = pcg_a_grid<V>(a);
+      constexpr int D = kColDepth;
+      if (vec16<V>(a)) {
+        if (timing) kb_pcg_a_col<1, 16, D><<<g, kBlock, 0, st>>>(a, m, dtau);
+        else kb_pcg_a_col<0, 16, D><<<g, kBlock, 0, st>>>(a, m, dtau);
+      } else {
+        if (timing) kb_pcg_a_col<1, 4, D><<<g, kBlock, 0, st>>>(a, m, dtau);
+        else kb_pcg_a_col<0, 4, D><<<g, kBlock, 0, st>>>(a, m, dtau);
+      }
+      return;
+    }
+  }
   const int g = tgrid<V>(a);
   if (vec16<V>(a)) {
     if (timing) kb_pcg_a<1, V, 16, true><<<g, kBlock, 0, st>>>(a, m, dtau);
@@ -1345,7 +1664,7 @@ static void cg_iterations(const BatchArgs &a, int m, double dtau, int slot, int 
   const int conv = std::is_same<V, float>::value ? 6 : 2;
   for (int it = 0; it < budget; ++it) {
     launch_pcg_a<V>(a, 0, m, dtau, st);
-    RED(tgrid<V>(a), 1, it, 0, slot, rtol);
+    RED(pcg_a_grid<V>(a), 1, it, 0, slot, rtol);
     if (vec16<V>(a)) kb_pcg_b<V, true><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
     else kb_pcg_b<V, false><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
     RED(a.grid, conv, it, it == budget - 1, slot, rtol);

@@ -225,3 +225,44 @@ def test_node_block_tiles_equal_row_run_tiles():
     runs, _, _ = run_batch(pb2, mem, 2)
     for s in range(len(mem)):
         assert np.array_equal(blocks[s], runs[s]), s
+
+
+def test_per_scenario_horizons():
+    """Each member advanced by its own horizon: every result equals the member
+    run alone for its own number of steps, bit for bit, and its clock shows
+    its own horizon; all members are active again afterwards."""
+    import paper_1707_03581_amd as m
+    pb = small_machine()
+    mem = members_for(pb, 4, seed0=1900)
+    dt = pb.scheme.dt
+    horizons = [2 * dt, 4 * dt, 0.0, 3 * dt]
+    ctx = m.batch_simulation(pb, mem)
+    st = ctx.advance_horizons(horizons)
+    assert st["steps"] == 4
+    for s, hz in enumerate(horizons):
+        assert ctx.get_scenario_time(s) == pytest.approx(hz)
+        got = ctx.get_scenario_temperature(s, pb.N)
+        alone, _, _ = run_batch(pb, [mem[s]], int(round(hz / dt)))
+        assert np.array_equal(got, alone[0] if hz > 0 else mem[s]["T0"]), s
+    # all of them step again afterwards
+    ctx.advance_steps(1)
+    assert all(ctx.get_scenario_time(s) == pytest.approx(hz + dt)
+               for s, hz in enumerate(horizons))
+    with pytest.raises(m.MrsdcError):
+        ctx.advance_horizons([dt, 0.5 * dt, dt, dt])  # not a multiple of dt
+    ctx.destroy()
+
+
+def test_device_copy_out():
+    import torch
+    import paper_1707_03581_amd as m
+    pb = small_machine()
+    mem = members_for(pb, 3, seed0=1950)
+    ctx = m.batch_simulation(pb, mem)
+    ctx.advance_steps(2)
+    for s in range(3):
+        t = torch.empty(pb.N, dtype=torch.float64, device="cuda")
+        ctx.get_scenario_temperature_device(s, t)
+        torch.cuda.synchronize()
+        assert np.array_equal(t.cpu().numpy(), ctx.get_scenario_temperature(s, pb.N))
+    ctx.destroy()
