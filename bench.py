@@ -180,6 +180,7 @@ def extras(pkg, args, out):
         out["machine_fp32_refine"] = precision_form(pkg, args)
     out["irregular_machine"] = irregular_form(pkg, args)
     out["graph_capture"] = graph_form(pkg, args)
+    out["autotune"] = autotune_form(pkg, args)
     out["stationary"] = stationary_form(pkg, args)
     if args.wp_levels > 0:
         out["work_precision"] = work_precision_form(pkg, args)
@@ -667,7 +668,7 @@ def graph_form(pkg, args):
     res = {}
     for graph in (0, 1):
         ctx = pkg.simulation(pb, device=0, use_graph=graph)
-        ctx.advance(4 * pb.scheme.dt)
+        ctx.advance(4 * pb.scheme.dt)  # three direct steps learn the budgets, the fourth is captured
         torch.cuda.synchronize()
         n = 40
         t = time.perf_counter()
@@ -687,7 +688,7 @@ def graph_form(pkg, args):
                             T0=20.0 + rng.uniform(-0.5, 0.5, size=pe.N)))
     for graph in (0, 1):
         ctx = pkg.batch_simulation(pe, members, device=0, use_graph=graph)
-        ctx.advance_steps(2)
+        ctx.advance_steps(4)  # three direct steps learn the budgets, the fourth is captured
         torch.cuda.synchronize()
         n = 6
         t = time.perf_counter()
@@ -697,6 +698,37 @@ def graph_form(pkg, args):
     out["ensemble_fp32_refine"] = {"ms_per_step_direct": res[0], "ms_per_step_graph": res[1],
                                    "speedup": res[0] / res[1]}
     print(f"[bench] graph capture: {out}", file=sys.stderr, flush=True)
+    return out
+
+
+def autotune_form(pkg, args):
+    """The 64-member ensemble (FP32 + refinement) with the launch variants of
+    its CG kernels chosen by timing (autotune) and with the default ones:
+    per-step time, the chosen variant and the operator time of each."""
+    import torch
+    import mrsdc_inputs as mi
+    pe = mi.ensemble_member(0, nsteps=1, precision=mi.FP32_REFINE)
+    members = []
+    for s in range(64):
+        h, alpha, pf, period, rng = mi.scenario_params(s)
+        members.append(dict(h=h, alpha=alpha, friction_W=pf, period=period,
+                            T0=20.0 + rng.uniform(-0.5, 0.5, size=pe.N)))
+    out = {}
+    for tune in (0, 1):
+        ctx = pkg.batch_simulation(pe, members, device=0, autotune=tune)
+        st = ctx.advance_steps(2)
+        torch.cuda.synchronize()
+        n = 6
+        t = time.perf_counter()
+        ctx.advance_steps(n)
+        ms = (time.perf_counter() - t) / n * 1e3
+        us, _ = ctx.time_operator(20)
+        ctx.destroy()
+        out["tuned" if tune else "default"] = {
+            "ms_per_step": ms, "op_avg_us": us, "col_depth": st["col_depth"],
+            "groups_b": st["groups_b"], "groups_c": st["groups_c"]}
+    out["speedup"] = out["default"]["ms_per_step"] / out["tuned"]["ms_per_step"]
+    print(f"[bench] autotune: {out}", file=sys.stderr, flush=True)
     return out
 
 

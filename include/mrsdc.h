@@ -85,10 +85,11 @@ typedef struct {
   int refine_maxit;   /* FP32_REFINE: outer refinement cap per solve */
   double inner_rtol;  /* FP32_REFINE: relative tolerance of each FP32 inner solve */
   int final_residual; /* nonzero: also evaluate the residual of the last sweep */
-  int use_graph;      /* nonzero: each time step is captured once into a HIP graph
-                         and replayed (one launch per step instead of hundreds);
-                         the learned CG launch budgets then only grow, and the
-                         step is captured again when one does (a converged
+  int use_graph;      /* nonzero: after three steps run directly (which learn
+                         the CG launch budgets), the time step is captured once
+                         into a HIP graph and replayed (one launch per step
+                         instead of hundreds); the learned budgets then only
+                         grow, and the step is captured again when one does (a converged
                          solve's spare launches return at once:
                          FP64 results bit for bit those of use_graph = 0; in
                          FP32_REFINE an inner solve that a smaller budget would
@@ -131,6 +132,15 @@ typedef struct {
                          device buffer of the context (and of its deformation
                          solve) comes from alloc and goes back through release;
                          both must be set */
+  int autotune;       /* nonzero (batched FP32_REFINE contexts): before the first
+                         step, time the launch variants of the CG kernels on this
+                         mesh (stages in flight of the column sweep, row groups
+                         in flight of the two CG updates) and keep the fastest.
+                         Every variant gives bit for bit the same results; the
+                         choice is kept per process for the mesh and scenario
+                         count and reported in mrsdc_stats.  2 .. 9 pick a
+                         variant without timing (bits of autotune - 2: 1 one
+                         stage in flight, 2 two groups in (b), 4 eight in (c)) */
 } mrsdc_config;
 
 enum {
@@ -159,6 +169,11 @@ typedef struct {
   int32_t col_bytes;       /* bytes per stored column: 2 (offset) or 4 (int32) */
   int32_t graph_captures;  /* steps captured into a HIP graph in this call (use_graph) */
   int32_t graph_launches;  /* graph launches (steps replayed) in this call */
+  int32_t col_depth;       /* batched: stages in flight of the column-sweep CG
+                              product (0: the tiled product runs) */
+  int32_t groups_b;        /* batched: row groups in flight of the CG updates */
+  int32_t groups_c;
+  int32_t autotuned;       /* 1 if the launch variants were chosen by timing */
 } mrsdc_stats;
 
 /* Fill *cfg with defaults: FP64, Lobatto M=3, P=2, K=2, dt=1, pcg_rtol 1e-13. */

@@ -37,7 +37,7 @@ class Config(C.Structure):
                 ("refine_maxit", C.c_int), ("inner_rtol", C.c_double),
                 ("final_residual", C.c_int), ("use_graph", C.c_int), ("sweep_tol", C.c_double),
                 ("method", C.c_int), ("stream", C.c_void_p), ("op_form", C.c_int),
-                ("alloc", C.c_void_p)]
+                ("alloc", C.c_void_p), ("autotune", C.c_int)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -74,7 +74,9 @@ class Stats(C.Structure):
                 ("redone_steps", C.c_int32), ("residual", C.c_double * 17),
                 ("wall_s", C.c_double), ("bytes_moved", C.c_int64), ("sweeps", C.c_int64),
                 ("op_form", C.c_int32), ("col_bytes", C.c_int32),
-                ("graph_captures", C.c_int32), ("graph_launches", C.c_int32)]
+                ("graph_captures", C.c_int32), ("graph_launches", C.c_int32),
+                ("col_depth", C.c_int32), ("groups_b", C.c_int32), ("groups_c", C.c_int32),
+                ("autotuned", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "residual"}

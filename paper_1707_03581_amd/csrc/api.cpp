@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cstdarg>
 #include <cmath>
@@ -22,6 +23,7 @@
 #include <cstring>
 #include <string>
 #include <map>
+#include <mutex>
 #include <queue>
 #include <unordered_map>
 #include <vector>
@@ -101,6 +103,8 @@ struct mrsdc_ctx {
   std::vector<int> graph_key;
   bool graph_off = false;
   int64_t graph_captures = 0, graph_replays = 0;
+  int graph_warm = 0;  // steps run directly (to learn the budgets) before the first capture
+  bool tuned = false;  // autotune: launch variants chosen for this device state
   int op_form_used = 0;       // MRSDC_OP_* the CG product reads (single contexts)
   int col_bytes = 0;          // 2: 16-bit column offsets, 4: int32 columns
   // event timing of kernel classes
@@ -224,6 +228,8 @@ void free_device(mrsdc_ctx *c) {
   if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
   c->graph_exec = nullptr;
   c->graph_key.clear();
+  c->graph_warm = 0;
+  c->tuned = false;
   for (void *p : c->allocs) dev_free(c, p);
   c->allocs.clear();
   c->footprint = 0;
@@ -643,6 +649,7 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
   a.sweep_tol = c->cfg.sweep_tol;
   // blocks of 4 rows, a multiple of the 8 XCDs
   a.grid = (int)std::min<int64_t>(((N + 3) / 4 + 7) / 8 * 8, kBatchMaxGrid);
+  set_resident_grids(a);
   for (int m = 0; m <= c->cfg.M; ++m) a.dtau_h[m] = c->w.dtau[m];
   double *pv;
   a.op.N = N;
@@ -1255,17 +1262,18 @@ int enqueue_cg(mrsdc_ctx *c, int slot, int m, bool fp32, bool defer = false) {
 // One implicit node solve of interval m (x = T[m] in place).  defer: an FP64
 // solve leaves its final check to the caller and returns its launch budget
 // (-1 when nothing is left to check).
-// Learned launch budgets.  Without graphs a slot's budget follows its recent
-// iteration counts both ways; with a captured step it only grows, so the
-// captured launch sequence stays valid (a converged solve's spare launches
-// return at once) and the step is re-captured only when a budget grows.
+// Learned launch budgets.  A slot's budget follows its recent iteration
+// counts both ways until a step is captured; from then on it only grows, so
+// the captured launch sequence stays valid (a converged solve's spare
+// launches return at once) and the step is re-captured only when a budget
+// grows.
 void learn_budget(mrsdc_ctx *c, int i, int v) {
   v = std::min(c->cfg.pcg_maxit, v);
-  c->budget[i] = c->cfg.use_graph ? std::max(c->budget[i], v) : v;
+  c->budget[i] = c->graph_exec ? std::max(c->budget[i], v) : v;
 }
 void learn_rounds(mrsdc_ctx *c, int i, int v) {
   v = std::min(c->cfg.refine_maxit, v);
-  c->rounds[i] = c->cfg.use_graph ? std::max(c->rounds[i], v) : v;
+  c->rounds[i] = c->graph_exec ? std::max(c->rounds[i], v) : v;
 }
 
 int enqueue_solve(mrsdc_ctx *c, int k, int m, bool defer = false) {
@@ -1433,12 +1441,92 @@ void enqueue_batch_step(mrsdc_ctx *c) {
   blaunch_commit(a, c->cfg.dt, st);
 }
 
+// Autotuner (batched FP32 contexts): time the launch variants of the CG
+// kernels on this mesh and keep the fastest: the column sweep's stages in
+// flight, and the row groups in flight of the two CG updates.  Every variant
+// forms the same sums in the same order (the grids, and so the partial sums,
+// stay fixed), so the choice changes time only.  Runs before the first step
+// (the updates then overwrite only inner CG vectors that every solve
+// re-initialises); the choice is kept per process for the mesh and scenario
+// count.
+mrsdc_status autotune_batch(mrsdc_ctx *c) {
+  c->tuned = true;
+  BatchArgs &a = c->ba;
+  if (c->cfg.precision != MRSDC_FP32_REFINE) return MRSDC_OK;
+  if (c->cfg.autotune >= 2) {  // a fixed variant: bits of autotune - 2
+    const int v = c->cfg.autotune - 2;
+    a.col_depth = (v & 1) ? 1 : kColDepth;
+    a.groups_b = (v & 2) ? 2 : 4;
+    a.groups_c = (v & 4) ? 8 : 4;
+    return MRSDC_OK;
+  }
+  static std::mutex mu;
+  static std::map<std::vector<int64_t>, std::array<int, 3>> cache;
+  const std::vector<int64_t> key = {c->cfg.device, a.N, a.S, c->batch_entries, a.op.ncol_items};
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto f = cache.find(key);
+    if (f != cache.end()) {
+      a.col_depth = f->second[0];
+      a.groups_b = f->second[1];
+      a.groups_c = f->second[2];
+      return MRSDC_OK;
+    }
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  auto time_it = [&](int which, float *us) -> hipError_t {
+    constexpr int kReps = 8;
+    blaunch_tune(a, which, 2, c->stream);  // warm
+    hipError_t e = hipEventRecord(e0, c->stream);
+    if (e == hipSuccess) {
+      blaunch_tune(a, which, kReps, c->stream);
+      e = hipEventRecord(e1, c->stream);
+    }
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    *us = 1e3f * ms / kReps;
+    return e;
+  };
+  struct Cand {
+    int *knob;
+    int which;
+    std::vector<int> values;
+  };
+  std::vector<Cand> cands = {{&a.groups_b, 1, {4, 2}}, {&a.groups_c, 2, {4, 8}}};
+  if (a.op.ncol_items > 0) cands.insert(cands.begin(), Cand{&a.col_depth, 0, {kColDepth, 1}});
+  hipError_t e = hipSuccess;
+  for (const Cand &k : cands) {
+    int best = k.values[0];
+    float tbest = 0.f;
+    for (size_t i = 0; i < k.values.size() && e == hipSuccess; ++i) {
+      *k.knob = k.values[i];
+      float us = 0.f;
+      e = time_it(k.which, &us);
+      if (i == 0 || us < tbest) tbest = us, best = k.values[i];
+    }
+    *k.knob = best;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(c, MRSDC_EDEVICE, "autotune: %s", hipGetErrorString(e));
+  std::lock_guard<std::mutex> g(mu);
+  cache[key] = {a.col_depth, a.groups_b, a.groups_c};
+  return MRSDC_OK;
+}
+
 // One time step on the context's stream: its launches directly, or (use_graph)
 // the step captured once into a HIP graph and replayed while the launch
-// budgets stay as they were at capture.  A stream that cannot be captured
-// (the legacy default stream) turns graphs off for the context.
+// budgets stay as they were at capture.  The first kGraphWarmSteps steps run
+// directly, so the capture holds budgets learned from iteration counts rather
+// than the initial ones.  A stream that cannot be captured (the legacy
+// default stream) turns graphs off for the context.
+constexpr int kGraphWarmSteps = 3;
 hipError_t run_step(mrsdc_ctx *c, void (*enqueue)(mrsdc_ctx *)) {
-  if (!c->cfg.use_graph || c->graph_off || c->prof) {
+  if (!c->cfg.use_graph || c->graph_off || c->prof || c->graph_warm < kGraphWarmSteps) {
+    if (c->cfg.use_graph) c->graph_warm++;
     enqueue(c);
     return hipGetLastError();
   }
@@ -2114,6 +2202,7 @@ mrsdc_status mrsdc_batch_advance(mrsdc_ctx *c, int nsteps, mrsdc_stats *stats) {
       return fail(c, MRSDC_ESTATE, "temperature of scenario %d not set", s);
   if ((st = prepare(c))) return st;
   if ((st = batch_upload_pending(c))) return st;
+  if (c->cfg.autotune && !c->tuned && (st = autotune_batch(c))) return st;
   auto t0 = std::chrono::steady_clock::now();
   mrsdc_stats acc;
   std::memset(&acc, 0, sizeof acc);
@@ -2216,6 +2305,10 @@ mrsdc_status mrsdc_batch_advance(mrsdc_ctx *c, int nsteps, mrsdc_stats *stats) {
   acc.wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   acc.graph_captures = (int32_t)(c->graph_captures - cap0);
   acc.graph_launches = (int32_t)(c->graph_replays - rep0);
+  acc.col_depth = c->ba.op.ncol_items > 0 ? c->ba.col_depth : 0;
+  acc.groups_b = c->ba.groups_b;
+  acc.groups_c = c->ba.groups_c;
+  acc.autotuned = c->tuned ? 1 : 0;
   if (stats) *stats = acc;
   return MRSDC_OK;
 }
@@ -2292,6 +2385,10 @@ mrsdc_status mrsdc_batch_advance_horizons(mrsdc_ctx *c, const double *horizon, m
     acc.sweeps += one.sweeps;
     acc.graph_captures += one.graph_captures;
     acc.graph_launches += one.graph_launches;
+    acc.col_depth = one.col_depth;
+    acc.groups_b = one.groups_b;
+    acc.groups_c = one.groups_c;
+    acc.autotuned = one.autotuned;
     for (int r = 0; r < 17; ++r) acc.residual[r] = one.residual[r];
   }
   for (int s = 0; s < S; ++s)  // every scenario active again as it was

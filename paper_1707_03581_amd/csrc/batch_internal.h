@@ -96,6 +96,11 @@ struct BatchArgs {
   int S = 0, M = 0, P = 0, grid = 0;
   int sgrid64 = 0, sgrid32 = 0;  // workgroups of the tiled kernels (FP64 / FP32 staging)
   int cgrid64 = 0, cgrid32 = 0;  // workgroups of the column-sweep kernels (0: tiles)
+  int bgrid64 = 0, bgrid32 = 0;  // workgroups of the CG update (b): all resident
+  // launch variants (every one gives the same results): stages in flight of
+  // the column sweep (1 or kColDepth), row groups in flight of the CG
+  // updates (b: 2 or 4, c: 4 or 8)
+  int col_depth = kColDepth, groups_b = 4, groups_c = 4;
   int64_t N = 0;
   double dtau_h[kMaxM + 1] = {};
   BatchOp op;
@@ -131,10 +136,16 @@ void blaunch_quad_resid(const BatchArgs &a, int k, hipStream_t st);
 void blaunch_solve(const BatchArgs &a, const BSolve &sv, hipStream_t st);
 void blaunch_iface(const BatchArgs &a, int m, bool corr, hipStream_t st);
 void blaunch_operator_timing(const BatchArgs &a, int m, int reps, hipStream_t st);
+// FP32 form, for the autotuner: reps launches of the column-sweep or tiled
+// operator (which 0, timing variant), the update (b) (1) or the update (c)
+// (2) with the launch variants in a; b and c overwrite only inner CG vectors
+void blaunch_tune(const BatchArgs &a, int which, int reps, hipStream_t st);
 void blaunch_commit(const BatchArgs &a, double dt, hipStream_t st);
 void blaunch_scatter(double *dst, const double *src, int64_t n, int S, int s, hipStream_t st);
 void blaunch_gather(double *dst, const double *src, int64_t n, int S, int s, hipStream_t st);
 // workgroups of the column-sweep operator resident per CU (set by its LDS ring)
 int col_workgroups_per_cu();
+// bgrid64 / bgrid32 from the occupancy of the update kernels (device current)
+void set_resident_grids(BatchArgs &a);
 
 }  // namespace mrsdc

@@ -695,8 +695,28 @@ __global__ __launch_bounds__(64 * kRedWaves) void kb_resid_reduce(BatchArgs a, i
 // implicit node solve per scenario: Jacobi-PCG, 3 kernels per iteration plus
 // one-block scalar reductions
 // ---------------------------------------------------------------------------
+// Jacobi preconditioner 1 / diag(M + dtau (K + h R)) of a row, one rounding
+// pattern in every kernel; where the row has no R part the value does not
+// depend on h (fma(h, 0, kd) = kd), so a lane computes it once for its
+// scenarios
+__device__ __forceinline__ double dinv_of(double ms, double kd, double rd, double h,
+                                          double dtau) {
+  return 1.0 / __builtin_fma(dtau, __builtin_fma(h, rd, kd), ms);
+}
+template <typename V, int VEC>
+__device__ __forceinline__ void dinv_row(double ms, double kd, double rd, const double (&h)[VEC],
+                                         double dtau, V (&d)[VEC]) {
+  if (rd == 0.0) {
+    const V d0 = (V)dinv_of(ms, kd, 0.0, 0.0, dtau);
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) d[k] = d0;
+  } else {
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) d[k] = (V)dinv_of(ms, kd, rd, h[k], dtau);
+  }
+}
 __device__ inline double bdinv(const BatchArgs &a, int64_t row, double h, double dtau) {
-  return 1.0 / (a.mass[row] + dtau * (a.Kd[row] + h * a.Rd[row]));
+  return dinv_of(a.mass[row], a.Kd[row], a.Rd[row], h, dtau);
 }
 
 // Solve initialisation of one row.  Predictor: x0 = T_{m-1}, b = M T_{m-1} +
@@ -1136,7 +1156,7 @@ __device__ inline GroupRange xcd_groups(int64_t G) {
   r.stride = (int64_t)per * (kBlock / 64);
   return r;
 }
-constexpr int kGroupsAhead = 4;  // row groups of a lane in flight
+constexpr int kGroupsAhead = 4;  // row groups of a lane in flight (default)
 
 // VEC values of scenarios s0.. of element base (AL: one 16-byte access; else
 // element by element, lanes past S untouched)
@@ -1170,8 +1190,9 @@ __device__ __forceinline__ void vstore(V *p, int64_t base, int s0, int S, const 
   }
 }
 
-// (b) x += alpha p; r -= alpha q; partial r.z, r.r
-template <typename V, bool AL>
+// (b) x += alpha p; r -= alpha q; partial r.z, r.r; GA row groups of a lane
+// in flight (any GA gives the same results)
+template <typename V, bool AL, int GA>
 __global__ __launch_bounds__(kBlock) void kb_pcg_b(BatchArgs a, int m, double dtau) {
   using LY = Lanes<V>;
   constexpr int VEC = LY::VEC, RPW = LY::RPW;
@@ -1193,13 +1214,13 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_b(BatchArgs a, int m, double dt
   const V *p = BV<V>::p(a), *q = BV<V>::q(a);
   const int64_t N = a.N, G = (N + RPW - 1) / RPW;
   if (__ballot(any) != 0ull) {  // some lane of the wave has work
-    for (GroupRange gr = xcd_groups(G); gr.g < gr.end; gr.g += kGroupsAhead * gr.stride) {
-      V xs[kGroupsAhead][VEC], ps[kGroupsAhead][VEC], qs[kGroupsAhead][VEC],
-          rs[kGroupsAhead][VEC];
-      double ms[kGroupsAhead], kd[kGroupsAhead], rd[kGroupsAhead];
-      bool ok[kGroupsAhead];
+    for (GroupRange gr = xcd_groups(G); gr.g < gr.end; gr.g += GA * gr.stride) {
+      V xs[GA][VEC], ps[GA][VEC], qs[GA][VEC],
+          rs[GA][VEC];
+      double ms[GA], kd[GA], rd[GA];
+      bool ok[GA];
 #pragma unroll
-      for (int u = 0; u < kGroupsAhead; ++u) {
+      for (int u = 0; u < GA; ++u) {
         const int64_t g = gr.g + u * gr.stride, row = g * RPW + lr;
         ok[u] = (g < gr.end) & (row < N) & (s0 < S);
         const int64_t rw = ok[u] ? row : 0, base = rw * S + (s0 < S ? s0 : 0);
@@ -1212,17 +1233,18 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_b(BatchArgs a, int m, double dt
         rd[u] = a.Rd[rw];
       }
 #pragma unroll
-      for (int u = 0; u < kGroupsAhead; ++u) {
+      for (int u = 0; u < GA; ++u) {
         if (!ok[u]) continue;
         const int64_t row = (gr.g + u * gr.stride) * RPW + lr, base = row * S + s0;
+        V di[VEC];
+        dinv_row<V, VEC>(ms[u], kd[u], rd[u], h, dtau, di);
 #pragma unroll
         for (int k = 0; k < VEC; ++k) {
           if (!on[k]) continue;  // idle scenarios keep their values
           xs[u][k] = xs[u][k] + alpha[k] * ps[u][k];
           const V r = rs[u][k] - alpha[k] * qs[u][k];
           rs[u][k] = r;
-          // the diagonal inverse of bdinv, from the loaded row data
-          const V z = (V)(1.0 / (ms[u] + dtau * (kd[u] + h[k] * rd[u]))) * r;
+          const V z = di[k] * r;
           v[0][k] += (double)r * (double)z;
           v[1][k] += (double)r * (double)r;
         }
@@ -1243,8 +1265,8 @@ __device__ __forceinline__ double pupdate(double di, double r, double beta, doub
   return __builtin_fma(di, r, beta * p);
 }
 
-// (c) p = z + beta p, row groups as in (b)
-template <typename V, bool AL>
+// (c) p = z + beta p, row groups as in (b), GA of a lane in flight
+template <typename V, bool AL, int GA>
 __global__ __launch_bounds__(kBlock) void kb_pcg_c(BatchArgs a, double dtau) {
   using LY = Lanes<V>;
   constexpr int VEC = LY::VEC, RPW = LY::RPW;
@@ -1265,12 +1287,12 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_c(BatchArgs a, double dtau) {
   V *p = BV<V>::p(a);
   const V *rv = BV<V>::r(a);
   const int64_t N = a.N, G = (N + RPW - 1) / RPW;
-  for (GroupRange gr = xcd_groups(G); gr.g < gr.end; gr.g += kGroupsAhead * gr.stride) {
-    V ps[kGroupsAhead][VEC], rs[kGroupsAhead][VEC];
-    double ms[kGroupsAhead], kd[kGroupsAhead], rd[kGroupsAhead];
-    bool ok[kGroupsAhead];
+  for (GroupRange gr = xcd_groups(G); gr.g < gr.end; gr.g += GA * gr.stride) {
+    V ps[GA][VEC], rs[GA][VEC];
+    double ms[GA], kd[GA], rd[GA];
+    bool ok[GA];
 #pragma unroll
-    for (int u = 0; u < kGroupsAhead; ++u) {
+    for (int u = 0; u < GA; ++u) {
       const int64_t g = gr.g + u * gr.stride, row = g * RPW + lr;
       ok[u] = (g < gr.end) & (row < N) & (s0 < S);
       const int64_t rw = ok[u] ? row : 0, base = rw * S + (s0 < S ? s0 : 0);
@@ -1281,14 +1303,14 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_c(BatchArgs a, double dtau) {
       rd[u] = a.Rd[rw];
     }
 #pragma unroll
-    for (int u = 0; u < kGroupsAhead; ++u) {
+    for (int u = 0; u < GA; ++u) {
       if (!ok[u]) continue;
       const int64_t row = (gr.g + u * gr.stride) * RPW + lr, base = row * S + s0;
+      V di[VEC];
+      dinv_row<V, VEC>(ms[u], kd[u], rd[u], h, dtau, di);
 #pragma unroll
       for (int k = 0; k < VEC; ++k)
-        if (on[k])  // the diagonal inverse of bdinv, from the loaded row data
-          ps[u][k] = pupdate((V)(1.0 / (ms[u] + dtau * (kd[u] + h[k] * rd[u]))), rs[u][k],
-                             beta[k], ps[u][k]);
+        if (on[k]) ps[u][k] = pupdate(di[k], rs[u][k], beta[k], ps[u][k]);
       vstore<V, VEC, AL>(p, base, s0, S, ps[u]);
     }
   }
@@ -1632,19 +1654,25 @@ static int pcg_a_grid(const BatchArgs &a) {
   return use_columns<V>(a) ? a.cgrid32 : tgrid<V>(a);
 }
 
+// the column sweep with D stages in flight (any D gives the same results)
+template <int D>
+static void launch_col(const BatchArgs &a, int timing, int g, int m, double dtau, hipStream_t st) {
+  if (vec16<float>(a)) {
+    if (timing) kb_pcg_a_col<1, 16, D><<<g, kBlock, 0, st>>>(a, m, dtau);
+    else kb_pcg_a_col<0, 16, D><<<g, kBlock, 0, st>>>(a, m, dtau);
+  } else {
+    if (timing) kb_pcg_a_col<1, 4, D><<<g, kBlock, 0, st>>>(a, m, dtau);
+    else kb_pcg_a_col<0, 4, D><<<g, kBlock, 0, st>>>(a, m, dtau);
+  }
+}
+
 template <typename V>
 static void launch_pcg_a(const BatchArgs &a, int timing, int m, double dtau, hipStream_t st) {
   if constexpr (sizeof(V) == 4) {
     if (use_columns<V>(a)) {
       const int g = pcg_a_grid<V>(a);
-      constexpr int D = kColDepth;
-      if (vec16<V>(a)) {
-        if (timing) kb_pcg_a_col<1, 16, D><<<g, kBlock, 0, st>>>(a, m, dtau);
-        else kb_pcg_a_col<0, 16, D><<<g, kBlock, 0, st>>>(a, m, dtau);
-      } else {
-        if (timing) kb_pcg_a_col<1, 4, D><<<g, kBlock, 0, st>>>(a, m, dtau);
-        else kb_pcg_a_col<0, 4, D><<<g, kBlock, 0, st>>>(a, m, dtau);
-      }
+      if (a.col_depth == 1) launch_col<1>(a, timing, g, m, dtau, st);
+      else launch_col<kColDepth>(a, timing, g, m, dtau, st);
       return;
     }
   }
@@ -1658,18 +1686,65 @@ static void launch_pcg_a(const BatchArgs &a, int timing, int m, double dtau, hip
   }
 }
 
+// Workgroups of a grid-stride launch of fn: at most want, every one resident
+// at once (a launch larger than what fits runs a second, partial round), a
+// multiple of the 8 XCDs
+static int resident_grid(const void *fn, int want) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kBlock, 0) != hipSuccess)
+    return want;
+  const int fit = per * cus / kXcd * kXcd;
+  return fit >= kXcd ? std::min(want, fit) : want;
+}
+
+void set_resident_grids(BatchArgs &a) {
+  // from the default variant, whatever the tuner picks later: the grid sets
+  // the partial sums, so it stays fixed
+  a.bgrid32 = std::min(resident_grid((const void *)kb_pcg_b<float, true, kGroupsAhead>, a.grid),
+                       resident_grid((const void *)kb_pcg_b<float, false, kGroupsAhead>, a.grid));
+  a.bgrid64 = std::min(resident_grid((const void *)kb_pcg_b<double, true, kGroupsAhead>, a.grid),
+                       resident_grid((const void *)kb_pcg_b<double, false, kGroupsAhead>, a.grid));
+}
+
+template <typename V>
+static int pcg_b_grid(const BatchArgs &a) {
+  return std::is_same<V, float>::value ? a.bgrid32 : a.bgrid64;
+}
+
+template <typename V, int GA>
+static void launch_pcg_b_ga(const BatchArgs &a, int m, double dtau, hipStream_t st) {
+  if (vec16<V>(a)) kb_pcg_b<V, true, GA><<<pcg_b_grid<V>(a), kBlock, 0, st>>>(a, m, dtau);
+  else kb_pcg_b<V, false, GA><<<pcg_b_grid<V>(a), kBlock, 0, st>>>(a, m, dtau);
+}
+template <typename V>
+static void launch_pcg_b(const BatchArgs &a, int m, double dtau, hipStream_t st) {
+  if (a.groups_b == 2) launch_pcg_b_ga<V, 2>(a, m, dtau, st);
+  else launch_pcg_b_ga<V, kGroupsAhead>(a, m, dtau, st);
+}
+template <typename V, int GA>
+static void launch_pcg_c_ga(const BatchArgs &a, double dtau, hipStream_t st) {
+  if (vec16<V>(a)) kb_pcg_c<V, true, GA><<<a.grid, kBlock, 0, st>>>(a, dtau);
+  else kb_pcg_c<V, false, GA><<<a.grid, kBlock, 0, st>>>(a, dtau);
+}
+template <typename V>
+static void launch_pcg_c(const BatchArgs &a, double dtau, hipStream_t st) {
+  if (a.groups_c == 8) launch_pcg_c_ga<V, 8>(a, dtau, st);
+  else launch_pcg_c_ga<V, kGroupsAhead>(a, dtau, st);
+}
+
 template <typename V>
 static void cg_iterations(const BatchArgs &a, int m, double dtau, int slot, int budget,
                           double rtol, hipStream_t st) {
   const int conv = std::is_same<V, float>::value ? 6 : 2;
+  const int gb = pcg_b_grid<V>(a);
   for (int it = 0; it < budget; ++it) {
     launch_pcg_a<V>(a, 0, m, dtau, st);
     RED(pcg_a_grid<V>(a), 1, it, 0, slot, rtol);
-    if (vec16<V>(a)) kb_pcg_b<V, true><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
-    else kb_pcg_b<V, false><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
-    RED(a.grid, conv, it, it == budget - 1, slot, rtol);
-    if (vec16<V>(a)) kb_pcg_c<V, true><<<a.grid, kBlock, 0, st>>>(a, dtau);
-    else kb_pcg_c<V, false><<<a.grid, kBlock, 0, st>>>(a, dtau);
+    launch_pcg_b<V>(a, m, dtau, st);
+    RED(gb, conv, it, it == budget - 1, slot, rtol);
+    launch_pcg_c<V>(a, dtau, st);
   }
 }
 
@@ -1706,6 +1781,17 @@ void blaunch_solve(const BatchArgs &a, const BSolve &sv, hipStream_t st) {
   }
 }
 #undef RED
+
+void blaunch_tune(const BatchArgs &a, int which, int reps, hipStream_t st) {
+  int m = 1;
+  while (m <= a.M && a.dtau_h[m] == 0.0) ++m;
+  const double dtau = a.dtau_h[m];
+  for (int i = 0; i < reps; ++i) {
+    if (which == 0) launch_pcg_a<float>(a, 1, m, dtau, st);
+    else if (which == 1) launch_pcg_b<float>(a, m, dtau, st);
+    else launch_pcg_c<float>(a, dtau, st);
+  }
+}
 
 void blaunch_operator_timing(const BatchArgs &a, int m, int reps, hipStream_t st) {
   for (int i = 0; i < reps; ++i) {

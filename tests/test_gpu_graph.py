@@ -1,8 +1,9 @@
 """The time step captured into a HIP graph and replayed (use_graph) against
 the same step launched directly, through the C-ABI.
 
-Each test advances a captured and a direct context side by side one step at
-a time, with the program's own host work and synchronisations between the
+A context with use_graph runs its first WARM steps directly (they learn the
+CG launch budgets) and captures the step after them.  Each test advances a
+captured and a direct context side by side one step at a time, with the program's own host work and synchronisations between the
 replays, and compares every step: FP64 bit for bit (a converged solve's
 spare launches change nothing), FP32 + refinement within the refinement's
 tolerance; both against the oracle as well.
@@ -16,6 +17,7 @@ import mrsdc_inputs as mi
 import oracle
 
 pytestmark = pytest.mark.gpu
+WARM = 3  # steps a use_graph context runs directly before its first capture
 
 
 @pytest.fixture(autouse=True)
@@ -61,21 +63,22 @@ def test_single_captured_step_matches_direct(precision):
     g.destroy()
     d.destroy()
     print(f"  captures {captures}, graph launches {launches}", flush=True)
-    assert launches == pb.nsteps and 1 <= captures < pb.nsteps
+    assert launches == pb.nsteps - WARM and 1 <= captures <= launches
     ref, _ = oracle.run(pb, nsteps=pb.nsteps)
     assert rel(Tg, ref) <= (1e-10 if precision == mi.FP64 else 1e-7)
 
 
 def test_single_machine_310k_captured():
-    """The 310,042-DOF machine, 3 steps captured, bit for bit the direct run."""
+    """The 310,042-DOF machine, 3 steps captured after the direct ones, bit for
+    bit the direct run."""
     m = pkg()
-    pb = mi.machine_310k(nsteps=3)
+    pb = mi.machine_310k(nsteps=WARM + 3)
     g = m.simulation(pb, use_graph=1)
     d = m.simulation(pb)
-    for n in range(3):
+    for n in range(WARM + 3):
         st = g.advance(pb.scheme.dt)
         d.advance(pb.scheme.dt)
-        assert st["graph_launches"] == 1
+        assert st["graph_launches"] == (1 if n >= WARM else 0)
         assert np.array_equal(m.get_state(g, pb), m.get_state(d, pb)), f"step {n}"
     g.destroy()
     d.destroy()
@@ -112,4 +115,4 @@ def test_batch_captured_step_matches_direct(precision):
         assert rel(Tg, Td) <= (0.0 if precision == mi.FP64 else 1e-9)
     g.destroy()
     d.destroy()
-    assert launches == pb.nsteps
+    assert launches == pb.nsteps - WARM
