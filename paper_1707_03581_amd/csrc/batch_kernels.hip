@@ -424,10 +424,12 @@ struct ColLds {
   uint4 x[NX][kColPlaneUnits];
   uint4 rec[NR][kColRecSlot];
 };
-// workgroups per CU that the ring leaves room for (160 KB of LDS)
-template <int D>
+// workgroups per CU that the ring leaves room for (160 KB of LDS); four only
+// with 16-byte copies (the 4-byte form needs more than 128 registers)
+template <int D, int UB = 16>
 struct ColOcc {
-  static constexpr int W = 3 * sizeof(ColLds<D>) + 768 <= 160 * 1024   ? 3
+  static constexpr int W = UB == 16 && 4 * sizeof(ColLds<D>) + 1024 <= 160 * 1024 ? 4
+                           : 3 * sizeof(ColLds<D>) + 768 <= 160 * 1024 ? 3
                            : 2 * sizeof(ColLds<D>) + 512 <= 160 * 1024 ? 2
                                                                         : 1;
 };
@@ -445,61 +447,105 @@ __device__ inline ColItem col_item(const BatchOp &op, int t) {
   return ColItem{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], v[9],
                  (unsigned)v[10], (unsigned)v[11]};
 }
-template <int N>
-__device__ inline int col_slot(int p) { return (p + 4 * N) % N; }  // p >= -2
 
-// Issue wave w's copies of stage s >= z0 - 2: plane P = s + 1 (staged as
-// zeros outside the body and past the run's top neighbour z1) and the
-// record of plane s + 2 (the run's first record past the run).  Every lane
-// copies from a valid address: halo rows outside the body and the values
-// past S of a row come from 64 zeros; the records' tail repeats the first K
-// unit.
+// Wave w's copies of the stages of one item: copy j = w + 4 i of a stage
+// moves LDS units [64 j', 64 j' + 64) of the staged plane (j' = j < X) or
+// of the record slot (j' = j - X).  What a lane copies depends on the stage
+// only through the plane and record indices, so the per-lane parts (halo row
+// offset, inside flag, record unit) are formed once per item; issuing a
+// stage then costs a few instructions per copy.  Every lane copies from a
+// valid address: halo rows outside the body and the values past S of a row
+// come from 64 zeros; the records' tail repeats the first K unit.
 template <int UB, int D>
-__device__ __forceinline__ void col_issue(const BatchOp &op, const ColItem &it, int s,
-                                          const float *__restrict__ x, int S, ColLds<D> &L,
-                                          int w) {
+struct ColIssue {
   using CC = ColCopies<UB>;
-  constexpr int UPH = 64 * 4 / UB;  // units per staged row (64 values)
-  const int lane = threadIdx.x & 63, upr = S * 4 / UB, P = s + 1, R = s + 2;
-  const bool pin = (P >= 0) & (P < it.nz) & (P <= it.z1);
-  const int pr = ((R >= it.z0) & (R < it.z1)) ? R - it.z0 : 0;
-  const unsigned long long mask = ((unsigned long long)it.mhi << 32) | it.mlo;
-  const bool hasr = (mask >> pr) & 1ull;
-  const int kr = it.kb + pr, rr = it.rb + __builtin_popcountll(mask & ((1ull << pr) - 1ull));
-  const char *xb = reinterpret_cast<const char *>(x);
-  const char *zb = reinterpret_cast<const char *>(op.col_zero);
-  const char *kb = reinterpret_cast<const char *>(op.kcol32) + (size_t)kr * kColRecUnits * 16;
-  const char *rb = reinterpret_cast<const char *>(op.rcol32) + (size_t)rr * kColRecUnits * 16;
-  auto *lx = reinterpret_cast<char *>(L.x[col_slot<ColLds<D>::NX>(s)]);
-  uint4 *lr = L.rec[col_slot<ColLds<D>::NR>(R)];
+  static constexpr int UPH = 64 * 4 / UB;  // units per staged row (64 values)
+  static constexpr unsigned XB = kColPlaneUnits * 16, RB = kColRecSlot * 16;  // slot bytes
+  unsigned xoff[CC::C0];  // plane-0 byte offset of the lane's unit (x copies)
+  unsigned zoff[CC::C0];  // its offset in the row of zeros
+  bool xin[CC::C0];       // halo row inside the body, unit inside the row
+  unsigned roff;          // record copy: byte offset of the lane's unit in a record
+  int rpart;              // 0: K unit, 1: R unit, 2: tail
+  unsigned pstride;       // bytes between planes of x
+  int w;
+  // the next stage (wave-uniform): its plane P and record plane R = P + 1,
+  // the byte offsets of its slots, P's offset in x, and R's record indices
+  int P, R, kr, rr;
+  unsigned xso, rso, pbase;
+  unsigned long long rbits;  // R plane bits of the records not issued yet
+
+  // ring slots: stage z0 - 2 + i in plane slot i mod NX, record plane z0 + i
+  // in record slot i mod NR
+  __device__ __forceinline__ void init(const ColItem &it, int S, int wave) {
+    w = wave;
+    const int lane = threadIdx.x & 63, upr = S * 4 / UB;
+    pstride = (unsigned)it.nx * (unsigned)it.ny * (unsigned)upr * (unsigned)UB;
 #pragma unroll
-  for (int i = 0; i < CC::C0; ++i) {
-    const int j = w + 4 * i;  // wave-uniform
-    if (j >= CC::N) break;
-    if (j < CC::X) {
-      const int u = j * 64 + lane, hs = u / UPH, part = u % UPH;
+    for (int i = 0; i < CC::C0; ++i) {
+      const int j = w + 4 * i;
+      const int u = (j < CC::X ? j : 0) * 64 + lane, hs = u / UPH, part = u % UPH;
       const int hx = hs % (kColFX + 2), hy = hs / (kColFX + 2);
       const int gx = it.x0 - 1 + hx, gy = it.y0 - 1 + hy;
-      const bool in = pin & ((unsigned)gx < (unsigned)it.nx) & ((unsigned)gy < (unsigned)it.ny) &
-                      (part < upr);
+      xin[i] = ((unsigned)gx < (unsigned)it.nx) & ((unsigned)gy < (unsigned)it.ny) & (part < upr);
       // (32-bit offsets: the column sweep runs only on vectors below 2 GB)
-      const unsigned row = (unsigned)(it.off + gx + it.nx * (gy + it.ny * P));
-      const char *src = in ? xb + (row * (unsigned)upr + (unsigned)part) * (unsigned)UB
-                           : zb + part * UB;
-      auto *dst = (__attribute__((address_space(3))) void *)(lx + j * 64 * UB);
-      if constexpr (UB == 16) __builtin_amdgcn_global_load_lds((const void *)src, dst, 16, 0, 0);
-      else __builtin_amdgcn_global_load_lds((const void *)src, dst, 4, 0, 0);
-    } else {
-      const int u = (j - CC::X) * 64 + lane;
-      const bool isr = hasr & (u >= kColRecUnits) & (u < 2 * kColRecUnits);
-      const int uk = u < kColRecUnits ? u : (u < 2 * kColRecUnits ? u - kColRecUnits : 0);
-      const char *src = (isr ? rb : kb) + uk * 16;
-      __builtin_amdgcn_global_load_lds(
-          (const void *)src, (__attribute__((address_space(3))) void *)&lr[(j - CC::X) * 64], 16,
-          0, 0);
+      const unsigned row = xin[i] ? (unsigned)(it.off + gx + it.nx * gy) : 0u;
+      xoff[i] = (row * (unsigned)upr + (unsigned)part) * (unsigned)UB;
+      zoff[i] = (unsigned)(part * UB);
     }
+    const int jr = w + 4 * ((CC::X - w + 3) / 4);  // this wave's record copy
+    const int u = (jr - CC::X) * 64 + lane;
+    rpart = u < kColRecUnits ? 0 : (u < 2 * kColRecUnits ? 1 : 2);
+    roff = (unsigned)((rpart == 0 ? u : (rpart == 1 ? u - kColRecUnits : 0)) * 16);
+    P = it.z0 - 1;
+    R = it.z0;
+    kr = it.kb;
+    rr = it.rb;
+    rbits = ((unsigned long long)it.mhi << 32) | it.mlo;
+    xso = rso = 0;
+    pbase = (unsigned)P * pstride;
   }
-}
+
+  // Issue the next stage: plane P (zeros outside the body and past the
+  // run's top neighbour z1) and the record of plane R (the run's first record
+  // past the run), then step to the stage after it.
+  __device__ __forceinline__ void issue(const BatchOp &op, const ColItem &it,
+                                        const float *__restrict__ x, ColLds<D> &L) {
+    const bool pin = (P >= 0) & (P < it.nz) & (P <= it.z1);
+    const bool inrun = R < it.z1;
+    const bool hasr = inrun & ((rbits & 1ull) != 0);
+    const char *xb = reinterpret_cast<const char *>(x);
+    const char *zb = reinterpret_cast<const char *>(op.col_zero);
+    char *lx = reinterpret_cast<char *>(&L.x[0][0]) + xso;
+#pragma unroll
+    for (int i = 0; i < CC::C0; ++i) {
+      const int j = w + 4 * i;  // wave-uniform
+      if (j >= CC::N) break;
+      if (j < CC::X) {
+        const char *src = (pin & xin[i]) ? xb + (xoff[i] + pbase) : zb + zoff[i];
+        auto *dst = (__attribute__((address_space(3))) void *)(lx + j * 64 * UB);
+        if constexpr (UB == 16) __builtin_amdgcn_global_load_lds((const void *)src, dst, 16, 0, 0);
+        else __builtin_amdgcn_global_load_lds((const void *)src, dst, 4, 0, 0);
+      } else {
+        const int k = inrun ? kr : it.kb, q = inrun ? rr : it.rb;
+        const char *kb = reinterpret_cast<const char *>(op.kcol32) + (size_t)k * kColRecUnits * 16;
+        const char *rb = reinterpret_cast<const char *>(op.rcol32) + (size_t)q * kColRecUnits * 16;
+        const char *src = (((rpart == 1) & hasr) ? rb : kb) + roff;
+        char *lr = reinterpret_cast<char *>(&L.rec[0][0]) + rso;
+        __builtin_amdgcn_global_load_lds(
+            (const void *)src, (__attribute__((address_space(3))) void *)(lr + (j - CC::X) * 1024),
+            16, 0, 0);
+      }
+    }
+    P += 1;
+    pbase += pstride;
+    xso = xso + XB == ColLds<D>::NX * XB ? 0u : xso + XB;
+    rr += hasr ? 1 : 0;
+    kr += 1;
+    rbits >>= 1;
+    R += 1;
+    rso = rso + RB == ColLds<D>::NR * RB ? 0u : rso + RB;
+  }
+};
 
 // s_waitcnt vmcnt(N) lgkmcnt(0) (gfx9 encoding: vmcnt in bits 3:0 and 15:14)
 template <int N>
@@ -1028,7 +1074,7 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_a(BatchArgs a, int m, double dt
 // at once (the values of idle scenarios too, which no later step reads);
 // otherwise each value apart, only where its scenario is on.
 template <int TIMING, int UB, int D>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ColOcc<D>::W)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ColOcc<D, UB>::W)))
 void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
   using CC = ColCopies<UB>;
   constexpr int ST = UB == 16 ? 1 : 4;  // stores per step
@@ -1064,22 +1110,32 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
     // only start rows z0 and z0 + 1 (what they add to rows below z0 is never
     // used).
     const int zb = it.z0 - 2;
-    for (int q = zb; q <= zb + D; ++q) col_issue<UB, D>(a.op, it, q, p, S, L, w);
+    ColIssue<UB, D> ci;
+    ci.init(it, S, w);
+    for (int q = 0; q <= D; ++q) ci.issue(a.op, it, p, L);  // stages z0 - 2 .. z0 - 2 + D
     if (w == 0) col_wait<D * CC::C0>();
     else col_wait<D * CC::C1>();
     col_barrier();
     // K and R sums of rows z, z + 1, z + 2 (a: z, b: z + 1, c: z + 2)
     float ka[4] = {}, kb4[4] = {}, ra[4] = {}, rb4[4] = {};
     float4 own = make_float4(0.f, 0.f, 0.f, 0.f);  // x of row z (plane z's centre)
+    // ring slots as ColIssue lays them out: plane z + 1 (stage z) in plane
+    // slot (z - zb) mod NX, the record of plane z in slot (z - z0) mod NR
+    constexpr unsigned XB = ColIssue<UB, D>::XB, RB = ColIssue<UB, D>::RB;
+    auto next_r = [&](unsigned o) { return o + RB == NR * RB ? 0u : o + RB; };
+    unsigned xro = 0, r0o = (NR - 2) * RB;  // step zb: plane slot 0, record z0 - 2
+    const char *lxb = reinterpret_cast<const char *>(&L.x[0][0]) + lb * 4;
+    const char *lrb = reinterpret_cast<const char *>(&L.rec[0][0]) + r * kStencil * 4;
     for (int z = zb; z < it.z1; ++z) {
-      const float *xs = reinterpret_cast<const float *>(L.x[col_slot<NX>(z)]) + lb;
+      const float *xs = reinterpret_cast<const float *>(lxb + xro);
       float4 xv[9];
 #pragma unroll
       for (int j = 0; j < 9; ++j)
         xv[j] = *reinterpret_cast<const float4 *>(xs + ((j / 3) * (kColFX + 2) + j % 3) * 64);
-      const float *c2 = reinterpret_cast<const float *>(L.rec[col_slot<NR>(z + 2)]) + r * kStencil;
-      const float *c1 = reinterpret_cast<const float *>(L.rec[col_slot<NR>(z + 1)]) + r * kStencil;
-      const float *c0 = reinterpret_cast<const float *>(L.rec[col_slot<NR>(z)]) + r * kStencil;
+      const unsigned r1o = next_r(r0o), r2o = next_r(r1o);
+      const float *c2 = reinterpret_cast<const float *>(lrb + r2o);
+      const float *c1 = reinterpret_cast<const float *>(lrb + r1o);
+      const float *c0 = reinterpret_cast<const float *>(lrb + r0o);
       constexpr int RO = kColRows * kStencil;  // the R record after the K record
       float kc[4] = {}, rc[4] = {};
       col_part(c2, xv, kc);       // row z + 2: dz = -1
@@ -1129,7 +1185,9 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
       if (w == 0) col_wait_plane<CC::C0, ST, D>(min(z - zb, D - 1));
       else col_wait_plane<CC::C1, ST, D>(min(z - zb, D - 1));
       col_barrier();  // stage z + 1 landed; plane z + 1 and the record of z free
-      col_issue<UB, D>(a.op, it, z + 1 + D, p, S, L, w);
+      ci.issue(a.op, it, p, L);  // stage z + 1 + D
+      xro = xro + XB == NX * XB ? 0u : xro + XB;
+      r0o = r1o;
     }
   }
   __syncthreads();  // every copy landed before the LDS is reused
