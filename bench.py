@@ -41,9 +41,9 @@ COUNTER_TRAFFIC = {
     },
     ("ensemble-64x714798", 1): {
         "source": "batch_kernels.hip",
-        "sha256": "d081761db2de9265f79ade6de8c8ab7d4589aa4149ddd513084e4994da97cc1e",
-        "fetch_kib": 241652.6, "fetch_scale": 1.99975,
-        "write_kib": 180285.7, "write_scale": 1.0,
+        "sha256": "cec936da33b18f4cc94becce53709fdc8d4a882e1af94762945fc7d6f92630da",
+        "fetch_kib": 163599.0, "fetch_scale": 1.99975,
+        "write_kib": 181721.0, "write_scale": 1.0,
     },
 }
 

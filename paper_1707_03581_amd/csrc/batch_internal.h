@@ -72,6 +72,7 @@ struct BatchScalars {
   double resid[17][kMaxS];
   int active[kMaxS];
   int done[kMaxS];
+  int done_it[kMaxS];             // iteration whose check found the solve converged (-1: none)
   int ref_done[kMaxS];
   int fail[kMaxS];
   int stop[kMaxS];                // residual control: no further sweeps this step

@@ -977,6 +977,7 @@ __global__ __launch_bounds__(kBlock) void kb_reduce(BatchArgs a, int np, int mod
     sc->rz[0][s] = o[0];
     sc->tol2[s] = rtol * rtol * o[2];
     sc->done[s] = (o[1] <= sc->tol2[s]) ? 1 : 0;
+    sc->done_it[s] = -1;
     if (sc->done[s]) sc->slot_iters[slot][s] = 0;
     return;
   }
@@ -984,6 +985,7 @@ __global__ __launch_bounds__(kBlock) void kb_reduce(BatchArgs a, int np, int mod
     sc->ref_tol2[s] = rtol * rtol * o[1];
     sc->ref_done[s] = (o[0] <= sc->ref_tol2[s]) ? 1 : 0;
     sc->done[s] = 0;
+    sc->done_it[s] = -1;
     if (sc->ref_done[s]) sc->slot_rounds[slot][s] = 0;
     return;
   }
@@ -992,6 +994,7 @@ __global__ __launch_bounds__(kBlock) void kb_reduce(BatchArgs a, int np, int mod
     sc->rz[0][s] = o[0];
     sc->tol2[s] = rtol * rtol * o[1];  // relative to the inner right-hand side
     sc->done[s] = (o[1] == 0.0) ? 1 : 0;
+    sc->done_it[s] = -1;
     return;
   }
   if (mode == 5) {
@@ -1013,6 +1016,7 @@ __global__ __launch_bounds__(kBlock) void kb_reduce(BatchArgs a, int np, int mod
   const bool inner = mode == 6;
   if (o[1] <= sc->tol2[s]) {
     sc->done[s] = 1;
+    sc->done_it[s] = it;  // the update (c) of this iteration still moves x
     sc->iters_total[s] += it + 1;
     if (!inner) sc->slot_iters[slot][s] = it + 1;
     else if (sc->slot_iters[slot][s] >= 0 && it + 1 > sc->slot_iters[slot][s])
@@ -1248,8 +1252,9 @@ __device__ __forceinline__ void vstore(V *p, int64_t base, int s0, int S, const 
   }
 }
 
-// (b) x += alpha p; r -= alpha q; partial r.z, r.r; GA row groups of a lane
-// in flight (any GA gives the same results)
+// (b) r -= alpha q; partial r.z, r.r; GA row groups of a lane in flight (any
+// GA gives the same results).  x += alpha p waits for the update (c), which
+// reads p anyway: (b) moves only q and r.
 template <typename V, bool AL, int GA>
 __global__ __launch_bounds__(kBlock) void kb_pcg_b(BatchArgs a, int m, double dtau) {
   using LY = Lanes<V>;
@@ -1268,13 +1273,12 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_b(BatchArgs a, int m, double dt
     any |= on[k];
   }
   double v[2][VEC] = {};
-  V *x = BV<V>::x(a, m), *rv = BV<V>::r(a);
-  const V *p = BV<V>::p(a), *q = BV<V>::q(a);
+  V *rv = BV<V>::r(a);
+  const V *q = BV<V>::q(a);
   const int64_t N = a.N, G = (N + RPW - 1) / RPW;
   if (__ballot(any) != 0ull) {  // some lane of the wave has work
     for (GroupRange gr = xcd_groups(G); gr.g < gr.end; gr.g += GA * gr.stride) {
-      V xs[GA][VEC], ps[GA][VEC], qs[GA][VEC],
-          rs[GA][VEC];
+      V qs[GA][VEC], rs[GA][VEC];
       double ms[GA], kd[GA], rd[GA];
       bool ok[GA];
 #pragma unroll
@@ -1282,8 +1286,6 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_b(BatchArgs a, int m, double dt
         const int64_t g = gr.g + u * gr.stride, row = g * RPW + lr;
         ok[u] = (g < gr.end) & (row < N) & (s0 < S);
         const int64_t rw = ok[u] ? row : 0, base = rw * S + (s0 < S ? s0 : 0);
-        vload<V, VEC, AL>(x, base, s0, S, xs[u]);
-        vload<V, VEC, AL>(p, base, s0, S, ps[u]);
         vload<V, VEC, AL>(q, base, s0, S, qs[u]);
         vload<V, VEC, AL>(rv, base, s0, S, rs[u]);
         ms[u] = a.mass[rw];
@@ -1299,14 +1301,12 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_b(BatchArgs a, int m, double dt
 #pragma unroll
         for (int k = 0; k < VEC; ++k) {
           if (!on[k]) continue;  // idle scenarios keep their values
-          xs[u][k] = xs[u][k] + alpha[k] * ps[u][k];
           const V r = rs[u][k] - alpha[k] * qs[u][k];
           rs[u][k] = r;
           const V z = di[k] * r;
           v[0][k] += (double)r * (double)z;
           v[1][k] += (double)r * (double)r;
         }
-        vstore<V, VEC, AL>(x, base, s0, S, xs[u]);
         vstore<V, VEC, AL>(rv, base, s0, S, rs[u]);
       }
     }
@@ -1323,30 +1323,36 @@ __device__ __forceinline__ double pupdate(double di, double r, double beta, doub
   return __builtin_fma(di, r, beta * p);
 }
 
-// (c) p = z + beta p, row groups as in (b), GA of a lane in flight
+// (c) x += alpha p, then p = z + beta p, row groups as in (b), GA of a lane in
+// flight.  x moves for every scenario that iterated in this iteration (it),
+// including one whose solve the check after (b) has just found converged;
+// p only for the scenarios still iterating.
 template <typename V, bool AL, int GA>
-__global__ __launch_bounds__(kBlock) void kb_pcg_c(BatchArgs a, double dtau) {
+__global__ __launch_bounds__(kBlock) void kb_pcg_c(BatchArgs a, int m, double dtau, int it) {
   using LY = Lanes<V>;
   constexpr int VEC = LY::VEC, RPW = LY::RPW;
   const int S = a.S, lane = threadIdx.x & 63;
   const int lr = lane / LY::LPR, s0 = (lane % LY::LPR) * VEC;
-  bool on[VEC], any = false;
+  bool on[VEC], mv[VEC], any = false;
   double h[VEC];
-  V beta[VEC];
+  V alpha[VEC], beta[VEC];
 #pragma unroll
   for (int k = 0; k < VEC; ++k) {
     const int s = s0 + k, sc = s < S ? s : 0;
     on[k] = lane_on(a.sc, s, S);
+    mv[k] = on[k] | (sweeping(a.sc, s, S) & (a.sc->ref_done[sc] == 0) & (a.sc->done[sc] != 0) &
+                     (a.sc->done_it[sc] == it));
     h[k] = on[k] ? a.h[sc] : 0.0;
+    alpha[k] = mv[k] ? (V)a.sc->alpha[sc] : (V)0;
     beta[k] = on[k] ? (V)a.sc->beta[sc] : (V)0;
-    any |= on[k];
+    any |= mv[k];
   }
   if (__ballot(any) == 0ull) return;  // no lane of the wave has work
-  V *p = BV<V>::p(a);
+  V *p = BV<V>::p(a), *x = BV<V>::x(a, m);
   const V *rv = BV<V>::r(a);
   const int64_t N = a.N, G = (N + RPW - 1) / RPW;
   for (GroupRange gr = xcd_groups(G); gr.g < gr.end; gr.g += GA * gr.stride) {
-    V ps[GA][VEC], rs[GA][VEC];
+    V ps[GA][VEC], rs[GA][VEC], xs[GA][VEC];
     double ms[GA], kd[GA], rd[GA];
     bool ok[GA];
 #pragma unroll
@@ -1356,6 +1362,7 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_c(BatchArgs a, double dtau) {
       const int64_t rw = ok[u] ? row : 0, base = rw * S + (s0 < S ? s0 : 0);
       vload<V, VEC, AL>(p, base, s0, S, ps[u]);
       vload<V, VEC, AL>(rv, base, s0, S, rs[u]);
+      vload<V, VEC, AL>(x, base, s0, S, xs[u]);
       ms[u] = a.mass[rw];
       kd[u] = a.Kd[rw];
       rd[u] = a.Rd[rw];
@@ -1367,8 +1374,11 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_c(BatchArgs a, double dtau) {
       V di[VEC];
       dinv_row<V, VEC>(ms[u], kd[u], rd[u], h, dtau, di);
 #pragma unroll
-      for (int k = 0; k < VEC; ++k)
+      for (int k = 0; k < VEC; ++k) {
+        if (mv[k]) xs[u][k] = xs[u][k] + alpha[k] * ps[u][k];
         if (on[k]) ps[u][k] = pupdate(di[k], rs[u][k], beta[k], ps[u][k]);
+      }
+      vstore<V, VEC, AL>(x, base, s0, S, xs[u]);
       vstore<V, VEC, AL>(p, base, s0, S, ps[u]);
     }
   }
@@ -1782,14 +1792,14 @@ static void launch_pcg_b(const BatchArgs &a, int m, double dtau, hipStream_t st)
   else launch_pcg_b_ga<V, kGroupsAhead>(a, m, dtau, st);
 }
 template <typename V, int GA>
-static void launch_pcg_c_ga(const BatchArgs &a, double dtau, hipStream_t st) {
-  if (vec16<V>(a)) kb_pcg_c<V, true, GA><<<a.grid, kBlock, 0, st>>>(a, dtau);
-  else kb_pcg_c<V, false, GA><<<a.grid, kBlock, 0, st>>>(a, dtau);
+static void launch_pcg_c_ga(const BatchArgs &a, int m, double dtau, int it, hipStream_t st) {
+  if (vec16<V>(a)) kb_pcg_c<V, true, GA><<<a.grid, kBlock, 0, st>>>(a, m, dtau, it);
+  else kb_pcg_c<V, false, GA><<<a.grid, kBlock, 0, st>>>(a, m, dtau, it);
 }
 template <typename V>
-static void launch_pcg_c(const BatchArgs &a, double dtau, hipStream_t st) {
-  if (a.groups_c == 8) launch_pcg_c_ga<V, 8>(a, dtau, st);
-  else launch_pcg_c_ga<V, kGroupsAhead>(a, dtau, st);
+static void launch_pcg_c(const BatchArgs &a, int m, double dtau, int it, hipStream_t st) {
+  if (a.groups_c == 8) launch_pcg_c_ga<V, 8>(a, m, dtau, it, st);
+  else launch_pcg_c_ga<V, kGroupsAhead>(a, m, dtau, it, st);
 }
 
 template <typename V>
@@ -1802,7 +1812,7 @@ static void cg_iterations(const BatchArgs &a, int m, double dtau, int slot, int 
     RED(pcg_a_grid<V>(a), 1, it, 0, slot, rtol);
     launch_pcg_b<V>(a, m, dtau, st);
     RED(gb, conv, it, it == budget - 1, slot, rtol);
-    launch_pcg_c<V>(a, dtau, st);
+    launch_pcg_c<V>(a, m, dtau, it, st);
   }
 }
 
@@ -1847,7 +1857,7 @@ void blaunch_tune(const BatchArgs &a, int which, int reps, hipStream_t st) {
   for (int i = 0; i < reps; ++i) {
     if (which == 0) launch_pcg_a<float>(a, 1, m, dtau, st);
     else if (which == 1) launch_pcg_b<float>(a, m, dtau, st);
-    else launch_pcg_c<float>(a, dtau, st);
+    else launch_pcg_c<float>(a, m, dtau, 0, st);
   }
 }
 
