@@ -480,7 +480,7 @@ mrsdc_status build_stage_tiles(mrsdc_ctx *c, int64_t N, const std::vector<int64_
 // 2 GB or more.
 mrsdc_status build_columns(mrsdc_ctx *c, int64_t N, BatchArgs &a) {
   if (c->cfg.precision != MRSDC_FP32_REFINE) return MRSDC_OK;  // the FP32 operator only
-  if (N * c->S * 4 >= ((int64_t)1 << 31)) return MRSDC_OK;
+  if ((N * c->S + kColZeroRow) * 4 >= ((int64_t)1 << 31)) return MRSDC_OK;
   int64_t dm[2][3];
   for (int b = 0; b < c->nbody; ++b)
     if (!box_dims(c->body[b], dm[b])) return MRSDC_OK;
@@ -593,12 +593,14 @@ mrsdc_status build_columns(mrsdc_ctx *c, int64_t N, BatchArgs &a) {
   if ((st = upload(c, &pi, items))) return st;
   a.op.col_items = pi;
   a.op.ncol_items = (int)(items.size() / kColItem);
+  // K records then R records in one buffer (one buffer resource in the kernel)
+  const size_t nk = krec.size();
+  krec.insert(krec.end(), rrec.begin(), rrec.end());
+  if (krec.size() * 4 >= ((size_t)1 << 31)) return fail(c, MRSDC_EINVAL, "column records above 2 GB");
   if ((st = upload(c, &pf, krec))) return st;
   a.op.kcol32 = pf;
-  if ((st = upload(c, &pf, rrec))) return st;
-  a.op.rcol32 = pf;
-  if ((st = upload(c, &pf, std::vector<float>(64, 0.0f)))) return st;
-  a.op.col_zero = pf;
+  a.op.rcol32 = pf + nk;
+  a.op.col_rec_bytes = (int64_t)krec.size() * 4;
   // one workgroup per item: the dispatcher balances the items over the CUs
   a.cgrid64 = a.cgrid32 = (a.op.ncol_items + 7) / 8 * 8 + 8;
   return MRSDC_OK;
@@ -707,13 +709,16 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
     // inner vectors and the FP64 refinement residual, scenario-interleaved
     a.fp32 = 1;
     const size_t NS = (size_t)N * S;
+    // p32 ends in one row of 64 zeros (shared, not per scenario): the column
+    // sweep stages halo rows outside a body from it
     if ((st = dalloc(c, &a.x32, NS, true)) || (st = dalloc(c, &a.r32, NS, true)) ||
-        (st = dalloc(c, &a.p32, NS, true)) || (st = dalloc(c, &a.q32, NS, true)) ||
+        (st = dalloc(c, &a.p32, NS + kColZeroRow, true)) || (st = dalloc(c, &a.q32, NS, true)) ||
         (st = dalloc(c, &a.r64, NS, true)))
       return st;
+    c->scen_bytes -= (int64_t)kColZeroRow * sizeof(float);
     HIPCHK(hipMemset(a.x32, 0, NS * sizeof(float)));
     HIPCHK(hipMemset(a.r32, 0, NS * sizeof(float)));
-    HIPCHK(hipMemset(a.p32, 0, NS * sizeof(float)));
+    HIPCHK(hipMemset(a.p32, 0, (NS + kColZeroRow) * sizeof(float)));
     HIPCHK(hipMemset(a.q32, 0, NS * sizeof(float)));
     HIPCHK(hipMemset(a.r64, 0, NS * sizeof(double)));
   }

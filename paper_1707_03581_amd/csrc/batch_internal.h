@@ -41,11 +41,12 @@ struct BatchOp {
   // [ncol_items][kColItem]: row offset, nx, ny, nz, x0, y0, z0, z1, first K
   // record, first R record, R plane mask (bit z - z0; two words)
   const int *col_items = nullptr;
-  const float *kcol32 = nullptr;    // [K records][kColRows][kStencil]
-  const float *rcol32 = nullptr;    // [R records][kColRows][kStencil]
-  const float *col_zero = nullptr;  // 64 zeros: the halo rows outside a body
+  const float *kcol32 = nullptr;  // [K records][kColRows][kStencil], then the R records:
+  const float *rcol32 = nullptr;  // [R records][kColRows][kStencil] (same buffer)
+  int64_t col_rec_bytes = 0;      // bytes of both
 };
 constexpr int kColFX = 4, kColFY = 4;                // footprint of a column item
+constexpr int kColZeroRow = 64;                      // zeros after the FP32 direction p
 constexpr int kColRows = kColFX * kColFY;            // rows of a plane of an item
 constexpr int kColPL = (kColFX + 2) * (kColFY + 2);  // staged rows per plane (halo included)
 constexpr int kColDepth = 2;                         // stages in flight beyond the one read

@@ -322,7 +322,8 @@ __device__ __attribute__((always_inline)) inline void tile_apply(
 #pragma unroll
     for (int k = 0; k < VEC; ++k) {
       if (s0 + k >= S) continue;
-      const AT y = n == nk[i] ? acc[k] : acc[k] + h[k] * accr[k];
+      // (one explicit rounding pattern: the column sweep forms the same)
+      const AT y = n == nk[i] ? acc[k] : fma_t(h[k], accr[k], acc[k]);
       epi(row, k, s0 + k, y, own[k], ms[i]);
     }
   }
@@ -461,12 +462,17 @@ struct ColIssue {
   using CC = ColCopies<UB>;
   static constexpr int UPH = 64 * 4 / UB;  // units per staged row (64 values)
   static constexpr unsigned XB = kColPlaneUnits * 16, RB = kColRecSlot * 16;  // slot bytes
-  unsigned xoff[CC::C0];  // plane-0 byte offset of the lane's unit (x copies)
+  static constexpr unsigned RECB = kColRecUnits * 16;                         // record bytes
+  // buffer resources: x (the FP32 direction, which ends in a row of zeros)
+  // and the records (K, then R); every copy reads inside them
+  __amdgpu_buffer_rsrc_t rx, rrec;
+  unsigned xoff[CC::C0];  // the lane's unit: plane-0 byte offset (x copies)
   unsigned zoff[CC::C0];  // its offset in the row of zeros
   bool xin[CC::C0];       // halo row inside the body, unit inside the row
   unsigned roff;          // record copy: byte offset of the lane's unit in a record
   int rpart;              // 0: K unit, 1: R unit, 2: tail
   unsigned pstride;       // bytes between planes of x
+  unsigned rbase;         // byte offset of the R records
   int w;
   // the next stage (wave-uniform): its plane P and record plane R = P + 1,
   // the byte offsets of its slots, P's offset in x, and R's record indices
@@ -476,9 +482,15 @@ struct ColIssue {
 
   // ring slots: stage z0 - 2 + i in plane slot i mod NX, record plane z0 + i
   // in record slot i mod NR
-  __device__ __forceinline__ void init(const ColItem &it, int S, int wave) {
+  __device__ __forceinline__ void init(const BatchArgs &a, const ColItem &it, int wave) {
     w = wave;
-    const int lane = threadIdx.x & 63, upr = S * 4 / UB;
+    const int S = a.S, lane = threadIdx.x & 63, upr = S * 4 / UB;
+    const unsigned zrow = (unsigned)(a.N * S) * 4u;  // the row of zeros after p
+    rx = __builtin_amdgcn_make_buffer_rsrc((void *)a.p32, 0, (int)(zrow + kColZeroRow * 4),
+                                           0x00020000);
+    rrec = __builtin_amdgcn_make_buffer_rsrc((void *)a.op.kcol32, 0, (int)a.op.col_rec_bytes,
+                                             0x00020000);
+    rbase = (unsigned)((a.op.rcol32 - a.op.kcol32) * 4);
     pstride = (unsigned)it.nx * (unsigned)it.ny * (unsigned)upr * (unsigned)UB;
 #pragma unroll
     for (int i = 0; i < CC::C0; ++i) {
@@ -490,7 +502,7 @@ struct ColIssue {
       // (32-bit offsets: the column sweep runs only on vectors below 2 GB)
       const unsigned row = xin[i] ? (unsigned)(it.off + gx + it.nx * gy) : 0u;
       xoff[i] = (row * (unsigned)upr + (unsigned)part) * (unsigned)UB;
-      zoff[i] = (unsigned)(part * UB);
+      zoff[i] = zrow + (unsigned)(part * UB);
     }
     const int jr = w + 4 * ((CC::X - w + 3) / 4);  // this wave's record copy
     const int u = (jr - CC::X) * 64 + lane;
@@ -508,32 +520,28 @@ struct ColIssue {
   // Issue the next stage: plane P (zeros outside the body and past the
   // run's top neighbour z1) and the record of plane R (the run's first record
   // past the run), then step to the stage after it.
-  __device__ __forceinline__ void issue(const BatchOp &op, const ColItem &it,
-                                        const float *__restrict__ x, ColLds<D> &L) {
+  __device__ __forceinline__ void issue(const ColItem &it, ColLds<D> &L) {
     const bool pin = (P >= 0) & (P < it.nz) & (P <= it.z1);
     const bool inrun = R < it.z1;
     const bool hasr = inrun & ((rbits & 1ull) != 0);
-    const char *xb = reinterpret_cast<const char *>(x);
-    const char *zb = reinterpret_cast<const char *>(op.col_zero);
     char *lx = reinterpret_cast<char *>(&L.x[0][0]) + xso;
 #pragma unroll
     for (int i = 0; i < CC::C0; ++i) {
       const int j = w + 4 * i;  // wave-uniform
       if (j >= CC::N) break;
       if (j < CC::X) {
-        const char *src = (pin & xin[i]) ? xb + (xoff[i] + pbase) : zb + zoff[i];
+        const unsigned off = (pin & xin[i]) ? xoff[i] + pbase : zoff[i];
         auto *dst = (__attribute__((address_space(3))) void *)(lx + j * 64 * UB);
-        if constexpr (UB == 16) __builtin_amdgcn_global_load_lds((const void *)src, dst, 16, 0, 0);
-        else __builtin_amdgcn_global_load_lds((const void *)src, dst, 4, 0, 0);
+        if constexpr (UB == 16) __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, dst, 16, off, 0, 0, 0);
+        else __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, dst, 4, off, 0, 0, 0);
       } else {
-        const int k = inrun ? kr : it.kb, q = inrun ? rr : it.rb;
-        const char *kb = reinterpret_cast<const char *>(op.kcol32) + (size_t)k * kColRecUnits * 16;
-        const char *rb = reinterpret_cast<const char *>(op.rcol32) + (size_t)q * kColRecUnits * 16;
-        const char *src = (((rpart == 1) & hasr) ? rb : kb) + roff;
+        const unsigned ko = (unsigned)(inrun ? kr : it.kb) * RECB;
+        const unsigned ro = rbase + (unsigned)(inrun ? rr : it.rb) * RECB;
+        const unsigned off = (((rpart == 1) & hasr) ? ro : ko) + roff;
         char *lr = reinterpret_cast<char *>(&L.rec[0][0]) + rso;
-        __builtin_amdgcn_global_load_lds(
-            (const void *)src, (__attribute__((address_space(3))) void *)(lr + (j - CC::X) * 1024),
-            16, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rrec, (__attribute__((address_space(3))) void *)(lr + (j - CC::X) * 1024), 16, off, 0,
+            0, 0);
       }
     }
     P += 1;
@@ -1061,9 +1069,9 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_a(BatchArgs a, int m, double dt
       tile_apply<V, V, V, UB, AL>(a, t, BV<V>::vals(a), BV<V>::p(a), h, L,
                                   [&](int64_t row, int i, int s, V y, V pi, double mass) {
                                     if (!on[i]) return;
-                                    const V qi = (V)mass * pi + dt * y;
+                                    const V qi = fma_t((V)mass, pi, dt * y);
                                     q[row * S + s] = qi;
-                                    v[0][i] += (double)pi * (double)qi;
+                                    v[0][i] = fma_t((double)pi, (double)qi, v[0][i]);
                                   });
     }
   }
@@ -1099,7 +1107,6 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
     any |= on[i];
   }
   const float dt = (float)dtau;
-  const float *p = a.p32;
   const __amdgpu_buffer_rsrc_t qres =
       __builtin_amdgcn_make_buffer_rsrc(a.q32, 0, (int)(a.N * S * 4), 0x00020000);
   const int T = a.op.ncol_items, xcd = blockIdx.x % kXcd, local = blockIdx.x / kXcd;
@@ -1115,8 +1122,8 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
     // used).
     const int zb = it.z0 - 2;
     ColIssue<UB, D> ci;
-    ci.init(it, S, w);
-    for (int q = 0; q <= D; ++q) ci.issue(a.op, it, p, L);  // stages z0 - 2 .. z0 - 2 + D
+    ci.init(a, it, w);
+    for (int q = 0; q <= D; ++q) ci.issue(it, L);  // stages z0 - 2 .. z0 - 2 + D
     if (w == 0) col_wait<D * CC::C0>();
     else col_wait<D * CC::C1>();
     col_barrier();
@@ -1157,9 +1164,20 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
       float qv[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float y = m0 < 0.0f ? ka[q] + h[q] * ra[q] : ka[q];
-        qv[q] = mass * ow[q] + dt * y;
-        if (row_in & on[q]) v[0][q] += (double)ow[q] * (double)qv[q];
+        // (explicit fused forms, as in the tiled product, so that no
+        // instantiation contracts them differently)
+        const float y = m0 < 0.0f ? fma_t(h[q], ra[q], ka[q]) : ka[q];
+        qv[q] = fma_t(mass, ow[q], dt * y);
+      }
+      // p.q over the run's rows (wave-uniform test: the rows below the run
+      // come from records that were never copied); a masked lane adds an
+      // exact zero (rows outside the body have zero records, so finite q)
+      if (z >= it.z0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float om = (rok & on[q]) ? ow[q] : 0.0f;
+          v[0][q] = fma_t((double)om, (double)qv[q], v[0][q]);
+        }
       }
       // a fixed number of stores per step whatever the masks (a masked
       // store's offset lies past the buffer, so it is dropped)
@@ -1189,7 +1207,7 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
       if (w == 0) col_wait_plane<CC::C0, ST, D>(min(z - zb, D - 1));
       else col_wait_plane<CC::C1, ST, D>(min(z - zb, D - 1));
       col_barrier();  // stage z + 1 landed; plane z + 1 and the record of z free
-      ci.issue(a.op, it, p, L);  // stage z + 1 + D
+      ci.issue(it, L);  // stage z + 1 + D
       xro = xro + XB == NX * XB ? 0u : xro + XB;
       r0o = r1o;
     }
@@ -1301,11 +1319,12 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_b(BatchArgs a, int m, double dt
 #pragma unroll
         for (int k = 0; k < VEC; ++k) {
           if (!on[k]) continue;  // idle scenarios keep their values
-          const V r = rs[u][k] - alpha[k] * qs[u][k];
+          // (explicit fused forms: every instantiation rounds alike)
+          const V r = fma_t(-alpha[k], qs[u][k], rs[u][k]);
           rs[u][k] = r;
           const V z = di[k] * r;
-          v[0][k] += (double)r * (double)z;
-          v[1][k] += (double)r * (double)r;
+          v[0][k] = fma_t((double)r, (double)z, v[0][k]);
+          v[1][k] = fma_t((double)r, (double)r, v[1][k]);
         }
         vstore<V, VEC, AL>(rv, base, s0, S, rs[u]);
       }
@@ -1375,7 +1394,7 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_c(BatchArgs a, int m, double dt
       dinv_row<V, VEC>(ms[u], kd[u], rd[u], h, dtau, di);
 #pragma unroll
       for (int k = 0; k < VEC; ++k) {
-        if (mv[k]) xs[u][k] = xs[u][k] + alpha[k] * ps[u][k];
+        if (mv[k]) xs[u][k] = fma_t(alpha[k], ps[u][k], xs[u][k]);
         if (on[k]) ps[u][k] = pupdate(di[k], rs[u][k], beta[k], ps[u][k]);
       }
       vstore<V, VEC, AL>(x, base, s0, S, xs[u]);
