@@ -127,20 +127,28 @@ typedef struct {
                          OR-ed with MRSDC_OP_COL32: int32 columns even where
                          16-bit offsets fit.  The first advance (or stationary
                          solve) returns EINVAL when the form does not apply.
-                         Batched contexts take MRSDC_OP_AUTO only. */
+                         Batched contexts take MRSDC_OP_AUTO (the column sweep,
+                         which finds each entry from its stencil position, on
+                         meshes whose bodies are boxes of the 27-point
+                         pattern, else LDS tiles of the stored entries) or
+                         MRSDC_OP_VALUES (the tiles on every mesh); the two
+                         form each row's sums in the same order but reduce
+                         p.q in a different order, so they agree to rounding */
   const mrsdc_allocator *alloc; /* NULL: hipMalloc / hipFree.  Otherwise every
                          device buffer of the context (and of its deformation
                          solve) comes from alloc and goes back through release;
                          both must be set */
-  int autotune;       /* nonzero (batched FP32_REFINE contexts): before the first
-                         step, time the launch variants of the CG kernels on this
-                         mesh (stages in flight of the column sweep, row groups
-                         in flight of the two CG updates) and keep the fastest.
-                         Every variant gives bit for bit the same results; the
-                         choice is kept per process for the mesh and scenario
-                         count and reported in mrsdc_stats.  2 .. 9 pick a
-                         variant without timing (bits of autotune - 2: 1 one
-                         stage in flight, 2 two groups in (b), 4 eight in (c)) */
+  int autotune;       /* nonzero (batched contexts): before the first step,
+                         time the launch variants of the CG kernels on this
+                         mesh (stages in flight of the column sweep; in
+                         FP32_REFINE also the row groups in flight of the two
+                         CG updates) and keep the fastest.  Every variant
+                         gives bit for bit the same results; the choice is
+                         kept per process for the mesh, precision and
+                         scenario count and reported in mrsdc_stats.  2 .. 9
+                         pick a variant without timing (bits of autotune - 2:
+                         1 one stage in flight, 2 two groups in (b), 4 eight
+                         in (c)) */
 } mrsdc_config;
 
 enum {

@@ -467,27 +467,31 @@ mrsdc_status build_stage_tiles(mrsdc_ctx *c, int64_t N, const std::vector<int64_
   return fail(c, MRSDC_EINVAL, "a row block exceeds the staging capacity of %d columns", kStageSlots);
 }
 
-// Column sweep of the FP32 operator when every body is a box of the 27-point
+// Column sweep of the operator when every body is a box of the 27-point
 // pattern: work items of kColFX x kColFY nodes of one body over a run of z
 // planes, and per item plane a record of the footprint rows' K stencils
 // (value k = entry of neighbour (dz+1) 9 + (dy+1) 3 + (dx+1); value 27 = the
-// row's FP32 mass, negated where the row has R entries) plus, for the planes
-// where a row has R entries, a record of their R stencils.  Items run body by
-// body, then by z run, then by footprint row and column, so neighbouring
-// footprints (which share halo rows) are dealt to the same XCD and run side
-// by side.
-// Leaves ncol_items = 0 (tiles only) for any other mesh and for vectors of
-// 2 GB or more.
+// row's mass, negated where the row has R entries) plus, for the planes
+// where a row has R entries, a record of their R stencils, in the context's
+// form (FP32 or FP64 values).  Items run body by body, then by z run, then
+// by footprint row and column, so neighbouring footprints (which share halo
+// rows) are dealt to the same XCD and run side by side.  In FP64 each item
+// is two work units (the two halves of the scenarios).
+// Leaves ncol_items = 0 (tiles only) for any other mesh, for vectors of 2 GB
+// or more, and where the context asks for the stored values
+// (MRSDC_OP_VALUES).
 mrsdc_status build_columns(mrsdc_ctx *c, int64_t N, BatchArgs &a) {
-  if (c->cfg.precision != MRSDC_FP32_REFINE) return MRSDC_OK;  // the FP32 operator only
-  if ((N * c->S + kColZeroRow) * 4 >= ((int64_t)1 << 31)) return MRSDC_OK;
+  if (c->cfg.op_form == MRSDC_OP_VALUES) return MRSDC_OK;  // stored values: tiles
+  const bool fp32 = c->cfg.precision == MRSDC_FP32_REFINE;
+  const int64_t vb = fp32 ? 4 : 8, units = fp32 ? 1 : 2;
+  if ((N * c->S + kColZeroRow) * vb >= ((int64_t)1 << 31)) return MRSDC_OK;
   int64_t dm[2][3];
   for (int b = 0; b < c->nbody; ++b)
     if (!box_dims(c->body[b], dm[b])) return MRSDC_OK;
   // per-row stencils in natural row order
   std::vector<double> ks((size_t)N * kStencil, 0.0), rs;
   std::vector<int> ridx(N, -1);
-  std::vector<float> mass32(N);
+  std::vector<double> mass(N);
   int64_t colplanes = 0;
   for (int b = 0; b < c->nbody; ++b) {
     const HostBody &B = c->body[b];
@@ -496,7 +500,7 @@ mrsdc_status build_columns(mrsdc_ctx *c, int64_t N, BatchArgs &a) {
     for (int64_t i = 0; i < B.n; ++i) {
       const int64_t row = c->off[b] + i;
       const int64_t ix = i % nx, iy = (i / nx) % ny, iz = i / (nx * ny);
-      mass32[row] = (float)B.mass[i];
+      mass[row] = B.mass[i];
       bool hasR = false;
       for (int64_t e = B.rowptr[i]; e < B.rowptr[i + 1]; ++e) {
         const int64_t j = B.col[e];
@@ -520,13 +524,14 @@ mrsdc_status build_columns(mrsdc_ctx *c, int64_t N, BatchArgs &a) {
   // makespan when XCD x deals its eighth of the items, in order, to its
   // resident workgroups as they come free, an item costing its planes plus
   // the steps that fill its pipeline.
-  const int64_t slots = std::max<int64_t>(1, 256 * (int64_t)col_workgroups_per_cu() / 8);
+  const int64_t slots =
+      std::max<int64_t>(1, 256 * (int64_t)col_workgroups_per_cu(fp32, a.col_depth) / 8);
   auto makespan = [&](int64_t zr) {
     std::vector<int64_t> cost;
     for (int b = 0; b < c->nbody; ++b) {
       const int64_t fp = ((dm[b][0] + kColFX - 1) / kColFX) * ((dm[b][1] + kColFY - 1) / kColFY);
       for (int64_t z0 = 0; z0 < dm[b][2]; z0 += zr)
-        cost.insert(cost.end(), fp, std::min(dm[b][2], z0 + zr) - z0 + 3 + kColDepth);
+        cost.insert(cost.end(), fp * units, std::min(dm[b][2], z0 + zr) - z0 + 3 + a.col_depth);
     }
     const int64_t T = (int64_t)cost.size();
     int64_t worst = 0;
@@ -548,7 +553,7 @@ mrsdc_status build_columns(mrsdc_ctx *c, int64_t N, BatchArgs &a) {
     if (ms < best) best = ms, zrun = zr;
   }
   std::vector<int> items;
-  std::vector<float> krec, rrec;
+  std::vector<double> krec, rrec;
   const size_t rec = (size_t)kColRows * kStencil;
   for (int b = 0; b < c->nbody; ++b)
     for (int64_t z0 = 0; z0 < dm[b][2]; z0 += zrun)
@@ -558,22 +563,21 @@ mrsdc_status build_columns(mrsdc_ctx *c, int64_t N, BatchArgs &a) {
           const int kb = (int)(krec.size() / rec), rb = (int)(rrec.size() / rec);
           uint64_t mask = 0;
           for (int64_t z = z0; z < z1; ++z) {
-            krec.resize(krec.size() + rec, 0.0f);
-            float *kr = krec.data() + krec.size() - rec;
-            std::vector<float> rr(rec, 0.0f);
+            krec.resize(krec.size() + rec, 0.0);
+            double *kr = krec.data() + krec.size() - rec;
+            std::vector<double> rr(rec, 0.0);
             bool anyR = false;
             for (int r = 0; r < kColRows; ++r) {
               const int64_t gx = x0 + r % kColFX, gy = y0 + r / kColFX;
               if (gx >= dm[b][0] || gy >= dm[b][1]) continue;  // outside the body: zeros
               const int64_t row = c->off[b] + gx + dm[b][0] * (gy + dm[b][1] * z);
-              for (int k = 0; k < 27; ++k)
-                kr[r * kStencil + k] = (float)ks[(size_t)row * kStencil + k];
+              for (int k = 0; k < 27; ++k) kr[r * kStencil + k] = ks[(size_t)row * kStencil + k];
               const bool hasR = ridx[row] >= 0;
-              kr[r * kStencil + 27] = hasR ? -mass32[row] : mass32[row];
+              kr[r * kStencil + 27] = hasR ? -mass[row] : mass[row];
               if (!hasR) continue;
               anyR = true;
               for (int k = 0; k < 27; ++k)
-                rr[r * kStencil + k] = (float)rs[(size_t)ridx[row] * kStencil + k];
+                rr[r * kStencil + k] = rs[(size_t)ridx[row] * kStencil + k];
             }
             if (anyR) {
               mask |= 1ull << (z - z0);
@@ -585,24 +589,32 @@ mrsdc_status build_columns(mrsdc_ctx *c, int64_t N, BatchArgs &a) {
                                     (int)(uint32_t)mask, (int)(uint32_t)(mask >> 32)};
           items.insert(items.end(), it, it + kColItem);
         }
-  c->col_stored_bytes = (int64_t)(krec.size() + rrec.size()) * 4 + (int64_t)items.size() * 4;
-  if (rrec.empty()) rrec.assign(rec, 0.0f);
+  c->col_stored_bytes = (int64_t)(krec.size() + rrec.size()) * vb + (int64_t)items.size() * 4;
+  if (rrec.empty()) rrec.assign(rec, 0.0);
   mrsdc_status st;
   int *pi;
-  float *pf;
   if ((st = upload(c, &pi, items))) return st;
   a.op.col_items = pi;
   a.op.ncol_items = (int)(items.size() / kColItem);
   // K records then R records in one buffer (one buffer resource in the kernel)
   const size_t nk = krec.size();
   krec.insert(krec.end(), rrec.begin(), rrec.end());
-  if (krec.size() * 4 >= ((size_t)1 << 31)) return fail(c, MRSDC_EINVAL, "column records above 2 GB");
-  if ((st = upload(c, &pf, krec))) return st;
-  a.op.kcol32 = pf;
-  a.op.rcol32 = pf + nk;
-  a.op.col_rec_bytes = (int64_t)krec.size() * 4;
-  // one workgroup per item: the dispatcher balances the items over the CUs
-  a.cgrid64 = a.cgrid32 = (a.op.ncol_items + 7) / 8 * 8 + 8;
+  if (krec.size() * vb >= ((size_t)1 << 31))
+    return fail(c, MRSDC_EINVAL, "column records above 2 GB");
+  if (fp32) {
+    float *pf;
+    if ((st = upload(c, &pf, std::vector<float>(krec.begin(), krec.end())))) return st;
+    a.op.kcol32 = pf;
+    a.op.rcol32 = pf + nk;
+  } else {
+    double *pd;
+    if ((st = upload(c, &pd, krec))) return st;
+    a.op.kcol64 = pd;
+    a.op.rcol64 = pd + nk;
+  }
+  a.op.col_rec_bytes = (int64_t)krec.size() * vb;
+  // one workgroup per work unit: the dispatcher balances them over the CUs
+  a.cgrid32 = (int)((a.op.ncol_items * units + 7) / 8 * 8 + 8);
   return MRSDC_OK;
 }
 
@@ -688,7 +700,7 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
   if ((st = dalloc(c, &a.sc, 1))) return st;
   HIPCHK(hipMemset(a.sc, 0, sizeof(BatchScalars)));
   HIPCHK(hipMemcpy(a.sc->active, act.data(), sizeof(int) * S, hipMemcpyHostToDevice));
-  const int maxgrid = std::max({a.grid, a.sgrid64, a.sgrid32, a.cgrid64, a.cgrid32});
+  const int maxgrid = std::max({a.grid, a.sgrid64, a.sgrid32, a.cgrid32});
   if ((st = dalloc(c, &a.partial, 3 * (size_t)maxgrid * S, true)))
     return st;
   if ((st = dalloc(c, &c->stage, N))) return st;
@@ -776,8 +788,8 @@ mrsdc_status prepare(mrsdc_ctx *c) {
     return fail(c, MRSDC_EINVAL, "batched contexts support the contact coupling only");
   if (batch && cfg.method != MRSDC_MULTIRATE)
     return fail(c, MRSDC_EINVAL, "batched contexts run the multi-rate method");
-  if (batch && cfg.op_form != MRSDC_OP_AUTO)
-    return fail(c, MRSDC_EINVAL, "batched contexts keep their own operator form (MRSDC_OP_AUTO)");
+  if (batch && cfg.op_form != MRSDC_OP_AUTO && cfg.op_form != MRSDC_OP_VALUES)
+    return fail(c, MRSDC_EINVAL, "batched contexts take MRSDC_OP_AUTO or MRSDC_OP_VALUES");
   const int form = cfg.op_form & 0xff;  // requested operator form of the CG product
   const bool want_dict = form == MRSDC_OP_AUTO || form >= MRSDC_OP_DICT;
 
@@ -1031,7 +1043,7 @@ mrsdc_status prepare(mrsdc_ctx *c) {
     if (m >= 1 && c->w.dtau[m] != 0.0 && (st = dalloc(c, &d.I[m], NS, true))) return st;
   }
   if (!(batch && fp32) &&
-      ((st = dalloc(c, &d.r, NS, true)) || (st = dalloc(c, &d.p, NS, true)) ||
+      ((st = dalloc(c, &d.r, NS, true)) || (st = dalloc(c, &d.p, batch ? NS + kColZeroRow : NS, true)) ||
        (st = dalloc(c, &d.q, NS, true)) ||
        (!batch && ((st = dalloc(c, &d.u, NS, true)) || (st = dalloc(c, &d.s, NS, true))))))
     return st;
@@ -1042,8 +1054,11 @@ mrsdc_status prepare(mrsdc_ctx *c) {
       if (d.I[m]) HIPCHK(hipMemset(d.I[m], 0, NS * sizeof(double)));
     }
     if (!fp32) {
+      // p ends in one row of 64 zeros (shared, not per scenario): the column
+      // sweep stages halo rows outside a body from it
+      c->scen_bytes -= (int64_t)kColZeroRow * sizeof(double);
       HIPCHK(hipMemset(d.r, 0, NS * sizeof(double)));
-      HIPCHK(hipMemset(d.p, 0, NS * sizeof(double)));
+      HIPCHK(hipMemset(d.p, 0, (NS + kColZeroRow) * sizeof(double)));
       HIPCHK(hipMemset(d.q, 0, NS * sizeof(double)));
     }
   }
@@ -1446,18 +1461,18 @@ void enqueue_batch_step(mrsdc_ctx *c) {
   blaunch_commit(a, c->cfg.dt, st);
 }
 
-// Autotuner (batched FP32 contexts): time the launch variants of the CG
-// kernels on this mesh and keep the fastest: the column sweep's stages in
-// flight, and the row groups in flight of the two CG updates.  Every variant
-// forms the same sums in the same order (the grids, and so the partial sums,
-// stay fixed), so the choice changes time only.  Runs before the first step
-// (the updates then overwrite only inner CG vectors that every solve
-// re-initialises); the choice is kept per process for the mesh and scenario
-// count.
+// Autotuner (batched contexts): time the launch variants of the CG kernels
+// on this mesh and keep the fastest: the column sweep's stages in flight,
+// and in the FP32 form the row groups in flight of the two CG updates.
+// Every variant forms the same sums in the same order (the grids, and so the
+// partial sums, stay fixed), so the choice changes time only.  Runs before
+// the first step (the launches then overwrite only CG vectors that every
+// solve re-initialises); the choice is kept per process for the mesh, form
+// and scenario count.
 mrsdc_status autotune_batch(mrsdc_ctx *c) {
   c->tuned = true;
   BatchArgs &a = c->ba;
-  if (c->cfg.precision != MRSDC_FP32_REFINE) return MRSDC_OK;
+  const bool fp32 = c->cfg.precision == MRSDC_FP32_REFINE;
   if (c->cfg.autotune >= 2) {  // a fixed variant: bits of autotune - 2
     const int v = c->cfg.autotune - 2;
     a.col_depth = (v & 1) ? 1 : kColDepth;
@@ -1465,9 +1480,11 @@ mrsdc_status autotune_batch(mrsdc_ctx *c) {
     a.groups_c = (v & 4) ? 8 : 4;
     return MRSDC_OK;
   }
+  if (!fp32 && a.op.ncol_items == 0) return MRSDC_OK;
   static std::mutex mu;
   static std::map<std::vector<int64_t>, std::array<int, 3>> cache;
-  const std::vector<int64_t> key = {c->cfg.device, a.N, a.S, c->batch_entries, a.op.ncol_items};
+  const std::vector<int64_t> key = {c->cfg.device, a.N,           a.S,
+                                    c->batch_entries, a.op.ncol_items, a.fp32};
   {
     std::lock_guard<std::mutex> g(mu);
     auto f = cache.find(key);
@@ -1500,7 +1517,9 @@ mrsdc_status autotune_batch(mrsdc_ctx *c) {
     int which;
     std::vector<int> values;
   };
-  std::vector<Cand> cands = {{&a.groups_b, 1, {4, 2}}, {&a.groups_c, 2, {4, 8}}};
+  // (in FP64 the operator only: the updates there would write the states)
+  std::vector<Cand> cands;
+  if (fp32) cands = {{&a.groups_b, 1, {4, 2}}, {&a.groups_c, 2, {4, 8}}};
   if (a.op.ncol_items > 0) cands.insert(cands.begin(), Cand{&a.col_depth, 0, {kColDepth, 1}});
   hipError_t e = hipSuccess;
   for (const Cand &k : cands) {

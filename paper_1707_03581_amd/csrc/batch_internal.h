@@ -28,25 +28,28 @@ struct BatchOp {
   const int64_t *tstart = nullptr;  // [ntiles + 1]
   const int64_t *prow = nullptr;    // [N]
   const double *pmass = nullptr;    // [N] lumped mass of row prow[pos]
-  // Column sweep (FP32 operator, every body a box of the 27-point pattern).
-  // Work items are footprints of kColFX x kColFY nodes of one body over a run
-  // of z planes.  Each plane of an item has one record of its footprint rows'
-  // K stencils (kColRows rows of kStencil values, row r = node (x0 + r %
-  // kColFX, y0 + r / kColFX)): value k is the entry of neighbour
-  // k = (dz+1) 9 + (dy+1) 3 + (dx+1), 0 where there is none, and value 27 is
-  // the row's lumped mass in FP32, negated when the row has R entries (rows
-  // outside the body are all zeros).  The planes where a row has R entries
-  // also have one record of the rows' R stencils (same layout, no mass).
+  // Column sweep (every body a box of the 27-point pattern), in the form of
+  // the context (FP32 or FP64 records).  Work items are footprints of
+  // kColFX x kColFY nodes of one body over a run of z planes.  Each plane of
+  // an item has one record of its footprint rows' K stencils (kColRows rows
+  // of kStencil values, row r = node (x0 + r % kColFX, y0 + r / kColFX)):
+  // value k is the entry of neighbour k = (dz+1) 9 + (dy+1) 3 + (dx+1), 0
+  // where there is none, and value 27 is the row's lumped mass, negated when
+  // the row has R entries (rows outside the body are all zeros).  The planes
+  // where a row has R entries also have one record of the rows' R stencils
+  // (same layout, no mass).
   int ncol_items = 0;
   // [ncol_items][kColItem]: row offset, nx, ny, nz, x0, y0, z0, z1, first K
   // record, first R record, R plane mask (bit z - z0; two words)
   const int *col_items = nullptr;
-  const float *kcol32 = nullptr;  // [K records][kColRows][kStencil], then the R records:
-  const float *rcol32 = nullptr;  // [R records][kColRows][kStencil] (same buffer)
-  int64_t col_rec_bytes = 0;      // bytes of both
+  const float *kcol32 = nullptr;   // [K records][kColRows][kStencil], then the R records:
+  const float *rcol32 = nullptr;   // [R records][kColRows][kStencil] (same buffer)
+  const double *kcol64 = nullptr;  // the same in FP64 (FP64 contexts)
+  const double *rcol64 = nullptr;
+  int64_t col_rec_bytes = 0;  // bytes of both
 };
 constexpr int kColFX = 4, kColFY = 4;                // footprint of a column item
-constexpr int kColZeroRow = 64;                      // zeros after the FP32 direction p
+constexpr int kColZeroRow = 64;                      // zeros after the direction p
 constexpr int kColRows = kColFX * kColFY;            // rows of a plane of an item
 constexpr int kColPL = (kColFX + 2) * (kColFY + 2);  // staged rows per plane (halo included)
 constexpr int kColDepth = 2;                         // stages in flight beyond the one read
@@ -97,7 +100,7 @@ struct BSolve {
 struct BatchArgs {
   int S = 0, M = 0, P = 0, grid = 0;
   int sgrid64 = 0, sgrid32 = 0;  // workgroups of the tiled kernels (FP64 / FP32 staging)
-  int cgrid64 = 0, cgrid32 = 0;  // workgroups of the column-sweep kernels (0: tiles)
+  int cgrid32 = 0;               // workgroups of the column-sweep kernel (0: tiles)
   int bgrid64 = 0, bgrid32 = 0;  // workgroups of the CG update (b): all resident
   // launch variants (every one gives the same results): stages in flight of
   // the column sweep (1 or kColDepth), row groups in flight of the CG
@@ -138,15 +141,17 @@ void blaunch_quad_resid(const BatchArgs &a, int k, hipStream_t st);
 void blaunch_solve(const BatchArgs &a, const BSolve &sv, hipStream_t st);
 void blaunch_iface(const BatchArgs &a, int m, bool corr, hipStream_t st);
 void blaunch_operator_timing(const BatchArgs &a, int m, int reps, hipStream_t st);
-// FP32 form, for the autotuner: reps launches of the column-sweep or tiled
-// operator (which 0, timing variant), the update (b) (1) or the update (c)
-// (2) with the launch variants in a; b and c overwrite only inner CG vectors
+// For the autotuner: reps launches of the column-sweep or tiled operator
+// (which 0, timing variant; either form), the FP32 update (b) (1) or the FP32
+// update (c) (2) with the launch variants in a; b and c overwrite only inner
+// CG vectors
 void blaunch_tune(const BatchArgs &a, int which, int reps, hipStream_t st);
 void blaunch_commit(const BatchArgs &a, double dt, hipStream_t st);
 void blaunch_scatter(double *dst, const double *src, int64_t n, int S, int s, hipStream_t st);
 void blaunch_gather(double *dst, const double *src, int64_t n, int S, int s, hipStream_t st);
-// workgroups of the column-sweep operator resident per CU (set by its LDS ring)
-int col_workgroups_per_cu();
+// workgroups of the column-sweep operator resident per CU (set by its LDS
+// ring) in the FP32 (fp32 = 1) or FP64 form with depth stages in flight
+int col_workgroups_per_cu(int fp32, int depth);
 // bgrid64 / bgrid32 from the occupancy of the update kernels (device current)
 void set_resident_grids(BatchArgs &a);
 

@@ -380,59 +380,72 @@ __device__ inline void publish_groups(const double (&v)[K][VEC], double *partial
 }
 
 // ---------------------------------------------------------------------------
-// Column-sweep multi-RHS operator (FP32 form; every body a box of the
-// 27-point pattern).  A work item is a footprint of kColFX x kColFY nodes of
-// one body over a run of z planes.  The workgroup streams up the run one
-// staged plane at a time (the footprint and its one-node halo: kColPL rows,
-// 64 values apart whatever S is): a lane reads the 3 x 3 neighbourhood of
-// its column in plane P once and adds it to the three rows it touches, the
+// Column-sweep multi-RHS operator (every body a box of the 27-point
+// pattern).  A work item is a footprint of kColFX x kColFY nodes of one body
+// over a run of z planes.  The workgroup streams up the run one staged plane
+// at a time (the footprint and its one-node halo: kColPL rows of 256 bytes
+// whatever S is): a lane reads the 3 x 3 neighbourhood of its column in
+// plane P once and adds it to the three rows it touches, the
 // neighbour-below part (dz = -1) of row P + 1, the dz = 0 part of row P and
 // the dz = +1 part of row P - 1, which is then complete.  Each row so gets
 // its stencil values in stencil order (dz, then dy, then dx), which is the
 // CSR order of its entries, with exact zeros where a neighbour or entry is
-// missing: the same sums, rounded the same way, as the tiled product (K and
-// R apart, then K + h R).  Each staged value is read from LDS once per
-// lane instead of three times, each staged row is copied once per item
-// instead of once per tile that touches it, and each matrix entry is found
-// from its stencil position instead of a stored column.  The planes (and the
-// rows' stencil records) arrive by direct global-to-LDS copies that hold no
-// registers, kColDepth stages ahead, waited for by count one stage at a time.
+// missing (K and R apart, then K + h R).  Each staged value is read from LDS
+// once per lane instead of three times, each staged row is copied once per
+// item instead of once per tile that touches it, and each matrix entry is
+// found from its stencil position instead of a stored column.  The planes
+// (and the rows' stencil records) arrive by direct global-to-LDS copies that
+// hold no registers, D stages ahead, waited for by count one stage at a time.
 //
-// Lane mapping as in the tiled product: a lane owns four consecutive
-// scenarios of a row, a wave the four rows w 4 .. w 4 + 3 of the plane.
+// A staged row is 64 FP32 or 32 FP64 values, so in FP64 an item is swept
+// twice, once per half of the scenarios (by neighbouring workgroups of one
+// XCD: the second reads the item's records from L2).  A lane owns the 16
+// bytes of four (FP32) or two (FP64) consecutive scenarios of a row, a wave
+// the four rows w 4 .. w 4 + 3 of the plane.
 // ---------------------------------------------------------------------------
-constexpr int kColPlaneUnits = kColPL * 16;                     // 16-byte units of a plane
-constexpr int kColRecUnits = kColRows * kStencil * 4 / 16;      // of a K (or R) record
-constexpr int kColRecSlot = (2 * kColRecUnits + 63) / 64 * 64;  // K, R and the copy tail
-static_assert(kColPlaneUnits % 64 == 0, "a plane is whole wave-wide copies");
-static_assert(kColRows == 16 && kBlock == 256, "four waves of four rows");
-// Wave-wide copies per plane: the staged rows in UB-byte units (16 when a row
-// of S values is a multiple of 16 bytes, else 4), then the records in 16-byte
-// units; copy j is issued by wave j % 4, so wave 0 issues C0 and the others C1
-template <int UB>
+template <typename V>
+struct ColGeom {
+  static constexpr int VB = (int)sizeof(V);
+  static constexpr int VEC = 16 / VB;  // scenarios per lane
+  static constexpr int SW = 256 / VB;  // scenarios per workgroup (one staged row)
+  static constexpr int H = 64 / SW;    // workgroups per item
+  static constexpr int PlaneUnits = kColPL * 16;                  // 16-byte units of a plane
+  static constexpr int RecUnits = kColRows * kStencil * VB / 16;  // of a K (or R) record
+  static constexpr int RecSlot = (2 * RecUnits + 63) / 64 * 64;   // K, R and the copy tail
+  static_assert(kColRows == 16 && kBlock == 256, "four waves of four rows");
+};
+// Wave-wide copies per stage: the staged rows in UB-byte units (16 when a
+// row of S values is a multiple of 16 bytes, else 4), then the records in
+// 16-byte units; copy j is issued by wave j % 4, so wave w issues C<w> of
+// them (C0 the most)
+template <typename V, int UB>
 struct ColCopies {
-  static constexpr int X = kColPlaneUnits * 16 / UB / 64;
-  static constexpr int N = X + kColRecSlot / 64;
-  static constexpr int C0 = (N + 3) / 4, C1 = N / 4;
+  static constexpr int X = ColGeom<V>::PlaneUnits * 16 / UB / 64;
+  static constexpr int N = X + ColGeom<V>::RecSlot / 64;
+  template <int W>
+  static constexpr int C = (N - W + 3) / 4;
+  static constexpr int C0 = C<0>;
 };
 
 // Stage s = staged plane s + 1 (read in step s) and the stencil record of
 // plane s + 2 (read in steps s .. s + 2).  With D stages in flight beyond
 // the one being read: D + 1 plane slots and D + 3 record slots.
-template <int D>
+template <typename V, int D>
 struct ColLds {
   static constexpr int NX = D + 1, NR = D + 3;
-  uint4 x[NX][kColPlaneUnits];
-  uint4 rec[NR][kColRecSlot];
+  uint4 x[NX][ColGeom<V>::PlaneUnits];
+  uint4 rec[NR][ColGeom<V>::RecSlot];
 };
 // workgroups per CU that the ring leaves room for (160 KB of LDS); four only
-// with 16-byte copies (the 4-byte form needs more than 128 registers)
-template <int D, int UB = 16>
+// for FP32 with 16-byte copies, at most two for FP64 with 4-byte copies (the
+// other forms need more than 128, that one more than 168 registers)
+template <typename V, int D, int UB = 16>
 struct ColOcc {
-  static constexpr int W = UB == 16 && 4 * sizeof(ColLds<D>) + 1024 <= 160 * 1024 ? 4
-                           : 3 * sizeof(ColLds<D>) + 768 <= 160 * 1024 ? 3
-                           : 2 * sizeof(ColLds<D>) + 512 <= 160 * 1024 ? 2
-                                                                        : 1;
+  static constexpr size_t B = sizeof(ColLds<V, D>);
+  static constexpr int W = sizeof(V) == 4 && UB == 16 && 4 * B + 1024 <= 160 * 1024 ? 4
+                           : !(sizeof(V) == 8 && UB == 4) && 3 * B + 768 <= 160 * 1024 ? 3
+                           : 2 * B + 512 <= 160 * 1024                                 ? 2
+                                                                                       : 1;
 };
 
 struct ColItem {
@@ -449,28 +462,59 @@ __device__ inline ColItem col_item(const BatchOp &op, int t) {
                  (unsigned)v[10], (unsigned)v[11]};
 }
 
+// the stencil records and the vectors of the form
+template <typename V>
+struct ColVec;
+template <>
+struct ColVec<float> {
+  using V16 = float4;
+  __device__ static const float *rec(const BatchOp &op) { return op.kcol32; }
+  __device__ static const float *rrec(const BatchOp &op) { return op.rcol32; }
+  __device__ static const float *p(const BatchArgs &a) { return a.p32; }
+  __device__ static float *q(const BatchArgs &a) { return a.q32; }
+  __device__ static void split(const float4 &v, float (&o)[4]) {
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  }
+};
+template <>
+struct ColVec<double> {
+  using V16 = double2;
+  __device__ static const double *rec(const BatchOp &op) { return op.kcol64; }
+  __device__ static const double *rrec(const BatchOp &op) { return op.rcol64; }
+  __device__ static const double *p(const BatchArgs &a) { return a.p; }
+  __device__ static double *q(const BatchArgs &a) { return a.q; }
+  __device__ static void split(const double2 &v, double (&o)[2]) {
+    o[0] = v.x;
+    o[1] = v.y;
+  }
+};
+
 // Wave w's copies of the stages of one item: copy j = w + 4 i of a stage
 // moves LDS units [64 j', 64 j' + 64) of the staged plane (j' = j < X) or
 // of the record slot (j' = j - X).  What a lane copies depends on the stage
 // only through the plane and record indices, so the per-lane parts (halo row
 // offset, inside flag, record unit) are formed once per item; issuing a
-// stage then costs a few instructions per copy.  Every lane copies from a
-// valid address: halo rows outside the body and the values past S of a row
-// come from 64 zeros; the records' tail repeats the first K unit.
-template <int UB, int D>
+// stage then costs a few instructions per copy.  Every lane copies from
+// inside a buffer: halo rows outside the body and the values past S of a
+// row come from the row of zeros after the direction; the records' tail
+// repeats the first K unit.
+template <typename V, int UB, int D>
 struct ColIssue {
-  using CC = ColCopies<UB>;
-  static constexpr int UPH = 64 * 4 / UB;  // units per staged row (64 values)
-  static constexpr unsigned XB = kColPlaneUnits * 16, RB = kColRecSlot * 16;  // slot bytes
-  static constexpr unsigned RECB = kColRecUnits * 16;                         // record bytes
-  // buffer resources: x (the FP32 direction, which ends in a row of zeros)
-  // and the records (K, then R); every copy reads inside them
+  using G = ColGeom<V>;
+  using CC = ColCopies<V, UB>;
+  static constexpr int UPH = 256 / UB;  // units per staged row
+  static constexpr unsigned XB = G::PlaneUnits * 16, RB = G::RecSlot * 16;  // slot bytes
+  static constexpr unsigned RECB = G::RecUnits * 16;                        // record bytes
+  // buffer resources: x (the direction, which ends in a row of zeros) and
+  // the records (K, then R)
   __amdgpu_buffer_rsrc_t rx, rrec;
-  unsigned xoff[CC::C0];  // the lane's unit: plane-0 byte offset (x copies)
-  unsigned zoff[CC::C0];  // its offset in the row of zeros
-  bool xin[CC::C0];       // halo row inside the body, unit inside the row
-  unsigned roff;          // record copy: byte offset of the lane's unit in a record
-  int rpart;              // 0: K unit, 1: R unit, 2: tail
+  unsigned off0[CC::C0];  // x copy: the lane's unit at plane 0; record copy: in a record
+  unsigned zoff[CC::C0];  // x copy: its offset in the row of zeros
+  bool xin[CC::C0];       // x copy: halo row inside the body, unit inside the row
+  int rpart[CC::C0];      // record copy: 0 K unit, 1 R unit, 2 tail
   unsigned pstride;       // bytes between planes of x
   unsigned rbase;         // byte offset of the R records
   int w;
@@ -481,33 +525,40 @@ struct ColIssue {
   unsigned long long rbits;  // R plane bits of the records not issued yet
 
   // ring slots: stage z0 - 2 + i in plane slot i mod NX, record plane z0 + i
-  // in record slot i mod NR
-  __device__ __forceinline__ void init(const BatchArgs &a, const ColItem &it, int wave) {
+  // in record slot i mod NR; hs = this workgroup's first scenario
+  __device__ __forceinline__ void init(const BatchArgs &a, const ColItem &it, int wave, int hs) {
     w = wave;
-    const int S = a.S, lane = threadIdx.x & 63, upr = S * 4 / UB;
-    const unsigned zrow = (unsigned)(a.N * S) * 4u;  // the row of zeros after p
-    rx = __builtin_amdgcn_make_buffer_rsrc((void *)a.p32, 0, (int)(zrow + kColZeroRow * 4),
-                                           0x00020000);
-    rrec = __builtin_amdgcn_make_buffer_rsrc((void *)a.op.kcol32, 0, (int)a.op.col_rec_bytes,
-                                             0x00020000);
-    rbase = (unsigned)((a.op.rcol32 - a.op.kcol32) * 4);
-    pstride = (unsigned)it.nx * (unsigned)it.ny * (unsigned)upr * (unsigned)UB;
+    const int S = a.S, lane = threadIdx.x & 63;
+    const int upr = (min(S - hs, G::SW) * G::VB) / UB;  // units of the row in this half
+    const unsigned zrow = (unsigned)(a.N * S) * (unsigned)G::VB;  // the row of zeros
+    rx = __builtin_amdgcn_make_buffer_rsrc((void *)ColVec<V>::p(a), 0,
+                                           (int)(zrow + kColZeroRow * G::VB), 0x00020000);
+    rrec = __builtin_amdgcn_make_buffer_rsrc((void *)ColVec<V>::rec(a.op), 0,
+                                             (int)a.op.col_rec_bytes, 0x00020000);
+    rbase = (unsigned)((ColVec<V>::rrec(a.op) - ColVec<V>::rec(a.op)) * G::VB);
+    pstride = (unsigned)it.nx * (unsigned)it.ny * (unsigned)S * (unsigned)G::VB;
 #pragma unroll
     for (int i = 0; i < CC::C0; ++i) {
       const int j = w + 4 * i;
-      const int u = (j < CC::X ? j : 0) * 64 + lane, hs = u / UPH, part = u % UPH;
-      const int hx = hs % (kColFX + 2), hy = hs / (kColFX + 2);
-      const int gx = it.x0 - 1 + hx, gy = it.y0 - 1 + hy;
-      xin[i] = ((unsigned)gx < (unsigned)it.nx) & ((unsigned)gy < (unsigned)it.ny) & (part < upr);
-      // (32-bit offsets: the column sweep runs only on vectors below 2 GB)
-      const unsigned row = xin[i] ? (unsigned)(it.off + gx + it.nx * gy) : 0u;
-      xoff[i] = (row * (unsigned)upr + (unsigned)part) * (unsigned)UB;
-      zoff[i] = zrow + (unsigned)(part * UB);
+      if (j < CC::X) {
+        const int u = j * 64 + lane, hr = u / UPH, part = u % UPH;
+        const int hx = hr % (kColFX + 2), hy = hr / (kColFX + 2);
+        const int gx = it.x0 - 1 + hx, gy = it.y0 - 1 + hy;
+        xin[i] =
+            ((unsigned)gx < (unsigned)it.nx) & ((unsigned)gy < (unsigned)it.ny) & (part < upr);
+        // (32-bit offsets: the column sweep runs only on vectors below 2 GB)
+        const unsigned row = xin[i] ? (unsigned)(it.off + gx + it.nx * gy) : 0u;
+        off0[i] = (row * (unsigned)S + (unsigned)hs) * (unsigned)G::VB + (unsigned)(part * UB);
+        zoff[i] = zrow + (unsigned)(part * UB);
+        rpart[i] = 0;
+      } else {
+        const int u = (j - CC::X) * 64 + lane;
+        rpart[i] = u < G::RecUnits ? 0 : (u < 2 * G::RecUnits ? 1 : 2);
+        off0[i] = (unsigned)((rpart[i] == 0 ? u : (rpart[i] == 1 ? u - G::RecUnits : 0)) * 16);
+        zoff[i] = 0;
+        xin[i] = false;
+      }
     }
-    const int jr = w + 4 * ((CC::X - w + 3) / 4);  // this wave's record copy
-    const int u = (jr - CC::X) * 64 + lane;
-    rpart = u < kColRecUnits ? 0 : (u < 2 * kColRecUnits ? 1 : 2);
-    roff = (unsigned)((rpart == 0 ? u : (rpart == 1 ? u - kColRecUnits : 0)) * 16);
     P = it.z0 - 1;
     R = it.z0;
     kr = it.kb;
@@ -520,25 +571,25 @@ struct ColIssue {
   // Issue the next stage: plane P (zeros outside the body and past the
   // run's top neighbour z1) and the record of plane R (the run's first record
   // past the run), then step to the stage after it.
-  __device__ __forceinline__ void issue(const ColItem &it, ColLds<D> &L) {
+  __device__ __forceinline__ void issue(const ColItem &it, ColLds<V, D> &L) {
     const bool pin = (P >= 0) & (P < it.nz) & (P <= it.z1);
     const bool inrun = R < it.z1;
     const bool hasr = inrun & ((rbits & 1ull) != 0);
+    const unsigned ko = (unsigned)(inrun ? kr : it.kb) * RECB;
+    const unsigned ro = rbase + (unsigned)(inrun ? rr : it.rb) * RECB;
     char *lx = reinterpret_cast<char *>(&L.x[0][0]) + xso;
+    char *lr = reinterpret_cast<char *>(&L.rec[0][0]) + rso;
 #pragma unroll
     for (int i = 0; i < CC::C0; ++i) {
       const int j = w + 4 * i;  // wave-uniform
       if (j >= CC::N) break;
       if (j < CC::X) {
-        const unsigned off = (pin & xin[i]) ? xoff[i] + pbase : zoff[i];
+        const unsigned off = (pin & xin[i]) ? off0[i] + pbase : zoff[i];
         auto *dst = (__attribute__((address_space(3))) void *)(lx + j * 64 * UB);
         if constexpr (UB == 16) __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, dst, 16, off, 0, 0, 0);
         else __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, dst, 4, off, 0, 0, 0);
       } else {
-        const unsigned ko = (unsigned)(inrun ? kr : it.kb) * RECB;
-        const unsigned ro = rbase + (unsigned)(inrun ? rr : it.rb) * RECB;
-        const unsigned off = (((rpart == 1) & hasr) ? ro : ko) + roff;
-        char *lr = reinterpret_cast<char *>(&L.rec[0][0]) + rso;
+        const unsigned off = (((rpart[i] == 1) & hasr) ? ro : ko) + off0[i];
         __builtin_amdgcn_raw_ptr_buffer_load_lds(
             rrec, (__attribute__((address_space(3))) void *)(lr + (j - CC::X) * 1024), 16, off, 0,
             0, 0);
@@ -546,12 +597,12 @@ struct ColIssue {
     }
     P += 1;
     pbase += pstride;
-    xso = xso + XB == ColLds<D>::NX * XB ? 0u : xso + XB;
+    xso = xso + XB == ColLds<V, D>::NX * XB ? 0u : xso + XB;
     rr += hasr ? 1 : 0;
     kr += 1;
     rbits >>= 1;
     R += 1;
-    rso = rso + RB == ColLds<D>::NR * RB ? 0u : rso + RB;
+    rso = rso + RB == ColLds<V, D>::NR * RB ? 0u : rso + RB;
   }
 };
 
@@ -584,9 +635,30 @@ __device__ __forceinline__ void col_wait_plane(int k) {
     else col_wait_plane<C, ST, D, K + 1>(k);
   }
 }
+// the same for wave w (wave-uniform) issuing CC::C<w> copies per stage
+template <typename CC, int ST, int D>
+__device__ __forceinline__ void col_wait_wave(int w, int k) {
+  switch (w) {
+    case 0: col_wait_plane<CC::template C<0>, ST, D>(k); break;
+    case 1: col_wait_plane<CC::template C<1>, ST, D>(k); break;
+    case 2: col_wait_plane<CC::template C<2>, ST, D>(k); break;
+    default: col_wait_plane<CC::template C<3>, ST, D>(k); break;
+  }
+}
+// Wait until wave w's copies of the first of the D + 1 stages issued have
+// landed.
+template <typename CC, int D>
+__device__ __forceinline__ void col_wait_first(int w) {
+  switch (w) {
+    case 0: col_wait<D * CC::template C<0>>(); break;
+    case 1: col_wait<D * CC::template C<1>>(); break;
+    case 2: col_wait<D * CC::template C<2>>(); break;
+    default: col_wait<D * CC::template C<3>>(); break;
+  }
+}
 
 // acc[q] += sum over the nine positions j = 3 dy + dx of one plane (in
-// order) of c[j] xv[j][q]
+// order) of c[j] xv[j][q] (q over the lane's scenarios)
 __device__ __forceinline__ void col_part(const float *c, const float4 (&xv)[9], float (&acc)[4]) {
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
@@ -597,7 +669,15 @@ __device__ __forceinline__ void col_part(const float *c, const float4 (&xv)[9], 
     acc[3] = fma_t(w, xv[j].w, acc[3]);
   }
 }
-
+__device__ __forceinline__ void col_part(const double *c, const double2 (&xv)[9],
+                                         double (&acc)[2]) {
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    const double w = c[j];
+    acc[0] = fma_t(w, xv[j].x, acc[0]);
+    acc[1] = fma_t(w, xv[j].y, acc[1]);
+  }
+}
 // CG vectors and stored operator values of the FP64 (double) or FP32 (float) form
 template <typename V>
 struct BV;
@@ -1079,94 +1159,121 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_a(BatchArgs a, int m, double dt
 }
 
 
+// The column sweep's partial p.q: as publish_groups_in, with the lane
+// mapping of the sweep (a lane's VEC scenarios start at s0; 16 lanes a row)
+// and exact zeros for the scenarios of the other half.
+template <typename V>
+__device__ inline void publish_col(const double (&v)[ColGeom<V>::VEC], double *partial, int grid,
+                                   int S, int s0, double *sh) {
+  constexpr int VEC = ColGeom<V>::VEC;
+  const int j = threadIdx.x >> 4;  // the lane's row of the workgroup
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) {
+    sh[j * 64 + s0 + i] = v[i];
+    if constexpr (ColGeom<V>::H == 2) sh[j * 64 + (s0 ^ 32) + i] = 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x < (unsigned)S) {
+    double acc = 0.0;
+    for (int r = 0; r < kColRows; ++r) acc += sh[r * 64 + threadIdx.x];
+    partial[(size_t)threadIdx.x * grid + blockIdx.x] = acc;
+  }
+}
+
 // (a) in the column sweep: q = M p + dtau (K + h R) p and the partial p.q,
-// one item per workgroup, XCD x taking the x-th eighth of the items (their
-// footprints are neighbours: shared halo rows stay in that XCD's L2).  Where
-// a row of S values is a multiple of 16 bytes, a lane stores its four values
-// at once (the values of idle scenarios too, which no later step reads);
-// otherwise each value apart, only where its scenario is on.
-template <int TIMING, int UB, int D>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ColOcc<D, UB>::W)))
+// one item (or half an item) per workgroup, XCD x taking the x-th eighth of
+// the work (neighbouring footprints share halo rows, and the two halves of
+// an item its records, in that XCD's L2).  Where a row of S values is a
+// multiple of 16 bytes, a lane stores its 16 bytes at once (the values of
+// idle scenarios too, which no later step reads); otherwise each value
+// apart, only where its scenario is on.
+template <int TIMING, typename V, int UB, int D>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ColOcc<V, D, UB>::W)))
 void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
-  using CC = ColCopies<UB>;
-  constexpr int ST = UB == 16 ? 1 : 4;  // stores per step
-  constexpr int NX = ColLds<D>::NX, NR = ColLds<D>::NR;
-  __shared__ ColLds<D> L;
+  using G = ColGeom<V>;
+  using CC = ColCopies<V, UB>;
+  using V16 = typename ColVec<V>::V16;
+  constexpr int VEC = G::VEC, VB = G::VB;
+  constexpr int ST = UB == 16 ? 1 : VEC;  // stores per step
+  constexpr int NX = ColLds<V, D>::NX, NR = ColLds<V, D>::NR;
+  __shared__ ColLds<V, D> L;
   const int S = a.S, lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lr = lane >> 4, s0 = (lane & 15) * 4;
-  float h[4];
-  double v[1][4] = {};
-  bool on[4], any = false;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int s = s0 + i;
-    on[i] = TIMING ? s < S : lane_on(a.sc, s, S);
-    const float hs = (float)lane_h(a, s);
-    h[i] = on[i] ? hs : 0.0f;
-    any |= on[i];
-  }
-  const float dt = (float)dtau;
-  const __amdgpu_buffer_rsrc_t qres =
-      __builtin_amdgcn_make_buffer_rsrc(a.q32, 0, (int)(a.N * S * 4), 0x00020000);
-  const int T = a.op.ncol_items, xcd = blockIdx.x % kXcd, local = blockIdx.x / kXcd;
+  const int T = a.op.ncol_items * G::H, xcd = blockIdx.x % kXcd, local = blockIdx.x / kXcd;
   const int t = (int)((int64_t)T * xcd / kXcd) + local;
   const bool has = t < (int)((int64_t)T * (xcd + 1) / kXcd);
-  if (__syncthreads_or(any) && has) {
-    const ColItem it = col_item(a.op, t);
+  const int hs = (G::H == 1 ? 0 : t % G::H) * G::SW;  // first scenario of the half
+  const int lr = lane >> 4, s0 = hs + (lane & 15) * VEC;
+  V h[VEC];
+  double v[VEC] = {};
+  bool on[VEC], any = false;
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) {
+    const int s = s0 + i;
+    on[i] = has && (TIMING ? s < S : lane_on(a.sc, s, S));
+    const V hv = (V)lane_h(a, s);
+    h[i] = on[i] ? hv : V(0);
+    any |= on[i];
+  }
+  const V dt = (V)dtau;
+  const __amdgpu_buffer_rsrc_t qres = __builtin_amdgcn_make_buffer_rsrc(
+      ColVec<V>::q(a), 0, (int)(a.N * S * VB), 0x00020000);
+  if (__syncthreads_or(any)) {
+    const ColItem it = col_item(a.op, G::H == 1 ? t : t / G::H);
     const int r = w * 4 + lr, lx = r % kColFX, ly = r / kColFX;
-    const int lb = (ly * (kColFX + 2) + lx) * 64 + s0;  // the row's (-1, -1) halo row
+    // the row's (-1, -1) halo row, in values of the staged rows
+    const int lb = (ly * (kColFX + 2) + lx) * G::SW + (lane & 15) * VEC;
     const bool rok = (it.x0 + lx < it.nx) & (it.y0 + ly < it.ny);
     // Step z reads plane z + 1 and completes row z; steps z0 - 2 and z0 - 1
     // only start rows z0 and z0 + 1 (what they add to rows below z0 is never
     // used).
     const int zb = it.z0 - 2;
-    ColIssue<UB, D> ci;
-    ci.init(a, it, w);
+    ColIssue<V, UB, D> ci;
+    ci.init(a, it, w, hs);
     for (int q = 0; q <= D; ++q) ci.issue(it, L);  // stages z0 - 2 .. z0 - 2 + D
-    if (w == 0) col_wait<D * CC::C0>();
-    else col_wait<D * CC::C1>();
+    col_wait_first<CC, D>(w);
     col_barrier();
     // K and R sums of rows z, z + 1, z + 2 (a: z, b: z + 1, c: z + 2)
-    float ka[4] = {}, kb4[4] = {}, ra[4] = {}, rb4[4] = {};
-    float4 own = make_float4(0.f, 0.f, 0.f, 0.f);  // x of row z (plane z's centre)
+    V ka[VEC] = {}, kb4[VEC] = {}, ra[VEC] = {}, rb4[VEC] = {};
+    V16 own = {};  // x of row z (plane z's centre)
     // ring slots as ColIssue lays them out: plane z + 1 (stage z) in plane
     // slot (z - zb) mod NX, the record of plane z in slot (z - z0) mod NR
-    constexpr unsigned XB = ColIssue<UB, D>::XB, RB = ColIssue<UB, D>::RB;
+    constexpr unsigned XB = ColIssue<V, UB, D>::XB, RB = ColIssue<V, UB, D>::RB;
     auto next_r = [&](unsigned o) { return o + RB == NR * RB ? 0u : o + RB; };
     unsigned xro = 0, r0o = (NR - 2) * RB;  // step zb: plane slot 0, record z0 - 2
-    const char *lxb = reinterpret_cast<const char *>(&L.x[0][0]) + lb * 4;
-    const char *lrb = reinterpret_cast<const char *>(&L.rec[0][0]) + r * kStencil * 4;
+    const char *lxb = reinterpret_cast<const char *>(&L.x[0][0]) + lb * VB;
+    const char *lrb = reinterpret_cast<const char *>(&L.rec[0][0]) + r * kStencil * VB;
     for (int z = zb; z < it.z1; ++z) {
-      const float *xs = reinterpret_cast<const float *>(lxb + xro);
-      float4 xv[9];
+      const V *xs = reinterpret_cast<const V *>(lxb + xro);
+      V16 xv[9];
 #pragma unroll
       for (int j = 0; j < 9; ++j)
-        xv[j] = *reinterpret_cast<const float4 *>(xs + ((j / 3) * (kColFX + 2) + j % 3) * 64);
+        xv[j] = *reinterpret_cast<const V16 *>(xs + ((j / 3) * (kColFX + 2) + j % 3) * G::SW);
       const unsigned r1o = next_r(r0o), r2o = next_r(r1o);
-      const float *c2 = reinterpret_cast<const float *>(lrb + r2o);
-      const float *c1 = reinterpret_cast<const float *>(lrb + r1o);
-      const float *c0 = reinterpret_cast<const float *>(lrb + r0o);
+      const V *c2 = reinterpret_cast<const V *>(lrb + r2o);
+      const V *c1 = reinterpret_cast<const V *>(lrb + r1o);
+      const V *c0 = reinterpret_cast<const V *>(lrb + r0o);
       constexpr int RO = kColRows * kStencil;  // the R record after the K record
-      float kc[4] = {}, rc[4] = {};
+      V kc[VEC] = {}, rc[VEC] = {};
       col_part(c2, xv, kc);       // row z + 2: dz = -1
       col_part(c1 + 9, xv, kb4);  // row z + 1: dz = 0
       col_part(c0 + 18, xv, ka);  // row z: dz = +1
-      const float m2 = c2[kStencil - 1], m1 = c1[kStencil - 1], m0 = c0[kStencil - 1];
-      if (m2 < 0.0f) col_part(c2 + RO, xv, rc);  // rows with R entries: mass < 0
-      if (m1 < 0.0f) col_part(c1 + RO + 9, xv, rb4);
-      if (m0 < 0.0f) col_part(c0 + RO + 18, xv, ra);
+      const V m2 = c2[kStencil - 1], m1 = c1[kStencil - 1], m0 = c0[kStencil - 1];
+      if (m2 < V(0)) col_part(c2 + RO, xv, rc);  // rows with R entries: mass < 0
+      if (m1 < V(0)) col_part(c1 + RO + 9, xv, rb4);
+      if (m0 < V(0)) col_part(c0 + RO + 18, xv, ra);
       // row z complete
-      const float ow[4] = {own.x, own.y, own.z, own.w};
-      const float mass = fabsf(m0);
+      V ow[VEC];
+      ColVec<V>::split(own, ow);
+      const V mass = fabs(m0);
       const bool row_in = rok & (z >= it.z0);
       const unsigned row = (unsigned)(it.off + it.x0 + lx + it.nx * (it.y0 + ly + it.ny * z));
-      float qv[4];
+      V qv[VEC];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < VEC; ++q) {
         // (explicit fused forms, as in the tiled product, so that no
         // instantiation contracts them differently)
-        const float y = m0 < 0.0f ? fma_t(h[q], ra[q], ka[q]) : ka[q];
+        const V y = m0 < V(0) ? fma_t(h[q], ra[q], ka[q]) : ka[q];
         qv[q] = fma_t(mass, ow[q], dt * y);
       }
       // p.q over the run's rows (wave-uniform test: the rows below the run
@@ -1174,38 +1281,44 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
       // exact zero (rows outside the body have zero records, so finite q)
       if (z >= it.z0) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float om = (rok & on[q]) ? ow[q] : 0.0f;
-          v[0][q] = fma_t((double)om, (double)qv[q], v[0][q]);
+        for (int q = 0; q < VEC; ++q) {
+          const V om = (rok & on[q]) ? ow[q] : V(0);
+          v[q] = fma_t((double)om, (double)qv[q], v[q]);
         }
       }
       // a fixed number of stores per step whatever the masks (a masked
       // store's offset lies past the buffer, so it is dropped)
-      const unsigned off = (row * (unsigned)S + (unsigned)s0) * 4u;
+      const unsigned off = (row * (unsigned)S + (unsigned)s0) * (unsigned)VB;
       if constexpr (ST == 1) {
         typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-        const u32x4 val = {__float_as_uint(qv[0]), __float_as_uint(qv[1]), __float_as_uint(qv[2]),
-                           __float_as_uint(qv[3])};
+        u32x4 val;
+        __builtin_memcpy(&val, qv, 16);
         const bool st = row_in & (s0 < S);
         __builtin_amdgcn_raw_buffer_store_b128(val, qres, (int)(off | ((unsigned)!st << 31)), 0, 0);
       } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < VEC; ++q) {
           const bool st = row_in & on[q];
-          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(qv[q]), qres,
-                                                (int)((off + 4u * q) | ((unsigned)!st << 31)), 0, 0);
+          const int o = (int)((off + (unsigned)(VB * q)) | ((unsigned)!st << 31));
+          if constexpr (VB == 4) {
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(qv[q]), qres, o, 0, 0);
+          } else {
+            typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+            u32x2 val;
+            __builtin_memcpy(&val, &qv[q], 8);
+            __builtin_amdgcn_raw_buffer_store_b64(val, qres, o, 0, 0);
+          }
         }
       }
       own = xv[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < VEC; ++q) {
         ka[q] = kb4[q];
         kb4[q] = kc[q];
         ra[q] = rb4[q];
         rb4[q] = rc[q];
       }
-      if (w == 0) col_wait_plane<CC::C0, ST, D>(min(z - zb, D - 1));
-      else col_wait_plane<CC::C1, ST, D>(min(z - zb, D - 1));
+      col_wait_wave<CC, ST, D>(w, min(z - zb, D - 1));
       col_barrier();  // stage z + 1 landed; plane z + 1 and the record of z free
       ci.issue(it, L);  // stage z + 1 + D
       xro = xro + XB == NX * XB ? 0u : xro + XB;
@@ -1213,7 +1326,7 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
     }
   }
   __syncthreads();  // every copy landed before the LDS is reused
-  publish_groups_in<1, 4, 4>(v, a.partial, gridDim.x, S, reinterpret_cast<double *>(L.x[0]));
+  publish_col<V>(v, a.partial, gridDim.x, S, s0, reinterpret_cast<double *>(L.x[0]));
 }
 
 // ---------------------------------------------------------------------------
@@ -1726,13 +1839,16 @@ void blaunch_quad_resid(const BatchArgs &a, int k, hipStream_t st) {
   kb_resid_reduce<<<1, 64 * kRedWaves, 0, st>>>(a, k);
 }
 
-// The column sweep runs the FP32 operator (its three staged planes of 64 FP64
-// values would leave one workgroup per CU); FP64 keeps the tiles.
-int col_workgroups_per_cu() { return ColOcc<kColDepth>::W; }
+int col_workgroups_per_cu(int fp32, int depth) {
+  if (fp32) return depth == 1 ? ColOcc<float, 1>::W : ColOcc<float, kColDepth>::W;
+  return depth == 1 ? ColOcc<double, 1>::W : ColOcc<double, kColDepth>::W;
+}
 
+// the column sweep runs the operator of the context's form (its records hold
+// that form's values)
 template <typename V>
 static bool use_columns(const BatchArgs &a) {
-  return sizeof(V) == 4 && a.op.ncol_items > 0;
+  return a.op.ncol_items > 0 && (sizeof(V) == 4) == (a.fp32 != 0);
 }
 
 // workgroups of the operator launch
@@ -1742,26 +1858,24 @@ static int pcg_a_grid(const BatchArgs &a) {
 }
 
 // the column sweep with D stages in flight (any D gives the same results)
-template <int D>
+template <typename V, int D>
 static void launch_col(const BatchArgs &a, int timing, int g, int m, double dtau, hipStream_t st) {
-  if (vec16<float>(a)) {
-    if (timing) kb_pcg_a_col<1, 16, D><<<g, kBlock, 0, st>>>(a, m, dtau);
-    else kb_pcg_a_col<0, 16, D><<<g, kBlock, 0, st>>>(a, m, dtau);
+  if (vec16<V>(a)) {
+    if (timing) kb_pcg_a_col<1, V, 16, D><<<g, kBlock, 0, st>>>(a, m, dtau);
+    else kb_pcg_a_col<0, V, 16, D><<<g, kBlock, 0, st>>>(a, m, dtau);
   } else {
-    if (timing) kb_pcg_a_col<1, 4, D><<<g, kBlock, 0, st>>>(a, m, dtau);
-    else kb_pcg_a_col<0, 4, D><<<g, kBlock, 0, st>>>(a, m, dtau);
+    if (timing) kb_pcg_a_col<1, V, 4, D><<<g, kBlock, 0, st>>>(a, m, dtau);
+    else kb_pcg_a_col<0, V, 4, D><<<g, kBlock, 0, st>>>(a, m, dtau);
   }
 }
 
 template <typename V>
 static void launch_pcg_a(const BatchArgs &a, int timing, int m, double dtau, hipStream_t st) {
-  if constexpr (sizeof(V) == 4) {
-    if (use_columns<V>(a)) {
-      const int g = pcg_a_grid<V>(a);
-      if (a.col_depth == 1) launch_col<1>(a, timing, g, m, dtau, st);
-      else launch_col<kColDepth>(a, timing, g, m, dtau, st);
-      return;
-    }
+  if (use_columns<V>(a)) {
+    const int g = pcg_a_grid<V>(a);
+    if (a.col_depth == 1) launch_col<V, 1>(a, timing, g, m, dtau, st);
+    else launch_col<V, kColDepth>(a, timing, g, m, dtau, st);
+    return;
   }
   const int g = tgrid<V>(a);
   if (vec16<V>(a)) {
@@ -1874,7 +1988,8 @@ void blaunch_tune(const BatchArgs &a, int which, int reps, hipStream_t st) {
   while (m <= a.M && a.dtau_h[m] == 0.0) ++m;
   const double dtau = a.dtau_h[m];
   for (int i = 0; i < reps; ++i) {
-    if (which == 0) launch_pcg_a<float>(a, 1, m, dtau, st);
+    if (which == 0 && !a.fp32) launch_pcg_a<double>(a, 1, m, dtau, st);
+    else if (which == 0) launch_pcg_a<float>(a, 1, m, dtau, st);
     else if (which == 1) launch_pcg_b<float>(a, m, dtau, st);
     else launch_pcg_c<float>(a, m, dtau, 0, st);
   }

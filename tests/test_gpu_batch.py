@@ -205,15 +205,17 @@ def test_ensemble_7p5mm_fp32_refine_sampled():
 
 
 def test_node_block_tiles_equal_row_run_tiles():
-    """Box bodies are tiled by 3 x 3 x 3 node blocks, other operators by runs
-    of consecutive rows.  A stored zero outside the 27-point pattern (it adds
-    no arithmetic) turns the stand into a general operator, so the same
-    problem runs through both tilings: every row keeps its entry order, so
-    the results must agree bitwise."""
+    """With stored values (OP_VALUES), box bodies are tiled by 3 x 3 x 3 node
+    blocks, other operators by runs of consecutive rows.  A stored zero
+    outside the 27-point pattern (it adds no arithmetic) turns the stand into
+    a general operator, so the same problem runs through both tilings: every
+    row keeps its entry order, so the results must agree bitwise."""
+    import paper_1707_03581_amd as m
     from dataclasses import replace
     pb = small_machine()
     mem = members_for(pb, 5, seed0=1700)
-    blocks, _, _ = run_batch(pb, mem, 2)
+    blocks, st, _ = run_batch(pb, mem, 2, op_form=m.OP_VALUES)
+    assert st["col_depth"] == 0
     b = pb.bodies[0]
     n = b.n
     rp = b.rowptr.copy()
@@ -222,9 +224,36 @@ def test_node_block_tiles_equal_row_run_tiles():
     K = np.insert(b.K, int(b.rowptr[1]), 0.0)
     R = np.insert(b.R, int(b.rowptr[1]), 0.0)
     pb2 = replace(pb, bodies=[replace(b, rowptr=rp, col=col, K=K, R=R), pb.bodies[1]])
-    runs, _, _ = run_batch(pb2, mem, 2)
+    runs, st, _ = run_batch(pb2, mem, 2)
+    assert st["col_depth"] == 0
     for s in range(len(mem)):
         assert np.array_equal(blocks[s], runs[s]), s
+
+
+# (FP64, FP32 + refinement) x (S = 6: 16-byte rows in FP64 only; 5: 4-byte
+# copies; 40: both FP64 halves, the second one partly idle)
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("S", [6, 5, 40])
+def test_column_sweep_agrees_with_tiles(precision, S):
+    """On box bodies the CG product runs as the column sweep; OP_VALUES runs
+    the LDS tiles of the stored entries instead.  Each row's sums are formed
+    in the same order, p.q is reduced in another order, so the two agree to
+    rounding, and each matches the oracle."""
+    import paper_1707_03581_amd as m
+    pb = small_machine()
+    mem = members_for(pb, S, seed0=1900)
+    cols, sc, _ = run_batch(pb, mem, 2, precision=precision)
+    tiles, stl, _ = run_batch(pb, mem, 2, precision=precision, op_form=m.OP_VALUES)
+    assert sc["col_depth"] > 0 and stl["col_depth"] == 0
+    for s in (0, S - 1):
+        e = rel(cols[s], tiles[s])
+        print(f"  precision {precision} S={S} member {s}: columns vs tiles {e:.3e}", flush=True)
+        # (both solves stop at the same relative residual, 1e-13)
+        assert e <= (1e-11 if precision == 0 else 1e-9)
+    mb = mem[S - 1]
+    ref, _ = oracle.run(pb, nsteps=2, T0=mb["T0"], h=mb["h"], alpha=mb["alpha"],
+                        friction_W=mb["friction_W"], period=mb["period"])
+    assert rel(cols[S - 1], ref) <= (1e-10 if precision == 0 else TOL32)
 
 
 def test_per_scenario_horizons():
