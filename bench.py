@@ -576,7 +576,7 @@ def serving(pkg, args):
 
 def ensemble(pkg, args, precision, steps, warmup, headline=False):
     """64 seeded scenarios on the 7.5 mm machine (714,798 DOF each), one batch:
-    per-step latency and throughput, the multi-RHS operator kb_pcg_a against
+    per-step latency and throughput, the multi-RHS operator kb_pcg_a_col against
     the HBM roofline, and (headline) the oracle on member 0 over every step."""
     import torch
     import mrsdc_inputs as mi
@@ -614,10 +614,8 @@ def ensemble(pkg, args, precision, steps, warmup, headline=False):
     ctx.destroy()
     lat_ms = np.array(lat) * 1e3
     b = 4 if precision == mi.FP32_REFINE else 8
-    # the FP32 operator of box bodies runs as the column sweep, FP64 as tiles
-    op_kernel = ("kb_pcg_a_col (column-sweep multi-RHS CG operator, 64 scenarios)"
-                 if precision == mi.FP32_REFINE else
-                 "kb_pcg_a (tiled multi-RHS CG operator, 64 scenarios)")
+    # the operator of box bodies runs as the column sweep in both forms
+    op_kernel = "kb_pcg_a_col (column-sweep multi-RHS CG operator, 64 scenarios)"
     # algorithmic bytes of one multi-RHS operator launch as the shared operator
     # arrives (CSR): every stored entry once (value + int32 column), the row
     # pointers, and the S right-hand sides read once and written once

@@ -659,7 +659,8 @@ __device__ __forceinline__ void col_wait_first(int w) {
 
 // acc[q] += sum over the nine positions j = 3 dy + dx of one plane (in
 // order) of c[j] xv[j][q] (q over the lane's scenarios)
-__device__ __forceinline__ void col_part(const float *c, const float4 (&xv)[9], float (&acc)[4]) {
+__device__ __forceinline__ void col_part(const __attribute__((address_space(3))) float *c,
+                                         const float4 (&xv)[9], float (&acc)[4]) {
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
     const float w = c[j];
@@ -669,8 +670,8 @@ __device__ __forceinline__ void col_part(const float *c, const float4 (&xv)[9], 
     acc[3] = fma_t(w, xv[j].w, acc[3]);
   }
 }
-__device__ __forceinline__ void col_part(const double *c, const double2 (&xv)[9],
-                                         double (&acc)[2]) {
+__device__ __forceinline__ void col_part(const __attribute__((address_space(3))) double *c,
+                                         const double2 (&xv)[9], double (&acc)[2]) {
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
     const double w = c[j];
@@ -1242,7 +1243,12 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
     auto next_r = [&](unsigned o) { return o + RB == NR * RB ? 0u : o + RB; };
     unsigned xro = 0, r0o = (NR - 2) * RB;  // step zb: plane slot 0, record z0 - 2
     const char *lxb = reinterpret_cast<const char *>(&L.x[0][0]) + lb * VB;
-    const char *lrb = reinterpret_cast<const char *>(&L.rec[0][0]) + r * kStencil * VB;
+    // the row's stencils: an LDS address the compiler may not split into a
+    // constant part (else each pair of coefficient reads gets its own add)
+    using lds_char = const __attribute__((address_space(3))) char;
+    lds_char *lrb = (lds_char *)(reinterpret_cast<const char *>(&L.rec[0][0]) + r * kStencil * VB);
+    lds_char *lrr = lrb + kColRows * kStencil * VB;  // its R stencils, after the K record
+    asm volatile("" : "+v"(lrb), "+v"(lrr));
     for (int z = zb; z < it.z1; ++z) {
       const V *xs = reinterpret_cast<const V *>(lxb + xro);
       V16 xv[9];
@@ -1250,18 +1256,19 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
       for (int j = 0; j < 9; ++j)
         xv[j] = *reinterpret_cast<const V16 *>(xs + ((j / 3) * (kColFX + 2) + j % 3) * G::SW);
       const unsigned r1o = next_r(r0o), r2o = next_r(r1o);
-      const V *c2 = reinterpret_cast<const V *>(lrb + r2o);
-      const V *c1 = reinterpret_cast<const V *>(lrb + r1o);
-      const V *c0 = reinterpret_cast<const V *>(lrb + r0o);
-      constexpr int RO = kColRows * kStencil;  // the R record after the K record
+      using lds_v = const __attribute__((address_space(3))) V;
+      lds_v *c2 = reinterpret_cast<lds_v *>(lrb + r2o);
+      lds_v *c1 = reinterpret_cast<lds_v *>(lrb + r1o);
+      lds_v *c0 = reinterpret_cast<lds_v *>(lrb + r0o);
       V kc[VEC] = {}, rc[VEC] = {};
       col_part(c2, xv, kc);       // row z + 2: dz = -1
       col_part(c1 + 9, xv, kb4);  // row z + 1: dz = 0
       col_part(c0 + 18, xv, ka);  // row z: dz = +1
       const V m2 = c2[kStencil - 1], m1 = c1[kStencil - 1], m0 = c0[kStencil - 1];
-      if (m2 < V(0)) col_part(c2 + RO, xv, rc);  // rows with R entries: mass < 0
-      if (m1 < V(0)) col_part(c1 + RO + 9, xv, rb4);
-      if (m0 < V(0)) col_part(c0 + RO + 18, xv, ra);
+      // rows with R entries (mass < 0)
+      if (m2 < V(0)) col_part(reinterpret_cast<lds_v *>(lrr + r2o), xv, rc);
+      if (m1 < V(0)) col_part(reinterpret_cast<lds_v *>(lrr + r1o) + 9, xv, rb4);
+      if (m0 < V(0)) col_part(reinterpret_cast<lds_v *>(lrr + r0o) + 18, xv, ra);
       // row z complete
       V ow[VEC];
       ColVec<V>::split(own, ow);
@@ -1271,9 +1278,9 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
       V qv[VEC];
 #pragma unroll
       for (int q = 0; q < VEC; ++q) {
-        // (explicit fused forms, as in the tiled product, so that no
-        // instantiation contracts them differently)
-        const V y = m0 < V(0) ? fma_t(h[q], ra[q], ka[q]) : ka[q];
+        // (explicit fused forms, so that no instantiation contracts them
+        // differently; a row without R entries has ra = 0, so y = ka)
+        const V y = fma_t(h[q], ra[q], ka[q]);
         qv[q] = fma_t(mass, ow[q], dt * y);
       }
       // p.q over the run's rows (wave-uniform test: the rows below the run
