@@ -117,14 +117,15 @@ def test_forms_that_do_not_apply_are_rejected():
     with pytest.raises(m.MrsdcError):
         ctx.advance(pb.scheme.dt)
     ctx.destroy()
-    # batched contexts keep their own operator
-    ctx = m.batch_simulation(small(mi.FP64), [dict(h=10.0, alpha=1000.0, friction_W=100.0,
-                                                   period=3.0, T0=small(mi.FP64).T0)],
-                             op_form=m.OP_VALUES)
-    with pytest.raises(m.MrsdcError) as ei:
-        ctx.advance_steps(1)
-    assert ei.value.status == m.EINVAL
-    ctx.destroy()
+    # batched contexts take OP_AUTO or OP_VALUES only
+    for form in (m.OP_DICT, m.OP_PACKED, m.OP_PATTERNS, m.OP_VALUES | m.OP_COL32):
+        ctx = m.batch_simulation(small(mi.FP64), [dict(h=10.0, alpha=1000.0, friction_W=100.0,
+                                                       period=3.0, T0=small(mi.FP64).T0)],
+                                 op_form=form)
+        with pytest.raises(m.MrsdcError) as ei:
+            ctx.advance_steps(1)
+        assert ei.value.status == m.EINVAL
+        ctx.destroy()
 
 
 @pytest.mark.parametrize("precision", [mi.FP64, mi.FP32_REFINE], ids=["fp64", "fp32refine"])
