@@ -467,24 +467,29 @@ mrsdc_status build_stage_tiles(mrsdc_ctx *c, int64_t N, const std::vector<int64_
   return fail(c, MRSDC_EINVAL, "a row block exceeds the staging capacity of %d columns", kStageSlots);
 }
 
-// Column sweep of the operator when every body is a box of the 27-point
-// pattern: work items of kColFX x kColFY nodes of one body over a run of z
-// planes, and per item plane a record of the footprint rows' K stencils
-// (value k = entry of neighbour (dz+1) 9 + (dy+1) 3 + (dx+1); value 27 = the
-// row's mass, negated where the row has R entries) plus, for the planes
-// where a row has R entries, a record of their R stencils, in the context's
-// form (FP32 or FP64 values).  Items run body by body, then by z run, then
-// by footprint row and column, so neighbouring footprints (which share halo
-// rows) are dealt to the same XCD and run side by side.  In FP64 each item
-// is two work units (the two halves of the scenarios).
-// Leaves ncol_items = 0 (tiles only) for any other mesh, for vectors of 2 GB
-// or more, and where the context asks for the stored values
-// (MRSDC_OP_VALUES).
-mrsdc_status build_columns(mrsdc_ctx *c, int64_t N, BatchArgs &a) {
+// Column sweeps when every body is a box of the 27-point pattern: work items
+// of kColFX x kColFY nodes of one body over a run of z planes, and per item
+// plane a record of the footprint rows' K stencils (value k = entry of
+// neighbour (dz+1) 9 + (dy+1) 3 + (dx+1); value 27 = the row's mass,
+// negated where the row has an R stencil) plus, for the planes where a row
+// has one (R entries or a boundary load g), a record of their R stencils
+// (value 27 = g).  Items run body by body, then by z run, then by footprint
+// row and column, so neighbouring footprints (which share halo rows) are
+// dealt to the same XCD and run side by side.  The CG operator sweeps in
+// the context's form (cgrid; FP32 records in FP32 contexts), F = h g - L T
+// in FP64 (cgrid_f; FP64 records); an FP64 sweep takes each item as two work
+// units (the two halves of the scenarios).
+// Leaves cgrid = cgrid_f = 0 (tiles only) for any other mesh and where the
+// context asks for the stored values (MRSDC_OP_VALUES), and either one at 0
+// where its vectors hold 2 GB or more.
+mrsdc_status build_columns(mrsdc_ctx *c, int64_t N, const std::vector<double> &gbase,
+                           BatchArgs &a) {
   if (c->cfg.op_form == MRSDC_OP_VALUES) return MRSDC_OK;  // stored values: tiles
   const bool fp32 = c->cfg.precision == MRSDC_FP32_REFINE;
   const int64_t vb = fp32 ? 4 : 8, units = fp32 ? 1 : 2;
-  if ((N * c->S + kColZeroRow) * vb >= ((int64_t)1 << 31)) return MRSDC_OK;
+  const bool cg = (N * c->S + kColZeroRow) * vb < ((int64_t)1 << 31);
+  const bool fsweep = (N * c->S + kColZeroRow) * 8 < ((int64_t)1 << 31);
+  if (!cg && !fsweep) return MRSDC_OK;
   int64_t dm[2][3];
   for (int b = 0; b < c->nbody; ++b)
     if (!box_dims(c->body[b], dm[b])) return MRSDC_OK;
@@ -509,10 +514,11 @@ mrsdc_status build_columns(mrsdc_ctx *c, int64_t N, BatchArgs &a) {
         ks[(size_t)row * kStencil + k] = B.K[e];
         hasR |= !B.R.empty() && B.R[e] != 0.0;
       }
-      if (!hasR) continue;
+      if (!hasR && gbase[row] == 0.0) continue;
       ridx[row] = (int)(rs.size() / kStencil);
       rs.resize(rs.size() + kStencil, 0.0);
       double *r = rs.data() + rs.size() - kStencil;
+      r[27] = gbase[row];
       for (int64_t e = B.rowptr[i]; e < B.rowptr[i + 1]; ++e) {
         const int64_t j = B.col[e];
         const int64_t jx = j % nx, jy = (j / nx) % ny, jz = j / (nx * ny);
@@ -523,15 +529,17 @@ mrsdc_status build_columns(mrsdc_ctx *c, int64_t N, BatchArgs &a) {
   // Run length: the one (8 .. 64 planes) with the shortest simulated
   // makespan when XCD x deals its eighth of the items, in order, to its
   // resident workgroups as they come free, an item costing its planes plus
-  // the steps that fill its pipeline.
+  // the steps that fill its pipeline (for the CG operator's sweep, else F's).
+  const bool sim32 = fp32 && cg;
   const int64_t slots =
-      std::max<int64_t>(1, 256 * (int64_t)col_workgroups_per_cu(fp32, a.col_depth) / 8);
+      std::max<int64_t>(1, 256 * (int64_t)col_workgroups_per_cu(sim32, a.col_depth) / 8);
   auto makespan = [&](int64_t zr) {
     std::vector<int64_t> cost;
     for (int b = 0; b < c->nbody; ++b) {
       const int64_t fp = ((dm[b][0] + kColFX - 1) / kColFX) * ((dm[b][1] + kColFY - 1) / kColFY);
       for (int64_t z0 = 0; z0 < dm[b][2]; z0 += zr)
-        cost.insert(cost.end(), fp * units, std::min(dm[b][2], z0 + zr) - z0 + 3 + a.col_depth);
+        cost.insert(cost.end(), fp * (sim32 ? 1 : 2),
+                    std::min(dm[b][2], z0 + zr) - z0 + 3 + a.col_depth);
     }
     const int64_t T = (int64_t)cost.size();
     int64_t worst = 0;
@@ -576,7 +584,7 @@ mrsdc_status build_columns(mrsdc_ctx *c, int64_t N, BatchArgs &a) {
               kr[r * kStencil + 27] = hasR ? -mass[row] : mass[row];
               if (!hasR) continue;
               anyR = true;
-              for (int k = 0; k < 27; ++k)
+              for (int k = 0; k < kStencil; ++k)
                 rr[r * kStencil + k] = rs[(size_t)ridx[row] * kStencil + k];
             }
             if (anyR) {
@@ -589,7 +597,7 @@ mrsdc_status build_columns(mrsdc_ctx *c, int64_t N, BatchArgs &a) {
                                     (int)(uint32_t)mask, (int)(uint32_t)(mask >> 32)};
           items.insert(items.end(), it, it + kColItem);
         }
-  c->col_stored_bytes = (int64_t)(krec.size() + rrec.size()) * vb + (int64_t)items.size() * 4;
+  c->col_stored_bytes = cg ? (int64_t)(krec.size() + rrec.size()) * vb + (int64_t)items.size() * 4 : 0;
   if (rrec.empty()) rrec.assign(rec, 0.0);
   mrsdc_status st;
   int *pi;
@@ -599,22 +607,24 @@ mrsdc_status build_columns(mrsdc_ctx *c, int64_t N, BatchArgs &a) {
   // K records then R records in one buffer (one buffer resource in the kernel)
   const size_t nk = krec.size();
   krec.insert(krec.end(), rrec.begin(), rrec.end());
-  if (krec.size() * vb >= ((size_t)1 << 31))
+  if (krec.size() * 8 >= ((size_t)1 << 31))
     return fail(c, MRSDC_EINVAL, "column records above 2 GB");
-  if (fp32) {
+  if (fp32 && cg) {
     float *pf;
     if ((st = upload(c, &pf, std::vector<float>(krec.begin(), krec.end())))) return st;
     a.op.kcol32 = pf;
     a.op.rcol32 = pf + nk;
-  } else {
-    double *pd;
-    if ((st = upload(c, &pd, krec))) return st;
-    a.op.kcol64 = pd;
-    a.op.rcol64 = pd + nk;
+    a.op.col_rec_bytes32 = (int64_t)krec.size() * 4;
   }
-  a.op.col_rec_bytes = (int64_t)krec.size() * vb;
+  double *pd;
+  if ((st = upload(c, &pd, krec))) return st;
+  a.op.kcol64 = pd;
+  a.op.rcol64 = pd + nk;
+  a.op.col_rec_bytes64 = (int64_t)krec.size() * 8;
   // one workgroup per work unit: the dispatcher balances them over the CUs
-  a.cgrid32 = (int)((a.op.ncol_items * units + 7) / 8 * 8 + 8);
+  const int64_t nit = a.op.ncol_items;
+  a.cgrid = cg ? (int)((nit * units + 7) / 8 * 8 + 8) : 0;
+  a.cgrid_f = fsweep ? (int)((nit * 2 + 7) / 8 * 8 + 8) : 0;
   return MRSDC_OK;
 }
 
@@ -668,7 +678,7 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
   double *pv;
   a.op.N = N;
   if ((st = build_stage_tiles(c, N, rowptr, col, val, nk, a))) return st;
-  if ((st = build_columns(c, N, a))) return st;
+  if ((st = build_columns(c, N, gbase, a))) return st;
   if ((st = upload(c, &pv, Kd))) return st;
   a.Kd = pv;
   if ((st = upload(c, &pv, Rd))) return st;
@@ -700,7 +710,7 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
   if ((st = dalloc(c, &a.sc, 1))) return st;
   HIPCHK(hipMemset(a.sc, 0, sizeof(BatchScalars)));
   HIPCHK(hipMemcpy(a.sc->active, act.data(), sizeof(int) * S, hipMemcpyHostToDevice));
-  const int maxgrid = std::max({a.grid, a.sgrid64, a.sgrid32, a.cgrid32});
+  const int maxgrid = std::max({a.grid, a.sgrid64, a.sgrid32, a.cgrid});
   if ((st = dalloc(c, &a.partial, 3 * (size_t)maxgrid * S, true)))
     return st;
   if ((st = dalloc(c, &c->stage, N))) return st;
@@ -1036,7 +1046,7 @@ mrsdc_status prepare(mrsdc_ctx *c) {
   for (int m = 0; m <= cfg.M; ++m) {
     if (lob && m == 1) {
       d.T[1] = d.T[0];
-    } else if ((st = dalloc(c, &d.T[m], NS, true))) {
+    } else if ((st = dalloc(c, &d.T[m], batch ? NS + kColZeroRow : NS, true))) {
       return st;
     }
     if (m >= 1 && (st = dalloc(c, &d.F[m], NS, true))) return st;
@@ -1049,7 +1059,12 @@ mrsdc_status prepare(mrsdc_ctx *c) {
     return st;
   if (batch) {  // inactive scenarios keep finite zeros
     for (int m = 0; m <= cfg.M; ++m) {
-      if (!(lob && m == 1)) HIPCHK(hipMemset(d.T[m], 0, NS * sizeof(double)));
+      // (each node state ends in one row of 64 zeros, shared by the
+      // scenarios: the column sweep of F stages halo rows from it)
+      if (!(lob && m == 1)) {
+        c->scen_bytes -= (int64_t)kColZeroRow * sizeof(double);
+        HIPCHK(hipMemset(d.T[m], 0, (NS + kColZeroRow) * sizeof(double)));
+      }
       if (m >= 1) HIPCHK(hipMemset(d.F[m], 0, NS * sizeof(double)));
       if (d.I[m]) HIPCHK(hipMemset(d.I[m], 0, NS * sizeof(double)));
     }
@@ -1480,11 +1495,11 @@ mrsdc_status autotune_batch(mrsdc_ctx *c) {
     a.groups_c = (v & 4) ? 8 : 4;
     return MRSDC_OK;
   }
-  if (!fp32 && a.op.ncol_items == 0) return MRSDC_OK;
+  if (!fp32 && a.cgrid == 0) return MRSDC_OK;
   static std::mutex mu;
   static std::map<std::vector<int64_t>, std::array<int, 3>> cache;
   const std::vector<int64_t> key = {c->cfg.device, a.N,           a.S,
-                                    c->batch_entries, a.op.ncol_items, a.fp32};
+                                    c->batch_entries, a.cgrid,     a.fp32};
   {
     std::lock_guard<std::mutex> g(mu);
     auto f = cache.find(key);
@@ -1520,7 +1535,7 @@ mrsdc_status autotune_batch(mrsdc_ctx *c) {
   // (in FP64 the operator only: the updates there would write the states)
   std::vector<Cand> cands;
   if (fp32) cands = {{&a.groups_b, 1, {4, 2}}, {&a.groups_c, 2, {4, 8}}};
-  if (a.op.ncol_items > 0) cands.insert(cands.begin(), Cand{&a.col_depth, 0, {kColDepth, 1}});
+  if (a.cgrid > 0) cands.insert(cands.begin(), Cand{&a.col_depth, 0, {kColDepth, 1}});
   hipError_t e = hipSuccess;
   for (const Cand &k : cands) {
     int best = k.values[0];
@@ -2106,7 +2121,7 @@ mrsdc_status mrsdc_time_operator(mrsdc_ctx *c, int reps, double *avg_us, int64_t
     const bool f32 = c->cfg.precision == MRSDC_FP32_REFINE;
     const int64_t vb = f32 ? 4 : 8, rhs = 2 * vb * (int64_t)c->S * c->ba.N;
     *bytes = c->S == 0                 ? c->times.cg_spmv_bytes
-             : c->ba.op.ncol_items > 0 ? c->col_stored_bytes + rhs
+             : c->ba.cgrid > 0         ? c->col_stored_bytes + rhs
                                        : c->batch_entries * (4 + vb) + 22 * c->ba.N + rhs;
   }
   return MRSDC_OK;
@@ -2329,7 +2344,7 @@ mrsdc_status mrsdc_batch_advance(mrsdc_ctx *c, int nsteps, mrsdc_stats *stats) {
   acc.wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   acc.graph_captures = (int32_t)(c->graph_captures - cap0);
   acc.graph_launches = (int32_t)(c->graph_replays - rep0);
-  acc.col_depth = c->ba.op.ncol_items > 0 ? c->ba.col_depth : 0;
+  acc.col_depth = c->ba.cgrid > 0 ? c->ba.col_depth : 0;
   acc.groups_b = c->ba.groups_b;
   acc.groups_c = c->ba.groups_c;
   acc.autotuned = c->tuned ? 1 : 0;

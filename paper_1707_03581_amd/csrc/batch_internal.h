@@ -28,28 +28,29 @@ struct BatchOp {
   const int64_t *tstart = nullptr;  // [ntiles + 1]
   const int64_t *prow = nullptr;    // [N]
   const double *pmass = nullptr;    // [N] lumped mass of row prow[pos]
-  // Column sweep (every body a box of the 27-point pattern), in the form of
-  // the context (FP32 or FP64 records).  Work items are footprints of
-  // kColFX x kColFY nodes of one body over a run of z planes.  Each plane of
-  // an item has one record of its footprint rows' K stencils (kColRows rows
-  // of kStencil values, row r = node (x0 + r % kColFX, y0 + r / kColFX)):
-  // value k is the entry of neighbour k = (dz+1) 9 + (dy+1) 3 + (dx+1), 0
-  // where there is none, and value 27 is the row's lumped mass, negated when
-  // the row has R entries (rows outside the body are all zeros).  The planes
-  // where a row has R entries also have one record of the rows' R stencils
-  // (same layout, no mass).
+  // Column sweep (every body a box of the 27-point pattern): FP64 records,
+  // and FP32 ones in FP32 contexts.  Work items are footprints of kColFX x
+  // kColFY nodes of one body over a run of z planes.  Each plane of an item
+  // has one record of its footprint rows' K stencils (kColRows rows of
+  // kStencil values, row r = node (x0 + r % kColFX, y0 + r / kColFX)): value
+  // k is the entry of neighbour k = (dz+1) 9 + (dy+1) 3 + (dx+1), 0 where
+  // there is none, and value 27 is the row's lumped mass, negated when the
+  // row has an R stencil (rows outside the body are all zeros).  Rows with R
+  // entries or a boundary load g have an R stencil: the planes where some
+  // row has one also have one record of the rows' R stencils (same layout,
+  // value 27 the row's g).
   int ncol_items = 0;
   // [ncol_items][kColItem]: row offset, nx, ny, nz, x0, y0, z0, z1, first K
   // record, first R record, R plane mask (bit z - z0; two words)
   const int *col_items = nullptr;
   const float *kcol32 = nullptr;   // [K records][kColRows][kStencil], then the R records:
   const float *rcol32 = nullptr;   // [R records][kColRows][kStencil] (same buffer)
-  const double *kcol64 = nullptr;  // the same in FP64 (FP64 contexts)
+  const double *kcol64 = nullptr;  // the same in FP64
   const double *rcol64 = nullptr;
-  int64_t col_rec_bytes = 0;  // bytes of both
+  int64_t col_rec_bytes32 = 0, col_rec_bytes64 = 0;  // bytes of both, per form
 };
 constexpr int kColFX = 4, kColFY = 4;                // footprint of a column item
-constexpr int kColZeroRow = 64;                      // zeros after the direction p
+constexpr int kColZeroRow = 64;  // zeros after the direction p and the node states
 constexpr int kColRows = kColFX * kColFY;            // rows of a plane of an item
 constexpr int kColPL = (kColFX + 2) * (kColFY + 2);  // staged rows per plane (halo included)
 constexpr int kColDepth = 2;                         // stages in flight beyond the one read
@@ -100,7 +101,8 @@ struct BSolve {
 struct BatchArgs {
   int S = 0, M = 0, P = 0, grid = 0;
   int sgrid64 = 0, sgrid32 = 0;  // workgroups of the tiled kernels (FP64 / FP32 staging)
-  int cgrid32 = 0;               // workgroups of the column-sweep kernel (0: tiles)
+  int cgrid = 0;    // workgroups of the column-sweep CG operator (0: tiles)
+  int cgrid_f = 0;  // of the FP64 column sweep of F (0: tiles)
   int bgrid64 = 0, bgrid32 = 0;  // workgroups of the CG update (b): all resident
   // launch variants (every one gives the same results): stages in flight of
   // the column sweep (1 or kColDepth), row groups in flight of the CG

@@ -470,6 +470,7 @@ struct ColVec<float> {
   using V16 = float4;
   __device__ static const float *rec(const BatchOp &op) { return op.kcol32; }
   __device__ static const float *rrec(const BatchOp &op) { return op.rcol32; }
+  __device__ static int64_t rec_bytes(const BatchOp &op) { return op.col_rec_bytes32; }
   __device__ static const float *p(const BatchArgs &a) { return a.p32; }
   __device__ static float *q(const BatchArgs &a) { return a.q32; }
   __device__ static void split(const float4 &v, float (&o)[4]) {
@@ -484,6 +485,7 @@ struct ColVec<double> {
   using V16 = double2;
   __device__ static const double *rec(const BatchOp &op) { return op.kcol64; }
   __device__ static const double *rrec(const BatchOp &op) { return op.rcol64; }
+  __device__ static int64_t rec_bytes(const BatchOp &op) { return op.col_rec_bytes64; }
   __device__ static const double *p(const BatchArgs &a) { return a.p; }
   __device__ static double *q(const BatchArgs &a) { return a.q; }
   __device__ static void split(const double2 &v, double (&o)[2]) {
@@ -525,16 +527,18 @@ struct ColIssue {
   unsigned long long rbits;  // R plane bits of the records not issued yet
 
   // ring slots: stage z0 - 2 + i in plane slot i mod NX, record plane z0 + i
-  // in record slot i mod NR; hs = this workgroup's first scenario
-  __device__ __forceinline__ void init(const BatchArgs &a, const ColItem &it, int wave, int hs) {
+  // in record slot i mod NR; xsrc = the staged vector (N S values, then a
+  // row of zeros), hs = this workgroup's first scenario
+  __device__ __forceinline__ void init(const BatchArgs &a, const V *xsrc, const ColItem &it,
+                                       int wave, int hs) {
     w = wave;
     const int S = a.S, lane = threadIdx.x & 63;
     const int upr = (min(S - hs, G::SW) * G::VB) / UB;  // units of the row in this half
     const unsigned zrow = (unsigned)(a.N * S) * (unsigned)G::VB;  // the row of zeros
-    rx = __builtin_amdgcn_make_buffer_rsrc((void *)ColVec<V>::p(a), 0,
-                                           (int)(zrow + kColZeroRow * G::VB), 0x00020000);
+    rx = __builtin_amdgcn_make_buffer_rsrc((void *)xsrc, 0, (int)(zrow + kColZeroRow * G::VB),
+                                           0x00020000);
     rrec = __builtin_amdgcn_make_buffer_rsrc((void *)ColVec<V>::rec(a.op), 0,
-                                             (int)a.op.col_rec_bytes, 0x00020000);
+                                             (int)ColVec<V>::rec_bytes(a.op), 0x00020000);
     rbase = (unsigned)((ColVec<V>::rrec(a.op) - ColVec<V>::rec(a.op)) * G::VB);
     pstride = (unsigned)it.nx * (unsigned)it.ny * (unsigned)S * (unsigned)G::VB;
 #pragma unroll
@@ -1181,16 +1185,21 @@ __device__ inline void publish_col(const double (&v)[ColGeom<V>::VEC], double *p
   }
 }
 
-// (a) in the column sweep: q = M p + dtau (K + h R) p and the partial p.q,
-// one item (or half an item) per workgroup, XCD x taking the x-th eighth of
-// the work (neighbouring footprints share halo rows, and the two halves of
-// an item its records, in that XCD's L2).  Where a row of S values is a
-// multiple of 16 bytes, a lane stores its 16 bytes at once (the values of
-// idle scenarios too, which no later step reads); otherwise each value
-// apart, only where its scenario is on.
-template <int TIMING, typename V, int UB, int D>
+// The column sweep, one item (or half an item) per workgroup, XCD x taking
+// the x-th eighth of the work (neighbouring footprints share halo rows, and
+// the two halves of an item its records, in that XCD's L2):
+//   MODE kColCG (the CG operator (a)): q = M p + dtau (K + h R) p and the
+//     partial p.q (m: the node, dtau its step);
+//   MODE kColF: F_m = h g - (K + h R) T_m for every scenario (FP64 only;
+//     g of a row is value 27 of its R stencil).
+// Where a row of S values is a multiple of 16 bytes, a lane stores its 16
+// bytes at once (the values of idle scenarios too, which no later step
+// reads); otherwise each value apart, only where its scenario is on.
+constexpr int kColCG = 0, kColF = 1;
+template <int TIMING, typename V, int UB, int D, int MODE = kColCG>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ColOcc<V, D, UB>::W)))
 void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
+  static_assert(MODE == kColCG || sizeof(V) == 8, "F in FP64");
   using G = ColGeom<V>;
   using CC = ColCopies<V, UB>;
   using V16 = typename ColVec<V>::V16;
@@ -1211,14 +1220,23 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
 #pragma unroll
   for (int i = 0; i < VEC; ++i) {
     const int s = s0 + i;
-    on[i] = has && (TIMING ? s < S : lane_on(a.sc, s, S));
+    on[i] = has && ((TIMING || MODE == kColF) ? s < S : lane_on(a.sc, s, S));
     const V hv = (V)lane_h(a, s);
     h[i] = on[i] ? hv : V(0);
     any |= on[i];
   }
   const V dt = (V)dtau;
-  const __amdgpu_buffer_rsrc_t qres = __builtin_amdgcn_make_buffer_rsrc(
-      ColVec<V>::q(a), 0, (int)(a.N * S * VB), 0x00020000);
+  const V *xsrc;
+  V *qdst;
+  if constexpr (MODE == kColCG) {
+    xsrc = ColVec<V>::p(a);
+    qdst = ColVec<V>::q(a);
+  } else {
+    xsrc = reinterpret_cast<const V *>(a.T[m]);
+    qdst = reinterpret_cast<V *>(a.F[m]);
+  }
+  const __amdgpu_buffer_rsrc_t qres =
+      __builtin_amdgcn_make_buffer_rsrc(qdst, 0, (int)(a.N * S * VB), 0x00020000);
   if (__syncthreads_or(any)) {
     const ColItem it = col_item(a.op, G::H == 1 ? t : t / G::H);
     const int r = w * 4 + lr, lx = r % kColFX, ly = r / kColFX;
@@ -1230,7 +1248,7 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
     // used).
     const int zb = it.z0 - 2;
     ColIssue<V, UB, D> ci;
-    ci.init(a, it, w, hs);
+    ci.init(a, xsrc, it, w, hs);
     for (int q = 0; q <= D; ++q) ci.issue(it, L);  // stages z0 - 2 .. z0 - 2 + D
     col_wait_first<CC, D>(w);
     col_barrier();
@@ -1276,17 +1294,24 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
       const bool row_in = rok & (z >= it.z0);
       const unsigned row = (unsigned)(it.off + it.x0 + lx + it.nx * (it.y0 + ly + it.ny * z));
       V qv[VEC];
+      if constexpr (MODE == kColCG) {
 #pragma unroll
-      for (int q = 0; q < VEC; ++q) {
-        // (explicit fused forms, so that no instantiation contracts them
-        // differently; a row without R entries has ra = 0, so y = ka)
-        const V y = fma_t(h[q], ra[q], ka[q]);
-        qv[q] = fma_t(mass, ow[q], dt * y);
+        for (int q = 0; q < VEC; ++q) {
+          // (explicit fused forms, so that no instantiation contracts them
+          // differently; a row without R entries has ra = 0, so y = ka)
+          const V y = fma_t(h[q], ra[q], ka[q]);
+          qv[q] = fma_t(mass, ow[q], dt * y);
+        }
+      } else {
+        // g of the row: after its R stencil (rows without one have g = 0)
+        const V g = m0 < V(0) ? reinterpret_cast<lds_v *>(lrr + r0o)[kStencil - 1] : V(0);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) qv[q] = fma_t(h[q], g, -fma_t(h[q], ra[q], ka[q]));
       }
       // p.q over the run's rows (wave-uniform test: the rows below the run
       // come from records that were never copied); a masked lane adds an
       // exact zero (rows outside the body have zero records, so finite q)
-      if (z >= it.z0) {
+      if (MODE == kColCG && z >= it.z0) {
 #pragma unroll
         for (int q = 0; q < VEC; ++q) {
           const V om = (rok & on[q]) ? ow[q] : V(0);
@@ -1332,8 +1357,9 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
       r0o = r1o;
     }
   }
-  __syncthreads();  // every copy landed before the LDS is reused
-  publish_col<V>(v, a.partial, gridDim.x, S, s0, reinterpret_cast<double *>(L.x[0]));
+  __syncthreads();  // every copy landed before the LDS is reused (or freed)
+  if constexpr (MODE == kColCG)
+    publish_col<V>(v, a.partial, gridDim.x, S, s0, reinterpret_cast<double *>(L.x[0]));
 }
 
 // ---------------------------------------------------------------------------
@@ -1837,6 +1863,14 @@ static int tgrid(const BatchArgs &a) {
 #define RED(np, ...) kb_reduce<<<a.S, kBlock, 0, st>>>(a, np, __VA_ARGS__)
 
 void blaunch_f_multi(const BatchArgs &a, int j0, int j1, hipStream_t st) {
+  if (a.cgrid_f > 0) {  // the FP64 column sweep, one launch per node
+    for (int j = j0; j <= j1; ++j) {
+      if (vec16<double>(a))
+        kb_pcg_a_col<0, double, 16, kColDepth, kColF><<<a.cgrid_f, kBlock, 0, st>>>(a, j, 0.0);
+      else kb_pcg_a_col<0, double, 4, kColDepth, kColF><<<a.cgrid_f, kBlock, 0, st>>>(a, j, 0.0);
+    }
+    return;
+  }
   if (vec16<double>(a)) kb_f_multi<16, true><<<a.sgrid64, kBlock, 0, st>>>(a, j0, j1);
   else kb_f_multi<4, false><<<a.sgrid64, kBlock, 0, st>>>(a, j0, j1);
 }
@@ -1861,7 +1895,7 @@ static bool use_columns(const BatchArgs &a) {
 // workgroups of the operator launch
 template <typename V>
 static int pcg_a_grid(const BatchArgs &a) {
-  return use_columns<V>(a) ? a.cgrid32 : tgrid<V>(a);
+  return use_columns<V>(a) ? a.cgrid : tgrid<V>(a);
 }
 
 // the column sweep with D stages in flight (any D gives the same results)
