@@ -731,14 +731,15 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
     // inner vectors and the FP64 refinement residual, scenario-interleaved
     a.fp32 = 1;
     const size_t NS = (size_t)N * S;
-    // p32 ends in one row of 64 zeros (shared, not per scenario): the column
-    // sweep stages halo rows outside a body from it
-    if ((st = dalloc(c, &a.x32, NS, true)) || (st = dalloc(c, &a.r32, NS, true)) ||
+    // p32 and x32 end in one row of 64 zeros (shared, not per scenario): the
+    // column sweeps of the CG operator and of the refinement stage halo rows
+    // outside a body from it
+    if ((st = dalloc(c, &a.x32, NS + kColZeroRow, true)) || (st = dalloc(c, &a.r32, NS, true)) ||
         (st = dalloc(c, &a.p32, NS + kColZeroRow, true)) || (st = dalloc(c, &a.q32, NS, true)) ||
         (st = dalloc(c, &a.r64, NS, true)))
       return st;
-    c->scen_bytes -= (int64_t)kColZeroRow * sizeof(float);
-    HIPCHK(hipMemset(a.x32, 0, NS * sizeof(float)));
+    c->scen_bytes -= 2 * (int64_t)kColZeroRow * sizeof(float);
+    HIPCHK(hipMemset(a.x32, 0, (NS + kColZeroRow) * sizeof(float)));
     HIPCHK(hipMemset(a.r32, 0, NS * sizeof(float)));
     HIPCHK(hipMemset(a.p32, 0, (NS + kColZeroRow) * sizeof(float)));
     HIPCHK(hipMemset(a.q32, 0, NS * sizeof(float)));

@@ -403,25 +403,27 @@ __device__ inline void publish_groups(const double (&v)[K][VEC], double *partial
 // bytes of four (FP32) or two (FP64) consecutive scenarios of a row, a wave
 // the four rows w 4 .. w 4 + 3 of the plane.
 // ---------------------------------------------------------------------------
-template <typename V>
+// (XV: the staged values, RV: the stencil records)
+template <typename XV, typename RV = XV>
 struct ColGeom {
-  static constexpr int VB = (int)sizeof(V);
+  static constexpr int VB = (int)sizeof(XV);
   static constexpr int VEC = 16 / VB;  // scenarios per lane
   static constexpr int SW = 256 / VB;  // scenarios per workgroup (one staged row)
   static constexpr int H = 64 / SW;    // workgroups per item
-  static constexpr int PlaneUnits = kColPL * 16;                  // 16-byte units of a plane
-  static constexpr int RecUnits = kColRows * kStencil * VB / 16;  // of a K (or R) record
-  static constexpr int RecSlot = (2 * RecUnits + 63) / 64 * 64;   // K, R and the copy tail
+  static constexpr int PlaneUnits = kColPL * 16;  // 16-byte units of a plane
+  static constexpr int RVB = (int)sizeof(RV);
+  static constexpr int RecUnits = kColRows * kStencil * RVB / 16;  // of a K (or R) record
+  static constexpr int RecSlot = (2 * RecUnits + 63) / 64 * 64;    // K, R and the copy tail
   static_assert(kColRows == 16 && kBlock == 256, "four waves of four rows");
 };
 // Wave-wide copies per stage: the staged rows in UB-byte units (16 when a
 // row of S values is a multiple of 16 bytes, else 4), then the records in
 // 16-byte units; copy j is issued by wave j % 4, so wave w issues C<w> of
 // them (C0 the most)
-template <typename V, int UB>
+template <typename XV, typename RV, int UB>
 struct ColCopies {
-  static constexpr int X = ColGeom<V>::PlaneUnits * 16 / UB / 64;
-  static constexpr int N = X + ColGeom<V>::RecSlot / 64;
+  static constexpr int X = ColGeom<XV, RV>::PlaneUnits * 16 / UB / 64;
+  static constexpr int N = X + ColGeom<XV, RV>::RecSlot / 64;
   template <int W>
   static constexpr int C = (N - W + 3) / 4;
   static constexpr int C0 = C<0>;
@@ -430,22 +432,34 @@ struct ColCopies {
 // Stage s = staged plane s + 1 (read in step s) and the stencil record of
 // plane s + 2 (read in steps s .. s + 2).  With D stages in flight beyond
 // the one being read: D + 1 plane slots and D + 3 record slots.
-template <typename V, int D>
+template <typename XV, typename RV, int D>
 struct ColLds {
   static constexpr int NX = D + 1, NR = D + 3;
-  uint4 x[NX][ColGeom<V>::PlaneUnits];
-  uint4 rec[NR][ColGeom<V>::RecSlot];
+  uint4 x[NX][ColGeom<XV, RV>::PlaneUnits];
+  uint4 rec[NR][ColGeom<XV, RV>::RecSlot];
+};
+// The refinement's sweep also brings the FP64 rows it updates (T and r64 of
+// the wave's four rows: 4 KB per wave) into LDS, one step ahead, each lane
+// its own values.
+constexpr int kColIOBytes = 4 * 4096;
+template <typename XV, typename RV, int D>
+struct ColLdsIO : ColLds<XV, RV, D> {
+  uint4 io[kColIOBytes / 16];
 };
 // workgroups per CU that the ring leaves room for (160 KB of LDS); four only
-// for FP32 with 16-byte copies, at most two for FP64 with 4-byte copies (the
-// other forms need more than 128, that one more than 168 registers)
-template <typename V, int D, int UB = 16>
+// for FP32 with 16-byte copies, at most two for FP64 records with 4-byte
+// copies or FP32 staged values (the other forms need more than 128, those
+// more than 168 registers)
+template <typename XV, typename RV, int D, int UB = 16>
 struct ColOcc {
-  static constexpr size_t B = sizeof(ColLds<V, D>);
-  static constexpr int W = sizeof(V) == 4 && UB == 16 && 4 * B + 1024 <= 160 * 1024 ? 4
-                           : !(sizeof(V) == 8 && UB == 4) && 3 * B + 768 <= 160 * 1024 ? 3
-                           : 2 * B + 512 <= 160 * 1024                                 ? 2
-                                                                                       : 1;
+  static constexpr size_t B =
+      sizeof(ColLds<XV, RV, D>) + (sizeof(XV) != sizeof(RV) ? kColIOBytes : 0);
+  static constexpr bool F32 = sizeof(XV) == 4 && sizeof(RV) == 4;
+  static constexpr bool BIG = sizeof(RV) == 8 && (UB == 4 || sizeof(XV) == 4);
+  static constexpr int W = F32 && UB == 16 && 4 * B + 1024 <= 160 * 1024 ? 4
+                           : !BIG && 3 * B + 768 <= 160 * 1024          ? 3
+                           : 2 * B + 512 <= 160 * 1024                  ? 2
+                                                                        : 1;
 };
 
 struct ColItem {
@@ -503,10 +517,10 @@ struct ColVec<double> {
 // inside a buffer: halo rows outside the body and the values past S of a
 // row come from the row of zeros after the direction; the records' tail
 // repeats the first K unit.
-template <typename V, int UB, int D>
+template <typename XV, typename RV, int UB, int D>
 struct ColIssue {
-  using G = ColGeom<V>;
-  using CC = ColCopies<V, UB>;
+  using G = ColGeom<XV, RV>;
+  using CC = ColCopies<XV, RV, UB>;
   static constexpr int UPH = 256 / UB;  // units per staged row
   static constexpr unsigned XB = G::PlaneUnits * 16, RB = G::RecSlot * 16;  // slot bytes
   static constexpr unsigned RECB = G::RecUnits * 16;                        // record bytes
@@ -529,7 +543,7 @@ struct ColIssue {
   // ring slots: stage z0 - 2 + i in plane slot i mod NX, record plane z0 + i
   // in record slot i mod NR; xsrc = the staged vector (N S values, then a
   // row of zeros), hs = this workgroup's first scenario
-  __device__ __forceinline__ void init(const BatchArgs &a, const V *xsrc, const ColItem &it,
+  __device__ __forceinline__ void init(const BatchArgs &a, const XV *xsrc, const ColItem &it,
                                        int wave, int hs) {
     w = wave;
     const int S = a.S, lane = threadIdx.x & 63;
@@ -537,9 +551,9 @@ struct ColIssue {
     const unsigned zrow = (unsigned)(a.N * S) * (unsigned)G::VB;  // the row of zeros
     rx = __builtin_amdgcn_make_buffer_rsrc((void *)xsrc, 0, (int)(zrow + kColZeroRow * G::VB),
                                            0x00020000);
-    rrec = __builtin_amdgcn_make_buffer_rsrc((void *)ColVec<V>::rec(a.op), 0,
-                                             (int)ColVec<V>::rec_bytes(a.op), 0x00020000);
-    rbase = (unsigned)((ColVec<V>::rrec(a.op) - ColVec<V>::rec(a.op)) * G::VB);
+    rrec = __builtin_amdgcn_make_buffer_rsrc((void *)ColVec<RV>::rec(a.op), 0,
+                                             (int)ColVec<RV>::rec_bytes(a.op), 0x00020000);
+    rbase = (unsigned)((ColVec<RV>::rrec(a.op) - ColVec<RV>::rec(a.op)) * G::RVB);
     pstride = (unsigned)it.nx * (unsigned)it.ny * (unsigned)S * (unsigned)G::VB;
 #pragma unroll
     for (int i = 0; i < CC::C0; ++i) {
@@ -575,7 +589,7 @@ struct ColIssue {
   // Issue the next stage: plane P (zeros outside the body and past the
   // run's top neighbour z1) and the record of plane R (the run's first record
   // past the run), then step to the stage after it.
-  __device__ __forceinline__ void issue(const ColItem &it, ColLds<V, D> &L) {
+  __device__ __forceinline__ void issue(const ColItem &it, ColLds<XV, RV, D> &L) {
     const bool pin = (P >= 0) & (P < it.nz) & (P <= it.z1);
     const bool inrun = R < it.z1;
     const bool hasr = inrun & ((rbits & 1ull) != 0);
@@ -601,12 +615,12 @@ struct ColIssue {
     }
     P += 1;
     pbase += pstride;
-    xso = xso + XB == ColLds<V, D>::NX * XB ? 0u : xso + XB;
+    xso = xso + XB == ColLds<XV, RV, D>::NX * XB ? 0u : xso + XB;
     rr += hasr ? 1 : 0;
     kr += 1;
     rbits >>= 1;
     R += 1;
-    rso = rso + RB == ColLds<V, D>::NR * RB ? 0u : rso + RB;
+    rso = rso + RB == ColLds<XV, RV, D>::NR * RB ? 0u : rso + RB;
   }
 };
 
@@ -625,28 +639,41 @@ __device__ __forceinline__ void col_barrier() {
 }
 // Wait until this wave's copies of plane z + 2 have landed, k + 1 planes
 // (k = min(z - z0, D - 1)) into the run, with D planes in flight beyond
-// z + 1, C copies per plane and ST stores per plane formed by this wave.  In
-// issue order, what follows those copies is exactly: the copies of the D - 1
-// later planes and the stores of the last k + 1 planes formed (the stores
-// are unconditional buffer stores, so the count is exact), and vmcnt counts
-// them in order.
-template <int C, int ST, int D, int K = 0>
+// z + 1, C copies per plane, ST stores per plane formed and LD loads issued
+// per step (before the step's copies) by this wave.  In issue order, what
+// follows those copies is exactly: the loads and copies of the D - 1 later
+// steps (k of them so far) and the stores of the last k + 1 planes formed
+// (the stores and loads are unconditional buffer accesses, so the count is
+// exact; if the loads were issued after the copies the wait would only be
+// longer), and vmcnt counts them in order.
+template <int C, int ST, int D, int LD, int K = 0>
 __device__ __forceinline__ void col_wait_plane(int k) {
   if constexpr (K == D - 1) {
-    col_wait<(D - 1) * C + ST * D>();
+    col_wait<(D - 1) * C + ST + K * (ST + LD)>();
   } else {
-    if (k == K) col_wait<(D - 1) * C + ST * (K + 1)>();
-    else col_wait_plane<C, ST, D, K + 1>(k);
+    if (k == K) col_wait<(D - 1) * C + ST + K * (ST + LD)>();
+    else col_wait_plane<C, ST, D, LD, K + 1>(k);
   }
 }
-// the same for wave w (wave-uniform) issuing CC::C<w> copies per stage
-template <typename CC, int ST, int D>
+// the same for wave w (wave-uniform) issuing CC::C<w> copies per stage and
+// LD loads per step just before them
+template <typename CC, int ST, int D, int LD>
 __device__ __forceinline__ void col_wait_wave(int w, int k) {
   switch (w) {
-    case 0: col_wait_plane<CC::template C<0>, ST, D>(k); break;
-    case 1: col_wait_plane<CC::template C<1>, ST, D>(k); break;
-    case 2: col_wait_plane<CC::template C<2>, ST, D>(k); break;
-    default: col_wait_plane<CC::template C<3>, ST, D>(k); break;
+    case 0: col_wait_plane<CC::template C<0>, ST, D, LD>(k); break;
+    case 1: col_wait_plane<CC::template C<1>, ST, D, LD>(k); break;
+    case 2: col_wait_plane<CC::template C<2>, ST, D, LD>(k); break;
+    default: col_wait_plane<CC::template C<3>, ST, D, LD>(k); break;
+  }
+}
+// Wait until no more than wave w's copies of one stage are in flight.
+template <typename CC, int EXTRA>
+__device__ __forceinline__ void col_wait_copies(int w) {
+  switch (w) {
+    case 0: col_wait<CC::template C<0> + EXTRA>(); break;
+    case 1: col_wait<CC::template C<1> + EXTRA>(); break;
+    case 2: col_wait<CC::template C<2> + EXTRA>(); break;
+    default: col_wait<CC::template C<3> + EXTRA>(); break;
   }
 }
 // Wait until wave w's copies of the first of the D + 1 stages issued have
@@ -672,6 +699,15 @@ __device__ __forceinline__ void col_part(const __attribute__((address_space(3)))
     acc[1] = fma_t(w, xv[j].y, acc[1]);
     acc[2] = fma_t(w, xv[j].z, acc[2]);
     acc[3] = fma_t(w, xv[j].w, acc[3]);
+  }
+}
+__device__ __forceinline__ void col_part(const __attribute__((address_space(3))) double *c,
+                                         const double (&xv)[9][4], double (&acc)[4]) {
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    const double w = c[j];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = fma_t(w, xv[j][q], acc[q]);
   }
 }
 __device__ __forceinline__ void col_part(const __attribute__((address_space(3))) double *c,
@@ -1191,22 +1227,35 @@ __device__ inline void publish_col(const double (&v)[ColGeom<V>::VEC], double *p
 //   MODE kColCG (the CG operator (a)): q = M p + dtau (K + h R) p and the
 //     partial p.q (m: the node, dtau its step);
 //   MODE kColF: F_m = h g - (K + h R) T_m for every scenario (FP64 only;
-//     g of a row is value 27 of its R stencil).
+//     g of a row is value 27 of its R stencil);
+//   MODE kColRefine (the FP32 form's refinement update, V = double): the
+//     FP32 correction d = x32 staged, FP64 stencils and sums: T_m += d,
+//     r64 -= M d + dtau (K + h R) d and the partial r64.r64, for the
+//     scenarios still refining.
 // Where a row of S values is a multiple of 16 bytes, a lane stores its 16
 // bytes at once (the values of idle scenarios too, which no later step
-// reads); otherwise each value apart, only where its scenario is on.
-constexpr int kColCG = 0, kColF = 1;
+// reads, or in kColRefine the values it loaded); otherwise each value apart,
+// only where its scenario is on.
+constexpr int kColCG = 0, kColF = 1, kColRefine = 2;
+template <int MODE, typename V>
+using ColX = typename std::conditional<MODE == kColRefine, float, V>::type;
 template <int TIMING, typename V, int UB, int D, int MODE = kColCG>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ColOcc<V, D, UB>::W)))
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(ColOcc<ColX<MODE, V>, V, D, UB>::W)))
 void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
-  static_assert(MODE == kColCG || sizeof(V) == 8, "F in FP64");
-  using G = ColGeom<V>;
-  using CC = ColCopies<V, UB>;
-  using V16 = typename ColVec<V>::V16;
-  constexpr int VEC = G::VEC, VB = G::VB;
-  constexpr int ST = UB == 16 ? 1 : VEC;  // stores per step
-  constexpr int NX = ColLds<V, D>::NX, NR = ColLds<V, D>::NR;
-  __shared__ ColLds<V, D> L;
+  static_assert(MODE == kColCG || sizeof(V) == 8, "F and the refinement in FP64");
+  using XV = ColX<MODE, V>;  // staged values
+  using G = ColGeom<XV, V>;
+  using CC = ColCopies<XV, V, UB>;
+  using X16 = typename ColVec<XV>::V16;
+  constexpr int VEC = G::VEC, VB = G::VB, RVB = G::RVB;
+  constexpr bool REF = MODE == kColRefine;
+  // stores per step: the output row (REF: T_m and r64, also copied into LDS
+  // one step ahead)
+  constexpr int ST = (REF ? 2 * VEC * RVB / 16 : 1) * (UB == 16 ? 1 : (REF ? 16 / RVB : VEC));
+  constexpr int LD = REF ? 2 * VEC * RVB / UB : 0;  // copies of the loaded rows
+  constexpr int NX = ColLds<XV, V, D>::NX, NR = ColLds<XV, V, D>::NR;
+  __shared__ typename std::conditional<REF, ColLdsIO<XV, V, D>, ColLds<XV, V, D>>::type L;
   const int S = a.S, lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int T = a.op.ncol_items * G::H, xcd = blockIdx.x % kXcd, local = blockIdx.x / kXcd;
@@ -1219,81 +1268,139 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
   bool on[VEC], any = false;
 #pragma unroll
   for (int i = 0; i < VEC; ++i) {
-    const int s = s0 + i;
-    on[i] = has && ((TIMING || MODE == kColF) ? s < S : lane_on(a.sc, s, S));
+    const int s = s0 + i, sc = s < S ? s : 0;
+    if constexpr (REF) on[i] = has && sweeping(a.sc, s, S) && a.sc->ref_done[sc] == 0;
+    else on[i] = has && ((TIMING || MODE == kColF) ? s < S : lane_on(a.sc, s, S));
     const V hv = (V)lane_h(a, s);
     h[i] = on[i] ? hv : V(0);
     any |= on[i];
   }
   const V dt = (V)dtau;
-  const V *xsrc;
+  const XV *xsrc;
   V *qdst;
   if constexpr (MODE == kColCG) {
     xsrc = ColVec<V>::p(a);
     qdst = ColVec<V>::q(a);
-  } else {
-    xsrc = reinterpret_cast<const V *>(a.T[m]);
+  } else if constexpr (MODE == kColF) {
+    xsrc = reinterpret_cast<const XV *>(a.T[m]);
     qdst = reinterpret_cast<V *>(a.F[m]);
+  } else {
+    xsrc = a.x32;
+    qdst = reinterpret_cast<V *>(a.T[m]);
   }
+  const unsigned obytes = (unsigned)(a.N * S) * (unsigned)RVB;  // an output vector
   const __amdgpu_buffer_rsrc_t qres =
-      __builtin_amdgcn_make_buffer_rsrc(qdst, 0, (int)(a.N * S * VB), 0x00020000);
+      __builtin_amdgcn_make_buffer_rsrc(qdst, 0, (int)obytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rres =
+      __builtin_amdgcn_make_buffer_rsrc(REF ? (void *)a.r64 : (void *)qdst, 0, (int)obytes,
+                                        0x00020000);
   if (__syncthreads_or(any)) {
     const ColItem it = col_item(a.op, G::H == 1 ? t : t / G::H);
     const int r = w * 4 + lr, lx = r % kColFX, ly = r / kColFX;
     // the row's (-1, -1) halo row, in values of the staged rows
     const int lb = (ly * (kColFX + 2) + lx) * G::SW + (lane & 15) * VEC;
     const bool rok = (it.x0 + lx < it.nx) & (it.y0 + ly < it.ny);
+    const unsigned pstep = (unsigned)(it.nx * it.ny);  // rows between planes
     // Step z reads plane z + 1 and completes row z; steps z0 - 2 and z0 - 1
     // only start rows z0 and z0 + 1 (what they add to rows below z0 is never
     // used).
     const int zb = it.z0 - 2;
-    ColIssue<V, UB, D> ci;
+    // REF: T_m and r64 of row z, copied into the wave's LDS area during step
+    // z - 1 (a copy outside the run or the body reads past the buffer:
+    // zeros, never used).  Copy k moves 16 (UB = 4: 4) bytes per lane: the
+    // lane's k-th unit of its T values (k < LD / 2), else of its r64 values,
+    // to io + w 4096 + k 64 UB + lane UB.
+    auto load_row = [&](int z) {
+      if constexpr (REF) {
+        const bool in = rok & (z >= it.z0) & (z < it.z1);
+        const unsigned row = (unsigned)(it.off + it.x0 + lx + it.nx * (it.y0 + ly + it.ny * z));
+        const unsigned off = (row * (unsigned)S + (unsigned)s0) * (unsigned)RVB;
+        char *dst = reinterpret_cast<char *>(&L.io[0]) + w * 4096;
+#pragma unroll
+        for (int k = 0; k < LD; ++k) {
+          const int u = k % (LD / 2);  // unit of the lane's values
+          const bool ok = in & (UB == 16 || s0 + u * UB / RVB < S);
+          const unsigned o = (off + (unsigned)(u * UB)) | ((unsigned)!ok << 31);
+          auto *d = (__attribute__((address_space(3))) void *)(dst + k * 64 * UB);
+          if constexpr (UB == 16)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(k < LD / 2 ? qres : rres, d, 16, o, 0, 0, 0);
+          else
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(k < LD / 2 ? qres : rres, d, 4, o, 0, 0, 0);
+        }
+      }
+    };
+    ColIssue<XV, V, UB, D> ci;
     ci.init(a, xsrc, it, w, hs);
+    load_row(zb);                                  // (never used: keeps the count per step)
     for (int q = 0; q <= D; ++q) ci.issue(it, L);  // stages z0 - 2 .. z0 - 2 + D
     col_wait_first<CC, D>(w);
     col_barrier();
     // K and R sums of rows z, z + 1, z + 2 (a: z, b: z + 1, c: z + 2)
     V ka[VEC] = {}, kb4[VEC] = {}, ra[VEC] = {}, rb4[VEC] = {};
-    V16 own = {};  // x of row z (plane z's centre)
+    X16 own = {};  // x of row z (plane z's centre)
     // ring slots as ColIssue lays them out: plane z + 1 (stage z) in plane
     // slot (z - zb) mod NX, the record of plane z in slot (z - z0) mod NR
-    constexpr unsigned XB = ColIssue<V, UB, D>::XB, RB = ColIssue<V, UB, D>::RB;
+    constexpr unsigned XB = ColIssue<XV, V, UB, D>::XB, RB = ColIssue<XV, V, UB, D>::RB;
     auto next_r = [&](unsigned o) { return o + RB == NR * RB ? 0u : o + RB; };
     unsigned xro = 0, r0o = (NR - 2) * RB;  // step zb: plane slot 0, record z0 - 2
     const char *lxb = reinterpret_cast<const char *>(&L.x[0][0]) + lb * VB;
     // the row's stencils: an LDS address the compiler may not split into a
     // constant part (else each pair of coefficient reads gets its own add)
     using lds_char = const __attribute__((address_space(3))) char;
-    lds_char *lrb = (lds_char *)(reinterpret_cast<const char *>(&L.rec[0][0]) + r * kStencil * VB);
-    lds_char *lrr = lrb + kColRows * kStencil * VB;  // its R stencils, after the K record
+    lds_char *lrb = (lds_char *)(reinterpret_cast<const char *>(&L.rec[0][0]) + r * kStencil * RVB);
+    lds_char *lrr = lrb + kColRows * kStencil * RVB;  // its R stencils, after the K record
     asm volatile("" : "+v"(lrb), "+v"(lrr));
     for (int z = zb; z < it.z1; ++z) {
-      const V *xs = reinterpret_cast<const V *>(lxb + xro);
-      V16 xv[9];
+      const XV *xs = reinterpret_cast<const XV *>(lxb + xro);
+      X16 xv[9];
 #pragma unroll
       for (int j = 0; j < 9; ++j)
-        xv[j] = *reinterpret_cast<const V16 *>(xs + ((j / 3) * (kColFX + 2) + j % 3) * G::SW);
+        xv[j] = *reinterpret_cast<const X16 *>(xs + ((j / 3) * (kColFX + 2) + j % 3) * G::SW);
       const unsigned r1o = next_r(r0o), r2o = next_r(r1o);
       using lds_v = const __attribute__((address_space(3))) V;
       lds_v *c2 = reinterpret_cast<lds_v *>(lrb + r2o);
       lds_v *c1 = reinterpret_cast<lds_v *>(lrb + r1o);
       lds_v *c0 = reinterpret_cast<lds_v *>(lrb + r0o);
       V kc[VEC] = {}, rc[VEC] = {};
-      col_part(c2, xv, kc);       // row z + 2: dz = -1
-      col_part(c1 + 9, xv, kb4);  // row z + 1: dz = 0
-      col_part(c0 + 18, xv, ka);  // row z: dz = +1
-      const V m2 = c2[kStencil - 1], m1 = c1[kStencil - 1], m0 = c0[kStencil - 1];
-      // rows with R entries (mass < 0)
-      if (m2 < V(0)) col_part(reinterpret_cast<lds_v *>(lrr + r2o), xv, rc);
-      if (m1 < V(0)) col_part(reinterpret_cast<lds_v *>(lrr + r1o) + 9, xv, rb4);
-      if (m0 < V(0)) col_part(reinterpret_cast<lds_v *>(lrr + r0o) + 18, xv, ra);
+      V m2, m1, m0;
+      if constexpr (REF) {  // FP32 staged values, FP64 sums: each value widened once
+        double xd[9][VEC];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+          XV o4[VEC];
+          ColVec<XV>::split(xv[j], o4);
+#pragma unroll
+          for (int q = 0; q < VEC; ++q) xd[j][q] = (double)o4[q];
+        }
+        col_part(c2, xd, kc);       // row z + 2: dz = -1
+        col_part(c1 + 9, xd, kb4);  // row z + 1: dz = 0
+        col_part(c0 + 18, xd, ka);  // row z: dz = +1
+        m2 = c2[kStencil - 1], m1 = c1[kStencil - 1], m0 = c0[kStencil - 1];
+        if (m2 < V(0)) col_part(reinterpret_cast<lds_v *>(lrr + r2o), xd, rc);
+        if (m1 < V(0)) col_part(reinterpret_cast<lds_v *>(lrr + r1o) + 9, xd, rb4);
+        if (m0 < V(0)) col_part(reinterpret_cast<lds_v *>(lrr + r0o) + 18, xd, ra);
+      } else {
+        col_part(c2, xv, kc);       // row z + 2: dz = -1
+        col_part(c1 + 9, xv, kb4);  // row z + 1: dz = 0
+        col_part(c0 + 18, xv, ka);  // row z: dz = +1
+        m2 = c2[kStencil - 1], m1 = c1[kStencil - 1], m0 = c0[kStencil - 1];
+        // rows with R entries (mass < 0)
+        if (m2 < V(0)) col_part(reinterpret_cast<lds_v *>(lrr + r2o), xv, rc);
+        if (m1 < V(0)) col_part(reinterpret_cast<lds_v *>(lrr + r1o) + 9, xv, rb4);
+        if (m0 < V(0)) col_part(reinterpret_cast<lds_v *>(lrr + r0o) + 18, xv, ra);
+      }
       // row z complete
       V ow[VEC];
-      ColVec<V>::split(own, ow);
+      {
+        XV o4[VEC];
+        ColVec<XV>::split(own, o4);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) ow[q] = (V)o4[q];
+      }
       const V mass = fabs(m0);
       const bool row_in = rok & (z >= it.z0);
       const unsigned row = (unsigned)(it.off + it.x0 + lx + it.nx * (it.y0 + ly + it.ny * z));
-      V qv[VEC];
+      V qv[VEC], rn[VEC];
       if constexpr (MODE == kColCG) {
 #pragma unroll
         for (int q = 0; q < VEC; ++q) {
@@ -1302,43 +1409,86 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
           const V y = fma_t(h[q], ra[q], ka[q]);
           qv[q] = fma_t(mass, ow[q], dt * y);
         }
-      } else {
+      } else if constexpr (MODE == kColF) {
         // g of the row: after its R stencil (rows without one have g = 0)
         const V g = m0 < V(0) ? reinterpret_cast<lds_v *>(lrr + r0o)[kStencil - 1] : V(0);
 #pragma unroll
         for (int q = 0; q < VEC; ++q) qv[q] = fma_t(h[q], g, -fma_t(h[q], ra[q], ka[q]));
-      }
-      // p.q over the run's rows (wave-uniform test: the rows below the run
-      // come from records that were never copied); a masked lane adds an
-      // exact zero (rows outside the body have zero records, so finite q)
-      if (MODE == kColCG && z >= it.z0) {
+      } else {
+        // T += d, r -= M d + dtau L d where the scenario still refines; the
+        // loaded values elsewhere.  Row z's values landed once no more than
+        // the copies of the stage issued after them are in flight.
+        col_wait_copies<CC, 0>(w);
+        V tl[VEC], rl[VEC];
+        {
+          const char *src = reinterpret_cast<const char *>(&L.io[0]) + w * 4096 + lane * UB;
+#pragma unroll
+          for (int k = 0; k < LD; ++k) {
+            const int u = k % (LD / 2);
+            char *dv = reinterpret_cast<char *>(k < LD / 2 ? tl : rl) + u * UB;
+            if constexpr (UB == 16)
+              *reinterpret_cast<uint4 *>(dv) = *reinterpret_cast<const uint4 *>(src + k * 64 * UB);
+            else
+              *reinterpret_cast<unsigned *>(dv) =
+                  *reinterpret_cast<const unsigned *>(src + k * 64 * UB);
+          }
+        }
 #pragma unroll
         for (int q = 0; q < VEC; ++q) {
-          const V om = (rok & on[q]) ? ow[q] : V(0);
-          v[q] = fma_t((double)om, (double)qv[q], v[q]);
+          const V y = fma_t(h[q], ra[q], ka[q]);
+          const V rq = rl[q] - fma_t(mass, ow[q], dt * y);
+          qv[q] = on[q] ? tl[q] + ow[q] : tl[q];
+          rn[q] = on[q] ? rq : rl[q];
+        }
+      }
+      // p.q (r.r) over the run's rows (wave-uniform test: the rows below the
+      // run come from records that were never copied); a masked lane adds an
+      // exact zero (rows outside the body have zero records, so finite q)
+      if (MODE != kColF && z >= it.z0) {
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+          if constexpr (REF) {
+            const V rr = (rok & on[q]) ? rn[q] : V(0);
+            v[q] = fma_t(rr, rr, v[q]);
+          } else {
+            const V om = (rok & on[q]) ? ow[q] : V(0);
+            v[q] = fma_t((double)om, (double)qv[q], v[q]);
+          }
         }
       }
       // a fixed number of stores per step whatever the masks (a masked
       // store's offset lies past the buffer, so it is dropped)
-      const unsigned off = (row * (unsigned)S + (unsigned)s0) * (unsigned)VB;
-      if constexpr (ST == 1) {
-        typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-        u32x4 val;
-        __builtin_memcpy(&val, qv, 16);
+      const unsigned off = (row * (unsigned)S + (unsigned)s0) * (unsigned)RVB;
+      typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+      typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+      if constexpr (UB == 16) {
         const bool st = row_in & (s0 < S);
-        __builtin_amdgcn_raw_buffer_store_b128(val, qres, (int)(off | ((unsigned)!st << 31)), 0, 0);
+#pragma unroll
+        for (int k = 0; k < VEC * RVB / 16; ++k) {
+          const int o = (int)((off + 16u * k) | ((unsigned)!st << 31));
+          u32x4 val;
+          __builtin_memcpy(&val, &qv[k * 16 / RVB], 16);
+          __builtin_amdgcn_raw_buffer_store_b128(val, qres, o, 0, 0);
+          if constexpr (REF) {
+            __builtin_memcpy(&val, &rn[k * 16 / RVB], 16);
+            __builtin_amdgcn_raw_buffer_store_b128(val, rres, o, 0, 0);
+          }
+        }
       } else {
 #pragma unroll
         for (int q = 0; q < VEC; ++q) {
           const bool st = row_in & on[q];
-          const int o = (int)((off + (unsigned)(VB * q)) | ((unsigned)!st << 31));
-          if constexpr (VB == 4) {
+          const int o = (int)((off + (unsigned)(RVB * q)) | ((unsigned)!st << 31));
+          if constexpr (RVB == 4) {
             __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(qv[q]), qres, o, 0, 0);
           } else {
-            typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
             u32x2 val;
             __builtin_memcpy(&val, &qv[q], 8);
             __builtin_amdgcn_raw_buffer_store_b64(val, qres, o, 0, 0);
+            if constexpr (REF) {
+              __builtin_memcpy(&val, &rn[q], 8);
+              __builtin_amdgcn_raw_buffer_store_b64(val, rres, o, 0, 0);
+            }
           }
         }
       }
@@ -1350,16 +1500,17 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
         ra[q] = rb4[q];
         rb4[q] = rc[q];
       }
-      col_wait_wave<CC, ST, D>(w, min(z - zb, D - 1));
-      col_barrier();  // stage z + 1 landed; plane z + 1 and the record of z free
+      col_wait_wave<CC, ST, D, LD>(w, min(z - zb, D - 1));
+      col_barrier();    // stage z + 1 landed; plane z + 1 and the record of z free
+      load_row(z + 1);  // (REF)
       ci.issue(it, L);  // stage z + 1 + D
       xro = xro + XB == NX * XB ? 0u : xro + XB;
       r0o = r1o;
     }
   }
   __syncthreads();  // every copy landed before the LDS is reused (or freed)
-  if constexpr (MODE == kColCG)
-    publish_col<V>(v, a.partial, gridDim.x, S, s0, reinterpret_cast<double *>(L.x[0]));
+  if constexpr (MODE != kColF)
+    publish_col<XV>(v, a.partial, gridDim.x, S, s0, reinterpret_cast<double *>(L.x[0]));
 }
 
 // ---------------------------------------------------------------------------
@@ -1881,8 +2032,8 @@ void blaunch_quad_resid(const BatchArgs &a, int k, hipStream_t st) {
 }
 
 int col_workgroups_per_cu(int fp32, int depth) {
-  if (fp32) return depth == 1 ? ColOcc<float, 1>::W : ColOcc<float, kColDepth>::W;
-  return depth == 1 ? ColOcc<double, 1>::W : ColOcc<double, kColDepth>::W;
+  if (fp32) return depth == 1 ? ColOcc<float, float, 1>::W : ColOcc<float, float, kColDepth>::W;
+  return depth == 1 ? ColOcc<double, double, 1>::W : ColOcc<double, double, kColDepth>::W;
 }
 
 // the column sweep runs the operator of the context's form (its records hold
@@ -2017,9 +2168,18 @@ void blaunch_solve(const BatchArgs &a, const BSolve &sv, hipStream_t st) {
     kb_inner_init<<<a.grid, kBlock, 0, st>>>(a, dtau);
     RED(a.grid, 4, 0, 0, sv.slot, sv.inner_rtol);
     cg_iterations<float>(a, m, dtau, sv.slot, sv.budget, sv.inner_rtol, st);
-    if (vec16<float>(a)) kb_refine_update<16, true><<<a.sgrid32, kBlock, 0, st>>>(a, m, dtau);
-    else kb_refine_update<4, false><<<a.sgrid32, kBlock, 0, st>>>(a, m, dtau);
-    RED(a.sgrid32, 5, r, r == sv.rounds - 1, sv.slot, sv.refine_rtol);
+    int gr = a.sgrid32;
+    if (a.cgrid > 0 && a.op.kcol64) {  // the FP64-stencil column sweep of the correction
+      gr = a.cgrid;
+      if (vec16<float>(a))
+        kb_pcg_a_col<0, double, 16, kColDepth, kColRefine><<<gr, kBlock, 0, st>>>(a, m, dtau);
+      else kb_pcg_a_col<0, double, 4, kColDepth, kColRefine><<<gr, kBlock, 0, st>>>(a, m, dtau);
+    } else if (vec16<float>(a)) {
+      kb_refine_update<16, true><<<gr, kBlock, 0, st>>>(a, m, dtau);
+    } else {
+      kb_refine_update<4, false><<<gr, kBlock, 0, st>>>(a, m, dtau);
+    }
+    RED(gr, 5, r, r == sv.rounds - 1, sv.slot, sv.refine_rtol);
   }
 }
 #undef RED
