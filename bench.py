@@ -41,15 +41,15 @@ COUNTER_TRAFFIC = {
     },
     ("ensemble-64x714798", 1): {
         "source": "batch_kernels.hip",
-        "sha256": "39aea1f5ca6218320f1bd59a0116fef169a2baced3fc5df01015c1b078c960ac",
-        "fetch_kib": 162801.7, "fetch_scale": 1.99974,
-        "write_kib": 181808.0, "write_scale": 1.0,
+        "sha256": "0bb08afdbb7853433bc65aad951788d5d408ace9ddbfeae0b1b33af679177e50",
+        "fetch_kib": 163424.0, "fetch_scale": 1.99973,
+        "write_kib": 181778.4, "write_scale": 1.0,
     },
     ("ensemble-64x714798", 0): {
         "source": "batch_kernels.hip",
-        "sha256": "39aea1f5ca6218320f1bd59a0116fef169a2baced3fc5df01015c1b078c960ac",
-        "fetch_kib": 395489.2, "fetch_scale": 1.99974,
-        "write_kib": 361188.6, "write_scale": 1.0,
+        "sha256": "0bb08afdbb7853433bc65aad951788d5d408ace9ddbfeae0b1b33af679177e50",
+        "fetch_kib": 395483.2, "fetch_scale": 1.99974,
+        "write_kib": 361187.5, "write_scale": 1.0,
     },
 }
 
