@@ -983,40 +983,6 @@ __global__ __launch_bounds__(kBlock) void kb_init_corr(BatchArgs a, int m, doubl
   bpublish<NV>(v, a.partial, gridDim.x, S);
 }
 
-// inner init: r32 = r64, d = 0, p = dinv r32; partial r.z, r.r
-__global__ __launch_bounds__(kBlock) void kb_inner_init(BatchArgs a, double dtau) {
-  const int s = threadIdx.x & 63, S = a.S;
-  double v[2] = {0.0, 0.0};
-  if (sweeping(a.sc, s, S) && !a.sc->ref_done[s]) {
-    const double h = a.h[s];
-    // kRowsAhead rows per pass, their loads issued before the first store
-    for (RowRange rr = xcd_rows(a.N); rr.row < rr.end; rr.row += kRowsAhead * rr.stride) {
-      double r64[kRowsAhead], di[kRowsAhead];
-#pragma unroll
-      for (int u = 0; u < kRowsAhead; ++u) {
-        const int64_t row = rr.row + u * rr.stride;
-        if (row >= rr.end) continue;
-        r64[u] = a.r64[row * S + s];
-        di[u] = bdinv(a, row, h, dtau);
-      }
-#pragma unroll
-      for (int u = 0; u < kRowsAhead; ++u) {
-        const int64_t row = rr.row + u * rr.stride;
-        if (row >= rr.end) continue;
-        const int64_t i = row * S + s;
-        const float r = (float)r64[u];
-        const float z = (float)di[u] * r;
-        a.r32[i] = r;
-        a.x32[i] = 0.0f;
-        a.p32[i] = z;
-        v[0] += (double)r * (double)z;
-        v[1] += (double)r * (double)r;
-      }
-    }
-  }
-  bpublish<2>(v, a.partial, gridDim.x, S);
-}
-
 // x64 += d; r64 -= A d with the FP64 operator on the FP32 correction d
 // (staged as FP32); partial r.r
 template <int UB, bool AL>
@@ -1700,6 +1666,75 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_c(BatchArgs a, int m, double dt
   }
 }
 
+// inner init of the FP32 form: r32 = r64, x32 = 0, p32 = dinv r32; partial
+// r.z, r.r.  Row groups as in (b) (16-byte accesses); a lane's values of
+// scenarios that do not refine are written too (no later step of theirs
+// reads them).
+template <bool AL, int GA>
+__global__ __launch_bounds__(kBlock) void kb_inner_init(BatchArgs a, double dtau) {
+  using LY = Lanes<float>;
+  constexpr int VEC = LY::VEC, RPW = LY::RPW;
+  const int S = a.S, lane = threadIdx.x & 63;
+  const int lr = lane / LY::LPR, s0 = (lane % LY::LPR) * VEC;
+  bool on[VEC], any = false;
+  double h[VEC];
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) {
+    const int s = s0 + k, sc = s < S ? s : 0;
+    on[k] = sweeping(a.sc, s, S) & (a.sc->ref_done[sc] == 0);
+    h[k] = on[k] ? a.h[sc] : 0.0;
+    any |= on[k];
+  }
+  double v[2][VEC] = {};
+  const int64_t N = a.N, G = (N + RPW - 1) / RPW;
+  if (__ballot(any) != 0ull) {
+    for (GroupRange gr = xcd_groups(G); gr.g < gr.end; gr.g += GA * gr.stride) {
+      double rs[GA][VEC], ms[GA], kd[GA], rd[GA];
+      bool ok[GA];
+#pragma unroll
+      for (int u = 0; u < GA; ++u) {
+        const int64_t g = gr.g + u * gr.stride, row = g * RPW + lr;
+        ok[u] = (g < gr.end) & (row < N) & (s0 < S);
+        const int64_t rw = ok[u] ? row : 0, base = rw * S + (s0 < S ? s0 : 0);
+        if constexpr (AL) {
+          const double2 d0 = *reinterpret_cast<const double2 *>(a.r64 + base);
+          const double2 d1 = *reinterpret_cast<const double2 *>(a.r64 + base + 2);
+          rs[u][0] = d0.x;
+          rs[u][1] = d0.y;
+          rs[u][2] = d1.x;
+          rs[u][3] = d1.y;
+        } else {
+#pragma unroll
+          for (int k = 0; k < VEC; ++k) rs[u][k] = s0 + k < S ? a.r64[base + k] : 0.0;
+        }
+        ms[u] = a.mass[rw];
+        kd[u] = a.Kd[rw];
+        rd[u] = a.Rd[rw];
+      }
+#pragma unroll
+      for (int u = 0; u < GA; ++u) {
+        if (!ok[u]) continue;
+        const int64_t row = (gr.g + u * gr.stride) * RPW + lr, base = row * S + s0;
+        float di[VEC], r[VEC], z[VEC];
+        const float zero[VEC] = {};
+        dinv_row<float, VEC>(ms[u], kd[u], rd[u], h, dtau, di);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+          r[k] = (float)rs[u][k];
+          z[k] = di[k] * r[k];
+          if (!on[k]) continue;
+          v[0][k] = fma_t((double)r[k], (double)z[k], v[0][k]);
+          v[1][k] = fma_t((double)r[k], (double)r[k], v[1][k]);
+        }
+        vstore<float, VEC, AL>(a.r32, base, s0, S, r);
+        vstore<float, VEC, AL>(a.x32, base, s0, S, zero);
+        vstore<float, VEC, AL>(a.p32, base, s0, S, z);
+      }
+    }
+  }
+  publish_groups<2, VEC, RPW>(v, a.partial, gridDim.x, S);
+}
+
 // ---------------------------------------------------------------------------
 // interface substeps, per scenario (tables with the scenario index fastest)
 // ---------------------------------------------------------------------------
@@ -2165,8 +2200,10 @@ void blaunch_solve(const BatchArgs &a, const BSolve &sv, hipStream_t st) {
   launch_init<2>(a, sv.pred, m, dtau, st);
   RED(npi, 3, 0, 0, sv.slot, sv.refine_rtol);
   for (int r = 0; r < sv.rounds; ++r) {
-    kb_inner_init<<<a.grid, kBlock, 0, st>>>(a, dtau);
-    RED(a.grid, 4, 0, 0, sv.slot, sv.inner_rtol);
+    const int gi = pcg_b_grid<float>(a);
+    if (vec16<float>(a)) kb_inner_init<true, kGroupsAhead><<<gi, kBlock, 0, st>>>(a, dtau);
+    else kb_inner_init<false, kGroupsAhead><<<gi, kBlock, 0, st>>>(a, dtau);
+    RED(gi, 4, 0, 0, sv.slot, sv.inner_rtol);
     cg_iterations<float>(a, m, dtau, sv.slot, sv.budget, sv.inner_rtol, st);
     int gr = a.sgrid32;
     if (a.cgrid > 0 && a.op.kcol64) {  // the FP64-stencil column sweep of the correction
