@@ -41,15 +41,15 @@ COUNTER_TRAFFIC = {
     },
     ("ensemble-64x714798", 1): {
         "source": "batch_kernels.hip",
-        "sha256": "0bb08afdbb7853433bc65aad951788d5d408ace9ddbfeae0b1b33af679177e50",
-        "fetch_kib": 163424.0, "fetch_scale": 1.99973,
-        "write_kib": 181778.4, "write_scale": 1.0,
+        "sha256": "66fa5d3174fe41e10d59caabdd50e16f5f4cf3f226819435709ece02c5044ae8",
+        "fetch_kib": 162694.2, "fetch_scale": 1.99974,
+        "write_kib": 181808.0, "write_scale": 1.0,
     },
     ("ensemble-64x714798", 0): {
         "source": "batch_kernels.hip",
-        "sha256": "0bb08afdbb7853433bc65aad951788d5d408ace9ddbfeae0b1b33af679177e50",
-        "fetch_kib": 395483.2, "fetch_scale": 1.99974,
-        "write_kib": 361187.5, "write_scale": 1.0,
+        "sha256": "66fa5d3174fe41e10d59caabdd50e16f5f4cf3f226819435709ece02c5044ae8",
+        "fetch_kib": 395783.4, "fetch_scale": 1.99974,
+        "write_kib": 361187.1, "write_scale": 1.0,
     },
 }
 
