@@ -1169,21 +1169,24 @@ __global__ __launch_bounds__(kBlock) void kb_pcg_a(BatchArgs a, int m, double dt
 // The column sweep's partial p.q: as publish_groups_in, with the lane
 // mapping of the sweep (a lane's VEC scenarios start at s0; 16 lanes a row)
 // and exact zeros for the scenarios of the other half.
-template <typename V>
-__device__ inline void publish_col(const double (&v)[ColGeom<V>::VEC], double *partial, int grid,
-                                   int S, int s0, double *sh) {
+template <typename V, int K>
+__device__ inline void publish_col(const double (&v)[K][ColGeom<V>::VEC], double *partial,
+                                   int grid, int S, int s0, double *sh) {
   constexpr int VEC = ColGeom<V>::VEC;
   const int j = threadIdx.x >> 4;  // the lane's row of the workgroup
+  for (int k = 0; k < K; ++k) {
 #pragma unroll
-  for (int i = 0; i < VEC; ++i) {
-    sh[j * 64 + s0 + i] = v[i];
-    if constexpr (ColGeom<V>::H == 2) sh[j * 64 + (s0 ^ 32) + i] = 0.0;
-  }
-  __syncthreads();
-  if (threadIdx.x < (unsigned)S) {
-    double acc = 0.0;
-    for (int r = 0; r < kColRows; ++r) acc += sh[r * 64 + threadIdx.x];
-    partial[(size_t)threadIdx.x * grid + blockIdx.x] = acc;
+    for (int i = 0; i < VEC; ++i) {
+      sh[j * 64 + s0 + i] = v[k][i];
+      if constexpr (ColGeom<V>::H == 2) sh[j * 64 + (s0 ^ 32) + i] = 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)S) {
+      double acc = 0.0;
+      for (int r = 0; r < kColRows; ++r) acc += sh[r * 64 + threadIdx.x];
+      partial[((size_t)k * S + threadIdx.x) * grid + blockIdx.x] = acc;
+    }
+    __syncthreads();
   }
 }
 
@@ -1197,28 +1200,38 @@ __device__ inline void publish_col(const double (&v)[ColGeom<V>::VEC], double *p
 //   MODE kColRefine (the FP32 form's refinement update, V = double): the
 //     FP32 correction d = x32 staged, FP64 stencils and sums: T_m += d,
 //     r64 -= M d + dtau (K + h R) d and the partial r64.r64, for the
-//     scenarios still refining.
+//     scenarios still refining;
+//   MODE kColPred32 / kColPred64 (the predictor's solve initialisation,
+//     V = double): T_{m-1} staged, x0 = T_m = T_{m-1}, b = M T_{m-1} +
+//     dtau h g, r = b - (M + dtau (K + h R)) T_{m-1}; FP32 form: r64 = r and
+//     the partials r.r, b.b; FP64 form: r, p = dinv r and r.p, r.r, b.b
+//     (dinv from the row's own stencils: mass, K and R centre values), for
+//     the active scenarios.
 // Where a row of S values is a multiple of 16 bytes, a lane stores its 16
 // bytes at once (the values of idle scenarios too, which no later step
 // reads, or in kColRefine the values it loaded); otherwise each value apart,
 // only where its scenario is on.
-constexpr int kColCG = 0, kColF = 1, kColRefine = 2;
+constexpr int kColCG = 0, kColF = 1, kColRefine = 2, kColPred32 = 3, kColPred64 = 4;
 template <int MODE, typename V>
 using ColX = typename std::conditional<MODE == kColRefine, float, V>::type;
 template <int TIMING, typename V, int UB, int D, int MODE = kColCG>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(ColOcc<ColX<MODE, V>, V, D, UB>::W)))
 void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
-  static_assert(MODE == kColCG || sizeof(V) == 8, "F and the refinement in FP64");
+  static_assert(MODE == kColCG || sizeof(V) == 8, "F, the refinement and the predictor in FP64");
   using XV = ColX<MODE, V>;  // staged values
   using G = ColGeom<XV, V>;
   using CC = ColCopies<XV, V, UB>;
   using X16 = typename ColVec<XV>::V16;
   constexpr int VEC = G::VEC, VB = G::VB, RVB = G::RVB;
   constexpr bool REF = MODE == kColRefine;
-  // stores per step: the output row (REF: T_m and r64, also copied into LDS
-  // one step ahead)
-  constexpr int ST = (REF ? 2 * VEC * RVB / 16 : 1) * (UB == 16 ? 1 : (REF ? 16 / RVB : VEC));
+  constexpr bool PRED = MODE == kColPred32 || MODE == kColPred64;
+  // output vectors (REF: T_m and r64, also copied into LDS one step ahead;
+  // PRED: T_m and r64, or T_m, r and p), partial sums
+  constexpr int NOUT = MODE == kColPred64 ? 3 : ((REF || PRED) ? 2 : 1);
+  constexpr int NV = MODE == kColPred64 ? 3 : (MODE == kColPred32 ? 2 : 1);
+  // stores per step
+  constexpr int ST = NOUT * (UB == 16 ? VEC * RVB / 16 : VEC);
   constexpr int LD = REF ? 2 * VEC * RVB / UB : 0;  // copies of the loaded rows
   constexpr int NX = ColLds<XV, V, D>::NX, NR = ColLds<XV, V, D>::NR;
   __shared__ typename std::conditional<REF, ColLdsIO<XV, V, D>, ColLds<XV, V, D>>::type L;
@@ -1230,12 +1243,13 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
   const int hs = (G::H == 1 ? 0 : t % G::H) * G::SW;  // first scenario of the half
   const int lr = lane >> 4, s0 = hs + (lane & 15) * VEC;
   V h[VEC];
-  double v[VEC] = {};
+  double v[NV][VEC] = {};
   bool on[VEC], any = false;
 #pragma unroll
   for (int i = 0; i < VEC; ++i) {
     const int s = s0 + i, sc = s < S ? s : 0;
     if constexpr (REF) on[i] = has && sweeping(a.sc, s, S) && a.sc->ref_done[sc] == 0;
+    else if constexpr (PRED) on[i] = has && s < S && a.sc->active[sc] != 0;
     else on[i] = has && ((TIMING || MODE == kColF) ? s < S : lane_on(a.sc, s, S));
     const V hv = (V)lane_h(a, s);
     h[i] = on[i] ? hv : V(0);
@@ -1250,16 +1264,27 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
   } else if constexpr (MODE == kColF) {
     xsrc = reinterpret_cast<const XV *>(a.T[m]);
     qdst = reinterpret_cast<V *>(a.F[m]);
-  } else {
+  } else if constexpr (REF) {
     xsrc = a.x32;
     qdst = reinterpret_cast<V *>(a.T[m]);
+  } else {
+    xsrc = reinterpret_cast<const XV *>(a.T[m - 1]);
+    qdst = reinterpret_cast<V *>(a.T[m]);
+  }
+  // further outputs: REF and kColPred32 r64, kColPred64 r and p
+  void *odst1 = (void *)qdst, *odst2 = (void *)qdst;
+  if constexpr (REF || MODE == kColPred32) odst1 = (void *)a.r64;
+  if constexpr (MODE == kColPred64) {
+    odst1 = (void *)a.r;
+    odst2 = (void *)a.p;
   }
   const unsigned obytes = (unsigned)(a.N * S) * (unsigned)RVB;  // an output vector
   const __amdgpu_buffer_rsrc_t qres =
       __builtin_amdgcn_make_buffer_rsrc(qdst, 0, (int)obytes, 0x00020000);
   const __amdgpu_buffer_rsrc_t rres =
-      __builtin_amdgcn_make_buffer_rsrc(REF ? (void *)a.r64 : (void *)qdst, 0, (int)obytes,
-                                        0x00020000);
+      __builtin_amdgcn_make_buffer_rsrc(odst1, 0, (int)obytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t pres =
+      __builtin_amdgcn_make_buffer_rsrc(odst2, 0, (int)obytes, 0x00020000);
   if (__syncthreads_or(any)) {
     const ColItem it = col_item(a.op, G::H == 1 ? t : t / G::H);
     const int r = w * 4 + lr, lx = r % kColFX, ly = r / kColFX;
@@ -1366,7 +1391,7 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
       const V mass = fabs(m0);
       const bool row_in = rok & (z >= it.z0);
       const unsigned row = (unsigned)(it.off + it.x0 + lx + it.nx * (it.y0 + ly + it.ny * z));
-      V qv[VEC], rn[VEC];
+      V qv[VEC], rn[VEC], pn[VEC];
       if constexpr (MODE == kColCG) {
 #pragma unroll
         for (int q = 0; q < VEC; ++q) {
@@ -1380,6 +1405,34 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
         const V g = m0 < V(0) ? reinterpret_cast<lds_v *>(lrr + r0o)[kStencil - 1] : V(0);
 #pragma unroll
         for (int q = 0; q < VEC; ++q) qv[q] = fma_t(h[q], g, -fma_t(h[q], ra[q], ka[q]));
+      } else if constexpr (PRED) {
+        // the row's g (after its R stencil) and, FP64 form, its Jacobi
+        // inverse from the stencils' centre values
+        lds_v *cr = reinterpret_cast<lds_v *>(lrr + r0o);
+        const V g = m0 < V(0) ? cr[kStencil - 1] : V(0);
+        const V kd = c0[13], rd = m0 < V(0) ? cr[13] : V(0);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+          const V Lx = fma_t(h[q], ra[q], ka[q]);
+          const V mt = mass * ow[q];
+          const V bq = fma_t(dt, h[q] * g, mt);
+          const V rq = bq - fma_t(dt, Lx, mt);
+          qv[q] = ow[q];  // x0 = T_{m-1}
+          rn[q] = rq;
+          if constexpr (MODE == kColPred64) pn[q] = dinv_of(mass, kd, rd, h[q], dt) * rq;
+          if (z >= it.z0) {
+            const V on_r = (rok & on[q]) ? rq : V(0), on_b = (rok & on[q]) ? bq : V(0);
+            if constexpr (MODE == kColPred64) {
+              const V on_p = (rok & on[q]) ? pn[q] : V(0);
+              v[0][q] = fma_t(on_r, on_p, v[0][q]);
+              v[1][q] = fma_t(on_r, on_r, v[1][q]);
+              v[2][q] = fma_t(on_b, on_b, v[2][q]);
+            } else {
+              v[0][q] = fma_t(on_r, on_r, v[0][q]);
+              v[1][q] = fma_t(on_b, on_b, v[1][q]);
+            }
+          }
+        }
       } else {
         // T += d, r -= M d + dtau L d where the scenario still refines; the
         // loaded values elsewhere.  Row z's values landed once no more than
@@ -1410,15 +1463,15 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
       // p.q (r.r) over the run's rows (wave-uniform test: the rows below the
       // run come from records that were never copied); a masked lane adds an
       // exact zero (rows outside the body have zero records, so finite q)
-      if (MODE != kColF && z >= it.z0) {
+      if ((MODE == kColCG || REF) && z >= it.z0) {
 #pragma unroll
         for (int q = 0; q < VEC; ++q) {
           if constexpr (REF) {
             const V rr = (rok & on[q]) ? rn[q] : V(0);
-            v[q] = fma_t(rr, rr, v[q]);
+            v[0][q] = fma_t(rr, rr, v[0][q]);
           } else {
             const V om = (rok & on[q]) ? ow[q] : V(0);
-            v[q] = fma_t((double)om, (double)qv[q], v[q]);
+            v[0][q] = fma_t((double)om, (double)qv[q], v[0][q]);
           }
         }
       }
@@ -1435,9 +1488,13 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
           u32x4 val;
           __builtin_memcpy(&val, &qv[k * 16 / RVB], 16);
           __builtin_amdgcn_raw_buffer_store_b128(val, qres, o, 0, 0);
-          if constexpr (REF) {
+          if constexpr (NOUT >= 2) {
             __builtin_memcpy(&val, &rn[k * 16 / RVB], 16);
             __builtin_amdgcn_raw_buffer_store_b128(val, rres, o, 0, 0);
+          }
+          if constexpr (NOUT >= 3) {
+            __builtin_memcpy(&val, &pn[k * 16 / RVB], 16);
+            __builtin_amdgcn_raw_buffer_store_b128(val, pres, o, 0, 0);
           }
         }
       } else {
@@ -1451,9 +1508,13 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
             u32x2 val;
             __builtin_memcpy(&val, &qv[q], 8);
             __builtin_amdgcn_raw_buffer_store_b64(val, qres, o, 0, 0);
-            if constexpr (REF) {
+            if constexpr (NOUT >= 2) {
               __builtin_memcpy(&val, &rn[q], 8);
               __builtin_amdgcn_raw_buffer_store_b64(val, rres, o, 0, 0);
+            }
+            if constexpr (NOUT >= 3) {
+              __builtin_memcpy(&val, &pn[q], 8);
+              __builtin_amdgcn_raw_buffer_store_b64(val, pres, o, 0, 0);
             }
           }
         }
@@ -1476,7 +1537,7 @@ void kb_pcg_a_col(BatchArgs a, int m, double dtau) {
   }
   __syncthreads();  // every copy landed before the LDS is reused (or freed)
   if constexpr (MODE != kColF)
-    publish_col<XV>(v, a.partial, gridDim.x, S, s0, reinterpret_cast<double *>(L.x[0]));
+    publish_col<XV, NV>(v, a.partial, gridDim.x, S, s0, reinterpret_cast<double *>(L.x[0]));
 }
 
 // ---------------------------------------------------------------------------
@@ -2182,6 +2243,13 @@ static void launch_init(const BatchArgs &a, bool pred, int m, double dtau, hipSt
     kb_init_corr<NV><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
     return;
   }
+  if (a.cgrid_f > 0) {  // the FP64 column sweep of T_{m-1}
+    constexpr int MODE = NV == 3 ? kColPred64 : kColPred32;
+    if (vec16<double>(a))
+      kb_pcg_a_col<0, double, 16, kColDepth, MODE><<<a.cgrid_f, kBlock, 0, st>>>(a, m, dtau);
+    else kb_pcg_a_col<0, double, 4, kColDepth, MODE><<<a.cgrid_f, kBlock, 0, st>>>(a, m, dtau);
+    return;
+  }
   if (vec16<double>(a)) kb_init_pred<NV, 16, true><<<a.sgrid64, kBlock, 0, st>>>(a, m, dtau);
   else kb_init_pred<NV, 4, false><<<a.sgrid64, kBlock, 0, st>>>(a, m, dtau);
 }
@@ -2189,7 +2257,8 @@ static void launch_init(const BatchArgs &a, bool pred, int m, double dtau, hipSt
 void blaunch_solve(const BatchArgs &a, const BSolve &sv, hipStream_t st) {
   const int m = sv.m;
   const double dtau = a.dtau_h[m];
-  const int npi = sv.pred ? a.sgrid64 : a.grid;  // workgroups of the init kernel
+  // workgroups of the init kernel
+  const int npi = sv.pred ? (a.cgrid_f > 0 ? a.cgrid_f : a.sgrid64) : a.grid;
   if (!a.fp32) {
     launch_init<3>(a, sv.pred, m, dtau, st);
     RED(npi, 0, 0, 0, sv.slot, sv.rtol);
