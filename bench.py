@@ -41,15 +41,15 @@ COUNTER_TRAFFIC = {
     },
     ("ensemble-64x714798", 1): {
         "source": "batch_kernels.hip",
-        "sha256": "66fa5d3174fe41e10d59caabdd50e16f5f4cf3f226819435709ece02c5044ae8",
-        "fetch_kib": 162694.2, "fetch_scale": 1.99974,
-        "write_kib": 181808.0, "write_scale": 1.0,
+        "sha256": "1b21e0b4a3e08570eb7c849a81cb0a89c86f515632f40207b220939f34fa3fc5",
+        "fetch_kib": 162508.9, "fetch_scale": 1.99973,
+        "write_kib": 181804.6, "write_scale": 1.0,
     },
     ("ensemble-64x714798", 0): {
         "source": "batch_kernels.hip",
-        "sha256": "66fa5d3174fe41e10d59caabdd50e16f5f4cf3f226819435709ece02c5044ae8",
-        "fetch_kib": 395783.4, "fetch_scale": 1.99974,
-        "write_kib": 361187.1, "write_scale": 1.0,
+        "sha256": "1b21e0b4a3e08570eb7c849a81cb0a89c86f515632f40207b220939f34fa3fc5",
+        "fetch_kib": 395352.4, "fetch_scale": 1.99974,
+        "write_kib": 361185.4, "write_scale": 1.0,
     },
 }
 
