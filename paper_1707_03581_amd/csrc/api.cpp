@@ -710,7 +710,12 @@ mrsdc_status prepare_batch(mrsdc_ctx *c, int64_t N) {
   if ((st = dalloc(c, &a.sc, 1))) return st;
   HIPCHK(hipMemset(a.sc, 0, sizeof(BatchScalars)));
   HIPCHK(hipMemcpy(a.sc->active, act.data(), sizeof(int) * S, hipMemcpyHostToDevice));
-  const int maxgrid = std::max({a.grid, a.sgrid64, a.sgrid32, a.cgrid});
+  // partial sums: up to three per scenario from every workgroup of any
+  // launch that publishes them (the grids of the tiled, row, column-sweep
+  // and F / predictor-sweep kernels; the updates' resident grids are at
+  // most a.grid)
+  const int maxgrid = std::max({a.grid, a.sgrid64, a.sgrid32, a.cgrid, a.cgrid_f});
+  a.pgrid = maxgrid;
   if ((st = dalloc(c, &a.partial, 3 * (size_t)maxgrid * S, true)))
     return st;
   if ((st = dalloc(c, &c->stage, N))) return st;

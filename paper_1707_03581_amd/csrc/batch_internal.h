@@ -126,7 +126,8 @@ struct BatchArgs {
   double *r64 = nullptr;
   int fp32 = 0;
   double sweep_tol = 0.0;  // > 0: residual-controlled sweeps, per scenario
-  double *partial = nullptr;  // [3][max(grid, sgrid64, sgrid32)][S]
+  double *partial = nullptr;  // [3][pgrid][S]: per-workgroup partial sums
+  int pgrid = 0;              // workgroups whose three partial sums the buffer holds
   BatchScalars *sc = nullptr;
   double *Eold = nullptr, *Enew = nullptr;  // [(M+1)(P+1)][n_if][S]
   double *Tbuf[2] = {};                     // [n_if][S]

@@ -2243,7 +2243,9 @@ static void launch_init(const BatchArgs &a, bool pred, int m, double dtau, hipSt
     kb_init_corr<NV><<<a.grid, kBlock, 0, st>>>(a, m, dtau);
     return;
   }
-  if (a.cgrid_f > 0) {  // the FP64 column sweep of T_{m-1}
+  // the FP64 column sweep of T_{m-1} (its NV partial sums per workgroup must
+  // fit the partial-sum buffer)
+  if (a.cgrid_f > 0 && (int64_t)NV * a.cgrid_f <= 3 * (int64_t)a.pgrid) {
     constexpr int MODE = NV == 3 ? kColPred64 : kColPred32;
     if (vec16<double>(a))
       kb_pcg_a_col<0, double, 16, kColDepth, MODE><<<a.cgrid_f, kBlock, 0, st>>>(a, m, dtau);
@@ -2257,8 +2259,10 @@ static void launch_init(const BatchArgs &a, bool pred, int m, double dtau, hipSt
 void blaunch_solve(const BatchArgs &a, const BSolve &sv, hipStream_t st) {
   const int m = sv.m;
   const double dtau = a.dtau_h[m];
-  // workgroups of the init kernel
-  const int npi = sv.pred ? (a.cgrid_f > 0 ? a.cgrid_f : a.sgrid64) : a.grid;
+  // workgroups of the init kernel (as launch_init picks it)
+  const int nvi = a.fp32 ? 2 : 3;
+  const bool psweep = a.cgrid_f > 0 && (int64_t)nvi * a.cgrid_f <= 3 * (int64_t)a.pgrid;
+  const int npi = sv.pred ? (psweep ? a.cgrid_f : a.sgrid64) : a.grid;
   if (!a.fp32) {
     launch_init<3>(a, sv.pred, m, dtau, st);
     RED(npi, 0, 0, 0, sv.slot, sv.rtol);
