@@ -41,15 +41,15 @@ COUNTER_TRAFFIC = {
     },
     ("ensemble-64x714798", 1): {
         "source": "batch_kernels.hip",
-        "sha256": "1b21e0b4a3e08570eb7c849a81cb0a89c86f515632f40207b220939f34fa3fc5",
-        "fetch_kib": 162508.9, "fetch_scale": 1.99973,
-        "write_kib": 181804.6, "write_scale": 1.0,
+        "sha256": "201b75ce8220ad36b2ff773b4527f7a1a2a24ec4a715fad26ce90caf45bf4627",
+        "fetch_kib": 162599.7, "fetch_scale": 1.99974,
+        "write_kib": 181819.3, "write_scale": 1.0,
     },
     ("ensemble-64x714798", 0): {
         "source": "batch_kernels.hip",
-        "sha256": "1b21e0b4a3e08570eb7c849a81cb0a89c86f515632f40207b220939f34fa3fc5",
-        "fetch_kib": 395352.4, "fetch_scale": 1.99974,
-        "write_kib": 361185.4, "write_scale": 1.0,
+        "sha256": "201b75ce8220ad36b2ff773b4527f7a1a2a24ec4a715fad26ce90caf45bf4627",
+        "fetch_kib": 395504.9, "fetch_scale": 1.99974,
+        "write_kib": 361189.2, "write_scale": 1.0,
     },
 }
 
