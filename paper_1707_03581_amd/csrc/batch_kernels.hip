@@ -322,7 +322,8 @@ __device__ __attribute__((always_inline)) inline void tile_apply(
 #pragma unroll
     for (int k = 0; k < VEC; ++k) {
       if (s0 + k >= S) continue;
-      // (one explicit rounding pattern: the column sweep forms the same)
+      // (one explicit rounding pattern; the column sweep forms the same
+      // sums, and y = fma(h, accr, acc) with accr = 0 where there is no R)
       const AT y = n == nk[i] ? acc[k] : fma_t(h[k], accr[k], acc[k]);
       epi(row, k, s0 + k, y, own[k], ms[i]);
     }
@@ -515,7 +516,7 @@ struct ColVec<double> {
 // offset, inside flag, record unit) are formed once per item; issuing a
 // stage then costs a few instructions per copy.  Every lane copies from
 // inside a buffer: halo rows outside the body and the values past S of a
-// row come from the row of zeros after the direction; the records' tail
+// row come from the row of zeros after the staged vector; the records' tail
 // repeats the first K unit.
 template <typename XV, typename RV, int UB, int D>
 struct ColIssue {
@@ -524,8 +525,9 @@ struct ColIssue {
   static constexpr int UPH = 256 / UB;  // units per staged row
   static constexpr unsigned XB = G::PlaneUnits * 16, RB = G::RecSlot * 16;  // slot bytes
   static constexpr unsigned RECB = G::RecUnits * 16;                        // record bytes
-  // buffer resources: x (the direction, which ends in a row of zeros) and
-  // the records (K, then R)
+  // buffer resources: x (the staged vector: the CG direction, a node state or
+  // the FP32 correction, which ends in a row of zeros) and the records (K,
+  // then R)
   __amdgpu_buffer_rsrc_t rx, rrec;
   unsigned off0[CC::C0];  // x copy: the lane's unit at plane 0; record copy: in a record
   unsigned zoff[CC::C0];  // x copy: its offset in the row of zeros
@@ -760,7 +762,8 @@ __device__ inline double lane_h(const BatchArgs &a, int s) {
 }
 
 // ---------------------------------------------------------------------------
-// F_j = g - L_s T_j (several standard nodes j), all scenarios
+// F_j = g - L_s T_j (several standard nodes j), all scenarios, in LDS tiles
+// (meshes without the column sweep; box meshes take its F mode)
 // ---------------------------------------------------------------------------
 template <int UB, bool AL>
 __global__ __launch_bounds__(kBlock) void kb_f_multi(BatchArgs a, int j0, int j1) {
@@ -940,7 +943,8 @@ __device__ inline void init32_row(const BatchArgs &a, int m, double dtau, int64_
   v[1] += b * b;
 }
 
-// predictor initialisation: tiled, L T_{m-1} from the staged rows
+// predictor initialisation: tiled, L T_{m-1} from the staged rows (meshes
+// without the column sweep; box meshes take its predictor modes)
 template <int NV, int UB, bool AL>
 __global__ __launch_bounds__(kBlock) void kb_init_pred(BatchArgs a, int m, double dtau) {
   using LY = Lanes<double>;
@@ -984,7 +988,8 @@ __global__ __launch_bounds__(kBlock) void kb_init_corr(BatchArgs a, int m, doubl
 }
 
 // x64 += d; r64 -= A d with the FP64 operator on the FP32 correction d
-// (staged as FP32); partial r.r
+// (staged as FP32); partial r.r.  Tiled (meshes without the column sweep;
+// box meshes take its refinement mode).
 template <int UB, bool AL>
 __global__ __launch_bounds__(kBlock) void kb_refine_update(BatchArgs a, int m, double dtau) {
   using LY = Lanes<float>;
