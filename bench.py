@@ -41,15 +41,15 @@ COUNTER_TRAFFIC = {
     },
     ("ensemble-64x714798", 1): {
         "source": "batch_kernels.hip",
-        "sha256": "201b75ce8220ad36b2ff773b4527f7a1a2a24ec4a715fad26ce90caf45bf4627",
-        "fetch_kib": 162599.7, "fetch_scale": 1.99974,
-        "write_kib": 181819.3, "write_scale": 1.0,
+        "sha256": "397a8c615408062e7cfe64dca8db10423a7aa7863503d8953b3a0c832394f19c",
+        "fetch_kib": 162534.8, "fetch_scale": 1.99973,
+        "write_kib": 181818.2, "write_scale": 1.0,
     },
     ("ensemble-64x714798", 0): {
         "source": "batch_kernels.hip",
-        "sha256": "201b75ce8220ad36b2ff773b4527f7a1a2a24ec4a715fad26ce90caf45bf4627",
-        "fetch_kib": 395504.9, "fetch_scale": 1.99974,
-        "write_kib": 361189.2, "write_scale": 1.0,
+        "sha256": "397a8c615408062e7cfe64dca8db10423a7aa7863503d8953b3a0c832394f19c",
+        "fetch_kib": 395314.0, "fetch_scale": 1.99974,
+        "write_kib": 361189.8, "write_scale": 1.0,
     },
 }
 
