@@ -295,3 +295,36 @@ def test_device_copy_out():
         torch.cuda.synchronize()
         assert np.array_equal(t.cpu().numpy(), ctx.get_scenario_temperature(s, pb.N))
     ctx.destroy()
+
+
+def test_boundary_load_without_r_entries():
+    """A row with a boundary load g but no R entries (its R row and column
+    cleared: R stays symmetric positive semidefinite) keeps g in the column
+    sweeps' zero R stencil: the sweeps agree with the tiles and the oracle."""
+    import paper_1707_03581_amd as m
+    from dataclasses import replace
+    pb = small_machine()
+    b = pb.bodies[0]
+    rows = np.repeat(np.arange(b.n), np.diff(b.rowptr))
+    hasR = np.zeros(b.n, bool)
+    np.logical_or.at(hasR, rows, b.R != 0)
+    cand = np.flatnonzero(hasR & (b.rload != 0))
+    i = int(cand[len(cand) // 2])
+    R = b.R.copy()
+    R[(rows == i) | (b.col == i)] = 0.0
+    pb2 = replace(pb, bodies=[replace(b, R=R), pb.bodies[1]])
+    assert b.rload[i] != 0.0
+    mem = members_for(pb2, 6, seed0=2500)
+    for precision in (0, 1):
+        cols, sc, _ = run_batch(pb2, mem, 2, precision=precision)
+        tiles, stl, _ = run_batch(pb2, mem, 2, precision=precision, op_form=m.OP_VALUES)
+        assert sc["col_depth"] > 0 and stl["col_depth"] == 0
+        for s in (0, 5):
+            e = rel(cols[s], tiles[s])
+            print(f"  precision {precision} member {s}: columns vs tiles {e:.3e}", flush=True)
+            assert e <= (1e-11 if precision == 0 else 1e-9)
+    mb = mem[5]
+    ref, _ = oracle.run(pb2, nsteps=2, T0=mb["T0"], h=mb["h"], alpha=mb["alpha"],
+                        friction_W=mb["friction_W"], period=mb["period"])
+    cols, _, _ = run_batch(pb2, mem, 2)
+    assert rel(cols[5], ref) <= 1e-10
